@@ -1,0 +1,424 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test names the passage it checks. None of them re-types the oracle's formulas:
+they use closed forms, invariants, special cases and finite differences, chosen so
+that a dropped term, a wrong sign or index, or a transposed operand fails one.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+SQ2 = math.sqrt(2.0)
+# Eq. weight_function (cosine reading): w(0) = 1/2, w(+-1) = 1/4, w(+-2) = 0,
+# w(+-1/2) = (2 + sqrt 2)/8, w(+-3/2) = (2 - sqrt 2)/8.
+W0, W1 = 0.5, 0.25
+WH, W3H = (2 + SQ2) / 8, (2 - SQ2) / 8
+
+
+def periodic(dim, n, **kw):
+    n3 = tuple(n) + (1,) * (3 - len(n))
+    return W.Problem(dim=dim, n=n3, bc=(W.PERIODIC,) * 6, **kw)
+
+
+def coords(pb):
+    N = pb.N
+    i = np.arange(N)
+    return i % pb.n[0], (i // pb.n[0]) % pb.n[1], i // (pb.n[0] * pb.n[1])
+
+
+# ---------------------------------------------------------------- Sec. 2.2 LKS
+
+@pytest.mark.parametrize("case", ["p2", "p3", "ch2", "ch3"])
+def test_uniform_flow_is_fixed_point(orc, case):
+    """A uniform flow (p = 0, u = U) is steady under Eqs. local_equilibrium_function,
+    p_tmp, u_tmp; this fails for the '+3/2 u^2' sign as printed and for any weight
+    error (the moment identities of the D2Q9/D3Q15 weights)."""
+    U = (0.05, -0.02, 0.03)
+    if case == "p2":
+        pb = periodic(2, (10, 8), nu=0.12, n_steps=5)
+    elif case == "p3":
+        pb = periodic(3, (8, 7, 6), nu=0.05, n_steps=5)
+    elif case == "ch2":
+        pb = W.channel2d(14, 9, U[0], 0.1, n_steps=5)
+    else:
+        pb = W.Problem(dim=3, n=(10, 6, 5), bc=(W.VELOCITY, W.PRESSURE, 0, 0, 0, 0),
+                       bc_u=((U[0], U[1], U[2]),) + ((0, 0, 0),) * 5, nu=0.08, n_steps=5)
+    pb = pb.replace(u0=U[: pb.dim] + (0.0,) * (3 - pb.dim)) if case != "ch2" else pb
+    s0 = W.initial_state(pb)
+    s, _, _ = orc.forward(pb, None, s0, np.zeros(12))
+    assert np.abs(s - s0).max() < 1e-16
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("mode", [1, 3, 7])
+def test_shear_wave_decay_closed_form(orc, dim, mode):
+    """Linear shear wave u_y = a sin(kx): one step multiplies it by
+    G(k) = 2/3 + cos(k)/3 + (2A/9) sin^2(k) with nu = (1/6 - 2A/9) (Sec. 2.2), which
+    tends to 1 - nu k^2 for small k. Pins the A-term and its factor."""
+    nx, nu, a0 = 32, 0.09, 1e-7
+    pb = periodic(dim, (nx, 4) if dim == 2 else (nx, 4, 3), nu=nu, n_steps=1)
+    N = pb.N
+    x, _, _ = coords(pb)
+    k = 2 * np.pi * mode / nx
+    s0 = np.zeros((dim + 1) * N)
+    s0[2 * N:3 * N] = a0 * np.sin(k * x)
+    s1, _, _ = orc.forward(pb, None, s0, np.zeros(12))
+    A = (1 / 6 - nu) * 9 / 2
+    G = 2 / 3 + np.cos(k) / 3 + (2 * A / 9) * np.sin(k) ** 2
+    assert np.abs(s1[2 * N:3 * N] - G * s0[2 * N:3 * N]).max() < 1e-14 * a0
+    assert np.abs(s1[:N]).max() < 1e-18 and np.abs(s1[N:2 * N]).max() < 1e-18
+    # small-k limit of G is the viscous decay 1 - nu k^2
+    kk = 1e-3
+    Gs = 2 / 3 + np.cos(kk) / 3 + (2 * A / 9) * np.sin(kk) ** 2
+    assert abs((1 - Gs) / kk ** 2 - nu) < 1e-6
+
+
+def test_pressure_sum_conserved_with_body(orc):
+    """On a fully periodic grid sum_x p is invariant: p = p* (Eq. p) and the
+    equilibrium moments give sum_i f_i = 3p + (2A/3) div u, whose divergence sums
+    to zero. Holds with the body, since the Brinkman term only changes u."""
+    pb = periodic(2, (30, 28), nu=0.12, nd=(8, 7, 1), kappa_max=0.8, q=0.1, mass=40.0,
+                  inertia=3e3, dof_mask=W.DOF_TX | W.DOF_TY | W.DOF_ROT, n_itr=4, n_steps=30,
+                  x_g0=(13.2, 14.7, 0), theta0=0.4, seed=3, u0=(0.03, -0.01, 0))
+    s0 = W.initial_state(pb)
+    s0[:pb.N] = 1e-3 * np.random.default_rng(0).standard_normal(pb.N)
+    s, b, _ = orc.forward(pb, W.design(pb), s0, W.initial_body(pb))
+    assert abs(s[:pb.N].sum() - s0[:pb.N].sum()) < 1e-15
+    assert np.abs(b[:2] - pb.x_g0[:2]).max() > 1e-3  # the body did move
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_momentum_conserved_body_free(orc, dim):
+    """Body-free periodic grid: sum_x u is invariant (first moments of the weights)."""
+    pb = periodic(dim, (12, 10) if dim == 2 else (9, 8, 7), nu=0.07, n_steps=20)
+    rng = np.random.default_rng(1)
+    s0 = 1e-2 * rng.standard_normal((dim + 1) * pb.N)
+    s, _, _ = orc.forward(pb, None, s0, np.zeros(12))
+    for a in range(dim + 1):
+        sl = slice(a * pb.N, (a + 1) * pb.N)
+        assert abs(s[sl].sum() - s0[sl].sum()) < 1e-14
+
+
+def poiseuille(dim, nu=0.1, dp=1e-3):
+    n = (24, 11, 1) if dim == 2 else (12, 9, 4)
+    pb = W.Problem(dim=dim, n=n, bc=(W.PRESSURE, W.PRESSURE, W.WALL, W.WALL, 0, 0),
+                   bc_p=(dp, 0, 0, 0, 0, 0), nu=nu, n_steps=1)
+    x, y, _ = coords(pb)
+    H, G = n[1] - 1, dp / (n[0] - 1)
+    s = np.zeros((dim + 1) * pb.N)
+    s[:pb.N] = dp - G * x
+    s[pb.N:2 * pb.N] = G / (2 * nu) * y * (H - y)
+    return pb, s
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_poiseuille_exact_fixed_point(orc, dim):
+    """Pressure-driven flow between walls: u_x = (G / 2 nu) y (H - y), p linear, is an
+    exact fixed point of the scheme with the boundary treatment (prescribed p on the
+    PRESSURE faces, u = 0 on WALL faces, the rest copied from the nearest interior
+    node) and one-sided gradients on boundary nodes."""
+    pb, s0 = poiseuille(dim)
+    s1, _, _ = orc.forward(pb, None, s0, np.zeros(12))
+    assert np.abs(s1 - s0).max() < 1e-17
+
+
+def test_poiseuille_develops_from_rest(orc):
+    pb, sref = poiseuille(2)
+    s, _, _ = orc.forward(pb.replace(n_steps=6000), None, np.zeros_like(sref), np.zeros(12))
+    N = pb.N
+    assert np.abs(s[N:2 * N] - sref[N:2 * N]).max() < 1e-10 * sref[N:2 * N].max()
+
+
+# ------------------------------------------------------------- Sec. 2.3 mapping
+
+def one_point(dim, X, n=(12, 12, 12)):
+    n3 = n if dim == 3 else (n[0], n[1], 1)
+    pb = periodic(dim, n3[:dim], nd=(1, 1, 1), kappa_max=1.0, q=0.1, mass=1, inertia=1)
+    b = np.zeros(12)
+    b[:dim] = X
+    return pb, b
+
+
+def test_mapping_node_aligned_weights(orc):
+    """A design point on a node spreads with W = w(rx) w(ry): 1/4 on the node, 1/8 on
+    the 4 edge neighbours, 1/16 on the 4 diagonal ones, nothing further (Eq.
+    weight_function). Fails for the printed '1 - cos' kernel."""
+    pb, b = one_point(2, (5.0, 6.0))
+    kap, uS = orc.map_design(pb, np.array([1.0]), b)
+    k = kap.reshape(12, 12)
+    assert k[6, 5] == pytest.approx(W0 * W0, abs=1e-16)
+    for dx, dy in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+        assert k[6 + dy, 5 + dx] == pytest.approx(W0 * W1, abs=1e-16)
+    for dx, dy in ((1, 1), (-1, 1), (1, -1), (-1, -1)):
+        assert k[6 + dy, 5 + dx] == pytest.approx(W1 * W1, abs=1e-16)
+    assert abs(k.sum() - 1.0) < 1e-15
+    assert np.count_nonzero(np.abs(k) > 1e-30) == 9
+
+
+def test_mapping_half_offset_weights(orc):
+    """Point at half offsets in 3D: W is the product of the 1D taps
+    ((2-sqrt2)/8, (2+sqrt2)/8, (2+sqrt2)/8, (2-sqrt2)/8) on each axis."""
+    pb, b = one_point(3, (5.5, 4.5, 6.5))
+    kap, _ = orc.map_design(pb, np.array([2.0]), b)
+    k = kap.reshape(12, 12, 12)
+    taps = np.array([W3H, WH, WH, W3H])
+    expect = 2.0 * np.einsum("i,j,k->ijk", taps, taps, taps)  # (z, y, x)
+    got = k[5:9, 3:7, 4:8]
+    assert np.abs(got - expect).max() < 1e-15
+    assert abs(k.sum() - 2.0) < 1e-14
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_partition_of_unity_and_transpose(orc, dim):
+    """sum_x W(x - X) = 1 for any X whose taps lie inside, so sum_x kappa = sum_m
+    kappa_ref; and the spread (Eqs. kappa_mapping, us_mapping) is the transpose of the
+    interpolation (Eq. u_mapping): <S a, b> = <a, I b>."""
+    if dim == 2:
+        pb = periodic(2, (30, 26), nd=(7, 6, 1), seed=4, kappa_max=1.0, q=0.1, mass=1, inertia=1)
+    else:
+        pb = periodic(3, (18, 17, 16), nd=(4, 5, 3), seed=4, kappa_max=1.0, q=0.1, mass=1,
+                      inertia=1, axis=1)
+    rng = np.random.default_rng(7)
+    b = np.zeros(12)
+    b[:dim] = np.array(pb.n[:dim]) / 2 + rng.random(dim)
+    b[6] = 0.7
+    a = rng.random(pb.ND)
+    kap, _ = orc.map_design(pb, a, b)
+    assert abs(kap.sum() - a.sum()) < 1e-12
+    f = rng.standard_normal(dim * pb.N)
+    uref = orc.interp(pb, f, b)
+    lhs = float(kap @ f[:pb.N])
+    rhs = float(a @ uref[:pb.ND])
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_rigid_body_kinematics_quarter_turn(orc):
+    """Eqs. rigid_body_position / rigid_body_velocity at theta = pi/2: the point at
+    xi = (1, 0) sits at x^G + (0, 1) and moves with u^G + omega (-1, 0)
+    (counter-clockwise positive). Read back through the mapping at node x^G + (0,1)."""
+    pb = periodic(2, (16, 16), nd=(3, 1, 1), kappa_max=1, q=0.1, mass=1, inertia=1)
+    b = np.zeros(12)
+    b[0:2] = (8.0, 8.0)
+    b[3:5] = (0.01, -0.02)
+    b[6] = math.pi / 2
+    b[7] = 0.3
+    kref = np.array([0.7, 1.3, 2.9])  # xi = (-1,0), (0,0), (1,0)
+    kap, uS = orc.map_design(pb, kref, b)
+    node = 9 * 16 + 8
+    assert kap[node] == pytest.approx(W0 * W0 * 2.9 + W0 * W1 * 1.3, abs=1e-14)
+    ux = W0 * W0 * (0.01 - 0.3) + W0 * W1 * 0.01
+    uy = W0 * W0 * (-0.02) + W0 * W1 * (-0.02)
+    assert uS[node] == pytest.approx(ux, abs=1e-14)
+    assert uS[256 + node] == pytest.approx(uy, abs=1e-14)
+    # the point xi = (-1, 0) is at x^G - (0, 1): node (8, 7) sees it with weight 1/4
+    node2 = 7 * 16 + 8
+    assert kap[node2] == pytest.approx(W0 * W0 * 0.7 + W0 * W1 * 1.3, abs=1e-14)
+
+
+# ------------------------------------------------------------ Sec. 2.4 body
+
+def test_body_step_constant_force(orc):
+    """Explicit Euler of Sec. 2.4 under a constant force: u^G(t) = u^G(0) + t F/M,
+    x^G(t) = x^G(0) + t u^G(0) + (F/M) t(t+1)/2; inactive DOFs keep their values."""
+    pb = W.Problem(dim=3, n=(4, 4, 4), bc=(0,) * 6, nd=(1, 1, 1), mass=3.0, inertia=7.0,
+                   dof_mask=W.DOF_TX | W.DOF_TZ | W.DOF_ROT, axis=1)
+    FT = np.array([0.3, 0.5, -0.2, 0.11])
+    b0 = np.array([1.0, 2.0, 3.0, 0.01, 0.02, 0.03, 0.4, 0.05, 0, 0, 0, 0])
+    b = b0.copy()
+    T = 17
+    for _ in range(T):
+        b = orc.body_step(pb, FT, b)
+    aF = FT[:3] / 3.0
+    for a, active in ((0, True), (1, False), (2, True)):
+        if active:
+            assert b[3 + a] == pytest.approx(b0[3 + a] + T * aF[a], rel=1e-14)
+            assert b[a] == pytest.approx(b0[a] + T * b0[3 + a] + aF[a] * T * (T + 1) / 2, rel=1e-14)
+        else:
+            assert b[a] == b0[a] and b[3 + a] == b0[3 + a]
+    al = 0.11 / 7.0
+    assert b[7] == pytest.approx(0.05 + T * al, rel=1e-14)
+    assert b[6] == pytest.approx(0.4 + T * 0.05 + al * T * (T + 1) / 2, rel=1e-14)
+
+
+# ----------------------------------------- coupled closed forms (Eqs. u, Alg. 1)
+
+def covering(n_itr, dofs, mass=60.0, kmax=0.5, gam=0.5):
+    """Periodic 12x10 grid fully covered by a 22x20 design extending >= 3 nodes beyond
+    it: kappa(x) = kappa_ref and the mapped body velocity equal the body's everywhere,
+    and sum_m u^ref_m = N u for a uniform u (node-side partition of unity)."""
+    pb = periodic(2, (12, 10), nu=0.1, nd=(22, 20, 1), kappa_max=kmax, q=0.1, mass=mass,
+                  inertia=1e3, dof_mask=dofs, n_itr=n_itr, n_steps=6,
+                  x_g0=(5.5, 4.5, 0.0), u0=(0.04, 0.01, 0.0))
+    kr = kmax * 0.1 * gam / (1 - gam + 0.1)
+    return pb, np.full(pb.ND, gam), kr
+
+
+def test_brinkman_relaxation_closed_form(orc):
+    """Held body moving with u^G under a uniform flow: with kappa and u^S uniform, Eq. u
+    gives u(t) - u^G = (u(t-1) - u^G)/(1 + kappa) and p stays 0."""
+    pb, g, kr = covering(2, 0)
+    b0 = W.initial_body(pb)
+    b0[3:5] = (-0.02, 0.03)
+    s, b, _ = orc.forward(pb, g, W.initial_state(pb), b0)
+    N = pb.N
+    for a, (u0, ug) in enumerate(zip((0.04, 0.01), (-0.02, 0.03))):
+        expect = ug + (u0 - ug) / (1 + kr) ** pb.n_steps
+        assert np.abs(s[(1 + a) * N:(2 + a) * N] - expect).max() < 1e-16
+    assert np.abs(s[:N]).max() < 1e-17
+    assert np.array_equal(b, b0)
+
+
+def test_coupled_iteration_closed_form(orc):
+    """Free translation in the covering setting: F = kappa_ref (N u^(k) - N_D u^G,(k)),
+    u^(k) = (u* + kappa_ref u^G,(k))/(1 + kappa_ref), each of the N_itr iterations
+    restarting the Euler update from t-1 (Sec. 3.1, Alg. 1) and u(t) = u^(N_itr-1)."""
+    pb, g, kr = covering(3, W.DOF_TX | W.DOF_TY)
+    s, b, _ = orc.forward(pb, g, W.initial_state(pb), W.initial_body(pb))
+    N, ND, M = pb.N, pb.ND, pb.mass
+    u = np.array([0.04, 0.01])
+    uG = np.zeros(2)
+    xG = np.array([5.5, 4.5])
+    for _ in range(pb.n_steps):
+        uGk = uG.copy()
+        for _k in range(pb.n_itr):
+            uk = (u + kr * uGk) / (1 + kr)
+            F = kr * (N * uk - ND * uGk)
+            uG_new = uG + F / M
+            xG_new = xG + uG_new
+            uGk = uG_new
+        u, uG, xG = uk, uG_new, xG_new
+    assert np.abs(b[3:5] - uG).max() < 1e-15
+    assert np.abs(b[0:2] - xG).max() < 1e-13
+    for a in range(2):
+        assert np.abs(s[(1 + a) * N:(2 + a) * N] - u[a]).max() < 1e-16
+
+
+def test_force_and_torque_single_point(orc):
+    """One porous design point one node above the centre in a uniform flow U along x:
+    F_x = kappa U sum_x W/(1 + kappa W) over its 3x3 footprint (weights 1/4, 1/8, 1/16),
+    F_y = 0 and the torque about z is T = e_zab r_a F_b = -F_x (lever arm +1 in y).
+    One iteration per step so u^G(1) = F/M and omega(1) = T/I exactly."""
+    gam = 0.6
+    pb = periodic(2, (16, 16), nu=0.1, nd=(1, 3, 1), kappa_max=2.0, q=0.1, mass=5.0,
+                  inertia=11.0, dof_mask=W.DOF_TX | W.DOF_TY | W.DOF_ROT, n_itr=1, n_steps=1,
+                  x_g0=(8.0, 8.0, 0.0), u0=(0.05, 0.0, 0.0))
+    g = np.array([0.0, 0.0, gam])
+    k = 2.0 * 0.1 * gam / (1 - gam + 0.1)
+    Fx = k * 0.05 * (W0 * W0 / (1 + k * W0 * W0) + 4 * W0 * W1 / (1 + k * W0 * W1)
+                     + 4 * W1 * W1 / (1 + k * W1 * W1))
+    _, b, _ = orc.forward(pb, g, W.initial_state(pb), W.initial_body(pb))
+    assert b[3] == pytest.approx(Fx / 5.0, rel=1e-13)
+    assert abs(b[4]) < 1e-18
+    assert b[7] == pytest.approx(-Fx / 11.0, rel=1e-13)
+    assert b[0] == pytest.approx(8.0 + Fx / 5.0, rel=1e-15)
+    assert b[6] == pytest.approx(-Fx / 11.0, rel=1e-13)
+
+
+def test_quarter_turn_equivariance(orc):
+    """Rotating the whole periodic problem by 90 degrees (flow, body position and the
+    pose theta0 -> theta0 + pi/2) rotates the solution: D2Q9, the tensor-product
+    kernel, Eqs. rigid_body_position/velocity and the torque are all equivariant."""
+    L = 20
+    base = dict(nu=0.11, nd=(7, 5, 1), kappa_max=0.5, q=0.1, mass=50.0, inertia=2e3,
+                dof_mask=W.DOF_TX | W.DOF_TY | W.DOF_ROT, n_itr=3, n_steps=8, seed=8)
+    pa = periodic(2, (L, L), x_g0=(10.3, 9.6, 0), theta0=0.1, u0=(0.04, 0.01, 0), **base)
+    pr = periodic(2, (L, L), x_g0=(10.4, 10.3, 0), theta0=0.1 + math.pi / 2,
+                  u0=(-0.01, 0.04, 0), **base)
+    g = W.design(pa)
+    sa, ba, _ = orc.forward(pa, g, W.initial_state(pa), W.initial_body(pa))
+    sr, br, _ = orc.forward(pr, g, W.initial_state(pr), W.initial_body(pr))
+    N = L * L
+    x, y, _ = coords(pa)
+    rot = (L - y) % L + L * x  # node (x, y) -> (L - y, x)
+    assert np.abs(sr[rot] - sa[:N]).max() < 1e-14
+    assert np.abs(sr[N + rot] + sa[2 * N:3 * N]).max() < 1e-14
+    assert np.abs(sr[2 * N + rot] - sa[N:2 * N]).max() < 1e-14
+    assert br[0] == pytest.approx(10.0 - (ba[1] - 10.0), abs=1e-12)
+    assert br[1] == pytest.approx(10.0 + (ba[0] - 10.0), abs=1e-12)
+    assert br[3] == pytest.approx(-ba[4], abs=1e-15) and br[4] == pytest.approx(ba[3], abs=1e-15)
+    assert br[6] - math.pi / 2 == pytest.approx(ba[6], abs=1e-14)
+    assert br[7] == pytest.approx(ba[7], abs=1e-15)
+    assert abs(ba[7]) > 1e-7  # a torque acted
+
+
+# ------------------------------------------------- exact adjoint vs finite differences
+
+FD_CASES = {
+    "2d-x": lambda: W.small2d(),
+    "2d-theta": lambda: W.small2d(objective=W.OBJ_ANGLE, inertia=300.0),
+    "2d-y-walls": lambda: W.small2d(objective=W.OBJ_DISP_Y).replace(
+        bc=(W.VELOCITY, W.PRESSURE, W.WALL, W.WALL, 0, 0)),
+    "3d-theta": lambda: W.small3d(inertia=150.0),
+    "3d-y": lambda: W.small3d(objective=W.OBJ_DISP_Y),
+}
+
+
+@pytest.mark.parametrize("case", sorted(FD_CASES))
+def test_gradient_matches_central_differences(orc, case):
+    """The oracle's reverse sweep is the exact derivative of its forward map: central
+    differences (h = 1e-4, truncation O(h^2)) on random design entries agree."""
+    pb = FD_CASES[case]()
+    g = W.design(pb)
+    s0, b0 = W.initial_state(pb), W.initial_body(pb)
+    J, grad = orc.gradient(pb, g, s0, b0)
+    assert J == pytest.approx(orc.forward(pb, g, s0, b0)[2], rel=1e-15, abs=1e-300)
+    h = 1e-4
+    rng = np.random.default_rng(1003)
+    idx = rng.choice(pb.ND, 6, replace=False)
+    scale = np.abs(grad).max()
+    assert scale > 0
+    for m in idx:
+        gp, gm = g.copy(), g.copy()
+        gp[m] += h
+        gm[m] -= h
+        fd = (orc.forward(pb, gp, s0, b0)[2] - orc.forward(pb, gm, s0, b0)[2]) / (2 * h)
+        assert abs(grad[m] - fd) <= 2e-5 * abs(fd) + 2e-6 * scale, (m, grad[m], fd)
+
+
+@pytest.mark.parametrize("case", ["2d-x", "3d-y"])
+def test_initial_state_gradient_matches_central_differences(orc, case):
+    """Cotangents of the initial fluid state, at nodes on and next to VELOCITY,
+    PRESSURE and WALL faces and in the body's footprint: checks the transposes of the
+    boundary treatment and of the one-sided gradients."""
+    pb = FD_CASES[case]()
+    g = W.design(pb)
+    s0, b0 = W.initial_state(pb), W.initial_body(pb)
+    J, grad, ds, db = orc.gradient(pb, g, s0, b0, with_initial=True)
+    N, nx, ny = pb.N, pb.n[0], pb.n[1]
+    z = pb.n[2] // 2
+    picks = []
+    for (x, y) in ((0, 5), (1, 5), (2, 4), (nx - 1, 6), (nx - 2, 7), (int(pb.x_g0[0]), int(pb.x_g0[1])),
+                   (int(pb.x_g0[0]) + 3, 0), (5, 1)):
+        node = x + nx * (y + ny * z)
+        for comp in range(pb.dim + 1):
+            picks.append(comp * N + node)
+    h = 1e-6
+    scale = np.abs(ds).max()
+    for i in picks:
+        sp, sm = s0.copy(), s0.copy()
+        sp[i] += h
+        sm[i] -= h
+        fd = (orc.forward(pb, g, sp, b0)[2] - orc.forward(pb, g, sm, b0)[2]) / (2 * h)
+        assert abs(ds[i] - fd) <= 1e-5 * abs(fd) + 1e-6 * scale, (i, ds[i], fd)
+    # initial body state cotangent (velocity component of the objective's axis)
+    for j in (0, 3, 6, 7):
+        bp, bm = b0.copy(), b0.copy()
+        bp[j] += 1e-6
+        bm[j] -= 1e-6
+        fd = (orc.forward(pb, g, s0, bp)[2] - orc.forward(pb, g, s0, bm)[2]) / 2e-6
+        jac_scale = max(abs(fd), np.abs(db).max())
+        assert abs(db[j] - fd) <= 1e-5 * jac_scale + 1e-9, (j, db[j], fd)
+
+
+def test_invalid_problems_rejected(orc):
+    pb = W.small2d()
+    with pytest.raises(ValueError):
+        orc.forward(pb.replace(dim=4), W.design(pb), W.initial_state(pb), W.initial_body(pb))
+    with pytest.raises(ValueError):
+        orc.forward(pb.replace(bc=(W.PERIODIC, W.PRESSURE, 0, 0, 0, 0)), W.design(pb),
+                    W.initial_state(pb), W.initial_body(pb))
+    with pytest.raises(ValueError):
+        orc.forward(pb.replace(n_itr=0), W.design(pb), W.initial_state(pb), W.initial_body(pb))
