@@ -1,0 +1,158 @@
+/*
+ * lks.h -- C ABI of the MI355X (gfx950) library for the lattice kinetic scheme with a
+ * passively moving rigid body, and its discrete adjoint.
+ *
+ * Method: Tanabe, Yaji, Ushijima, "Topology optimization of passively moving rigid
+ * bodies in unsteady flows", arXiv 2601.18272. Lattice units (grid spacing = time
+ * step = 1, tau = 1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All array arguments are DEVICE pointers (hipMalloc'd or torch CUDA tensors on the
+ *    current device), owned by the caller. The library never allocates or frees
+ *    device memory; scratch space comes from the caller through `work`.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream). Every call
+ *    is enqueued on it; lks_forward and lks_adjoint additionally synchronise it once
+ *    at the end to read the device error flag, unless LKS_FLAG_ASYNC is set.
+ *  - Floating-point arrays marked "T" have the precision of lks_problem_t.precision
+ *    (float for LKS_FP32, double for LKS_FP64). Body states, force/torque, the
+ *    objective and gradients are always double.
+ *  - Node index n = x + nx*(y + ny*z) (nz = 1 in 2D). A state is [p | u_x | u_y (| u_z)],
+ *    (dim+1)*N elements. Design index m = i + ndx*(j + ndy*k), ndz = 1 in 2D; the design
+ *    grid has spacing 1 and is centred on the rotation centre x^G.
+ *  - A body state is 12 doubles {x^G[3], u^G[3], theta, omega, reserved[4]}.
+ *  - Return codes: LKS_OK, or a negative LKS_E* code; lks_last_error() then holds a
+ *    message (thread-local). No exception crosses the ABI.
+ *  - Calls that share `work` or `ckpt` buffers must not overlap.
+ */
+#ifndef LKS_H
+#define LKS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* boundary kinds per face; macroscopic values are prescribed directly (Sec. 2.2) */
+enum { LKS_PERIODIC = 0, LKS_VELOCITY = 1, LKS_PRESSURE = 2, LKS_WALL = 3 };
+enum { LKS_FP32 = 0, LKS_FP64 = 1 };
+/* objectives, Eqs. objective1 / objective2: displacement of x^G or rotation angle */
+enum { LKS_OBJ_DISP_X = 0, LKS_OBJ_DISP_Y = 1, LKS_OBJ_DISP_Z = 2, LKS_OBJ_ANGLE = 3 };
+/* free degrees of freedom of the body (Eqs. equation_of_motion_*) */
+enum { LKS_DOF_TX = 1, LKS_DOF_TY = 2, LKS_DOF_TZ = 4, LKS_DOF_ROT = 8 };
+enum { LKS_FLAG_ASYNC = 1 };
+
+enum {
+    LKS_OK = 0,
+    LKS_EINVAL = -1,    /* bad argument: dims, null pointer, n_itr < 1, ... */
+    LKS_ENOSPACE = -2,  /* `work` or `ckpt` smaller than the size query returned */
+    LKS_EUNSTABLE = -3, /* reserved */
+    LKS_EDIVERGED = -4, /* non-finite body state, or the body moved more than the
+                           footprint margin (2 nodes) within one step */
+    LKS_EHIP = -5       /* HIP runtime error (text in lks_last_error) */
+};
+
+typedef struct lks_problem {
+    int dim;              /* 2 (D2Q9) or 3 (D3Q15) */
+    int n[3];             /* analysis grid; n[2] = 1 in 2D; >= 3 along every axis used */
+    int bc[6];            /* faces x-, x+, y-, y+, z-, z+: LKS_PERIODIC | VELOCITY | PRESSURE | WALL;
+                             PERIODIC must be set on both faces of an axis */
+    double bc_p[6];       /* pressure prescribed on a PRESSURE face */
+    double bc_u[6][3];    /* velocity prescribed on a VELOCITY face (WALL: u = 0) */
+    double nu;            /* kinematic viscosity; A = 9/2 (1/6 - nu) (Sec. 2.2) */
+    int nd[3];            /* design grid (nd[2] = 1 in 2D); all zero: no body */
+    double kappa_max, q;  /* Eq. brinkman_coefficient */
+    double mass, inertia; /* M and the moment of inertia about the rotation axis */
+    int axis;             /* rotation axis 0/1/2 (ignored in 2D: z) */
+    int dof_mask;         /* LKS_DOF_* bits */
+    int n_itr;            /* fluid <-> body iterations per step (Sec. 3.1), >= 1 */
+    int n_steps;          /* time steps N_t */
+    int ckpt_every;       /* checkpoint interval K of the adjoint (>= 1 when ckpt is used) */
+    int precision;        /* LKS_FP32 | LKS_FP64: fields, stencils, mapping */
+    int objective;        /* LKS_OBJ_* */
+    int flags;            /* LKS_FLAG_* */
+} lks_problem_t;
+
+/* Elements (not bytes) of one state: (dim+1)*N. */
+size_t lks_state_elems(const lks_problem_t *P);
+
+/* Bytes of the checkpoint store that lks_forward fills for lks_adjoint:
+ * ceil(n_steps/ckpt_every) states plus their body states and a small header. */
+size_t lks_checkpoint_bytes(const lks_problem_t *P);
+
+/* Bytes of scratch space for lks_forward (adjoint = 0) or lks_adjoint (adjoint = 1).
+ * The adjoint workspace holds one recomputed segment of ckpt_every states. */
+size_t lks_workspace_bytes(const lks_problem_t *P, int adjoint);
+
+/*
+ * lks_forward -- n_steps coupled time steps (Algorithm 1, state loop): the LKS update
+ * of p, u (Eqs. local_equilibrium_function, p_tmp, u_tmp), then n_itr iterations of
+ * rigid body -> fluid (Eqs. rigid_body_position/velocity, kappa_mapping, us_mapping,
+ * p, u) and fluid -> rigid body (Eq. u_mapping and the Euler update of Sec. 2.4), then
+ * the boundary values.
+ *   gamma   [ND] T, design variable in [0, 1] (read only)
+ *   state   [(dim+1)*N] T, in: state at t = 0, out: state at t = n_steps
+ *   body    [12] double, in: body at t = 0, out: body at t = n_steps
+ *   ckpt    optional (NULL = no adjoint later): checkpoint store of ckpt_bytes
+ *   work    scratch of lks_workspace_bytes(P, 0) bytes
+ *   J       [1] double, out: objective (x^G component or theta at n_steps minus its
+ *           initial value)
+ * Errors: LKS_EINVAL, LKS_ENOSPACE, LKS_EDIVERGED, LKS_EHIP.
+ */
+int lks_forward(const lks_problem_t *P, const void *gamma, void *state, double *body,
+                void *ckpt, size_t ckpt_bytes, void *work, size_t work_bytes, double *J,
+                void *stream);
+
+/*
+ * lks_adjoint -- reverse-time sweep (Sec. 2.5, Algorithm 1, adjoint loop) giving the
+ * design sensitivity (Eq. design_sensitivity) as the exact derivative of the discrete
+ * map that lks_forward computes: segments of ckpt_every steps are recomputed from the
+ * checkpoints and swept backwards through the LKS, the boundary values, the n_itr
+ * body iterations, the mapping and the pose.
+ *   gamma   [ND] T, the same design as in the lks_forward call that filled ckpt
+ *   ckpt    checkpoint store filled by lks_forward (read only)
+ *   work    scratch of lks_workspace_bytes(P, 1) bytes
+ *   seed    dL/dJ
+ *   grad    [ND] double, out: seed * dJ/dgamma
+ *   dstate0 optional [(dim+1)*N] T, out: seed * dJ/d(initial state)
+ *   dbody0  optional [12] double, out: seed * dJ/d(initial body state)
+ * Errors: LKS_EINVAL, LKS_ENOSPACE, LKS_EHIP.
+ */
+int lks_adjoint(const lks_problem_t *P, const void *gamma, const void *ckpt, size_t ckpt_bytes,
+                void *work, size_t work_bytes, double seed, double *grad, void *dstate0,
+                double *dbody0, void *stream);
+
+/*
+ * map_design -- grid separation, Eqs. kappa_mapping, us_mapping with the weight of
+ * Eq. weight_function: the design-grid Brinkman coefficient and the rigid-body velocity
+ * of every design point (Eq. rigid_body_velocity) at pose `body`, mapped onto the
+ * interior analysis nodes.
+ *   kappa_ref [ND] T (read only)
+ *   body      [12] double (read only)
+ *   kappa     [N] T, out (zero where no design point reaches)
+ *   uS        [dim*N] T, out, component-major
+ * Errors: LKS_EINVAL, LKS_EHIP.
+ */
+int map_design(const lks_problem_t *P, const void *kappa_ref, const double *body, void *kappa,
+               void *uS, void *stream);
+
+/*
+ * body_step -- explicit Euler update of Sec. 2.4 with the DOF mask:
+ *   u^G = u^G_prev + F/M, x^G = x^G_prev + u^G, omega = omega_prev + T/I,
+ *   theta = theta_prev + omega; an inactive DOF keeps its previous values.
+ *   ft        [4] double {F_x, F_y, F_z, T} (read only)
+ *   body_prev [12] double (read only)
+ *   body      [12] double, out (may alias nothing)
+ * Errors: LKS_EINVAL, LKS_EHIP.
+ */
+int body_step(const lks_problem_t *P, const double *ft, const double *body_prev, double *body,
+              void *stream);
+
+/* Message of the last error on this thread ("" if none). */
+const char *lks_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,89 @@
+"""ctypes view of the C ABI declared in include/lks.h (liblks_hip.so, built in-tree).
+
+Loading fails loudly if the library has not been built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblks_hip.so")
+
+PERIODIC, VELOCITY, PRESSURE, WALL = 0, 1, 2, 3
+FP32, FP64 = 0, 1
+FLAG_ASYNC = 1
+
+OK, EINVAL, ENOSPACE, EUNSTABLE, EDIVERGED, EHIP = 0, -1, -2, -3, -4, -5
+
+EXPORTS = ("lks_state_elems", "lks_checkpoint_bytes", "lks_workspace_bytes", "lks_forward",
+           "lks_adjoint", "map_design", "body_step", "lks_last_error")
+
+
+class LksProblem(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int),
+        ("n", C.c_int * 3),
+        ("bc", C.c_int * 6),
+        ("bc_p", C.c_double * 6),
+        ("bc_u", (C.c_double * 3) * 6),
+        ("nu", C.c_double),
+        ("nd", C.c_int * 3),
+        ("kappa_max", C.c_double),
+        ("q", C.c_double),
+        ("mass", C.c_double),
+        ("inertia", C.c_double),
+        ("axis", C.c_int),
+        ("dof_mask", C.c_int),
+        ("n_itr", C.c_int),
+        ("n_steps", C.c_int),
+        ("ckpt_every", C.c_int),
+        ("precision", C.c_int),
+        ("objective", C.c_int),
+        ("flags", C.c_int),
+    ]
+
+
+class LksError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lks error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load liblks_hip.so (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run paper_2601_18272_amd.build.build()")
+    L = C.CDLL(LIB_PATH)
+    pp = C.POINTER(LksProblem)
+    vp = C.c_void_p
+    dp = C.c_void_p
+    L.lks_state_elems.argtypes = [pp]
+    L.lks_state_elems.restype = C.c_size_t
+    L.lks_checkpoint_bytes.argtypes = [pp]
+    L.lks_checkpoint_bytes.restype = C.c_size_t
+    L.lks_workspace_bytes.argtypes = [pp, C.c_int]
+    L.lks_workspace_bytes.restype = C.c_size_t
+    L.lks_forward.argtypes = [pp, vp, vp, dp, vp, C.c_size_t, vp, C.c_size_t, dp, vp]
+    L.lks_forward.restype = C.c_int
+    L.lks_adjoint.argtypes = [pp, vp, vp, C.c_size_t, vp, C.c_size_t, C.c_double, dp, vp, dp, vp]
+    L.lks_adjoint.restype = C.c_int
+    L.map_design.argtypes = [pp, vp, dp, vp, vp, vp]
+    L.map_design.restype = C.c_int
+    L.body_step.argtypes = [pp, dp, dp, dp, vp]
+    L.body_step.restype = C.c_int
+    L.lks_last_error.argtypes = []
+    L.lks_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def check(rc: int):
+    if rc != OK:
+        raise LksError(rc, load().lks_last_error().decode())

@@ -1,0 +1,169 @@
+"""Python binding of the gfx950 library: argument marshalling only.
+
+Every step of the computation runs in the HIP kernels of liblks_hip.so; torch supplies
+device memory and the current stream. Problems are described by any object with the
+fields of ``workloads.Problem`` (dim, n, bc, bc_p, bc_u, nu, nd, kappa_max, q, mass,
+inertia, axis, dof_mask, n_itr, n_steps, ckpt_every, objective).
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib
+from ._lib import LksError, LksProblem  # noqa: F401
+
+DTYPES = {"fp32": torch.float32, "fp64": torch.float64}
+
+
+def problem_struct(pb, precision: str = "fp32", flags: int = 0) -> LksProblem:
+    s = LksProblem()
+    s.dim = int(pb.dim)
+    for a in range(3):
+        s.n[a] = int(pb.n[a])
+        s.nd[a] = int(pb.nd[a])
+    for f in range(6):
+        s.bc[f] = int(pb.bc[f])
+        s.bc_p[f] = float(pb.bc_p[f])
+        for a in range(3):
+            s.bc_u[f][a] = float(pb.bc_u[f][a])
+    s.nu = float(pb.nu)
+    s.kappa_max = float(pb.kappa_max)
+    s.q = float(pb.q)
+    s.mass = float(pb.mass)
+    s.inertia = float(pb.inertia)
+    s.axis = int(pb.axis)
+    s.dof_mask = int(pb.dof_mask)
+    s.n_itr = int(pb.n_itr)
+    s.n_steps = int(pb.n_steps)
+    s.ckpt_every = int(pb.ckpt_every)
+    s.precision = _lib.FP32 if precision == "fp32" else _lib.FP64
+    s.objective = int(pb.objective)
+    s.flags = int(flags)
+    return s
+
+
+def _p(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(x, dtype):
+    if isinstance(x, torch.Tensor):
+        return x.to(device="cuda", dtype=dtype).contiguous()
+    return torch.as_tensor(x, dtype=dtype, device="cuda").contiguous()
+
+
+def state_elems(pb) -> int:
+    return int(_lib.load().lks_state_elems(C.byref(problem_struct(pb))))
+
+
+def checkpoint_bytes(pb, precision="fp32") -> int:
+    return int(_lib.load().lks_checkpoint_bytes(C.byref(problem_struct(pb, precision))))
+
+
+def workspace_bytes(pb, adjoint: bool, precision="fp32") -> int:
+    return int(_lib.load().lks_workspace_bytes(C.byref(problem_struct(pb, precision)), int(adjoint)))
+
+
+class Buffers:
+    """Device buffers for repeated calls on one problem (no allocation per call)."""
+
+    def __init__(self, pb, precision="fp32", adjoint=True):
+        L = _lib.load()
+        self.pb = pb
+        self.precision = precision
+        self.dtype = DTYPES[precision]
+        self.s = problem_struct(pb, precision)
+        nbytes = int(L.lks_workspace_bytes(C.byref(self.s), int(adjoint)))
+        if nbytes == 0:
+            raise LksError(_lib.EINVAL, L.lks_last_error().decode())
+        self.work = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.ckpt = None
+        if adjoint:
+            cb = int(L.lks_checkpoint_bytes(C.byref(self.s)))
+            self.ckpt = torch.empty(cb, dtype=torch.uint8, device="cuda")
+        self.J = torch.zeros(1, dtype=torch.float64, device="cuda")
+
+
+def forward(pb, gamma, state0, body0, precision="fp32", buffers: Buffers | None = None,
+            store_ckpt: bool = True, flags: int = 0):
+    """Run pb.n_steps coupled steps. Returns (state, body, J, buffers)."""
+    L = _lib.load()
+    dt = DTYPES[precision]
+    B = buffers or Buffers(pb, precision, adjoint=store_ckpt)
+    s = problem_struct(pb, precision, flags)
+    g = _dev(gamma, dt) if gamma is not None else None
+    st = _dev(state0, dt).clone()
+    bd = _dev(body0, torch.float64).clone()
+    ck = B.ckpt if store_ckpt else None
+    _lib.check(L.lks_forward(C.byref(s), _p(g), _p(st), _p(bd), _p(ck),
+                             ck.numel() if ck is not None else 0, _p(B.work), B.work.numel(),
+                             _p(B.J), _stream()))
+    return st, bd, B.J.clone(), B
+
+
+def adjoint(pb, gamma, buffers: Buffers, seed: float = 1.0, precision="fp32",
+            want_initial: bool = False, flags: int = 0):
+    """Reverse sweep after forward(..., store_ckpt=True). Returns grad (float64) and,
+    with want_initial, the cotangents of the initial state and body."""
+    L = _lib.load()
+    dt = DTYPES[precision]
+    s = problem_struct(pb, precision, flags)
+    g = _dev(gamma, dt)
+    grad = torch.empty(max(int(pb.nd[0] * pb.nd[1] * pb.nd[2]), 1), dtype=torch.float64, device="cuda")
+    ds = torch.empty(state_elems(pb), dtype=dt, device="cuda") if want_initial else None
+    db = torch.empty(12, dtype=torch.float64, device="cuda") if want_initial else None
+    _lib.check(L.lks_adjoint(C.byref(s), _p(g), _p(buffers.ckpt), buffers.ckpt.numel(),
+                             _p(buffers.work), buffers.work.numel(), float(seed), _p(grad), _p(ds),
+                             _p(db), _stream()))
+    return (grad, ds, db) if want_initial else grad
+
+
+def map_design(pb, kappa_ref, body, precision="fp32"):
+    """Mapped Brinkman coefficient and body velocity on the analysis grid."""
+    L = _lib.load()
+    dt = DTYPES[precision]
+    s = problem_struct(pb, precision)
+    kr = _dev(kappa_ref, dt)
+    bd = _dev(body, torch.float64)
+    N = int(pb.n[0] * pb.n[1] * pb.n[2])
+    kap = torch.empty(N, dtype=dt, device="cuda")
+    uS = torch.empty(pb.dim * N, dtype=dt, device="cuda")
+    _lib.check(L.map_design(C.byref(s), _p(kr), _p(bd), _p(kap), _p(uS), _stream()))
+    return kap, uS
+
+
+def body_step(pb, ft, body_prev):
+    """Euler update of the body from a force/torque [F_x, F_y, F_z, T]."""
+    L = _lib.load()
+    s = problem_struct(pb)
+    f = _dev(ft, torch.float64)
+    bp = _dev(body_prev, torch.float64)
+    out = torch.empty(12, dtype=torch.float64, device="cuda")
+    _lib.check(L.body_step(C.byref(s), _p(f), _p(bp), _p(out), _stream()))
+    return out
+
+
+class LKSFunction(torch.autograd.Function):
+    """J = LKSFunction.apply(gamma, problem, precision, state0, body0).
+
+    forward runs lks_forward with checkpoints every problem.ckpt_every steps; backward
+    runs lks_adjoint with seed dL/dJ and returns dL/dgamma."""
+
+    @staticmethod
+    def forward(ctx, gamma, pb, precision, state0, body0):
+        _, _, J, B = forward(pb, gamma.detach(), state0, body0, precision, store_ckpt=True)
+        ctx.pb, ctx.precision, ctx.buffers = pb, precision, B
+        ctx.save_for_backward(gamma)
+        return J.reshape(()).to(gamma.dtype)
+
+    @staticmethod
+    def backward(ctx, gJ):
+        (gamma,) = ctx.saved_tensors
+        grad = adjoint(ctx.pb, gamma.detach(), ctx.buffers, seed=float(gJ), precision=ctx.precision)
+        return grad.to(gamma.dtype).reshape(gamma.shape), None, None, None, None

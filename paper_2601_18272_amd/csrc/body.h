@@ -1,0 +1,682 @@
+// body.h -- rigid body <-> fluid coupling on gfx950 (Secs. 2.3, 2.4, 3.1) and its
+// exact reverse.
+//
+// Forward, per fluid <-> body iteration k of a step:
+//   spread   kappa(x) = sum_m W kappa_ref_m, u^S(x) = sum_m W u^S,ref_m (Eqs.
+//            kappa_mapping, us_mapping) in GATHER form: every node of the footprint box
+//            inverts the pose and visits its candidate design points, so no atomics
+//            and bitwise-reproducible sums; fused with the Brinkman correction
+//            u = (u* + kappa u^S)/(1 + kappa) (Eq. u).
+//   interp   u^ref_m = sum_x W u(x) (Eq. u_mapping), force/torque contributions in
+//            FP64, wave shuffles -> LDS -> per-block partials; the last block to finish
+//            sums the partials in fixed order (Neumaier) and applies the Euler update
+//            of Sec. 2.4 to the body state of t-1.
+// The footprint box of a step is fixed from x^G(t-1): origin floor(x^G) - H, size L,
+// wide enough for any rotation and a drift of `margin` nodes within the step.
+#pragma once
+#include "fluid.h"
+
+namespace lks {
+
+struct BodyParams {
+    double kmax, q, mass, inertia;
+    int dof;  // LKS_DOF_* bits
+};
+
+// ------------------------------------------------------------------ kappa_ref(gamma)
+template <typename T>
+__global__ __launch_bounds__(256) void k_kappa_ref(long long ND, double kmax, double q,
+                                                   const T *__restrict__ gamma, T *__restrict__ krT,
+                                                   double *__restrict__ krD) {
+    const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= ND) return;
+    const double k = kappa_of(kmax, q, (double)gamma[m]);
+    krT[m] = T(k);
+    krD[m] = k;
+}
+
+__device__ __forceinline__ void body_finish(double *B) {
+    double s, c;
+    sincos(B[B_TH], &s, &c);
+    B[B_COS] = c;
+    B[B_SIN] = s;
+    B[10] = 0.0;
+    B[11] = 0.0;
+}
+
+template <int DIM>
+__global__ void k_body_init(const double *__restrict__ body, double *__restrict__ B0) {
+    if (threadIdx.x != 0) return;
+    for (int j = 0; j < 8; j++) B0[j] = body[j];
+    body_finish(B0);
+}
+
+// Euler update (Sec. 2.4) from the state at t-1 and the force/torque; an inactive DOF
+// keeps its previous position and velocity.
+template <int DIM>
+__device__ __forceinline__ void body_update(const BodyParams &bp, const double *Bp, const double FT[4],
+                                            double *Bn) {
+    for (int j = 0; j < 8; j++) Bn[j] = Bp[j];
+#pragma unroll
+    for (int a = 0; a < DIM; a++)
+        if (bp.dof & (1 << a)) {
+            Bn[B_UG + a] = Bp[B_UG + a] + FT[a] / bp.mass;
+            Bn[B_XG + a] = Bp[B_XG + a] + Bn[B_UG + a];
+        }
+    if (bp.dof & 8) {
+        Bn[B_OM] = Bp[B_OM] + FT[3] / bp.inertia;
+        Bn[B_TH] = Bp[B_TH] + Bn[B_OM];
+    }
+    body_finish(Bn);
+}
+
+// Transpose of body_update: cotangent Bb of the updated state -> cotangent of the
+// force/torque, and the part that flows directly to the state at t-1 (added to acc).
+template <int DIM>
+__device__ __forceinline__ void body_update_rev(const BodyParams &bp, const double *Bb, double FTb[4],
+                                                double *acc) {
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        if (a < DIM && (bp.dof & (1 << a))) {
+            const double ut = Bb[B_UG + a] + Bb[B_XG + a];
+            FTb[a] = ut / bp.mass;
+            acc[B_XG + a] += Bb[B_XG + a];
+            acc[B_UG + a] += ut;
+        } else {
+            FTb[a] = 0.0;
+            acc[B_XG + a] += Bb[B_XG + a];
+            acc[B_UG + a] += Bb[B_UG + a];
+        }
+    }
+    if (bp.dof & 8) {
+        const double wt = Bb[B_OM] + Bb[B_TH];
+        FTb[3] = wt / bp.inertia;
+        acc[B_TH] += Bb[B_TH];
+        acc[B_OM] += wt;
+    } else {
+        FTb[3] = 0.0;
+        acc[B_TH] += Bb[B_TH];
+        acc[B_OM] += Bb[B_OM];
+    }
+}
+
+// ------------------------------------------------------------------ candidates
+// Design points within the support of node x at pose B: the node's position in the
+// body frame, xi0 = R^T (x - x^G), and every design index within 2 (along the
+// rotation axis) or 2(|cos| + |sin|) (in the rotation plane) of it; each candidate's
+// offset is then tested exactly. Calls f(m, W, r, pose) for W != 0.
+template <int DIM, typename T, typename F>
+__device__ __forceinline__ void for_each_candidate(const Design &D, const double *B, const int x[3], F &&f) {
+    const double c = B[B_COS], s = B[B_SIN];
+    double d[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < DIM; a++) d[a] = (double)x[a] - B[B_XG + a];
+    double xi0[3];
+    xi0[D.axis] = d[D.axis];
+    xi0[D.pi] = c * d[D.pi] + s * d[D.pj];
+    xi0[D.pj] = -s * d[D.pi] + c * d[D.pj];
+    const double rp = 2.0 * (fabs(c) + fabs(s)) + 1e-9;
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        if (a >= DIM) continue;
+        const double rho = (a == D.axis) ? 2.0 + 1e-9 : rp;
+        const double ic = xi0[a] + D.half[a];
+        int l = (int)ceil(ic - rho), h = (int)floor(ic + rho);
+        lo[a] = l < 0 ? 0 : l;
+        hi[a] = h > D.nd[a] - 1 ? D.nd[a] - 1 : h;
+    }
+    for (int kk = lo[2]; kk <= hi[2]; kk++)
+        for (int jj = lo[1]; jj <= hi[1]; jj++)
+            for (int ii = lo[0]; ii <= hi[0]; ii++) {
+                const double xi[3] = {(double)ii - D.half[0], (double)jj - D.half[1],
+                                      DIM == 3 ? (double)kk - D.half[2] : 0.0};
+                Pose P;
+                pose_point(D, B, xi, P);
+                T r[3];
+                bool in = true;
+#pragma unroll
+                for (int a = 0; a < DIM; a++) {
+                    r[a] = T((double)x[a] - P.X[a]);
+                    in = in && (r[a] < T(2) && r[a] > T(-2));
+                }
+                if (!in) continue;
+                T W = T(1);
+#pragma unroll
+                for (int a = 0; a < DIM; a++) W *= wk(r[a]);
+                const long long m = ii + (long long)D.nd[0] * (jj + (long long)D.nd[1] * kk);
+                f(m, W, P);
+            }
+}
+
+template <int DIM>
+__device__ __forceinline__ bool box_node(const Grid &g, const Design &D, const int o[3], long long l,
+                                         int x[3]) {
+    long long r = l;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        if (a < DIM) {
+            x[a] = o[a] + (int)(r % D.L[a]);
+            r /= D.L[a];
+        } else {
+            x[a] = 0;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < DIM; a++)
+        if (x[a] < 0 || x[a] >= g.n[a]) return false;
+    return is_interior<DIM>(g, x);
+}
+
+// ------------------------------------------------------------------ forward spread
+// Iteration k of a step: footprint nodes get kappa, u^S at pose B^(k) and the Brinkman
+// correction of u* (read from the state at k = 0 and kept in ustar; from ustar after).
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) void k_spread_fwd(Grid g, Design D, const double *__restrict__ Bk, int k,
+                                                    const T *__restrict__ krT, T *__restrict__ u,
+                                                    T *__restrict__ ustar) {
+    const long long l = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= D.boxN) return;
+    int o[3], x[3];
+    box_origin<DIM>(D, Bk, o);
+    if (!box_node<DIM>(g, D, o, l, x)) return;
+    const double *B = Bk + k * B_REC;
+    T kap = 0, us[3] = {0, 0, 0};
+    for_each_candidate<DIM, T>(D, B, x, [&](long long m, T W, const Pose &P) {
+        kap += W * krT[m];
+#pragma unroll
+        for (int a = 0; a < DIM; a++) us[a] += W * T(P.US[a]);
+    });
+    const long long N = g.N;
+    const long long id = node_id(g, x[0], x[1], x[2]);
+    const T inv = T(1) / (T(1) + kap);
+#pragma unroll
+    for (int a = 0; a < DIM; a++) {
+        T s;
+        if (k == 0) {
+            s = u[a * N + id];
+            ustar[a * D.boxN + l] = s;
+        } else {
+            s = ustar[a * D.boxN + l];
+        }
+        u[a * N + id] = (s + kap * us[a]) * inv;
+    }
+}
+
+// map_design: kappa, u^S on every interior node of the grid at one pose (an ABI body
+// state; cos/sin of theta are formed here).
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) void k_spread_map(Grid g, Design D, const double *__restrict__ body,
+                                                    const T *__restrict__ krT, T *__restrict__ kap_out,
+                                                    T *__restrict__ us_out) {
+    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= g.N) return;
+    double B[B_REC];
+    for (int j = 0; j < 8; j++) B[j] = body[j];
+    body_finish(B);
+    int x[3];
+    x[0] = (int)(id % g.n[0]);
+    x[1] = (int)((id / g.n[0]) % g.n[1]);
+    x[2] = (int)(id / ((long long)g.n[0] * g.n[1]));
+    T kap = 0, us[3] = {0, 0, 0};
+    if (is_interior<DIM>(g, x)) {
+        for_each_candidate<DIM, T>(D, B, x, [&](long long m, T W, const Pose &P) {
+            kap += W * krT[m];
+#pragma unroll
+            for (int a = 0; a < DIM; a++) us[a] += W * T(P.US[a]);
+        });
+    }
+    kap_out[id] = kap;
+#pragma unroll
+    for (int a = 0; a < DIM; a++) us_out[a * g.N + id] = us[a];
+}
+
+// ------------------------------------------------------------------ taps of a point
+// The 4^d nodes around x^ref (floor(X) - 1 .. floor(X) + 2 per axis), with the
+// per-axis weights; a node counts if it is an interior node of the grid.
+template <int DIM, typename T>
+struct Taps {
+    int base[3];
+    T w[3][4], dw[3][4];
+    __device__ __forceinline__ void init(const double X[3], bool want_dw) {
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            if (a >= DIM) {
+                base[a] = 0;
+                continue;
+            }
+            base[a] = (int)floor(X[a]) - 1;
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                const T r = T((double)(base[a] + t) - X[a]);
+                w[a][t] = wk(r);
+                dw[a][t] = want_dw ? dwk(r) : T(0);
+            }
+        }
+    }
+};
+
+template <int DIM>
+__device__ __forceinline__ bool tap_ok(const Grid &g, const int x[3]) {
+#pragma unroll
+    for (int a = 0; a < DIM; a++)
+        if (x[a] < 0 || x[a] >= g.n[a]) return false;
+    return is_interior<DIM>(g, x);
+}
+
+// ------------------------------------------------------------------ block reduction
+template <int NV>
+__device__ __forceinline__ void block_reduce_store(double v[NV], double *__restrict__ out) {
+    __shared__ double red[NV][16];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NV; j++) v[j] = wave_sum(v[j]);
+    if (lane == 0)
+#pragma unroll
+        for (int j = 0; j < NV; j++) red[j][wid] = v[j];
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double s = 0.0;
+        for (int w = 0; w < nw; w++) s += red[threadIdx.x][w];
+        out[(long long)blockIdx.x * NV + threadIdx.x] = s;
+    }
+}
+
+// Returns true in the one block that arrives last (all partials visible to it).
+__device__ __forceinline__ bool last_block(unsigned *counter) {
+    __shared__ bool is_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned prev = atomicAdd(counter, 1u);
+        is_last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (is_last) __threadfence();
+    return is_last;
+}
+
+// ------------------------------------------------------------------ forward interp
+// flag bits: 1 non-finite body state, 2 drift beyond the footprint margin.
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) void k_interp_force(Grid g, Design D, BodyParams bp,
+                                                      const T *__restrict__ u, const double *__restrict__ krD,
+                                                      double *__restrict__ Bk, int k, int K,
+                                                      double *__restrict__ Bnext0, double *__restrict__ part,
+                                                      unsigned *__restrict__ counter, int *__restrict__ flag) {
+    const long long N = g.N;
+    const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const double *B = Bk + k * B_REC;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (m < D.ND) {
+        double xi[3];
+        design_xi<DIM>(D, m, xi);
+        Pose P;
+        pose_point(D, B, xi, P);
+        Taps<DIM, T> tp;
+        tp.init(P.X, false);
+        T ur[3] = {0, 0, 0};
+        const int tz = DIM == 3 ? 4 : 1;
+        for (int c = 0; c < tz; c++)
+#pragma unroll
+            for (int b = 0; b < 4; b++)
+#pragma unroll
+                for (int a = 0; a < 4; a++) {
+                    const int x[3] = {tp.base[0] + a, tp.base[1] + b, tp.base[2] + c};
+                    if (!tap_ok<DIM>(g, x)) continue;
+                    const T W = tp.w[0][a] * tp.w[1][b] * (DIM == 3 ? tp.w[2][c] : T(1));
+                    const long long id = node_id(g, x[0], x[1], x[2]);
+#pragma unroll
+                    for (int e = 0; e < DIM; e++) ur[e] += W * u[e * N + id];
+                }
+        const double kr = krD[m];
+        double Dv[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int e = 0; e < DIM; e++) {
+            Dv[e] = (double)ur[e] - P.US[e];
+            v[e] = kr * Dv[e];
+        }
+        v[3] = kr * (P.r[D.pi] * Dv[D.pj] - P.r[D.pj] * Dv[D.pi]);
+    }
+    block_reduce_store<4>(v, part);
+    if (!last_block(counter)) return;
+    // fixed-order compensated sum of the partials
+    __shared__ double FT[4];
+    if (threadIdx.x < 4) {
+        Kahan s;
+        for (unsigned b = 0; b < gridDim.x; b++) s.add(part[(long long)b * 4 + threadIdx.x]);
+        FT[threadIdx.x] = s.value();
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ft[4] = {FT[0], FT[1], FT[2], FT[3]};
+        double *Bn = Bk + (k + 1) * B_REC;
+        body_update<DIM>(bp, Bk, ft, Bn);
+        bool bad = false;
+        for (int j = 0; j < 8; j++) bad = bad || !isfinite(Bn[j]);
+        if (bad) atomicOr(flag, 1);
+        if (k + 1 < K) {
+            for (int a = 0; a < DIM; a++)
+                if (fabs(Bn[B_XG + a] - Bk[B_XG + a]) > (double)D.margin) atomicOr(flag, 2);
+        } else if (Bnext0) {
+            for (int j = 0; j < B_REC; j++) Bnext0[j] = Bn[j];
+        }
+        *counter = 0u;
+    }
+}
+
+// Standalone Euler update (body_step entry point).
+template <int DIM>
+__global__ void k_body_step(BodyParams bp, const double *__restrict__ ft, const double *__restrict__ bprev,
+                            double *__restrict__ bout) {
+    if (threadIdx.x != 0) return;
+    double Bp[B_REC], Bn[B_REC], f[4];
+    for (int j = 0; j < 8; j++) Bp[j] = bprev[j];
+    for (int j = 8; j < B_REC; j++) Bp[j] = 0.0;
+    for (int j = 0; j < 4; j++) f[j] = ft[j];
+    body_update<DIM>(bp, Bp, f, Bn);
+    for (int j = 0; j < 8; j++) bout[j] = Bn[j];
+    for (int j = 8; j < 12; j++) bout[j] = bprev[j];
+}
+
+// Objective: x^G component or theta at the end minus at the start.
+__global__ void k_objective(const double *__restrict__ B0, const double *__restrict__ B1, int obj,
+                            double *__restrict__ J, double *__restrict__ body_out) {
+    if (threadIdx.x != 0) return;
+    const int j = obj == 3 ? B_TH : obj;
+    *J = B1[j] - B0[j];
+    if (body_out)
+        for (int i = 0; i < 8; i++) body_out[i] = B1[i];
+}
+
+// =================================================================== reverse sweep
+// Device record of the body adjoint (FP64):
+//   Bbar[12]  cotangent of B(t) of the step being reversed (B^(K))
+//   acc[12]   accumulating cotangent of B(t-1)
+//   FTb[4]    force/torque cotangent of the current iteration
+enum { AR_BBAR = 0, AR_ACC = 12, AR_FTB = 24, AR_SIZE = 32 };
+
+template <int DIM>
+__global__ void k_adj_init(BodyParams bp, int obj, double seed, double *__restrict__ rec) {
+    if (threadIdx.x != 0) return;
+    for (int j = 0; j < AR_SIZE; j++) rec[j] = 0.0;
+    rec[AR_BBAR + (obj == 3 ? B_TH : obj)] = seed;
+    body_update_rev<DIM>(bp, rec + AR_BBAR, rec + AR_FTB, rec + AR_ACC);
+}
+
+// Recompute, for all iterations of a step at once (blockIdx.y = k), the footprint
+// fields kappa^(k), u^S^(k), u^(k) from u* and the stored iterates B^(k). Also clears
+// the cotangent of u* on the box.
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) void k_adj_recompute(Grid g, Design D, const double *__restrict__ Bk,
+                                                       const T *__restrict__ krT, const T *__restrict__ ustar,
+                                                       T *__restrict__ kapk, T *__restrict__ usk,
+                                                       T *__restrict__ uk, T *__restrict__ ustb) {
+    const long long l = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    if (l >= D.boxN) return;
+    const long long bN = D.boxN;
+    if (k == 0)
+#pragma unroll
+        for (int a = 0; a < DIM; a++) ustb[a * bN + l] = T(0);
+    int o[3], x[3];
+    box_origin<DIM>(D, Bk, o);
+    T kap = 0, us[3] = {0, 0, 0};
+    const bool ok = box_node<DIM>(g, D, o, l, x);
+    if (ok) {
+        const double *B = Bk + k * B_REC;
+        for_each_candidate<DIM, T>(D, B, x, [&](long long m, T W, const Pose &P) {
+            kap += W * krT[m];
+#pragma unroll
+            for (int a = 0; a < DIM; a++) us[a] += W * T(P.US[a]);
+        });
+    }
+    kapk[k * bN + l] = kap;
+    const T inv = T(1) / (T(1) + kap);
+#pragma unroll
+    for (int a = 0; a < DIM; a++) {
+        usk[(k * DIM + a) * bN + l] = us[a];
+        uk[(k * DIM + a) * bN + l] = ok ? (ustar[a * bN + l] + kap * us[a]) * inv : T(0);
+    }
+}
+
+// Per-point pose cotangents -> (x^G, u^G, theta, omega) contributions.
+// Xb: cotangent of x^ref, USb: of u^S,ref, rb: of r = R xi used by the torque.
+__device__ __forceinline__ void pose_rev(const Design &D, const double *B, const Pose &P, const double Xb[3],
+                                         const double USb[3], const double rb[3], double v[8]) {
+    const int i = D.pi, j = D.pj;
+    const double om = B[B_OM];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        v[a] += Xb[a];
+        v[3 + a] += USb[a];
+    }
+    // d r / d theta = a x r = (-r_j, r_i) in the plane; d(a x r)/d theta = -(r_i, r_j)
+    v[6] += (Xb[i] + rb[i]) * (-P.r[j]) + (Xb[j] + rb[j]) * P.r[i] +
+            om * (USb[i] * (-P.r[i]) + USb[j] * (-P.r[j]));
+    v[7] += USb[i] * P.axr[i] + USb[j] * P.axr[j];
+}
+
+// R1: reverse of the force/torque and of the interpolation at iteration k.
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) void k_adj_r1(Grid g, Design D, const double *__restrict__ Bk, int k,
+                                                const T *__restrict__ uk, const double *__restrict__ krD,
+                                                const double *__restrict__ rec, T *__restrict__ URb,
+                                                double *__restrict__ krb, double *__restrict__ part) {
+    const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long bN = D.boxN;
+    const double *B = Bk + k * B_REC;
+    const T *u = uk + (long long)k * DIM * bN;
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (m < D.ND) {
+        int o[3];
+        box_origin<DIM>(D, Bk, o);
+        Box bx = {{o[0], o[1], o[2]}, {D.L[0], D.L[1], D.L[2]}};
+        double xi[3];
+        design_xi<DIM>(D, m, xi);
+        Pose P;
+        pose_point(D, B, xi, P);
+        Taps<DIM, T> tp;
+        tp.init(P.X, true);
+        T ur[3] = {0, 0, 0};
+        const int tz = DIM == 3 ? 4 : 1;
+        for (int c = 0; c < tz; c++)
+            for (int b = 0; b < 4; b++)
+                for (int a = 0; a < 4; a++) {
+                    const int x[3] = {tp.base[0] + a, tp.base[1] + b, tp.base[2] + c};
+                    if (!tap_ok<DIM>(g, x)) continue;
+                    const long long bi = box_index<DIM>(bx, x);
+                    if (bi < 0) continue;
+                    const T W = tp.w[0][a] * tp.w[1][b] * (DIM == 3 ? tp.w[2][c] : T(1));
+#pragma unroll
+                    for (int e = 0; e < DIM; e++) ur[e] += W * u[e * bN + bi];
+                }
+        const double kr = krD[m];
+        const double *FTb = rec + AR_FTB;
+        double Dv[3] = {0, 0, 0}, Db[3] = {0, 0, 0};
+#pragma unroll
+        for (int e = 0; e < DIM; e++) Dv[e] = (double)ur[e] - P.US[e];
+        double gsum = 0.0;
+#pragma unroll
+        for (int e = 0; e < DIM; e++) {
+            Db[e] = kr * (FTb[e] + FTb[3] * P.axr[e]);
+            gsum += FTb[e] * Dv[e];
+        }
+        gsum += FTb[3] * (P.r[D.pi] * Dv[D.pj] - P.r[D.pj] * Dv[D.pi]);
+        krb[m] += gsum;
+        double rb[3] = {0, 0, 0}, USb[3] = {0, 0, 0}, Xb[3] = {0, 0, 0};
+        rb[D.pi] = FTb[3] * kr * Dv[D.pj];
+        rb[D.pj] = -FTb[3] * kr * Dv[D.pi];
+#pragma unroll
+        for (int e = 0; e < DIM; e++) {
+            USb[e] = -Db[e];
+            URb[e * D.ND + m] = T(Db[e]);
+        }
+        // x^ref cotangent from the interpolation: sum_x dW/dX (Db . u(x))
+        T xb[3] = {0, 0, 0};
+        const T db[3] = {T(Db[0]), T(Db[1]), T(Db[2])};
+        for (int c = 0; c < tz; c++)
+            for (int b = 0; b < 4; b++)
+                for (int a = 0; a < 4; a++) {
+                    const int x[3] = {tp.base[0] + a, tp.base[1] + b, tp.base[2] + c};
+                    if (!tap_ok<DIM>(g, x)) continue;
+                    const long long bi = box_index<DIM>(bx, x);
+                    if (bi < 0) continue;
+                    T dot = 0;
+#pragma unroll
+                    for (int e = 0; e < DIM; e++) dot += db[e] * u[e * bN + bi];
+                    const T wz = DIM == 3 ? tp.w[2][c] : T(1);
+                    xb[0] -= tp.dw[0][a] * tp.w[1][b] * wz * dot;
+                    xb[1] -= tp.w[0][a] * tp.dw[1][b] * wz * dot;
+                    if (DIM == 3) xb[2] -= tp.w[0][a] * tp.w[1][b] * tp.dw[2][c] * dot;
+                }
+#pragma unroll
+        for (int e = 0; e < DIM; e++) Xb[e] = (double)xb[e];
+        pose_rev(D, B, P, Xb, USb, rb, v);
+    }
+    block_reduce_store<8>(v, part);
+}
+
+// R2: box nodes. u^(k) cotangent = (k = last: the step's velocity cotangent, with the
+// boundary fold) + sum_m W URb_m (transpose of the interpolation, gather form);
+// Brinkman correction reversed.
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) void k_adj_r2(Grid g, Bc bc, Design D, const double *__restrict__ Bk, int k,
+                                                int K, const T *__restrict__ ab, const T *__restrict__ URb,
+                                                const T *__restrict__ kapk, const T *__restrict__ usk,
+                                                const T *__restrict__ uk, T *__restrict__ ustb,
+                                                T *__restrict__ kb, T *__restrict__ usb) {
+    const long long l = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= D.boxN) return;
+    const long long bN = D.boxN;
+    int o[3], x[3];
+    box_origin<DIM>(D, Bk, o);
+    if (!box_node<DIM>(g, D, o, l, x)) {
+        kb[l] = T(0);
+#pragma unroll
+        for (int a = 0; a < DIM; a++) usb[a * bN + l] = T(0);
+        return;
+    }
+    T ub[3] = {0, 0, 0};
+    if (k == K - 1) {
+        const long long id = node_id(g, x[0], x[1], x[2]);
+        T pdummy;
+        fold_bc<DIM, T>(g, bc, ab, x, id, pdummy, ub, true);
+    }
+    const double *B = Bk + k * B_REC;
+    for_each_candidate<DIM, T>(D, B, x, [&](long long m, T W, const Pose &) {
+#pragma unroll
+        for (int a = 0; a < DIM; a++) ub[a] += W * URb[a * D.ND + m];
+    });
+    const T kap = kapk[k * bN + l];
+    const T inv = T(1) / (T(1) + kap);
+    T kbar = 0;
+#pragma unroll
+    for (int a = 0; a < DIM; a++) {
+        ustb[a * bN + l] += ub[a] * inv;
+        kbar += ub[a] * (usk[(k * DIM + a) * bN + l] - uk[(k * DIM + a) * bN + l]) * inv;
+        usb[a * bN + l] = ub[a] * kap * inv;
+    }
+    kb[l] = kbar;
+}
+
+// R3: transpose of the spread at iteration k (design-point parallel), the pose
+// reversed; the last block forms the body cotangent B^(k)bar and steps the record.
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) void k_adj_r3(Grid g, Design D, BodyParams bp, const double *__restrict__ Bk,
+                                                int k, const T *__restrict__ kb, const T *__restrict__ usb,
+                                                const double *__restrict__ krD, double *__restrict__ krb,
+                                                const double *__restrict__ part1, double *__restrict__ part3,
+                                                unsigned *__restrict__ counter, double *__restrict__ rec) {
+    const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long bN = D.boxN;
+    const double *B = Bk + k * B_REC;
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (m < D.ND) {
+        int o[3];
+        box_origin<DIM>(D, Bk, o);
+        Box bx = {{o[0], o[1], o[2]}, {D.L[0], D.L[1], D.L[2]}};
+        double xi[3];
+        design_xi<DIM>(D, m, xi);
+        Pose P;
+        pose_point(D, B, xi, P);
+        Taps<DIM, T> tp;
+        tp.init(P.X, true);
+        const T kr = T(krD[m]);
+        const T US[3] = {T(P.US[0]), T(P.US[1]), T(P.US[2])};
+        T ksum = 0, uss[3] = {0, 0, 0}, xb[3] = {0, 0, 0};
+        const int tz = DIM == 3 ? 4 : 1;
+        for (int c = 0; c < tz; c++)
+            for (int b = 0; b < 4; b++)
+                for (int a = 0; a < 4; a++) {
+                    const int x[3] = {tp.base[0] + a, tp.base[1] + b, tp.base[2] + c};
+                    if (!tap_ok<DIM>(g, x)) continue;
+                    const long long bi = box_index<DIM>(bx, x);
+                    if (bi < 0) continue;
+                    const T wz = DIM == 3 ? tp.w[2][c] : T(1);
+                    const T W = tp.w[0][a] * tp.w[1][b] * wz;
+                    const T kv = kb[bi];
+                    T dot = kv * kr;
+                    ksum += W * kv;
+#pragma unroll
+                    for (int e = 0; e < DIM; e++) {
+                        const T s = usb[e * bN + bi];
+                        uss[e] += W * s;
+                        dot += s * US[e];
+                    }
+                    xb[0] -= tp.dw[0][a] * tp.w[1][b] * wz * dot;
+                    xb[1] -= tp.w[0][a] * tp.dw[1][b] * wz * dot;
+                    if (DIM == 3) xb[2] -= tp.w[0][a] * tp.w[1][b] * tp.dw[2][c] * dot;
+                }
+        krb[m] += (double)ksum;
+        double Xb[3] = {0, 0, 0}, USb[3] = {0, 0, 0}, rb[3] = {0, 0, 0};
+#pragma unroll
+        for (int e = 0; e < DIM; e++) {
+            Xb[e] = (double)xb[e];
+            USb[e] = (double)uss[e];
+        }
+        pose_rev(D, B, P, Xb, USb, rb, v);
+    }
+    block_reduce_store<8>(v, part3);
+    if (!last_block(counter)) return;
+    __shared__ double Bkb[8];
+    if (threadIdx.x < 8) {
+        Kahan s;
+        for (unsigned b = 0; b < gridDim.x; b++) s.add(part1[(long long)b * 8 + threadIdx.x]);
+        for (unsigned b = 0; b < gridDim.x; b++) s.add(part3[(long long)b * 8 + threadIdx.x]);
+        Bkb[threadIdx.x] = s.value();
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double bb[B_REC];
+        for (int j = 0; j < B_REC; j++) bb[j] = j < 8 ? Bkb[j] : 0.0;
+        if (k > 0) {
+            body_update_rev<DIM>(bp, bb, rec + AR_FTB, rec + AR_ACC);
+        } else {
+            double *acc = rec + AR_ACC;
+            for (int j = 0; j < 8; j++) acc[j] += bb[j];
+            for (int j = 0; j < B_REC; j++) {
+                rec[AR_BBAR + j] = acc[j];
+                acc[j] = 0.0;
+            }
+            body_update_rev<DIM>(bp, rec + AR_BBAR, rec + AR_FTB, acc);
+        }
+        *counter = 0u;
+    }
+}
+
+// grad = krb * d kappa_ref / d gamma; optional body cotangent of t = 0.
+template <typename T>
+__global__ __launch_bounds__(256) void k_grad_final(long long ND, double kmax, double q, const T *__restrict__ gamma,
+                                                    const double *__restrict__ krb, double *__restrict__ grad,
+                                                    const double *__restrict__ rec, int obj, double seed,
+                                                    double *__restrict__ dbody0) {
+    const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < ND) grad[m] = krb[m] * dkappa_of(kmax, q, (double)gamma[m]);
+    if (m == 0 && dbody0) {
+        for (int j = 0; j < 12; j++) dbody0[j] = j < 8 ? rec[AR_BBAR + j] : 0.0;
+        dbody0[obj == 3 ? B_TH : obj] -= seed;
+    }
+}
+
+}  // namespace lks

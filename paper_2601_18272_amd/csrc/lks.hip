@@ -1,0 +1,608 @@
+// lks.hip -- host runtime and C ABI of the gfx950 library (declared in include/lks.h).
+//
+// The time loop lives on the host but every value it needs stays on the device: the
+// body state and its iterates, the force/torque, the footprint box origin and the
+// error flag never cross PCIe during a run. One call = one stream, kernels enqueued
+// back to back; lks_forward / lks_adjoint synchronise once at the end to read the
+// error flag (skipped with LKS_FLAG_ASYNC).
+//
+// Adjoint memory: checkpoints every ckpt_every steps (state + body record); the reverse
+// sweep recomputes one segment into the workspace (states, the u* footprint of every
+// step and every fluid <-> body iterate), then walks it backwards.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/lks.h"
+#include "body.h"
+
+using namespace lks;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(LKS_EHIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                        __LINE__);                                                      \
+    } while (0)
+
+constexpr size_t ALIGN = 256;
+inline size_t up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+inline unsigned blocks(long long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+struct Ctx {
+    int dim = 0, prec = 0;
+    size_t elt = 4;
+    Grid g{};
+    Bc bc{};
+    Design D{};
+    BodyParams bp{};
+    double A = 0;
+    int K = 1, NT = 0, Kc = 1;
+    bool has_body = false;
+    int face_axes = 0;
+    long long face_total = 0;
+    long long S = 0;  // elements of a state
+    unsigned nblk = 1;
+};
+
+constexpr int MARGIN = 2;
+
+// Footprint box: half-extents H from the largest distance of a design point from the
+// rotation centre (any angle if `rot_any`, else at angle theta0), plus the mapping
+// support (2) and the drift margin.
+void box_params(Ctx &c, const lks_problem_t *P, bool rot_any, double theta0) {
+    Design &D = c.D;
+    double rho[3] = {0, 0, 0};
+    const double hp = D.half[D.pi], hq = D.half[D.pj];
+    if (rot_any) {
+        const double r = std::sqrt(hp * hp + hq * hq);
+        rho[D.pi] = r;
+        rho[D.pj] = r;
+    } else {
+        const double cs = std::fabs(std::cos(theta0)), sn = std::fabs(std::sin(theta0));
+        rho[D.pi] = cs * hp + sn * hq;
+        rho[D.pj] = sn * hp + cs * hq;
+    }
+    rho[D.axis] = D.half[D.axis];
+    D.boxN = 1;
+    for (int a = 0; a < 3; a++) {
+        if (a < c.dim) {
+            D.H[a] = (int)std::ceil(rho[a] - 1e-12) + 2 + MARGIN;
+            D.L[a] = 2 * D.H[a] + 2;
+        } else {
+            D.H[a] = 0;
+            D.L[a] = 1;
+        }
+        D.boxN *= D.L[a];
+    }
+    D.margin = MARGIN;
+    (void)P;
+}
+
+int make_ctx(const lks_problem_t *P, Ctx &c) {
+    if (!P) return fail(LKS_EINVAL, "null problem");
+    if (P->dim != 2 && P->dim != 3) return fail(LKS_EINVAL, "dim must be 2 or 3 (got %d)", P->dim);
+    if (P->precision != LKS_FP32 && P->precision != LKS_FP64)
+        return fail(LKS_EINVAL, "precision must be LKS_FP32 or LKS_FP64");
+    c.dim = P->dim;
+    c.prec = P->precision;
+    c.elt = c.prec == LKS_FP32 ? 4 : 8;
+    if (c.dim == 2 && P->n[2] != 1) return fail(LKS_EINVAL, "2D problems need n[2] == 1");
+    c.g.N = 1;
+    for (int a = 0; a < 3; a++) {
+        if (P->n[a] < 1) return fail(LKS_EINVAL, "n[%d] < 1", a);
+        c.g.n[a] = P->n[a];
+        c.g.N *= P->n[a];
+    }
+    if (c.g.N > (1LL << 31)) return fail(LKS_EINVAL, "grid too large");
+    for (int a = 0; a < 3; a++) {
+        if (a >= c.dim) {
+            c.g.per[a] = 1;
+            continue;
+        }
+        const int lo = P->bc[2 * a], hi = P->bc[2 * a + 1];
+        for (int f : {lo, hi})
+            if (f < LKS_PERIODIC || f > LKS_WALL) return fail(LKS_EINVAL, "bad boundary kind %d", f);
+        if ((lo == LKS_PERIODIC) != (hi == LKS_PERIODIC))
+            return fail(LKS_EINVAL, "axis %d: PERIODIC must be set on both faces", a);
+        c.g.per[a] = lo == LKS_PERIODIC;
+        if (c.g.n[a] < 3) return fail(LKS_EINVAL, "n[%d] must be >= 3", a);
+        if (!c.g.per[a]) {
+            c.face_axes |= 1 << a;
+            c.face_total += 2 * (c.g.N / c.g.n[a]);
+        }
+    }
+    for (int f = 0; f < 6; f++) {
+        c.bc.kind[f] = f < 2 * c.dim ? P->bc[f] : LKS_PERIODIC;
+        c.bc.p[f] = P->bc_p[f];
+        for (int a = 0; a < 3; a++) c.bc.u[f][a] = P->bc_u[f][a];
+    }
+    if (!std::isfinite(P->nu)) return fail(LKS_EINVAL, "nu not finite");
+    c.A = 4.5 * (1.0 / 6.0 - P->nu);
+    c.S = (long long)(c.dim + 1) * c.g.N;
+    // design
+    Design &D = c.D;
+    D.ND = 1;
+    int zero = 0;
+    for (int a = 0; a < 3; a++) {
+        if (P->nd[a] < 0) return fail(LKS_EINVAL, "nd[%d] < 0", a);
+        zero += P->nd[a] == 0;
+        D.nd[a] = P->nd[a];
+        D.ND *= P->nd[a];
+    }
+    c.has_body = D.ND > 0;
+    if (!c.has_body && zero != 3 && !(c.dim == 2 && P->nd[0] == 0 && P->nd[1] == 0))
+        return fail(LKS_EINVAL, "nd must be all positive or all zero");
+    if (c.has_body) {
+        if (c.dim == 2 && P->nd[2] != 1) return fail(LKS_EINVAL, "2D designs need nd[2] == 1");
+        if (P->n_itr < 1) return fail(LKS_EINVAL, "n_itr must be >= 1");
+        if (!(P->mass > 0) || !(P->inertia > 0)) return fail(LKS_EINVAL, "mass and inertia must be > 0");
+        if (!std::isfinite(P->kappa_max) || !std::isfinite(P->q))
+            return fail(LKS_EINVAL, "kappa_max, q must be finite");
+    }
+    D.axis = c.dim == 2 ? 2 : P->axis;
+    if (D.axis < 0 || D.axis > 2) return fail(LKS_EINVAL, "axis must be 0, 1 or 2");
+    D.pi = (D.axis + 1) % 3;
+    D.pj = (D.axis + 2) % 3;
+    for (int a = 0; a < 3; a++) D.half[a] = D.nd[a] > 0 ? 0.5 * (D.nd[a] - 1) : 0.0;
+    if (c.dim == 2) D.half[2] = 0.0;
+    box_params(c, P, true, 0.0);
+    c.bp.kmax = P->kappa_max;
+    c.bp.q = P->q;
+    c.bp.mass = P->mass;
+    c.bp.inertia = P->inertia;
+    c.bp.dof = P->dof_mask & (c.dim == 2 ? (LKS_DOF_TX | LKS_DOF_TY | LKS_DOF_ROT) : 15);
+    c.K = c.has_body ? P->n_itr : 1;
+    if (P->n_steps < 0) return fail(LKS_EINVAL, "n_steps < 0");
+    c.NT = P->n_steps;
+    c.Kc = P->ckpt_every;
+    if (P->objective < 0 || P->objective > 3) return fail(LKS_EINVAL, "bad objective");
+    if (P->objective < 3 && P->objective >= c.dim) return fail(LKS_EINVAL, "objective axis >= dim");
+    c.nblk = c.has_body ? blocks(D.ND, 256) : 1;
+    return LKS_OK;
+}
+
+// ------------------------------------------------------------------ layout
+struct Layout {
+    size_t krT, krD, st1, ustar, Bf, Binit, part, counter, flag;
+    size_t seg, ustar_seg, Bseg, ab, kapk, usk, uk, ustb, kb, usb, URb, krb, part1, part3, rec, mom;
+    size_t total;
+};
+
+Layout layout(const Ctx &c, bool adjoint) {
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o += up(bytes);
+        return r;
+    };
+    const size_t ND = (size_t)(c.has_body ? c.D.ND : 1);
+    const size_t bN = (size_t)(c.has_body ? c.D.boxN : 1);
+    const size_t e = c.elt, d = (size_t)c.dim, K = (size_t)c.K;
+    const size_t stateB = (size_t)c.S * e;
+    const size_t rec = (K + 1) * B_REC * sizeof(double);
+    L.krT = take(ND * e);
+    L.krD = take(ND * 8);
+    L.st1 = take(stateB);
+    L.ustar = take(d * bN * e);
+    L.Bf = take(2 * rec);
+    L.Binit = take(B_REC * 8);
+    L.part = take((size_t)c.nblk * 8 * 8);
+    L.counter = take(16);
+    L.flag = take(16);
+    if (adjoint) {
+        const size_t Kc = (size_t)(c.Kc > 0 ? c.Kc : 1);
+        L.seg = take((Kc + 1) * stateB);
+        L.ustar_seg = take(Kc * d * bN * e);
+        L.Bseg = take((Kc + 2) * rec);
+        L.ab = take(2 * stateB);
+        L.kapk = take(K * bN * e);
+        L.usk = take(K * d * bN * e);
+        L.uk = take(K * d * bN * e);
+        L.ustb = take(d * bN * e);
+        L.kb = take(bN * e);
+        L.usb = take(d * bN * e);
+        L.URb = take(d * ND * e);
+        L.krb = take(ND * 8);
+        L.part1 = take((size_t)c.nblk * 8 * 8);
+        L.part3 = take((size_t)c.nblk * 8 * 8);
+        L.rec = take(AR_SIZE * 8);
+        L.mom = take(c.dim == 3 ? 10 * (size_t)c.g.N * e : 0);
+    }
+    L.total = o;
+    return L;
+}
+
+// checkpoint store: header, states, body records
+struct CkptHeader {
+    char magic[8];
+    int dim, prec, K, Kc, NT, ncp;
+    long long N, ND;
+    int H[3], L[3];
+    long long boxN;
+};
+
+size_t ckpt_count(const Ctx &c) { return c.Kc > 0 ? (size_t)((c.NT + c.Kc - 1) / c.Kc) : 0; }
+size_t ckpt_state_off(const Ctx &c, size_t i) { return up(sizeof(CkptHeader)) + i * up((size_t)c.S * c.elt); }
+size_t ckpt_body_off(const Ctx &c, size_t i) {
+    return ckpt_state_off(c, ckpt_count(c)) + i * B_REC * sizeof(double);
+}
+size_t ckpt_bytes(const Ctx &c) { return ckpt_body_off(c, ckpt_count(c)); }
+
+template <typename T> T *at(void *base, size_t off) { return (T *)((char *)base + off); }
+
+// ------------------------------------------------------------------ kernels by type
+template <typename T> struct Run {
+    const Ctx &c;
+    hipStream_t st;
+
+    void gather(const T *in, T *out) const {
+        if (c.dim == 2) {
+            dim3 grid(blocks(c.g.n[0], G2_TX), blocks(c.g.n[1], G2_TY));
+            hipLaunchKernelGGL(k_gather2d<T>, grid, dim3(G2_TX, G2_TY), 0, st, c.g, T(c.A), in, out);
+        } else {
+            hipLaunchKernelGGL(k_gather3d<T>, dim3(blocks(c.g.N, 256)), dim3(256), 0, st, c.g, T(c.A), in, out);
+        }
+    }
+    void bcs(T *s) const {
+        if (!c.face_total) return;
+        if (c.dim == 2)
+            hipLaunchKernelGGL((k_bc<2, T>), dim3(blocks(c.face_total, 256)), dim3(256), 0, st, c.g, c.bc, s,
+                               c.face_axes, c.face_total);
+        else
+            hipLaunchKernelGGL((k_bc<3, T>), dim3(blocks(c.face_total, 256)), dim3(256), 0, st, c.g, c.bc, s,
+                               c.face_axes, c.face_total);
+    }
+    // the n_itr fluid <-> body iterations of one step
+    void body_loop(T *state, double *Bk, double *Bnext0, const T *krT, const double *krD, T *ustar,
+                   double *part, unsigned *counter, int *flag) const {
+        T *u = state + c.g.N;
+        for (int k = 0; k < c.K; k++) {
+            if (c.dim == 2) {
+                hipLaunchKernelGGL((k_spread_fwd<2, T>), dim3(blocks(c.D.boxN, 256)), dim3(256), 0, st, c.g, c.D,
+                                   Bk, k, krT, u, ustar);
+                hipLaunchKernelGGL((k_interp_force<2, T>), dim3(c.nblk), dim3(256), 0, st, c.g, c.D, c.bp, u, krD,
+                                   Bk, k, c.K, Bnext0, part, counter, flag);
+            } else {
+                hipLaunchKernelGGL((k_spread_fwd<3, T>), dim3(blocks(c.D.boxN, 256)), dim3(256), 0, st, c.g, c.D,
+                                   Bk, k, krT, u, ustar);
+                hipLaunchKernelGGL((k_interp_force<3, T>), dim3(c.nblk), dim3(256), 0, st, c.g, c.D, c.bp, u, krD,
+                                   Bk, k, c.K, Bnext0, part, counter, flag);
+            }
+        }
+    }
+    // reverse of the body loop of one step (records Bk, footprint u* of the step)
+    void body_rev(const double *Bk, const T *ustar, const T *ab, const T *krT, const double *krD, const Layout &L,
+                  void *w) const {
+        T *kapk = at<T>(w, L.kapk), *usk = at<T>(w, L.usk), *uk = at<T>(w, L.uk);
+        T *ustb = at<T>(w, L.ustb), *kb = at<T>(w, L.kb), *usb = at<T>(w, L.usb), *URb = at<T>(w, L.URb);
+        double *krb = at<double>(w, L.krb), *p1 = at<double>(w, L.part1), *p3 = at<double>(w, L.part3);
+        double *rec = at<double>(w, L.rec);
+        unsigned *counter = at<unsigned>(w, L.counter);
+        const dim3 gb(blocks(c.D.boxN, 256), c.K);
+        if (c.dim == 2)
+            hipLaunchKernelGGL((k_adj_recompute<2, T>), gb, dim3(256), 0, st, c.g, c.D, Bk, krT, ustar, kapk, usk,
+                               uk, ustb);
+        else
+            hipLaunchKernelGGL((k_adj_recompute<3, T>), gb, dim3(256), 0, st, c.g, c.D, Bk, krT, ustar, kapk, usk,
+                               uk, ustb);
+        for (int k = c.K - 1; k >= 0; k--) {
+            if (c.dim == 2) {
+                hipLaunchKernelGGL((k_adj_r1<2, T>), dim3(c.nblk), dim3(256), 0, st, c.g, c.D, Bk, k, uk, krD, rec,
+                                   URb, krb, p1);
+                hipLaunchKernelGGL((k_adj_r2<2, T>), dim3(blocks(c.D.boxN, 256)), dim3(256), 0, st, c.g, c.bc, c.D,
+                                   Bk, k, c.K, ab, URb, kapk, usk, uk, ustb, kb, usb);
+                hipLaunchKernelGGL((k_adj_r3<2, T>), dim3(c.nblk), dim3(256), 0, st, c.g, c.D, c.bp, Bk, k, kb, usb,
+                                   krD, krb, p1, p3, counter, rec);
+            } else {
+                hipLaunchKernelGGL((k_adj_r1<3, T>), dim3(c.nblk), dim3(256), 0, st, c.g, c.D, Bk, k, uk, krD, rec,
+                                   URb, krb, p1);
+                hipLaunchKernelGGL((k_adj_r2<3, T>), dim3(blocks(c.D.boxN, 256)), dim3(256), 0, st, c.g, c.bc, c.D,
+                                   Bk, k, c.K, ab, URb, kapk, usk, uk, ustb, kb, usb);
+                hipLaunchKernelGGL((k_adj_r3<3, T>), dim3(c.nblk), dim3(256), 0, st, c.g, c.D, c.bp, Bk, k, kb, usb,
+                                   krD, krb, p1, p3, counter, rec);
+            }
+        }
+    }
+    void adj_gather(const T *ab, const T *ustb, const double *Bprev, const T *sprev, T *out, T *mom) const {
+        const int hb = c.has_body ? 1 : 0;
+        if (c.dim == 2) {
+            dim3 grid(blocks(c.g.n[0], G2_TX), blocks(c.g.n[1], G2_TY));
+            hipLaunchKernelGGL(k_adjgather2d<T>, grid, dim3(G2_TX, G2_TY), 0, st, c.g, c.bc, T(c.A), ab, ustb, Bprev,
+                               c.D, hb, sprev, out);
+        } else {
+            hipLaunchKernelGGL(k_adjmom3d<T>, dim3(blocks(c.g.N, 256)), dim3(256), 0, st, c.g, c.bc, ab, ustb, Bprev,
+                               c.D, hb, mom);
+            hipLaunchKernelGGL(k_adjout3d<T>, dim3(blocks(c.g.N, 256)), dim3(256), 0, st, c.g, T(c.A), mom, sprev,
+                               out);
+        }
+    }
+    void kappa_ref(const T *gamma, T *krT, double *krD) const {
+        if (!c.has_body) return;
+        hipLaunchKernelGGL(k_kappa_ref<T>, dim3(blocks(c.D.ND, 256)), dim3(256), 0, st, c.D.ND, c.bp.kmax, c.bp.q,
+                           gamma, krT, krD);
+    }
+};
+
+int check_flag(const Ctx &, const int *flag_d, hipStream_t st) {
+    int flag = 0;
+    HIP_TRY(hipMemcpyAsync(&flag, flag_d, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (flag & 1) return fail(LKS_EDIVERGED, "non-finite body state");
+    if (flag & 2) return fail(LKS_EDIVERGED, "body moved more than %d nodes within one step", MARGIN);
+    return LKS_OK;
+}
+
+template <typename T>
+int forward_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, T *state, double *body, void *ckpt,
+                 void *work, double *J, hipStream_t st) {
+    Ctx c = c0;
+    const Layout L = layout(c, false);
+    double b0[12];
+    HIP_TRY(hipMemcpyAsync(b0, body, sizeof b0, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int j = 0; j < 8; j++)
+        if (!std::isfinite(b0[j])) return fail(LKS_EINVAL, "initial body state not finite");
+    const bool rot_any = (c.bp.dof & LKS_DOF_ROT) != 0;
+    box_params(c, P, rot_any, b0[6]);
+    Run<T> R{c, st};
+    T *krT = at<T>(work, L.krT);
+    double *krD = at<double>(work, L.krD);
+    T *st1 = at<T>(work, L.st1), *ustar = at<T>(work, L.ustar);
+    double *Bf = at<double>(work, L.Bf), *Binit = at<double>(work, L.Binit), *part = at<double>(work, L.part);
+    unsigned *counter = at<unsigned>(work, L.counter);
+    int *flag = at<int>(work, L.flag);
+    const size_t rec = (size_t)(c.K + 1) * B_REC;
+    const size_t stateB = (size_t)c.S * sizeof(T);
+    HIP_TRY(hipMemsetAsync(counter, 0, 16, st));
+    HIP_TRY(hipMemsetAsync(flag, 0, 16, st));
+    R.kappa_ref(gamma, krT, krD);
+    hipLaunchKernelGGL(k_body_init<2>, dim3(1), dim3(64), 0, st, body, Bf);
+    HIP_TRY(hipMemcpyAsync(Binit, Bf, B_REC * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (ckpt) {
+        CkptHeader h{};
+        memcpy(h.magic, "LKSCKPT", 8);
+        h.dim = c.dim;
+        h.prec = c.prec;
+        h.K = c.K;
+        h.Kc = c.Kc;
+        h.NT = c.NT;
+        h.ncp = (int)ckpt_count(c);
+        h.N = c.g.N;
+        h.ND = c.has_body ? c.D.ND : 0;
+        for (int a = 0; a < 3; a++) {
+            h.H[a] = c.D.H[a];
+            h.L[a] = c.D.L[a];
+        }
+        h.boxN = c.D.boxN;
+        HIP_TRY(hipMemcpyAsync(ckpt, &h, sizeof h, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    T *cur = state, *nxt = st1;
+    for (int t = 1; t <= c.NT; t++) {
+        double *Bc = Bf + (size_t)((t - 1) & 1) * rec;
+        double *Bn = Bf + (size_t)(t & 1) * rec;
+        if (ckpt && (t - 1) % c.Kc == 0) {
+            const size_t ci = (size_t)((t - 1) / c.Kc);
+            HIP_TRY(hipMemcpyAsync(at<char>(ckpt, ckpt_state_off(c, ci)), cur, stateB, hipMemcpyDeviceToDevice, st));
+            HIP_TRY(hipMemcpyAsync(at<char>(ckpt, ckpt_body_off(c, ci)), Bc, B_REC * sizeof(double),
+                                   hipMemcpyDeviceToDevice, st));
+        }
+        R.gather(cur, nxt);
+        if (c.has_body)
+            R.body_loop(nxt, Bc, Bn, krT, krD, ustar, part, counter, flag);
+        else
+            HIP_TRY(hipMemcpyAsync(Bn, Bc, B_REC * sizeof(double), hipMemcpyDeviceToDevice, st));
+        R.bcs(nxt);
+        T *tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+        if ((t & 255) == 0) HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipGetLastError());
+    if (cur != state) HIP_TRY(hipMemcpyAsync(state, cur, stateB, hipMemcpyDeviceToDevice, st));
+    const double *Bfinal = Bf + (size_t)(c.NT & 1) * rec;
+    hipLaunchKernelGGL(k_objective, dim3(1), dim3(64), 0, st, Binit, Bfinal, P->objective, J, body);
+    HIP_TRY(hipGetLastError());
+    if (P->flags & LKS_FLAG_ASYNC) return LKS_OK;
+    return check_flag(c, flag, st);
+}
+
+template <typename T>
+int adjoint_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, const void *ckpt, void *work, double seed,
+                 double *grad, T *dstate0, double *dbody0, hipStream_t st) {
+    Ctx c = c0;
+    CkptHeader h{};
+    HIP_TRY(hipMemcpyAsync(&h, ckpt, sizeof h, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (memcmp(h.magic, "LKSCKPT", 8) != 0 || h.dim != c.dim || h.prec != c.prec || h.K != c.K || h.Kc != c.Kc ||
+        h.NT != c.NT || h.N != c.g.N || h.ND != (c.has_body ? c.D.ND : 0))
+        return fail(LKS_EINVAL, "checkpoint store does not match the problem (run lks_forward with it first)");
+    for (int a = 0; a < 3; a++) {
+        c.D.H[a] = h.H[a];
+        c.D.L[a] = h.L[a];
+    }
+    c.D.boxN = h.boxN;
+    const Layout L = layout(c0, true);  // sized with the worst-case box
+    Run<T> R{c, st};
+    T *krT = at<T>(work, L.krT);
+    double *krD = at<double>(work, L.krD);
+    double *part = at<double>(work, L.part);
+    unsigned *counter = at<unsigned>(work, L.counter);
+    int *flag = at<int>(work, L.flag);
+    T *seg = at<T>(work, L.seg), *ustar_seg = at<T>(work, L.ustar_seg), *ab = at<T>(work, L.ab);
+    double *Bseg = at<double>(work, L.Bseg), *rec = at<double>(work, L.rec), *krb = at<double>(work, L.krb);
+    T *mom = c.dim == 3 ? at<T>(work, L.mom) : nullptr;
+    T *ustb = at<T>(work, L.ustb);
+    const size_t recN = (size_t)(c.K + 1) * B_REC;
+    const size_t S = (size_t)c.S;
+    const size_t fp = (size_t)c.dim * (size_t)c.D.boxN;
+    HIP_TRY(hipMemsetAsync(counter, 0, 16, st));
+    HIP_TRY(hipMemsetAsync(flag, 0, 16, st));
+    R.kappa_ref(gamma, krT, krD);
+    if (c.has_body) HIP_TRY(hipMemsetAsync(krb, 0, (size_t)c.D.ND * 8, st));
+    HIP_TRY(hipMemsetAsync(ab, 0, S * sizeof(T), st));
+    if (c.dim == 2)
+        hipLaunchKernelGGL(k_adj_init<2>, dim3(1), dim3(64), 0, st, c.bp, P->objective, seed, rec);
+    else
+        hipLaunchKernelGGL(k_adj_init<3>, dim3(1), dim3(64), 0, st, c.bp, P->objective, seed, rec);
+    T *ab_cur = ab, *ab_nxt = ab + S;
+    const int ncp = (int)ckpt_count(c);
+    for (int ci = ncp - 1; ci >= 0; ci--) {
+        const int t0 = ci * c.Kc, t1 = std::min(t0 + c.Kc, c.NT), len = t1 - t0;
+        HIP_TRY(hipMemcpyAsync(seg, at<const char>(const_cast<void *>(ckpt), ckpt_state_off(c, ci)), S * sizeof(T),
+                               hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(Bseg + recN, at<const char>(const_cast<void *>(ckpt), ckpt_body_off(c, ci)),
+                               B_REC * sizeof(double), hipMemcpyDeviceToDevice, st));
+        // recompute the segment, keeping every state, footprint u* and iterate
+        for (int j = 1; j <= len; j++) {
+            T *prev = seg + (size_t)(j - 1) * S, *cur = seg + (size_t)j * S;
+            double *Bk = Bseg + (size_t)j * recN;
+            R.gather(prev, cur);
+            if (c.has_body)
+                R.body_loop(cur, Bk, Bseg + (size_t)(j + 1) * recN, krT, krD, ustar_seg + (size_t)(j - 1) * fp, part,
+                            counter, flag);
+            R.bcs(cur);
+        }
+        // sweep it backwards
+        for (int j = len; j >= 1; j--) {
+            const double *Bk = Bseg + (size_t)j * recN;
+            if (c.has_body) R.body_rev(Bk, ustar_seg + (size_t)(j - 1) * fp, ab_cur, krT, krD, L, work);
+            R.adj_gather(ab_cur, ustb, Bk, seg + (size_t)(j - 1) * S, ab_nxt, mom);
+            T *tmp = ab_cur;
+            ab_cur = ab_nxt;
+            ab_nxt = tmp;
+        }
+        HIP_TRY(hipGetLastError());
+    }
+    if (c.has_body)
+        hipLaunchKernelGGL(k_grad_final<T>, dim3(blocks(c.D.ND, 256)), dim3(256), 0, st, c.D.ND, c.bp.kmax, c.bp.q,
+                           gamma, krb, grad, rec, P->objective, seed, dbody0);
+    else if (dbody0)
+        HIP_TRY(hipMemsetAsync(dbody0, 0, 12 * sizeof(double), st));
+    if (dstate0) HIP_TRY(hipMemcpyAsync(dstate0, ab_cur, S * sizeof(T), hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipGetLastError());
+    if (P->flags & LKS_FLAG_ASYNC) return LKS_OK;
+    return check_flag(c, flag, st);
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+const char *lks_last_error(void) { return g_err.c_str(); }
+
+size_t lks_state_elems(const lks_problem_t *P) {
+    Ctx c;
+    if (make_ctx(P, c) != LKS_OK) return 0;
+    return (size_t)c.S;
+}
+
+size_t lks_checkpoint_bytes(const lks_problem_t *P) {
+    Ctx c;
+    if (make_ctx(P, c) != LKS_OK || c.Kc < 1) return 0;
+    return ckpt_bytes(c);
+}
+
+size_t lks_workspace_bytes(const lks_problem_t *P, int adjoint) {
+    Ctx c;
+    if (make_ctx(P, c) != LKS_OK) return 0;
+    if (adjoint && c.Kc < 1) return 0;
+    return layout(c, adjoint != 0).total;
+}
+
+int lks_forward(const lks_problem_t *P, const void *gamma, void *state, double *body, void *ckpt,
+                size_t ckpt_bytes_, void *work, size_t work_bytes, double *J, void *stream) {
+    g_err.clear();
+    Ctx c;
+    int rc = make_ctx(P, c);
+    if (rc) return rc;
+    if (!state || !body || !work || !J || (c.has_body && !gamma)) return fail(LKS_EINVAL, "null pointer argument");
+    if (work_bytes < layout(c, false).total) return fail(LKS_ENOSPACE, "work buffer too small");
+    if (ckpt) {
+        if (c.Kc < 1) return fail(LKS_EINVAL, "ckpt_every must be >= 1 to store checkpoints");
+        if (ckpt_bytes_ < ckpt_bytes(c)) return fail(LKS_ENOSPACE, "checkpoint buffer too small");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (c.prec == LKS_FP32)
+        return forward_impl<float>(c, P, (const float *)gamma, (float *)state, body, ckpt, work, J, st);
+    return forward_impl<double>(c, P, (const double *)gamma, (double *)state, body, ckpt, work, J, st);
+}
+
+int lks_adjoint(const lks_problem_t *P, const void *gamma, const void *ckpt, size_t ckpt_bytes_, void *work,
+                size_t work_bytes, double seed, double *grad, void *dstate0, double *dbody0, void *stream) {
+    g_err.clear();
+    Ctx c;
+    int rc = make_ctx(P, c);
+    if (rc) return rc;
+    if (c.Kc < 1) return fail(LKS_EINVAL, "ckpt_every must be >= 1");
+    if (!ckpt || !work || (c.has_body && (!gamma || !grad))) return fail(LKS_EINVAL, "null pointer argument");
+    if (ckpt_bytes_ < ckpt_bytes(c)) return fail(LKS_ENOSPACE, "checkpoint buffer too small");
+    if (work_bytes < layout(c, true).total) return fail(LKS_ENOSPACE, "work buffer too small");
+    if (!std::isfinite(seed)) return fail(LKS_EINVAL, "seed not finite");
+    hipStream_t st = (hipStream_t)stream;
+    if (c.prec == LKS_FP32)
+        return adjoint_impl<float>(c, P, (const float *)gamma, ckpt, work, seed, grad, (float *)dstate0, dbody0, st);
+    return adjoint_impl<double>(c, P, (const double *)gamma, ckpt, work, seed, grad, (double *)dstate0, dbody0, st);
+}
+
+int map_design(const lks_problem_t *P, const void *kappa_ref, const double *body, void *kappa, void *uS,
+               void *stream) {
+    g_err.clear();
+    Ctx c;
+    int rc = make_ctx(P, c);
+    if (rc) return rc;
+    if (!c.has_body) return fail(LKS_EINVAL, "map_design needs a design grid");
+    if (!kappa_ref || !body || !kappa || !uS) return fail(LKS_EINVAL, "null pointer argument");
+    hipStream_t st = (hipStream_t)stream;
+    const dim3 grid(blocks(c.g.N, 256));
+#define MAP_LAUNCH(D_, T_)                                                                                   \
+    hipLaunchKernelGGL((k_spread_map<D_, T_>), grid, dim3(256), 0, st, c.g, c.D, body, (const T_ *)kappa_ref, \
+                       (T_ *)kappa, (T_ *)uS)
+    if (c.dim == 2 && c.prec == LKS_FP32) MAP_LAUNCH(2, float);
+    else if (c.dim == 2) MAP_LAUNCH(2, double);
+    else if (c.prec == LKS_FP32) MAP_LAUNCH(3, float);
+    else MAP_LAUNCH(3, double);
+#undef MAP_LAUNCH
+    HIP_TRY(hipGetLastError());
+    return LKS_OK;
+}
+
+int body_step(const lks_problem_t *P, const double *ft, const double *body_prev, double *body, void *stream) {
+    g_err.clear();
+    Ctx c;
+    int rc = make_ctx(P, c);
+    if (rc) return rc;
+    if (!ft || !body_prev || !body) return fail(LKS_EINVAL, "null pointer argument");
+    if (body == body_prev) return fail(LKS_EINVAL, "body must not alias body_prev");
+    hipStream_t st = (hipStream_t)stream;
+    if (c.dim == 2)
+        hipLaunchKernelGGL(k_body_step<2>, dim3(1), dim3(64), 0, st, c.bp, ft, body_prev, body);
+    else
+        hipLaunchKernelGGL(k_body_step<3>, dim3(1), dim3(64), 0, st, c.bp, ft, body_prev, body);
+    HIP_TRY(hipGetLastError());
+    return LKS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,218 @@
+// lks_device.h -- device-side building blocks shared by the gfx950 kernels:
+// velocity sets, grid/boundary geometry, the mapping weight, the rigid-body pose.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lks {
+
+enum { BC_PERIODIC = 0, BC_VELOCITY = 1, BC_PRESSURE = 2, BC_WALL = 3 };
+
+// Body record layout (12 doubles). The first 8 entries are the ABI body state; the
+// library keeps cos(theta), sin(theta) of the same record in slots 8, 9.
+enum { B_XG = 0, B_UG = 3, B_TH = 6, B_OM = 7, B_COS = 8, B_SIN = 9, B_REC = 12 };
+
+// ------------------------------------------------------------ velocity sets
+// D2Q9 / D3Q15 (Sec. 2.2): rest, axis directions, diagonals / cube corners.
+template <int DIM> struct Lat;
+
+template <> struct Lat<2> {
+    static constexpr int Q = 9;
+    __host__ __device__ static constexpr int c(int i, int a) {
+        constexpr int t[9][3] = {{0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0}, {0, -1, 0},
+                                 {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}};
+        return t[i][a];
+    }
+    __host__ __device__ static constexpr double w(int i) {
+        return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+    }
+};
+
+template <> struct Lat<3> {
+    static constexpr int Q = 15;
+    __host__ __device__ static constexpr int c(int i, int a) {
+        constexpr int t[15][3] = {{0, 0, 0},   {1, 0, 0},   {-1, 0, 0},  {0, 1, 0},  {0, -1, 0},
+                                  {0, 0, 1},   {0, 0, -1},  {1, 1, 1},   {1, 1, -1}, {1, -1, 1},
+                                  {1, -1, -1}, {-1, 1, 1},  {-1, 1, -1}, {-1, -1, 1}, {-1, -1, -1}};
+        return t[i][a];
+    }
+    __host__ __device__ static constexpr double w(int i) {
+        return i == 0 ? 2.0 / 9.0 : (i < 7 ? 1.0 / 9.0 : 1.0 / 72.0);
+    }
+};
+
+// ------------------------------------------------------------ geometry
+struct Grid {
+    int n[3];
+    int per[3];      // axis is periodic (2D: z counts as periodic)
+    long long N;
+};
+
+struct Bc {
+    int kind[6];
+    double p[6];
+    double u[6][3];
+};
+
+__device__ __forceinline__ long long node_id(const Grid &g, int x, int y, int z) {
+    return (long long)x + (long long)g.n[0] * ((long long)y + (long long)g.n[1] * z);
+}
+
+// Wrap a coordinate on a periodic axis; report whether it lies on the grid.
+__device__ __forceinline__ bool wrap_coord(int &v, int n, int per) {
+    if (per) {
+        if (v < 0) v += n;
+        else if (v >= n) v -= n;
+        return v >= 0 && v < n;
+    }
+    return v >= 0 && v < n;
+}
+
+template <int DIM>
+__device__ __forceinline__ bool is_interior(const Grid &g, const int x[3]) {
+#pragma unroll
+    for (int a = 0; a < DIM; a++)
+        if (!g.per[a] && (x[a] == 0 || x[a] == g.n[a] - 1)) return false;
+    return true;
+}
+
+// Resolution of a boundary (non-interior) node: prescribed p and/or u and the
+// nearest interior node that supplies what is not prescribed. WALL beats VELOCITY.
+struct BcNode {
+    bool p_fixed, u_fixed;
+    double p, u[3];
+    int in[3];
+};
+
+template <int DIM>
+__device__ __forceinline__ void bc_resolve(const Grid &g, const Bc &bc, const int x[3], BcNode &r) {
+    bool wall = false;
+    int vel = -1, pres = -1;
+    r.in[0] = x[0];
+    r.in[1] = x[1];
+    r.in[2] = x[2];
+#pragma unroll
+    for (int a = 0; a < DIM; a++) {
+        if (g.per[a]) continue;
+        int f = -1;
+        if (x[a] == 0) {
+            f = 2 * a;
+            r.in[a] = 1;
+        } else if (x[a] == g.n[a] - 1) {
+            f = 2 * a + 1;
+            r.in[a] = g.n[a] - 2;
+        }
+        if (f < 0) continue;
+        const int k = bc.kind[f];
+        if (k == BC_WALL) wall = true;
+        if (k == BC_VELOCITY && vel < 0) vel = f;
+        if (k == BC_PRESSURE && pres < 0) pres = f;
+    }
+    r.p_fixed = pres >= 0;
+    r.p = pres >= 0 ? bc.p[pres] : 0.0;
+    r.u_fixed = wall || vel >= 0;
+#pragma unroll
+    for (int a = 0; a < 3; a++) r.u[a] = wall ? 0.0 : (vel >= 0 ? bc.u[vel][a] : 0.0);
+}
+
+// ------------------------------------------------------------ mapping weight
+// Eq. weight_function read as the cosine kernel w(r) = (1 + cos(pi r / 2)) / 4 on
+// |r| < 2, and its derivative -(pi/8) sin(pi r / 2).
+__device__ __forceinline__ float wk(float r) {
+    return fabsf(r) < 2.0f ? 0.25f * (1.0f + cospif(0.5f * r)) : 0.0f;
+}
+__device__ __forceinline__ double wk(double r) {
+    return fabs(r) < 2.0 ? 0.25 * (1.0 + cospi(0.5 * r)) : 0.0;
+}
+__device__ __forceinline__ float dwk(float r) {
+    return fabsf(r) < 2.0f ? -0.39269908169872414f * sinpif(0.5f * r) : 0.0f;
+}
+__device__ __forceinline__ double dwk(double r) {
+    return fabs(r) < 2.0 ? -0.39269908169872414 * sinpi(0.5 * r) : 0.0;
+}
+
+// ------------------------------------------------------------ design grid and pose
+struct Design {
+    int nd[3];
+    long long ND;
+    double half[3];   // (nd - 1) / 2: index of the rotation centre
+    int axis, pi, pj; // rotation axis and its (right-handed) plane
+    int H[3];         // footprint box: origin floor(x^G) - H, size L
+    int L[3];
+    long long boxN;
+    int margin;       // allowed drift of x^G within a step
+};
+
+// Eqs. rigid_body_position / rigid_body_velocity (rotation about `axis` through x^G):
+// r = R(theta) xi, x^ref = x^G + r, u^S,ref = u^G + omega (a x r). FP64.
+struct Pose {
+    double X[3], US[3], r[3], axr[3];
+};
+
+template <int DIM>
+__device__ __forceinline__ void design_xi(const Design &D, long long m, double xi[3]) {
+    const long long i = m % D.nd[0];
+    const long long j = (m / D.nd[0]) % D.nd[1];
+    const long long k = m / ((long long)D.nd[0] * D.nd[1]);
+    xi[0] = (double)i - D.half[0];
+    xi[1] = (double)j - D.half[1];
+    xi[2] = DIM == 3 ? (double)k - D.half[2] : 0.0;
+}
+
+__device__ __forceinline__ void pose_point(const Design &D, const double *B, const double xi[3],
+                                           Pose &o) {
+    // No contraction: the spread (gather form) and the interpolation evaluate the
+    // same positions in different kernels and must agree bit for bit.
+#pragma clang fp contract(off)
+    const double c = B[B_COS], s = B[B_SIN], om = B[B_OM];
+    const int a = D.axis, i = D.pi, j = D.pj;
+    o.r[a] = xi[a];
+    o.r[i] = c * xi[i] - s * xi[j];
+    o.r[j] = s * xi[i] + c * xi[j];
+    o.axr[a] = 0.0;
+    o.axr[i] = -o.r[j];
+    o.axr[j] = o.r[i];
+#pragma unroll
+    for (int b = 0; b < 3; b++) {
+        o.X[b] = B[B_XG + b] + o.r[b];
+        o.US[b] = B[B_UG + b] + om * o.axr[b];
+    }
+}
+
+// Footprint box of a step from the body state at t-1.
+template <int DIM>
+__device__ __forceinline__ void box_origin(const Design &D, const double *Bprev, int o[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+        o[a] = (a < DIM) ? (int)floor(Bprev[B_XG + a]) - D.H[a] : 0;
+}
+
+// Brinkman interpolation, Eq. brinkman_coefficient, and its derivative.
+__host__ __device__ __forceinline__ double kappa_of(double kmax, double q, double g) {
+    return kmax * q * g / ((1.0 - g) + q);
+}
+__host__ __device__ __forceinline__ double dkappa_of(double kmax, double q, double g) {
+    const double den = (1.0 - g) + q;
+    return kmax * q * (1.0 + q) / (den * den);
+}
+
+// ------------------------------------------------------------ reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Neumaier-compensated running sum.
+struct Kahan {
+    double s = 0.0, c = 0.0;
+    __device__ __forceinline__ void add(double x) {
+        const double t = s + x;
+        if (fabs(s) >= fabs(x)) c += (s - t) + x;
+        else c += (x - t) + s;
+        s = t;
+    }
+    __device__ __forceinline__ double value() const { return s + c; }
+};
+
+}  // namespace lks

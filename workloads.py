@@ -143,15 +143,15 @@ def duct3d(nx, ny, nz, U, nu, **kw) -> Problem:
 # K exceeds M); kappa_max is therefore set so that K = M/2 at t = 0 for the seeded
 # design. The values come from oracle/derive_kappa.py (oracle coupling constants).
 KAPPA = {
-    "config1": 0.28,
-    "config2": 1.3e-3,
-    "config4": 0.027,
-    "config5": 4.3e-3,
-    "config5d": 4.3e-3,
+    "config1": 0.278476,
+    "config2": 0.00125221,
+    "config4": 0.0266657,
+    "config5": 0.00431954,
+    "config5d": 0.910658,
 }
 # Config 3 keeps the paper's kappa_max = 300 and q = 0.1; its mass (not stated) is
 # twice the coupling constant, also from oracle/derive_kappa.py.
-MASS3 = 1.5e5
+MASS3 = 146666.0
 
 
 def config(name: str) -> Problem:
