@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Benchmark of the gfx950 library: forward + adjoint (design gradient) throughput.
+
+One bench step = one full gradient of the workload: lks_forward over all N_t time
+steps (with checkpoints) + lks_adjoint (segment recompute + reverse sweep). The
+metric is MLUPS = analysis nodes x N_t / (forward + adjoint time) / 1e6, inputs
+resident in HBM before the timed region. Also reported: FP32-vs-FP64 relative errors
+of the objective and the gradient (FP64 run of the same workload, untimed), the FP64
+speed, the dominant kernel against its roofline (durations from sampled HIP events
+inside the timed region), and the FP64 CPU oracle on a bounded sample of the same
+workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload config2]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "fwd+adjoint MLUPS, % HBM roofline; FP32 vs FP64 at stated rel. error"
+HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_TFLOPS = 157.3
+
+DESCRIPTIONS = {
+    "config1": "2D D2Q9 128x64 channel, Re 20, body free in x (M 50), design 32x32, 1000 steps",
+    "config2": "2D D2Q9 512x256 channel, Re 100, body rotating about a fixed pivot (I 1e4), "
+               "design 128x128, 10000 steps, objective rotation angle",
+    "config3": "2D D2Q9 1024x512 channel, Re 200, translating body, design 256x256, 20000 steps, "
+               "checkpoints every 250",
+    "config4": "3D D3Q15 128x64x64 duct, Re 100, 3-DOF translating body (M 500), design 48^3, "
+               "5000 steps, checkpoints every 200",
+    "config5": "3D D3Q15 256x128x128 duct, Re 300, body rotating about the duct axis + axial "
+               "translation, design 96^3, 10000 steps, checkpoints every 500",
+    "config5d": "3D D3Q15 64x32x32 duct (downscaled config5), design 24^3, 10000 steps",
+}
+
+
+def alg_bytes_per_launch(kernel, pb, elt):
+    """Bytes the method must move per launch (each field read and written once)."""
+    d, N = pb.dim, pb.N
+    if kernel == "gather":        # read p, u; write p*, u*
+        return 2 * (d + 1) * N * elt
+    if kernel == "adj_gather":    # read pbar, ubar and forward u(t-1); write pbar, ubar
+        return (3 * d + 2) * N * elt
+    return None
+
+
+def launches_per_gradient(pb):
+    NT, K = pb.n_steps, pb.n_itr
+    return {"gather": 2 * NT, "bc": 2 * NT, "spread": 2 * K * NT, "interp": 2 * K * NT,
+            "adj_gather": NT, "adj_recompute": NT, "adj_r1": K * NT, "adj_r2": K * NT,
+            "adj_r3": K * NT}
+
+
+def run_cpu_baseline(pb, sample_steps):
+    import oracle
+    import workloads as W
+
+    spb = pb.replace(n_steps=sample_steps)
+    g, s0, b0 = W.design(spb), W.initial_state(spb), W.initial_body(spb)
+    t0 = time.perf_counter()
+    J, grad = oracle.gradient(spb, g, s0, b0)
+    dt = time.perf_counter() - t0
+    return spb, J, grad, dt
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="config2")
+    ap.add_argument("--n-steps", type=int, default=None, help="override the workload's time steps")
+    ap.add_argument("--cpu-steps", type=int, default=40, help="time steps of the oracle sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the grid would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2601_18272_amd as lks
+    import workloads as W
+    from paper_2601_18272_amd import _lib
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    pb = W.config(args.workload)
+    if args.n_steps:
+        pb = pb.replace(n_steps=args.n_steps)
+    if pb.ckpt_every < 1:
+        pb = pb.replace(ckpt_every=250)
+    elt = 4
+    g = torch.tensor(W.design(pb), dtype=torch.float32, device="cuda")
+    s0 = torch.tensor(W.initial_state(pb), dtype=torch.float32, device="cuda")
+    b0 = torch.tensor(W.initial_body(pb), dtype=torch.float64, device="cuda")
+    bufs = lks.Buffers(pb, "fp32", adjoint=True)
+    flags = _lib.FLAG_PROFILE
+
+    def gradient_step():
+        _, _, J, B = lks.forward(pb, g, s0, b0, "fp32", buffers=bufs, flags=flags)
+        grad = lks.adjoint(pb, g, B, precision="fp32", flags=flags)
+        return J, grad
+
+    print(f"# workload {pb.name}: {DESCRIPTIONS.get(pb.name, '')}", file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        gradient_step()
+        print(f"# warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    _lib.profile_reset()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for i in range(args.steps):
+        J32, grad32 = gradient_step()
+        print(f"# step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_per_step = 1e3 * wall / args.steps
+    node_steps = pb.N * pb.n_steps
+    value = node_steps * args.steps / wall / 1e6
+    prof = _lib.profile_read()
+
+    # dominant kernel: largest estimated share of the gradient (sampled avg x launches)
+    lp = launches_per_gradient(pb)
+    est = {k: (ms / n) * lp[k] for k, (ms, n) in prof.items() if n > 0}
+    dom = max(est, key=est.get)
+    roof = None
+    hbm_kernels = {k: v for k, v in est.items() if alg_bytes_per_launch(k, pb, elt)}
+    for name in [dom] + sorted(hbm_kernels, key=hbm_kernels.get, reverse=True):
+        by = alg_bytes_per_launch(name, pb, elt)
+        if by is None:
+            continue
+        ms, n = prof[name]
+        avg_s = ms / n / 1e3
+        ach = by / avg_s / 1e9
+        roof = {"bound": "hbm", "kernel": name, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": by, "avg_launch_us": round(avg_s * 1e6, 3),
+                "samples": n, "dominant_kernel": dom,
+                "share_of_gradient_est": {k: round(v / sum(est.values()), 3) for k, v in est.items()}}
+        break
+
+    extra = {"ms_per_step_gpu_events": round(gpu_ms / args.steps, 3),
+             "kernel_avg_us": {k: round(ms / n * 1e3, 3) for k, (ms, n) in prof.items() if n > 0}}
+
+    if not args.no_fp64:
+        bufs64 = lks.Buffers(pb, "fp64", adjoint=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, _, J64, B64 = lks.forward(pb, g.double(), s0.double(), b0, "fp64", buffers=bufs64)
+        grad64 = lks.adjoint(pb, g.double(), B64, precision="fp64")
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t1
+        j32, j64 = J32.item(), J64.item()
+        g32, g64 = grad32.cpu().numpy(), grad64.cpu().numpy()
+        extra["fp32_vs_fp64"] = {
+            "J_fp32": j32, "J_fp64": j64, "J_rel_err": abs(j32 - j64) / max(abs(j64), 1e-300),
+            "grad_rel_l2": float(np.linalg.norm(g32 - g64) / max(np.linalg.norm(g64), 1e-300)),
+            "fp64_ms_per_step": round(t64 * 1e3, 1),
+            "speedup_fp32_over_fp64": round(t64 / (wall / args.steps), 3)}
+        del bufs64
+        print("# fp64 reference done", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu:
+        spb, Jo, go, dt = run_cpu_baseline(pb, args.cpu_steps)
+        cpu = {"value": round(spb.N * spb.n_steps / dt / 1e6, 4), "unit": "MLUPS", "cores": 1,
+               "kind": "oracle",
+               "sample": f"{pb.name} truncated to its first {spb.n_steps} time steps "
+                         f"(forward + exact adjoint, serial FP64, {dt:.1f} s)"}
+        # parity of the GPU FP32 path on the same full-grid sample
+        sb = lks.Buffers(spb, "fp32", adjoint=True)
+        _, _, Js, Bs = lks.forward(spb, g, s0, b0, "fp32", buffers=sb)
+        gs = lks.adjoint(spb, g, Bs, precision="fp32").cpu().numpy()
+        extra["oracle_parity_sample"] = {
+            "n_steps": spb.n_steps, "J_rel_err_fp32": abs(Js.item() - Jo) / max(abs(Jo), 1e-300),
+            "grad_rel_l2_fp32": float(np.linalg.norm(gs - go) / max(np.linalg.norm(go), 1e-300))}
+        print("# cpu baseline done", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{pb.name}: {DESCRIPTIONS.get(pb.name, '')}", "grid": list(pb.n[:pb.dim]),
+                   "design": list(pb.nd[:pb.dim]), "n_steps": pb.n_steps, "n_itr": pb.n_itr,
+                   "ckpt_every": pb.ckpt_every, "pass": "forward + adjoint (gradient)"},
+        "roofline": roof, "cpu_baseline": cpu, "extra": extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

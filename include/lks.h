@@ -41,7 +41,7 @@ enum { LKS_FP32 = 0, LKS_FP64 = 1 };
 enum { LKS_OBJ_DISP_X = 0, LKS_OBJ_DISP_Y = 1, LKS_OBJ_DISP_Z = 2, LKS_OBJ_ANGLE = 3 };
 /* free degrees of freedom of the body (Eqs. equation_of_motion_*) */
 enum { LKS_DOF_TX = 1, LKS_DOF_TY = 2, LKS_DOF_TZ = 4, LKS_DOF_ROT = 8 };
-enum { LKS_FLAG_ASYNC = 1 };
+enum { LKS_FLAG_ASYNC = 1, LKS_FLAG_PROFILE = 2 };
 
 enum {
     LKS_OK = 0,
@@ -151,6 +151,30 @@ int body_step(const lks_problem_t *P, const double *ft, const double *body_prev,
 
 /* Message of the last error on this thread ("" if none). */
 const char *lks_last_error(void);
+
+/*
+ * Live kernel timing. A call made with LKS_FLAG_PROFILE records HIP event pairs on its
+ * stream around the launches of a sample of its time steps (at most 32 sampled steps
+ * per call, every kernel of a sampled step) and, after its final synchronisation,
+ * adds the measured durations to process-wide totals. Not thread-safe.
+ *   kernel   LKS_K_* id
+ *   total_ms sum of the sampled launch durations (ms); samples: their number
+ * Returns LKS_OK or LKS_EINVAL for an unknown id.
+ */
+enum {
+    LKS_K_GATHER = 0,      /* LKS update of p, u on the grid */
+    LKS_K_BC = 1,          /* boundary values */
+    LKS_K_SPREAD = 2,      /* mapping design -> grid + Brinkman correction */
+    LKS_K_INTERP = 3,      /* grid -> design interpolation, force/torque, body update */
+    LKS_K_ADJ_GATHER = 4,  /* adjoint LKS update (with the boundary transpose) */
+    LKS_K_ADJ_RECOMPUTE = 5,
+    LKS_K_ADJ_R1 = 6,
+    LKS_K_ADJ_R2 = 7,
+    LKS_K_ADJ_R3 = 8,
+    LKS_K_COUNT = 9
+};
+int lks_profile_read(int kernel, double *total_ms, long long *samples);
+void lks_profile_reset(void);
 
 #ifdef __cplusplus
 }

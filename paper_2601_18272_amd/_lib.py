@@ -13,11 +13,15 @@ LIB_PATH = os.path.join(HERE, "liblks_hip.so")
 PERIODIC, VELOCITY, PRESSURE, WALL = 0, 1, 2, 3
 FP32, FP64 = 0, 1
 FLAG_ASYNC = 1
+FLAG_PROFILE = 2
+KERNELS = ("gather", "bc", "spread", "interp", "adj_gather", "adj_recompute", "adj_r1", "adj_r2",
+           "adj_r3")
 
 OK, EINVAL, ENOSPACE, EUNSTABLE, EDIVERGED, EHIP = 0, -1, -2, -3, -4, -5
 
 EXPORTS = ("lks_state_elems", "lks_checkpoint_bytes", "lks_workspace_bytes", "lks_forward",
-           "lks_adjoint", "map_design", "body_step", "lks_last_error")
+           "lks_adjoint", "map_design", "body_step", "lks_last_error", "lks_profile_read",
+           "lks_profile_reset")
 
 
 class LksProblem(C.Structure):
@@ -80,6 +84,10 @@ def load():
     L.body_step.restype = C.c_int
     L.lks_last_error.argtypes = []
     L.lks_last_error.restype = C.c_char_p
+    L.lks_profile_read.argtypes = [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]
+    L.lks_profile_read.restype = C.c_int
+    L.lks_profile_reset.argtypes = []
+    L.lks_profile_reset.restype = None
     _lib = L
     return L
 
@@ -87,3 +95,19 @@ def load():
 def check(rc: int):
     if rc != OK:
         raise LksError(rc, load().lks_last_error().decode())
+
+
+def profile_read() -> dict:
+    """{kernel name: (sampled total ms, samples)} from calls made with FLAG_PROFILE."""
+    L = load()
+    out = {}
+    for i, name in enumerate(KERNELS):
+        ms = C.c_double(0.0)
+        n = C.c_longlong(0)
+        check(L.lks_profile_read(i, C.byref(ms), C.byref(n)))
+        out[name] = (ms.value, n.value)
+    return out
+
+
+def profile_reset() -> None:
+    load().lks_profile_reset()

@@ -4,19 +4,21 @@
 // Forward, per fluid <-> body iteration k of a step:
 //   spread   kappa(x) = sum_m W kappa_ref_m, u^S(x) = sum_m W u^S,ref_m (Eqs.
 //            kappa_mapping, us_mapping) in GATHER form: every node of the footprint box
-//            inverts the pose and visits its candidate design points, so no atomics
-//            and bitwise-reproducible sums; fused with the Brinkman correction
-//            u = (u* + kappa u^S)/(1 + kappa) (Eq. u).
-//   interp   u^ref_m = sum_x W u(x) (Eq. u_mapping), force/torque contributions in
-//            FP64, wave shuffles -> LDS -> per-block partials; the last block to finish
-//            sums the partials in fixed order (Neumaier) and applies the Euler update
-//            of Sec. 2.4 to the body state of t-1.
+//            inverts the pose once (FP64) and visits its candidate design points with
+//            small FP32 body-frame offsets -- no atomics, bitwise-reproducible sums;
+//            fused with the Brinkman correction u = (u* + kappa u^S)/(1 + kappa) (Eq. u).
+//   interp   u^ref_m = sum_x W u(x) (Eq. u_mapping) over branch-free clamped taps,
+//            force/torque contributions in FP64, wave shuffles -> LDS -> per-block
+//            partials; the last block to finish sums the partials in a fixed order and
+//            applies the Euler update of Sec. 2.4 to the body state of t-1.
 // The footprint box of a step is fixed from x^G(t-1): origin floor(x^G) - H, size L,
 // wide enough for any rotation and a drift of `margin` nodes within the step.
 #pragma once
 #include "fluid.h"
 
 namespace lks {
+
+constexpr int DBLK = 128;  // threads per block of the design-point kernels
 
 struct BodyParams {
     double kmax, q, mass, inertia;
@@ -100,53 +102,82 @@ __device__ __forceinline__ void body_update_rev(const BodyParams &bp, const doub
     }
 }
 
-// ------------------------------------------------------------------ candidates
-// Design points within the support of node x at pose B: the node's position in the
-// body frame, xi0 = R^T (x - x^G), and every design index within 2 (along the
-// rotation axis) or 2(|cos| + |sin|) (in the rotation plane) of it; each candidate's
-// offset is then tested exactly. Calls f(m, W, r, pose) for W != 0.
-template <int DIM, typename T, typename F>
-__device__ __forceinline__ void for_each_candidate(const Design &D, const double *B, const int x[3], F &&f) {
+// ------------------------------------------------------------------ gather form
+// Design points within the support of node x at pose B. The node's body-frame
+// position xi0 = R^T (x - x^G) is formed once in FP64 and split into an integer design
+// index ib and a fraction f in [0, 1); a candidate ib + delta then has the body-frame
+// offset e = delta - f and the lab-frame offset r = x - x^ref = -R e, both small and
+// accurate in T. Window: delta in [-1, 2] along the rotation axis (|r| < 2) and in
+// the plane [-1, 2] without rotation, [-2, 3] with (|r| < 2 spans 2(|cos| + |sin|) <=
+// 2 sqrt 2 design spacings). Calls f(m, W, r) for every candidate with W != 0; also
+// returns d = x - x^G (FP64) for callers that rebuild lab-frame arms.
+template <int DIM, typename T, bool ROT, typename F>
+__device__ __forceinline__ void gather_design(const Design &D, const double *B, const int x[3], double d[3],
+                                              F &&f) {
     const double c = B[B_COS], s = B[B_SIN];
-    double d[3] = {0.0, 0.0, 0.0};
+    d[0] = d[1] = d[2] = 0.0;
 #pragma unroll
     for (int a = 0; a < DIM; a++) d[a] = (double)x[a] - B[B_XG + a];
     double xi0[3];
     xi0[D.axis] = d[D.axis];
     xi0[D.pi] = c * d[D.pi] + s * d[D.pj];
     xi0[D.pj] = -s * d[D.pi] + c * d[D.pj];
-    const double rp = 2.0 * (fabs(c) + fabs(s)) + 1e-9;
-    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    int ib[3] = {0, 0, 0};
+    T fr[3] = {0, 0, 0};
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         if (a >= DIM) continue;
-        const double rho = (a == D.axis) ? 2.0 + 1e-9 : rp;
-        const double ic = xi0[a] + D.half[a];
-        int l = (int)ceil(ic - rho), h = (int)floor(ic + rho);
-        lo[a] = l < 0 ? 0 : l;
-        hi[a] = h > D.nd[a] - 1 ? D.nd[a] - 1 : h;
+        const double i0 = xi0[a] + D.half[a];
+        const double fl = floor(i0);
+        ib[a] = (int)fmax(fmin(fl, 1.0e9), -1.0e9);
+        fr[a] = T(i0 - fl);
     }
-    for (int kk = lo[2]; kk <= hi[2]; kk++)
-        for (int jj = lo[1]; jj <= hi[1]; jj++)
-            for (int ii = lo[0]; ii <= hi[0]; ii++) {
-                const double xi[3] = {(double)ii - D.half[0], (double)jj - D.half[1],
-                                      DIM == 3 ? (double)kk - D.half[2] : 0.0};
-                Pose P;
-                pose_point(D, B, xi, P);
-                T r[3];
-                bool in = true;
+    const T cc = T(c), ss = T(s);
+    // along the rotation axis (3D): up to 4 candidates, weight depends on delta only
+    constexpr int NA = DIM == 3 ? 4 : 1;
+    T wa[NA];
+    int ia[NA];
 #pragma unroll
-                for (int a = 0; a < DIM; a++) {
-                    r[a] = T((double)x[a] - P.X[a]);
-                    in = in && (r[a] < T(2) && r[a] > T(-2));
-                }
-                if (!in) continue;
-                T W = T(1);
+    for (int t = 0; t < NA; t++) {
+        if (DIM == 3) {
+            const int i = ib[D.axis] + t - 1;
+            const bool ok = i >= 0 && i < D.nd[D.axis];
+            wa[t] = ok ? wk(T(t - 1) - fr[D.axis]) : T(0);  // w is even: w(-e) = w(e)
+            ia[t] = ok ? i : 0;
+        } else {
+            wa[t] = T(1);
+            ia[t] = 0;
+        }
+    }
+    constexpr int PW = ROT ? 6 : 4, P0 = ROT ? -2 : -1;
+    const int ni = D.nd[D.pi], nj = D.nd[D.pj];
+    for (int u = 0; u < PW; u++) {
+        const int ii = ib[D.pi] + P0 + u;
+        if (ii < 0 || ii >= ni) continue;
+        const T ei = T(P0 + u) - fr[D.pi];
+        for (int v = 0; v < PW; v++) {
+            const int jj = ib[D.pj] + P0 + v;
+            if (jj < 0 || jj >= nj) continue;
+            const T ej = T(P0 + v) - fr[D.pj];
+            T r[3];
+            r[D.pi] = -(cc * ei - ss * ej);
+            r[D.pj] = -(ss * ei + cc * ej);
+            if (!(fabs(r[D.pi]) < T(2) && fabs(r[D.pj]) < T(2))) continue;
+            const T wp = wk(r[D.pi]) * wk(r[D.pj]);
 #pragma unroll
-                for (int a = 0; a < DIM; a++) W *= wk(r[a]);
-                const long long m = ii + (long long)D.nd[0] * (jj + (long long)D.nd[1] * kk);
-                f(m, W, P);
+            for (int t = 0; t < NA; t++) {
+                const T W = wp * wa[t];
+                if (W == T(0)) continue;
+                r[D.axis] = DIM == 3 ? fr[D.axis] - T(t - 1) : T(0);
+                int idx[3];
+                idx[D.axis] = ia[t];
+                idx[D.pi] = ii;
+                idx[D.pj] = jj;
+                const long long m = idx[0] + (long long)D.nd[0] * (idx[1] + (long long)D.nd[1] * idx[2]);
+                f(m, W, r);
             }
+        }
+    }
 }
 
 template <int DIM>
@@ -168,10 +199,36 @@ __device__ __forceinline__ bool box_node(const Grid &g, const Design &D, const i
     return is_interior<DIM>(g, x);
 }
 
+// kappa(x) and u^S(x) at node x: sum W kappa_ref, and u^G phi + omega a x (sum W (x^ref - x^G))
+// with phi = sum W and sum W (x^ref - x^G) = phi d - sum W r formed in FP64.
+template <int DIM, typename T, bool ROT>
+__device__ __forceinline__ void spread_node(const Design &D, const double *B, const T *__restrict__ krT,
+                                            const int x[3], T &kap, T us[3]) {
+    double d[3];
+    T k = 0, phi = 0, wr[3] = {0, 0, 0};
+    gather_design<DIM, T, ROT>(D, B, x, d, [&](long long m, T W, const T r[3]) {
+        k += W * krT[m];
+        phi += W;
+#pragma unroll
+        for (int a = 0; a < DIM; a++) wr[a] += W * r[a];
+    });
+    double arm[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) arm[a] = a < DIM ? (double)phi * d[a] - (double)wr[a] : 0.0;
+    const double armp = pick3(arm, D.pi), armq = pick3(arm, D.pj);
+    double axa[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) axa[a] = a == D.axis ? 0.0 : (a == D.pi ? -armq : armp);
+    const double om = B[B_OM];
+    kap = k;
+#pragma unroll
+    for (int a = 0; a < 3; a++) us[a] = a < DIM ? T(B[B_UG + a] * (double)phi + om * axa[a]) : T(0);
+}
+
 // ------------------------------------------------------------------ forward spread
 // Iteration k of a step: footprint nodes get kappa, u^S at pose B^(k) and the Brinkman
 // correction of u* (read from the state at k = 0 and kept in ustar; from ustar after).
-template <int DIM, typename T>
+template <int DIM, typename T, bool ROT>
 __global__ __launch_bounds__(256) void k_spread_fwd(Grid g, Design D, const double *__restrict__ Bk, int k,
                                                     const T *__restrict__ krT, T *__restrict__ u,
                                                     T *__restrict__ ustar) {
@@ -180,13 +237,8 @@ __global__ __launch_bounds__(256) void k_spread_fwd(Grid g, Design D, const doub
     int o[3], x[3];
     box_origin<DIM>(D, Bk, o);
     if (!box_node<DIM>(g, D, o, l, x)) return;
-    const double *B = Bk + k * B_REC;
-    T kap = 0, us[3] = {0, 0, 0};
-    for_each_candidate<DIM, T>(D, B, x, [&](long long m, T W, const Pose &P) {
-        kap += W * krT[m];
-#pragma unroll
-        for (int a = 0; a < DIM; a++) us[a] += W * T(P.US[a]);
-    });
+    T kap, us[3];
+    spread_node<DIM, T, ROT>(D, Bk + k * B_REC, krT, x, kap, us);
     const long long N = g.N;
     const long long id = node_id(g, x[0], x[1], x[2]);
     const T inv = T(1) / (T(1) + kap);
@@ -219,56 +271,62 @@ __global__ __launch_bounds__(256) void k_spread_map(Grid g, Design D, const doub
     x[1] = (int)((id / g.n[0]) % g.n[1]);
     x[2] = (int)(id / ((long long)g.n[0] * g.n[1]));
     T kap = 0, us[3] = {0, 0, 0};
-    if (is_interior<DIM>(g, x)) {
-        for_each_candidate<DIM, T>(D, B, x, [&](long long m, T W, const Pose &P) {
-            kap += W * krT[m];
-#pragma unroll
-            for (int a = 0; a < DIM; a++) us[a] += W * T(P.US[a]);
-        });
-    }
+    if (is_interior<DIM>(g, x)) spread_node<DIM, T, true>(D, B, krT, x, kap, us);
     kap_out[id] = kap;
 #pragma unroll
     for (int a = 0; a < DIM; a++) us_out[a * g.N + id] = us[a];
 }
 
 // ------------------------------------------------------------------ taps of a point
-// The 4^d nodes around x^ref (floor(X) - 1 .. floor(X) + 2 per axis), with the
-// per-axis weights; a node counts if it is an interior node of the grid.
+// The 4^d nodes around x^ref (floor(X) - 1 .. floor(X) + 2 per axis). Per-axis weights
+// are zero for coordinates off the grid or on a boundary layer (the sums run over
+// interior nodes) and the coordinates are clamped, so the tap loops have no branches.
+// Box-relative variant: coordinates relative to the footprint box, zero weight outside.
 template <int DIM, typename T>
 struct Taps {
-    int base[3];
+    int c[3][4];
     T w[3][4], dw[3][4];
-    __device__ __forceinline__ void init(const double X[3], bool want_dw) {
+    __device__ __forceinline__ void init(const Grid &g, const double X[3], bool want_dw, const int *bo = nullptr,
+                                         const int *bl = nullptr) {
 #pragma unroll
         for (int a = 0; a < 3; a++) {
-            if (a >= DIM) {
-                base[a] = 0;
-                continue;
-            }
-            base[a] = (int)floor(X[a]) - 1;
+            const int base = a < DIM ? (int)fmax(fmin(floor(X[a]), 1.0e9), -1.0e9) - 1 : 0;
 #pragma unroll
             for (int t = 0; t < 4; t++) {
-                const T r = T((double)(base[a] + t) - X[a]);
-                w[a][t] = wk(r);
-                dw[a][t] = want_dw ? dwk(r) : T(0);
+                if (a >= DIM) {
+                    c[a][t] = 0;
+                    w[a][t] = t == 0 ? T(1) : T(0);
+                    dw[a][t] = T(0);
+                    continue;
+                }
+                const int v = base + t;
+                bool ok = v >= 0 && v < g.n[a] && (g.per[a] || (v >= 1 && v <= g.n[a] - 2));
+                int cv = v;
+                if (bo) {
+                    cv = v - bo[a];
+                    ok = ok && cv >= 0 && cv < bl[a];
+                    cv = cv < 0 ? 0 : (cv >= bl[a] ? bl[a] - 1 : cv);
+                } else {
+                    cv = v < 0 ? 0 : (v >= g.n[a] ? g.n[a] - 1 : v);
+                }
+                c[a][t] = cv;
+                const T r = T((double)v - X[a]);
+                w[a][t] = ok ? wk(r) : T(0);
+                dw[a][t] = (ok && want_dw) ? dwk(r) : T(0);
             }
         }
     }
 };
 
-template <int DIM>
-__device__ __forceinline__ bool tap_ok(const Grid &g, const int x[3]) {
-#pragma unroll
-    for (int a = 0; a < DIM; a++)
-        if (x[a] < 0 || x[a] >= g.n[a]) return false;
-    return is_interior<DIM>(g, x);
+template <typename V> __device__ __forceinline__ V sel4(const V v[4], int i) {
+    return i == 0 ? v[0] : (i == 1 ? v[1] : (i == 2 ? v[2] : v[3]));
 }
 
 // ------------------------------------------------------------------ block reduction
 template <int NV>
 __device__ __forceinline__ void block_reduce_store(double v[NV], double *__restrict__ out) {
-    __shared__ double red[NV][16];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __shared__ double red[NV][DBLK / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int j = 0; j < NV; j++) v[j] = wave_sum(v[j]);
     if (lane == 0)
@@ -277,7 +335,8 @@ __device__ __forceinline__ void block_reduce_store(double v[NV], double *__restr
     __syncthreads();
     if (threadIdx.x < NV) {
         double s = 0.0;
-        for (int w = 0; w < nw; w++) s += red[threadIdx.x][w];
+#pragma unroll
+        for (int w = 0; w < DBLK / 64; w++) s += red[threadIdx.x][w];
         out[(long long)blockIdx.x * NV + threadIdx.x] = s;
     }
 }
@@ -296,14 +355,35 @@ __device__ __forceinline__ bool last_block(unsigned *counter) {
     return is_last;
 }
 
+// Fixed-order sum of nb partial vectors of NV doubles (and optionally a second set),
+// by the first wave of the last block: lane l sums blocks l, l+64, ... (Neumaier),
+// then a fixed xor-tree. Result in out[NV] (shared memory), valid after the barrier.
+template <int NV>
+__device__ __forceinline__ void reduce_partials(const double *__restrict__ p1, const double *__restrict__ p2,
+                                                unsigned nb, double *out) {
+    if (threadIdx.x < 64) {
+#pragma unroll
+        for (int j = 0; j < NV; j++) {
+            Kahan s;
+            for (unsigned b = threadIdx.x; b < nb; b += 64) {
+                s.add(p1[(long long)b * NV + j]);
+                if (p2) s.add(p2[(long long)b * NV + j]);
+            }
+            const double v = wave_sum(s.value());
+            if (threadIdx.x == 0) out[j] = v;
+        }
+    }
+    __syncthreads();
+}
+
 // ------------------------------------------------------------------ forward interp
 // flag bits: 1 non-finite body state, 2 drift beyond the footprint margin.
 template <int DIM, typename T>
-__global__ __launch_bounds__(256) void k_interp_force(Grid g, Design D, BodyParams bp,
-                                                      const T *__restrict__ u, const double *__restrict__ krD,
-                                                      double *__restrict__ Bk, int k, int K,
-                                                      double *__restrict__ Bnext0, double *__restrict__ part,
-                                                      unsigned *__restrict__ counter, int *__restrict__ flag) {
+__global__ __launch_bounds__(DBLK) void k_interp_force(Grid g, Design D, BodyParams bp,
+                                                       const T *__restrict__ u, const double *__restrict__ krD,
+                                                       double *__restrict__ Bk, int k, int K,
+                                                       double *__restrict__ Bnext0, double *__restrict__ part,
+                                                       unsigned *__restrict__ counter, int *__restrict__ flag) {
     const long long N = g.N;
     const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const double *B = Bk + k * B_REC;
@@ -314,21 +394,26 @@ __global__ __launch_bounds__(256) void k_interp_force(Grid g, Design D, BodyPara
         Pose P;
         pose_point(D, B, xi, P);
         Taps<DIM, T> tp;
-        tp.init(P.X, false);
+        tp.init(g, P.X, false);
         T ur[3] = {0, 0, 0};
-        const int tz = DIM == 3 ? 4 : 1;
-        for (int c = 0; c < tz; c++)
+        constexpr int TZ = DIM == 3 ? 4 : 1;
+#pragma unroll 1
+        for (int c = 0; c < TZ; c++) {
+            const T wz = sel4(tp.w[2], c);
+            const int cz = sel4(tp.c[2], c);
 #pragma unroll
-            for (int b = 0; b < 4; b++)
+            for (int b = 0; b < 4; b++) {
+                const T wyz = tp.w[1][b] * wz;
+                const long long row = (long long)g.n[0] * (tp.c[1][b] + (long long)g.n[1] * cz);
 #pragma unroll
                 for (int a = 0; a < 4; a++) {
-                    const int x[3] = {tp.base[0] + a, tp.base[1] + b, tp.base[2] + c};
-                    if (!tap_ok<DIM>(g, x)) continue;
-                    const T W = tp.w[0][a] * tp.w[1][b] * (DIM == 3 ? tp.w[2][c] : T(1));
-                    const long long id = node_id(g, x[0], x[1], x[2]);
+                    const T W = tp.w[0][a] * wyz;
+                    const long long id = row + tp.c[0][a];
 #pragma unroll
                     for (int e = 0; e < DIM; e++) ur[e] += W * u[e * N + id];
                 }
+            }
+        }
         const double kr = krD[m];
         double Dv[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -336,18 +421,12 @@ __global__ __launch_bounds__(256) void k_interp_force(Grid g, Design D, BodyPara
             Dv[e] = (double)ur[e] - P.US[e];
             v[e] = kr * Dv[e];
         }
-        v[3] = kr * (P.r[D.pi] * Dv[D.pj] - P.r[D.pj] * Dv[D.pi]);
+        v[3] = kr * (pick3(P.r, D.pi) * pick3(Dv, D.pj) - pick3(P.r, D.pj) * pick3(Dv, D.pi));
     }
     block_reduce_store<4>(v, part);
     if (!last_block(counter)) return;
-    // fixed-order compensated sum of the partials
     __shared__ double FT[4];
-    if (threadIdx.x < 4) {
-        Kahan s;
-        for (unsigned b = 0; b < gridDim.x; b++) s.add(part[(long long)b * 4 + threadIdx.x]);
-        FT[threadIdx.x] = s.value();
-    }
-    __syncthreads();
+    reduce_partials<4>(part, nullptr, gridDim.x, FT);
     if (threadIdx.x == 0) {
         double ft[4] = {FT[0], FT[1], FT[2], FT[3]};
         double *Bn = Bk + (k + 1) * B_REC;
@@ -357,7 +436,7 @@ __global__ __launch_bounds__(256) void k_interp_force(Grid g, Design D, BodyPara
         if (bad) atomicOr(flag, 1);
         if (k + 1 < K) {
             for (int a = 0; a < DIM; a++)
-                if (fabs(Bn[B_XG + a] - Bk[B_XG + a]) > (double)D.margin) atomicOr(flag, 2);
+                if (!(fabs(Bn[B_XG + a] - Bk[B_XG + a]) <= (double)D.margin)) atomicOr(flag, 2);
         } else if (Bnext0) {
             for (int j = 0; j < B_REC; j++) Bnext0[j] = Bn[j];
         }
@@ -407,7 +486,7 @@ __global__ void k_adj_init(BodyParams bp, int obj, double seed, double *__restri
 // Recompute, for all iterations of a step at once (blockIdx.y = k), the footprint
 // fields kappa^(k), u^S^(k), u^(k) from u* and the stored iterates B^(k). Also clears
 // the cotangent of u* on the box.
-template <int DIM, typename T>
+template <int DIM, typename T, bool ROT>
 __global__ __launch_bounds__(256) void k_adj_recompute(Grid g, Design D, const double *__restrict__ Bk,
                                                        const T *__restrict__ krT, const T *__restrict__ ustar,
                                                        T *__restrict__ kapk, T *__restrict__ usk,
@@ -423,14 +502,7 @@ __global__ __launch_bounds__(256) void k_adj_recompute(Grid g, Design D, const d
     box_origin<DIM>(D, Bk, o);
     T kap = 0, us[3] = {0, 0, 0};
     const bool ok = box_node<DIM>(g, D, o, l, x);
-    if (ok) {
-        const double *B = Bk + k * B_REC;
-        for_each_candidate<DIM, T>(D, B, x, [&](long long m, T W, const Pose &P) {
-            kap += W * krT[m];
-#pragma unroll
-            for (int a = 0; a < DIM; a++) us[a] += W * T(P.US[a]);
-        });
-    }
+    if (ok) spread_node<DIM, T, ROT>(D, Bk + k * B_REC, krT, x, kap, us);
     kapk[k * bN + l] = kap;
     const T inv = T(1) / (T(1) + kap);
 #pragma unroll
@@ -451,18 +523,20 @@ __device__ __forceinline__ void pose_rev(const Design &D, const double *B, const
         v[a] += Xb[a];
         v[3 + a] += USb[a];
     }
+    const double ri = pick3(P.r, i), rj = pick3(P.r, j);
+    const double ui = pick3(USb, i), uj = pick3(USb, j);
     // d r / d theta = a x r = (-r_j, r_i) in the plane; d(a x r)/d theta = -(r_i, r_j)
-    v[6] += (Xb[i] + rb[i]) * (-P.r[j]) + (Xb[j] + rb[j]) * P.r[i] +
-            om * (USb[i] * (-P.r[i]) + USb[j] * (-P.r[j]));
-    v[7] += USb[i] * P.axr[i] + USb[j] * P.axr[j];
+    v[6] += (pick3(Xb, i) + pick3(rb, i)) * (-rj) + (pick3(Xb, j) + pick3(rb, j)) * ri +
+            om * (ui * (-ri) + uj * (-rj));
+    v[7] += ui * (-rj) + uj * ri;
 }
 
 // R1: reverse of the force/torque and of the interpolation at iteration k.
 template <int DIM, typename T>
-__global__ __launch_bounds__(256) void k_adj_r1(Grid g, Design D, const double *__restrict__ Bk, int k,
-                                                const T *__restrict__ uk, const double *__restrict__ krD,
-                                                const double *__restrict__ rec, T *__restrict__ URb,
-                                                double *__restrict__ krb, double *__restrict__ part) {
+__global__ __launch_bounds__(DBLK) void k_adj_r1(Grid g, Design D, const double *__restrict__ Bk, int k,
+                                                 const T *__restrict__ uk, const double *__restrict__ krD,
+                                                 const double *__restrict__ rec, T *__restrict__ URb,
+                                                 double *__restrict__ krb, double *__restrict__ part) {
     const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long bN = D.boxN;
     const double *B = Bk + k * B_REC;
@@ -471,26 +545,29 @@ __global__ __launch_bounds__(256) void k_adj_r1(Grid g, Design D, const double *
     if (m < D.ND) {
         int o[3];
         box_origin<DIM>(D, Bk, o);
-        Box bx = {{o[0], o[1], o[2]}, {D.L[0], D.L[1], D.L[2]}};
         double xi[3];
         design_xi<DIM>(D, m, xi);
         Pose P;
         pose_point(D, B, xi, P);
         Taps<DIM, T> tp;
-        tp.init(P.X, true);
+        tp.init(g, P.X, true, o, D.L);
+        constexpr int TZ = DIM == 3 ? 4 : 1;
         T ur[3] = {0, 0, 0};
-        const int tz = DIM == 3 ? 4 : 1;
-        for (int c = 0; c < tz; c++)
-            for (int b = 0; b < 4; b++)
-                for (int a = 0; a < 4; a++) {
-                    const int x[3] = {tp.base[0] + a, tp.base[1] + b, tp.base[2] + c};
-                    if (!tap_ok<DIM>(g, x)) continue;
-                    const long long bi = box_index<DIM>(bx, x);
-                    if (bi < 0) continue;
-                    const T W = tp.w[0][a] * tp.w[1][b] * (DIM == 3 ? tp.w[2][c] : T(1));
+#pragma unroll 1
+        for (int c = 0; c < TZ; c++) {
+            const T wz = sel4(tp.w[2], c);
+            const int cz = sel4(tp.c[2], c);
 #pragma unroll
-                    for (int e = 0; e < DIM; e++) ur[e] += W * u[e * bN + bi];
+            for (int b = 0; b < 4; b++) {
+                const long long row = (long long)D.L[0] * (tp.c[1][b] + (long long)D.L[1] * cz);
+#pragma unroll
+                for (int a = 0; a < 4; a++) {
+                    const T W = tp.w[0][a] * tp.w[1][b] * wz;
+#pragma unroll
+                    for (int e = 0; e < DIM; e++) ur[e] += W * u[e * bN + row + tp.c[0][a]];
                 }
+            }
+        }
         const double kr = krD[m];
         const double *FTb = rec + AR_FTB;
         double Dv[3] = {0, 0, 0}, Db[3] = {0, 0, 0};
@@ -502,11 +579,13 @@ __global__ __launch_bounds__(256) void k_adj_r1(Grid g, Design D, const double *
             Db[e] = kr * (FTb[e] + FTb[3] * P.axr[e]);
             gsum += FTb[e] * Dv[e];
         }
-        gsum += FTb[3] * (P.r[D.pi] * Dv[D.pj] - P.r[D.pj] * Dv[D.pi]);
+        const double dp = pick3(Dv, D.pi), dq = pick3(Dv, D.pj);
+        gsum += FTb[3] * (pick3(P.r, D.pi) * dq - pick3(P.r, D.pj) * dp);
         krb[m] += gsum;
-        double rb[3] = {0, 0, 0}, USb[3] = {0, 0, 0}, Xb[3] = {0, 0, 0};
-        rb[D.pi] = FTb[3] * kr * Dv[D.pj];
-        rb[D.pj] = -FTb[3] * kr * Dv[D.pi];
+        double rb[3], USb[3] = {0, 0, 0}, Xb[3] = {0, 0, 0};
+#pragma unroll
+        for (int e = 0; e < 3; e++)
+            rb[e] = e == D.pi ? FTb[3] * kr * dq : (e == D.pj ? -FTb[3] * kr * dp : 0.0);
 #pragma unroll
         for (int e = 0; e < DIM; e++) {
             USb[e] = -Db[e];
@@ -515,21 +594,24 @@ __global__ __launch_bounds__(256) void k_adj_r1(Grid g, Design D, const double *
         // x^ref cotangent from the interpolation: sum_x dW/dX (Db . u(x))
         T xb[3] = {0, 0, 0};
         const T db[3] = {T(Db[0]), T(Db[1]), T(Db[2])};
-        for (int c = 0; c < tz; c++)
-            for (int b = 0; b < 4; b++)
+#pragma unroll 1
+        for (int c = 0; c < TZ; c++) {
+            const T wz = sel4(tp.w[2], c), dwz = sel4(tp.dw[2], c);
+            const int cz = sel4(tp.c[2], c);
+#pragma unroll
+            for (int b = 0; b < 4; b++) {
+                const long long row = (long long)D.L[0] * (tp.c[1][b] + (long long)D.L[1] * cz);
+#pragma unroll
                 for (int a = 0; a < 4; a++) {
-                    const int x[3] = {tp.base[0] + a, tp.base[1] + b, tp.base[2] + c};
-                    if (!tap_ok<DIM>(g, x)) continue;
-                    const long long bi = box_index<DIM>(bx, x);
-                    if (bi < 0) continue;
                     T dot = 0;
 #pragma unroll
-                    for (int e = 0; e < DIM; e++) dot += db[e] * u[e * bN + bi];
-                    const T wz = DIM == 3 ? tp.w[2][c] : T(1);
+                    for (int e = 0; e < DIM; e++) dot += db[e] * u[e * bN + row + tp.c[0][a]];
                     xb[0] -= tp.dw[0][a] * tp.w[1][b] * wz * dot;
                     xb[1] -= tp.w[0][a] * tp.dw[1][b] * wz * dot;
-                    if (DIM == 3) xb[2] -= tp.w[0][a] * tp.w[1][b] * tp.dw[2][c] * dot;
+                    if (DIM == 3) xb[2] -= tp.w[0][a] * tp.w[1][b] * dwz * dot;
                 }
+            }
+        }
 #pragma unroll
         for (int e = 0; e < DIM; e++) Xb[e] = (double)xb[e];
         pose_rev(D, B, P, Xb, USb, rb, v);
@@ -540,7 +622,7 @@ __global__ __launch_bounds__(256) void k_adj_r1(Grid g, Design D, const double *
 // R2: box nodes. u^(k) cotangent = (k = last: the step's velocity cotangent, with the
 // boundary fold) + sum_m W URb_m (transpose of the interpolation, gather form);
 // Brinkman correction reversed.
-template <int DIM, typename T>
+template <int DIM, typename T, bool ROT>
 __global__ __launch_bounds__(256) void k_adj_r2(Grid g, Bc bc, Design D, const double *__restrict__ Bk, int k,
                                                 int K, const T *__restrict__ ab, const T *__restrict__ URb,
                                                 const T *__restrict__ kapk, const T *__restrict__ usk,
@@ -563,8 +645,8 @@ __global__ __launch_bounds__(256) void k_adj_r2(Grid g, Bc bc, Design D, const d
         T pdummy;
         fold_bc<DIM, T>(g, bc, ab, x, id, pdummy, ub, true);
     }
-    const double *B = Bk + k * B_REC;
-    for_each_candidate<DIM, T>(D, B, x, [&](long long m, T W, const Pose &) {
+    double d[3];
+    gather_design<DIM, T, ROT>(D, Bk + k * B_REC, x, d, [&](long long m, T W, const T *) {
 #pragma unroll
         for (int a = 0; a < DIM; a++) ub[a] += W * URb[a * D.ND + m];
     });
@@ -583,11 +665,11 @@ __global__ __launch_bounds__(256) void k_adj_r2(Grid g, Bc bc, Design D, const d
 // R3: transpose of the spread at iteration k (design-point parallel), the pose
 // reversed; the last block forms the body cotangent B^(k)bar and steps the record.
 template <int DIM, typename T>
-__global__ __launch_bounds__(256) void k_adj_r3(Grid g, Design D, BodyParams bp, const double *__restrict__ Bk,
-                                                int k, const T *__restrict__ kb, const T *__restrict__ usb,
-                                                const double *__restrict__ krD, double *__restrict__ krb,
-                                                const double *__restrict__ part1, double *__restrict__ part3,
-                                                unsigned *__restrict__ counter, double *__restrict__ rec) {
+__global__ __launch_bounds__(DBLK) void k_adj_r3(Grid g, Design D, BodyParams bp, const double *__restrict__ Bk,
+                                                 int k, const T *__restrict__ kb, const T *__restrict__ usb,
+                                                 const double *__restrict__ krD, double *__restrict__ krb,
+                                                 const double *__restrict__ part1, double *__restrict__ part3,
+                                                 unsigned *__restrict__ counter, double *__restrict__ rec) {
     const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long bN = D.boxN;
     const double *B = Bk + k * B_REC;
@@ -595,25 +677,26 @@ __global__ __launch_bounds__(256) void k_adj_r3(Grid g, Design D, BodyParams bp,
     if (m < D.ND) {
         int o[3];
         box_origin<DIM>(D, Bk, o);
-        Box bx = {{o[0], o[1], o[2]}, {D.L[0], D.L[1], D.L[2]}};
         double xi[3];
         design_xi<DIM>(D, m, xi);
         Pose P;
         pose_point(D, B, xi, P);
         Taps<DIM, T> tp;
-        tp.init(P.X, true);
+        tp.init(g, P.X, true, o, D.L);
         const T kr = T(krD[m]);
         const T US[3] = {T(P.US[0]), T(P.US[1]), T(P.US[2])};
         T ksum = 0, uss[3] = {0, 0, 0}, xb[3] = {0, 0, 0};
-        const int tz = DIM == 3 ? 4 : 1;
-        for (int c = 0; c < tz; c++)
-            for (int b = 0; b < 4; b++)
+        constexpr int TZ = DIM == 3 ? 4 : 1;
+#pragma unroll 1
+        for (int c = 0; c < TZ; c++) {
+            const T wz = sel4(tp.w[2], c), dwz = sel4(tp.dw[2], c);
+            const int cz = sel4(tp.c[2], c);
+#pragma unroll
+            for (int b = 0; b < 4; b++) {
+                const long long row = (long long)D.L[0] * (tp.c[1][b] + (long long)D.L[1] * cz);
+#pragma unroll
                 for (int a = 0; a < 4; a++) {
-                    const int x[3] = {tp.base[0] + a, tp.base[1] + b, tp.base[2] + c};
-                    if (!tap_ok<DIM>(g, x)) continue;
-                    const long long bi = box_index<DIM>(bx, x);
-                    if (bi < 0) continue;
-                    const T wz = DIM == 3 ? tp.w[2][c] : T(1);
+                    const long long bi = row + tp.c[0][a];
                     const T W = tp.w[0][a] * tp.w[1][b] * wz;
                     const T kv = kb[bi];
                     T dot = kv * kr;
@@ -626,8 +709,10 @@ __global__ __launch_bounds__(256) void k_adj_r3(Grid g, Design D, BodyParams bp,
                     }
                     xb[0] -= tp.dw[0][a] * tp.w[1][b] * wz * dot;
                     xb[1] -= tp.w[0][a] * tp.dw[1][b] * wz * dot;
-                    if (DIM == 3) xb[2] -= tp.w[0][a] * tp.w[1][b] * tp.dw[2][c] * dot;
+                    if (DIM == 3) xb[2] -= tp.w[0][a] * tp.w[1][b] * dwz * dot;
                 }
+            }
+        }
         krb[m] += (double)ksum;
         double Xb[3] = {0, 0, 0}, USb[3] = {0, 0, 0}, rb[3] = {0, 0, 0};
 #pragma unroll
@@ -640,13 +725,7 @@ __global__ __launch_bounds__(256) void k_adj_r3(Grid g, Design D, BodyParams bp,
     block_reduce_store<8>(v, part3);
     if (!last_block(counter)) return;
     __shared__ double Bkb[8];
-    if (threadIdx.x < 8) {
-        Kahan s;
-        for (unsigned b = 0; b < gridDim.x; b++) s.add(part1[(long long)b * 8 + threadIdx.x]);
-        for (unsigned b = 0; b < gridDim.x; b++) s.add(part3[(long long)b * 8 + threadIdx.x]);
-        Bkb[threadIdx.x] = s.value();
-    }
-    __syncthreads();
+    reduce_partials<8>(part1, part3, gridDim.x, Bkb);
     if (threadIdx.x == 0) {
         double bb[B_REC];
         for (int j = 0; j < B_REC; j++) bb[j] = j < 8 ? Bkb[j] : 0.0;

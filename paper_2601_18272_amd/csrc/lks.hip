@@ -16,6 +16,8 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
+#include <vector>
 
 #include "../../include/lks.h"
 #include "body.h"
@@ -48,6 +50,50 @@ constexpr size_t ALIGN = 256;
 inline size_t up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 inline unsigned blocks(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// ------------------------------------------------------------------ live kernel timing
+// Sampled HIP event pairs around launches (LKS_FLAG_PROFILE); durations are read after
+// the call's final synchronisation and added to process-wide totals.
+std::vector<hipEvent_t> g_events;
+double g_prof_ms[LKS_K_COUNT];
+long long g_prof_n[LKS_K_COUNT];
+
+struct Prof {
+    bool on = false;
+    bool sample = false;
+    hipStream_t st = nullptr;
+    std::vector<int> ids;
+
+    template <typename F> void run(int id, F &&launch) {
+        if (!on || !sample) {
+            launch();
+            return;
+        }
+        const size_t i = ids.size();
+        while (g_events.size() < 2 * (i + 1)) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) {
+                launch();
+                return;
+            }
+            g_events.push_back(e);
+        }
+        (void)hipEventRecord(g_events[2 * i], st);
+        launch();
+        (void)hipEventRecord(g_events[2 * i + 1], st);
+        ids.push_back(id);
+    }
+    void finish() {
+        for (size_t i = 0; i < ids.size(); i++) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, g_events[2 * i], g_events[2 * i + 1]) == hipSuccess) {
+                g_prof_ms[ids[i]] += ms;
+                g_prof_n[ids[i]] += 1;
+            }
+        }
+        ids.clear();
+    }
+};
+
 struct Ctx {
     int dim = 0, prec = 0;
     size_t elt = 4;
@@ -58,6 +104,7 @@ struct Ctx {
     double A = 0;
     int K = 1, NT = 0, Kc = 1;
     bool has_body = false;
+    bool rot = true;  // the pose may rotate (wider gather window)
     int face_axes = 0;
     long long face_total = 0;
     long long S = 0;  // elements of a state
@@ -95,6 +142,8 @@ void box_params(Ctx &c, const lks_problem_t *P, bool rot_any, double theta0) {
         D.boxN *= D.L[a];
     }
     D.margin = MARGIN;
+    const double sn = std::fabs(std::sin(theta0)), cs = std::fabs(std::cos(theta0));
+    c.rot = rot_any || std::min(sn, cs) > 1e-12;
     (void)P;
 }
 
@@ -177,7 +226,7 @@ int make_ctx(const lks_problem_t *P, Ctx &c) {
     c.Kc = P->ckpt_every;
     if (P->objective < 0 || P->objective > 3) return fail(LKS_EINVAL, "bad objective");
     if (P->objective < 3 && P->objective >= c.dim) return fail(LKS_EINVAL, "objective axis >= dim");
-    c.nblk = c.has_body ? blocks(D.ND, 256) : 1;
+    c.nblk = c.has_body ? blocks(D.ND, DBLK) : 1;
     return LKS_OK;
 }
 
@@ -240,6 +289,7 @@ struct CkptHeader {
     long long N, ND;
     int H[3], L[3];
     long long boxN;
+    int rot;
 };
 
 size_t ckpt_count(const Ctx &c) { return c.Kc > 0 ? (size_t)((c.NT + c.Kc - 1) / c.Kc) : 0; }
@@ -252,44 +302,65 @@ size_t ckpt_bytes(const Ctx &c) { return ckpt_body_off(c, ckpt_count(c)); }
 template <typename T> T *at(void *base, size_t off) { return (T *)((char *)base + off); }
 
 // ------------------------------------------------------------------ kernels by type
+// Calls f(dim, rot) with compile-time constants matching the problem.
+template <typename F> void dispatch(const Ctx &c, F &&f) {
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    if (c.dim == 2) {
+        if (c.rot) f(I2{}, std::true_type{});
+        else f(I2{}, std::false_type{});
+    } else {
+        if (c.rot) f(I3{}, std::true_type{});
+        else f(I3{}, std::false_type{});
+    }
+}
+
 template <typename T> struct Run {
     const Ctx &c;
     hipStream_t st;
+    Prof *pf;
 
     void gather(const T *in, T *out) const {
         if (c.dim == 2) {
             dim3 grid(blocks(c.g.n[0], G2_TX), blocks(c.g.n[1], G2_TY));
-            hipLaunchKernelGGL(k_gather2d<T>, grid, dim3(G2_TX, G2_TY), 0, st, c.g, T(c.A), in, out);
+            pf->run(LKS_K_GATHER, [&] {
+                hipLaunchKernelGGL(k_gather2d<T>, grid, dim3(G2_TX, G2_TY), 0, st, c.g, T(c.A), in, out);
+            });
         } else {
-            hipLaunchKernelGGL(k_gather3d<T>, dim3(blocks(c.g.N, 256)), dim3(256), 0, st, c.g, T(c.A), in, out);
+            pf->run(LKS_K_GATHER, [&] {
+                hipLaunchKernelGGL(k_gather3d<T>, dim3(blocks(c.g.N, 256)), dim3(256), 0, st, c.g, T(c.A), in, out);
+            });
         }
     }
     void bcs(T *s) const {
         if (!c.face_total) return;
-        if (c.dim == 2)
-            hipLaunchKernelGGL((k_bc<2, T>), dim3(blocks(c.face_total, 256)), dim3(256), 0, st, c.g, c.bc, s,
-                               c.face_axes, c.face_total);
-        else
-            hipLaunchKernelGGL((k_bc<3, T>), dim3(blocks(c.face_total, 256)), dim3(256), 0, st, c.g, c.bc, s,
-                               c.face_axes, c.face_total);
+        pf->run(LKS_K_BC, [&] {
+            if (c.dim == 2)
+                hipLaunchKernelGGL((k_bc<2, T>), dim3(blocks(c.face_total, 256)), dim3(256), 0, st, c.g, c.bc, s,
+                                   c.face_axes, c.face_total);
+            else
+                hipLaunchKernelGGL((k_bc<3, T>), dim3(blocks(c.face_total, 256)), dim3(256), 0, st, c.g, c.bc, s,
+                                   c.face_axes, c.face_total);
+        });
     }
     // the n_itr fluid <-> body iterations of one step
     void body_loop(T *state, double *Bk, double *Bnext0, const T *krT, const double *krD, T *ustar,
                    double *part, unsigned *counter, int *flag) const {
         T *u = state + c.g.N;
-        for (int k = 0; k < c.K; k++) {
-            if (c.dim == 2) {
-                hipLaunchKernelGGL((k_spread_fwd<2, T>), dim3(blocks(c.D.boxN, 256)), dim3(256), 0, st, c.g, c.D,
-                                   Bk, k, krT, u, ustar);
-                hipLaunchKernelGGL((k_interp_force<2, T>), dim3(c.nblk), dim3(256), 0, st, c.g, c.D, c.bp, u, krD,
-                                   Bk, k, c.K, Bnext0, part, counter, flag);
-            } else {
-                hipLaunchKernelGGL((k_spread_fwd<3, T>), dim3(blocks(c.D.boxN, 256)), dim3(256), 0, st, c.g, c.D,
-                                   Bk, k, krT, u, ustar);
-                hipLaunchKernelGGL((k_interp_force<3, T>), dim3(c.nblk), dim3(256), 0, st, c.g, c.D, c.bp, u, krD,
-                                   Bk, k, c.K, Bnext0, part, counter, flag);
+        dispatch(c, [&](auto dm, auto rt) {
+            constexpr int DIM = decltype(dm)::value;
+            constexpr bool ROT = decltype(rt)::value;
+            for (int k = 0; k < c.K; k++) {
+                pf->run(LKS_K_SPREAD, [&] {
+                    hipLaunchKernelGGL((k_spread_fwd<DIM, T, ROT>), dim3(blocks(c.D.boxN, 256)), dim3(256), 0, st,
+                                       c.g, c.D, Bk, k, krT, u, ustar);
+                });
+                pf->run(LKS_K_INTERP, [&] {
+                    hipLaunchKernelGGL((k_interp_force<DIM, T>), dim3(c.nblk), dim3(DBLK), 0, st, c.g, c.D, c.bp, u,
+                                       krD, Bk, k, c.K, Bnext0, part, counter, flag);
+                });
             }
-        }
+        });
     }
     // reverse of the body loop of one step (records Bk, footprint u* of the step)
     void body_rev(const double *Bk, const T *ustar, const T *ab, const T *krT, const double *krD, const Layout &L,
@@ -300,42 +371,43 @@ template <typename T> struct Run {
         double *rec = at<double>(w, L.rec);
         unsigned *counter = at<unsigned>(w, L.counter);
         const dim3 gb(blocks(c.D.boxN, 256), c.K);
-        if (c.dim == 2)
-            hipLaunchKernelGGL((k_adj_recompute<2, T>), gb, dim3(256), 0, st, c.g, c.D, Bk, krT, ustar, kapk, usk,
-                               uk, ustb);
-        else
-            hipLaunchKernelGGL((k_adj_recompute<3, T>), gb, dim3(256), 0, st, c.g, c.D, Bk, krT, ustar, kapk, usk,
-                               uk, ustb);
-        for (int k = c.K - 1; k >= 0; k--) {
-            if (c.dim == 2) {
-                hipLaunchKernelGGL((k_adj_r1<2, T>), dim3(c.nblk), dim3(256), 0, st, c.g, c.D, Bk, k, uk, krD, rec,
-                                   URb, krb, p1);
-                hipLaunchKernelGGL((k_adj_r2<2, T>), dim3(blocks(c.D.boxN, 256)), dim3(256), 0, st, c.g, c.bc, c.D,
-                                   Bk, k, c.K, ab, URb, kapk, usk, uk, ustb, kb, usb);
-                hipLaunchKernelGGL((k_adj_r3<2, T>), dim3(c.nblk), dim3(256), 0, st, c.g, c.D, c.bp, Bk, k, kb, usb,
-                                   krD, krb, p1, p3, counter, rec);
-            } else {
-                hipLaunchKernelGGL((k_adj_r1<3, T>), dim3(c.nblk), dim3(256), 0, st, c.g, c.D, Bk, k, uk, krD, rec,
-                                   URb, krb, p1);
-                hipLaunchKernelGGL((k_adj_r2<3, T>), dim3(blocks(c.D.boxN, 256)), dim3(256), 0, st, c.g, c.bc, c.D,
-                                   Bk, k, c.K, ab, URb, kapk, usk, uk, ustb, kb, usb);
-                hipLaunchKernelGGL((k_adj_r3<3, T>), dim3(c.nblk), dim3(256), 0, st, c.g, c.D, c.bp, Bk, k, kb, usb,
-                                   krD, krb, p1, p3, counter, rec);
+        dispatch(c, [&](auto dm, auto rt) {
+            constexpr int DIM = decltype(dm)::value;
+            constexpr bool ROT = decltype(rt)::value;
+            pf->run(LKS_K_ADJ_RECOMPUTE, [&] {
+                hipLaunchKernelGGL((k_adj_recompute<DIM, T, ROT>), gb, dim3(256), 0, st, c.g, c.D, Bk, krT, ustar,
+                                   kapk, usk, uk, ustb);
+            });
+            for (int k = c.K - 1; k >= 0; k--) {
+                pf->run(LKS_K_ADJ_R1, [&] {
+                    hipLaunchKernelGGL((k_adj_r1<DIM, T>), dim3(c.nblk), dim3(DBLK), 0, st, c.g, c.D, Bk, k, uk, krD,
+                                       rec, URb, krb, p1);
+                });
+                pf->run(LKS_K_ADJ_R2, [&] {
+                    hipLaunchKernelGGL((k_adj_r2<DIM, T, ROT>), dim3(blocks(c.D.boxN, 256)), dim3(256), 0, st, c.g,
+                                       c.bc, c.D, Bk, k, c.K, ab, URb, kapk, usk, uk, ustb, kb, usb);
+                });
+                pf->run(LKS_K_ADJ_R3, [&] {
+                    hipLaunchKernelGGL((k_adj_r3<DIM, T>), dim3(c.nblk), dim3(DBLK), 0, st, c.g, c.D, c.bp, Bk, k,
+                                       kb, usb, krD, krb, p1, p3, counter, rec);
+                });
             }
-        }
+        });
     }
     void adj_gather(const T *ab, const T *ustb, const double *Bprev, const T *sprev, T *out, T *mom) const {
         const int hb = c.has_body ? 1 : 0;
-        if (c.dim == 2) {
-            dim3 grid(blocks(c.g.n[0], G2_TX), blocks(c.g.n[1], G2_TY));
-            hipLaunchKernelGGL(k_adjgather2d<T>, grid, dim3(G2_TX, G2_TY), 0, st, c.g, c.bc, T(c.A), ab, ustb, Bprev,
-                               c.D, hb, sprev, out);
-        } else {
-            hipLaunchKernelGGL(k_adjmom3d<T>, dim3(blocks(c.g.N, 256)), dim3(256), 0, st, c.g, c.bc, ab, ustb, Bprev,
-                               c.D, hb, mom);
-            hipLaunchKernelGGL(k_adjout3d<T>, dim3(blocks(c.g.N, 256)), dim3(256), 0, st, c.g, T(c.A), mom, sprev,
-                               out);
-        }
+        pf->run(LKS_K_ADJ_GATHER, [&] {
+            if (c.dim == 2) {
+                dim3 grid(blocks(c.g.n[0], G2_TX), blocks(c.g.n[1], G2_TY));
+                hipLaunchKernelGGL(k_adjgather2d<T>, grid, dim3(G2_TX, G2_TY), 0, st, c.g, c.bc, T(c.A), ab, ustb,
+                                   Bprev, c.D, hb, sprev, out);
+            } else {
+                hipLaunchKernelGGL(k_adjmom3d<T>, dim3(blocks(c.g.N, 256)), dim3(256), 0, st, c.g, c.bc, ab, ustb,
+                                   Bprev, c.D, hb, mom);
+                hipLaunchKernelGGL(k_adjout3d<T>, dim3(blocks(c.g.N, 256)), dim3(256), 0, st, c.g, T(c.A), mom,
+                                   sprev, out);
+            }
+        });
     }
     void kappa_ref(const T *gamma, T *krT, double *krD) const {
         if (!c.has_body) return;
@@ -365,7 +437,11 @@ int forward_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, T *state
         if (!std::isfinite(b0[j])) return fail(LKS_EINVAL, "initial body state not finite");
     const bool rot_any = (c.bp.dof & LKS_DOF_ROT) != 0;
     box_params(c, P, rot_any, b0[6]);
-    Run<T> R{c, st};
+    Prof pf;
+    pf.on = (P->flags & LKS_FLAG_PROFILE) != 0;
+    pf.st = st;
+    const int every = c.NT > 32 ? (c.NT + 31) / 32 : 1;
+    Run<T> R{c, st, &pf};
     T *krT = at<T>(work, L.krT);
     double *krD = at<double>(work, L.krD);
     T *st1 = at<T>(work, L.st1), *ustar = at<T>(work, L.ustar);
@@ -395,6 +471,7 @@ int forward_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, T *state
             h.L[a] = c.D.L[a];
         }
         h.boxN = c.D.boxN;
+        h.rot = c.rot ? 1 : 0;
         HIP_TRY(hipMemcpyAsync(ckpt, &h, sizeof h, hipMemcpyHostToDevice, st));
         HIP_TRY(hipStreamSynchronize(st));
     }
@@ -408,6 +485,7 @@ int forward_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, T *state
             HIP_TRY(hipMemcpyAsync(at<char>(ckpt, ckpt_body_off(c, ci)), Bc, B_REC * sizeof(double),
                                    hipMemcpyDeviceToDevice, st));
         }
+        pf.sample = (t - 1) % every == 0;
         R.gather(cur, nxt);
         if (c.has_body)
             R.body_loop(nxt, Bc, Bn, krT, krD, ustar, part, counter, flag);
@@ -424,6 +502,10 @@ int forward_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, T *state
     const double *Bfinal = Bf + (size_t)(c.NT & 1) * rec;
     hipLaunchKernelGGL(k_objective, dim3(1), dim3(64), 0, st, Binit, Bfinal, P->objective, J, body);
     HIP_TRY(hipGetLastError());
+    if (pf.on) {
+        HIP_TRY(hipStreamSynchronize(st));
+        pf.finish();
+    }
     if (P->flags & LKS_FLAG_ASYNC) return LKS_OK;
     return check_flag(c, flag, st);
 }
@@ -443,8 +525,13 @@ int adjoint_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, const vo
         c.D.L[a] = h.L[a];
     }
     c.D.boxN = h.boxN;
+    c.rot = h.rot != 0;
     const Layout L = layout(c0, true);  // sized with the worst-case box
-    Run<T> R{c, st};
+    Prof pf;
+    pf.on = (P->flags & LKS_FLAG_PROFILE) != 0;
+    pf.st = st;
+    const int every = c.NT > 32 ? (c.NT + 31) / 32 : 1;
+    Run<T> R{c, st, &pf};
     T *krT = at<T>(work, L.krT);
     double *krD = at<double>(work, L.krD);
     double *part = at<double>(work, L.part);
@@ -476,6 +563,7 @@ int adjoint_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, const vo
                                B_REC * sizeof(double), hipMemcpyDeviceToDevice, st));
         // recompute the segment, keeping every state, footprint u* and iterate
         for (int j = 1; j <= len; j++) {
+            pf.sample = (t0 + j - 1) % every == 0;
             T *prev = seg + (size_t)(j - 1) * S, *cur = seg + (size_t)j * S;
             double *Bk = Bseg + (size_t)j * recN;
             R.gather(prev, cur);
@@ -486,6 +574,7 @@ int adjoint_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, const vo
         }
         // sweep it backwards
         for (int j = len; j >= 1; j--) {
+            pf.sample = (t0 + j - 1) % every == 0;
             const double *Bk = Bseg + (size_t)j * recN;
             if (c.has_body) R.body_rev(Bk, ustar_seg + (size_t)(j - 1) * fp, ab_cur, krT, krD, L, work);
             R.adj_gather(ab_cur, ustb, Bk, seg + (size_t)(j - 1) * S, ab_nxt, mom);
@@ -502,6 +591,10 @@ int adjoint_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, const vo
         HIP_TRY(hipMemsetAsync(dbody0, 0, 12 * sizeof(double), st));
     if (dstate0) HIP_TRY(hipMemcpyAsync(dstate0, ab_cur, S * sizeof(T), hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipGetLastError());
+    if (pf.on) {
+        HIP_TRY(hipStreamSynchronize(st));
+        pf.finish();
+    }
     if (P->flags & LKS_FLAG_ASYNC) return LKS_OK;
     return check_flag(c, flag, st);
 }
@@ -512,6 +605,20 @@ int adjoint_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, const vo
 extern "C" {
 
 const char *lks_last_error(void) { return g_err.c_str(); }
+
+int lks_profile_read(int kernel, double *total_ms, long long *samples) {
+    if (kernel < 0 || kernel >= LKS_K_COUNT) return fail(LKS_EINVAL, "unknown kernel id %d", kernel);
+    if (total_ms) *total_ms = g_prof_ms[kernel];
+    if (samples) *samples = g_prof_n[kernel];
+    return LKS_OK;
+}
+
+void lks_profile_reset(void) {
+    for (int k = 0; k < LKS_K_COUNT; k++) {
+        g_prof_ms[k] = 0.0;
+        g_prof_n[k] = 0;
+    }
+}
 
 size_t lks_state_elems(const lks_problem_t *P) {
     Ctx c;

@@ -118,14 +118,34 @@ __device__ __forceinline__ void bc_resolve(const Grid &g, const Bc &bc, const in
 // ------------------------------------------------------------ mapping weight
 // Eq. weight_function read as the cosine kernel w(r) = (1 + cos(pi r / 2)) / 4 on
 // |r| < 2, and its derivative -(pi/8) sin(pi r / 2).
+//
+// FP32: with a = |r| and b = a (a <= 1) or 2 - a (a > 1), cos(pi a/2) = +-cos(pi b/2)
+// and sin(pi a/2) = sin(pi b/2) with pi b/2 in [0, pi/2], where the Taylor series of
+// cos to y^12 and of sin to y^13 are accurate to 7e-9 -- below FP32 rounding.
+__device__ __forceinline__ void cs_quarter(float b, float &c, float &s) {
+    const float y = 1.57079632679489662f * b, y2 = y * y;
+    c = 1.0f + y2 * (-0.5f + y2 * (4.16666667e-2f + y2 * (-1.38888889e-3f +
+        y2 * (2.48015873e-5f + y2 * (-2.75573192e-7f + y2 * 2.08767570e-9f)))));
+    s = y * (1.0f + y2 * (-1.66666667e-1f + y2 * (8.33333333e-3f + y2 * (-1.98412698e-4f +
+        y2 * (2.75573192e-6f + y2 * (-2.50521084e-8f + y2 * 1.60590438e-10f))))));
+}
 __device__ __forceinline__ float wk(float r) {
-    return fabsf(r) < 2.0f ? 0.25f * (1.0f + cospif(0.5f * r)) : 0.0f;
+    const float a = fabsf(r);
+    const float b = a <= 1.0f ? a : 2.0f - a;
+    float c, s;
+    cs_quarter(b, c, s);
+    c = a <= 1.0f ? c : -c;
+    return a < 2.0f ? 0.25f * (1.0f + c) : 0.0f;
+}
+__device__ __forceinline__ float dwk(float r) {
+    const float a = fabsf(r);
+    const float b = a <= 1.0f ? a : 2.0f - a;
+    float c, s;
+    cs_quarter(b, c, s);
+    return a < 2.0f ? (r < 0.0f ? 0.39269908169872414f : -0.39269908169872414f) * s : 0.0f;
 }
 __device__ __forceinline__ double wk(double r) {
     return fabs(r) < 2.0 ? 0.25 * (1.0 + cospi(0.5 * r)) : 0.0;
-}
-__device__ __forceinline__ float dwk(float r) {
-    return fabsf(r) < 2.0f ? -0.39269908169872414f * sinpif(0.5f * r) : 0.0f;
 }
 __device__ __forceinline__ double dwk(double r) {
     return fabs(r) < 2.0 ? -0.39269908169872414 * sinpi(0.5 * r) : 0.0;
@@ -159,21 +179,23 @@ __device__ __forceinline__ void design_xi(const Design &D, long long m, double x
     xi[2] = DIM == 3 ? (double)k - D.half[2] : 0.0;
 }
 
+// Select-based access to 3-vectors by a runtime axis index (keeps them in registers).
+template <typename T> __device__ __forceinline__ T pick3(const T v[3], int i) {
+    return i == 0 ? v[0] : (i == 1 ? v[1] : v[2]);
+}
+
 __device__ __forceinline__ void pose_point(const Design &D, const double *B, const double xi[3],
                                            Pose &o) {
     // No contraction: the spread (gather form) and the interpolation evaluate the
     // same positions in different kernels and must agree bit for bit.
 #pragma clang fp contract(off)
     const double c = B[B_COS], s = B[B_SIN], om = B[B_OM];
-    const int a = D.axis, i = D.pi, j = D.pj;
-    o.r[a] = xi[a];
-    o.r[i] = c * xi[i] - s * xi[j];
-    o.r[j] = s * xi[i] + c * xi[j];
-    o.axr[a] = 0.0;
-    o.axr[i] = -o.r[j];
-    o.axr[j] = o.r[i];
+    const double xa = pick3(xi, D.axis), xp = pick3(xi, D.pi), xq = pick3(xi, D.pj);
+    const double ra = xa, rp = c * xp - s * xq, rq = s * xp + c * xq;
 #pragma unroll
     for (int b = 0; b < 3; b++) {
+        o.r[b] = b == D.axis ? ra : (b == D.pi ? rp : rq);
+        o.axr[b] = b == D.axis ? 0.0 : (b == D.pi ? -rq : rp);
         o.X[b] = B[B_XG + b] + o.r[b];
         o.US[b] = B[B_UG + b] + om * o.axr[b];
     }
