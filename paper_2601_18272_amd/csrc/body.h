@@ -111,9 +111,12 @@ __device__ __forceinline__ void body_update_rev(const BodyParams &bp, const doub
 // the plane [-1, 2] without rotation, [-2, 3] with (|r| < 2 spans 2(|cos| + |sin|) <=
 // 2 sqrt 2 design spacings). Calls f(m, W, r) for every candidate with W != 0; also
 // returns d = x - x^G (FP64) for callers that rebuild lab-frame arms.
-template <int DIM, typename T, bool ROT, typename F>
+// With LPN > 1, lane q of a group of LPN consecutive lanes visits the candidates
+// q, q + LPN, ... of the flattened plane window; callers combine the groups with
+// lane_sum (a fixed xor tree: deterministic).
+template <int DIM, typename T, bool ROT, int LPN = 1, typename F>
 __device__ __forceinline__ void gather_design(const Design &D, const double *B, const int x[3], double d[3],
-                                              F &&f) {
+                                              int q, F &&f) {
     const double c = B[B_COS], s = B[B_SIN];
     d[0] = d[1] = d[2] = 0.0;
 #pragma unroll
@@ -151,33 +154,39 @@ __device__ __forceinline__ void gather_design(const Design &D, const double *B, 
     }
     constexpr int PW = ROT ? 6 : 4, P0 = ROT ? -2 : -1;
     const int ni = D.nd[D.pi], nj = D.nd[D.pj];
-    for (int u = 0; u < PW; u++) {
+    for (int cidx = q; cidx < PW * PW; cidx += LPN) {
+        const int u = cidx / PW, v = cidx - u * PW;
         const int ii = ib[D.pi] + P0 + u;
-        if (ii < 0 || ii >= ni) continue;
+        const int jj = ib[D.pj] + P0 + v;
+        if (ii < 0 || ii >= ni || jj < 0 || jj >= nj) continue;
         const T ei = T(P0 + u) - fr[D.pi];
-        for (int v = 0; v < PW; v++) {
-            const int jj = ib[D.pj] + P0 + v;
-            if (jj < 0 || jj >= nj) continue;
-            const T ej = T(P0 + v) - fr[D.pj];
-            T r[3];
-            r[D.pi] = -(cc * ei - ss * ej);
-            r[D.pj] = -(ss * ei + cc * ej);
-            if (!(fabs(r[D.pi]) < T(2) && fabs(r[D.pj]) < T(2))) continue;
-            const T wp = wk(r[D.pi]) * wk(r[D.pj]);
+        const T ej = T(P0 + v) - fr[D.pj];
+        T r[3];
+        r[D.pi] = -(cc * ei - ss * ej);
+        r[D.pj] = -(ss * ei + cc * ej);
+        if (!(fabs(r[D.pi]) < T(2) && fabs(r[D.pj]) < T(2))) continue;
+        const T wp = wk(r[D.pi]) * wk(r[D.pj]);
 #pragma unroll
-            for (int t = 0; t < NA; t++) {
-                const T W = wp * wa[t];
-                if (W == T(0)) continue;
-                r[D.axis] = DIM == 3 ? fr[D.axis] - T(t - 1) : T(0);
-                int idx[3];
-                idx[D.axis] = ia[t];
-                idx[D.pi] = ii;
-                idx[D.pj] = jj;
-                const long long m = idx[0] + (long long)D.nd[0] * (idx[1] + (long long)D.nd[1] * idx[2]);
-                f(m, W, r);
-            }
+        for (int t = 0; t < NA; t++) {
+            const T W = wp * wa[t];
+            if (W == T(0)) continue;
+            r[D.axis] = DIM == 3 ? fr[D.axis] - T(t - 1) : T(0);
+            int idx[3];
+            idx[D.axis] = ia[t];
+            idx[D.pi] = ii;
+            idx[D.pj] = jj;
+            const long long m = idx[0] + (long long)D.nd[0] * (idx[1] + (long long)D.nd[1] * idx[2]);
+            f(m, W, r);
         }
     }
+}
+
+// Sum over the LPN lanes of a group (xor tree, identical result in every lane).
+template <int LPN, typename V> __device__ __forceinline__ V lane_sum(V v) {
+    if (LPN >= 2) v += __shfl_xor(v, 1, 64);
+    if (LPN >= 4) v += __shfl_xor(v, 2, 64);
+    if (LPN >= 8) v += __shfl_xor(v, 4, 64);
+    return v;
 }
 
 template <int DIM>
@@ -201,17 +210,21 @@ __device__ __forceinline__ bool box_node(const Grid &g, const Design &D, const i
 
 // kappa(x) and u^S(x) at node x: sum W kappa_ref, and u^G phi + omega a x (sum W (x^ref - x^G))
 // with phi = sum W and sum W (x^ref - x^G) = phi d - sum W r formed in FP64.
-template <int DIM, typename T, bool ROT>
+template <int DIM, typename T, bool ROT, int LPN = 1>
 __device__ __forceinline__ void spread_node(const Design &D, const double *B, const T *__restrict__ krT,
-                                            const int x[3], T &kap, T us[3]) {
+                                            const int x[3], int q, T &kap, T us[3]) {
     double d[3];
     T k = 0, phi = 0, wr[3] = {0, 0, 0};
-    gather_design<DIM, T, ROT>(D, B, x, d, [&](long long m, T W, const T r[3]) {
+    gather_design<DIM, T, ROT, LPN>(D, B, x, d, q, [&](long long m, T W, const T r[3]) {
         k += W * krT[m];
         phi += W;
 #pragma unroll
         for (int a = 0; a < DIM; a++) wr[a] += W * r[a];
     });
+    k = lane_sum<LPN>(k);
+    phi = lane_sum<LPN>(phi);
+#pragma unroll
+    for (int a = 0; a < DIM; a++) wr[a] = lane_sum<LPN>(wr[a]);
     double arm[3];
 #pragma unroll
     for (int a = 0; a < 3; a++) arm[a] = a < DIM ? (double)phi * d[a] - (double)wr[a] : 0.0;
@@ -228,17 +241,20 @@ __device__ __forceinline__ void spread_node(const Design &D, const double *B, co
 // ------------------------------------------------------------------ forward spread
 // Iteration k of a step: footprint nodes get kappa, u^S at pose B^(k) and the Brinkman
 // correction of u* (read from the state at k = 0 and kept in ustar; from ustar after).
-template <int DIM, typename T, bool ROT>
+template <int DIM, typename T, bool ROT, int LPN>
 __global__ __launch_bounds__(256) void k_spread_fwd(Grid g, Design D, const double *__restrict__ Bk, int k,
                                                     const T *__restrict__ krT, T *__restrict__ u,
                                                     T *__restrict__ ustar) {
-    const long long l = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long l = t / LPN;
+    const int q = (int)(t % LPN);
     if (l >= D.boxN) return;
     int o[3], x[3];
     box_origin<DIM>(D, Bk, o);
     if (!box_node<DIM>(g, D, o, l, x)) return;
     T kap, us[3];
-    spread_node<DIM, T, ROT>(D, Bk + k * B_REC, krT, x, kap, us);
+    spread_node<DIM, T, ROT, LPN>(D, Bk + k * B_REC, krT, x, q, kap, us);
+    if (q != 0) return;
     const long long N = g.N;
     const long long id = node_id(g, x[0], x[1], x[2]);
     const T inv = T(1) / (T(1) + kap);
@@ -271,7 +287,7 @@ __global__ __launch_bounds__(256) void k_spread_map(Grid g, Design D, const doub
     x[1] = (int)((id / g.n[0]) % g.n[1]);
     x[2] = (int)(id / ((long long)g.n[0] * g.n[1]));
     T kap = 0, us[3] = {0, 0, 0};
-    if (is_interior<DIM>(g, x)) spread_node<DIM, T, true>(D, B, krT, x, kap, us);
+    if (is_interior<DIM>(g, x)) spread_node<DIM, T, true>(D, B, krT, x, 0, kap, us);
     kap_out[id] = kap;
 #pragma unroll
     for (int a = 0; a < DIM; a++) us_out[a * g.N + id] = us[a];
@@ -341,17 +357,18 @@ __device__ __forceinline__ void block_reduce_store(double v[NV], double *__restr
     }
 }
 
-// Returns true in the one block that arrives last (all partials visible to it).
+// Returns true in the one block that arrives last (all partials visible to it). The
+// partials of a block are stored by its first wave, so only that wave needs the
+// release fence before the arrival counter, and only it (which reads the partials in
+// reduce_partials) the acquire fence after.
 __device__ __forceinline__ bool last_block(unsigned *counter) {
     __shared__ bool is_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned prev = atomicAdd(counter, 1u);
-        is_last = (prev == gridDim.x - 1);
+    if (threadIdx.x < 64) {
+        __threadfence();
+        if (threadIdx.x == 0) is_last = atomicAdd(counter, 1u) == gridDim.x - 1;
     }
     __syncthreads();
-    if (is_last) __threadfence();
+    if (is_last && threadIdx.x < 64) __threadfence();
     return is_last;
 }
 
@@ -486,23 +503,26 @@ __global__ void k_adj_init(BodyParams bp, int obj, double seed, double *__restri
 // Recompute, for all iterations of a step at once (blockIdx.y = k), the footprint
 // fields kappa^(k), u^S^(k), u^(k) from u* and the stored iterates B^(k). Also clears
 // the cotangent of u* on the box.
-template <int DIM, typename T, bool ROT>
+template <int DIM, typename T, bool ROT, int LPN>
 __global__ __launch_bounds__(256) void k_adj_recompute(Grid g, Design D, const double *__restrict__ Bk,
                                                        const T *__restrict__ krT, const T *__restrict__ ustar,
                                                        T *__restrict__ kapk, T *__restrict__ usk,
                                                        T *__restrict__ uk, T *__restrict__ ustb) {
-    const long long l = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long l = t / LPN;
+    const int q = (int)(t % LPN);
     const int k = blockIdx.y;
     if (l >= D.boxN) return;
     const long long bN = D.boxN;
-    if (k == 0)
+    if (k == 0 && q == 0)
 #pragma unroll
         for (int a = 0; a < DIM; a++) ustb[a * bN + l] = T(0);
     int o[3], x[3];
     box_origin<DIM>(D, Bk, o);
     T kap = 0, us[3] = {0, 0, 0};
     const bool ok = box_node<DIM>(g, D, o, l, x);
-    if (ok) spread_node<DIM, T, ROT>(D, Bk + k * B_REC, krT, x, kap, us);
+    if (ok) spread_node<DIM, T, ROT, LPN>(D, Bk + k * B_REC, krT, x, q, kap, us);
+    if (q != 0) return;
     kapk[k * bN + l] = kap;
     const T inv = T(1) / (T(1) + kap);
 #pragma unroll
@@ -622,34 +642,42 @@ __global__ __launch_bounds__(DBLK) void k_adj_r1(Grid g, Design D, const double 
 // R2: box nodes. u^(k) cotangent = (k = last: the step's velocity cotangent, with the
 // boundary fold) + sum_m W URb_m (transpose of the interpolation, gather form);
 // Brinkman correction reversed.
-template <int DIM, typename T, bool ROT>
+template <int DIM, typename T, bool ROT, int LPN>
 __global__ __launch_bounds__(256) void k_adj_r2(Grid g, Bc bc, Design D, const double *__restrict__ Bk, int k,
                                                 int K, const T *__restrict__ ab, const T *__restrict__ URb,
                                                 const T *__restrict__ kapk, const T *__restrict__ usk,
                                                 const T *__restrict__ uk, T *__restrict__ ustb,
                                                 T *__restrict__ kb, T *__restrict__ usb) {
-    const long long l = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long l = t / LPN;
+    const int q = (int)(t % LPN);
     if (l >= D.boxN) return;
     const long long bN = D.boxN;
     int o[3], x[3];
     box_origin<DIM>(D, Bk, o);
     if (!box_node<DIM>(g, D, o, l, x)) {
+        if (q != 0) return;
         kb[l] = T(0);
 #pragma unroll
         for (int a = 0; a < DIM; a++) usb[a * bN + l] = T(0);
         return;
     }
     T ub[3] = {0, 0, 0};
-    if (k == K - 1) {
-        const long long id = node_id(g, x[0], x[1], x[2]);
-        T pdummy;
-        fold_bc<DIM, T>(g, bc, ab, x, id, pdummy, ub, true);
-    }
     double d[3];
-    gather_design<DIM, T, ROT>(D, Bk + k * B_REC, x, d, [&](long long m, T W, const T *) {
+    gather_design<DIM, T, ROT, LPN>(D, Bk + k * B_REC, x, d, q, [&](long long m, T W, const T *) {
 #pragma unroll
         for (int a = 0; a < DIM; a++) ub[a] += W * URb[a * D.ND + m];
     });
+#pragma unroll
+    for (int a = 0; a < DIM; a++) ub[a] = lane_sum<LPN>(ub[a]);
+    if (q != 0) return;
+    if (k == K - 1) {
+        const long long id = node_id(g, x[0], x[1], x[2]);
+        T pdummy, uf[3];
+        fold_bc<DIM, T>(g, bc, ab, x, id, pdummy, uf, true);
+#pragma unroll
+        for (int a = 0; a < DIM; a++) ub[a] += uf[a];
+    }
     const T kap = kapk[k * bN + l];
     const T inv = T(1) / (T(1) + kap);
     T kbar = 0;

@@ -302,6 +302,10 @@ size_t ckpt_bytes(const Ctx &c) { return ckpt_body_off(c, ckpt_count(c)); }
 template <typename T> T *at(void *base, size_t off) { return (T *)((char *)base + off); }
 
 // ------------------------------------------------------------------ kernels by type
+// Lanes per footprint node in the gather-form mapping kernels: 2D footprints are small
+// (latency-bound), so the candidate loop of a node is split over 4 lanes.
+template <int DIM> constexpr int lpn() { return DIM == 2 ? 4 : 1; }
+
 // Calls f(dim, rot) with compile-time constants matching the problem.
 template <typename F> void dispatch(const Ctx &c, F &&f) {
     using I2 = std::integral_constant<int, 2>;
@@ -352,8 +356,8 @@ template <typename T> struct Run {
             constexpr bool ROT = decltype(rt)::value;
             for (int k = 0; k < c.K; k++) {
                 pf->run(LKS_K_SPREAD, [&] {
-                    hipLaunchKernelGGL((k_spread_fwd<DIM, T, ROT>), dim3(blocks(c.D.boxN, 256)), dim3(256), 0, st,
-                                       c.g, c.D, Bk, k, krT, u, ustar);
+                    hipLaunchKernelGGL((k_spread_fwd<DIM, T, ROT, lpn<DIM>()>), dim3(blocks(c.D.boxN * lpn<DIM>(), 256)),
+                                       dim3(256), 0, st, c.g, c.D, Bk, k, krT, u, ustar);
                 });
                 pf->run(LKS_K_INTERP, [&] {
                     hipLaunchKernelGGL((k_interp_force<DIM, T>), dim3(c.nblk), dim3(DBLK), 0, st, c.g, c.D, c.bp, u,
@@ -370,13 +374,13 @@ template <typename T> struct Run {
         double *krb = at<double>(w, L.krb), *p1 = at<double>(w, L.part1), *p3 = at<double>(w, L.part3);
         double *rec = at<double>(w, L.rec);
         unsigned *counter = at<unsigned>(w, L.counter);
-        const dim3 gb(blocks(c.D.boxN, 256), c.K);
+        const dim3 gb(blocks(c.D.boxN * (c.dim == 2 ? 4 : 1), 256), c.K);
         dispatch(c, [&](auto dm, auto rt) {
             constexpr int DIM = decltype(dm)::value;
             constexpr bool ROT = decltype(rt)::value;
             pf->run(LKS_K_ADJ_RECOMPUTE, [&] {
-                hipLaunchKernelGGL((k_adj_recompute<DIM, T, ROT>), gb, dim3(256), 0, st, c.g, c.D, Bk, krT, ustar,
-                                   kapk, usk, uk, ustb);
+                hipLaunchKernelGGL((k_adj_recompute<DIM, T, ROT, lpn<DIM>()>), gb, dim3(256), 0, st, c.g, c.D, Bk,
+                                   krT, ustar, kapk, usk, uk, ustb);
             });
             for (int k = c.K - 1; k >= 0; k--) {
                 pf->run(LKS_K_ADJ_R1, [&] {
@@ -384,8 +388,9 @@ template <typename T> struct Run {
                                        rec, URb, krb, p1);
                 });
                 pf->run(LKS_K_ADJ_R2, [&] {
-                    hipLaunchKernelGGL((k_adj_r2<DIM, T, ROT>), dim3(blocks(c.D.boxN, 256)), dim3(256), 0, st, c.g,
-                                       c.bc, c.D, Bk, k, c.K, ab, URb, kapk, usk, uk, ustb, kb, usb);
+                    hipLaunchKernelGGL((k_adj_r2<DIM, T, ROT, lpn<DIM>()>), dim3(blocks(c.D.boxN * lpn<DIM>(), 256)),
+                                       dim3(256), 0, st, c.g, c.bc, c.D, Bk, k, c.K, ab, URb, kapk, usk, uk, ustb, kb,
+                                       usb);
                 });
                 pf->run(LKS_K_ADJ_R3, [&] {
                     hipLaunchKernelGGL((k_adj_r3<DIM, T>), dim3(c.nblk), dim3(DBLK), 0, st, c.g, c.D, c.bp, Bk, k,

@@ -422,3 +422,32 @@ def test_invalid_problems_rejected(orc):
                     W.initial_state(pb), W.initial_body(pb))
     with pytest.raises(ValueError):
         orc.forward(pb.replace(n_itr=0), W.design(pb), W.initial_state(pb), W.initial_body(pb))
+
+
+def test_paper_constants_fixture(orc):
+    """The printed weights (Sec. 2.2) sum to one and have the second moment 1/3 that the
+    shear-wave pin relies on; the viscosity relation at the paper's nu = 0.1 gives A = 0.3,
+    and the oracle's shear-wave decay at that A matches the closed form."""
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "paper_constants.txt")
+    c = {}
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            k, v = line.split()
+            c[k] = float(v)
+    assert abs(c["d2q9_w_rest"] + 4 * c["d2q9_w_axis"] + 4 * c["d2q9_w_diag"] - 1) < 1e-15
+    assert abs(2 * c["d2q9_w_axis"] + 4 * c["d2q9_w_diag"] - 1 / 3) < 1e-15
+    assert abs(c["d3q15_w_rest"] + 6 * c["d3q15_w_axis"] + 8 * c["d3q15_w_corner"] - 1) < 1e-15
+    assert abs(2 * c["d3q15_w_axis"] + 8 * c["d3q15_w_corner"] - 1 / 3) < 1e-15
+    A = c["A_at_nu_0.1"]
+    assert abs((1 / 6 - 2 * A / 9) - 0.1) < 1e-15
+    pb = periodic(2, (32, 4), nu=0.1, n_steps=1)
+    N = pb.N
+    x, _, _ = coords(pb)
+    k = 2 * np.pi * 2 / 32
+    s0 = np.zeros(3 * N)
+    s0[2 * N:] = 1e-7 * np.sin(k * x)
+    s1, _, _ = orc.forward(pb, None, s0, np.zeros(12))
+    G = 2 / 3 + np.cos(k) / 3 + (2 * A / 9) * np.sin(k) ** 2
+    assert np.abs(s1[2 * N:] - G * s0[2 * N:]).max() < 1e-21
