@@ -123,110 +123,159 @@ __global__ __launch_bounds__(512) void k_gather2d(Grid g, T A, const T *__restri
 }
 
 // ===================================================================== forward, 3D
-// First version: one node per thread, f_i(x - c_i) evaluated from global loads
-// (the neighbourhood is L1/L2 resident).
+// 2.5D blocking: a TX x TY tile of (x, y) columns marches along z over ZC output
+// planes. For every source plane s, the f_i of the tile plus a one-node (x, y) ring are
+// evaluated once into LDS and pushed to the destination planes s-1, s, s+1, whose
+// moments each thread keeps in registers for its column. p, u of planes s-2..s+2 sit
+// in a 5-slot LDS ring with a two-node (x, y) ring (the one-sided z-derivative at a
+// wall reaches two planes).
+template <typename T> struct G3 {
+    static constexpr int TX = 64, TY = sizeof(T) == 4 ? 8 : 4, NT = TX * TY;
+};
+
 template <typename T>
-__device__ __forceinline__ T ld(const T *__restrict__ a, long long i) {
-    return a[i];
+__device__ __forceinline__ T d1(T m2, T m1, T c, T p1, T p2, int v, int n, int per) {
+    // derivative along one axis from the values at offsets -2..2 (boundary-aware)
+    if (per || (v > 0 && v < n - 1)) return T(0.5) * (p1 - m1);
+    if (v == 0) return T(0.5) * (T(-3) * c + T(4) * p1 - p2);
+    return T(0.5) * (T(3) * c - T(4) * m1 + m2);
 }
 
 template <typename T>
-__device__ __forceinline__ void grad3(const Grid &g, const T *__restrict__ u, const int y[3], T S[3][3]) {
+__global__ __launch_bounds__(G3<T>::NT) void k_gather3d(Grid g, T A, int ZC, const T *__restrict__ sin_,
+                                                        T *__restrict__ sout) {
+    constexpr int TX = G3<T>::TX, TY = G3<T>::TY, NT = G3<T>::NT;
+    constexpr int RX = TX + 4, RY = TY + 4, FX = TX + 2, FY = TY + 2;
+    __shared__ T win[5][4][RY][RX];
+    __shared__ T fb[15][FY][FX];
     const long long N = g.N;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int z0 = blockIdx.z * ZC, z1 = min(z0 + ZC, nz);
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TX * ty;
+
+    // plane loads: each thread owns the ring-window entries l = tid + j*NT; a plane is
+    // fetched into registers one iteration ahead and stored into its LDS slot after the
+    // slot's previous plane is no longer read (software pipelining of the HBM latency)
+    constexpr int PER = (RX * RY + NT - 1) / NT;
+    T pre[PER][4];
+    auto fetch = [&](int zp) {
+        int zw = zp;
+        const bool zok = wrap_coord(zw, nz, g.per[2]);
 #pragma unroll
-    for (int a = 0; a < 3; a++) {
-        T cf[3];
-        int cnt;
-        const int n = g.n[a];
-        int ya = y[a];
-        int o[3];
-        if (g.per[a] || (ya > 0 && ya < n - 1)) {
-            o[0] = ya + 1;
-            o[1] = ya - 1;
-            cf[0] = T(0.5);
-            cf[1] = T(-0.5);
-            cnt = 2;
-            if (g.per[a]) {
-                if (o[0] >= n) o[0] -= n;
-                if (o[1] < 0) o[1] += n;
+        for (int j = 0; j < PER; j++) {
+            const int l = tid + j * NT;
+            const int lx = l % RX, ly = l / RX;
+            int x = x0 + lx - 2, y = y0 + ly - 2;
+#pragma unroll
+            for (int c = 0; c < 4; c++) pre[j][c] = 0;
+            if (l < RX * RY && zok && wrap_coord(x, nx, g.per[0]) && wrap_coord(y, ny, g.per[1])) {
+                const long long id = (long long)x + (long long)nx * ((long long)y + (long long)ny * zw);
+#pragma unroll
+                for (int c = 0; c < 4; c++) pre[j][c] = sin_[c * N + id];
             }
-        } else if (ya == 0) {
-            o[0] = 0;
-            o[1] = 1;
-            o[2] = 2;
-            cf[0] = T(-1.5);
-            cf[1] = T(2);
-            cf[2] = T(-0.5);
-            cnt = 3;
-        } else {
-            o[0] = n - 1;
-            o[1] = n - 2;
-            o[2] = n - 3;
-            cf[0] = T(1.5);
-            cf[1] = T(-2);
-            cf[2] = T(0.5);
-            cnt = 3;
         }
-        T acc[3] = {0, 0, 0};
-        for (int j = 0; j < cnt; j++) {
-            int z[3] = {y[0], y[1], y[2]};
-            z[a] = o[j];
-            const long long id = node_id(g, z[0], z[1], z[2]);
+    };
+    auto store = [&](int zp) {
+        const int slot = ((zp % 5) + 5) % 5;
 #pragma unroll
-            for (int b = 0; b < 3; b++) acc[b] += cf[j] * ld(u, b * N + id);
+        for (int j = 0; j < PER; j++) {
+            const int l = tid + j * NT;
+            if (l < RX * RY) {
+                const int lx = l % RX, ly = l / RX;
+#pragma unroll
+                for (int c = 0; c < 4; c++) win[slot][c][ly][lx] = pre[j][c];
+            }
         }
-#pragma unroll
-        for (int b = 0; b < 3; b++) S[a][b] = acc[b];
-    }
-}
+    };
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_gather3d(Grid g, T A, const T *__restrict__ sin_,
-                                                  T *__restrict__ sout) {
-    const long long N = g.N;
-    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= N) return;
-    int x[3];
-    x[0] = (int)(id % g.n[0]);
-    x[1] = (int)((id / g.n[0]) % g.n[1]);
-    x[2] = (int)(id / ((long long)g.n[0] * g.n[1]));
-    if (!is_interior<3>(g, x)) return;
-    const T *u = sin_ + N;
-    T ps = 0, us[3] = {0, 0, 0};
-#pragma unroll
-    for (int i = 0; i < 15; i++) {
-        int y[3];
-#pragma unroll
-        for (int a = 0; a < 3; a++) {
-            y[a] = x[a] - Lat<3>::c(i, a);
-            wrap_coord(y[a], g.n[a], g.per[a]);
-        }
-        const long long yi = node_id(g, y[0], y[1], y[2]);
-        const T p = sin_[yi];
-        T uy[3];
-#pragma unroll
-        for (int a = 0; a < 3; a++) uy[a] = u[a * N + yi];
-        T S[3][3];
-        grad3<T>(g, u, y, S);
-        T cu = 0, uu = 0, an = 0;
-#pragma unroll
-        for (int a = 0; a < 3; a++) {
-            cu += T(Lat<3>::c(i, a)) * uy[a];
-            uu += uy[a] * uy[a];
-        }
-#pragma unroll
-        for (int a = 0; a < 3; a++)
-#pragma unroll
-            for (int b = 0; b < 3; b++)
-                an += T(Lat<3>::c(i, a) * Lat<3>::c(i, b)) * (S[a][b] + S[b][a]);
-        const T f = T(Lat<3>::w(i)) * (T(3) * p + T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu + A * an);
-        ps += f;
-#pragma unroll
-        for (int a = 0; a < 3; a++) us[a] += T(Lat<3>::c(i, a)) * f;
+    T accP[3] = {0, 0, 0}, accU[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int zp = z0 - 3; zp <= z0 + 1; zp++) {
+        fetch(zp);
+        store(zp);
     }
-    sout[id] = ps * T(1.0 / 3.0);
+    for (int s = z0 - 1; s <= z1; s++) {
+        const bool more = s + 3 <= z1 + 2;  // planes up to z1 + 2 are read (last s = z1)
+        if (more) fetch(s + 3);
+        __syncthreads();
+        int zs = s;
+        const bool sok = wrap_coord(zs, nz, g.per[2]);
+        const int sm2 = ((s - 2) % 5 + 5) % 5, sm1 = ((s - 1) % 5 + 5) % 5, s0 = ((s % 5) + 5) % 5;
+        const int sp1 = ((s + 1) % 5 + 5) % 5, sp2 = ((s + 2) % 5 + 5) % 5;
+        for (int l = tid; l < FX * FY; l += NT) {
+            const int fx = l % FX, fy = l / FX;
+            const int lx = fx + 1, ly = fy + 1;
+            int x = x0 + fx - 1, y = y0 + fy - 1;
+            const bool ok = sok && wrap_coord(x, nx, g.per[0]) && wrap_coord(y, ny, g.per[1]);
+            T f[15];
+            if (ok) {
+                T S[3][3];  // S[a][b] = d_a u_b
 #pragma unroll
-    for (int a = 0; a < 3; a++) sout[(1 + a) * N + id] = us[a];
+                for (int b = 0; b < 3; b++) {
+                    const T(*U)[RX] = win[s0][1 + b];
+                    S[0][b] = d1(U[ly][lx - 2 < 0 ? 0 : lx - 2], U[ly][lx - 1], U[ly][lx], U[ly][lx + 1],
+                                 U[ly][lx + 2 >= RX ? RX - 1 : lx + 2], x, nx, g.per[0]);
+                    S[1][b] = d1(U[ly - 2 < 0 ? 0 : ly - 2][lx], U[ly - 1][lx], U[ly][lx], U[ly + 1][lx],
+                                 U[ly + 2 >= RY ? RY - 1 : ly + 2][lx], y, ny, g.per[1]);
+                    S[2][b] = d1(win[sm2][1 + b][ly][lx], win[sm1][1 + b][ly][lx], U[ly][lx],
+                                 win[sp1][1 + b][ly][lx], win[sp2][1 + b][ly][lx], zs, nz, g.per[2]);
+                }
+                const T p = win[s0][0][ly][lx];
+                const T u[3] = {win[s0][1][ly][lx], win[s0][2][ly][lx], win[s0][3][ly][lx]};
+                const T base = T(3) * p - T(1.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+                // A c.(S + S^T).c = 2A (sum_a c_a^2 S_aa + sum_{a<b} c_a c_b (S_ab + S_ba))
+                const T dxx = T(2) * A * S[0][0], dyy = T(2) * A * S[1][1], dzz = T(2) * A * S[2][2];
+                const T exy = T(2) * A * (S[0][1] + S[1][0]), exz = T(2) * A * (S[0][2] + S[2][0]);
+                const T eyz = T(2) * A * (S[1][2] + S[2][1]);
+#pragma unroll
+                for (int i = 0; i < 15; i++) {
+                    const int cx = Lat<3>::c(i, 0), cy = Lat<3>::c(i, 1), cz = Lat<3>::c(i, 2);
+                    const T cu = T(cx) * u[0] + T(cy) * u[1] + T(cz) * u[2];
+                    const T an = T(cx * cx) * dxx + T(cy * cy) * dyy + T(cz * cz) * dzz + T(cx * cy) * exy +
+                                 T(cx * cz) * exz + T(cy * cz) * eyz;
+                    f[i] = T(Lat<3>::w(i)) * (base + T(3) * cu + T(4.5) * cu * cu + an);
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 15; i++) f[i] = 0;
+            }
+#pragma unroll
+            for (int i = 0; i < 15; i++) fb[i][fy][fx] = f[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 15; i++) {
+            const int cx = Lat<3>::c(i, 0), cy = Lat<3>::c(i, 1), cz = Lat<3>::c(i, 2);
+            const T f = fb[i][ty + 1 - cy][tx + 1 - cx];
+            accP[cz + 1] += f;
+            accU[cz + 1][0] += T(cx) * f;
+            accU[cz + 1][1] += T(cy) * f;
+            accU[cz + 1][2] += T(cz) * f;
+        }
+        __syncthreads();
+        // destination plane s - 1 has received all its sources
+        const int zd = s - 1;
+        const int x = x0 + tx, y = y0 + ty;
+        if (zd >= z0 && zd < z1 && x < nx && y < ny) {
+            const int xx[3] = {x, y, zd};
+            if (is_interior<3>(g, xx)) {
+                const long long id = (long long)x + (long long)nx * ((long long)y + (long long)ny * zd);
+                sout[id] = accP[0] * T(1.0 / 3.0);
+#pragma unroll
+                for (int a = 0; a < 3; a++) sout[(1 + a) * N + id] = accU[0][a];
+            }
+        }
+        if (more) store(s + 3);
+        accP[0] = accP[1];
+        accP[1] = accP[2];
+        accP[2] = 0;
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            accU[0][a] = accU[1][a];
+            accU[1][a] = accU[2][a];
+            accU[2][a] = 0;
+        }
+    }
 }
 
 // ===================================================================== boundary values
@@ -479,19 +528,30 @@ __global__ __launch_bounds__(512) void k_adjgather2d(Grid g, Bc bc, T A, const T
 }
 
 // ===================================================================== adjoint, 3D
-// First version, two passes through global memory: moments (pi, ups[3], sig[6]) of
-// every node into `mom` (10 x N), then the outputs.
+// 2.5D blocking as in the forward. For every plane s: the inputs g (p*bar/3, u*bar) of
+// the planes s-1..s+1 with a 3-node (x, y) ring sit in a 3-slot LDS ring; the ten
+// moments (pi, ups, sig) of plane s are formed on a 2-node ring; each thread then forms
+// its node's local and in-plane transpose terms for plane s (kept in registers) and
+// records its column's sig_z* history; plane s-2 is completed with the z-transpose
+// terms and written.
+template <typename T> struct A3 {
+    static constexpr int TX = 64, TY = sizeof(T) == 4 ? 8 : 4, NT = TX * TY;
+};
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_adjmom3d(Grid g, Bc bc, const T *__restrict__ ab,
-                                                  const T *__restrict__ ustb, const double *__restrict__ Bprev,
-                                                  Design D, int has_box, T *__restrict__ mom) {
+__global__ __launch_bounds__(A3<T>::NT) void k_adjgather3d(Grid g, Bc bc, T A, int ZC, const T *__restrict__ ab,
+                                                           const T *__restrict__ ustb,
+                                                           const double *__restrict__ Bprev, Design D, int has_box,
+                                                           const T *__restrict__ sprev, T *__restrict__ out) {
+    constexpr int TX = A3<T>::TX, TY = A3<T>::TY, NT = A3<T>::NT;
+    constexpr int GX = TX + 6, GY = TY + 6, MX = TX + 4, MY = TY + 4;
+    __shared__ T gw[3][4][GY][GX];
+    __shared__ T mo[10][MY][MX];  // pi, ux, uy, uz, sxx, syy, szz, sxy, sxz, syz
     const long long N = g.N;
-    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= N) return;
-    int y[3];
-    y[0] = (int)(id % g.n[0]);
-    y[1] = (int)((id / g.n[0]) % g.n[1]);
-    y[2] = (int)(id / ((long long)g.n[0] * g.n[1]));
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int z0 = blockIdx.z * ZC, z1 = min(z0 + ZC, nz);
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TX * ty;
     Box bx;
     if (has_box) {
         box_origin<3>(D, Bprev, bx.o);
@@ -499,88 +559,163 @@ __global__ __launch_bounds__(256) void k_adjmom3d(Grid g, Bc bc, const T *__rest
         bx.L[1] = D.L[1];
         bx.L[2] = D.L[2];
     }
-    T m[10];
+    // the inputs of plane s + 2 are formed into registers during iteration s and stored
+    // into the slot of plane s - 1 at its end (software pipelining of the loads)
+    constexpr int PER = (GX * GY + NT - 1) / NT;
+    T pre[PER][4];
+    auto fetch = [&](int zp) {
+        int zw = zp;
+        const bool zok = wrap_coord(zw, nz, g.per[2]);
 #pragma unroll
-    for (int j = 0; j < 10; j++) m[j] = 0;
-    for (int i = 0; i < 15; i++) {
-        int z[3];
-        bool ok = true;
+        for (int j = 0; j < PER; j++) {
+            const int l = tid + j * NT;
+            const int lx = l % GX, ly = l / GX;
+            int xx[3] = {x0 + lx - 3, y0 + ly - 3, zw};
 #pragma unroll
-        for (int a = 0; a < 3; a++) {
-            z[a] = y[a] + Lat<3>::c(i, a);
-            ok = ok && wrap_coord(z[a], g.n[a], g.per[a]);
+            for (int c = 0; c < 4; c++) pre[j][c] = 0;
+            if (l < GX * GY && zok && wrap_coord(xx[0], nx, g.per[0]) && wrap_coord(xx[1], ny, g.per[1]) &&
+                is_interior<3>(g, xx)) {
+                const long long id = node_id(g, xx[0], xx[1], xx[2]);
+                T pb, ub[3];
+                star_bar<3, T>(g, bc, ab, ustb, bx, has_box, D.boxN, xx, id, pb, ub);
+                pre[j][0] = pb * T(1.0 / 3.0);
+                pre[j][1] = ub[0];
+                pre[j][2] = ub[1];
+                pre[j][3] = ub[2];
+            }
         }
-        if (!ok || !is_interior<3>(g, z)) continue;
-        const long long zi = node_id(g, z[0], z[1], z[2]);
-        T pb, ub[3];
-        star_bar<3, T>(g, bc, ab, ustb, bx, has_box, D.boxN, z, zi, pb, ub);
-        T gi = pb * T(1.0 / 3.0);
+    };
+    auto store = [&](int zp) {
+        const int slot = ((zp % 3) + 3) % 3;
 #pragma unroll
-        for (int a = 0; a < 3; a++) gi += T(Lat<3>::c(i, a)) * ub[a];
-        const T wg = T(Lat<3>::w(i)) * gi;
-        const int cx = Lat<3>::c(i, 0), cy = Lat<3>::c(i, 1), cz = Lat<3>::c(i, 2);
-        m[0] += wg;
-        m[1] += T(cx) * wg;
-        m[2] += T(cy) * wg;
-        m[3] += T(cz) * wg;
-        m[4] += T(cx * cx) * wg;  // xx
-        m[5] += T(cy * cy) * wg;  // yy
-        m[6] += T(cz * cz) * wg;  // zz
-        m[7] += T(cx * cy) * wg;  // xy
-        m[8] += T(cx * cz) * wg;  // xz
-        m[9] += T(cy * cz) * wg;  // yz
-    }
+        for (int j = 0; j < PER; j++) {
+            const int l = tid + j * NT;
+            if (l < GX * GY) {
+                const int lx = l % GX, ly = l / GX;
 #pragma unroll
-    for (int j = 0; j < 10; j++) mom[j * N + id] = m[j];
-}
-
-__device__ __forceinline__ int sig_index(int a, int b) {
-    // symmetric index into mom[4..9]
-    if (a == b) return 4 + a;
-    const int lo = a < b ? a : b, hi = a < b ? b : a;
-    return lo == 0 ? (hi == 1 ? 7 : 8) : 9;
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_adjout3d(Grid g, T A, const T *__restrict__ mom,
-                                                  const T *__restrict__ sprev, T *__restrict__ out) {
-    const long long N = g.N;
-    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= N) return;
-    int z[3];
-    z[0] = (int)(id % g.n[0]);
-    z[1] = (int)((id / g.n[0]) % g.n[1]);
-    z[2] = (int)(id / ((long long)g.n[0] * g.n[1]));
-    T u[3];
+                for (int c = 0; c < 4; c++) gw[slot][c][ly][lx] = pre[j][c];
+            }
+        }
+    };
+    const int x = x0 + tx, y = y0 + ty;
+    const bool col_ok = x < nx && y < ny;
+    T part[3][4];   // local + in-plane terms of planes s-2, s-1, s
+    T hz[5][3];     // sig_xz, sig_yz, sig_zz of planes s-4..s
 #pragma unroll
-    for (int a = 0; a < 3; a++) u[a] = sprev[(1 + a) * N + id];
-    const T pi = mom[id];
-    T o[3];
+    for (int j = 0; j < 3; j++)
 #pragma unroll
-    for (int b = 0; b < 3; b++) {
-        T v = T(3) * mom[(1 + b) * N + id] - T(3) * pi * u[b];
+        for (int c = 0; c < 4; c++) part[j][c] = 0;
 #pragma unroll
-        for (int a = 0; a < 3; a++) v += T(9) * mom[sig_index(b, a) * N + id] * u[a];
-        o[b] = v;
-    }
+    for (int j = 0; j < 5; j++) hz[j][0] = hz[j][1] = hz[j][2] = 0;
     const T A2 = T(2) * A;
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        int off[5];
-        T cf[5];
-        const int k = dT_stencil<T>(z[a], g.n[a], g.per[a], off, cf);
-        for (int j = 0; j < k; j++) {
-            int y[3] = {z[0], z[1], z[2]};
-            y[a] += off[j];
-            wrap_coord(y[a], g.n[a], g.per[a]);
-            const long long yi = node_id(g, y[0], y[1], y[2]);
-#pragma unroll
-            for (int b = 0; b < 3; b++) o[b] += A2 * cf[j] * mom[sig_index(a, b) * N + yi];
-        }
+    for (int zp = z0 - 3; zp <= z0 - 1; zp++) {
+        fetch(zp);
+        store(zp);
     }
-    out[id] = T(3) * pi;
+    for (int s = z0 - 2; s <= z1 + 1; s++) {
+        const bool more = s + 2 <= z1 + 2;  // planes up to z1 + 2 are read (last s = z1 + 1)
+        if (more) fetch(s + 2);
+        __syncthreads();
+        const int gm = ((s - 1) % 3 + 3) % 3, g0 = ((s % 3) + 3) % 3, gp = ((s + 1) % 3 + 3) % 3;
+        for (int l = tid; l < MX * MY; l += NT) {
+            const int mx = l % MX, my = l / MX;
+            const int lx = mx + 1, ly = my + 1;  // in the 3-ring arrays
+            T m[10];
 #pragma unroll
-    for (int b = 0; b < 3; b++) out[(1 + b) * N + id] = o[b];
+            for (int j = 0; j < 10; j++) m[j] = 0;
+#pragma unroll
+            for (int i = 0; i < 15; i++) {
+                const int cx = Lat<3>::c(i, 0), cy = Lat<3>::c(i, 1), cz = Lat<3>::c(i, 2);
+                const int sl = cz < 0 ? gm : (cz > 0 ? gp : g0);
+                const T gi = gw[sl][0][ly + cy][lx + cx] + T(cx) * gw[sl][1][ly + cy][lx + cx] +
+                             T(cy) * gw[sl][2][ly + cy][lx + cx] + T(cz) * gw[sl][3][ly + cy][lx + cx];
+                const T wg = T(Lat<3>::w(i)) * gi;
+                m[0] += wg;
+                m[1] += T(cx) * wg;
+                m[2] += T(cy) * wg;
+                m[3] += T(cz) * wg;
+                m[4] += T(cx * cx) * wg;
+                m[5] += T(cy * cy) * wg;
+                m[6] += T(cz * cz) * wg;
+                m[7] += T(cx * cy) * wg;
+                m[8] += T(cx * cz) * wg;
+                m[9] += T(cy * cz) * wg;
+            }
+#pragma unroll
+            for (int j = 0; j < 10; j++) mo[j][my][mx] = m[j];
+        }
+        __syncthreads();
+        const int mx = tx + 2, my = ty + 2;
+        // history of sig_z* for the z-transpose
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) hz[j][c] = hz[j + 1][c];
+        hz[4][0] = mo[8][my][mx];
+        hz[4][1] = mo[9][my][mx];
+        hz[4][2] = mo[6][my][mx];
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int c = 0; c < 4; c++) part[j][c] = part[j + 1][c];
+        part[2][0] = part[2][1] = part[2][2] = part[2][3] = 0;
+        if (col_ok && s >= z0 && s < z1) {
+            const long long id = (long long)x + (long long)nx * ((long long)y + (long long)ny * s);
+            const T u0 = sprev[N + id], u1 = sprev[2 * N + id], u2 = sprev[3 * N + id];
+            const T pi = mo[0][my][mx];
+            const T sxx = mo[4][my][mx], syy = mo[5][my][mx], szz = mo[6][my][mx];
+            const T sxy = mo[7][my][mx], sxz = mo[8][my][mx], syz = mo[9][my][mx];
+            T o0 = T(3) * mo[1][my][mx] + T(9) * (sxx * u0 + sxy * u1 + sxz * u2) - T(3) * pi * u0;
+            T o1 = T(3) * mo[2][my][mx] + T(9) * (sxy * u0 + syy * u1 + syz * u2) - T(3) * pi * u1;
+            T o2 = T(3) * mo[3][my][mx] + T(9) * (sxz * u0 + syz * u1 + szz * u2) - T(3) * pi * u2;
+            int off[5];
+            T cf[5];
+            int k = dT_stencil<T>(x, nx, g.per[0], off, cf);
+            for (int j = 0; j < k; j++) {  // a = x: sig_xb -> u_b
+                o0 += A2 * cf[j] * mo[4][my][mx + off[j]];
+                o1 += A2 * cf[j] * mo[7][my][mx + off[j]];
+                o2 += A2 * cf[j] * mo[8][my][mx + off[j]];
+            }
+            k = dT_stencil<T>(y, ny, g.per[1], off, cf);
+            for (int j = 0; j < k; j++) {  // a = y: sig_yb -> u_b
+                o0 += A2 * cf[j] * mo[7][my + off[j]][mx];
+                o1 += A2 * cf[j] * mo[5][my + off[j]][mx];
+                o2 += A2 * cf[j] * mo[9][my + off[j]][mx];
+            }
+            part[2][0] = T(3) * pi;
+            part[2][1] = o0;
+            part[2][2] = o1;
+            part[2][3] = o2;
+        }
+        __syncthreads();
+        const int zo = s - 2;
+        if (col_ok && zo >= z0 && zo < z1) {
+            int off[5];
+            T cf[5];
+            const int k = dT_stencil<T>(zo, nz, g.per[2], off, cf);
+            T o[3] = {part[0][1], part[0][2], part[0][3]};
+            for (int j = 0; j < k; j++) {  // a = z: sig_zb -> u_b, history index off + 2
+                const int h = off[j] + 2;
+                T hx = hz[0][0], hy = hz[0][1], hzz = hz[0][2];
+#pragma unroll
+                for (int q = 1; q < 5; q++)
+                    if (q == h) {
+                        hx = hz[q][0];
+                        hy = hz[q][1];
+                        hzz = hz[q][2];
+                    }
+                o[0] += A2 * cf[j] * hx;
+                o[1] += A2 * cf[j] * hy;
+                o[2] += A2 * cf[j] * hzz;
+            }
+            const long long id = (long long)x + (long long)nx * ((long long)y + (long long)ny * zo);
+            out[id] = part[0][0];
+            out[N + id] = o[0];
+            out[2 * N + id] = o[1];
+            out[3 * N + id] = o[2];
+        }
+        if (more) store(s + 2);
+    }
 }
 
 }  // namespace lks

@@ -233,7 +233,7 @@ int make_ctx(const lks_problem_t *P, Ctx &c) {
 // ------------------------------------------------------------------ layout
 struct Layout {
     size_t krT, krD, st1, ustar, Bf, Binit, part, counter, flag;
-    size_t seg, ustar_seg, Bseg, ab, kapk, usk, uk, ustb, kb, usb, URb, krb, part1, part3, rec, mom;
+    size_t seg, ustar_seg, Bseg, ab, kapk, usk, uk, ustb, kb, usb, URb, krb, part1, part3, rec;
     size_t total;
 };
 
@@ -276,7 +276,6 @@ Layout layout(const Ctx &c, bool adjoint) {
         L.part1 = take((size_t)c.nblk * 8 * 8);
         L.part3 = take((size_t)c.nblk * 8 * 8);
         L.rec = take(AR_SIZE * 8);
-        L.mom = take(c.dim == 3 ? 10 * (size_t)c.g.N * e : 0);
     }
     L.total = o;
     return L;
@@ -324,6 +323,15 @@ template <typename T> struct Run {
     hipStream_t st;
     Prof *pf;
 
+    // z planes per block of the 2.5D 3D kernels: enough blocks to fill the chip
+    // (about 512), between 4 and 32 planes.
+    template <typename U> int zchunk(int ty) const {
+        const long long bxy = (long long)blocks(c.g.n[0], 64) * blocks(c.g.n[1], ty);
+        long long zc = (long long)c.g.n[2] * bxy / 512;
+        zc = zc < 8 ? 8 : (zc > 32 ? 32 : zc);
+        return (int)zc;
+    }
+
     void gather(const T *in, T *out) const {
         if (c.dim == 2) {
             dim3 grid(blocks(c.g.n[0], G2_TX), blocks(c.g.n[1], G2_TY));
@@ -331,8 +339,10 @@ template <typename T> struct Run {
                 hipLaunchKernelGGL(k_gather2d<T>, grid, dim3(G2_TX, G2_TY), 0, st, c.g, T(c.A), in, out);
             });
         } else {
+            const int zc = zchunk<T>(G3<T>::TY);
+            const dim3 grid(blocks(c.g.n[0], G3<T>::TX), blocks(c.g.n[1], G3<T>::TY), blocks(c.g.n[2], zc));
             pf->run(LKS_K_GATHER, [&] {
-                hipLaunchKernelGGL(k_gather3d<T>, dim3(blocks(c.g.N, 256)), dim3(256), 0, st, c.g, T(c.A), in, out);
+                hipLaunchKernelGGL(k_gather3d<T>, grid, dim3(G3<T>::TX, G3<T>::TY), 0, st, c.g, T(c.A), zc, in, out);
             });
         }
     }
@@ -399,7 +409,7 @@ template <typename T> struct Run {
             }
         });
     }
-    void adj_gather(const T *ab, const T *ustb, const double *Bprev, const T *sprev, T *out, T *mom) const {
+    void adj_gather(const T *ab, const T *ustb, const double *Bprev, const T *sprev, T *out) const {
         const int hb = c.has_body ? 1 : 0;
         pf->run(LKS_K_ADJ_GATHER, [&] {
             if (c.dim == 2) {
@@ -407,10 +417,10 @@ template <typename T> struct Run {
                 hipLaunchKernelGGL(k_adjgather2d<T>, grid, dim3(G2_TX, G2_TY), 0, st, c.g, c.bc, T(c.A), ab, ustb,
                                    Bprev, c.D, hb, sprev, out);
             } else {
-                hipLaunchKernelGGL(k_adjmom3d<T>, dim3(blocks(c.g.N, 256)), dim3(256), 0, st, c.g, c.bc, ab, ustb,
-                                   Bprev, c.D, hb, mom);
-                hipLaunchKernelGGL(k_adjout3d<T>, dim3(blocks(c.g.N, 256)), dim3(256), 0, st, c.g, T(c.A), mom,
-                                   sprev, out);
+                const int zc = zchunk<T>(A3<T>::TY);
+                const dim3 grid(blocks(c.g.n[0], A3<T>::TX), blocks(c.g.n[1], A3<T>::TY), blocks(c.g.n[2], zc));
+                hipLaunchKernelGGL(k_adjgather3d<T>, grid, dim3(A3<T>::TX, A3<T>::TY), 0, st, c.g, c.bc, T(c.A), zc,
+                                   ab, ustb, Bprev, c.D, hb, sprev, out);
             }
         });
     }
@@ -544,7 +554,6 @@ int adjoint_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, const vo
     int *flag = at<int>(work, L.flag);
     T *seg = at<T>(work, L.seg), *ustar_seg = at<T>(work, L.ustar_seg), *ab = at<T>(work, L.ab);
     double *Bseg = at<double>(work, L.Bseg), *rec = at<double>(work, L.rec), *krb = at<double>(work, L.krb);
-    T *mom = c.dim == 3 ? at<T>(work, L.mom) : nullptr;
     T *ustb = at<T>(work, L.ustb);
     const size_t recN = (size_t)(c.K + 1) * B_REC;
     const size_t S = (size_t)c.S;
@@ -582,7 +591,7 @@ int adjoint_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, const vo
             pf.sample = (t0 + j - 1) % every == 0;
             const double *Bk = Bseg + (size_t)j * recN;
             if (c.has_body) R.body_rev(Bk, ustar_seg + (size_t)(j - 1) * fp, ab_cur, krT, krD, L, work);
-            R.adj_gather(ab_cur, ustb, Bk, seg + (size_t)(j - 1) * S, ab_nxt, mom);
+            R.adj_gather(ab_cur, ustb, Bk, seg + (size_t)(j - 1) * S, ab_nxt);
             T *tmp = ab_cur;
             ab_cur = ab_nxt;
             ab_nxt = tmp;
