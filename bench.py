@@ -51,6 +51,35 @@ def alg_bytes_per_launch(kernel, pb, elt):
     return None
 
 
+def kernel_source_hash():
+    """sha256 of the HIP sources: traffic counters taken on other sources are stale."""
+    import hashlib
+
+    h = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_2601_18272_amd", "csrc")
+    for name in sorted(os.listdir(src)):
+        with open(os.path.join(src, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from profiles/traffic_<workload>.md (FETCH_SIZE and
+    WRITE_SIZE runs, scaled by a copy kernel of known size), or None if absent or taken
+    on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    if "```json" not in text:
+        return None
+    blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    if blob.get("source_sha256") != kernel_source_hash():
+        return None
+    k = blob.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
 def launches_per_gradient(pb):
     NT, K = pb.n_steps, pb.n_itr
     return {"gather": 2 * NT, "bc": 2 * NT, "spread": 2 * K * NT, "interp": 2 * K * NT,
@@ -80,6 +109,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=40, help="time steps of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 256 MiB device copy (reference for HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -147,11 +178,22 @@ def main():
         avg_s = ms / n / 1e3
         ach = by / avg_s / 1e9
         roof = {"bound": "hbm", "kernel": name, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(pb.name, name),
                 "bytes_per_launch": by, "avg_launch_us": round(avg_s * 1e6, 3),
                 "samples": n, "dominant_kernel": dom,
                 "share_of_gradient_est": {k: round(v / sum(est.values()), 3) for k, v in est.items()}}
         break
+
+    if args.calibrate_copy:
+        n = 64 * 1024 * 1024
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            torch.mul(src, 1.0, out=dst)  # one elementwise pass: 256 MiB read, 256 MiB written
+        torch.cuda.synchronize()
+        del src, dst
+        print("# calibration copy done (2 x 256 MiB)", file=sys.stderr, flush=True)
 
     extra = {"ms_per_step_gpu_events": round(gpu_ms / args.steps, 3),
              "kernel_avg_us": {k: round(ms / n * 1e3, 3) for k, (ms, n) in prof.items() if n > 0}}

@@ -394,13 +394,19 @@ __device__ __forceinline__ void reduce_partials(const double *__restrict__ p1, c
 }
 
 // ------------------------------------------------------------------ forward interp
-// flag bits: 1 non-finite body state, 2 drift beyond the footprint margin.
+template <int DIM>
+__device__ __forceinline__ void interp_finish(const Design &D, const BodyParams &bp, double *Bk, int k, int K,
+                                              double *Bnext0, const double *part, unsigned nb, int *flag);
+
+// flag bits: 1 non-finite body state, 2 drift beyond the footprint margin. With
+// last = 0 the kernel only writes its partials (k_interp_finish follows).
 template <int DIM, typename T>
 __global__ __launch_bounds__(DBLK) void k_interp_force(Grid g, Design D, BodyParams bp,
                                                        const T *__restrict__ u, const double *__restrict__ krD,
                                                        double *__restrict__ Bk, int k, int K,
                                                        double *__restrict__ Bnext0, double *__restrict__ part,
-                                                       unsigned *__restrict__ counter, int *__restrict__ flag) {
+                                                       unsigned *__restrict__ counter, int *__restrict__ flag,
+                                                       int last) {
     const long long N = g.N;
     const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const double *B = Bk + k * B_REC;
@@ -441,9 +447,19 @@ __global__ __launch_bounds__(DBLK) void k_interp_force(Grid g, Design D, BodyPar
         v[3] = kr * (pick3(P.r, D.pi) * pick3(Dv, D.pj) - pick3(P.r, D.pj) * pick3(Dv, D.pi));
     }
     block_reduce_store<4>(v, part);
+    if (!last) return;
     if (!last_block(counter)) return;
+    interp_finish<DIM>(D, bp, Bk, k, K, Bnext0, part, gridDim.x, flag);
+    if (threadIdx.x == 0) *counter = 0u;
+}
+
+// Fixed-order sum of the force/torque partials and the Euler update of Sec. 2.4:
+// B^(k+1) from B(t-1) (plus, after the last iteration, the next step's first record).
+template <int DIM>
+__device__ __forceinline__ void interp_finish(const Design &D, const BodyParams &bp, double *Bk, int k, int K,
+                                              double *Bnext0, const double *part, unsigned nb, int *flag) {
     __shared__ double FT[4];
-    reduce_partials<4>(part, nullptr, gridDim.x, FT);
+    reduce_partials<4>(part, nullptr, nb, FT);
     if (threadIdx.x == 0) {
         double ft[4] = {FT[0], FT[1], FT[2], FT[3]};
         double *Bn = Bk + (k + 1) * B_REC;
@@ -457,8 +473,17 @@ __global__ __launch_bounds__(DBLK) void k_interp_force(Grid g, Design D, BodyPar
         } else if (Bnext0) {
             for (int j = 0; j < B_REC; j++) Bnext0[j] = Bn[j];
         }
-        *counter = 0u;
     }
+}
+
+// One block: the same finish for grids too large for the last-block pattern (one
+// arrival counter shared by thousands of blocks serialises them).
+template <int DIM>
+__global__ __launch_bounds__(256) void k_interp_finish(Design D, BodyParams bp, double *__restrict__ Bk, int k,
+                                                       int K, double *__restrict__ Bnext0,
+                                                       const double *__restrict__ part, unsigned nb,
+                                                       int *__restrict__ flag) {
+    interp_finish<DIM>(D, bp, Bk, k, K, Bnext0, part, nb, flag);
 }
 
 // Standalone Euler update (body_step entry point).
@@ -690,14 +715,19 @@ __global__ __launch_bounds__(256) void k_adj_r2(Grid g, Bc bc, Design D, const d
     kb[l] = kbar;
 }
 
+template <int DIM>
+__device__ __forceinline__ void r3_finish(const BodyParams &bp, int k, const double *part1, const double *part3,
+                                          unsigned nb, double *rec);
+
 // R3: transpose of the spread at iteration k (design-point parallel), the pose
-// reversed; the last block forms the body cotangent B^(k)bar and steps the record.
+// reversed; the last block (or k_r3_finish when last = 0) forms the body cotangent
+// B^(k)bar and steps the record.
 template <int DIM, typename T>
 __global__ __launch_bounds__(DBLK) void k_adj_r3(Grid g, Design D, BodyParams bp, const double *__restrict__ Bk,
                                                  int k, const T *__restrict__ kb, const T *__restrict__ usb,
                                                  const double *__restrict__ krD, double *__restrict__ krb,
                                                  const double *__restrict__ part1, double *__restrict__ part3,
-                                                 unsigned *__restrict__ counter, double *__restrict__ rec) {
+                                                 unsigned *__restrict__ counter, double *__restrict__ rec, int last) {
     const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long bN = D.boxN;
     const double *B = Bk + k * B_REC;
@@ -751,9 +781,20 @@ __global__ __launch_bounds__(DBLK) void k_adj_r3(Grid g, Design D, BodyParams bp
         pose_rev(D, B, P, Xb, USb, rb, v);
     }
     block_reduce_store<8>(v, part3);
+    if (!last) return;
     if (!last_block(counter)) return;
+    r3_finish<DIM>(bp, k, part1, part3, gridDim.x, rec);
+    if (threadIdx.x == 0) *counter = 0u;
+}
+
+// Body cotangent B^(k)bar from the R1 and R3 partials (fixed order), then the record
+// step: the force/torque cotangent of iteration k-1, or at k = 0 the cotangent of
+// B(t-1) and the force/torque cotangent of the previous step's last iteration.
+template <int DIM>
+__device__ __forceinline__ void r3_finish(const BodyParams &bp, int k, const double *part1, const double *part3,
+                                          unsigned nb, double *rec) {
     __shared__ double Bkb[8];
-    reduce_partials<8>(part1, part3, gridDim.x, Bkb);
+    reduce_partials<8>(part1, part3, nb, Bkb);
     if (threadIdx.x == 0) {
         double bb[B_REC];
         for (int j = 0; j < B_REC; j++) bb[j] = j < 8 ? Bkb[j] : 0.0;
@@ -768,8 +809,14 @@ __global__ __launch_bounds__(DBLK) void k_adj_r3(Grid g, Design D, BodyParams bp
             }
             body_update_rev<DIM>(bp, rec + AR_BBAR, rec + AR_FTB, acc);
         }
-        *counter = 0u;
     }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_r3_finish(BodyParams bp, int k, const double *__restrict__ part1,
+                                                   const double *__restrict__ part3, unsigned nb,
+                                                   double *__restrict__ rec) {
+    r3_finish<DIM>(bp, k, part1, part3, nb, rec);
 }
 
 // grad = krb * d kappa_ref / d gamma; optional body cotangent of t = 0.

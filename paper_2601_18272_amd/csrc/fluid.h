@@ -559,42 +559,26 @@ __global__ __launch_bounds__(A3<T>::NT) void k_adjgather3d(Grid g, Bc bc, T A, i
         bx.L[1] = D.L[1];
         bx.L[2] = D.L[2];
     }
-    // the inputs of plane s + 2 are formed into registers during iteration s and stored
-    // into the slot of plane s - 1 at its end (software pipelining of the loads)
-    constexpr int PER = (GX * GY + NT - 1) / NT;
-    T pre[PER][4];
-    auto fetch = [&](int zp) {
+    auto load_plane = [&](int zp) {
         int zw = zp;
         const bool zok = wrap_coord(zw, nz, g.per[2]);
-#pragma unroll
-        for (int j = 0; j < PER; j++) {
-            const int l = tid + j * NT;
+        const int slot = ((zp % 3) + 3) % 3;
+        for (int l = tid; l < GX * GY; l += NT) {
             const int lx = l % GX, ly = l / GX;
             int xx[3] = {x0 + lx - 3, y0 + ly - 3, zw};
-#pragma unroll
-            for (int c = 0; c < 4; c++) pre[j][c] = 0;
-            if (l < GX * GY && zok && wrap_coord(xx[0], nx, g.per[0]) && wrap_coord(xx[1], ny, g.per[1]) &&
+            T v[4] = {0, 0, 0, 0};
+            if (zok && wrap_coord(xx[0], nx, g.per[0]) && wrap_coord(xx[1], ny, g.per[1]) &&
                 is_interior<3>(g, xx)) {
                 const long long id = node_id(g, xx[0], xx[1], xx[2]);
                 T pb, ub[3];
                 star_bar<3, T>(g, bc, ab, ustb, bx, has_box, D.boxN, xx, id, pb, ub);
-                pre[j][0] = pb * T(1.0 / 3.0);
-                pre[j][1] = ub[0];
-                pre[j][2] = ub[1];
-                pre[j][3] = ub[2];
+                v[0] = pb * T(1.0 / 3.0);
+                v[1] = ub[0];
+                v[2] = ub[1];
+                v[3] = ub[2];
             }
-        }
-    };
-    auto store = [&](int zp) {
-        const int slot = ((zp % 3) + 3) % 3;
 #pragma unroll
-        for (int j = 0; j < PER; j++) {
-            const int l = tid + j * NT;
-            if (l < GX * GY) {
-                const int lx = l % GX, ly = l / GX;
-#pragma unroll
-                for (int c = 0; c < 4; c++) gw[slot][c][ly][lx] = pre[j][c];
-            }
+            for (int c = 0; c < 4; c++) gw[slot][c][ly][lx] = v[c];
         }
     };
     const int x = x0 + tx, y = y0 + ty;
@@ -608,13 +592,10 @@ __global__ __launch_bounds__(A3<T>::NT) void k_adjgather3d(Grid g, Bc bc, T A, i
 #pragma unroll
     for (int j = 0; j < 5; j++) hz[j][0] = hz[j][1] = hz[j][2] = 0;
     const T A2 = T(2) * A;
-    for (int zp = z0 - 3; zp <= z0 - 1; zp++) {
-        fetch(zp);
-        store(zp);
-    }
+    load_plane(z0 - 3);
+    load_plane(z0 - 2);
     for (int s = z0 - 2; s <= z1 + 1; s++) {
-        const bool more = s + 2 <= z1 + 2;  // planes up to z1 + 2 are read (last s = z1 + 1)
-        if (more) fetch(s + 2);
+        load_plane(s + 1);
         __syncthreads();
         const int gm = ((s - 1) % 3 + 3) % 3, g0 = ((s % 3) + 3) % 3, gp = ((s + 1) % 3 + 3) % 3;
         for (int l = tid; l < MX * MY; l += NT) {
@@ -714,7 +695,6 @@ __global__ __launch_bounds__(A3<T>::NT) void k_adjgather3d(Grid g, Bc bc, T A, i
             out[2 * N + id] = o[1];
             out[3 * N + id] = o[2];
         }
-        if (more) store(s + 2);
     }
 }
 

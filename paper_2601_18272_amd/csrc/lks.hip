@@ -323,6 +323,11 @@ template <typename T> struct Run {
     hipStream_t st;
     Prof *pf;
 
+    // The cross-block finish of the design-point reductions runs in the last block to
+    // arrive while the grid is small; beyond that the arrival counter serialises the
+    // blocks and a one-block finish kernel is cheaper.
+    bool last_block_ok() const { return c.nblk <= 256; }
+
     // z planes per block of the 2.5D 3D kernels: enough blocks to fill the chip
     // (about 512), between 4 and 32 planes.
     template <typename U> int zchunk(int ty) const {
@@ -371,7 +376,10 @@ template <typename T> struct Run {
                 });
                 pf->run(LKS_K_INTERP, [&] {
                     hipLaunchKernelGGL((k_interp_force<DIM, T>), dim3(c.nblk), dim3(DBLK), 0, st, c.g, c.D, c.bp, u,
-                                       krD, Bk, k, c.K, Bnext0, part, counter, flag);
+                                       krD, Bk, k, c.K, Bnext0, part, counter, flag, last_block_ok() ? 1 : 0);
+                    if (!last_block_ok())
+                        hipLaunchKernelGGL((k_interp_finish<DIM>), dim3(1), dim3(256), 0, st, c.D, c.bp, Bk, k, c.K,
+                                           Bnext0, part, c.nblk, flag);
                 });
             }
         });
@@ -404,7 +412,9 @@ template <typename T> struct Run {
                 });
                 pf->run(LKS_K_ADJ_R3, [&] {
                     hipLaunchKernelGGL((k_adj_r3<DIM, T>), dim3(c.nblk), dim3(DBLK), 0, st, c.g, c.D, c.bp, Bk, k,
-                                       kb, usb, krD, krb, p1, p3, counter, rec);
+                                       kb, usb, krD, krb, p1, p3, counter, rec, last_block_ok() ? 1 : 0);
+                    if (!last_block_ok())
+                        hipLaunchKernelGGL((k_r3_finish<DIM>), dim3(1), dim3(256), 0, st, c.bp, k, p1, p3, c.nblk, rec);
                 });
             }
         });
