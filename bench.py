@@ -99,6 +99,80 @@ def run_cpu_baseline(pb, sample_steps):
     return spb, J, grad, dt
 
 
+def copy_bandwidth(mib=1024, reps=5):
+    """GB/s of a plain elementwise device copy (read + write) of `mib` MiB."""
+    import torch
+
+    n = mib * 1024 * 1024 // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.mul(src, 1.0, out=dst)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+    return 2 * n * 4 / sec / 1e9
+
+
+SWEEP = {
+    2: [(512, 256), (1024, 512), (2048, 1024), (4096, 2048), (8192, 4096), (8192, 8192)],
+    3: [(128, 64, 64), (256, 128, 128), (512, 256, 128), (512, 256, 256)],
+}
+
+
+def roofline_sweep(args):
+    """Body-free gradients (forward with checkpoints + adjoint) of growing channels and
+    ducts: the LKS and adjoint LKS kernels against the HBM roofline once the fields no
+    longer fit the caches (8192 x 8192 2D and 512 x 256 x 256 3D move > 1 GB per
+    launch)."""
+    import torch
+
+    import paper_2601_18272_amd as lks
+    import workloads as W
+    from paper_2601_18272_amd import _lib
+
+    for dim in (2, 3):
+        for n in SWEEP[dim]:
+            if dim == 2:
+                pb = W.channel2d(n[0], n[1], 0.05, 0.128, n_steps=16, ckpt_every=8, name=f"channel {n[0]}x{n[1]}")
+            else:
+                pb = W.duct3d(*n, 0.04, 0.01707, n_steps=8, ckpt_every=4, name="duct " + "x".join(map(str, n)))
+            s0 = torch.tensor(W.initial_state(pb), dtype=torch.float32, device="cuda")
+            b0 = torch.zeros(12, dtype=torch.float64, device="cuda")
+            bufs = lks.Buffers(pb, "fp32", adjoint=True)
+
+            def grad_step():
+                _, _, _, B = lks.forward(pb, None, s0, b0, "fp32", buffers=bufs, flags=_lib.FLAG_PROFILE)
+                lks.adjoint(pb, None, B, precision="fp32", flags=_lib.FLAG_PROFILE)
+
+            grad_step()
+            torch.cuda.synchronize()
+            _lib.profile_reset()
+            t0 = time.perf_counter()
+            for _ in range(max(args.steps, 1)):
+                grad_step()
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / max(args.steps, 1)
+            prof = _lib.profile_read()
+            line = {"sweep": "body-free roofline", "workload": pb.name, "dim": dim, "nodes": pb.N,
+                    "dtype": "f32", "gradient_MLUPS": round(pb.N * pb.n_steps / wall / 1e6, 1)}
+            for k in ("gather", "adj_gather"):
+                ms, cnt = prof[k]
+                us = ms / cnt * 1e3
+                by = alg_bytes_per_launch(k, pb, 4)
+                line[k] = {"avg_launch_us": round(us, 2), "bytes_per_launch": by,
+                           "achieved_GBs": round(by / us / 1e3, 1),
+                           "frac": round(by / us / 1e3 / HBM_PEAK_GBS, 4), "samples": cnt}
+            print(json.dumps(line), flush=True)
+            del bufs, s0
+            torch.cuda.empty_cache()
+    print(json.dumps({"sweep": "copy", "elementwise_copy_1GiB_GBs": round(copy_bandwidth(), 1)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +183,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=40, help="time steps of the oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--sweep", action="store_true",
+                    help="body-free roofline sweep of the LKS and adjoint LKS kernels over grid sizes "
+                         "up to > 1 GB per step (one JSON line per size instead of the headline)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB device copy (reference for HBM traffic counters)")
     args = ap.parse_args()
@@ -125,6 +202,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.sweep:
+        roofline_sweep(args)
+        return
     pb = W.config(args.workload)
     if args.n_steps:
         pb = pb.replace(n_steps=args.n_steps)
@@ -197,6 +277,15 @@ def main():
 
     extra = {"ms_per_step_gpu_events": round(gpu_ms / args.steps, 3),
              "kernel_avg_us": {k: round(ms / n * 1e3, 3) for k, (ms, n) in prof.items() if n > 0}}
+
+    # forward pass alone (with its checkpoints), outside the timed region
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lks.forward(pb, g, s0, b0, "fp32", buffers=bufs)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t1
+    extra["forward_only"] = {"ms": round(tf * 1e3, 2), "MLUPS": round(pb.N * pb.n_steps / tf / 1e6, 2)}
+    extra["copy_GBs_elementwise_1GiB"] = round(copy_bandwidth(), 1)
 
     if not args.no_fp64:
         bufs64 = lks.Buffers(pb, "fp64", adjoint=True)

@@ -114,7 +114,7 @@ def adjoint(pb, gamma, buffers: Buffers, seed: float = 1.0, precision="fp32",
     L = _lib.load()
     dt = DTYPES[precision]
     s = problem_struct(pb, precision, flags)
-    g = _dev(gamma, dt)
+    g = _dev(gamma, dt) if gamma is not None else None
     grad = torch.empty(max(int(pb.nd[0] * pb.nd[1] * pb.nd[2]), 1), dtype=torch.float64, device="cuda")
     ds = torch.empty(state_elems(pb), dtype=dt, device="cuda") if want_initial else None
     db = torch.empty(12, dtype=torch.float64, device="cuda") if want_initial else None

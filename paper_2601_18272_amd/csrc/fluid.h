@@ -14,6 +14,8 @@
 //   pbar(y) = 3 pi,  ubar_b(y) = 3 ups_b + 9 sig_ba u_a - 3 pi u_b + 2A sum_a D_a^T sig_ab,
 // with D_a^T the transpose of the boundary-aware difference operator.
 #pragma once
+#include <type_traits>
+
 #include "lks_device.h"
 
 namespace lks {
@@ -34,7 +36,8 @@ __global__ __launch_bounds__(512) void k_gather2d(Grid g, T A, const T *__restri
     __shared__ T sf[9][FY][FX];
     const long long N = g.N;
     const int nx = g.n[0], ny = g.n[1];
-    const int x0 = blockIdx.x * G2_TX, y0 = blockIdx.y * G2_TY;
+    const uint3 tb = xcd_tile();
+    const int x0 = tb.x * G2_TX, y0 = tb.y * G2_TY;
     const int tid = threadIdx.x + G2_TX * threadIdx.y;
 
     for (int l = tid; l < RX * RY; l += 512) {
@@ -123,149 +126,182 @@ __global__ __launch_bounds__(512) void k_gather2d(Grid g, T A, const T *__restri
 }
 
 // ===================================================================== forward, 3D
-// 2.5D blocking: a TX x TY tile of (x, y) columns marches along z over ZC output
-// planes. For every source plane s, the f_i of the tile plus a one-node (x, y) ring are
-// evaluated once into LDS and pushed to the destination planes s-1, s, s+1, whose
-// moments each thread keeps in registers for its column. p, u of planes s-2..s+2 sit
-// in a 5-slot LDS ring with a two-node (x, y) ring (the one-sided z-derivative at a
-// wall reaches two planes).
+// 2.5D blocking. A block of TX x TY threads is the tile of source columns (x, y) whose
+// f_i it evaluates, one column per thread; it writes the inner (TX-2) x (TY-2) columns
+// and marches along z over ZC output planes. Per source plane s each thread evaluates
+// the 15 f_i of its node into LDS and pushes them (by the gather of its output column)
+// to the destination planes s-1, s, s+1, whose moments it keeps in registers. The
+// thread's own column of p, u for planes s-2..s+2 (the z-derivative, one-sided at a
+// wall, reaches two planes) lives in registers, filled one plane ahead; only u of
+// plane s with a one-node ring is staged in LDS for the x and y derivatives.
 template <typename T> struct G3 {
-    static constexpr int TX = 64, TY = sizeof(T) == 4 ? 8 : 4, NT = TX * TY;
+    static constexpr int TX = 64, TY = 8, NT = TX * TY;
+    static constexpr int OX = TX - 2, OY = TY - 2;  // output tile
+    static constexpr int WX = TX + 2, WY = TY + 2;  // staged u plane
+    static constexpr int RING = 2 * WX + 2 * TY;    // staged nodes outside the tile
 };
 
+// Twice the derivative along one axis from the values at offsets -2..2: central in the
+// interior and on periodic axes, second-order one-sided on the end nodes of a
+// non-periodic axis.
 template <typename T>
-__device__ __forceinline__ T d1(T m2, T m1, T c, T p1, T p2, int v, int n, int per) {
-    // derivative along one axis from the values at offsets -2..2 (boundary-aware)
-    if (per || (v > 0 && v < n - 1)) return T(0.5) * (p1 - m1);
-    if (v == 0) return T(0.5) * (T(-3) * c + T(4) * p1 - p2);
-    return T(0.5) * (T(3) * c - T(4) * m1 + m2);
+__device__ __forceinline__ T d2(T m2, T m1, T c, T p1, T p2, int v, int n, int per) {
+    T d = p1 - m1;
+    if (!per && (v == 0 || v == n - 1)) d = v == 0 ? T(-3) * c + T(4) * p1 - p2 : T(3) * c - T(4) * m1 + m2;
+    return d;
+}
+
+// Weighted equilibria F_i = w_i f_i of one D3Q15 node (Lat<3> order), from p, u and
+// D[a][b] = 2 d_a u_b. Opposite directions share the quadratic part and differ in the
+// sign of 3 c.u, so each +-c pair costs one evaluation; the weights are folded into
+// the per-class constants.
+template <typename T>
+__device__ __forceinline__ void feq3(T p, const T u[3], const T D[3][3], T A, T F[15]) {
+    constexpr T w0 = T(2.0 / 9.0), w1 = T(1.0 / 9.0), w2 = T(1.0 / 72.0);
+    const T B = T(3) * p - T(1.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    F[0] = w0 * B;
+    const T B1 = w1 * B, a1 = w1 * A;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const T sq = B1 + a1 * D[a][a] + (T(4.5) * w1 * u[a]) * u[a];
+        const T li = (T(3) * w1) * u[a];
+        F[1 + 2 * a] = sq + li;
+        F[2 + 2 * a] = sq - li;
+    }
+    const T a2 = w2 * A;
+    const T C = w2 * B + a2 * (D[0][0] + D[1][1] + D[2][2]);
+    const T exy = a2 * (D[0][1] + D[1][0]), exz = a2 * (D[0][2] + D[2][0]), eyz = a2 * (D[1][2] + D[2][1]);
+    // corner pairs (i, opposite): (+,+,+) 7/14, (+,+,-) 8/13, (+,-,+) 9/12, (+,-,-) 10/11
+    const T cu[4] = {u[0] + u[1] + u[2], u[0] + u[1] - u[2], u[0] - u[1] + u[2], u[0] - u[1] - u[2]};
+    const T q[4] = {exy + exz + eyz, exy - exz - eyz, exz - exy - eyz, eyz - exy - exz};
+    constexpr int ip[4] = {7, 8, 9, 10}, im[4] = {14, 13, 12, 11};
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const T sq = C + q[k] + (T(4.5) * w2 * cu[k]) * cu[k];
+        const T li = (T(3) * w2) * cu[k];
+        F[ip[k]] = sq + li;
+        F[im[k]] = sq - li;
+    }
 }
 
 template <typename T>
-__global__ __launch_bounds__(G3<T>::NT) void k_gather3d(Grid g, T A, int ZC, const T *__restrict__ sin_,
+__global__ __launch_bounds__(G3<T>::NT, sizeof(T) == 4 ? 6 : 2) void k_gather3d(Grid g, T A, int ZC, const T *__restrict__ sin_,
                                                         T *__restrict__ sout) {
-    constexpr int TX = G3<T>::TX, TY = G3<T>::TY, NT = G3<T>::NT;
-    constexpr int RX = TX + 4, RY = TY + 4, FX = TX + 2, FY = TY + 2;
-    __shared__ T win[5][4][RY][RX];
-    __shared__ T fb[15][FY][FX];
+    using G = G3<T>;
+    constexpr int TX = G::TX, TY = G::TY, WX = G::WX, WY = G::WY;
+    __shared__ T wu[2][3][WY][WX];
+    __shared__ T fb[15][TY][TX];
     const long long N = g.N;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-    const int z0 = blockIdx.z * ZC, z1 = min(z0 + ZC, nz);
+    const uint3 tb = xcd_tile();
+    const int x0 = tb.x * G::OX, y0 = tb.y * G::OY;
+    const int z0 = tb.z * ZC, z1 = min(z0 + ZC, nz);
     const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TX * ty;
 
-    // plane loads: each thread owns the ring-window entries l = tid + j*NT; a plane is
-    // fetched into registers one iteration ahead and stored into its LDS slot after the
-    // slot's previous plane is no longer read (software pipelining of the HBM latency)
-    constexpr int PER = (RX * RY + NT - 1) / NT;
-    T pre[PER][4];
-    auto fetch = [&](int zp) {
+    // this thread's source column
+    int cx = x0 - 1 + tx, cy = y0 - 1 + ty;
+    const bool colok = wrap_coord(cx, nx, g.per[0]) && wrap_coord(cy, ny, g.per[1]);
+    const long long col = colok ? (long long)cx + (long long)nx * cy : 0;
+    // ring node of the staged plane handled by this thread (tid < RING)
+    int rx = 0, ry = 0;
+    if (tid < 2 * WX) {
+        rx = tid % WX;
+        ry = tid < WX ? 0 : WY - 1;
+    } else if (tid < G::RING) {
+        const int k = tid - 2 * WX;
+        ry = 1 + (k >> 1);
+        rx = (k & 1) ? WX - 1 : 0;
+    }
+    int gx = x0 - 2 + rx, gy = y0 - 2 + ry;
+    const bool ringok = tid < G::RING && wrap_coord(gx, nx, g.per[0]) && wrap_coord(gy, ny, g.per[1]);
+    const long long rcol = ringok ? (long long)gx + (long long)nx * gy : 0;
+
+    const long long plane = (long long)nx * ny;
+    auto load_col = [&](int zp, T v[4]) {
         int zw = zp;
-        const bool zok = wrap_coord(zw, nz, g.per[2]);
+        const bool ok = colok && wrap_coord(zw, nz, g.per[2]);
+        const long long id = col + plane * zw;
 #pragma unroll
-        for (int j = 0; j < PER; j++) {
-            const int l = tid + j * NT;
-            const int lx = l % RX, ly = l / RX;
-            int x = x0 + lx - 2, y = y0 + ly - 2;
-#pragma unroll
-            for (int c = 0; c < 4; c++) pre[j][c] = 0;
-            if (l < RX * RY && zok && wrap_coord(x, nx, g.per[0]) && wrap_coord(y, ny, g.per[1])) {
-                const long long id = (long long)x + (long long)nx * ((long long)y + (long long)ny * zw);
-#pragma unroll
-                for (int c = 0; c < 4; c++) pre[j][c] = sin_[c * N + id];
-            }
-        }
+        for (int c = 0; c < 4; c++) v[c] = ok ? sin_[c * N + id] : T(0);
     };
-    auto store = [&](int zp) {
-        const int slot = ((zp % 5) + 5) % 5;
+    auto load_ring = [&](int zp, T v[3]) {
+        int zw = zp;
+        const bool ok = ringok && wrap_coord(zw, nz, g.per[2]);
+        const long long id = rcol + plane * zw;
 #pragma unroll
-        for (int j = 0; j < PER; j++) {
-            const int l = tid + j * NT;
-            if (l < RX * RY) {
-                const int lx = l % RX, ly = l / RX;
-#pragma unroll
-                for (int c = 0; c < 4; c++) win[slot][c][ly][lx] = pre[j][c];
-            }
-        }
+        for (int c = 0; c < 3; c++) v[c] = ok ? sin_[(c + 1) * N + id] : T(0);
     };
 
+    T q[5][4];  // own column, planes s-2 .. s+2
+#pragma unroll
+    for (int j = 0; j < 5; j++) load_col(z0 - 3 + j, q[j]);
+    T rv[3];
+    load_ring(z0 - 1, rv);
+
     T accP[3] = {0, 0, 0}, accU[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    for (int zp = z0 - 3; zp <= z0 + 1; zp++) {
-        fetch(zp);
-        store(zp);
-    }
     for (int s = z0 - 1; s <= z1; s++) {
-        const bool more = s + 3 <= z1 + 2;  // planes up to z1 + 2 are read (last s = z1)
-        if (more) fetch(s + 3);
+        const int b = s & 1;
+        // stage u of plane s: own node and ring node
+#pragma unroll
+        for (int c = 0; c < 3; c++) wu[b][c][ty + 1][tx + 1] = q[2][1 + c];
+        if (tid < G::RING) {
+#pragma unroll
+            for (int c = 0; c < 3; c++) wu[b][c][ry][rx] = rv[c];
+        }
+        // next planes in flight while this one is evaluated
+        const bool more = s + 3 <= z1 + 2;
+        T nq[4], nr[3];
+        if (more) load_col(s + 3, nq);
+        if (s + 1 <= z1) load_ring(s + 1, nr);
         __syncthreads();
+
+        // Sources off the grid (non-periodic axes) only feed boundary nodes, which this
+        // kernel does not write; their f_i are evaluated from zeros and never used.
         int zs = s;
-        const bool sok = wrap_coord(zs, nz, g.per[2]);
-        const int sm2 = ((s - 2) % 5 + 5) % 5, sm1 = ((s - 1) % 5 + 5) % 5, s0 = ((s % 5) + 5) % 5;
-        const int sp1 = ((s + 1) % 5 + 5) % 5, sp2 = ((s + 2) % 5 + 5) % 5;
-        for (int l = tid; l < FX * FY; l += NT) {
-            const int fx = l % FX, fy = l / FX;
-            const int lx = fx + 1, ly = fy + 1;
-            int x = x0 + fx - 1, y = y0 + fy - 1;
-            const bool ok = sok && wrap_coord(x, nx, g.per[0]) && wrap_coord(y, ny, g.per[1]);
-            T f[15];
-            if (ok) {
-                T S[3][3];  // S[a][b] = d_a u_b
+        (void)wrap_coord(zs, nz, g.per[2]);
+        T f[15];
+        {
+            const int lx = tx + 1, ly = ty + 1;
+            T D[3][3];  // D[a][b] = 2 d_a u_b
 #pragma unroll
-                for (int b = 0; b < 3; b++) {
-                    const T(*U)[RX] = win[s0][1 + b];
-                    S[0][b] = d1(U[ly][lx - 2 < 0 ? 0 : lx - 2], U[ly][lx - 1], U[ly][lx], U[ly][lx + 1],
-                                 U[ly][lx + 2 >= RX ? RX - 1 : lx + 2], x, nx, g.per[0]);
-                    S[1][b] = d1(U[ly - 2 < 0 ? 0 : ly - 2][lx], U[ly - 1][lx], U[ly][lx], U[ly + 1][lx],
-                                 U[ly + 2 >= RY ? RY - 1 : ly + 2][lx], y, ny, g.per[1]);
-                    S[2][b] = d1(win[sm2][1 + b][ly][lx], win[sm1][1 + b][ly][lx], U[ly][lx],
-                                 win[sp1][1 + b][ly][lx], win[sp2][1 + b][ly][lx], zs, nz, g.per[2]);
-                }
-                const T p = win[s0][0][ly][lx];
-                const T u[3] = {win[s0][1][ly][lx], win[s0][2][ly][lx], win[s0][3][ly][lx]};
-                const T base = T(3) * p - T(1.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-                // A c.(S + S^T).c = 2A (sum_a c_a^2 S_aa + sum_{a<b} c_a c_b (S_ab + S_ba))
-                const T dxx = T(2) * A * S[0][0], dyy = T(2) * A * S[1][1], dzz = T(2) * A * S[2][2];
-                const T exy = T(2) * A * (S[0][1] + S[1][0]), exz = T(2) * A * (S[0][2] + S[2][0]);
-                const T eyz = T(2) * A * (S[1][2] + S[2][1]);
-#pragma unroll
-                for (int i = 0; i < 15; i++) {
-                    const int cx = Lat<3>::c(i, 0), cy = Lat<3>::c(i, 1), cz = Lat<3>::c(i, 2);
-                    const T cu = T(cx) * u[0] + T(cy) * u[1] + T(cz) * u[2];
-                    const T an = T(cx * cx) * dxx + T(cy * cy) * dyy + T(cz * cz) * dzz + T(cx * cy) * exy +
-                                 T(cx * cz) * exz + T(cy * cz) * eyz;
-                    f[i] = T(Lat<3>::w(i)) * (base + T(3) * cu + T(4.5) * cu * cu + an);
-                }
-            } else {
-#pragma unroll
-                for (int i = 0; i < 15; i++) f[i] = 0;
+            for (int c = 0; c < 3; c++) {
+                const T(*U)[WX] = wu[b][c];
+                D[0][c] = d2(U[ly][lx - 2 < 0 ? 0 : lx - 2], U[ly][lx - 1], U[ly][lx], U[ly][lx + 1],
+                             U[ly][lx + 2 >= WX ? WX - 1 : lx + 2], cx, nx, g.per[0]);
+                D[1][c] = d2(U[ly - 2 < 0 ? 0 : ly - 2][lx], U[ly - 1][lx], U[ly][lx], U[ly + 1][lx],
+                             U[ly + 2 >= WY ? WY - 1 : ly + 2][lx], cy, ny, g.per[1]);
+                D[2][c] = d2(q[0][1 + c], q[1][1 + c], q[2][1 + c], q[3][1 + c], q[4][1 + c], zs, nz, g.per[2]);
             }
-#pragma unroll
-            for (int i = 0; i < 15; i++) fb[i][fy][fx] = f[i];
+            const T u[3] = {q[2][1], q[2][2], q[2][3]};
+            feq3(q[2][0], u, D, A, f);
         }
-        __syncthreads();
 #pragma unroll
-        for (int i = 0; i < 15; i++) {
-            const int cx = Lat<3>::c(i, 0), cy = Lat<3>::c(i, 1), cz = Lat<3>::c(i, 2);
-            const T f = fb[i][ty + 1 - cy][tx + 1 - cx];
-            accP[cz + 1] += f;
-            accU[cz + 1][0] += T(cx) * f;
-            accU[cz + 1][1] += T(cy) * f;
-            accU[cz + 1][2] += T(cz) * f;
-        }
+        for (int i = 0; i < 15; i++) fb[i][ty][tx] = f[i];
         __syncthreads();
-        // destination plane s - 1 has received all its sources
-        const int zd = s - 1;
-        const int x = x0 + tx, y = y0 + ty;
-        if (zd >= z0 && zd < z1 && x < nx && y < ny) {
-            const int xx[3] = {x, y, zd};
-            if (is_interior<3>(g, xx)) {
-                const long long id = (long long)x + (long long)nx * ((long long)y + (long long)ny * zd);
-                sout[id] = accP[0] * T(1.0 / 3.0);
+
+        const bool out = tx < G::OX && ty < G::OY;
+        if (out) {
 #pragma unroll
-                for (int a = 0; a < 3; a++) sout[(1 + a) * N + id] = accU[0][a];
+            for (int i = 0; i < 15; i++) {
+                const int ex = Lat<3>::c(i, 0), ey = Lat<3>::c(i, 1), ez = Lat<3>::c(i, 2);
+                const T v = fb[i][ty + 1 - ey][tx + 1 - ex];
+                accP[ez + 1] += v;
+                accU[ez + 1][0] += T(ex) * v;
+                accU[ez + 1][1] += T(ey) * v;
+                accU[ez + 1][2] += T(ez) * v;
+            }
+            // destination plane s - 1 has received all its sources
+            const int zd = s - 1, x = x0 + tx, y = y0 + ty;
+            if (zd >= z0 && zd < z1 && x < nx && y < ny) {
+                const int xx[3] = {x, y, zd};
+                if (is_interior<3>(g, xx)) {
+                    const long long id = (long long)x + (long long)nx * ((long long)y + (long long)ny * zd);
+                    sout[id] = accP[0] * T(1.0 / 3.0);
+#pragma unroll
+                    for (int a = 0; a < 3; a++) sout[(1 + a) * N + id] = accU[0][a];
+                }
             }
         }
-        if (more) store(s + 3);
         accP[0] = accP[1];
         accP[1] = accP[2];
         accP[2] = 0;
@@ -274,6 +310,19 @@ __global__ __launch_bounds__(G3<T>::NT) void k_gather3d(Grid g, T A, int ZC, con
             accU[0][a] = accU[1][a];
             accU[1][a] = accU[2][a];
             accU[2][a] = 0;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+#pragma unroll
+            for (int c = 0; c < 4; c++) q[j][c] = q[j + 1][c];
+        }
+        if (more) {
+#pragma unroll
+            for (int c = 0; c < 4; c++) q[4][c] = nq[c];
+        }
+        if (s + 1 <= z1) {
+#pragma unroll
+            for (int c = 0; c < 3; c++) rv[c] = nr[c];
         }
     }
 }
@@ -409,6 +458,37 @@ __device__ __forceinline__ int dT_stencil(int za, int n, int per, int off[5], T 
     return k;
 }
 
+// o += scale * (D_a^T sig)(z) for three sig components, with get(off, v) returning the
+// components at z + off * e_a; the same coefficients as dT_stencil in straight-line
+// form (no local arrays), central away from the ends of a non-periodic axis.
+template <typename T, typename F>
+__device__ __forceinline__ void dT_apply3(int za, int n, int per, T scale, F &&get, T o[3]) {
+    auto add = [&](T cf, auto offc) {
+        T v[3];
+        get(decltype(offc)::value, v);
+        const T k = scale * cf;
+        o[0] += k * v[0];
+        o[1] += k * v[1];
+        o[2] += k * v[2];
+    };
+    using m2 = std::integral_constant<int, -2>;
+    using m1 = std::integral_constant<int, -1>;
+    using z0 = std::integral_constant<int, 0>;
+    using p1 = std::integral_constant<int, 1>;
+    using p2 = std::integral_constant<int, 2>;
+    if (per || (za >= 3 && za <= n - 4)) {
+        add(T(0.5), m1{});
+        add(T(-0.5), p1{});
+        return;
+    }
+    if (za - 1 >= 0) add((za - 1 == 0) ? T(2) : T(0.5), m1{});
+    if (za + 1 <= n - 1) add((za + 1 == n - 1) ? T(-2) : T(-0.5), p1{});
+    if (za == 0) add(T(-1.5), z0{});
+    if (za == n - 1) add(T(1.5), z0{});
+    if (za - 2 == 0) add(T(-0.5), m2{});
+    if (za + 2 == n - 1) add(T(0.5), p2{});
+}
+
 struct Box {
     int o[3];
     int L[3];
@@ -452,7 +532,8 @@ __global__ __launch_bounds__(512) void k_adjgather2d(Grid g, Bc bc, T A, const T
     __shared__ T mpi[MY][MX], mux[MY][MX], muy[MY][MX], mxx[MY][MX], myy[MY][MX], mxy[MY][MX];
     const long long N = g.N;
     const int nx = g.n[0], ny = g.n[1];
-    const int x0 = blockIdx.x * G2_TX, y0 = blockIdx.y * G2_TY;
+    const uint3 tb = xcd_tile();
+    const int x0 = tb.x * G2_TX, y0 = tb.y * G2_TY;
     const int tid = threadIdx.x + G2_TX * threadIdx.y;
     Box bx;
     if (has_box) {
@@ -528,29 +609,39 @@ __global__ __launch_bounds__(512) void k_adjgather2d(Grid g, Bc bc, T A, const T
 }
 
 // ===================================================================== adjoint, 3D
-// 2.5D blocking as in the forward. For every plane s: the inputs g (p*bar/3, u*bar) of
-// the planes s-1..s+1 with a 3-node (x, y) ring sit in a 3-slot LDS ring; the ten
-// moments (pi, ups, sig) of plane s are formed on a 2-node ring; each thread then forms
-// its node's local and in-plane transpose terms for plane s (kept in registers) and
-// records its column's sig_z* history; plane s-2 is completed with the z-transpose
-// terms and written.
+// 2.5D blocking like the forward kernel. A block of TX x TY threads is the tile of
+// columns whose moments pi, ups, sig it evaluates (one column per thread); it writes the
+// inner (TX-2) x (TY-2) columns. Per plane s: g of plane s+1 (own column and a one-node
+// ring) goes into a three-plane LDS ring, the moments of plane s are formed from the
+// ring, the in-plane transposed-difference terms need sig of the x and y neighbours
+// (LDS), the z term the own column's sig history (registers), so a column's output is
+// complete two planes later.
+//
+// The second-order one-sided difference on a wall node reaches two nodes inward, so the
+// transpose at the node two away from a wall needs sig on the wall node. Tile origins
+// are shifted by `off` (0 or 1 per axis, chosen on the host) so that no tile boundary
+// falls on node 2 or node n-2 of a non-periodic axis; the one-node moment ring then
+// always contains the wall node where it is needed.
 template <typename T> struct A3 {
-    static constexpr int TX = 64, TY = sizeof(T) == 4 ? 8 : 4, NT = TX * TY;
+    static constexpr int TX = 64, TY = 8, NT = TX * TY;
+    static constexpr int OX = TX - 2, OY = TY - 2;
+    static constexpr int WX = TX + 2, WY = TY + 2;
+    static constexpr int RING = 2 * WX + 2 * TY;
 };
 
 template <typename T>
-__global__ __launch_bounds__(A3<T>::NT) void k_adjgather3d(Grid g, Bc bc, T A, int ZC, const T *__restrict__ ab,
-                                                           const T *__restrict__ ustb,
-                                                           const double *__restrict__ Bprev, Design D, int has_box,
-                                                           const T *__restrict__ sprev, T *__restrict__ out) {
-    constexpr int TX = A3<T>::TX, TY = A3<T>::TY, NT = A3<T>::NT;
-    constexpr int GX = TX + 6, GY = TY + 6, MX = TX + 4, MY = TY + 4;
-    __shared__ T gw[3][4][GY][GX];
-    __shared__ T mo[10][MY][MX];  // pi, ux, uy, uz, sxx, syy, szz, sxy, sxz, syz
+__global__ __launch_bounds__(A3<T>::NT, sizeof(T) == 4 ? 4 : 2) void k_adjgather3d(
+    Grid g, Bc bc, T A, int ZC, int offx, int offy, const T *__restrict__ ab, const T *__restrict__ ustb,
+    const double *__restrict__ Bprev, Design D, int has_box, const T *__restrict__ sprev, T *__restrict__ out) {
+    using G = A3<T>;
+    constexpr int TX = G::TX, TY = G::TY, WX = G::WX, WY = G::WY;
+    __shared__ T gr[3][4][WY][WX];  // g = (p*bar / 3, u*bar) of planes s-1, s, s+1
+    __shared__ T sg[5][TY][TX];     // sig_xx, sig_xy, sig_xz, sig_yy, sig_yz of plane s
     const long long N = g.N;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-    const int z0 = blockIdx.z * ZC, z1 = min(z0 + ZC, nz);
+    const uint3 tb = xcd_tile();
+    const int x0 = (int)tb.x * G::OX - offx, y0 = (int)tb.y * G::OY - offy;
+    const int z0 = tb.z * ZC, z1 = min(z0 + ZC, nz);
     const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TX * ty;
     Box bx;
     if (has_box) {
@@ -559,17 +650,32 @@ __global__ __launch_bounds__(A3<T>::NT) void k_adjgather3d(Grid g, Bc bc, T A, i
         bx.L[1] = D.L[1];
         bx.L[2] = D.L[2];
     }
-    auto load_plane = [&](int zp) {
+    // own column (x, y as the output node when inside the output tile)
+    const int ox = x0 - 1 + tx, oy = y0 - 1 + ty;
+    int cx = ox, cy = oy;
+    const bool colok = wrap_coord(cx, nx, g.per[0]) && wrap_coord(cy, ny, g.per[1]);
+    // ring node of the g planes handled by this thread (tid < RING)
+    int rx = 0, ry = 0;
+    if (tid < 2 * WX) {
+        rx = tid % WX;
+        ry = tid < WX ? 0 : WY - 1;
+    } else if (tid < G::RING) {
+        const int k = tid - 2 * WX;
+        ry = 1 + (k >> 1);
+        rx = (k & 1) ? WX - 1 : 0;
+    }
+    int gx = x0 - 2 + rx, gy = y0 - 2 + ry;
+    const bool ringok = tid < G::RING && wrap_coord(gx, nx, g.per[0]) && wrap_coord(gy, ny, g.per[1]);
+
+    // g at (x, y, plane zp): zero off the interior
+    auto g_at = [&](bool ok, int x, int y, int zp, T v[4]) {
         int zw = zp;
-        const bool zok = wrap_coord(zw, nz, g.per[2]);
-        const int slot = ((zp % 3) + 3) % 3;
-        for (int l = tid; l < GX * GY; l += NT) {
-            const int lx = l % GX, ly = l / GX;
-            int xx[3] = {x0 + lx - 3, y0 + ly - 3, zw};
-            T v[4] = {0, 0, 0, 0};
-            if (zok && wrap_coord(xx[0], nx, g.per[0]) && wrap_coord(xx[1], ny, g.per[1]) &&
-                is_interior<3>(g, xx)) {
-                const long long id = node_id(g, xx[0], xx[1], xx[2]);
+        v[0] = v[1] = v[2] = v[3] = T(0);
+        int xx[3] = {x, y, zw};
+        if (ok && wrap_coord(zw, nz, g.per[2])) {
+            xx[2] = zw;
+            if (is_interior<3>(g, xx)) {
+                const long long id = node_id(g, x, y, zw);
                 T pb, ub[3];
                 star_bar<3, T>(g, bc, ab, ustb, bx, has_box, D.boxN, xx, id, pb, ub);
                 v[0] = pb * T(1.0 / 3.0);
@@ -577,14 +683,25 @@ __global__ __launch_bounds__(A3<T>::NT) void k_adjgather3d(Grid g, Bc bc, T A, i
                 v[2] = ub[1];
                 v[3] = ub[2];
             }
-#pragma unroll
-            for (int c = 0; c < 4; c++) gw[slot][c][ly][lx] = v[c];
         }
     };
-    const int x = x0 + tx, y = y0 + ty;
-    const bool col_ok = x < nx && y < ny;
-    T part[3][4];   // local + in-plane terms of planes s-2, s-1, s
-    T hz[5][3];     // sig_xz, sig_yz, sig_zz of planes s-4..s
+    auto put = [&](int zp) {
+        const int sl = ((zp % 3) + 3) % 3;
+        T v[4];
+        g_at(colok, cx, cy, zp, v);
+#pragma unroll
+        for (int c = 0; c < 4; c++) gr[sl][c][ty + 1][tx + 1] = v[c];
+        if (tid < G::RING) {
+            g_at(ringok, gx, gy, zp, v);
+#pragma unroll
+            for (int c = 0; c < 4; c++) gr[sl][c][ry][rx] = v[c];
+        }
+    };
+
+    const bool outcol = tx >= 1 && tx <= G::OX && ty >= 1 && ty <= G::OY && ox >= 0 && ox < nx && oy >= 0 &&
+                        oy < ny;
+    T part[3][4];  // local + in-plane terms of planes s-2, s-1, s
+    T hz[5][3];    // sig_xz, sig_yz, sig_zz of planes s-4 .. s
 #pragma unroll
     for (int j = 0; j < 3; j++)
 #pragma unroll
@@ -592,104 +709,120 @@ __global__ __launch_bounds__(A3<T>::NT) void k_adjgather3d(Grid g, Bc bc, T A, i
 #pragma unroll
     for (int j = 0; j < 5; j++) hz[j][0] = hz[j][1] = hz[j][2] = 0;
     const T A2 = T(2) * A;
-    load_plane(z0 - 3);
-    load_plane(z0 - 2);
+    constexpr T w0 = T(2.0 / 9.0), w1 = T(1.0 / 9.0), w2 = T(1.0 / 72.0);
+
+    put(z0 - 3);
+    put(z0 - 2);
     for (int s = z0 - 2; s <= z1 + 1; s++) {
-        load_plane(s + 1);
+        put(s + 1);
         __syncthreads();
-        const int gm = ((s - 1) % 3 + 3) % 3, g0 = ((s % 3) + 3) % 3, gp = ((s + 1) % 3 + 3) % 3;
-        for (int l = tid; l < MX * MY; l += NT) {
-            const int mx = l % MX, my = l / MX;
-            const int lx = mx + 1, ly = my + 1;  // in the 3-ring arrays
-            T m[10];
-#pragma unroll
-            for (int j = 0; j < 10; j++) m[j] = 0;
-#pragma unroll
-            for (int i = 0; i < 15; i++) {
-                const int cx = Lat<3>::c(i, 0), cy = Lat<3>::c(i, 1), cz = Lat<3>::c(i, 2);
-                const int sl = cz < 0 ? gm : (cz > 0 ? gp : g0);
-                const T gi = gw[sl][0][ly + cy][lx + cx] + T(cx) * gw[sl][1][ly + cy][lx + cx] +
-                             T(cy) * gw[sl][2][ly + cy][lx + cx] + T(cz) * gw[sl][3][ly + cy][lx + cx];
-                const T wg = T(Lat<3>::w(i)) * gi;
-                m[0] += wg;
-                m[1] += T(cx) * wg;
-                m[2] += T(cy) * wg;
-                m[3] += T(cz) * wg;
-                m[4] += T(cx * cx) * wg;
-                m[5] += T(cy * cy) * wg;
-                m[6] += T(cz * cz) * wg;
-                m[7] += T(cx * cy) * wg;
-                m[8] += T(cx * cz) * wg;
-                m[9] += T(cy * cz) * wg;
+        // moments of plane s at the own node: g_i taken at the node + c_i
+        const int sm = ((s - 1) % 3 + 3) % 3, s0 = ((s % 3) + 3) % 3, sp = ((s + 1) % 3 + 3) % 3;
+        const int lx = tx + 1, ly = ty + 1;
+        T pi, up[3], sxx, syy, szz, sxy, sxz, syz;
+        {
+            // rest and axis pairs: s = g(+e) + g(-e), d = g(+e) - g(-e)
+            const T g0 = gr[s0][0][ly][lx];
+            T sa[3], da[3];
+            {
+                const T gp = gr[s0][0][ly][lx + 1] + gr[s0][1][ly][lx + 1];
+                const T gm = gr[s0][0][ly][lx - 1] - gr[s0][1][ly][lx - 1];
+                sa[0] = gp + gm;
+                da[0] = gp - gm;
             }
+            {
+                const T gp = gr[s0][0][ly + 1][lx] + gr[s0][2][ly + 1][lx];
+                const T gm = gr[s0][0][ly - 1][lx] - gr[s0][2][ly - 1][lx];
+                sa[1] = gp + gm;
+                da[1] = gp - gm;
+            }
+            {
+                const T gp = gr[sp][0][ly][lx] + gr[sp][3][ly][lx];
+                const T gm = gr[sm][0][ly][lx] - gr[sm][3][ly][lx];
+                sa[2] = gp + gm;
+                da[2] = gp - gm;
+            }
+            // corner pairs (+,+,+), (+,+,-), (+,-,+), (+,-,-) and their opposites
+            T sc[4], dc[4];
+            constexpr int cyk[4] = {1, 1, -1, -1}, czk[4] = {1, -1, 1, -1};
 #pragma unroll
-            for (int j = 0; j < 10; j++) mo[j][my][mx] = m[j];
+            for (int k = 0; k < 4; k++) {
+                const int ey = cyk[k], ez = czk[k];
+                const int zl = ez > 0 ? sp : sm, zo = ez > 0 ? sm : sp;
+                const T gp = gr[zl][0][ly + ey][lx + 1] + gr[zl][1][ly + ey][lx + 1] +
+                             T(ey) * gr[zl][2][ly + ey][lx + 1] + T(ez) * gr[zl][3][ly + ey][lx + 1];
+                const T gm = gr[zo][0][ly - ey][lx - 1] - gr[zo][1][ly - ey][lx - 1] -
+                             T(ey) * gr[zo][2][ly - ey][lx - 1] - T(ez) * gr[zo][3][ly - ey][lx - 1];
+                sc[k] = gp + gm;
+                dc[k] = gp - gm;
+            }
+            const T scs = (sc[0] + sc[1]) + (sc[2] + sc[3]);
+            pi = w0 * g0 + w1 * (sa[0] + sa[1] + sa[2]) + w2 * scs;
+            up[0] = w1 * da[0] + w2 * ((dc[0] + dc[1]) + (dc[2] + dc[3]));
+            up[1] = w1 * da[1] + w2 * ((dc[0] + dc[1]) - (dc[2] + dc[3]));
+            up[2] = w1 * da[2] + w2 * ((dc[0] - dc[1]) + (dc[2] - dc[3]));
+            sxx = w1 * sa[0] + w2 * scs;
+            syy = w1 * sa[1] + w2 * scs;
+            szz = w1 * sa[2] + w2 * scs;
+            sxy = w2 * ((sc[0] + sc[1]) - (sc[2] + sc[3]));
+            sxz = w2 * ((sc[0] - sc[1]) + (sc[2] - sc[3]));
+            syz = w2 * ((sc[0] - sc[1]) - (sc[2] - sc[3]));
         }
-        __syncthreads();
-        const int mx = tx + 2, my = ty + 2;
-        // history of sig_z* for the z-transpose
+        sg[0][ty][tx] = sxx;
+        sg[1][ty][tx] = sxy;
+        sg[2][ty][tx] = sxz;
+        sg[3][ty][tx] = syy;
+        sg[4][ty][tx] = syz;
 #pragma unroll
         for (int j = 0; j < 4; j++)
 #pragma unroll
             for (int c = 0; c < 3; c++) hz[j][c] = hz[j + 1][c];
-        hz[4][0] = mo[8][my][mx];
-        hz[4][1] = mo[9][my][mx];
-        hz[4][2] = mo[6][my][mx];
+        hz[4][0] = sxz;
+        hz[4][1] = syz;
+        hz[4][2] = szz;
 #pragma unroll
         for (int j = 0; j < 2; j++)
 #pragma unroll
             for (int c = 0; c < 4; c++) part[j][c] = part[j + 1][c];
         part[2][0] = part[2][1] = part[2][2] = part[2][3] = 0;
-        if (col_ok && s >= z0 && s < z1) {
-            const long long id = (long long)x + (long long)nx * ((long long)y + (long long)ny * s);
+        __syncthreads();
+        if (outcol && s >= z0 && s < z1) {
+            const long long id = (long long)ox + (long long)nx * ((long long)oy + (long long)ny * s);
             const T u0 = sprev[N + id], u1 = sprev[2 * N + id], u2 = sprev[3 * N + id];
-            const T pi = mo[0][my][mx];
-            const T sxx = mo[4][my][mx], syy = mo[5][my][mx], szz = mo[6][my][mx];
-            const T sxy = mo[7][my][mx], sxz = mo[8][my][mx], syz = mo[9][my][mx];
-            T o0 = T(3) * mo[1][my][mx] + T(9) * (sxx * u0 + sxy * u1 + sxz * u2) - T(3) * pi * u0;
-            T o1 = T(3) * mo[2][my][mx] + T(9) * (sxy * u0 + syy * u1 + syz * u2) - T(3) * pi * u1;
-            T o2 = T(3) * mo[3][my][mx] + T(9) * (sxz * u0 + syz * u1 + szz * u2) - T(3) * pi * u2;
-            int off[5];
-            T cf[5];
-            int k = dT_stencil<T>(x, nx, g.per[0], off, cf);
-            for (int j = 0; j < k; j++) {  // a = x: sig_xb -> u_b
-                o0 += A2 * cf[j] * mo[4][my][mx + off[j]];
-                o1 += A2 * cf[j] * mo[7][my][mx + off[j]];
-                o2 += A2 * cf[j] * mo[8][my][mx + off[j]];
-            }
-            k = dT_stencil<T>(y, ny, g.per[1], off, cf);
-            for (int j = 0; j < k; j++) {  // a = y: sig_yb -> u_b
-                o0 += A2 * cf[j] * mo[7][my + off[j]][mx];
-                o1 += A2 * cf[j] * mo[5][my + off[j]][mx];
-                o2 += A2 * cf[j] * mo[9][my + off[j]][mx];
-            }
+            T o0 = T(3) * up[0] + T(9) * (sxx * u0 + sxy * u1 + sxz * u2) - T(3) * pi * u0;
+            T o1 = T(3) * up[1] + T(9) * (sxy * u0 + syy * u1 + syz * u2) - T(3) * pi * u1;
+            T o2 = T(3) * up[2] + T(9) * (sxz * u0 + syz * u1 + szz * u2) - T(3) * pi * u2;
+            T o[3] = {o0, o1, o2};
+            dT_apply3<T>(ox, nx, g.per[0], A2, [&](int d, T v[3]) {  // a = x: sig_xb -> u_b
+                const int xi = min(max(tx + d, 0), TX - 1);
+                v[0] = sg[0][ty][xi];
+                v[1] = sg[1][ty][xi];
+                v[2] = sg[2][ty][xi];
+            }, o);
+            dT_apply3<T>(oy, ny, g.per[1], A2, [&](int d, T v[3]) {  // a = y: sig_yb -> u_b
+                const int yi = min(max(ty + d, 0), TY - 1);
+                v[0] = sg[1][yi][tx];
+                v[1] = sg[3][yi][tx];
+                v[2] = sg[4][yi][tx];
+            }, o);
+            o0 = o[0];
+            o1 = o[1];
+            o2 = o[2];
             part[2][0] = T(3) * pi;
             part[2][1] = o0;
             part[2][2] = o1;
             part[2][3] = o2;
         }
-        __syncthreads();
         const int zo = s - 2;
-        if (col_ok && zo >= z0 && zo < z1) {
-            int off[5];
-            T cf[5];
-            const int k = dT_stencil<T>(zo, nz, g.per[2], off, cf);
+        if (outcol && zo >= z0 && zo < z1) {
             T o[3] = {part[0][1], part[0][2], part[0][3]};
-            for (int j = 0; j < k; j++) {  // a = z: sig_zb -> u_b, history index off + 2
-                const int h = off[j] + 2;
-                T hx = hz[0][0], hy = hz[0][1], hzz = hz[0][2];
-#pragma unroll
-                for (int q = 1; q < 5; q++)
-                    if (q == h) {
-                        hx = hz[q][0];
-                        hy = hz[q][1];
-                        hzz = hz[q][2];
-                    }
-                o[0] += A2 * cf[j] * hx;
-                o[1] += A2 * cf[j] * hy;
-                o[2] += A2 * cf[j] * hzz;
-            }
-            const long long id = (long long)x + (long long)nx * ((long long)y + (long long)ny * zo);
+            // a = z: sig_zb -> u_b from the history (plane zo + d is entry d + 2)
+            dT_apply3<T>(zo, nz, g.per[2], A2, [&](int d, T v[3]) {
+                v[0] = hz[d + 2][0];
+                v[1] = hz[d + 2][1];
+                v[2] = hz[d + 2][2];
+            }, o);
+            const long long id = (long long)ox + (long long)nx * ((long long)oy + (long long)ny * zo);
             out[id] = part[0][0];
             out[N + id] = o[0];
             out[2 * N + id] = o[1];

@@ -9,6 +9,7 @@
 // Adjoint memory: checkpoints every ckpt_every steps (state + body record); the reverse
 // sweep recomputes one segment into the workspace (states, the u* footprint of every
 // step and every fluid <-> body iterate), then walks it backwards.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -51,8 +52,8 @@ inline size_t up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 inline unsigned blocks(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 // ------------------------------------------------------------------ live kernel timing
-// Sampled HIP event pairs around launches (LKS_FLAG_PROFILE); durations are read after
-// the call's final synchronisation and added to process-wide totals.
+// Kernel begin/end timestamps on sampled steps (LKS_FLAG_PROFILE); durations are read
+// after the call's final synchronisation and added to process-wide totals.
 std::vector<hipEvent_t> g_events;
 double g_prof_ms[LKS_K_COUNT];
 long long g_prof_n[LKS_K_COUNT];
@@ -63,23 +64,24 @@ struct Prof {
     hipStream_t st = nullptr;
     std::vector<int> ids;
 
+    // `launch(start, stop)` passes the events to hipExtLaunchKernelGGL, which stamps them
+    // with the kernel's own begin and end times (no marker packets in between), so the
+    // sampled durations are the kernels' execution times; null events record nothing.
     template <typename F> void run(int id, F &&launch) {
         if (!on || !sample) {
-            launch();
+            launch(nullptr, nullptr);
             return;
         }
         const size_t i = ids.size();
         while (g_events.size() < 2 * (i + 1)) {
             hipEvent_t e;
             if (hipEventCreate(&e) != hipSuccess) {
-                launch();
+                launch(nullptr, nullptr);
                 return;
             }
             g_events.push_back(e);
         }
-        (void)hipEventRecord(g_events[2 * i], st);
-        launch();
-        (void)hipEventRecord(g_events[2 * i + 1], st);
+        launch(g_events[2 * i], g_events[2 * i + 1]);
         ids.push_back(id);
     }
     void finish() {
@@ -318,6 +320,18 @@ template <typename F> void dispatch(const Ctx &c, F &&f) {
     }
 }
 
+// Blocks of `kernel` that the device holds at once (occupancy x compute units); 512 if
+// the runtime cannot say.
+template <typename K> long long resident_blocks(K kernel, int threads) {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu < 1 ||
+        cus < 1)
+        return 512;
+    return (long long)per_cu * cus;
+}
+
 template <typename T> struct Run {
     const Ctx &c;
     hipStream_t st;
@@ -328,37 +342,44 @@ template <typename T> struct Run {
     // blocks and a one-block finish kernel is cheaper.
     bool last_block_ok() const { return c.nblk <= 256; }
 
-    // z planes per block of the 2.5D 3D kernels: enough blocks to fill the chip
-    // (about 512), between 4 and 32 planes.
-    template <typename U> int zchunk(int ty) const {
-        const long long bxy = (long long)blocks(c.g.n[0], 64) * blocks(c.g.n[1], ty);
-        long long zc = (long long)c.g.n[2] * bxy / 512;
-        zc = zc < 8 ? 8 : (zc > 32 ? 32 : zc);
-        return (int)zc;
+    // z planes per block of the 2.5D 3D kernels. A block costs about (planes + 2) plane
+    // steps (two planes of lead-in), and `resident` blocks run at once (occupancy x
+    // CUs); pick the chunk (4..32 planes) that minimises rounds x (planes + 2).
+    int zchunk(int ox, int oy, long long resident) const {
+        const long long bxy = (long long)blocks(c.g.n[0], ox) * blocks(c.g.n[1], oy);
+        int best = 32;
+        long long best_cost = -1;
+        for (int zc = 32; zc >= 4; zc--) {
+            const long long nb = bxy * blocks(c.g.n[2], zc);
+            const long long cost = (nb + resident - 1) / resident * (zc + 2);
+            if (best_cost < 0 || cost < best_cost) best = zc, best_cost = cost;
+        }
+        return best;
     }
 
     void gather(const T *in, T *out) const {
         if (c.dim == 2) {
             dim3 grid(blocks(c.g.n[0], G2_TX), blocks(c.g.n[1], G2_TY));
-            pf->run(LKS_K_GATHER, [&] {
-                hipLaunchKernelGGL(k_gather2d<T>, grid, dim3(G2_TX, G2_TY), 0, st, c.g, T(c.A), in, out);
+            pf->run(LKS_K_GATHER, [&](hipEvent_t e0, hipEvent_t e1) {
+                hipExtLaunchKernelGGL(k_gather2d<T>, grid, dim3(G2_TX, G2_TY), 0, st, e0, e1, 0, c.g, T(c.A), in, out);
             });
         } else {
-            const int zc = zchunk<T>(G3<T>::TY);
-            const dim3 grid(blocks(c.g.n[0], G3<T>::TX), blocks(c.g.n[1], G3<T>::TY), blocks(c.g.n[2], zc));
-            pf->run(LKS_K_GATHER, [&] {
-                hipLaunchKernelGGL(k_gather3d<T>, grid, dim3(G3<T>::TX, G3<T>::TY), 0, st, c.g, T(c.A), zc, in, out);
+            static const long long res = resident_blocks(k_gather3d<T>, G3<T>::NT);
+            const int zc = zchunk(G3<T>::OX, G3<T>::OY, res);
+            const dim3 grid(blocks(c.g.n[0], G3<T>::OX), blocks(c.g.n[1], G3<T>::OY), blocks(c.g.n[2], zc));
+            pf->run(LKS_K_GATHER, [&](hipEvent_t e0, hipEvent_t e1) {
+                hipExtLaunchKernelGGL(k_gather3d<T>, grid, dim3(G3<T>::TX, G3<T>::TY), 0, st, e0, e1, 0, c.g, T(c.A), zc, in, out);
             });
         }
     }
     void bcs(T *s) const {
         if (!c.face_total) return;
-        pf->run(LKS_K_BC, [&] {
+        pf->run(LKS_K_BC, [&](hipEvent_t e0, hipEvent_t e1) {
             if (c.dim == 2)
-                hipLaunchKernelGGL((k_bc<2, T>), dim3(blocks(c.face_total, 256)), dim3(256), 0, st, c.g, c.bc, s,
+                hipExtLaunchKernelGGL((k_bc<2, T>), dim3(blocks(c.face_total, 256)), dim3(256), 0, st, e0, e1, 0, c.g, c.bc, s,
                                    c.face_axes, c.face_total);
             else
-                hipLaunchKernelGGL((k_bc<3, T>), dim3(blocks(c.face_total, 256)), dim3(256), 0, st, c.g, c.bc, s,
+                hipExtLaunchKernelGGL((k_bc<3, T>), dim3(blocks(c.face_total, 256)), dim3(256), 0, st, e0, e1, 0, c.g, c.bc, s,
                                    c.face_axes, c.face_total);
         });
     }
@@ -370,15 +391,16 @@ template <typename T> struct Run {
             constexpr int DIM = decltype(dm)::value;
             constexpr bool ROT = decltype(rt)::value;
             for (int k = 0; k < c.K; k++) {
-                pf->run(LKS_K_SPREAD, [&] {
-                    hipLaunchKernelGGL((k_spread_fwd<DIM, T, ROT, lpn<DIM>()>), dim3(blocks(c.D.boxN * lpn<DIM>(), 256)),
-                                       dim3(256), 0, st, c.g, c.D, Bk, k, krT, u, ustar);
+                pf->run(LKS_K_SPREAD, [&](hipEvent_t e0, hipEvent_t e1) {
+                    hipExtLaunchKernelGGL((k_spread_fwd<DIM, T, ROT, lpn<DIM>()>), dim3(blocks(c.D.boxN * lpn<DIM>(), 256)),
+                                       dim3(256), 0, st, e0, e1, 0, c.g, c.D, Bk, k, krT, u, ustar);
                 });
-                pf->run(LKS_K_INTERP, [&] {
-                    hipLaunchKernelGGL((k_interp_force<DIM, T>), dim3(c.nblk), dim3(DBLK), 0, st, c.g, c.D, c.bp, u,
+                pf->run(LKS_K_INTERP, [&](hipEvent_t e0, hipEvent_t e1) {
+                    hipExtLaunchKernelGGL((k_interp_force<DIM, T>), dim3(c.nblk), dim3(DBLK), 0, st, e0,
+                                          last_block_ok() ? e1 : nullptr, 0, c.g, c.D, c.bp, u,
                                        krD, Bk, k, c.K, Bnext0, part, counter, flag, last_block_ok() ? 1 : 0);
                     if (!last_block_ok())
-                        hipLaunchKernelGGL((k_interp_finish<DIM>), dim3(1), dim3(256), 0, st, c.D, c.bp, Bk, k, c.K,
+                        hipExtLaunchKernelGGL((k_interp_finish<DIM>), dim3(1), dim3(256), 0, st, nullptr, e1, 0, c.D, c.bp, Bk, k, c.K,
                                            Bnext0, part, c.nblk, flag);
                 });
             }
@@ -396,41 +418,48 @@ template <typename T> struct Run {
         dispatch(c, [&](auto dm, auto rt) {
             constexpr int DIM = decltype(dm)::value;
             constexpr bool ROT = decltype(rt)::value;
-            pf->run(LKS_K_ADJ_RECOMPUTE, [&] {
-                hipLaunchKernelGGL((k_adj_recompute<DIM, T, ROT, lpn<DIM>()>), gb, dim3(256), 0, st, c.g, c.D, Bk,
+            pf->run(LKS_K_ADJ_RECOMPUTE, [&](hipEvent_t e0, hipEvent_t e1) {
+                hipExtLaunchKernelGGL((k_adj_recompute<DIM, T, ROT, lpn<DIM>()>), gb, dim3(256), 0, st, e0, e1, 0, c.g, c.D, Bk,
                                    krT, ustar, kapk, usk, uk, ustb);
             });
             for (int k = c.K - 1; k >= 0; k--) {
-                pf->run(LKS_K_ADJ_R1, [&] {
-                    hipLaunchKernelGGL((k_adj_r1<DIM, T>), dim3(c.nblk), dim3(DBLK), 0, st, c.g, c.D, Bk, k, uk, krD,
+                pf->run(LKS_K_ADJ_R1, [&](hipEvent_t e0, hipEvent_t e1) {
+                    hipExtLaunchKernelGGL((k_adj_r1<DIM, T>), dim3(c.nblk), dim3(DBLK), 0, st, e0, e1, 0, c.g, c.D, Bk, k, uk, krD,
                                        rec, URb, krb, p1);
                 });
-                pf->run(LKS_K_ADJ_R2, [&] {
-                    hipLaunchKernelGGL((k_adj_r2<DIM, T, ROT, lpn<DIM>()>), dim3(blocks(c.D.boxN * lpn<DIM>(), 256)),
-                                       dim3(256), 0, st, c.g, c.bc, c.D, Bk, k, c.K, ab, URb, kapk, usk, uk, ustb, kb,
+                pf->run(LKS_K_ADJ_R2, [&](hipEvent_t e0, hipEvent_t e1) {
+                    hipExtLaunchKernelGGL((k_adj_r2<DIM, T, ROT, lpn<DIM>()>), dim3(blocks(c.D.boxN * lpn<DIM>(), 256)),
+                                       dim3(256), 0, st, e0, e1, 0, c.g, c.bc, c.D, Bk, k, c.K, ab, URb, kapk, usk, uk, ustb, kb,
                                        usb);
                 });
-                pf->run(LKS_K_ADJ_R3, [&] {
-                    hipLaunchKernelGGL((k_adj_r3<DIM, T>), dim3(c.nblk), dim3(DBLK), 0, st, c.g, c.D, c.bp, Bk, k,
+                pf->run(LKS_K_ADJ_R3, [&](hipEvent_t e0, hipEvent_t e1) {
+                    hipExtLaunchKernelGGL((k_adj_r3<DIM, T>), dim3(c.nblk), dim3(DBLK), 0, st, e0,
+                                          last_block_ok() ? e1 : nullptr, 0, c.g, c.D, c.bp, Bk, k,
                                        kb, usb, krD, krb, p1, p3, counter, rec, last_block_ok() ? 1 : 0);
                     if (!last_block_ok())
-                        hipLaunchKernelGGL((k_r3_finish<DIM>), dim3(1), dim3(256), 0, st, c.bp, k, p1, p3, c.nblk, rec);
+                        hipExtLaunchKernelGGL((k_r3_finish<DIM>), dim3(1), dim3(256), 0, st, nullptr, e1, 0, c.bp, k, p1, p3, c.nblk, rec);
                 });
             }
         });
     }
     void adj_gather(const T *ab, const T *ustb, const double *Bprev, const T *sprev, T *out) const {
         const int hb = c.has_body ? 1 : 0;
-        pf->run(LKS_K_ADJ_GATHER, [&] {
+        pf->run(LKS_K_ADJ_GATHER, [&](hipEvent_t e0, hipEvent_t e1) {
             if (c.dim == 2) {
                 dim3 grid(blocks(c.g.n[0], G2_TX), blocks(c.g.n[1], G2_TY));
-                hipLaunchKernelGGL(k_adjgather2d<T>, grid, dim3(G2_TX, G2_TY), 0, st, c.g, c.bc, T(c.A), ab, ustb,
+                hipExtLaunchKernelGGL(k_adjgather2d<T>, grid, dim3(G2_TX, G2_TY), 0, st, e0, e1, 0, c.g, c.bc, T(c.A), ab, ustb,
                                    Bprev, c.D, hb, sprev, out);
             } else {
-                const int zc = zchunk<T>(A3<T>::TY);
-                const dim3 grid(blocks(c.g.n[0], A3<T>::TX), blocks(c.g.n[1], A3<T>::TY), blocks(c.g.n[2], zc));
-                hipLaunchKernelGGL(k_adjgather3d<T>, grid, dim3(A3<T>::TX, A3<T>::TY), 0, st, c.g, c.bc, T(c.A), zc,
-                                   ab, ustb, Bprev, c.D, hb, sprev, out);
+                static const long long res = resident_blocks(k_adjgather3d<T>, A3<T>::NT);
+                // shift the tiles of a non-periodic axis by one node where a tile
+                // boundary would fall on node n-2 (see k_adjgather3d)
+                const int offx = !c.g.per[0] && (c.g.n[0] - 2) % A3<T>::OX == 0 ? 1 : 0;
+                const int offy = !c.g.per[1] && (c.g.n[1] - 2) % A3<T>::OY == 0 ? 1 : 0;
+                const int zc = zchunk(A3<T>::OX, A3<T>::OY, res);
+                const dim3 grid(blocks(c.g.n[0] + offx, A3<T>::OX), blocks(c.g.n[1] + offy, A3<T>::OY),
+                                blocks(c.g.n[2], zc));
+                hipExtLaunchKernelGGL(k_adjgather3d<T>, grid, dim3(A3<T>::TX, A3<T>::TY), 0, st, e0, e1, 0, c.g, c.bc,
+                                      T(c.A), zc, offx, offy, ab, ustb, Bprev, c.D, hb, sprev, out);
             }
         });
     }

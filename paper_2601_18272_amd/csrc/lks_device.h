@@ -68,6 +68,18 @@ __device__ __forceinline__ bool wrap_coord(int &v, int n, int per) {
     return v >= 0 && v < n;
 }
 
+// Workgroups are handed out round-robin over the eight XCDs (workgroup b, counted x
+// fastest, runs on XCD b mod 8), and each XCD has its own L2. Renumber the tiles so
+// that XCD j gets the j-th contiguous run of them (x fastest): neighbouring tiles then
+// share their halo lines in one L2 instead of fetching them twice.
+__device__ __forceinline__ uint3 xcd_tile() {
+    const unsigned gx = gridDim.x, gy = gridDim.y, nb = gx * gy * gridDim.z;
+    const unsigned b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const unsigned per = nb >> 3, rem = nb & 7, x = b & 7;
+    const unsigned t = x * per + min(x, rem) + (b >> 3);
+    return make_uint3(t % gx, (t / gx) % gy, t / (gx * gy));
+}
+
 template <int DIM>
 __device__ __forceinline__ bool is_interior(const Grid &g, const int x[3]) {
 #pragma unroll
