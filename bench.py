@@ -84,7 +84,7 @@ def launches_per_gradient(pb):
     NT, K = pb.n_steps, pb.n_itr
     return {"gather": 2 * NT, "bc": 2 * NT, "spread": 2 * K * NT, "interp": 2 * K * NT,
             "adj_gather": NT, "adj_recompute": NT, "adj_r1": K * NT, "adj_r2": K * NT,
-            "adj_r3": K * NT}
+            "adj_r3": K * NT, "iter": 2 * K * NT, "iter_final": 2 * NT}
 
 
 def run_cpu_baseline(pb, sample_steps):

@@ -173,7 +173,9 @@ enum {
     LKS_K_ADJ_R1 = 6,
     LKS_K_ADJ_R2 = 7,
     LKS_K_ADJ_R3 = 8,
-    LKS_K_COUNT = 9
+    LKS_K_ITER = 9,        /* 2D: one fused iteration (partials -> B^(k), tile spread, interp) */
+    LKS_K_ITER_FINAL = 10, /* 2D: B^(K) and the step's spread into the state */
+    LKS_K_COUNT = 11
 };
 int lks_profile_read(int kernel, double *total_ms, long long *samples);
 void lks_profile_reset(void);

@@ -176,7 +176,7 @@ __device__ __forceinline__ void gather_design(const Design &D, const double *B, 
             idx[D.pi] = ii;
             idx[D.pj] = jj;
             const long long m = idx[0] + (long long)D.nd[0] * (idx[1] + (long long)D.nd[1] * idx[2]);
-            f(m, W, r);
+            f(m, W, r, idx);
         }
     }
 }
@@ -210,13 +210,14 @@ __device__ __forceinline__ bool box_node(const Grid &g, const Design &D, const i
 
 // kappa(x) and u^S(x) at node x: sum W kappa_ref, and u^G phi + omega a x (sum W (x^ref - x^G))
 // with phi = sum W and sum W (x^ref - x^G) = phi d - sum W r formed in FP64.
-template <int DIM, typename T, bool ROT, int LPN = 1>
-__device__ __forceinline__ void spread_node(const Design &D, const double *B, const T *__restrict__ krT,
-                                            const int x[3], int q, T &kap, T us[3]) {
+// kr(m, idx) returns kappa^ref of design point m (design index idx).
+template <int DIM, typename T, bool ROT, int LPN = 1, typename KR>
+__device__ __forceinline__ void spread_node_kr(const Design &D, const double *B, KR &&kr, const int x[3], int q,
+                                               T &kap, T us[3]) {
     double d[3];
     T k = 0, phi = 0, wr[3] = {0, 0, 0};
-    gather_design<DIM, T, ROT, LPN>(D, B, x, d, q, [&](long long m, T W, const T r[3]) {
-        k += W * krT[m];
+    gather_design<DIM, T, ROT, LPN>(D, B, x, d, q, [&](long long m, T W, const T r[3], const int *idx) {
+        k += W * kr(m, idx);
         phi += W;
 #pragma unroll
         for (int a = 0; a < DIM; a++) wr[a] += W * r[a];
@@ -236,6 +237,12 @@ __device__ __forceinline__ void spread_node(const Design &D, const double *B, co
     kap = k;
 #pragma unroll
     for (int a = 0; a < 3; a++) us[a] = a < DIM ? T(B[B_UG + a] * (double)phi + om * axa[a]) : T(0);
+}
+
+template <int DIM, typename T, bool ROT, int LPN = 1>
+__device__ __forceinline__ void spread_node(const Design &D, const double *B, const T *__restrict__ krT,
+                                            const int x[3], int q, T &kap, T us[3]) {
+    spread_node_kr<DIM, T, ROT, LPN>(D, B, [&](long long m, const int *) { return krT[m]; }, x, q, kap, us);
 }
 
 // ------------------------------------------------------------------ forward spread
@@ -372,29 +379,52 @@ __device__ __forceinline__ bool last_block(unsigned *counter) {
     return is_last;
 }
 
-// Fixed-order sum of nb partial vectors of NV doubles (and optionally a second set),
-// by the first wave of the last block: lane l sums blocks l, l+64, ... (Neumaier),
-// then a fixed xor-tree. Result in out[NV] (shared memory), valid after the barrier.
-template <int NV>
+// Fixed-order, compensated sum of nb partial vectors of NV doubles (plus a second set
+// p2 when given) by all NTHR threads of a block: thread t adds (Neumaier) the vectors
+// t, t + NTHR, t + 2 NTHR, ... with two vectors' loads in flight, then the threads'
+// sums meet in a fixed xor tree per wave and a fixed-order sum over the waves. The
+// same inputs give the same bits in every block. Result in out[NV] (shared memory),
+// valid after the call (it ends with a barrier).
+template <int NV, int NTHR>
 __device__ __forceinline__ void reduce_partials(const double *__restrict__ p1, const double *__restrict__ p2,
                                                 unsigned nb, double *out) {
-    if (threadIdx.x < 64) {
+    constexpr int NW = NTHR / 64;
+    __shared__ double red[NV][NW];
+    Kahan s[NV];
+    for (unsigned b0 = threadIdx.x; b0 < nb; b0 += 2 * NTHR) {
+        double v[2][NV];
 #pragma unroll
-        for (int j = 0; j < NV; j++) {
-            Kahan s;
-            for (unsigned b = threadIdx.x; b < nb; b += 64) {
-                s.add(p1[(long long)b * NV + j]);
-                if (p2) s.add(p2[(long long)b * NV + j]);
+        for (int u = 0; u < 2; u++) {
+            const unsigned b = b0 + u * NTHR;
+#pragma unroll
+            for (int j = 0; j < NV; j++) {
+                v[u][j] = b < nb ? p1[(long long)b * NV + j] : 0.0;
+                if (p2) v[u][j] += b < nb ? p2[(long long)b * NV + j] : 0.0;
             }
-            const double v = wave_sum(s.value());
-            if (threadIdx.x == 0) out[j] = v;
         }
+#pragma unroll
+        for (int u = 0; u < 2; u++)
+#pragma unroll
+            for (int j = 0; j < NV; j++) s[j].add(v[u][j]);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NV; j++) {
+        const double w = wave_sum(s[j].value());
+        if (lane == 0) red[j][wid] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; w++) t += red[threadIdx.x][w];
+        out[threadIdx.x] = t;
     }
     __syncthreads();
 }
 
 // ------------------------------------------------------------------ forward interp
-template <int DIM>
+template <int DIM, int NTHR>
 __device__ __forceinline__ void interp_finish(const Design &D, const BodyParams &bp, double *Bk, int k, int K,
                                               double *Bnext0, const double *part, unsigned nb, int *flag);
 
@@ -449,17 +479,17 @@ __global__ __launch_bounds__(DBLK) void k_interp_force(Grid g, Design D, BodyPar
     block_reduce_store<4>(v, part);
     if (!last) return;
     if (!last_block(counter)) return;
-    interp_finish<DIM>(D, bp, Bk, k, K, Bnext0, part, gridDim.x, flag);
+    interp_finish<DIM, DBLK>(D, bp, Bk, k, K, Bnext0, part, gridDim.x, flag);
     if (threadIdx.x == 0) *counter = 0u;
 }
 
 // Fixed-order sum of the force/torque partials and the Euler update of Sec. 2.4:
 // B^(k+1) from B(t-1) (plus, after the last iteration, the next step's first record).
-template <int DIM>
+template <int DIM, int NTHR>
 __device__ __forceinline__ void interp_finish(const Design &D, const BodyParams &bp, double *Bk, int k, int K,
                                               double *Bnext0, const double *part, unsigned nb, int *flag) {
     __shared__ double FT[4];
-    reduce_partials<4>(part, nullptr, nb, FT);
+    reduce_partials<4, NTHR>(part, nullptr, nb, FT);
     if (threadIdx.x == 0) {
         double ft[4] = {FT[0], FT[1], FT[2], FT[3]};
         double *Bn = Bk + (k + 1) * B_REC;
@@ -479,11 +509,258 @@ __device__ __forceinline__ void interp_finish(const Design &D, const BodyParams 
 // One block: the same finish for grids too large for the last-block pattern (one
 // arrival counter shared by thousands of blocks serialises them).
 template <int DIM>
-__global__ __launch_bounds__(256) void k_interp_finish(Design D, BodyParams bp, double *__restrict__ Bk, int k,
+__global__ __launch_bounds__(1024) void k_interp_finish(Design D, BodyParams bp, double *__restrict__ Bk, int k,
                                                        int K, double *__restrict__ Bnext0,
                                                        const double *__restrict__ part, unsigned nb,
                                                        int *__restrict__ flag) {
-    interp_finish<DIM>(D, bp, Bk, k, K, Bnext0, part, nb, flag);
+    interp_finish<DIM, 1024>(D, bp, Bk, k, K, Bnext0, part, nb, flag);
+}
+
+// ------------------------------------------------------------------ fused 2D iteration
+// One kernel per fluid <-> body iteration in 2D. Every block first sums the
+// force/torque partials of iteration k-1 in a fixed order (the same bits in every
+// block) and applies the Euler update, so B^(k) needs no grid-wide fence; block 0
+// keeps the record. Each block then owns a TT x TT tile of design points: it forms
+// kappa, u^S and the Brinkman-corrected velocity on the patch of nodes touched by the
+// tile's interpolation stencils (in LDS; the spread is evaluated again where patches
+// overlap), interpolates at its points and stores its force/torque partial. The state
+// is left untouched (it holds u* throughout); the step's last spread writes it.
+template <int TT> struct It2 {
+    static constexpr int NT = 1024;
+    static constexpr int HE = TT + 12;  // design halo edge: spread candidates of patch nodes
+    // patch edge: the floors of TT points along a rotated lattice line span at most
+    // ceil((TT - 1) sqrt 2) + 1 nodes, the stencil adds 3
+    static constexpr int PE = TT == 8 ? 14 : 26;
+    static constexpr int NW = (TT * TT + 63) / 64;  // waves holding design points
+};
+
+// B^(k) (k >= 1) into shared memory from B(t-1) and the partials of iteration k-1.
+template <int DIM, int NTHR>
+__device__ __forceinline__ void body_from_partials(const BodyParams &bp, const double *B0, const double *part,
+                                                   unsigned nb, double *Bs, double *FT) {
+    reduce_partials<4, NTHR>(part, nullptr, nb, FT);
+    if (threadIdx.x == 0) body_update<DIM>(bp, B0, FT, Bs);
+    __syncthreads();
+}
+
+template <typename T, bool ROT, int TT>
+__global__ __launch_bounds__(It2<TT>::NT) void k_iter2d(Grid g, Design D, BodyParams bp, double *__restrict__ Bk,
+                                                         int k, const T *__restrict__ krT,
+                                                         const double *__restrict__ krD, const T *__restrict__ u,
+                                                         const double *__restrict__ part_in, unsigned nb,
+                                                         double *__restrict__ part_out, int *__restrict__ flag) {
+    constexpr int NT = It2<TT>::NT, PE = It2<TT>::PE, NW = It2<TT>::NW, HE = It2<TT>::HE;
+    __shared__ double B0s[B_REC];
+    __shared__ double FT[4];
+    __shared__ double red[4][NW];
+    __shared__ T up[2][PE][PE];
+    __shared__ T kh[HE * HE];
+    const int tid = threadIdx.x;
+    // everything that does not depend on B^(k) is requested first: B(t-1), the point's
+    // kappa^ref, the kappa^ref halo; then the partials
+    if (tid < B_REC) B0s[tid] = Bk[tid];
+    const int tilesX = (D.nd[0] + TT - 1) / TT;
+    const int ti = (int)blockIdx.x % tilesX, tj = (int)blockIdx.x / tilesX;
+    const int mi = ti * TT + tid % TT, mj = tj * TT + tid / TT;
+    const bool own = tid < TT * TT && mi < D.nd[0] && mj < D.nd[1];
+    const long long m = own ? mi + (long long)D.nd[0] * mj : 0;
+    const double kr = own ? krD[m] : 0.0;
+    // kappa^ref of the tile and a six-point halo, loaded while the partials are summed.
+    // A patch node x lies within 2 grid spacings (per axis) of a tile point p, so its
+    // body-frame position is within 2 sqrt 2 of xi_p, its window base within 3 of xi_p
+    // and its gather-form candidates (base - 2 .. base + 3) within 5 of xi_p.
+    const int hi0 = ti * TT - 6, hj0 = tj * TT - 6;
+    for (int l = tid; l < HE * HE; l += NT) {
+        const int i = hi0 + l % HE, j = hj0 + l / HE;
+        kh[l] = (i >= 0 && i < D.nd[0] && j >= 0 && j < D.nd[1]) ? krT[i + (long long)D.nd[0] * j] : T(0);
+    }
+    // B^(k) in every thread's registers: B(t-1) at k = 0, else the Euler update with the
+    // fixed-order sum of iteration k-1's partials (reduce_partials ends with a barrier,
+    // which also publishes B0s)
+    double Bs[B_REC];
+    if (k == 0) {
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < B_REC; j++) Bs[j] = B0s[j];
+    } else {
+        reduce_partials<4, NT>(part_in, nullptr, nb, FT);
+        const double ft[4] = {FT[0], FT[1], FT[2], FT[3]};
+        double B0[B_REC];
+#pragma unroll
+        for (int j = 0; j < B_REC; j++) B0[j] = B0s[j];
+        body_update<2>(bp, B0, ft, Bs);
+        if (blockIdx.x == 0 && tid == 0) {
+            bool bad = false;
+            for (int j = 0; j < B_REC; j++) Bk[k * B_REC + j] = Bs[j];
+            for (int j = 0; j < 8; j++) bad = bad || !isfinite(Bs[j]);
+            if (bad) atomicOr(flag, 1);
+            for (int a = 0; a < 2; a++)
+                if (!(fabs(Bs[B_XG + a] - B0[B_XG + a]) <= (double)D.margin)) atomicOr(flag, 2);
+        }
+    }
+    // this thread's design point and its interpolation stencil
+    // Patch: the nodes of the tile points' stencils, floor(X) - 1 .. floor(X) + 2 per
+    // axis (clamped to the grid like the taps). pose_point rounds c xi_p, s xi_q, their
+    // difference and the sum with x^G, each monotone in its operands, so the computed X
+    // is monotone in each design index and its floors are extreme at the tile's corners
+    // (exactly, not only up to rounding); every thread forms the four corners.
+    int lo[2] = {0x7fffffff, 0x7fffffff}, hi[2] = {-0x7fffffff, -0x7fffffff};
+    {
+        const int i0 = ti * TT, i1 = min(i0 + TT, D.nd[0]) - 1;
+        const int j0 = tj * TT, j1 = min(j0 + TT, D.nd[1]) - 1;
+#pragma unroll
+        for (int cc = 0; cc < 4; cc++) {
+            const long long mc = ((cc & 1) ? i1 : i0) + (long long)D.nd[0] * ((cc & 2) ? j1 : j0);
+            double xi[3];
+            design_xi<2>(D, mc, xi);
+            Pose Pc;
+            pose_point(D, Bs, xi, Pc);
+#pragma unroll
+            for (int a = 0; a < 2; a++) {
+                const int f = (int)fmax(fmin(floor(Pc.X[a]), 1.0e9), -1.0e9);
+                lo[a] = min(lo[a], f - 1);
+                hi[a] = max(hi[a], f + 2);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 2; a++) {
+            lo[a] = min(max(lo[a], 0), g.n[a] - 1);
+            hi[a] = min(max(hi[a], 0), g.n[a] - 1);
+        }
+    }
+    const int ox = lo[0], oy = lo[1], sx = hi[0] - lo[0] + 1, sy = hi[1] - lo[1] + 1;
+    if (sx > PE || sy > PE) {  // excluded by the bound on PE; keeps LDS accesses in range
+        if (tid == 0) atomicOr(flag, 4);
+        return;
+    }
+    // own point's pose and stencil (used after the patch)
+    Pose P;
+    Taps<2, T> tp;
+    if (own) {
+        double xi[3];
+        design_xi<2>(D, m, xi);
+        pose_point(D, Bs, xi, P);
+        tp.init(g, P.X, false);
+    }
+    // patch: kappa, u^S at pose B^(k), Brinkman correction of u* (LPN lanes per node)
+    int bo[3];
+    box_origin<2>(D, B0s, bo);
+    const long long N = g.N;
+    constexpr int LPN = 4;
+    for (int task = tid; task < PE * PE * LPN; task += NT) {
+        const int node = task / LPN, q = task % LPN;
+        const int px = node % PE, py = node / PE;
+        const int x[3] = {ox + px, oy + py, 0};
+        const bool in = px < sx && py < sy && x[0] >= 0 && x[0] < g.n[0] && x[1] >= 0 && x[1] < g.n[1] &&
+                        is_interior<2>(g, x);
+        T v0 = 0, v1 = 0;
+        if (in) {
+            const long long id = x[0] + (long long)g.n[0] * x[1];
+            v0 = u[id];
+            v1 = u[N + id];
+            const int lx = x[0] - bo[0], ly = x[1] - bo[1];
+            if (lx >= 0 && lx < D.L[0] && ly >= 0 && ly < D.L[1]) {
+                T kap, us[3];
+                spread_node_kr<2, T, ROT, LPN>(
+                    D, Bs,
+                    [&](long long, const int *idx) {
+                        // always inside the halo (see kh); the clamp only keeps the read in range
+                        const int li = min(max(idx[0] - hi0, 0), HE - 1), lj = min(max(idx[1] - hj0, 0), HE - 1);
+                        return kh[lj * HE + li];
+                    },
+                    x, q, kap, us);
+                const T inv = T(1) / (T(1) + kap);
+                v0 = (v0 + kap * us[0]) * inv;
+                v1 = (v1 + kap * us[1]) * inv;
+            }
+        }
+        if (q == 0 && px < sx && py < sy) {
+            up[0][py][px] = v0;
+            up[1][py][px] = v1;
+        }
+    }
+    __syncthreads();
+    // interpolation at the tile's points, force and torque terms
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (own) {
+        T ur[2] = {0, 0};
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            const T wyz = tp.w[1][b] * tp.w[2][0];
+            const int yy = min(max(tp.c[1][b] - oy, 0), PE - 1);
+#pragma unroll
+            for (int a = 0; a < 4; a++) {
+                const T W = tp.w[0][a] * wyz;
+                const int xx = min(max(tp.c[0][a] - ox, 0), PE - 1);
+                ur[0] += W * up[0][yy][xx];
+                ur[1] += W * up[1][yy][xx];
+            }
+        }
+        double Dv[3] = {(double)ur[0] - P.US[0], (double)ur[1] - P.US[1], 0.0};
+        v[0] = kr * Dv[0];
+        v[1] = kr * Dv[1];
+        v[3] = kr * (pick3(P.r, D.pi) * pick3(Dv, D.pj) - pick3(P.r, D.pj) * pick3(Dv, D.pi));
+    }
+    // fixed-order block sum of the waves holding points
+    const int lane = tid & 63, wid = tid >> 6;
+    if (wid < NW) {
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const double s = wave_sum(v[j]);
+            if (lane == 0) red[j][wid] = s;
+        }
+    }
+    __syncthreads();
+    if (tid < 4) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; w++) s += red[tid][w];
+        part_out[(long long)blockIdx.x * 4 + tid] = s;
+    }
+}
+
+// Last step of the 2D loop: block 0 forms B^(K) from the partials of iteration K-1
+// (record, next step's first record, finiteness flag); all blocks spread at pose
+// B^(K-1) over the footprint box and write u <- (u* + kappa u^S) / (1 + kappa) into
+// the state, keeping u* in ustar.
+template <typename T, bool ROT, int LPN>
+__global__ __launch_bounds__(256) void k_iter_final2d(Grid g, Design D, BodyParams bp, double *__restrict__ Bk,
+                                                      int K, const T *__restrict__ krT, T *__restrict__ u,
+                                                      T *__restrict__ ustar, const double *__restrict__ part_in,
+                                                      unsigned nb, double *__restrict__ Bnext0,
+                                                      int *__restrict__ flag) {
+    if (blockIdx.x == 0) {
+        __shared__ double Bs[B_REC];
+        __shared__ double FT[4];
+        body_from_partials<2, 256>(bp, Bk, part_in, nb, Bs, FT);
+        if (threadIdx.x == 0) {
+            bool bad = false;
+            for (int j = 0; j < B_REC; j++) Bk[K * B_REC + j] = Bs[j];
+            for (int j = 0; j < 8; j++) bad = bad || !isfinite(Bs[j]);
+            if (bad) atomicOr(flag, 1);
+            if (Bnext0)
+                for (int j = 0; j < B_REC; j++) Bnext0[j] = Bs[j];
+        }
+    }
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long l = t / LPN;
+    const int q = (int)(t % LPN);
+    if (l >= D.boxN) return;
+    int o[3], x[3];
+    box_origin<2>(D, Bk, o);
+    if (!box_node<2>(g, D, o, l, x)) return;
+    T kap, us[3];
+    spread_node<2, T, ROT, LPN>(D, Bk + (K - 1) * B_REC, krT, x, q, kap, us);
+    if (q != 0) return;
+    const long long N = g.N;
+    const long long id = node_id(g, x[0], x[1], x[2]);
+    const T inv = T(1) / (T(1) + kap);
+#pragma unroll
+    for (int a = 0; a < 2; a++) {
+        const T s = u[a * N + id];
+        ustar[a * D.boxN + l] = s;
+        u[a * N + id] = (s + kap * us[a]) * inv;
+    }
 }
 
 // Standalone Euler update (body_step entry point).
@@ -689,7 +966,7 @@ __global__ __launch_bounds__(256) void k_adj_r2(Grid g, Bc bc, Design D, const d
     }
     T ub[3] = {0, 0, 0};
     double d[3];
-    gather_design<DIM, T, ROT, LPN>(D, Bk + k * B_REC, x, d, q, [&](long long m, T W, const T *) {
+    gather_design<DIM, T, ROT, LPN>(D, Bk + k * B_REC, x, d, q, [&](long long m, T W, const T *, const int *) {
 #pragma unroll
         for (int a = 0; a < DIM; a++) ub[a] += W * URb[a * D.ND + m];
     });
@@ -715,7 +992,7 @@ __global__ __launch_bounds__(256) void k_adj_r2(Grid g, Bc bc, Design D, const d
     kb[l] = kbar;
 }
 
-template <int DIM>
+template <int DIM, int NTHR>
 __device__ __forceinline__ void r3_finish(const BodyParams &bp, int k, const double *part1, const double *part3,
                                           unsigned nb, double *rec);
 
@@ -783,18 +1060,18 @@ __global__ __launch_bounds__(DBLK) void k_adj_r3(Grid g, Design D, BodyParams bp
     block_reduce_store<8>(v, part3);
     if (!last) return;
     if (!last_block(counter)) return;
-    r3_finish<DIM>(bp, k, part1, part3, gridDim.x, rec);
+    r3_finish<DIM, DBLK>(bp, k, part1, part3, gridDim.x, rec);
     if (threadIdx.x == 0) *counter = 0u;
 }
 
 // Body cotangent B^(k)bar from the R1 and R3 partials (fixed order), then the record
 // step: the force/torque cotangent of iteration k-1, or at k = 0 the cotangent of
 // B(t-1) and the force/torque cotangent of the previous step's last iteration.
-template <int DIM>
+template <int DIM, int NTHR>
 __device__ __forceinline__ void r3_finish(const BodyParams &bp, int k, const double *part1, const double *part3,
                                           unsigned nb, double *rec) {
     __shared__ double Bkb[8];
-    reduce_partials<8>(part1, part3, nb, Bkb);
+    reduce_partials<8, NTHR>(part1, part3, nb, Bkb);
     if (threadIdx.x == 0) {
         double bb[B_REC];
         for (int j = 0; j < B_REC; j++) bb[j] = j < 8 ? Bkb[j] : 0.0;
@@ -813,10 +1090,10 @@ __device__ __forceinline__ void r3_finish(const BodyParams &bp, int k, const dou
 }
 
 template <int DIM>
-__global__ __launch_bounds__(256) void k_r3_finish(BodyParams bp, int k, const double *__restrict__ part1,
+__global__ __launch_bounds__(1024) void k_r3_finish(BodyParams bp, int k, const double *__restrict__ part1,
                                                    const double *__restrict__ part3, unsigned nb,
                                                    double *__restrict__ rec) {
-    r3_finish<DIM>(bp, k, part1, part3, nb, rec);
+    r3_finish<DIM, 1024>(bp, k, part1, part3, nb, rec);
 }
 
 // grad = krb * d kappa_ref / d gamma; optional body cotangent of t = 0.

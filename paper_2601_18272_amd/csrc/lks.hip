@@ -12,6 +12,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -111,6 +112,8 @@ struct Ctx {
     long long face_total = 0;
     long long S = 0;  // elements of a state
     unsigned nblk = 1;
+    int tt2 = 0;         // 2D fused iteration: design tile edge (0: separate kernels)
+    unsigned ntile = 0;  // its number of tiles
 };
 
 constexpr int MARGIN = 2;
@@ -229,6 +232,17 @@ int make_ctx(const lks_problem_t *P, Ctx &c) {
     if (P->objective < 0 || P->objective > 3) return fail(LKS_EINVAL, "bad objective");
     if (P->objective < 3 && P->objective >= c.dim) return fail(LKS_EINVAL, "objective axis >= dim");
     c.nblk = c.has_body ? blocks(D.ND, DBLK) : 1;
+    // fused 2D iterations while every block can afford to read all partials (<= 256)
+    if (c.has_body && c.dim == 2) {
+        for (int tt : {8, 16}) {
+            const unsigned nt = blocks(D.nd[0], tt) * blocks(D.nd[1], tt);
+            if (nt <= 256) {
+                c.tt2 = tt;
+                c.ntile = nt;
+                break;
+            }
+        }
+    }
     return LKS_OK;
 }
 
@@ -258,7 +272,7 @@ Layout layout(const Ctx &c, bool adjoint) {
     L.ustar = take(d * bN * e);
     L.Bf = take(2 * rec);
     L.Binit = take(B_REC * 8);
-    L.part = take((size_t)c.nblk * 8 * 8);
+    L.part = take(std::max((size_t)c.nblk * 8, (size_t)c.ntile * 8) * 8);
     L.counter = take(16);
     L.flag = take(16);
     if (adjoint) {
@@ -387,6 +401,10 @@ template <typename T> struct Run {
     void body_loop(T *state, double *Bk, double *Bnext0, const T *krT, const double *krD, T *ustar,
                    double *part, unsigned *counter, int *flag) const {
         T *u = state + c.g.N;
+        if (c.tt2) {
+            body_loop_fused(u, Bk, Bnext0, krT, krD, ustar, part, flag);
+            return;
+        }
         dispatch(c, [&](auto dm, auto rt) {
             constexpr int DIM = decltype(dm)::value;
             constexpr bool ROT = decltype(rt)::value;
@@ -400,11 +418,42 @@ template <typename T> struct Run {
                                           last_block_ok() ? e1 : nullptr, 0, c.g, c.D, c.bp, u,
                                        krD, Bk, k, c.K, Bnext0, part, counter, flag, last_block_ok() ? 1 : 0);
                     if (!last_block_ok())
-                        hipExtLaunchKernelGGL((k_interp_finish<DIM>), dim3(1), dim3(256), 0, st, nullptr, e1, 0, c.D, c.bp, Bk, k, c.K,
+                        hipExtLaunchKernelGGL((k_interp_finish<DIM>), dim3(1), dim3(1024), 0, st, nullptr, e1, 0, c.D, c.bp, Bk, k, c.K,
                                            Bnext0, part, c.nblk, flag);
                 });
             }
         });
+    }
+    // 2D: one fused kernel per iteration, then B^(K) and the step's spread
+    void body_loop_fused(T *u, double *Bk, double *Bnext0, const T *krT, const double *krD, T *ustar,
+                         double *part, int *flag) const {
+        const size_t half = (size_t)c.ntile * 4;
+        auto run = [&](auto rt, auto tt) {
+            constexpr bool ROT = decltype(rt)::value;
+            constexpr int TT = decltype(tt)::value;
+            for (int k = 0; k < c.K; k++) {
+                const double *pin = part + (size_t)((k + 1) & 1) * half;
+                double *pout = part + (size_t)(k & 1) * half;
+                pf->run(LKS_K_ITER, [&](hipEvent_t e0, hipEvent_t e1) {
+                    hipExtLaunchKernelGGL((k_iter2d<T, ROT, TT>), dim3(c.ntile), dim3(It2<TT>::NT), 0, st, e0, e1, 0,
+                                          c.g, c.D, c.bp, Bk, k, krT, krD, (const T *)u, pin, c.ntile, pout, flag);
+                });
+            }
+            const double *plast = part + (size_t)((c.K - 1) & 1) * half;
+            pf->run(LKS_K_ITER_FINAL, [&](hipEvent_t e0, hipEvent_t e1) {
+                hipExtLaunchKernelGGL((k_iter_final2d<T, ROT, 4>), dim3(blocks(c.D.boxN * 4, 256)), dim3(256), 0, st,
+                                      e0, e1, 0, c.g, c.D, c.bp, Bk, c.K, krT, u, ustar, plast, c.ntile, Bnext0,
+                                      flag);
+            });
+        };
+        const bool r = c.rot;
+        if (c.tt2 == 8) {
+            if (r) run(std::true_type{}, std::integral_constant<int, 8>{});
+            else run(std::false_type{}, std::integral_constant<int, 8>{});
+        } else {
+            if (r) run(std::true_type{}, std::integral_constant<int, 16>{});
+            else run(std::false_type{}, std::integral_constant<int, 16>{});
+        }
     }
     // reverse of the body loop of one step (records Bk, footprint u* of the step)
     void body_rev(const double *Bk, const T *ustar, const T *ab, const T *krT, const double *krD, const Layout &L,
@@ -437,7 +486,7 @@ template <typename T> struct Run {
                                           last_block_ok() ? e1 : nullptr, 0, c.g, c.D, c.bp, Bk, k,
                                        kb, usb, krD, krb, p1, p3, counter, rec, last_block_ok() ? 1 : 0);
                     if (!last_block_ok())
-                        hipExtLaunchKernelGGL((k_r3_finish<DIM>), dim3(1), dim3(256), 0, st, nullptr, e1, 0, c.bp, k, p1, p3, c.nblk, rec);
+                        hipExtLaunchKernelGGL((k_r3_finish<DIM>), dim3(1), dim3(1024), 0, st, nullptr, e1, 0, c.bp, k, p1, p3, c.nblk, rec);
                 });
             }
         });
@@ -476,6 +525,7 @@ int check_flag(const Ctx &, const int *flag_d, hipStream_t st) {
     HIP_TRY(hipStreamSynchronize(st));
     if (flag & 1) return fail(LKS_EDIVERGED, "non-finite body state");
     if (flag & 2) return fail(LKS_EDIVERGED, "body moved more than %d nodes within one step", MARGIN);
+    if (flag & 4) return fail(LKS_EHIP, "internal: design tile patch exceeds its bound");
     return LKS_OK;
 }
 

@@ -131,30 +131,17 @@ __device__ __forceinline__ void bc_resolve(const Grid &g, const Bc &bc, const in
 // Eq. weight_function read as the cosine kernel w(r) = (1 + cos(pi r / 2)) / 4 on
 // |r| < 2, and its derivative -(pi/8) sin(pi r / 2).
 //
-// FP32: with a = |r| and b = a (a <= 1) or 2 - a (a > 1), cos(pi a/2) = +-cos(pi b/2)
-// and sin(pi a/2) = sin(pi b/2) with pi b/2 in [0, pi/2], where the Taylor series of
-// cos to y^12 and of sin to y^13 are accurate to 7e-9 -- below FP32 rounding.
-__device__ __forceinline__ void cs_quarter(float b, float &c, float &s) {
-    const float y = 1.57079632679489662f * b, y2 = y * y;
-    c = 1.0f + y2 * (-0.5f + y2 * (4.16666667e-2f + y2 * (-1.38888889e-3f +
-        y2 * (2.48015873e-5f + y2 * (-2.75573192e-7f + y2 * 2.08767570e-9f)))));
-    s = y * (1.0f + y2 * (-1.66666667e-1f + y2 * (8.33333333e-3f + y2 * (-1.98412698e-4f +
-        y2 * (2.75573192e-6f + y2 * (-2.50521084e-8f + y2 * 1.60590438e-10f))))));
-}
+//
+// FP32 uses the hardware sine and cosine (v_sin_f32 / v_cos_f32, argument in
+// revolutions); FP64 uses cospi / sinpi.
 __device__ __forceinline__ float wk(float r) {
-    const float a = fabsf(r);
-    const float b = a <= 1.0f ? a : 2.0f - a;
-    float c, s;
-    cs_quarter(b, c, s);
-    c = a <= 1.0f ? c : -c;
-    return a < 2.0f ? 0.25f * (1.0f + c) : 0.0f;
+    // the hardware cosine takes revolutions: cos(pi r / 2) = cos(2 pi (r / 4))
+    const float c = __builtin_amdgcn_cosf(0.25f * r);
+    return fabsf(r) < 2.0f ? fmaf(0.25f, c, 0.25f) : 0.0f;
 }
 __device__ __forceinline__ float dwk(float r) {
-    const float a = fabsf(r);
-    const float b = a <= 1.0f ? a : 2.0f - a;
-    float c, s;
-    cs_quarter(b, c, s);
-    return a < 2.0f ? (r < 0.0f ? 0.39269908169872414f : -0.39269908169872414f) * s : 0.0f;
+    const float s = __builtin_amdgcn_sinf(0.25f * r);
+    return fabsf(r) < 2.0f ? -0.39269908169872414f * s : 0.0f;
 }
 __device__ __forceinline__ double wk(double r) {
     return fabs(r) < 2.0 ? 0.25 * (1.0 + cospi(0.5 * r)) : 0.0;
