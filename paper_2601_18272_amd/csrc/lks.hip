@@ -249,7 +249,10 @@ int make_ctx(const lks_problem_t *P, Ctx &c) {
 // ------------------------------------------------------------------ layout
 struct Layout {
     size_t krT, krD, st1, ustar, Bf, Binit, part, counter, flag;
-    size_t seg, ustar_seg, Bseg, ab, kapk, usk, uk, ustb, kb, usb, URb, krb, part1, part3, rec;
+    // adjoint: two segment buffers (recompute of one segment overlaps the reverse sweep
+    // of the other), each of seg_n / ustar_seg_n / Bseg_n bytes
+    size_t seg, ustar_seg, Bseg, seg_n, ustar_seg_n, Bseg_n;
+    size_t ab, kapk, usk, uk, ustb, kb, usb, URb, krb, part1, part3, rec, counter2;
     size_t total;
 };
 
@@ -277,9 +280,12 @@ Layout layout(const Ctx &c, bool adjoint) {
     L.flag = take(16);
     if (adjoint) {
         const size_t Kc = (size_t)(c.Kc > 0 ? c.Kc : 1);
-        L.seg = take((Kc + 1) * stateB);
-        L.ustar_seg = take(Kc * d * bN * e);
-        L.Bseg = take((Kc + 2) * rec);
+        L.seg_n = up((Kc + 1) * stateB);
+        L.ustar_seg_n = up(Kc * d * bN * e);
+        L.Bseg_n = up((Kc + 2) * rec);
+        L.seg = take(2 * L.seg_n);
+        L.ustar_seg = take(2 * L.ustar_seg_n);
+        L.Bseg = take(2 * L.Bseg_n);
         L.ab = take(2 * stateB);
         L.kapk = take(K * bN * e);
         L.usk = take(K * d * bN * e);
@@ -292,6 +298,7 @@ Layout layout(const Ctx &c, bool adjoint) {
         L.part1 = take((size_t)c.nblk * 8 * 8);
         L.part3 = take((size_t)c.nblk * 8 * 8);
         L.rec = take(AR_SIZE * 8);
+        L.counter2 = take(16);
     }
     L.total = o;
     return L;
@@ -462,7 +469,7 @@ template <typename T> struct Run {
         T *ustb = at<T>(w, L.ustb), *kb = at<T>(w, L.kb), *usb = at<T>(w, L.usb), *URb = at<T>(w, L.URb);
         double *krb = at<double>(w, L.krb), *p1 = at<double>(w, L.part1), *p3 = at<double>(w, L.part3);
         double *rec = at<double>(w, L.rec);
-        unsigned *counter = at<unsigned>(w, L.counter);
+        unsigned *counter = at<unsigned>(w, L.counter2);
         const dim3 gb(blocks(c.D.boxN * (c.dim == 2 ? 4 : 1), 256), c.K);
         dispatch(c, [&](auto dm, auto rt) {
             constexpr int DIM = decltype(dm)::value;
@@ -635,19 +642,43 @@ int adjoint_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, const vo
     pf.on = (P->flags & LKS_FLAG_PROFILE) != 0;
     pf.st = st;
     const int every = c.NT > 32 ? (c.NT + 31) / 32 : 1;
+    // The forward recompute of a segment runs on a second stream while the reverse
+    // sweep of the following segment runs on `st`; two segment buffers alternate, and
+    // events order each recompute after the sweep that last used its buffer and each
+    // sweep after its recompute.
+    struct Side {
+        hipStream_t s = nullptr;
+        hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // entry, fwd[2], rev[2]
+        ~Side() {
+            if (s) {
+                (void)hipStreamSynchronize(s);
+                (void)hipStreamDestroy(s);
+            }
+            for (hipEvent_t e : ev)
+                if (e) (void)hipEventDestroy(e);
+        }
+    } side;
+    HIP_TRY(hipStreamCreateWithFlags(&side.s, hipStreamNonBlocking));
+    for (hipEvent_t &e : side.ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    hipEvent_t evEntry = side.ev[0], *evFwd = side.ev + 1, *evRev = side.ev + 3;
     Run<T> R{c, st, &pf};
+    Run<T> F{c, side.s, &pf};
     T *krT = at<T>(work, L.krT);
     double *krD = at<double>(work, L.krD);
     double *part = at<double>(work, L.part);
-    unsigned *counter = at<unsigned>(work, L.counter);
+    unsigned *counter = at<unsigned>(work, L.counter), *counter2 = at<unsigned>(work, L.counter2);
     int *flag = at<int>(work, L.flag);
-    T *seg = at<T>(work, L.seg), *ustar_seg = at<T>(work, L.ustar_seg), *ab = at<T>(work, L.ab);
-    double *Bseg = at<double>(work, L.Bseg), *rec = at<double>(work, L.rec), *krb = at<double>(work, L.krb);
+    T *ab = at<T>(work, L.ab);
+    double *rec = at<double>(work, L.rec), *krb = at<double>(work, L.krb);
     T *ustb = at<T>(work, L.ustb);
+    auto segb = [&](int b) { return at<T>(work, L.seg + (size_t)b * L.seg_n); };
+    auto ustar_segb = [&](int b) { return at<T>(work, L.ustar_seg + (size_t)b * L.ustar_seg_n); };
+    auto Bsegb = [&](int b) { return at<double>(work, L.Bseg + (size_t)b * L.Bseg_n); };
     const size_t recN = (size_t)(c.K + 1) * B_REC;
     const size_t S = (size_t)c.S;
     const size_t fp = (size_t)c.dim * (size_t)c.D.boxN;
     HIP_TRY(hipMemsetAsync(counter, 0, 16, st));
+    HIP_TRY(hipMemsetAsync(counter2, 0, 16, st));
     HIP_TRY(hipMemsetAsync(flag, 0, 16, st));
     R.kappa_ref(gamma, krT, krD);
     if (c.has_body) HIP_TRY(hipMemsetAsync(krb, 0, (size_t)c.D.ND * 8, st));
@@ -656,26 +687,49 @@ int adjoint_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, const vo
         hipLaunchKernelGGL(k_adj_init<2>, dim3(1), dim3(64), 0, st, c.bp, P->objective, seed, rec);
     else
         hipLaunchKernelGGL(k_adj_init<3>, dim3(1), dim3(64), 0, st, c.bp, P->objective, seed, rec);
+    HIP_TRY(hipEventRecord(evEntry, st));
+    HIP_TRY(hipStreamWaitEvent(side.s, evEntry, 0));
     T *ab_cur = ab, *ab_nxt = ab + S;
     const int ncp = (int)ckpt_count(c);
-    for (int ci = ncp - 1; ci >= 0; ci--) {
+    // recompute segment ci into buffer ci & 1, keeping every state, footprint u* and iterate
+    auto recompute = [&](int ci) -> int {
+        const int b = ci & 1;
         const int t0 = ci * c.Kc, t1 = std::min(t0 + c.Kc, c.NT), len = t1 - t0;
+        T *seg = segb(b), *ustar_seg = ustar_segb(b);
+        double *Bseg = Bsegb(b);
+        if (ci + 2 < ncp) HIP_TRY(hipStreamWaitEvent(side.s, evRev[b], 0));
         HIP_TRY(hipMemcpyAsync(seg, at<const char>(const_cast<void *>(ckpt), ckpt_state_off(c, ci)), S * sizeof(T),
-                               hipMemcpyDeviceToDevice, st));
+                               hipMemcpyDeviceToDevice, side.s));
         HIP_TRY(hipMemcpyAsync(Bseg + recN, at<const char>(const_cast<void *>(ckpt), ckpt_body_off(c, ci)),
-                               B_REC * sizeof(double), hipMemcpyDeviceToDevice, st));
-        // recompute the segment, keeping every state, footprint u* and iterate
+                               B_REC * sizeof(double), hipMemcpyDeviceToDevice, side.s));
         for (int j = 1; j <= len; j++) {
             pf.sample = (t0 + j - 1) % every == 0;
             T *prev = seg + (size_t)(j - 1) * S, *cur = seg + (size_t)j * S;
             double *Bk = Bseg + (size_t)j * recN;
-            R.gather(prev, cur);
+            F.gather(prev, cur);
             if (c.has_body)
-                R.body_loop(cur, Bk, Bseg + (size_t)(j + 1) * recN, krT, krD, ustar_seg + (size_t)(j - 1) * fp, part,
+                F.body_loop(cur, Bk, Bseg + (size_t)(j + 1) * recN, krT, krD, ustar_seg + (size_t)(j - 1) * fp, part,
                             counter, flag);
-            R.bcs(cur);
+            F.bcs(cur);
         }
-        // sweep it backwards
+        HIP_TRY(hipEventRecord(evFwd[b], side.s));
+        return LKS_OK;
+    };
+    if (ncp > 0) {
+        const int r0 = recompute(ncp - 1);
+        if (r0 != LKS_OK) return r0;
+    }
+    for (int ci = ncp - 1; ci >= 0; ci--) {
+        if (ci - 1 >= 0) {
+            const int r1 = recompute(ci - 1);
+            if (r1 != LKS_OK) return r1;
+        }
+        const int b = ci & 1;
+        const int t0 = ci * c.Kc, t1 = std::min(t0 + c.Kc, c.NT), len = t1 - t0;
+        T *seg = segb(b), *ustar_seg = ustar_segb(b);
+        double *Bseg = Bsegb(b);
+        HIP_TRY(hipStreamWaitEvent(st, evFwd[b], 0));
+        // sweep the segment backwards
         for (int j = len; j >= 1; j--) {
             pf.sample = (t0 + j - 1) % every == 0;
             const double *Bk = Bseg + (size_t)j * recN;
@@ -685,6 +739,7 @@ int adjoint_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, const vo
             ab_cur = ab_nxt;
             ab_nxt = tmp;
         }
+        HIP_TRY(hipEventRecord(evRev[b], st));
         HIP_TRY(hipGetLastError());
     }
     if (c.has_body)
