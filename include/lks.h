@@ -153,12 +153,15 @@ int body_step(const lks_problem_t *P, const double *ft, const double *body_prev,
 const char *lks_last_error(void);
 
 /*
- * Live kernel timing. A call made with LKS_FLAG_PROFILE has the kernels of a sample of
- * its time steps (at most 32 sampled steps per call, every kernel of a sampled step)
- * stamp HIP events with their own begin and end times (hipExtLaunchKernelGGL), and,
- * after its final synchronisation, adds these execution times to process-wide totals.
- * A unit that is two launches (a reduction plus its one-block finish) is timed from
- * the first kernel's begin to the second's end. Not thread-safe.
+ * Live kernel timing. A call made with LKS_FLAG_PROFILE times the kernels of a sample
+ * of its time steps (at most 32 sampled steps per call, every kernel of a sampled step)
+ * and, after its final synchronisation, adds the durations to process-wide totals. The
+ * LKS and adjoint LKS kernels stamp their own span on the device wall clock (earliest
+ * block start to latest block end, into the workspace); the others are timed with
+ * HIP events attached to the launch (hipExtLaunchKernelGGL), which also count the
+ * dispatch latency of the launch. A unit that is two launches (a reduction plus its
+ * one-block finish) is timed from the first kernel's begin to the second's end. Not
+ * thread-safe.
  *   kernel   LKS_K_* id
  *   total_ms sum of the sampled launch durations (ms); samples: their number
  * Returns LKS_OK or LKS_EINVAL for an unknown id.

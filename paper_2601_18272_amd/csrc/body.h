@@ -18,7 +18,11 @@
 
 namespace lks {
 
-constexpr int DBLK = 128;  // threads per block of the design-point kernels
+// Threads per block of the design-point kernels: 128 in 2D (more blocks, more CUs for
+// small designs), 512 in 3D (fewer block partials for the fixed-order final sums).
+template <int DIM> struct Dblk {
+    static constexpr int v = DIM == 3 ? 512 : 128;
+};
 
 struct BodyParams {
     double kmax, q, mass, inertia;
@@ -346,9 +350,9 @@ template <typename V> __device__ __forceinline__ V sel4(const V v[4], int i) {
 }
 
 // ------------------------------------------------------------------ block reduction
-template <int NV>
+template <int NV, int NTHR>
 __device__ __forceinline__ void block_reduce_store(double v[NV], double *__restrict__ out) {
-    __shared__ double red[NV][DBLK / 64];
+    __shared__ double red[NV][NTHR / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int j = 0; j < NV; j++) v[j] = wave_sum(v[j]);
@@ -359,7 +363,7 @@ __device__ __forceinline__ void block_reduce_store(double v[NV], double *__restr
     if (threadIdx.x < NV) {
         double s = 0.0;
 #pragma unroll
-        for (int w = 0; w < DBLK / 64; w++) s += red[threadIdx.x][w];
+        for (int w = 0; w < NTHR / 64; w++) s += red[threadIdx.x][w];
         out[(long long)blockIdx.x * NV + threadIdx.x] = s;
     }
 }
@@ -431,7 +435,7 @@ __device__ __forceinline__ void interp_finish(const Design &D, const BodyParams 
 // flag bits: 1 non-finite body state, 2 drift beyond the footprint margin. With
 // last = 0 the kernel only writes its partials (k_interp_finish follows).
 template <int DIM, typename T>
-__global__ __launch_bounds__(DBLK) void k_interp_force(Grid g, Design D, BodyParams bp,
+__global__ __launch_bounds__(Dblk<DIM>::v) void k_interp_force(Grid g, Design D, BodyParams bp,
                                                        const T *__restrict__ u, const double *__restrict__ krD,
                                                        double *__restrict__ Bk, int k, int K,
                                                        double *__restrict__ Bnext0, double *__restrict__ part,
@@ -476,10 +480,10 @@ __global__ __launch_bounds__(DBLK) void k_interp_force(Grid g, Design D, BodyPar
         }
         v[3] = kr * (pick3(P.r, D.pi) * pick3(Dv, D.pj) - pick3(P.r, D.pj) * pick3(Dv, D.pi));
     }
-    block_reduce_store<4>(v, part);
+    block_reduce_store<4, Dblk<DIM>::v>(v, part);
     if (!last) return;
     if (!last_block(counter)) return;
-    interp_finish<DIM, DBLK>(D, bp, Bk, k, K, Bnext0, part, gridDim.x, flag);
+    interp_finish<DIM, Dblk<DIM>::v>(D, bp, Bk, k, K, Bnext0, part, gridDim.x, flag);
     if (threadIdx.x == 0) *counter = 0u;
 }
 
@@ -855,7 +859,7 @@ __device__ __forceinline__ void pose_rev(const Design &D, const double *B, const
 
 // R1: reverse of the force/torque and of the interpolation at iteration k.
 template <int DIM, typename T>
-__global__ __launch_bounds__(DBLK) void k_adj_r1(Grid g, Design D, const double *__restrict__ Bk, int k,
+__global__ __launch_bounds__(Dblk<DIM>::v) void k_adj_r1(Grid g, Design D, const double *__restrict__ Bk, int k,
                                                  const T *__restrict__ uk, const double *__restrict__ krD,
                                                  const double *__restrict__ rec, T *__restrict__ URb,
                                                  double *__restrict__ krb, double *__restrict__ part) {
@@ -938,7 +942,7 @@ __global__ __launch_bounds__(DBLK) void k_adj_r1(Grid g, Design D, const double 
         for (int e = 0; e < DIM; e++) Xb[e] = (double)xb[e];
         pose_rev(D, B, P, Xb, USb, rb, v);
     }
-    block_reduce_store<8>(v, part);
+    block_reduce_store<8, Dblk<DIM>::v>(v, part);
 }
 
 // R2: box nodes. u^(k) cotangent = (k = last: the step's velocity cotangent, with the
@@ -1000,7 +1004,7 @@ __device__ __forceinline__ void r3_finish(const BodyParams &bp, int k, const dou
 // reversed; the last block (or k_r3_finish when last = 0) forms the body cotangent
 // B^(k)bar and steps the record.
 template <int DIM, typename T>
-__global__ __launch_bounds__(DBLK) void k_adj_r3(Grid g, Design D, BodyParams bp, const double *__restrict__ Bk,
+__global__ __launch_bounds__(Dblk<DIM>::v) void k_adj_r3(Grid g, Design D, BodyParams bp, const double *__restrict__ Bk,
                                                  int k, const T *__restrict__ kb, const T *__restrict__ usb,
                                                  const double *__restrict__ krD, double *__restrict__ krb,
                                                  const double *__restrict__ part1, double *__restrict__ part3,
@@ -1057,10 +1061,10 @@ __global__ __launch_bounds__(DBLK) void k_adj_r3(Grid g, Design D, BodyParams bp
         }
         pose_rev(D, B, P, Xb, USb, rb, v);
     }
-    block_reduce_store<8>(v, part3);
+    block_reduce_store<8, Dblk<DIM>::v>(v, part3);
     if (!last) return;
     if (!last_block(counter)) return;
-    r3_finish<DIM, DBLK>(bp, k, part1, part3, gridDim.x, rec);
+    r3_finish<DIM, Dblk<DIM>::v>(bp, k, part1, part3, gridDim.x, rec);
     if (threadIdx.x == 0) *counter = 0u;
 }
 

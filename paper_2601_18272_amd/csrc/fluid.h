@@ -29,11 +29,12 @@ constexpr int G2_TX = 64, G2_TY = 8;
 
 template <typename T>
 __global__ __launch_bounds__(512) void k_gather2d(Grid g, T A, const T *__restrict__ sin_,
-                                                  T *__restrict__ sout) {
+                                                  T *__restrict__ sout, unsigned long long *ts) {
     constexpr int RX = G2_TX + 4, RY = G2_TY + 4;  // p, u with a 2-ring
     constexpr int FX = G2_TX + 2, FY = G2_TY + 2;  // f with a 1-ring
     __shared__ T sp[RY][RX], sux[RY][RX], suy[RY][RX];
     __shared__ T sf[9][FY][FX];
+    span_begin(ts);
     const long long N = g.N;
     const int nx = g.n[0], ny = g.n[1];
     const uint3 tb = xcd_tile();
@@ -108,21 +109,24 @@ __global__ __launch_bounds__(512) void k_gather2d(Grid g, T A, const T *__restri
     __syncthreads();
 
     const int x = x0 + threadIdx.x, y = y0 + threadIdx.y;
-    if (x >= nx || y >= ny) return;
-    if ((!g.per[0] && (x == 0 || x == nx - 1)) || (!g.per[1] && (y == 0 || y == ny - 1))) return;
-    T ps = 0, usx = 0, usy = 0;
+    const bool act = x < nx && y < ny && !((!g.per[0] && (x == 0 || x == nx - 1)) ||
+                                           (!g.per[1] && (y == 0 || y == ny - 1)));
+    if (act) {
+        T ps = 0, usx = 0, usy = 0;
 #pragma unroll
-    for (int i = 0; i < 9; i++) {
-        const int cx = Lat<2>::c(i, 0), cy = Lat<2>::c(i, 1);
-        const T f = sf[i][threadIdx.y + 1 - cy][threadIdx.x + 1 - cx];
-        ps += f;
-        usx += T(cx) * f;
-        usy += T(cy) * f;
+        for (int i = 0; i < 9; i++) {
+            const int cx = Lat<2>::c(i, 0), cy = Lat<2>::c(i, 1);
+            const T f = sf[i][threadIdx.y + 1 - cy][threadIdx.x + 1 - cx];
+            ps += f;
+            usx += T(cx) * f;
+            usy += T(cy) * f;
+        }
+        const long long id = (long long)x + (long long)nx * y;
+        sout[id] = ps * T(1.0 / 3.0);
+        sout[N + id] = usx;
+        sout[2 * N + id] = usy;
     }
-    const long long id = (long long)x + (long long)nx * y;
-    sout[id] = ps * T(1.0 / 3.0);
-    sout[N + id] = usx;
-    sout[2 * N + id] = usy;
+    span_end(ts);
 }
 
 // ===================================================================== forward, 3D
@@ -186,11 +190,12 @@ __device__ __forceinline__ void feq3(T p, const T u[3], const T D[3][3], T A, T 
 
 template <typename T>
 __global__ __launch_bounds__(G3<T>::NT, sizeof(T) == 4 ? 6 : 2) void k_gather3d(Grid g, T A, int ZC, const T *__restrict__ sin_,
-                                                        T *__restrict__ sout) {
+                                                        T *__restrict__ sout, unsigned long long *ts) {
     using G = G3<T>;
     constexpr int TX = G::TX, TY = G::TY, WX = G::WX, WY = G::WY;
     __shared__ T wu[2][3][WY][WX];
     __shared__ T fb[15][TY][TX];
+    span_begin(ts);
     const long long N = g.N;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     const uint3 tb = xcd_tile();
@@ -325,6 +330,7 @@ __global__ __launch_bounds__(G3<T>::NT, sizeof(T) == 4 ? 6 : 2) void k_gather3d(
             for (int c = 0; c < 3; c++) rv[c] = nr[c];
         }
     }
+    span_end(ts);
 }
 
 // ===================================================================== boundary values
@@ -525,11 +531,12 @@ template <typename T>
 __global__ __launch_bounds__(512) void k_adjgather2d(Grid g, Bc bc, T A, const T *__restrict__ ab,
                                                      const T *__restrict__ ustb, const double *__restrict__ Bprev,
                                                      Design D, int has_box, const T *__restrict__ sprev,
-                                                     T *__restrict__ out) {
+                                                     T *__restrict__ out, unsigned long long *ts) {
     constexpr int RX = G2_TX + 6, RY = G2_TY + 6;
     constexpr int MX = G2_TX + 4, MY = G2_TY + 4;
     __shared__ T sP[RY][RX], sU[RY][RX], sV[RY][RX];
     __shared__ T mpi[MY][MX], mux[MY][MX], muy[MY][MX], mxx[MY][MX], myy[MY][MX], mxy[MY][MX];
+    span_begin(ts);
     const long long N = g.N;
     const int nx = g.n[0], ny = g.n[1];
     const uint3 tb = xcd_tile();
@@ -583,29 +590,31 @@ __global__ __launch_bounds__(512) void k_adjgather2d(Grid g, Bc bc, T A, const T
     }
     __syncthreads();
     const int x = x0 + threadIdx.x, y = y0 + threadIdx.y;
-    if (x >= nx || y >= ny) return;
-    const int mx = threadIdx.x + 2, my = threadIdx.y + 2;
-    const long long id = (long long)x + (long long)nx * y;
-    const T u0 = sprev[N + id], u1 = sprev[2 * N + id];
-    const T pi = mpi[my][mx];
-    T ox = T(3) * mux[my][mx] + T(9) * (mxx[my][mx] * u0 + mxy[my][mx] * u1) - T(3) * pi * u0;
-    T oy = T(3) * muy[my][mx] + T(9) * (mxy[my][mx] * u0 + myy[my][mx] * u1) - T(3) * pi * u1;
-    int off[5];
-    T cf[5];
-    const T A2 = T(2) * A;
-    int k = dT_stencil<T>(x, nx, g.per[0], off, cf);
-    for (int j = 0; j < k; j++) {  // a = x: sig_xx -> u_x, sig_xy -> u_y
-        ox += A2 * cf[j] * mxx[my][mx + off[j]];
-        oy += A2 * cf[j] * mxy[my][mx + off[j]];
+    if (x < nx && y < ny) {
+        const int mx = threadIdx.x + 2, my = threadIdx.y + 2;
+        const long long id = (long long)x + (long long)nx * y;
+        const T u0 = sprev[N + id], u1 = sprev[2 * N + id];
+        const T pi = mpi[my][mx];
+        T ox = T(3) * mux[my][mx] + T(9) * (mxx[my][mx] * u0 + mxy[my][mx] * u1) - T(3) * pi * u0;
+        T oy = T(3) * muy[my][mx] + T(9) * (mxy[my][mx] * u0 + myy[my][mx] * u1) - T(3) * pi * u1;
+        int off[5];
+        T cf[5];
+        const T A2 = T(2) * A;
+        int k = dT_stencil<T>(x, nx, g.per[0], off, cf);
+        for (int j = 0; j < k; j++) {  // a = x: sig_xx -> u_x, sig_xy -> u_y
+            ox += A2 * cf[j] * mxx[my][mx + off[j]];
+            oy += A2 * cf[j] * mxy[my][mx + off[j]];
+        }
+        k = dT_stencil<T>(y, ny, g.per[1], off, cf);
+        for (int j = 0; j < k; j++) {  // a = y: sig_yx -> u_x, sig_yy -> u_y
+            ox += A2 * cf[j] * mxy[my + off[j]][mx];
+            oy += A2 * cf[j] * myy[my + off[j]][mx];
+        }
+        out[id] = T(3) * pi;
+        out[N + id] = ox;
+        out[2 * N + id] = oy;
     }
-    k = dT_stencil<T>(y, ny, g.per[1], off, cf);
-    for (int j = 0; j < k; j++) {  // a = y: sig_yx -> u_x, sig_yy -> u_y
-        ox += A2 * cf[j] * mxy[my + off[j]][mx];
-        oy += A2 * cf[j] * myy[my + off[j]][mx];
-    }
-    out[id] = T(3) * pi;
-    out[N + id] = ox;
-    out[2 * N + id] = oy;
+    span_end(ts);
 }
 
 // ===================================================================== adjoint, 3D
@@ -632,11 +641,13 @@ template <typename T> struct A3 {
 template <typename T>
 __global__ __launch_bounds__(A3<T>::NT, sizeof(T) == 4 ? 4 : 2) void k_adjgather3d(
     Grid g, Bc bc, T A, int ZC, int offx, int offy, const T *__restrict__ ab, const T *__restrict__ ustb,
-    const double *__restrict__ Bprev, Design D, int has_box, const T *__restrict__ sprev, T *__restrict__ out) {
+    const double *__restrict__ Bprev, Design D, int has_box, const T *__restrict__ sprev, T *__restrict__ out,
+    unsigned long long *ts) {
     using G = A3<T>;
     constexpr int TX = G::TX, TY = G::TY, WX = G::WX, WY = G::WY;
     __shared__ T gr[3][4][WY][WX];  // g = (p*bar / 3, u*bar) of planes s-1, s, s+1
     __shared__ T sg[5][TY][TX];     // sig_xx, sig_xy, sig_xz, sig_yy, sig_yz of plane s
+    span_begin(ts);
     const long long N = g.N;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     const uint3 tb = xcd_tile();
@@ -829,6 +840,7 @@ __global__ __launch_bounds__(A3<T>::NT, sizeof(T) == 4 ? 4 : 2) void k_adjgather
             out[3 * N + id] = o[2];
         }
     }
+    span_end(ts);
 }
 
 }  // namespace lks

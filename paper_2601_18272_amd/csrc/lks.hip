@@ -59,6 +59,14 @@ std::vector<hipEvent_t> g_events;
 double g_prof_ms[LKS_K_COUNT];
 long long g_prof_n[LKS_K_COUNT];
 
+constexpr int NSPAN = 256;  // stamped launches per call (at most)
+__global__ void k_span_init(unsigned long long *s, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        s[2 * i] = ~0ull;
+        s[2 * i + 1] = 0ull;
+    }
+}
+
 struct Prof {
     bool on = false;
     bool sample = false;
@@ -85,6 +93,21 @@ struct Prof {
         launch(g_events[2 * i], g_events[2 * i + 1]);
         ids.push_back(id);
     }
+    // Stencil kernels stamp their own span (first block start, last block end) into a
+    // slot pair of a small workspace area instead; `launch(ts)` passes the slot (null:
+    // not sampled).
+    unsigned long long *span = nullptr;
+    int nspan = 0;
+    std::vector<int> span_ids;
+    template <typename F> void run_span(int id, F &&launch) {
+        if (!on || !sample || !span || (int)span_ids.size() >= nspan) {
+            launch(nullptr);
+            return;
+        }
+        unsigned long long *ts = span + 2 * span_ids.size();
+        span_ids.push_back(id);
+        launch(ts);
+    }
     void finish() {
         for (size_t i = 0; i < ids.size(); i++) {
             float ms = 0.f;
@@ -94,6 +117,27 @@ struct Prof {
             }
         }
         ids.clear();
+        if (!span_ids.empty()) {
+            std::vector<unsigned long long> h(2 * span_ids.size());
+            int dev = 0, khz = 0;
+            if (hipMemcpy(h.data(), span, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost) ==
+                    hipSuccess &&
+                hipGetDevice(&dev) == hipSuccess &&
+                hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0) {
+                for (size_t i = 0; i < span_ids.size(); i++)
+                    if (h[2 * i + 1] > h[2 * i]) {
+                        g_prof_ms[span_ids[i]] += (double)(h[2 * i + 1] - h[2 * i]) / khz;
+                        g_prof_n[span_ids[i]] += 1;
+                    }
+            }
+            span_ids.clear();
+        }
+    }
+    // preset the slots (all-ones start, zero end) on stream s
+    void arm(unsigned long long *slots, int n, hipStream_t s) {
+        span = slots;
+        nspan = n;
+        if (on) hipLaunchKernelGGL(k_span_init, dim3(1), dim3(256), 0, s, slots, n);
     }
 };
 
@@ -112,6 +156,7 @@ struct Ctx {
     long long face_total = 0;
     long long S = 0;  // elements of a state
     unsigned nblk = 1;
+    int dblk = 128;      // threads per block of the design-point kernels
     int tt2 = 0;         // 2D fused iteration: design tile edge (0: separate kernels)
     unsigned ntile = 0;  // its number of tiles
 };
@@ -231,7 +276,8 @@ int make_ctx(const lks_problem_t *P, Ctx &c) {
     c.Kc = P->ckpt_every;
     if (P->objective < 0 || P->objective > 3) return fail(LKS_EINVAL, "bad objective");
     if (P->objective < 3 && P->objective >= c.dim) return fail(LKS_EINVAL, "objective axis >= dim");
-    c.nblk = c.has_body ? blocks(D.ND, DBLK) : 1;
+    c.dblk = c.dim == 3 ? Dblk<3>::v : Dblk<2>::v;
+    c.nblk = c.has_body ? blocks(D.ND, c.dblk) : 1;
     // fused 2D iterations while every block can afford to read all partials (<= 256)
     if (c.has_body && c.dim == 2) {
         for (int tt : {8, 16}) {
@@ -248,7 +294,7 @@ int make_ctx(const lks_problem_t *P, Ctx &c) {
 
 // ------------------------------------------------------------------ layout
 struct Layout {
-    size_t krT, krD, st1, ustar, Bf, Binit, part, counter, flag;
+    size_t krT, krD, st1, ustar, Bf, Binit, part, counter, flag, span;
     // adjoint: two segment buffers (recompute of one segment overlaps the reverse sweep
     // of the other), each of seg_n / ustar_seg_n / Bseg_n bytes
     size_t seg, ustar_seg, Bseg, seg_n, ustar_seg_n, Bseg_n;
@@ -278,6 +324,7 @@ Layout layout(const Ctx &c, bool adjoint) {
     L.part = take(std::max((size_t)c.nblk * 8, (size_t)c.ntile * 8) * 8);
     L.counter = take(16);
     L.flag = take(16);
+    L.span = take(2 * NSPAN * sizeof(unsigned long long));
     if (adjoint) {
         const size_t Kc = (size_t)(c.Kc > 0 ? c.Kc : 1);
         L.seg_n = up((Kc + 1) * stateB);
@@ -381,15 +428,16 @@ template <typename T> struct Run {
     void gather(const T *in, T *out) const {
         if (c.dim == 2) {
             dim3 grid(blocks(c.g.n[0], G2_TX), blocks(c.g.n[1], G2_TY));
-            pf->run(LKS_K_GATHER, [&](hipEvent_t e0, hipEvent_t e1) {
-                hipExtLaunchKernelGGL(k_gather2d<T>, grid, dim3(G2_TX, G2_TY), 0, st, e0, e1, 0, c.g, T(c.A), in, out);
+            pf->run_span(LKS_K_GATHER, [&](unsigned long long *ts) {
+                hipLaunchKernelGGL(k_gather2d<T>, grid, dim3(G2_TX, G2_TY), 0, st, c.g, T(c.A), in, out, ts);
             });
         } else {
             static const long long res = resident_blocks(k_gather3d<T>, G3<T>::NT);
             const int zc = zchunk(G3<T>::OX, G3<T>::OY, res);
             const dim3 grid(blocks(c.g.n[0], G3<T>::OX), blocks(c.g.n[1], G3<T>::OY), blocks(c.g.n[2], zc));
-            pf->run(LKS_K_GATHER, [&](hipEvent_t e0, hipEvent_t e1) {
-                hipExtLaunchKernelGGL(k_gather3d<T>, grid, dim3(G3<T>::TX, G3<T>::TY), 0, st, e0, e1, 0, c.g, T(c.A), zc, in, out);
+            pf->run_span(LKS_K_GATHER, [&](unsigned long long *ts) {
+                hipLaunchKernelGGL(k_gather3d<T>, grid, dim3(G3<T>::TX, G3<T>::TY), 0, st, c.g, T(c.A), zc, in, out,
+                                   ts);
             });
         }
     }
@@ -421,7 +469,7 @@ template <typename T> struct Run {
                                        dim3(256), 0, st, e0, e1, 0, c.g, c.D, Bk, k, krT, u, ustar);
                 });
                 pf->run(LKS_K_INTERP, [&](hipEvent_t e0, hipEvent_t e1) {
-                    hipExtLaunchKernelGGL((k_interp_force<DIM, T>), dim3(c.nblk), dim3(DBLK), 0, st, e0,
+                    hipExtLaunchKernelGGL((k_interp_force<DIM, T>), dim3(c.nblk), dim3(c.dblk), 0, st, e0,
                                           last_block_ok() ? e1 : nullptr, 0, c.g, c.D, c.bp, u,
                                        krD, Bk, k, c.K, Bnext0, part, counter, flag, last_block_ok() ? 1 : 0);
                     if (!last_block_ok())
@@ -480,7 +528,7 @@ template <typename T> struct Run {
             });
             for (int k = c.K - 1; k >= 0; k--) {
                 pf->run(LKS_K_ADJ_R1, [&](hipEvent_t e0, hipEvent_t e1) {
-                    hipExtLaunchKernelGGL((k_adj_r1<DIM, T>), dim3(c.nblk), dim3(DBLK), 0, st, e0, e1, 0, c.g, c.D, Bk, k, uk, krD,
+                    hipExtLaunchKernelGGL((k_adj_r1<DIM, T>), dim3(c.nblk), dim3(c.dblk), 0, st, e0, e1, 0, c.g, c.D, Bk, k, uk, krD,
                                        rec, URb, krb, p1);
                 });
                 pf->run(LKS_K_ADJ_R2, [&](hipEvent_t e0, hipEvent_t e1) {
@@ -489,7 +537,7 @@ template <typename T> struct Run {
                                        usb);
                 });
                 pf->run(LKS_K_ADJ_R3, [&](hipEvent_t e0, hipEvent_t e1) {
-                    hipExtLaunchKernelGGL((k_adj_r3<DIM, T>), dim3(c.nblk), dim3(DBLK), 0, st, e0,
+                    hipExtLaunchKernelGGL((k_adj_r3<DIM, T>), dim3(c.nblk), dim3(c.dblk), 0, st, e0,
                                           last_block_ok() ? e1 : nullptr, 0, c.g, c.D, c.bp, Bk, k,
                                        kb, usb, krD, krb, p1, p3, counter, rec, last_block_ok() ? 1 : 0);
                     if (!last_block_ok())
@@ -500,11 +548,11 @@ template <typename T> struct Run {
     }
     void adj_gather(const T *ab, const T *ustb, const double *Bprev, const T *sprev, T *out) const {
         const int hb = c.has_body ? 1 : 0;
-        pf->run(LKS_K_ADJ_GATHER, [&](hipEvent_t e0, hipEvent_t e1) {
+        pf->run_span(LKS_K_ADJ_GATHER, [&](unsigned long long *ts) {
             if (c.dim == 2) {
                 dim3 grid(blocks(c.g.n[0], G2_TX), blocks(c.g.n[1], G2_TY));
-                hipExtLaunchKernelGGL(k_adjgather2d<T>, grid, dim3(G2_TX, G2_TY), 0, st, e0, e1, 0, c.g, c.bc, T(c.A), ab, ustb,
-                                   Bprev, c.D, hb, sprev, out);
+                hipLaunchKernelGGL(k_adjgather2d<T>, grid, dim3(G2_TX, G2_TY), 0, st, c.g, c.bc, T(c.A), ab, ustb,
+                                   Bprev, c.D, hb, sprev, out, ts);
             } else {
                 static const long long res = resident_blocks(k_adjgather3d<T>, A3<T>::NT);
                 // shift the tiles of a non-periodic axis by one node where a tile
@@ -514,8 +562,8 @@ template <typename T> struct Run {
                 const int zc = zchunk(A3<T>::OX, A3<T>::OY, res);
                 const dim3 grid(blocks(c.g.n[0] + offx, A3<T>::OX), blocks(c.g.n[1] + offy, A3<T>::OY),
                                 blocks(c.g.n[2], zc));
-                hipExtLaunchKernelGGL(k_adjgather3d<T>, grid, dim3(A3<T>::TX, A3<T>::TY), 0, st, e0, e1, 0, c.g, c.bc,
-                                      T(c.A), zc, offx, offy, ab, ustb, Bprev, c.D, hb, sprev, out);
+                hipLaunchKernelGGL(k_adjgather3d<T>, grid, dim3(A3<T>::TX, A3<T>::TY), 0, st, c.g, c.bc, T(c.A), zc,
+                                   offx, offy, ab, ustb, Bprev, c.D, hb, sprev, out, ts);
             }
         });
     }
@@ -551,6 +599,7 @@ int forward_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, T *state
     Prof pf;
     pf.on = (P->flags & LKS_FLAG_PROFILE) != 0;
     pf.st = st;
+    pf.arm(at<unsigned long long>(work, L.span), NSPAN, st);
     const int every = c.NT > 32 ? (c.NT + 31) / 32 : 1;
     Run<T> R{c, st, &pf};
     T *krT = at<T>(work, L.krT);
@@ -641,6 +690,7 @@ int adjoint_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, const vo
     Prof pf;
     pf.on = (P->flags & LKS_FLAG_PROFILE) != 0;
     pf.st = st;
+    pf.arm(at<unsigned long long>(work, L.span), NSPAN, st);
     const int every = c.NT > 32 ? (c.NT + 31) / 32 : 1;
     // The forward recompute of a segment runs on a second stream while the reverse
     // sweep of the following segment runs on `st`; two segment buffers alternate, and

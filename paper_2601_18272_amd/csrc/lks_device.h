@@ -68,6 +68,22 @@ __device__ __forceinline__ bool wrap_coord(int &v, int n, int per) {
     return v >= 0 && v < n;
 }
 
+// Span of a sampled launch on the constant-rate wall clock: ts[0] keeps the earliest
+// block start, ts[1] the latest block end (preset to all-ones and zero on the host
+// side). span_end waits for the whole block; every thread calls both, and the kernels
+// that use them have no early returns.
+__device__ __forceinline__ void span_begin(unsigned long long *ts) {
+    if (ts && threadIdx.x == 0 && threadIdx.y == 0 && threadIdx.z == 0)
+        atomicMin(&ts[0], (unsigned long long)wall_clock64());
+}
+__device__ __forceinline__ void span_end(unsigned long long *ts) {
+    if (ts) {
+        __syncthreads();
+        if (threadIdx.x == 0 && threadIdx.y == 0 && threadIdx.z == 0)
+            atomicMax(&ts[1], (unsigned long long)wall_clock64());
+    }
+}
+
 // Workgroups are handed out round-robin over the eight XCDs (workgroup b, counted x
 // fastest, runs on XCD b mod 8), and each XCD has its own L2. Renumber the tiles so
 // that XCD j gets the j-th contiguous run of them (x fastest): neighbouring tiles then
