@@ -166,10 +166,12 @@ def roofline_sweep(args):
             for k in ("gather", "adj_gather"):
                 ms, cnt = prof[k]
                 us = ms / cnt * 1e3
+                sms, scnt = prof[k + "_span"]
+                sus = sms / scnt * 1e3
                 by = alg_bytes_per_launch(k, pb, 4)
-                line[k] = {"avg_launch_us": round(us, 2), "bytes_per_launch": by,
-                           "achieved_GBs": round(by / us / 1e3, 1),
-                           "frac": round(by / us / 1e3 / HBM_PEAK_GBS, 4), "samples": cnt}
+                line[k] = {"avg_launch_us": round(us, 2), "kernel_span_us": round(sus, 2), "bytes_per_launch": by,
+                           "achieved_GBs": round(by / us / 1e3, 1), "frac": round(by / us / 1e3 / HBM_PEAK_GBS, 4),
+                           "achieved_GBs_span": round(by / sus / 1e3, 1), "samples": cnt}
             print(json.dumps(line), flush=True)
             del bufs, s0
             torch.cuda.empty_cache()
@@ -268,7 +270,7 @@ def main():
 
     # dominant kernel: largest estimated share of the gradient (sampled avg x launches)
     lp = launches_per_gradient(pb)
-    est = {k: (ms / n) * lp[k] for k, (ms, n) in prof.items() if n > 0}
+    est = {k: (ms / n) * lp[k] for k, (ms, n) in prof.items() if n > 0 and k in lp}
     dom = max(est, key=est.get)
     roof = None
     hbm_kernels = {k: v for k, v in est.items() if alg_bytes_per_launch(k, pb, elt)}
@@ -285,6 +287,11 @@ def main():
                 "bytes_per_launch": by, "avg_launch_us": round(avg_s * 1e6, 3),
                 "samples": n, "dominant_kernel": dom,
                 "share_of_gradient_est": {k: round(v / sum(est.values()), 3) for k, v in est.items()}}
+        span = prof.get(name + "_span")
+        if span and span[1] > 0:
+            span_s = span[0] / span[1] / 1e3
+            roof["kernel_span_us"] = round(span_s * 1e6, 3)
+            roof["achieved_kernel_span"] = round(by / span_s / 1e9, 1)
         break
 
     if args.calibrate_copy:

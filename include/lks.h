@@ -156,10 +156,11 @@ const char *lks_last_error(void);
  * Live kernel timing. A call made with LKS_FLAG_PROFILE times the kernels of a sample
  * of its time steps (at most 32 sampled steps per call, every kernel of a sampled step)
  * and, after its final synchronisation, adds the durations to process-wide totals. The
- * LKS and adjoint LKS kernels stamp their own span on the device wall clock (earliest
- * block start to latest block end, into the workspace); the others are timed with
- * HIP events attached to the launch (hipExtLaunchKernelGGL), which also count the
- * dispatch latency of the launch. A unit that is two launches (a reduction plus its
+ * durations come from HIP events attached to the launch (hipExtLaunchKernelGGL:
+ * dispatch to completion, as a profiler counts a launch). The LKS and adjoint LKS
+ * kernels also stamp their own span on the device wall clock (first blocks' start to
+ * last blocks' end, into the workspace), read as LKS_K_GATHER_SPAN and
+ * LKS_K_ADJ_GATHER_SPAN. A unit that is two launches (a reduction plus its
  * one-block finish) is timed from the first kernel's begin to the second's end. Not
  * thread-safe.
  *   kernel   LKS_K_* id
@@ -178,7 +179,9 @@ enum {
     LKS_K_ADJ_R3 = 8,
     LKS_K_ITER = 9,        /* 2D: one fused iteration (partials -> B^(k), tile spread, interp) */
     LKS_K_ITER_FINAL = 10, /* 2D: B^(K) and the step's spread into the state */
-    LKS_K_COUNT = 11
+    LKS_K_GATHER_SPAN = 11,     /* LKS_K_GATHER, the kernel's own span (no dispatch) */
+    LKS_K_ADJ_GATHER_SPAN = 12, /* LKS_K_ADJ_GATHER, the kernel's own span */
+    LKS_K_COUNT = 13
 };
 int lks_profile_read(int kernel, double *total_ms, long long *samples);
 void lks_profile_reset(void);

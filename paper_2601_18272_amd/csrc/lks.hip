@@ -99,14 +99,23 @@ struct Prof {
     unsigned long long *span = nullptr;
     int nspan = 0;
     std::vector<int> span_ids;
-    template <typename F> void run_span(int id, F &&launch) {
-        if (!on || !sample || !span || (int)span_ids.size() >= nspan) {
-            launch(nullptr);
+    // Stencil kernels: sampled launches alternate between launch-attached events
+    // (dispatch to completion, as a profiler counts a launch; recorded under `id`) and
+    // the kernel's own span (under `span_id`), so that neither perturbs the other.
+    bool next_span = false;
+    template <typename F> void run_span(int id, int span_id, F &&launch) {
+        if (!on || !sample) {
+            launch(nullptr, nullptr, nullptr);
+            return;
+        }
+        next_span = !next_span;
+        if (!next_span || !span || (int)span_ids.size() >= nspan) {
+            run(id, [&](hipEvent_t e0, hipEvent_t e1) { launch(e0, e1, nullptr); });
             return;
         }
         unsigned long long *ts = span + 2 * span_ids.size();
-        span_ids.push_back(id);
-        launch(ts);
+        span_ids.push_back(span_id);
+        launch(nullptr, nullptr, ts);
     }
     void finish() {
         for (size_t i = 0; i < ids.size(); i++) {
@@ -428,16 +437,17 @@ template <typename T> struct Run {
     void gather(const T *in, T *out) const {
         if (c.dim == 2) {
             dim3 grid(blocks(c.g.n[0], G2_TX), blocks(c.g.n[1], G2_TY));
-            pf->run_span(LKS_K_GATHER, [&](unsigned long long *ts) {
-                hipLaunchKernelGGL(k_gather2d<T>, grid, dim3(G2_TX, G2_TY), 0, st, c.g, T(c.A), in, out, ts);
+            pf->run_span(LKS_K_GATHER, LKS_K_GATHER_SPAN, [&](hipEvent_t e0, hipEvent_t e1, unsigned long long *ts) {
+                hipExtLaunchKernelGGL(k_gather2d<T>, grid, dim3(G2_TX, G2_TY), 0, st, e0, e1, 0, c.g, T(c.A), in, out,
+                                      ts);
             });
         } else {
             static const long long res = resident_blocks(k_gather3d<T>, G3<T>::NT);
             const int zc = zchunk(G3<T>::OX, G3<T>::OY, res);
             const dim3 grid(blocks(c.g.n[0], G3<T>::OX), blocks(c.g.n[1], G3<T>::OY), blocks(c.g.n[2], zc));
-            pf->run_span(LKS_K_GATHER, [&](unsigned long long *ts) {
-                hipLaunchKernelGGL(k_gather3d<T>, grid, dim3(G3<T>::TX, G3<T>::TY), 0, st, c.g, T(c.A), zc, in, out,
-                                   ts);
+            pf->run_span(LKS_K_GATHER, LKS_K_GATHER_SPAN, [&](hipEvent_t e0, hipEvent_t e1, unsigned long long *ts) {
+                hipExtLaunchKernelGGL(k_gather3d<T>, grid, dim3(G3<T>::TX, G3<T>::TY), 0, st, e0, e1, 0, c.g, T(c.A),
+                                      zc, in, out, ts);
             });
         }
     }
@@ -548,11 +558,12 @@ template <typename T> struct Run {
     }
     void adj_gather(const T *ab, const T *ustb, const double *Bprev, const T *sprev, T *out) const {
         const int hb = c.has_body ? 1 : 0;
-        pf->run_span(LKS_K_ADJ_GATHER, [&](unsigned long long *ts) {
+        pf->run_span(LKS_K_ADJ_GATHER, LKS_K_ADJ_GATHER_SPAN, [&](hipEvent_t e0, hipEvent_t e1,
+                                                                   unsigned long long *ts) {
             if (c.dim == 2) {
                 dim3 grid(blocks(c.g.n[0], G2_TX), blocks(c.g.n[1], G2_TY));
-                hipLaunchKernelGGL(k_adjgather2d<T>, grid, dim3(G2_TX, G2_TY), 0, st, c.g, c.bc, T(c.A), ab, ustb,
-                                   Bprev, c.D, hb, sprev, out, ts);
+                hipExtLaunchKernelGGL(k_adjgather2d<T>, grid, dim3(G2_TX, G2_TY), 0, st, e0, e1, 0, c.g, c.bc, T(c.A),
+                                      ab, ustb, Bprev, c.D, hb, sprev, out, ts);
             } else {
                 static const long long res = resident_blocks(k_adjgather3d<T>, A3<T>::NT);
                 // shift the tiles of a non-periodic axis by one node where a tile
@@ -562,8 +573,8 @@ template <typename T> struct Run {
                 const int zc = zchunk(A3<T>::OX, A3<T>::OY, res);
                 const dim3 grid(blocks(c.g.n[0] + offx, A3<T>::OX), blocks(c.g.n[1] + offy, A3<T>::OY),
                                 blocks(c.g.n[2], zc));
-                hipLaunchKernelGGL(k_adjgather3d<T>, grid, dim3(A3<T>::TX, A3<T>::TY), 0, st, c.g, c.bc, T(c.A), zc,
-                                   offx, offy, ab, ustb, Bprev, c.D, hb, sprev, out, ts);
+                hipExtLaunchKernelGGL(k_adjgather3d<T>, grid, dim3(A3<T>::TX, A3<T>::TY), 0, st, e0, e1, 0, c.g, c.bc,
+                                      T(c.A), zc, offx, offy, ab, ustb, Bprev, c.D, hb, sprev, out, ts);
             }
         });
     }

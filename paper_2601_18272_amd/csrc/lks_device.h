@@ -70,16 +70,22 @@ __device__ __forceinline__ bool wrap_coord(int &v, int n, int per) {
 
 // Span of a sampled launch on the constant-rate wall clock: ts[0] keeps the earliest
 // block start, ts[1] the latest block end (preset to all-ones and zero on the host
-// side). span_end waits for the whole block; every thread calls both, and the kernels
-// that use them have no early returns.
+// side). Blocks are dispatched in index order and do equal work here, so the first 64
+// blocks stamp the start and the last 64 the end (a bounded number of atomics on the
+// two slots, whatever the grid). span_end waits for the whole block; every thread
+// calls both, and the kernels that use them have no early returns.
+__device__ __forceinline__ unsigned span_block() {
+    return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+}
 __device__ __forceinline__ void span_begin(unsigned long long *ts) {
-    if (ts && threadIdx.x == 0 && threadIdx.y == 0 && threadIdx.z == 0)
+    if (ts && threadIdx.x == 0 && threadIdx.y == 0 && threadIdx.z == 0 && span_block() < 64)
         atomicMin(&ts[0], (unsigned long long)wall_clock64());
 }
 __device__ __forceinline__ void span_end(unsigned long long *ts) {
     if (ts) {
         __syncthreads();
-        if (threadIdx.x == 0 && threadIdx.y == 0 && threadIdx.z == 0)
+        const unsigned nb = gridDim.x * gridDim.y * gridDim.z;
+        if (threadIdx.x == 0 && threadIdx.y == 0 && threadIdx.z == 0 && span_block() + 64 >= nb)
             atomicMax(&ts[1], (unsigned long long)wall_clock64());
     }
 }
