@@ -166,12 +166,14 @@ def roofline_sweep(args):
             for k in ("gather", "adj_gather"):
                 ms, cnt = prof[k]
                 us = ms / cnt * 1e3
-                sms, scnt = prof[k + "_span"]
-                sus = sms / scnt * 1e3
                 by = alg_bytes_per_launch(k, pb, 4)
-                line[k] = {"avg_launch_us": round(us, 2), "kernel_span_us": round(sus, 2), "bytes_per_launch": by,
+                line[k] = {"avg_launch_us": round(us, 2), "bytes_per_launch": by,
                            "achieved_GBs": round(by / us / 1e3, 1), "frac": round(by / us / 1e3 / HBM_PEAK_GBS, 4),
-                           "achieved_GBs_span": round(by / sus / 1e3, 1), "samples": cnt}
+                           "samples": cnt}
+                sms, scnt = prof.get(k + "_span", (0.0, 0))
+                if scnt:
+                    sus = sms / scnt * 1e3
+                    line[k].update({"kernel_span_us": round(sus, 2), "achieved_GBs_span": round(by / sus / 1e3, 1)})
             print(json.dumps(line), flush=True)
             del bufs, s0
             torch.cuda.empty_cache()
@@ -265,8 +267,8 @@ def main():
     avg_f = {k: ms / n for k, (ms, n) in prof_f.items() if n > 0}
     avg_a = {k: ms / n for k, (ms, n) in prof_a.items() if n > 0}
     # forward kernels at their forward-pass durations (the recompute overlaps the sweep)
-    prof = {k: v for k, v in prof_a.items()}
-    prof.update(prof_f)
+    prof = {k: v for k, v in prof_a.items() if v[1] > 0}
+    prof.update({k: v for k, v in prof_f.items() if v[1] > 0})
 
     # dominant kernel: largest estimated share of the gradient (sampled avg x launches)
     lp = launches_per_gradient(pb)

@@ -157,10 +157,10 @@ const char *lks_last_error(void);
  * of its time steps (at most 32 sampled steps per call, every kernel of a sampled step)
  * and, after its final synchronisation, adds the durations to process-wide totals. The
  * durations come from HIP events attached to the launch (hipExtLaunchKernelGGL:
- * dispatch to completion, as a profiler counts a launch). The LKS and adjoint LKS
- * kernels also stamp their own span on the device wall clock (first blocks' start to
- * last blocks' end, into the workspace), read as LKS_K_GATHER_SPAN and
- * LKS_K_ADJ_GATHER_SPAN. A unit that is two launches (a reduction plus its
+ * dispatch to completion, as a profiler counts a launch). In 2D, the LKS and adjoint
+ * LKS kernels also stamp their own span on the device wall clock (first blocks' start
+ * to last blocks' end, into the workspace) on every other sampled launch, read as
+ * LKS_K_GATHER_SPAN and LKS_K_ADJ_GATHER_SPAN. A unit that is two launches (a reduction plus its
  * one-block finish) is timed from the first kernel's begin to the second's end. Not
  * thread-safe.
  *   kernel   LKS_K_* id

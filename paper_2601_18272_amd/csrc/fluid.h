@@ -27,14 +27,14 @@ namespace lks {
 // ring nodes).
 constexpr int G2_TX = 64, G2_TY = 8;
 
-template <typename T>
+template <typename T, bool SP>
 __global__ __launch_bounds__(512) void k_gather2d(Grid g, T A, const T *__restrict__ sin_,
                                                   T *__restrict__ sout, unsigned long long *ts) {
     constexpr int RX = G2_TX + 4, RY = G2_TY + 4;  // p, u with a 2-ring
     constexpr int FX = G2_TX + 2, FY = G2_TY + 2;  // f with a 1-ring
     __shared__ T sp[RY][RX], sux[RY][RX], suy[RY][RX];
     __shared__ T sf[9][FY][FX];
-    span_begin(ts);
+    if (SP) span_begin(ts);
     const long long N = g.N;
     const int nx = g.n[0], ny = g.n[1];
     const uint3 tb = xcd_tile();
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(512) void k_gather2d(Grid g, T A, const T *__restri
         sout[N + id] = usx;
         sout[2 * N + id] = usy;
     }
-    span_end(ts);
+    if (SP) span_end(ts);
 }
 
 // ===================================================================== forward, 3D
@@ -188,14 +188,14 @@ __device__ __forceinline__ void feq3(T p, const T u[3], const T D[3][3], T A, T 
     }
 }
 
-template <typename T>
+template <typename T, bool SP>
 __global__ __launch_bounds__(G3<T>::NT, sizeof(T) == 4 ? 6 : 2) void k_gather3d(Grid g, T A, int ZC, const T *__restrict__ sin_,
                                                         T *__restrict__ sout, unsigned long long *ts) {
     using G = G3<T>;
     constexpr int TX = G::TX, TY = G::TY, WX = G::WX, WY = G::WY;
     __shared__ T wu[2][3][WY][WX];
     __shared__ T fb[15][TY][TX];
-    span_begin(ts);
+    if (SP) span_begin(ts);
     const long long N = g.N;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     const uint3 tb = xcd_tile();
@@ -330,7 +330,7 @@ __global__ __launch_bounds__(G3<T>::NT, sizeof(T) == 4 ? 6 : 2) void k_gather3d(
             for (int c = 0; c < 3; c++) rv[c] = nr[c];
         }
     }
-    span_end(ts);
+    if (SP) span_end(ts);
 }
 
 // ===================================================================== boundary values
@@ -527,7 +527,7 @@ __device__ __forceinline__ void star_bar(const Grid &g, const Bc &bc, const T *_
 // ===================================================================== adjoint, 2D
 // 64 x 8 tile. Stage p*bar, u*bar with a 3-node ring (zero off the interior), form
 // the moments (pi, ups, sig) on the tile plus a 2-ring, then the outputs.
-template <typename T>
+template <typename T, bool SP>
 __global__ __launch_bounds__(512) void k_adjgather2d(Grid g, Bc bc, T A, const T *__restrict__ ab,
                                                      const T *__restrict__ ustb, const double *__restrict__ Bprev,
                                                      Design D, int has_box, const T *__restrict__ sprev,
@@ -536,7 +536,7 @@ __global__ __launch_bounds__(512) void k_adjgather2d(Grid g, Bc bc, T A, const T
     constexpr int MX = G2_TX + 4, MY = G2_TY + 4;
     __shared__ T sP[RY][RX], sU[RY][RX], sV[RY][RX];
     __shared__ T mpi[MY][MX], mux[MY][MX], muy[MY][MX], mxx[MY][MX], myy[MY][MX], mxy[MY][MX];
-    span_begin(ts);
+    if (SP) span_begin(ts);
     const long long N = g.N;
     const int nx = g.n[0], ny = g.n[1];
     const uint3 tb = xcd_tile();
@@ -614,7 +614,7 @@ __global__ __launch_bounds__(512) void k_adjgather2d(Grid g, Bc bc, T A, const T
         out[N + id] = ox;
         out[2 * N + id] = oy;
     }
-    span_end(ts);
+    if (SP) span_end(ts);
 }
 
 // ===================================================================== adjoint, 3D
@@ -638,7 +638,7 @@ template <typename T> struct A3 {
     static constexpr int RING = 2 * WX + 2 * TY;
 };
 
-template <typename T>
+template <typename T, bool SP>
 __global__ __launch_bounds__(A3<T>::NT, sizeof(T) == 4 ? 4 : 2) void k_adjgather3d(
     Grid g, Bc bc, T A, int ZC, int offx, int offy, const T *__restrict__ ab, const T *__restrict__ ustb,
     const double *__restrict__ Bprev, Design D, int has_box, const T *__restrict__ sprev, T *__restrict__ out,
@@ -647,7 +647,7 @@ __global__ __launch_bounds__(A3<T>::NT, sizeof(T) == 4 ? 4 : 2) void k_adjgather
     constexpr int TX = G::TX, TY = G::TY, WX = G::WX, WY = G::WY;
     __shared__ T gr[3][4][WY][WX];  // g = (p*bar / 3, u*bar) of planes s-1, s, s+1
     __shared__ T sg[5][TY][TX];     // sig_xx, sig_xy, sig_xz, sig_yy, sig_yz of plane s
-    span_begin(ts);
+    if (SP) span_begin(ts);
     const long long N = g.N;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     const uint3 tb = xcd_tile();
@@ -840,7 +840,7 @@ __global__ __launch_bounds__(A3<T>::NT, sizeof(T) == 4 ? 4 : 2) void k_adjgather
             out[3 * N + id] = o[2];
         }
     }
-    span_end(ts);
+    if (SP) span_end(ts);
 }
 
 }  // namespace lks

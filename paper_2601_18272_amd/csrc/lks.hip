@@ -109,7 +109,7 @@ struct Prof {
             return;
         }
         next_span = !next_span;
-        if (!next_span || !span || (int)span_ids.size() >= nspan) {
+        if (span_id < 0 || !next_span || !span || (int)span_ids.size() >= nspan) {
             run(id, [&](hipEvent_t e0, hipEvent_t e1) { launch(e0, e1, nullptr); });
             return;
         }
@@ -438,16 +438,21 @@ template <typename T> struct Run {
         if (c.dim == 2) {
             dim3 grid(blocks(c.g.n[0], G2_TX), blocks(c.g.n[1], G2_TY));
             pf->run_span(LKS_K_GATHER, LKS_K_GATHER_SPAN, [&](hipEvent_t e0, hipEvent_t e1, unsigned long long *ts) {
-                hipExtLaunchKernelGGL(k_gather2d<T>, grid, dim3(G2_TX, G2_TY), 0, st, e0, e1, 0, c.g, T(c.A), in, out,
-                                      ts);
+                if (ts)
+                    hipLaunchKernelGGL((k_gather2d<T, true>), grid, dim3(G2_TX, G2_TY), 0, st, c.g, T(c.A), in, out,
+                                       ts);
+                else
+                    hipExtLaunchKernelGGL((k_gather2d<T, false>), grid, dim3(G2_TX, G2_TY), 0, st, e0, e1, 0, c.g,
+                                          T(c.A), in, out, ts);
             });
         } else {
-            static const long long res = resident_blocks(k_gather3d<T>, G3<T>::NT);
+            static const long long res = resident_blocks(k_gather3d<T, false>, G3<T>::NT);
             const int zc = zchunk(G3<T>::OX, G3<T>::OY, res);
             const dim3 grid(blocks(c.g.n[0], G3<T>::OX), blocks(c.g.n[1], G3<T>::OY), blocks(c.g.n[2], zc));
-            pf->run_span(LKS_K_GATHER, LKS_K_GATHER_SPAN, [&](hipEvent_t e0, hipEvent_t e1, unsigned long long *ts) {
-                hipExtLaunchKernelGGL(k_gather3d<T>, grid, dim3(G3<T>::TX, G3<T>::TY), 0, st, e0, e1, 0, c.g, T(c.A),
-                                      zc, in, out, ts);
+            // 3D: launch events only (long launches; the stamping variant would spill)
+            pf->run_span(LKS_K_GATHER, -1, [&](hipEvent_t e0, hipEvent_t e1, unsigned long long *) {
+                hipExtLaunchKernelGGL((k_gather3d<T, false>), grid, dim3(G3<T>::TX, G3<T>::TY), 0, st, e0, e1, 0,
+                                      c.g, T(c.A), zc, in, out, nullptr);
             });
         }
     }
@@ -558,14 +563,18 @@ template <typename T> struct Run {
     }
     void adj_gather(const T *ab, const T *ustb, const double *Bprev, const T *sprev, T *out) const {
         const int hb = c.has_body ? 1 : 0;
-        pf->run_span(LKS_K_ADJ_GATHER, LKS_K_ADJ_GATHER_SPAN, [&](hipEvent_t e0, hipEvent_t e1,
-                                                                   unsigned long long *ts) {
+        pf->run_span(LKS_K_ADJ_GATHER, c.dim == 2 ? LKS_K_ADJ_GATHER_SPAN : -1,
+                     [&](hipEvent_t e0, hipEvent_t e1, unsigned long long *ts) {
             if (c.dim == 2) {
                 dim3 grid(blocks(c.g.n[0], G2_TX), blocks(c.g.n[1], G2_TY));
-                hipExtLaunchKernelGGL(k_adjgather2d<T>, grid, dim3(G2_TX, G2_TY), 0, st, e0, e1, 0, c.g, c.bc, T(c.A),
-                                      ab, ustb, Bprev, c.D, hb, sprev, out, ts);
+                if (ts)
+                    hipLaunchKernelGGL((k_adjgather2d<T, true>), grid, dim3(G2_TX, G2_TY), 0, st, c.g, c.bc, T(c.A),
+                                       ab, ustb, Bprev, c.D, hb, sprev, out, ts);
+                else
+                    hipExtLaunchKernelGGL((k_adjgather2d<T, false>), grid, dim3(G2_TX, G2_TY), 0, st, e0, e1, 0,
+                                          c.g, c.bc, T(c.A), ab, ustb, Bprev, c.D, hb, sprev, out, ts);
             } else {
-                static const long long res = resident_blocks(k_adjgather3d<T>, A3<T>::NT);
+                static const long long res = resident_blocks(k_adjgather3d<T, false>, A3<T>::NT);
                 // shift the tiles of a non-periodic axis by one node where a tile
                 // boundary would fall on node n-2 (see k_adjgather3d)
                 const int offx = !c.g.per[0] && (c.g.n[0] - 2) % A3<T>::OX == 0 ? 1 : 0;
@@ -573,8 +582,8 @@ template <typename T> struct Run {
                 const int zc = zchunk(A3<T>::OX, A3<T>::OY, res);
                 const dim3 grid(blocks(c.g.n[0] + offx, A3<T>::OX), blocks(c.g.n[1] + offy, A3<T>::OY),
                                 blocks(c.g.n[2], zc));
-                hipExtLaunchKernelGGL(k_adjgather3d<T>, grid, dim3(A3<T>::TX, A3<T>::TY), 0, st, e0, e1, 0, c.g, c.bc,
-                                      T(c.A), zc, offx, offy, ab, ustb, Bprev, c.D, hb, sprev, out, ts);
+                hipExtLaunchKernelGGL((k_adjgather3d<T, false>), grid, dim3(A3<T>::TX, A3<T>::TY), 0, st, e0, e1, 0,
+                                      c.g, c.bc, T(c.A), zc, offx, offy, ab, ustb, Bprev, c.D, hb, sprev, out, ts);
             }
         });
     }
