@@ -73,6 +73,9 @@ def lib():
         L.orc_body_step.argtypes = [pp, dp, dp, dp]
         L.orc_coupling.argtypes = [pp, dp, dp, dp, dp]
         L.orc_kappa_ref.argtypes = [pp, dp, dp]
+        ip = C.POINTER(C.c_int)
+        L.orc_filter.argtypes = [C.c_int, ip, C.c_double, C.c_double, C.c_double, dp, dp, dp]
+        L.orc_filter_adjoint.argtypes = [C.c_int, ip, C.c_double, C.c_double, C.c_double, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -199,3 +202,23 @@ def coupling(pb, gamma, state, body):
     _check(lib().orc_coupling(C.byref(s), _p(_f64(gamma)), _p(_f64(state)), _p(_f64(body)),
                               _p(K)), "orc_coupling")
     return K
+
+
+def filter(dim, nd, R, beta, eta, g):
+    """Density filter + Heaviside projection (Sec. 3.2): returns (gt, gh)."""
+    nd3 = (C.c_int * 3)(*[int(v) for v in nd])
+    g = _f64(g)
+    gt, gh = np.empty_like(g), np.empty_like(g)
+    _check(lib().orc_filter(int(dim), nd3, float(R), float(beta), float(eta), _p(g), _p(gt), _p(gh)),
+           "orc_filter")
+    return gt, gh
+
+
+def filter_adjoint(dim, nd, R, beta, eta, gt, gbh):
+    """Cotangent of gamma from the cotangent of the projected field."""
+    nd3 = (C.c_int * 3)(*[int(v) for v in nd])
+    gt, gbh = _f64(gt), _f64(gbh)
+    gb = np.empty_like(gt)
+    _check(lib().orc_filter_adjoint(int(dim), nd3, float(R), float(beta), float(eta), _p(gt), _p(gbh), _p(gb)),
+           "orc_filter_adjoint")
+    return gb

@@ -1061,3 +1061,78 @@ done:
     free(u);
     return rc;
 }
+
+/* ------------------------------------------------------------------ filter (Sec. 3.2) */
+
+/* Weight of Eq. filter between design points i and j (index space, spacing one). */
+static double filter_w(double R, const int *a, const int *b) {
+    double d2 = 0.0;
+    for (int k = 0; k < 3; k++) d2 += (double)(a[k] - b[k]) * (a[k] - b[k]);
+    const double d = sqrt(d2);
+    return d <= R ? (R - d) / R : 0.0;
+}
+
+static int filter_args(int dim, const int nd[3], double R) {
+    if ((dim != 2 && dim != 3) || !nd || !(R > 0.0)) return -1;
+    if (nd[0] < 1 || nd[1] < 1 || nd[2] < 1 || (dim == 2 && nd[2] != 1)) return -1;
+    return 0;
+}
+
+/* Visits every design point j with |x_i - x_j| <= R and calls f(j, w_ij). */
+#define FOR_NEIGHBOURS(nd, R, xi, j, w, BODY)                                                \
+    do {                                                                                     \
+        const int r_ = (int)floor(R);                                                        \
+        int xj[3];                                                                           \
+        for (xj[2] = xi[2] - r_; xj[2] <= xi[2] + r_; xj[2]++)                               \
+            for (xj[1] = xi[1] - r_; xj[1] <= xi[1] + r_; xj[1]++)                           \
+                for (xj[0] = xi[0] - r_; xj[0] <= xi[0] + r_; xj[0]++) {                     \
+                    if (xj[0] < 0 || xj[0] >= nd[0] || xj[1] < 0 || xj[1] >= nd[1] ||        \
+                        xj[2] < 0 || xj[2] >= nd[2])                                         \
+                        continue;                                                            \
+                    const double w = filter_w(R, xi, xj);                                    \
+                    if (w <= 0.0) continue;                                                  \
+                    const long j = xj[0] + (long)nd[0] * (xj[1] + (long)nd[1] * xj[2]);      \
+                    BODY;                                                                    \
+                }                                                                            \
+    } while (0)
+
+static double proj_den(double beta, double eta) { return tanh(beta * eta) + tanh(beta * (1.0 - eta)); }
+
+int orc_filter(int dim, const int nd[3], double R, double beta, double eta, const double *g, double *gt,
+               double *gh) {
+    if (filter_args(dim, nd, R) || !g || !gt || !gh || !(beta > 0.0)) return -1;
+    const long n = (long)nd[0] * nd[1] * nd[2];
+    const double den = proj_den(beta, eta);
+    for (long i = 0; i < n; i++) {
+        const int xi[3] = {(int)(i % nd[0]), (int)((i / nd[0]) % nd[1]), (int)(i / ((long)nd[0] * nd[1]))};
+        double num = 0.0, wsum = 0.0;
+        FOR_NEIGHBOURS(nd, R, xi, j, w, {
+            num += w * g[j];
+            wsum += w;
+        });
+        gt[i] = num / wsum;
+        gh[i] = (tanh(beta * eta) + tanh(beta * (gt[i] - eta))) / den;
+    }
+    return 0;
+}
+
+int orc_filter_adjoint(int dim, const int nd[3], double R, double beta, double eta, const double *gt,
+                       const double *gbh, double *gb) {
+    if (filter_args(dim, nd, R) || !gt || !gbh || !gb || !(beta > 0.0)) return -1;
+    const long n = (long)nd[0] * nd[1] * nd[2];
+    const double den = proj_den(beta, eta);
+    for (long j = 0; j < n; j++) gb[j] = 0.0;
+    /* gb_j = sum_i (dgh_i / dgt_i) gbh_i w_ij / W_i, scattered from every i */
+    for (long i = 0; i < n; i++) {
+        const int xi[3] = {(int)(i % nd[0]), (int)((i / nd[0]) % nd[1]), (int)(i / ((long)nd[0] * nd[1]))};
+        double wsum = 0.0;
+        FOR_NEIGHBOURS(nd, R, xi, j, w, {
+            (void)j;
+            wsum += w;
+        });
+        const double th = tanh(beta * (gt[i] - eta));
+        const double gbt = gbh[i] * beta * (1.0 - th * th) / den;
+        FOR_NEIGHBOURS(nd, R, xi, j, w, { gb[j] += w * gbt / wsum; });
+    }
+    return 0;
+}

@@ -89,6 +89,20 @@ int orc_coupling(const orc_problem *P, const double *gamma, const double *state,
 /* Brinkman interpolation kappa_ref(gamma). */
 int orc_kappa_ref(const orc_problem *P, const double *gamma, double *kappa_ref);
 
+/* Density filter with Heaviside projection (Sec. 3.2), on a design grid of dim axes
+ * with nd[] points (spacing one):
+ *   Eq. filter      gt_i = sum_j w_ij g_j / sum_j w_ij,  w_ij = (R - |x_i - x_j|) / R
+ *                   for |x_i - x_j| <= R (else 0), j over the design grid;
+ *   Eq. projection  gh_i = (tanh(beta eta) + tanh(beta (gt_i - eta)))
+ *                          / (tanh(beta eta) + tanh(beta (1 - eta))).
+ * orc_filter returns gt and gh; orc_filter_adjoint maps the cotangent gbh of gh to the
+ * cotangent gb of g (the transpose of the projection's and the filter's Jacobians),
+ * given gt. */
+int orc_filter(int dim, const int nd[3], double R, double beta, double eta, const double *g, double *gt,
+               double *gh);
+int orc_filter_adjoint(int dim, const int nd[3], double R, double beta, double eta, const double *gt,
+                       const double *gbh, double *gb);
+
 #ifdef __cplusplus
 }
 #endif

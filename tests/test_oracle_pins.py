@@ -451,3 +451,105 @@ def test_paper_constants_fixture(orc):
     s1, _, _ = orc.forward(pb, None, s0, np.zeros(12))
     G = 2 / 3 + np.cos(k) / 3 + (2 * A / 9) * np.sin(k) ** 2
     assert np.abs(s1[2 * N:] - G * s0[2 * N:]).max() < 1e-21
+
+
+# ---------------------------------------------------------------- filter and projection (Sec. 3.2)
+FILTER_CASES = [(2, (9, 7, 1), 1.5), (2, (12, 5, 1), 2.6), (3, (6, 5, 4), 1.8), (3, (7, 6, 5), 2.2)]
+
+
+@pytest.mark.parametrize("dim,nd,R", FILTER_CASES)
+def test_filter_preserves_constants(orc, dim, nd, R):
+    """Normalised weights sum to one at every point, edges and corners included."""
+    n = int(np.prod(nd))
+    gt, gh = orc.filter(dim, nd, R, 4.0, 0.5, np.full(n, 0.37))
+    assert np.abs(gt - 0.37).max() < 1e-15
+
+
+@pytest.mark.parametrize("dim,nd,R", FILTER_CASES)
+def test_filter_preserves_linear_fields_in_the_interior(orc, dim, nd, R):
+    """The cone weights are symmetric about a point whose whole disc lies on the grid, so a
+    linear field is reproduced there (and not at the truncated edges)."""
+    n = int(np.prod(nd))
+    idx = np.arange(n)
+    x = np.stack([idx % nd[0], (idx // nd[0]) % nd[1], idx // (nd[0] * nd[1])]).astype(float)
+    g = 0.1 + 0.03 * x[0] - 0.02 * x[1] + 0.05 * x[2]
+    gt, _ = orc.filter(dim, nd, R, 4.0, 0.5, g)
+    r = int(np.floor(R))
+    inner = np.all([(x[a] >= r) & (x[a] <= nd[a] - 1 - r) for a in range(dim)], axis=0)
+    assert inner.any()
+    assert np.abs(gt[inner] - g[inner]).max() < 1e-14
+    assert np.abs(gt[~inner] - g[~inner]).max() > 1e-6
+
+
+@pytest.mark.parametrize("dim,nd,R", FILTER_CASES)
+def test_filter_weights_symmetric(orc, dim, nd, R):
+    """Responses to unit impulses: gt_i(e_j) / gt_i(e_i) is the raw weight w_ij, which must
+    equal w_ji (and 1/gt_i(e_i) is the normaliser W_i)."""
+    n = int(np.prod(nd))
+    rng = np.random.default_rng(11)
+    pts = rng.choice(n, 6, replace=False)
+    resp = {}
+    for j in pts:
+        e = np.zeros(n)
+        e[j] = 1.0
+        resp[j] = orc.filter(dim, nd, R, 4.0, 0.5, e)[0]
+    for i in pts:
+        for j in pts:
+            wij = resp[j][i] / resp[i][i]
+            wji = resp[i][j] / resp[j][j]
+            assert abs(wij - wji) < 1e-14
+
+
+def test_filter_node_weights(orc):
+    """Cone weights (R - d)/R: with R = 2 the axis neighbour weighs 1/2 of the centre, the
+    diagonal neighbour 1 - sqrt(2)/2, the second axis neighbour nothing."""
+    nd = (9, 9, 1)
+    e = np.zeros(81)
+    c = 4 + 9 * 4
+    e[c] = 1.0
+    gt, _ = orc.filter(2, nd, 2.0, 1.0, 0.5, e)
+    w = gt / gt[c]
+    assert abs(w[c + 1] - 0.5) < 1e-15 and abs(w[c + 9] - 0.5) < 1e-15
+    assert abs(w[c + 10] - (1 - np.sqrt(2) / 2)) < 1e-15
+    assert w[c + 2] == 0.0 and w[c + 18] == 0.0
+
+
+def test_filter_identity_below_unit_radius(orc):
+    g = np.random.default_rng(3).random(60)
+    gt, _ = orc.filter(3, (5, 4, 3), 0.9, 2.0, 0.5, g)
+    assert np.array_equal(gt, g)
+
+
+def test_projection_limits_and_symmetry(orc):
+    """Projection: 0 -> 0, 1 -> 1, monotone; with eta = 1/2 it is odd about 1/2; beta -> 0
+    gives the identity, large beta a step at eta."""
+    g = np.linspace(0.0, 1.0, 41)
+    nd = (41, 1, 1)
+    for beta in (0.5, 4.0, 32.0):
+        _, gh = orc.filter(2, nd, 0.5, beta, 0.5, g)
+        assert abs(gh[0]) < 1e-15 and abs(gh[-1] - 1.0) < 1e-15
+        assert np.all(np.diff(gh) > 0)
+        assert np.abs(gh + gh[::-1] - 1.0).max() < 1e-14
+    _, gh = orc.filter(2, nd, 0.5, 1e-5, 0.3, g)
+    assert np.abs(gh - g).max() < 1e-9
+    _, gh = orc.filter(2, nd, 0.5, 2000.0, 0.3, g)
+    assert np.all(gh[g < 0.29] < 1e-6) and np.all(gh[g > 0.31] > 1 - 1e-6)
+
+
+@pytest.mark.parametrize("dim,nd,R", FILTER_CASES)
+def test_filter_adjoint_vs_finite_differences(orc, dim, nd, R):
+    """<gbh, d gh> = <gb, d g> for a random direction, d gh by central differences."""
+    n = int(np.prod(nd))
+    rng = np.random.default_rng(7)
+    g = rng.random(n)
+    beta, eta = 6.0, 0.45
+    gt, _ = orc.filter(dim, nd, R, beta, eta, g)
+    gbh = rng.standard_normal(n)
+    gb = orc.filter_adjoint(dim, nd, R, beta, eta, gt, gbh)
+    d = rng.standard_normal(n)
+    h = 1e-6
+    ghp = orc.filter(dim, nd, R, beta, eta, g + h * d)[1]
+    ghm = orc.filter(dim, nd, R, beta, eta, g - h * d)[1]
+    lhs = gbh @ ((ghp - ghm) / (2 * h))
+    rhs = gb @ d
+    assert abs(lhs - rhs) <= 1e-7 * max(abs(rhs), 1.0)
