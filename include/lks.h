@@ -149,6 +149,46 @@ int map_design(const lks_problem_t *P, const void *kappa_ref, const double *body
 int body_step(const lks_problem_t *P, const double *ft, const double *body_prev, double *body,
               void *stream);
 
+/* Density filter and Heaviside projection of the design field (Sec. 3.2). */
+typedef struct lks_filter {
+    double radius; /* R of Eq. filter in design-grid spacings: R > 0, floor(R) <= 8 in 2D, <= 4 in 3D */
+    double beta;   /* steepness of Eq. projection, > 0 */
+    double eta;    /* threshold of Eq. projection, in [0, 1] */
+} lks_filter_t;
+
+/*
+ * lks_design_filter -- Eq. filter, then Eq. projection, on the design grid of P (only
+ * P->dim, P->nd and P->precision are used; P must be valid and have a design grid):
+ *   gamma_tilde_i = sum_j w_ij gamma_j / sum_j w_ij, w_ij = (R - |x_i - x_j|) / R for
+ *                   design points within distance R (the cone is cut at the grid's edge);
+ *   gamma_hat_i   = (tanh(beta eta) + tanh(beta (gamma_tilde_i - eta)))
+ *                   / (tanh(beta eta) + tanh(beta (1 - eta))).
+ * gamma_hat is what lks_forward and lks_adjoint take as their design.
+ *   gamma       [ND] T (read only)
+ *   gamma_tilde [ND] T, out
+ *   gamma_hat   [ND] T, out
+ * The three arrays must not overlap. Enqueued on `stream` without synchronising, unless
+ * P->flags has LKS_FLAG_PROFILE: then the call synchronises the stream and adds the
+ * kernel's duration to LKS_K_FILTER.
+ * Errors: LKS_EINVAL, LKS_EHIP.
+ */
+int lks_design_filter(const lks_problem_t *P, const lks_filter_t *F, const void *gamma, void *gamma_tilde,
+                      void *gamma_hat, void *stream);
+
+/*
+ * lks_design_filter_adjoint -- reverse of lks_design_filter, in FP64: a sensitivity with
+ * respect to gamma_hat is taken through the derivative of Eq. projection at gamma_tilde
+ * and the transpose of Eq. filter:
+ *   dJ_dgamma_j = sum_i w_ij dJ_dgamma_hat_i (d gamma_hat / d gamma_tilde)_i / sum_k w_ik.
+ *   gamma_tilde   [ND] T, the filtered field of the forward call (read only)
+ *   dJ_dgamma_hat [ND] double (read only), e.g. the grad of lks_adjoint
+ *   dJ_dgamma     [ND] double, out; must not overlap the two inputs
+ * Stream and LKS_FLAG_PROFILE (kernel LKS_K_FILTER_ADJ) as for lks_design_filter.
+ * Errors: LKS_EINVAL, LKS_EHIP.
+ */
+int lks_design_filter_adjoint(const lks_problem_t *P, const lks_filter_t *F, const void *gamma_tilde,
+                              const double *dJ_dgamma_hat, double *dJ_dgamma, void *stream);
+
 /* Message of the last error on this thread ("" if none). */
 const char *lks_last_error(void);
 
@@ -181,7 +221,9 @@ enum {
     LKS_K_ITER_FINAL = 10, /* 2D: B^(K) and the step's spread into the state */
     LKS_K_GATHER_SPAN = 11,     /* LKS_K_GATHER, the kernel's own span (no dispatch) */
     LKS_K_ADJ_GATHER_SPAN = 12, /* LKS_K_ADJ_GATHER, the kernel's own span */
-    LKS_K_COUNT = 13
+    LKS_K_FILTER = 13,          /* lks_design_filter */
+    LKS_K_FILTER_ADJ = 14,      /* lks_design_filter_adjoint */
+    LKS_K_COUNT = 15
 };
 int lks_profile_read(int kernel, double *total_ms, long long *samples);
 void lks_profile_reset(void);

@@ -15,13 +15,13 @@ FP32, FP64 = 0, 1
 FLAG_ASYNC = 1
 FLAG_PROFILE = 2
 KERNELS = ("gather", "bc", "spread", "interp", "adj_gather", "adj_recompute", "adj_r1", "adj_r2",
-           "adj_r3", "iter", "iter_final", "gather_span", "adj_gather_span")
+           "adj_r3", "iter", "iter_final", "gather_span", "adj_gather_span", "filter", "filter_adj")
 
 OK, EINVAL, ENOSPACE, EUNSTABLE, EDIVERGED, EHIP = 0, -1, -2, -3, -4, -5
 
 EXPORTS = ("lks_state_elems", "lks_checkpoint_bytes", "lks_workspace_bytes", "lks_forward",
            "lks_adjoint", "map_design", "body_step", "lks_last_error", "lks_profile_read",
-           "lks_profile_reset")
+           "lks_profile_reset", "lks_design_filter", "lks_design_filter_adjoint")
 
 
 class LksProblem(C.Structure):
@@ -46,6 +46,10 @@ class LksProblem(C.Structure):
         ("objective", C.c_int),
         ("flags", C.c_int),
     ]
+
+
+class LksFilter(C.Structure):
+    _fields_ = [("radius", C.c_double), ("beta", C.c_double), ("eta", C.c_double)]
 
 
 class LksError(RuntimeError):
@@ -82,6 +86,11 @@ def load():
     L.map_design.restype = C.c_int
     L.body_step.argtypes = [pp, dp, dp, dp, vp]
     L.body_step.restype = C.c_int
+    fp = C.POINTER(LksFilter)
+    L.lks_design_filter.argtypes = [pp, fp, vp, vp, vp, vp]
+    L.lks_design_filter.restype = C.c_int
+    L.lks_design_filter_adjoint.argtypes = [pp, fp, vp, dp, dp, vp]
+    L.lks_design_filter_adjoint.restype = C.c_int
     L.lks_last_error.argtypes = []
     L.lks_last_error.restype = C.c_char_p
     L.lks_profile_read.argtypes = [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]

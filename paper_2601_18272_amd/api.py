@@ -12,7 +12,7 @@ import ctypes as C
 import torch
 
 from . import _lib
-from ._lib import LksError, LksProblem  # noqa: F401
+from ._lib import LksError, LksFilter, LksProblem  # noqa: F401
 
 DTYPES = {"fp32": torch.float32, "fp64": torch.float64}
 
@@ -147,6 +147,39 @@ def body_step(pb, ft, body_prev):
     out = torch.empty(12, dtype=torch.float64, device="cuda")
     _lib.check(L.body_step(C.byref(s), _p(f), _p(bp), _p(out), _stream()))
     return out
+
+
+def filter_struct(radius: float, beta: float, eta: float = 0.5) -> LksFilter:
+    f = LksFilter()
+    f.radius, f.beta, f.eta = float(radius), float(beta), float(eta)
+    return f
+
+
+def design_filter(pb, gamma, radius, beta, eta=0.5, precision="fp32", flags: int = 0):
+    """Filtered and projected design (gamma_tilde, gamma_hat) on pb's design grid."""
+    L = _lib.load()
+    dt = DTYPES[precision]
+    s = problem_struct(pb, precision, flags)
+    g = _dev(gamma, dt).reshape(-1)
+    gt = torch.empty_like(g)
+    gh = torch.empty_like(g)
+    f = filter_struct(radius, beta, eta)
+    _lib.check(L.lks_design_filter(C.byref(s), C.byref(f), _p(g), _p(gt), _p(gh), _stream()))
+    return gt, gh
+
+
+def design_filter_adjoint(pb, gamma_tilde, dJ_dgamma_hat, radius, beta, eta=0.5, precision="fp32",
+                          flags: int = 0):
+    """dJ/dgamma (FP64) from dJ/dgamma_hat through the projection and the filter."""
+    L = _lib.load()
+    dt = DTYPES[precision]
+    s = problem_struct(pb, precision, flags)
+    gt = _dev(gamma_tilde, dt).reshape(-1)
+    gbh = _dev(dJ_dgamma_hat, torch.float64).reshape(-1)
+    gb = torch.empty_like(gbh)
+    f = filter_struct(radius, beta, eta)
+    _lib.check(L.lks_design_filter_adjoint(C.byref(s), C.byref(f), _p(gt), _p(gbh), _p(gb), _stream()))
+    return gb
 
 
 class LKSFunction(torch.autograd.Function):

@@ -23,6 +23,7 @@
 
 #include "../../include/lks.h"
 #include "body.h"
+#include "filter.h"
 
 using namespace lks;
 
@@ -829,6 +830,53 @@ int adjoint_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, const vo
 
 }  // namespace
 
+// =================================================================== design filter
+namespace {
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+    const char *pa = (const char *)a, *pb = (const char *)b;
+    return pa < pb + nb && pb < pa + na;
+}
+
+// Problem and filter parameters of lks_design_filter(_adjoint).
+int filter_ctx(const lks_problem_t *P, const lks_filter_t *F, Ctx &c, FltArgs &a) {
+    int rc = make_ctx(P, c);
+    if (rc) return rc;
+    if (!c.has_body) return fail(LKS_EINVAL, "the design filter needs a design grid");
+    if (!F) return fail(LKS_EINVAL, "null filter parameters");
+    const int rmax = c.dim == 2 ? Flt<2>::RMAX : Flt<3>::RMAX;
+    if (!(F->radius > 0.0) || !(F->radius < rmax + 1.0))
+        return fail(LKS_EINVAL, "filter radius %g outside (0, %d)", F->radius, rmax + 1);
+    if (!(F->beta > 0.0) || !std::isfinite(F->beta)) return fail(LKS_EINVAL, "projection beta must be > 0");
+    if (!(F->eta >= 0.0 && F->eta <= 1.0)) return fail(LKS_EINVAL, "projection eta must lie in [0, 1]");
+    for (int k = 0; k < 3; k++) a.n[k] = c.D.nd[k];
+    a.r = (int)std::floor(F->radius);
+    a.R = F->radius;
+    a.beta = F->beta;
+    a.eta = F->eta;
+    return LKS_OK;
+}
+
+// One launch over the design tiles, timed under `id` with LKS_FLAG_PROFILE.
+template <typename L> int filter_run(const Ctx &c, bool prof, int id, hipStream_t st, L &&launch) {
+    const int tx = c.dim == 2 ? Flt<2>::TX : Flt<3>::TX, ty = c.dim == 2 ? Flt<2>::TY : Flt<3>::TY,
+              tz = c.dim == 2 ? Flt<2>::TZ : Flt<3>::TZ;
+    const dim3 grid(blocks(c.D.nd[0], tx), blocks(c.D.nd[1], ty), blocks(c.D.nd[2], tz));
+    const dim3 blk(tx * ty * tz);
+    Prof pf;
+    pf.on = pf.sample = prof;
+    pf.st = st;
+    pf.run(id, [&](hipEvent_t e0, hipEvent_t e1) { launch(grid, blk, e0, e1); });
+    HIP_TRY(hipGetLastError());
+    if (pf.on) {
+        HIP_TRY(hipStreamSynchronize(st));
+        pf.finish();
+    }
+    return LKS_OK;
+}
+
+}  // namespace
+
 // =================================================================== C ABI
 extern "C" {
 
@@ -856,14 +904,21 @@ size_t lks_state_elems(const lks_problem_t *P) {
 
 size_t lks_checkpoint_bytes(const lks_problem_t *P) {
     Ctx c;
-    if (make_ctx(P, c) != LKS_OK || c.Kc < 1) return 0;
+    if (make_ctx(P, c) != LKS_OK) return 0;
+    if (c.Kc < 1) {
+        fail(LKS_EINVAL, "ckpt_every must be >= 1 to store checkpoints");
+        return 0;
+    }
     return ckpt_bytes(c);
 }
 
 size_t lks_workspace_bytes(const lks_problem_t *P, int adjoint) {
     Ctx c;
     if (make_ctx(P, c) != LKS_OK) return 0;
-    if (adjoint && c.Kc < 1) return 0;
+    if (adjoint && c.Kc < 1) {
+        fail(LKS_EINVAL, "ckpt_every must be >= 1 for the adjoint");
+        return 0;
+    }
     return layout(c, adjoint != 0).total;
 }
 
@@ -938,6 +993,55 @@ int body_step(const lks_problem_t *P, const double *ft, const double *body_prev,
         hipLaunchKernelGGL(k_body_step<3>, dim3(1), dim3(64), 0, st, c.bp, ft, body_prev, body);
     HIP_TRY(hipGetLastError());
     return LKS_OK;
+}
+
+int lks_design_filter(const lks_problem_t *P, const lks_filter_t *F, const void *gamma, void *gamma_tilde,
+                      void *gamma_hat, void *stream) {
+    g_err.clear();
+    Ctx c;
+    FltArgs a;
+    int rc = filter_ctx(P, F, c, a);
+    if (rc) return rc;
+    if (!gamma || !gamma_tilde || !gamma_hat) return fail(LKS_EINVAL, "null pointer argument");
+    const size_t nb = (size_t)c.D.ND * c.elt;
+    if (overlap(gamma, nb, gamma_tilde, nb) || overlap(gamma, nb, gamma_hat, nb) ||
+        overlap(gamma_tilde, nb, gamma_hat, nb))
+        return fail(LKS_EINVAL, "gamma, gamma_tilde and gamma_hat must not overlap");
+    hipStream_t st = (hipStream_t)stream;
+    return filter_run(c, (P->flags & LKS_FLAG_PROFILE) != 0, LKS_K_FILTER, st, [&](dim3 grid, dim3 blk, hipEvent_t e0, hipEvent_t e1) {
+#define FLT_LAUNCH(D_, T_)                                                                               \
+    hipExtLaunchKernelGGL((k_filter_fwd<D_, T_>), grid, blk, 0, st, e0, e1, 0, a, (const T_ *)gamma, \
+                          (T_ *)gamma_tilde, (T_ *)gamma_hat)
+        if (c.dim == 2 && c.prec == LKS_FP32) FLT_LAUNCH(2, float);
+        else if (c.dim == 2) FLT_LAUNCH(2, double);
+        else if (c.prec == LKS_FP32) FLT_LAUNCH(3, float);
+        else FLT_LAUNCH(3, double);
+#undef FLT_LAUNCH
+    });
+}
+
+int lks_design_filter_adjoint(const lks_problem_t *P, const lks_filter_t *F, const void *gamma_tilde,
+                              const double *dJ_dgamma_hat, double *dJ_dgamma, void *stream) {
+    g_err.clear();
+    Ctx c;
+    FltArgs a;
+    int rc = filter_ctx(P, F, c, a);
+    if (rc) return rc;
+    if (!gamma_tilde || !dJ_dgamma_hat || !dJ_dgamma) return fail(LKS_EINVAL, "null pointer argument");
+    const size_t nt = (size_t)c.D.ND * c.elt, nd = (size_t)c.D.ND * sizeof(double);
+    if (overlap(dJ_dgamma, nd, gamma_tilde, nt) || overlap(dJ_dgamma, nd, dJ_dgamma_hat, nd))
+        return fail(LKS_EINVAL, "dJ_dgamma must not overlap gamma_tilde or dJ_dgamma_hat");
+    hipStream_t st = (hipStream_t)stream;
+    return filter_run(c, (P->flags & LKS_FLAG_PROFILE) != 0, LKS_K_FILTER_ADJ, st, [&](dim3 grid, dim3 blk, hipEvent_t e0, hipEvent_t e1) {
+#define FLT_LAUNCH(D_, T_)                                                                                   \
+    hipExtLaunchKernelGGL((k_filter_adj<D_, T_>), grid, blk, 0, st, e0, e1, 0, a, (const T_ *)gamma_tilde, \
+                          dJ_dgamma_hat, dJ_dgamma)
+        if (c.dim == 2 && c.prec == LKS_FP32) FLT_LAUNCH(2, float);
+        else if (c.dim == 2) FLT_LAUNCH(2, double);
+        else if (c.prec == LKS_FP32) FLT_LAUNCH(3, float);
+        else FLT_LAUNCH(3, double);
+#undef FLT_LAUNCH
+    });
 }
 
 }  // extern "C"

@@ -105,3 +105,53 @@ def test_validation_errors_without_gpu(lib):
     assert L.lks_adjoint(C.byref(s), dummy, dummy, 1 << 30, dummy, 1 << 30, float("nan"), dummy,
                          None, None, None) == lib.EINVAL
     assert L.body_step(C.byref(s), dummy, dummy, dummy, None) == lib.EINVAL  # aliasing
+
+
+def test_filter_struct_layout_matches_header(lib, tmp_path):
+    fields = [f[0] for f in lib.LksFilter._fields_]
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "lks.h"', "int main(void){",
+           'printf("%zu\\n", sizeof(lks_filter_t));']
+    src += [f'printf("%zu\\n", offsetof(lks_filter_t, {f}));' for f in fields]
+    src.append("return 0;}")
+    c = tmp_path / "probe.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "probe"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(c)])
+    out = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    assert out[0] == C.sizeof(lib.LksFilter)
+    for f, off in zip(fields, out[1:]):
+        assert getattr(lib.LksFilter, f).offset == off, f
+
+
+def test_filter_validation_errors_without_gpu(lib):
+    """Bad filter parameters, missing design grids, null and overlapping arrays are
+    rejected before any HIP call."""
+    from paper_2601_18272_amd import api
+
+    L = lib.load()
+    pb = W.small2d()
+    s = api.problem_struct(pb)
+    ND = pb.nd[0] * pb.nd[1] * pb.nd[2]
+    a, b, c = C.c_void_p(1 << 20), C.c_void_p(2 << 20), C.c_void_p(3 << 20)
+    good = api.filter_struct(2.5, 8.0, 0.5)
+    for f in [api.filter_struct(0.0, 8.0, 0.5), api.filter_struct(9.0, 8.0, 0.5),
+              api.filter_struct(float("nan"), 8.0, 0.5), api.filter_struct(2.0, 0.0, 0.5),
+              api.filter_struct(2.0, float("inf"), 0.5), api.filter_struct(2.0, 8.0, 1.5),
+              api.filter_struct(2.0, 8.0, -0.1)]:
+        assert L.lks_design_filter(C.byref(s), C.byref(f), a, b, c, None) == lib.EINVAL
+        assert L.lks_design_filter_adjoint(C.byref(s), C.byref(f), a, b, c, None) == lib.EINVAL
+        assert L.lks_last_error()
+    s3 = api.problem_struct(W.small3d())
+    assert L.lks_design_filter(C.byref(s3), C.byref(api.filter_struct(5.0, 8.0, 0.5)), a, b, c,
+                               None) == lib.EINVAL  # floor(R) > 4 in 3D
+    assert L.lks_design_filter(C.byref(s), None, a, b, c, None) == lib.EINVAL
+    assert L.lks_design_filter(C.byref(s), C.byref(good), None, b, c, None) == lib.EINVAL
+    assert L.lks_design_filter_adjoint(C.byref(s), C.byref(good), a, b, None, None) == lib.EINVAL
+    nob = api.problem_struct(pb.replace(nd=(0, 0, 0)))
+    assert L.lks_design_filter(C.byref(nob), C.byref(good), a, b, c, None) == lib.EINVAL
+    # overlapping arrays (fp32: 4 bytes a design point, fp64 gradients: 8)
+    inside = C.c_void_p((1 << 20) + 4 * (ND - 1))
+    assert L.lks_design_filter(C.byref(s), C.byref(good), a, inside, c, None) == lib.EINVAL
+    assert L.lks_design_filter(C.byref(s), C.byref(good), a, b, b, None) == lib.EINVAL
+    assert L.lks_design_filter_adjoint(C.byref(s), C.byref(good), a, b, inside, None) == lib.EINVAL
+    assert L.lks_design_filter_adjoint(C.byref(s), C.byref(good), inside, b, a, None) == lib.EINVAL

@@ -1,0 +1,169 @@
+"""Parity of the design filter and projection (Sec. 3.2, Eqs. filter and projection) and
+of their reverse, through the C ABI, with the FP64 oracle.
+
+Tolerances. FP64: the GPU and the oracle differ only in summation order (and W_i taken
+from the whole table in the interior), so 1e-13 relative to the field's scale.
+FP32: the filtered field is a convex combination of at most n_tap values in [0, 1],
+summed in float: |error| <= (n_tap + 3) * 2^-24 (weights rounded once, the sum, the
+division); the projection multiplies it by at most beta / den (den = tanh(beta eta) +
+tanh(beta (1 - eta))) and adds the rounding of tanh. The reverse runs in FP64 on the
+FP32 gamma_tilde, so its error is that of t_i through d(1 - th^2) <= 2 beta |d gt|:
+|error in gb| <= 2 (2 beta^2 / den) tol_gt max|gbh| (the factor 2 bounds
+sum_i w_ij / W_i near the edges).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2601_18272_amd as lib
+
+    lib._lib.load()
+    return lib
+
+
+def problem(dim, nd):
+    return W.small2d(nd=nd) if dim == 2 else W.small3d(nd=nd)
+
+
+def n_tap(dim, R):
+    r = int(math.floor(R))
+    rng = range(-r, r + 1)
+    if dim == 2:
+        return sum(1 for x in rng for y in rng if math.hypot(x, y) <= R)
+    return sum(1 for x in rng for y in rng for z in rng if math.sqrt(x * x + y * y + z * z) <= R)
+
+
+def tolerances(dim, R, beta, eta, prec):
+    den = math.tanh(beta * eta) + math.tanh(beta * (1.0 - eta))
+    if prec == "fp64":
+        return 1e-13, 1e-13 * max(1.0, beta / den), None
+    tgt = (n_tap(dim, R) + 3) * 2.0 ** -24
+    tgh = beta / den * tgt + 4 * 2.0 ** -24
+    tgb = 2 * (2 * beta * beta / den) * tgt
+    return tgt, tgh, tgb
+
+
+CASES = [
+    # dim, nd, R, beta, eta
+    (2, (10, 8, 1), 2.5, 8.0, 0.5),            # one tile, ragged
+    (2, (75, 37, 1), 3.0, 1.0, 0.5),           # 3 x 3 tiles, ragged in x and y
+    (2, (64, 32, 1), 3.0, 32.0, 0.5),          # exact tiles, steepest beta
+    (2, (41, 50, 1), 1.5, 4.0, 0.3),           # small radius, eta off centre
+    (2, (70, 21, 1), 8.9, 16.0, 0.6),          # largest radius (floor 8), halo > tile in y
+    (2, (33, 17, 1), 0.7, 2.0, 0.5),           # R < 1: the filter is the identity
+    (2, (1, 1, 1), 2.0, 8.0, 0.5),             # a single design point
+    (3, (6, 5, 4), 1.8, 8.0, 0.5),
+    (3, (20, 11, 9), 2.2, 2.0, 0.5),           # 2 x 2 x 3 tiles, ragged
+    (3, (35, 17, 10), 3.0, 32.0, 0.5),
+    (3, (18, 10, 7), 4.9, 8.0, 0.4),           # largest radius (floor 4)
+    (3, (16, 8, 4), 3.0, 1.0, 0.5),            # exactly one tile
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_filter_forward_and_reverse(L, orc, case, prec):
+    dim, nd, R, beta, eta = CASES[case]
+    pb = problem(dim, nd)
+    ND = int(np.prod(nd))
+    g = W.raw_design(nd, 100 + case)
+    if prec == "fp32":
+        g = g.astype(np.float32).astype(np.float64)  # the GPU sees these values
+    gbh = W.cotangent(ND, 200 + case)
+    print(f"filter case {case} dim={dim} nd={nd} R={R} beta={beta} eta={eta} {prec}", flush=True)
+    gt_ref, gh_ref = orc.filter(dim, nd, R, beta, eta, g)
+    gb_ref = orc.filter_adjoint(dim, nd, R, beta, eta, gt_ref, gbh)
+    gt, gh = L.design_filter(pb, g, R, beta, eta, precision=prec)
+    gb = L.design_filter_adjoint(pb, gt, gbh, R, beta, eta, precision=prec)
+    gt, gh, gb = (v.cpu().numpy().astype(np.float64) for v in (gt, gh, gb))
+    tgt, tgh, tgb = tolerances(dim, R, beta, eta, prec)
+    assert np.abs(gt - gt_ref).max() <= tgt
+    assert np.abs(gh - gh_ref).max() <= tgh
+    scale = np.abs(gbh).max()
+    tol_gb = (1e-13 * scale * max(1.0, beta)) if prec == "fp64" else tgb * scale
+    assert np.abs(gb - gb_ref).max() <= tol_gb
+    if R < 1.0:
+        assert np.array_equal(gt, g if prec == "fp64" else g.astype(np.float32))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_filter_reverse_is_transpose(L, prec):
+    """<gbh, J v> == <J^T gbh, v> for the GPU pair itself, J the forward's Jacobian,
+    taken by a central difference of the FP64 forward along v (the forward is smooth)."""
+    dim, nd, R, beta, eta = 2, (45, 29, 1), 3.0, 4.0, 0.5
+    pb = problem(dim, nd)
+    g = W.raw_design(nd, 7)
+    v = W.cotangent(g.size, 8)
+    gbh = W.cotangent(g.size, 9)
+    h = 1e-6
+    _, ghp = L.design_filter(pb, g + h * v, R, beta, eta, precision="fp64")
+    _, ghm = L.design_filter(pb, g - h * v, R, beta, eta, precision="fp64")
+    jv = (ghp - ghm).cpu().numpy() / (2 * h)
+    gt, _ = L.design_filter(pb, g, R, beta, eta, precision=prec)
+    gb = L.design_filter_adjoint(pb, gt, gbh, R, beta, eta, precision=prec).cpu().numpy()
+    lhs, rhs = float(gbh @ jv), float(gb @ v)
+    assert abs(lhs - rhs) <= (1e-7 if prec == "fp64" else 1e-4) * (abs(lhs) + abs(rhs))
+
+
+FULL = {
+    "2d-256x256": (2, (256, 256, 1)),   # the 2D design grid of the 1024 x 512 channel
+    "3d-96^3": (3, (96, 96, 96)),       # the 3D design grid of the 256 x 128 x 128 duct
+}
+
+
+@pytest.mark.parametrize("name", sorted(FULL))
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_filter_full_size(L, orc, name, prec):
+    """Whole design grids of the benchmark workloads at R = 3, eta = 0.5 and a mid beta,
+    every element against the oracle (the oracle finishes them in about a second)."""
+    dim, nd = FULL[name]
+    R, beta, eta = W.FILTER_R, 8.0, W.FILTER_ETA
+    pb = problem(dim, nd)
+    g = W.raw_design(nd, 31)
+    if prec == "fp32":
+        g = g.astype(np.float32).astype(np.float64)
+    gbh = W.cotangent(g.size, 32)
+    print(f"filter full size {name} {prec}", flush=True)
+    gt_ref, gh_ref = orc.filter(dim, nd, R, beta, eta, g)
+    gb_ref = orc.filter_adjoint(dim, nd, R, beta, eta, gt_ref, gbh)
+    gt, gh = L.design_filter(pb, g, R, beta, eta, precision=prec)
+    gb = L.design_filter_adjoint(pb, gt, gbh, R, beta, eta, precision=prec)
+    gt, gh, gb = (v.cpu().numpy().astype(np.float64) for v in (gt, gh, gb))
+    tgt, tgh, tgb = tolerances(dim, R, beta, eta, prec)
+    assert np.abs(gt - gt_ref).max() <= tgt
+    assert np.abs(gh - gh_ref).max() <= tgh
+    scale = np.abs(gbh).max()
+    tol_gb = (1e-13 * scale * beta) if prec == "fp64" else tgb * scale
+    assert np.abs(gb - gb_ref).max() <= tol_gb
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_filtered_design_gradient_chain(L, orc, dim):
+    """gamma -> filter -> projection -> lks_forward -> J and back: the library's chain
+    (lks_design_filter, lks_forward, lks_adjoint, lks_design_filter_adjoint) against the
+    oracle's, FP64."""
+    pb = W.small2d(ckpt_every=5) if dim == 2 else W.small3d(ckpt_every=4)
+    R, beta, eta = 2.0, 4.0, 0.5
+    g = W.raw_design(pb.nd, 41)
+    s0, b0 = W.initial_state(pb), W.initial_body(pb)
+    print(f"filtered gradient chain dim={dim}", flush=True)
+    gt_ref, gh_ref = orc.filter(dim, pb.nd, R, beta, eta, g)
+    J_ref, grad_ref = orc.gradient(pb, gh_ref, s0, b0)
+    gb_ref = orc.filter_adjoint(dim, pb.nd, R, beta, eta, gt_ref, grad_ref)
+    gt, gh = L.design_filter(pb, g, R, beta, eta, precision="fp64")
+    _, _, J, B = L.forward(pb, gh, s0, b0, precision="fp64", store_ckpt=True)
+    grad = L.adjoint(pb, gh, B, precision="fp64")
+    gb = L.design_filter_adjoint(pb, gt, grad, R, beta, eta, precision="fp64").cpu().numpy()
+    assert abs(J.item() - J_ref) <= 1e-9 * abs(J_ref) + 1e-15
+    assert np.linalg.norm(gb - gb_ref) <= 1e-8 * np.linalg.norm(gb_ref)

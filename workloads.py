@@ -90,6 +90,25 @@ def smoothed_design(nd, seed: int) -> np.ndarray:
     return (acc / cnt).reshape(-1).astype(np.float64)
 
 
+def raw_design(nd, seed: int) -> np.ndarray:
+    """gamma ~ U[0,1) from default_rng(seed): the design variable before the filter.
+    Flat array, first index fastest."""
+    return np.random.default_rng(seed).random(int(np.prod(nd))).astype(np.float64)
+
+
+def cotangent(n: int, seed: int) -> np.ndarray:
+    """Standard normal sensitivities (inputs of a reverse-mode step)."""
+    return np.random.default_rng(seed).standard_normal(int(n))
+
+
+# Design processing (Sec. 3.2). The paper's continuation raises beta through 1, 2, 4,
+# ..., 32 (the parameter lists of Sec. 4); it states neither the filter radius nor eta:
+# R = 3 design spacings and eta = 0.5 are readings.
+FILTER_BETAS = (1.0, 2.0, 4.0, 8.0, 16.0, 32.0)
+FILTER_R = 3.0
+FILTER_ETA = 0.5
+
+
 def design(pb: Problem) -> np.ndarray:
     return smoothed_design(pb.nd, pb.seed)
 
