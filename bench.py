@@ -27,6 +27,7 @@ import numpy as np  # noqa: E402
 METRIC = "fwd+adjoint MLUPS, % HBM roofline; FP32 vs FP64 at stated rel. error"
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_TFLOPS = 157.3
+FP64_VECTOR_TFLOPS = 78.6
 
 DESCRIPTIONS = {
     "config1": "2D D2Q9 128x64 channel, Re 20, body free in x (M 50), design 32x32, 1000 steps",
@@ -180,6 +181,61 @@ def roofline_sweep(args):
     print(json.dumps({"sweep": "copy", "elementwise_copy_1GiB_GBs": round(copy_bandwidth(), 1)}), flush=True)
 
 
+def ball_taps(dim, R):
+    """Design points within distance R of a point (the taps of the density filter)."""
+    r = int(np.floor(R))
+    ax = np.arange(-r, r + 1)
+    if dim == 2:
+        d2 = ax[:, None] ** 2 + ax[None, :] ** 2
+    else:
+        d2 = ax[:, None, None] ** 2 + ax[None, :, None] ** 2 + ax[None, None, :] ** 2
+    return int((np.sqrt(d2) <= R).sum())
+
+
+def filter_measure(pb, reps=20):
+    """Density filter + projection and its reverse on the workload's design grid (FP32
+    forward, FP64 reverse), live kernel durations from HIP events (LKS_FLAG_PROFILE)."""
+    import torch
+
+    import paper_2601_18272_amd as lks
+    import workloads as W
+    from paper_2601_18272_amd import _lib
+
+    R, beta, eta = W.FILTER_R, 8.0, W.FILTER_ETA
+    nd = pb.nd
+    ND = int(np.prod(nd))
+    g = torch.tensor(W.raw_design(nd, pb.seed), dtype=torch.float32, device="cuda")
+    gbh = torch.tensor(W.cotangent(ND, pb.seed + 1), dtype=torch.float64, device="cuda")
+    work = torch.empty(lks.filter_workspace_bytes(pb), dtype=torch.uint8, device="cuda")
+    for _ in range(3):
+        gt, gh = lks.design_filter(pb, g, R, beta, eta, "fp32")
+        lks.design_filter_adjoint(pb, gt, gbh, R, beta, eta, "fp32", work=work)
+    torch.cuda.synchronize()
+    _lib.profile_reset()
+    for _ in range(reps):
+        lks.design_filter(pb, g, R, beta, eta, "fp32", flags=_lib.FLAG_PROFILE)
+        lks.design_filter_adjoint(pb, gt, gbh, R, beta, eta, "fp32", flags=_lib.FLAG_PROFILE, work=work)
+    p = _lib.profile_read()
+    _lib.profile_reset()
+    taps = ball_taps(pb.dim, R)
+    fwd_s = p["filter"][0] / p["filter"][1] / 1e3
+    adj_s = p["filter_adj"][0] / p["filter_adj"][1] / 1e3
+    flops = 2.0 * taps * ND  # one multiply-add per tap and point
+    return {
+        "design": list(nd[:pb.dim]), "radius": R, "beta": beta, "eta": eta, "taps": taps,
+        "forward": {"kernel": "k_filter_tile (FP32)", "avg_launch_us": round(fwd_s * 1e6, 3),
+                    "samples": p["filter"][1], "bound": "alu",
+                    "achieved_TFLOPs": round(flops / fwd_s / 1e12, 3), "peak_TFLOPs": FP32_VECTOR_TFLOPS,
+                    "frac": round(flops / fwd_s / 1e12 / FP32_VECTOR_TFLOPS, 4),
+                    "hbm_GBs": round(3 * 4 * ND / fwd_s / 1e9, 1)},
+        "reverse": {"kernels": "k_filter_scale + k_filter_tile (FP64), first begin to last end",
+                    "avg_us": round(adj_s * 1e6, 3), "samples": p["filter_adj"][1], "bound": "alu",
+                    "achieved_TFLOPs": round(flops / adj_s / 1e12, 3), "peak_TFLOPs": FP64_VECTOR_TFLOPS,
+                    "frac": round(flops / adj_s / 1e12 / FP64_VECTOR_TFLOPS, 4),
+                    "hbm_GBs": round((4 + 8 + 8) * ND / adj_s / 1e9, 1)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -318,6 +374,8 @@ def main():
     tf = time.perf_counter() - t1
     extra["forward_only"] = {"ms": round(tf * 1e3, 2), "MLUPS": round(pb.N * pb.n_steps / tf / 1e6, 2)}
     extra["copy_GBs_elementwise_1GiB"] = round(copy_bandwidth(), 1)
+    extra["design_filter"] = filter_measure(pb)
+    print("# design filter done", file=sys.stderr, flush=True)
 
     if not args.no_fp64:
         bufs64 = lks.Buffers(pb, "fp64", adjoint=True)

@@ -175,19 +175,26 @@ typedef struct lks_filter {
 int lks_design_filter(const lks_problem_t *P, const lks_filter_t *F, const void *gamma, void *gamma_tilde,
                       void *gamma_hat, void *stream);
 
+/* Bytes of scratch space for lks_design_filter_adjoint: ND doubles (0 without a design grid). */
+size_t lks_filter_workspace_bytes(const lks_problem_t *P);
+
 /*
  * lks_design_filter_adjoint -- reverse of lks_design_filter, in FP64: a sensitivity with
  * respect to gamma_hat is taken through the derivative of Eq. projection at gamma_tilde
  * and the transpose of Eq. filter:
- *   dJ_dgamma_j = sum_i w_ij dJ_dgamma_hat_i (d gamma_hat / d gamma_tilde)_i / sum_k w_ik.
+ *   t_i         = dJ_dgamma_hat_i (d gamma_hat / d gamma_tilde)_i / sum_k w_ik   (into work)
+ *   dJ_dgamma_j = sum_i w_ij t_i
  *   gamma_tilde   [ND] T, the filtered field of the forward call (read only)
  *   dJ_dgamma_hat [ND] double (read only), e.g. the grad of lks_adjoint
- *   dJ_dgamma     [ND] double, out; must not overlap the two inputs
- * Stream and LKS_FLAG_PROFILE (kernel LKS_K_FILTER_ADJ) as for lks_design_filter.
- * Errors: LKS_EINVAL, LKS_EHIP.
+ *   work          scratch of lks_filter_workspace_bytes(P) bytes
+ *   dJ_dgamma     [ND] double, out
+ * The four arrays must not overlap. Stream and LKS_FLAG_PROFILE (kernel
+ * LKS_K_FILTER_ADJ, both launches) as for lks_design_filter.
+ * Errors: LKS_EINVAL, LKS_ENOSPACE, LKS_EHIP.
  */
 int lks_design_filter_adjoint(const lks_problem_t *P, const lks_filter_t *F, const void *gamma_tilde,
-                              const double *dJ_dgamma_hat, double *dJ_dgamma, void *stream);
+                              const double *dJ_dgamma_hat, void *work, size_t work_bytes, double *dJ_dgamma,
+                              void *stream);
 
 /* Message of the last error on this thread ("" if none). */
 const char *lks_last_error(void);
@@ -222,7 +229,7 @@ enum {
     LKS_K_GATHER_SPAN = 11,     /* LKS_K_GATHER, the kernel's own span (no dispatch) */
     LKS_K_ADJ_GATHER_SPAN = 12, /* LKS_K_ADJ_GATHER, the kernel's own span */
     LKS_K_FILTER = 13,          /* lks_design_filter */
-    LKS_K_FILTER_ADJ = 14,      /* lks_design_filter_adjoint */
+    LKS_K_FILTER_ADJ = 14,      /* lks_design_filter_adjoint (its two launches) */
     LKS_K_COUNT = 15
 };
 int lks_profile_read(int kernel, double *total_ms, long long *samples);

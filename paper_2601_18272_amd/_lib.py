@@ -21,7 +21,8 @@ OK, EINVAL, ENOSPACE, EUNSTABLE, EDIVERGED, EHIP = 0, -1, -2, -3, -4, -5
 
 EXPORTS = ("lks_state_elems", "lks_checkpoint_bytes", "lks_workspace_bytes", "lks_forward",
            "lks_adjoint", "map_design", "body_step", "lks_last_error", "lks_profile_read",
-           "lks_profile_reset", "lks_design_filter", "lks_design_filter_adjoint")
+           "lks_profile_reset", "lks_design_filter", "lks_design_filter_adjoint",
+           "lks_filter_workspace_bytes")
 
 
 class LksProblem(C.Structure):
@@ -89,8 +90,10 @@ def load():
     fp = C.POINTER(LksFilter)
     L.lks_design_filter.argtypes = [pp, fp, vp, vp, vp, vp]
     L.lks_design_filter.restype = C.c_int
-    L.lks_design_filter_adjoint.argtypes = [pp, fp, vp, dp, dp, vp]
+    L.lks_design_filter_adjoint.argtypes = [pp, fp, vp, dp, vp, C.c_size_t, dp, vp]
     L.lks_design_filter_adjoint.restype = C.c_int
+    L.lks_filter_workspace_bytes.argtypes = [pp]
+    L.lks_filter_workspace_bytes.restype = C.c_size_t
     L.lks_last_error.argtypes = []
     L.lks_last_error.restype = C.c_char_p
     L.lks_profile_read.argtypes = [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]

@@ -168,17 +168,28 @@ def design_filter(pb, gamma, radius, beta, eta=0.5, precision="fp32", flags: int
     return gt, gh
 
 
+def filter_workspace_bytes(pb) -> int:
+    return int(_lib.load().lks_filter_workspace_bytes(C.byref(problem_struct(pb))))
+
+
 def design_filter_adjoint(pb, gamma_tilde, dJ_dgamma_hat, radius, beta, eta=0.5, precision="fp32",
-                          flags: int = 0):
-    """dJ/dgamma (FP64) from dJ/dgamma_hat through the projection and the filter."""
+                          flags: int = 0, work=None):
+    """dJ/dgamma (FP64) from dJ/dgamma_hat through the projection and the filter. `work`
+    (optional) is a uint8 device tensor of filter_workspace_bytes(pb) bytes."""
     L = _lib.load()
     dt = DTYPES[precision]
     s = problem_struct(pb, precision, flags)
     gt = _dev(gamma_tilde, dt).reshape(-1)
     gbh = _dev(dJ_dgamma_hat, torch.float64).reshape(-1)
     gb = torch.empty_like(gbh)
+    if work is None:
+        nbytes = int(L.lks_filter_workspace_bytes(C.byref(s)))
+        if nbytes == 0:
+            raise LksError(_lib.EINVAL, L.lks_last_error().decode())
+        work = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     f = filter_struct(radius, beta, eta)
-    _lib.check(L.lks_design_filter_adjoint(C.byref(s), C.byref(f), _p(gt), _p(gbh), _p(gb), _stream()))
+    _lib.check(L.lks_design_filter_adjoint(C.byref(s), C.byref(f), _p(gt), _p(gbh), _p(work), work.numel(),
+                                           _p(gb), _stream()))
     return gb
 
 

@@ -844,7 +844,7 @@ int filter_ctx(const lks_problem_t *P, const lks_filter_t *F, Ctx &c, FltArgs &a
     if (rc) return rc;
     if (!c.has_body) return fail(LKS_EINVAL, "the design filter needs a design grid");
     if (!F) return fail(LKS_EINVAL, "null filter parameters");
-    const int rmax = c.dim == 2 ? Flt<2>::RMAX : Flt<3>::RMAX;
+    const int rmax = c.dim == 2 ? FltShape<2, float>::RMAX : FltShape<3, float>::RMAX;
     if (!(F->radius > 0.0) || !(F->radius < rmax + 1.0))
         return fail(LKS_EINVAL, "filter radius %g outside (0, %d)", F->radius, rmax + 1);
     if (!(F->beta > 0.0) || !std::isfinite(F->beta)) return fail(LKS_EINVAL, "projection beta must be > 0");
@@ -857,22 +857,80 @@ int filter_ctx(const lks_problem_t *P, const lks_filter_t *F, Ctx &c, FltArgs &a
     return LKS_OK;
 }
 
-// One launch over the design tiles, timed under `id` with LKS_FLAG_PROFILE.
-template <typename L> int filter_run(const Ctx &c, bool prof, int id, hipStream_t st, L &&launch) {
-    const int tx = c.dim == 2 ? Flt<2>::TX : Flt<3>::TX, ty = c.dim == 2 ? Flt<2>::TY : Flt<3>::TY,
-              tz = c.dim == 2 ? Flt<2>::TZ : Flt<3>::TZ;
-    const dim3 grid(blocks(c.D.nd[0], tx), blocks(c.D.nd[1], ty), blocks(c.D.nd[2], tz));
-    const dim3 blk(tx * ty * tz);
+// Launch configuration of the tile kernel for FltShape<DIM, A>.
+template <int DIM, typename A> dim3 filter_grid(const Ctx &c) {
+    using F = FltShape<DIM, A>;
+    return dim3(blocks(c.D.nd[0], F::TX), blocks(c.D.nd[1], F::TY), blocks(c.D.nd[2], F::TZ));
+}
+
+// Runs `launch(e0, e1)` (the unit's first launch takes e0, its last e1), timed under `id`
+// with LKS_FLAG_PROFILE.
+template <typename L> int filter_timed(bool prof, int id, hipStream_t st, L &&launch) {
     Prof pf;
     pf.on = pf.sample = prof;
     pf.st = st;
-    pf.run(id, [&](hipEvent_t e0, hipEvent_t e1) { launch(grid, blk, e0, e1); });
+    pf.run(id, launch);
     HIP_TRY(hipGetLastError());
     if (pf.on) {
         HIP_TRY(hipStreamSynchronize(st));
         pf.finish();
     }
     return LKS_OK;
+}
+
+// Calls f(std::integral_constant<int, r>) for the run-time radius r in [0, RM].
+template <int RM, typename Fn> int with_radius(int r, Fn &&f) {
+    if constexpr (RM >= 0) {
+        if (r == RM) return f(std::integral_constant<int, RM>{});
+        return with_radius<RM - 1>(r, f);
+    } else {
+        return fail(LKS_EINVAL, "filter radius out of range");
+    }
+}
+
+// Calls f(std::integral_constant<int, K2>) for the smallest compiled tap set of radius RR
+// that holds every offset with |d|^2 <= floor(R^2).
+template <int DIM, int RR, typename Fn> int with_tapset(double R, Fn &&f) {
+    const int k2 = (int)std::floor(R * R);
+    if constexpr (DIM == 3 && RR > 0) {
+        if (k2 <= FLT_K2<RR, 0>) return f(std::integral_constant<int, FLT_K2<RR, 0>>{});
+        if (k2 <= FLT_K2<RR, 1>) return f(std::integral_constant<int, FLT_K2<RR, 1>>{});
+    }
+    (void)k2;
+    return f(std::integral_constant<int, FLT_K2<RR, 2>>{});
+}
+
+template <int DIM, typename T>
+int filter_fwd(const Ctx &c, const FltArgs &a, bool prof, hipStream_t st, const T *g, T *gt, T *gh) {
+    return with_radius<FltShape<DIM, T>::RMAX>(a.r, [&](auto rc) {
+        constexpr int RR = decltype(rc)::value;
+        return with_tapset<DIM, RR>(a.R, [&](auto kc) {
+            constexpr int K2 = decltype(kc)::value;
+            return filter_timed(prof, LKS_K_FILTER, st, [&](hipEvent_t e0, hipEvent_t e1) {
+                hipExtLaunchKernelGGL((k_filter_tile<DIM, T, RR, K2, true>), filter_grid<DIM, T>(c),
+                                      dim3(FltShape<DIM, T>::NT), 0, st, e0, e1, 0, a, g, gt, gh);
+            });
+        });
+    });
+}
+
+template <int DIM, typename T>
+int filter_adj(const Ctx &c, const FltArgs &a, bool prof, hipStream_t st, const T *gt, const double *gbh,
+               double *t, double *gb) {
+    return with_radius<FltShape<DIM, double>::RMAX>(a.r, [&](auto rc) {
+        constexpr int RR = decltype(rc)::value;
+        return with_tapset<DIM, RR>(a.R, [&](auto kc) {
+            constexpr int K2 = decltype(kc)::value;
+            return filter_timed(prof, LKS_K_FILTER_ADJ, st, [&](hipEvent_t e0, hipEvent_t e1) {
+                const long long nd = c.D.ND;
+                hipExtLaunchKernelGGL((k_filter_scale<DIM, T, RR>), dim3(blocks(nd, FLT_SCALE_NT * FLT_SCALE_PT)),
+                                      dim3(FLT_SCALE_NT), 0, st, e0, nullptr, 0, a, nd, gt, gbh, t);
+                hipExtLaunchKernelGGL((k_filter_tile<DIM, double, RR, K2, false>), filter_grid<DIM, double>(c),
+                                      dim3(FltShape<DIM, double>::NT), 0, st, nullptr, e1, 0, a,
+                                      (const double *)t, gb, (double *)nullptr);
+            });
+        });
+    });
 }
 
 }  // namespace
@@ -1008,40 +1066,49 @@ int lks_design_filter(const lks_problem_t *P, const lks_filter_t *F, const void 
         overlap(gamma_tilde, nb, gamma_hat, nb))
         return fail(LKS_EINVAL, "gamma, gamma_tilde and gamma_hat must not overlap");
     hipStream_t st = (hipStream_t)stream;
-    return filter_run(c, (P->flags & LKS_FLAG_PROFILE) != 0, LKS_K_FILTER, st, [&](dim3 grid, dim3 blk, hipEvent_t e0, hipEvent_t e1) {
-#define FLT_LAUNCH(D_, T_)                                                                               \
-    hipExtLaunchKernelGGL((k_filter_fwd<D_, T_>), grid, blk, 0, st, e0, e1, 0, a, (const T_ *)gamma, \
-                          (T_ *)gamma_tilde, (T_ *)gamma_hat)
-        if (c.dim == 2 && c.prec == LKS_FP32) FLT_LAUNCH(2, float);
-        else if (c.dim == 2) FLT_LAUNCH(2, double);
-        else if (c.prec == LKS_FP32) FLT_LAUNCH(3, float);
-        else FLT_LAUNCH(3, double);
-#undef FLT_LAUNCH
-    });
+    const bool prof = (P->flags & LKS_FLAG_PROFILE) != 0;
+    if (c.dim == 2 && c.prec == LKS_FP32)
+        return filter_fwd<2>(c, a, prof, st, (const float *)gamma, (float *)gamma_tilde, (float *)gamma_hat);
+    if (c.dim == 2)
+        return filter_fwd<2>(c, a, prof, st, (const double *)gamma, (double *)gamma_tilde, (double *)gamma_hat);
+    if (c.prec == LKS_FP32)
+        return filter_fwd<3>(c, a, prof, st, (const float *)gamma, (float *)gamma_tilde, (float *)gamma_hat);
+    return filter_fwd<3>(c, a, prof, st, (const double *)gamma, (double *)gamma_tilde, (double *)gamma_hat);
+}
+
+size_t lks_filter_workspace_bytes(const lks_problem_t *P) {
+    Ctx c;
+    if (make_ctx(P, c) != LKS_OK) return 0;
+    if (!c.has_body) {
+        fail(LKS_EINVAL, "the design filter needs a design grid");
+        return 0;
+    }
+    return up((size_t)c.D.ND * sizeof(double));
 }
 
 int lks_design_filter_adjoint(const lks_problem_t *P, const lks_filter_t *F, const void *gamma_tilde,
-                              const double *dJ_dgamma_hat, double *dJ_dgamma, void *stream) {
+                              const double *dJ_dgamma_hat, void *work, size_t work_bytes, double *dJ_dgamma,
+                              void *stream) {
     g_err.clear();
     Ctx c;
     FltArgs a;
     int rc = filter_ctx(P, F, c, a);
     if (rc) return rc;
-    if (!gamma_tilde || !dJ_dgamma_hat || !dJ_dgamma) return fail(LKS_EINVAL, "null pointer argument");
+    if (!gamma_tilde || !dJ_dgamma_hat || !work || !dJ_dgamma) return fail(LKS_EINVAL, "null pointer argument");
     const size_t nt = (size_t)c.D.ND * c.elt, nd = (size_t)c.D.ND * sizeof(double);
-    if (overlap(dJ_dgamma, nd, gamma_tilde, nt) || overlap(dJ_dgamma, nd, dJ_dgamma_hat, nd))
-        return fail(LKS_EINVAL, "dJ_dgamma must not overlap gamma_tilde or dJ_dgamma_hat");
+    if (work_bytes < nd) return fail(LKS_ENOSPACE, "work buffer too small");
+    if (overlap(dJ_dgamma, nd, gamma_tilde, nt) || overlap(dJ_dgamma, nd, dJ_dgamma_hat, nd) ||
+        overlap(work, nd, gamma_tilde, nt) || overlap(work, nd, dJ_dgamma_hat, nd) || overlap(work, nd, dJ_dgamma, nd))
+        return fail(LKS_EINVAL, "dJ_dgamma, work, gamma_tilde and dJ_dgamma_hat must not overlap");
     hipStream_t st = (hipStream_t)stream;
-    return filter_run(c, (P->flags & LKS_FLAG_PROFILE) != 0, LKS_K_FILTER_ADJ, st, [&](dim3 grid, dim3 blk, hipEvent_t e0, hipEvent_t e1) {
-#define FLT_LAUNCH(D_, T_)                                                                                   \
-    hipExtLaunchKernelGGL((k_filter_adj<D_, T_>), grid, blk, 0, st, e0, e1, 0, a, (const T_ *)gamma_tilde, \
-                          dJ_dgamma_hat, dJ_dgamma)
-        if (c.dim == 2 && c.prec == LKS_FP32) FLT_LAUNCH(2, float);
-        else if (c.dim == 2) FLT_LAUNCH(2, double);
-        else if (c.prec == LKS_FP32) FLT_LAUNCH(3, float);
-        else FLT_LAUNCH(3, double);
-#undef FLT_LAUNCH
-    });
+    const bool prof = (P->flags & LKS_FLAG_PROFILE) != 0;
+    double *t = (double *)work;
+    if (c.dim == 2 && c.prec == LKS_FP32)
+        return filter_adj<2>(c, a, prof, st, (const float *)gamma_tilde, dJ_dgamma_hat, t, dJ_dgamma);
+    if (c.dim == 2) return filter_adj<2>(c, a, prof, st, (const double *)gamma_tilde, dJ_dgamma_hat, t, dJ_dgamma);
+    if (c.prec == LKS_FP32)
+        return filter_adj<3>(c, a, prof, st, (const float *)gamma_tilde, dJ_dgamma_hat, t, dJ_dgamma);
+    return filter_adj<3>(c, a, prof, st, (const double *)gamma_tilde, dJ_dgamma_hat, t, dJ_dgamma);
 }
 
 }  // extern "C"

@@ -132,26 +132,31 @@ def test_filter_validation_errors_without_gpu(lib):
     pb = W.small2d()
     s = api.problem_struct(pb)
     ND = pb.nd[0] * pb.nd[1] * pb.nd[2]
-    a, b, c = C.c_void_p(1 << 20), C.c_void_p(2 << 20), C.c_void_p(3 << 20)
+    a, b, c, d = C.c_void_p(1 << 20), C.c_void_p(2 << 20), C.c_void_p(3 << 20), C.c_void_p(4 << 20)
     good = api.filter_struct(2.5, 8.0, 0.5)
     for f in [api.filter_struct(0.0, 8.0, 0.5), api.filter_struct(9.0, 8.0, 0.5),
               api.filter_struct(float("nan"), 8.0, 0.5), api.filter_struct(2.0, 0.0, 0.5),
               api.filter_struct(2.0, float("inf"), 0.5), api.filter_struct(2.0, 8.0, 1.5),
               api.filter_struct(2.0, 8.0, -0.1)]:
         assert L.lks_design_filter(C.byref(s), C.byref(f), a, b, c, None) == lib.EINVAL
-        assert L.lks_design_filter_adjoint(C.byref(s), C.byref(f), a, b, c, None) == lib.EINVAL
+        assert L.lks_design_filter_adjoint(C.byref(s), C.byref(f), a, b, d, 1 << 20, c, None) == lib.EINVAL
         assert L.lks_last_error()
+    nob = api.problem_struct(pb.replace(nd=(0, 0, 0)))
+    assert L.lks_design_filter(C.byref(nob), C.byref(good), a, b, c, None) == lib.EINVAL
     s3 = api.problem_struct(W.small3d())
     assert L.lks_design_filter(C.byref(s3), C.byref(api.filter_struct(5.0, 8.0, 0.5)), a, b, c,
                                None) == lib.EINVAL  # floor(R) > 4 in 3D
     assert L.lks_design_filter(C.byref(s), None, a, b, c, None) == lib.EINVAL
     assert L.lks_design_filter(C.byref(s), C.byref(good), None, b, c, None) == lib.EINVAL
-    assert L.lks_design_filter_adjoint(C.byref(s), C.byref(good), a, b, None, None) == lib.EINVAL
-    nob = api.problem_struct(pb.replace(nd=(0, 0, 0)))
-    assert L.lks_design_filter(C.byref(nob), C.byref(good), a, b, c, None) == lib.EINVAL
+    assert L.lks_design_filter_adjoint(C.byref(s), C.byref(good), a, b, d, 1 << 20, None, None) == lib.EINVAL
+    assert L.lks_design_filter_adjoint(C.byref(s), C.byref(good), a, b, None, 1 << 20, c, None) == lib.EINVAL
+    assert L.lks_design_filter_adjoint(C.byref(s), C.byref(good), a, b, d, 8 * ND - 1, c, None) == lib.ENOSPACE
+    assert L.lks_filter_workspace_bytes(C.byref(s)) >= 8 * ND
+    assert L.lks_filter_workspace_bytes(C.byref(nob)) == 0
     # overlapping arrays (fp32: 4 bytes a design point, fp64 gradients: 8)
     inside = C.c_void_p((1 << 20) + 4 * (ND - 1))
     assert L.lks_design_filter(C.byref(s), C.byref(good), a, inside, c, None) == lib.EINVAL
     assert L.lks_design_filter(C.byref(s), C.byref(good), a, b, b, None) == lib.EINVAL
-    assert L.lks_design_filter_adjoint(C.byref(s), C.byref(good), a, b, inside, None) == lib.EINVAL
-    assert L.lks_design_filter_adjoint(C.byref(s), C.byref(good), inside, b, a, None) == lib.EINVAL
+    assert L.lks_design_filter_adjoint(C.byref(s), C.byref(good), a, b, d, 1 << 20, inside, None) == lib.EINVAL
+    assert L.lks_design_filter_adjoint(C.byref(s), C.byref(good), inside, b, d, 1 << 20, a, None) == lib.EINVAL
+    assert L.lks_design_filter_adjoint(C.byref(s), C.byref(good), a, c, inside, 1 << 20, d, None) == lib.EINVAL

@@ -5,7 +5,8 @@ Tolerances. FP64: the GPU and the oracle differ only in summation order (and W_i
 from the whole table in the interior), so 1e-13 relative to the field's scale.
 FP32: the filtered field is a convex combination of at most n_tap values in [0, 1],
 summed in float: |error| <= (n_tap + 3) * 2^-24 (weights rounded once, the sum, the
-division); the projection multiplies it by at most beta / den (den = tanh(beta eta) +
+division). The tap sets compiled per radius cover every R (R^2 between r^2, r^2 + r and
+r^2 + 2r selects the set), and the cases below use each of them. The projection multiplies it by at most beta / den (den = tanh(beta eta) +
 tanh(beta (1 - eta))) and adds the rounding of tanh. The reverse runs in FP64 on the
 FP32 gamma_tilde, so its error is that of t_i through d(1 - th^2) <= 2 beta |d gt|:
 |error in gb| <= 2 (2 beta^2 / den) tol_gt max|gbh| (the factor 2 bounds
@@ -68,6 +69,9 @@ CASES = [
     (3, (35, 17, 10), 3.0, 32.0, 0.5),
     (3, (18, 10, 7), 4.9, 8.0, 0.4),           # largest radius (floor 4)
     (3, (16, 8, 4), 3.0, 1.0, 0.5),            # exactly one tile
+    (3, (23, 13, 9), 3.5, 8.0, 0.5),           # middle tap set of r = 3 (|d|^2 <= 12)
+    (3, (15, 9, 11), 2.3, 4.0, 0.5),           # middle tap set of r = 2 (|d|^2 <= 6)
+    (3, (40, 9, 5), 4.0, 16.0, 0.5),           # smallest tap set of r = 4 (the ball of R = 4)
 ]
 
 
