@@ -66,7 +66,7 @@ def lib():
         pp = C.POINTER(OrcProblem)
         L.orc_step.argtypes = [pp, dp, dp, dp, dp, dp]
         L.orc_forward.argtypes = [pp, dp, dp, dp, dp, dp]
-        L.orc_gradient.argtypes = [pp, dp, dp, dp, C.c_double, dp, dp, dp, dp]
+        L.orc_gradient.argtypes = [pp, dp, dp, dp, C.c_double, dp, dp, dp, dp, dp, dp]
         L.orc_map_design.argtypes = [pp, dp, dp, dp, dp]
         L.orc_interp.argtypes = [pp, dp, dp, dp]
         L.orc_force.argtypes = [pp, dp, dp, dp, dp]
@@ -140,16 +140,23 @@ def forward(pb, gamma, state, body, traj=False):
     return (st, bd, J.value, tr) if traj else (st, bd, J.value)
 
 
-def gradient(pb, gamma, state0, body0, seed=1.0, with_initial=False):
-    """Exact discrete adjoint. Returns (J, grad[, dstate0, dbody0])."""
+def gradient(pb, gamma, state0, body0, seed=1.0, with_initial=False, dstate_T=None, dbody_T=None):
+    """Exact discrete adjoint of seed * J + <dstate_T, state(N_t)> + <dbody_T, body(N_t)>
+    (the terminal cotangents are optional). Returns (J, grad[, dstate0, dbody0])."""
     s = problem_struct(pb)
     g = _f64(gamma)
     grad = np.zeros_like(g)
     J = C.c_double(0.0)
     ds = np.zeros_like(_f64(state0)) if with_initial else None
     db = np.zeros(12) if with_initial else None
+    sT = _f64(dstate_T) if dstate_T is not None else None
+    bT = _f64(dbody_T) if dbody_T is not None else None
+    if bT is not None and bT.size < 8:
+        raise ValueError("dbody_T needs at least 8 entries")
+    if sT is not None and sT.size != _f64(state0).size:
+        raise ValueError("dstate_T must have the size of a state")
     _check(lib().orc_gradient(C.byref(s), _p(g), _p(_f64(state0)), _p(_f64(body0)),
-                              float(seed), _p(grad), C.byref(J), _p(ds), _p(db)),
+                              float(seed), _p(sT), _p(bT), _p(grad), C.byref(J), _p(ds), _p(db)),
            "orc_gradient")
     return (J.value, grad, ds, db) if with_initial else (J.value, grad)
 

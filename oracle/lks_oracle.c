@@ -901,8 +901,8 @@ int orc_forward(const orc_problem *P, const double *gamma, double *state, double
 }
 
 int orc_gradient(const orc_problem *P, const double *gamma, const double *state0,
-                 const double *body0, double seed, double *grad, double *J,
-                 double *dstate0, double *dbody0)
+                 const double *body0, double seed, const double *dstate_T, const double *dbody_T,
+                 double *grad, double *J, double *dstate0, double *dbody0)
 {
     ctx_t C;
     if (ctx_init(&C, P) || !state0 || !body0 || !gamma || !grad || P->n_steps < 0) return -1;
@@ -929,10 +929,14 @@ int orc_gradient(const orc_problem *P, const double *gamma, const double *state0
         step_fwd(&C, kr, states + S * (t - 1), bodies + 12 * (t - 1), states + S * t,
                  bodies + 12 * t, &W);
     if (J) *J = objective_value(&C, bodies, bodies + 12 * NT);
-    /* reverse */
+    /* reverse, from the terminal adjoint values: seed on the objective's coordinate plus
+       the given cotangents of the final state and body (Sec. 3.4) */
     double Bb[12];
     memset(Bb, 0, sizeof Bb);
     Bb[P->objective == ORC_OBJ_ANGLE ? 6 : P->objective] = seed;
+    if (dbody_T)
+        for (int j = 0; j < 8; j++) Bb[j] += dbody_T[j];
+    if (dstate_T) memcpy(sb, dstate_T, sizeof(double) * S);
     for (int t = NT; t >= 1; t--)
         step_rev(&C, kr, states + S * (t - 1), bodies + 12 * (t - 1), sb, Bb, krb, &W, scratch);
     for (long m = 0; m < C.ND; m++) grad[m] = krb[m] * dkappa_of(P, gamma[m]);

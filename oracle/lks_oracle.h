@@ -56,12 +56,15 @@ int orc_step(const orc_problem *P, const double *gamma, const double *s_in,
 int orc_forward(const orc_problem *P, const double *gamma, double *state, double *body,
                 double *traj, double *J);
 
-/* Forward run plus the exact reverse-mode (discrete adjoint) sweep. grad receives
- * seed * dJ/dgamma (N_D doubles). dstate0 ((d+1)*N) and dbody0 (12) optionally
- * receive seed * dJ/d(initial state) and seed * dJ/d(initial body state). */
+/* Forward run plus the exact reverse-mode (discrete adjoint) sweep of
+ *   L = seed * J + <dstate_T, state(n_steps)> + <dbody_T[0..7], body(n_steps)[0..7]>
+ * (dstate_T, dbody_T optional, NULL = zero: the terminal adjoint values, which the
+ * periodic problem approximation of Sec. 3.4 takes from the previous optimization
+ * iteration). grad receives dL/dgamma (N_D doubles); dstate0 ((d+1)*N) and dbody0 (12)
+ * optionally receive dL/d(initial state) and dL/d(initial body state). */
 int orc_gradient(const orc_problem *P, const double *gamma, const double *state0,
-                 const double *body0, double seed, double *grad, double *J,
-                 double *dstate0, double *dbody0);
+                 const double *body0, double seed, const double *dstate_T, const double *dbody_T,
+                 double *grad, double *J, double *dstate0, double *dbody0);
 
 /* Design -> analysis-grid mapping of kappa_ref and of the rigid-body velocity at the
  * pose `body` (full-grid outputs; non-interior nodes are zero). */

@@ -553,3 +553,56 @@ def test_filter_adjoint_vs_finite_differences(orc, dim, nd, R):
     lhs = gbh @ ((ghp - ghm) / (2 * h))
     rhs = gb @ d
     assert abs(lhs - rhs) <= 1e-7 * max(abs(rhs), 1.0)
+
+
+# ------------------------------------------ terminal adjoint values (Sec. 3.4, warm start)
+
+@pytest.mark.parametrize("case", ["2d-theta", "3d-y"])
+def test_terminal_cotangents_match_central_differences(orc, case):
+    """With terminal adjoint values the sweep differentiates
+    L = seed J + <dstate_T, state(N_t)> + <dbody_T, body(N_t)>: central differences of L
+    along a random design direction agree."""
+    pb = FD_CASES[case]()
+    g = W.design(pb)
+    s0, b0 = W.initial_state(pb), W.initial_body(pb)
+    rng = np.random.default_rng(77)
+    sT = rng.standard_normal(s0.size) * 0.1
+    bT = np.zeros(12)
+    bT[:8] = rng.standard_normal(8)
+    seed = 0.6
+
+    def L(gg):
+        st, bd, J = orc.forward(pb, gg, s0, b0)
+        return seed * J + sT @ st + bT[:8] @ bd[:8]
+
+    J, grad = orc.gradient(pb, g, s0, b0, seed=seed, dstate_T=sT, dbody_T=bT)
+    v = rng.standard_normal(g.size)
+    h = 1e-4
+    fd = (L(g + h * v) - L(g - h * v)) / (2 * h)
+    assert grad @ v == pytest.approx(fd, rel=2e-5, abs=1e-9 * np.abs(grad).sum())
+    # without the terminal values the sweep is the plain gradient
+    J0, grad0 = orc.gradient(pb, g, s0, b0, seed=seed)
+    assert np.abs(grad0 - grad).max() > 1e-6 * np.abs(grad).max()
+
+
+@pytest.mark.parametrize("case", ["2d-x", "2d-theta", "3d-theta"])
+def test_gradient_chains_over_split_runs(orc, case):
+    """A run of N_t steps split into two runs (the second starts from the first's final
+    state and body) gives the same objective and gradient when the second run's initial
+    cotangents are the first run's terminal adjoint values: J = J1 + J2 telescopes and the
+    two sweeps add up to the sweep of the whole run, initial cotangents included."""
+    pb = FD_CASES[case]().replace(n_steps=11)
+    n1 = 4
+    g = W.design(pb)
+    s0, b0 = W.initial_state(pb), W.initial_body(pb)
+    seed = 1.3
+    J, grad, ds, db = orc.gradient(pb, g, s0, b0, seed=seed, with_initial=True)
+    p1, p2 = pb.replace(n_steps=n1), pb.replace(n_steps=pb.n_steps - n1)
+    s1, b1, _ = orc.forward(p1, g, s0, b0)
+    J2, g2, ds1, db1 = orc.gradient(p2, g, s1, b1, seed=seed, with_initial=True)
+    J1, g1, ds0, db0 = orc.gradient(p1, g, s0, b0, seed=seed, with_initial=True, dstate_T=ds1, dbody_T=db1)
+    assert J1 + J2 == pytest.approx(J, rel=1e-11, abs=1e-15)
+    scale = np.abs(grad).max()
+    assert np.abs(g1 + g2 - grad).max() <= 1e-11 * scale
+    assert np.abs(ds0 - ds).max() <= 1e-11 * np.abs(ds).max()
+    assert np.abs(db0[:8] - db[:8]).max() <= 1e-11 * np.abs(db[:8]).max()
