@@ -67,6 +67,10 @@ def lib():
         L.orc_step.argtypes = [pp, dp, dp, dp, dp, dp]
         L.orc_forward.argtypes = [pp, dp, dp, dp, dp, dp]
         L.orc_gradient.argtypes = [pp, dp, dp, dp, C.c_double, dp, dp, dp, dp, dp, dp]
+        L.orc_cyclic_sector_points.argtypes = [pp, C.c_int]
+        L.orc_cyclic_sector_points.restype = C.c_long
+        L.orc_cyclic_expand.argtypes = [pp, C.c_int, dp, dp]
+        L.orc_cyclic_collect.argtypes = [pp, C.c_int, dp, dp]
         L.orc_map_design.argtypes = [pp, dp, dp, dp, dp]
         L.orc_interp.argtypes = [pp, dp, dp, dp]
         L.orc_force.argtypes = [pp, dp, dp, dp, dp]
@@ -229,3 +233,28 @@ def filter_adjoint(dim, nd, R, beta, eta, gt, gbh):
     _check(lib().orc_filter_adjoint(int(dim), nd3, float(R), float(beta), float(eta), _p(gt), _p(gbh), _p(gb)),
            "orc_filter_adjoint")
     return gb
+
+
+def cyclic_sector_points(pb, n_sec):
+    """Design variables of one sector of the cyclic periodic design (Sec. 4.2), or -1."""
+    return int(lib().orc_cyclic_sector_points(C.byref(problem_struct(pb)), int(n_sec)))
+
+
+def cyclic_expand(pb, n_sec, gs):
+    """Sector design -> design grid (repeated by the rotations about the rotation axis)."""
+    s = problem_struct(pb)
+    gs = _f64(gs)
+    if gs.size != cyclic_sector_points(pb, n_sec):
+        raise ValueError("sector array has the wrong size")
+    g = np.empty(int(np.prod(pb.nd)))
+    _check(lib().orc_cyclic_expand(C.byref(s), int(n_sec), _p(gs), _p(g)), "orc_cyclic_expand")
+    return g
+
+
+def cyclic_collect(pb, n_sec, grad):
+    """Design-grid sensitivities -> sector (transpose of cyclic_expand)."""
+    s = problem_struct(pb)
+    grad = _f64(grad)
+    gs = np.empty(cyclic_sector_points(pb, n_sec))
+    _check(lib().orc_cyclic_collect(C.byref(s), int(n_sec), _p(grad), _p(gs)), "orc_cyclic_collect")
+    return gs

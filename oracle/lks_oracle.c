@@ -1140,3 +1140,108 @@ int orc_filter_adjoint(int dim, const int nd[3], double R, double beta, double e
     }
     return 0;
 }
+
+/* ------------------------------------------------- cyclic periodic design (Sec. 4.2) */
+
+/* The design is defined on one sector and repeated by the rotations by 2 pi k / n_sec
+ * about the rotation axis through the design grid's centre. Plane coordinates (u, v)
+ * run along the two axes of the rotation plane (pi, pj), w along the rotation axis. On a
+ * Cartesian design grid the rotation maps grid points to grid points for n_sec = 1, 2,
+ * and, when the plane is square, 4; by a quarter turn (u, v) -> (nv - 1 - v, u).
+ * Sector (the design variables), in plane coordinates:
+ *   n_sec = 1: the whole plane, index u + nu v;
+ *   n_sec = 2: plane indices q = u + nu v with q <= nu nv - 1 - q (the half turn maps q
+ *              to nu nv - 1 - q); sector index q;
+ *   n_sec = 4: 0 <= u < ceil(n/2), 0 <= v < floor(n/2), index u + ceil(n/2) v, then the
+ *              centre (odd n) as the last index.
+ * Sector index of a grid point = plane index + (plane sector size) * w. */
+typedef struct {
+    int pi, pj, ax, nu, nv, nw, n_sec;
+    long plane, sector_plane;
+} cyc_t;
+
+static int cyc_init(const orc_problem *P, int n_sec, cyc_t *Y) {
+    ctx_t C;
+    if (ctx_init(&C, P) || !C.has_body) return -1;
+    Y->pi = C.pi;
+    Y->pj = C.pj;
+    Y->ax = C.axis;
+    Y->nu = P->nd[C.pi];
+    Y->nv = P->nd[C.pj];
+    Y->nw = P->nd[C.axis];
+    Y->n_sec = n_sec;
+    Y->plane = (long)Y->nu * Y->nv;
+    if (n_sec == 1) Y->sector_plane = Y->plane;
+    else if (n_sec == 2) Y->sector_plane = (Y->plane + 1) / 2;
+    else if (n_sec == 4 && Y->nu == Y->nv) Y->sector_plane = (long)((Y->nu + 1) / 2) * (Y->nu / 2) + (Y->nu % 2);
+    else return -1;
+    return 0;
+}
+
+/* sector plane index of (u, v) if the point lies in the sector, else -1 */
+static long cyc_in_sector(const cyc_t *Y, int u, int v) {
+    const long q = u + (long)Y->nu * v;
+    if (Y->n_sec == 1) return q;
+    if (Y->n_sec == 2) return q <= Y->plane - 1 - q ? q : -1;
+    const int n = Y->nu, cu = (n + 1) / 2, cv = n / 2;
+    if (u < cu && v < cv) return u + (long)cu * v;
+    if (n % 2 == 1 && u == n / 2 && v == n / 2) return (long)cu * cv;
+    return -1;
+}
+
+/* one rotation of the group: half turn for n_sec = 2, quarter turn for n_sec = 4 */
+static void cyc_rotate(const cyc_t *Y, int *u, int *v) {
+    if (Y->n_sec == 2) {
+        *u = Y->nu - 1 - *u;
+        *v = Y->nv - 1 - *v;
+    } else if (Y->n_sec == 4) {
+        const int t = *u;
+        *u = Y->nv - 1 - *v;
+        *v = t;
+    }
+}
+
+/* sector index of design point m: rotate until the point lies in the sector */
+static long cyc_sector_of(const cyc_t *Y, long m, const int nd[3]) {
+    int c[3] = {(int)(m % nd[0]), (int)((m / nd[0]) % nd[1]), (int)(m / ((long)nd[0] * nd[1]))};
+    int u = c[Y->pi], v = c[Y->pj];
+    const int w = c[Y->ax];
+    for (int k = 0; k < Y->n_sec; k++) {
+        const long s = cyc_in_sector(Y, u, v);
+        if (s >= 0) return s + Y->sector_plane * w;
+        cyc_rotate(Y, &u, &v);
+    }
+    return -1; /* not reached for a valid sector */
+}
+
+long orc_cyclic_sector_points(const orc_problem *P, int n_sec) {
+    cyc_t Y;
+    if (cyc_init(P, n_sec, &Y)) return -1;
+    return Y.sector_plane * Y.nw;
+}
+
+int orc_cyclic_expand(const orc_problem *P, int n_sec, const double *gs, double *g) {
+    cyc_t Y;
+    if (cyc_init(P, n_sec, &Y) || !gs || !g) return -1;
+    const long ND = (long)P->nd[0] * P->nd[1] * P->nd[2];
+    for (long m = 0; m < ND; m++) {
+        const long s = cyc_sector_of(&Y, m, P->nd);
+        if (s < 0) return -2;
+        g[m] = gs[s];
+    }
+    return 0;
+}
+
+/* transpose of the expansion: every design point's sensitivity goes to its sector point */
+int orc_cyclic_collect(const orc_problem *P, int n_sec, const double *grad, double *gs) {
+    cyc_t Y;
+    if (cyc_init(P, n_sec, &Y) || !grad || !gs) return -1;
+    const long ND = (long)P->nd[0] * P->nd[1] * P->nd[2];
+    for (long s = 0; s < Y.sector_plane * Y.nw; s++) gs[s] = 0.0;
+    for (long m = 0; m < ND; m++) {
+        const long s = cyc_sector_of(&Y, m, P->nd);
+        if (s < 0) return -2;
+        gs[s] += grad[m];
+    }
+    return 0;
+}

@@ -106,6 +106,15 @@ int orc_filter(int dim, const int nd[3], double R, double beta, double eta, cons
 int orc_filter_adjoint(int dim, const int nd[3], double R, double beta, double eta, const double *gt,
                        const double *gbh, double *gb);
 
+/* Cyclic periodic design (Sec. 4.2): the design variables live on one of n_sec sectors
+ * (n_sec = 1, 2, or 4 with a square rotation plane) and are repeated by the rotations
+ * about the rotation axis through the design grid's centre. Sector size (or -1 if
+ * n_sec is not supported for this grid); expansion sector -> design grid; collection
+ * (its transpose) design-grid sensitivities -> sector. */
+long orc_cyclic_sector_points(const orc_problem *P, int n_sec);
+int orc_cyclic_expand(const orc_problem *P, int n_sec, const double *gs, double *g);
+int orc_cyclic_collect(const orc_problem *P, int n_sec, const double *grad, double *gs);
+
 #ifdef __cplusplus
 }
 #endif

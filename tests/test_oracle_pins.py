@@ -606,3 +606,66 @@ def test_gradient_chains_over_split_runs(orc, case):
     assert np.abs(g1 + g2 - grad).max() <= 1e-11 * scale
     assert np.abs(ds0 - ds).max() <= 1e-11 * np.abs(ds).max()
     assert np.abs(db0[:8] - db[:8]).max() <= 1e-11 * np.abs(db[:8]).max()
+
+
+# ------------------------------------------------- cyclic periodic design (Sec. 4.2)
+
+def _design_problem(dim, nd, axis=0):
+    pb = W.small2d(nd=nd) if dim == 2 else W.small3d(nd=nd)
+    return pb.replace(axis=axis) if dim == 3 else pb
+
+
+def _plane_view(pb, g):
+    """(w, v, u) view of a design array: u, v the rotation plane's axes (pi, pj), w the
+    rotation axis, as the library defines them (pi = axis + 1, pj = axis + 2 mod 3)."""
+    a = pb.axis if pb.dim == 3 else 2
+    pi, pj = (a + 1) % 3, (a + 2) % 3
+    arr = np.asarray(g).reshape(pb.nd[2], pb.nd[1], pb.nd[0])  # (z, y, x)
+    ax_of = {0: 2, 1: 1, 2: 0}  # grid axis -> array axis
+    return np.transpose(arr, (ax_of[a], ax_of[pj], ax_of[pi]))
+
+
+CYC_CASES = [(2, (6, 6, 1), 0, 4), (2, (5, 5, 1), 0, 4), (2, (7, 4, 1), 0, 2), (2, (5, 3, 1), 0, 2),
+             (3, (4, 6, 6), 0, 4), (3, (5, 3, 4), 1, 2), (3, (5, 5, 3), 2, 4), (2, (4, 3, 1), 0, 1)]
+
+
+@pytest.mark.parametrize("case", range(len(CYC_CASES)))
+def test_cyclic_expansion_is_rotation_invariant(orc, case):
+    """The expanded design is unchanged by the rotations of the group (checked with
+    numpy's rot90 / flips of the plane), every sector variable appears exactly on its
+    orbit (orbit sizes n_sec, or 1 at fixed points), and collection is the transpose."""
+    dim, nd, axis, n = CYC_CASES[case]
+    pb = _design_problem(dim, nd, axis)
+    ns = orc.cyclic_sector_points(pb, n)
+    assert ns > 0
+    rng = np.random.default_rng(case)
+    gs = rng.random(ns)
+    g = orc.cyclic_expand(pb, n, gs)
+    V = _plane_view(pb, g)
+    if n == 2:
+        assert np.array_equal(V, V[:, ::-1, ::-1])
+    if n == 4:
+        assert np.array_equal(V, np.rot90(V, 1, axes=(1, 2)))
+    # each sector value occupies a whole orbit: counts are orbit sizes, summing to ND
+    counts = orc.cyclic_collect(pb, n, np.ones(g.size))
+    assert counts.sum() == pytest.approx(g.size)
+    assert set(np.unique(counts)) <= {1.0, float(n)}
+    assert np.isin(g, gs).all() and np.unique(g).size == ns
+    # transpose
+    x = rng.standard_normal(g.size)
+    assert orc.cyclic_collect(pb, n, x) @ gs == pytest.approx(x @ g, rel=1e-13)
+
+
+def test_cyclic_expansion_small_tables(orc):
+    """Hand-derived layouts: a 3x3 plane with four sectors (corners, edge midpoints,
+    centre) and a 3x2 plane with two (q and 5 - q)."""
+    pb = _design_problem(2, (3, 3, 1))
+    assert orc.cyclic_sector_points(pb, 4) == 3
+    a, b, c = 1.0, 2.0, 3.0
+    assert np.array_equal(orc.cyclic_expand(pb, 4, [a, b, c]).reshape(3, 3),
+                          [[a, b, a], [b, c, b], [a, b, a]])
+    pb = _design_problem(2, (3, 2, 1))
+    assert orc.cyclic_sector_points(pb, 2) == 3
+    assert np.array_equal(orc.cyclic_expand(pb, 2, [a, b, c]), [a, b, c, c, b, a])
+    assert orc.cyclic_sector_points(pb, 4) == -1  # quarter turns need a square plane
+    assert orc.cyclic_sector_points(pb, 3) == -1
