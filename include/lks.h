@@ -109,19 +109,25 @@ int lks_forward(const lks_problem_t *P, const void *gamma, void *state, double *
  * design sensitivity (Eq. design_sensitivity) as the exact derivative of the discrete
  * map that lks_forward computes: segments of ckpt_every steps are recomputed from the
  * checkpoints and swept backwards through the LKS, the boundary values, the n_itr
- * body iterations, the mapping and the pose.
- *   gamma   [ND] T, the same design as in the lks_forward call that filled ckpt
- *   ckpt    checkpoint store filled by lks_forward (read only)
- *   work    scratch of lks_workspace_bytes(P, 1) bytes
- *   seed    dL/dJ
- *   grad    [ND] double, out: seed * dJ/dgamma
- *   dstate0 optional [(dim+1)*N] T, out: seed * dJ/d(initial state)
- *   dbody0  optional [12] double, out: seed * dJ/d(initial body state)
+ * body iterations, the mapping and the pose. The sweep differentiates
+ *   L = seed * J + <dstate_T, state(n_steps)> + <dbody_T[0..7], body(n_steps)[0..7]>:
+ * the terminal adjoint values dstate_T, dbody_T are where the periodic problem
+ * approximation (Sec. 3.4) starts the adjoint of optimization iteration k+1 (from
+ * dstate0, dbody0 of iteration k); they also chain runs split in time.
+ *   gamma    [ND] T, the same design as in the lks_forward call that filled ckpt
+ *   ckpt     checkpoint store filled by lks_forward (read only)
+ *   work     scratch of lks_workspace_bytes(P, 1) bytes
+ *   seed     dL/dJ
+ *   dstate_T optional [(dim+1)*N] T (NULL = zero), read only; must not overlap work
+ *   dbody_T  optional [12] double (NULL = zero; entries 8..11 are ignored), read only
+ *   grad     [ND] double, out: dL/dgamma
+ *   dstate0  optional [(dim+1)*N] T, out: dL/d(initial state)
+ *   dbody0   optional [12] double, out: dL/d(initial body state)
  * Errors: LKS_EINVAL, LKS_ENOSPACE, LKS_EHIP.
  */
 int lks_adjoint(const lks_problem_t *P, const void *gamma, const void *ckpt, size_t ckpt_bytes,
-                void *work, size_t work_bytes, double seed, double *grad, void *dstate0,
-                double *dbody0, void *stream);
+                void *work, size_t work_bytes, double seed, const void *dstate_T, const double *dbody_T,
+                double *grad, void *dstate0, double *dbody0, void *stream);
 
 /*
  * map_design -- grid separation, Eqs. kappa_mapping, us_mapping with the weight of
@@ -194,6 +200,38 @@ size_t lks_filter_workspace_bytes(const lks_problem_t *P);
  */
 int lks_design_filter_adjoint(const lks_problem_t *P, const lks_filter_t *F, const void *gamma_tilde,
                               const double *dJ_dgamma_hat, void *work, size_t work_bytes, double *dJ_dgamma,
+                              void *stream);
+
+/*
+ * Cyclic periodic design (Sec. 4.2): the design variables live on one of n_sectors
+ * sectors of the design grid of P and are repeated by the rotations by 2 pi k / n_sectors
+ * about P's rotation axis (2D: z) through the design grid's centre. Supported: n_sectors
+ * = 1, 2 (half turn), 4 (quarter turn; the rotation plane must be square). In plane
+ * coordinates (u, v) along the plane's axes (axis+1, axis+2 mod 3) and w along the axis,
+ * the sector is: n = 2: plane indices q = u + nu v with q <= nu nv - 1 - q (index q);
+ * n = 4 (side s): u < ceil(s/2), v < floor(s/2) (index u + ceil(s/2) v), then for odd s
+ * the centre. Sector index = plane sector index + (points of the plane sector) * w.
+ * lks_cyclic_sector_points returns the sector size (0 if unsupported or no design grid).
+ */
+size_t lks_cyclic_sector_points(const lks_problem_t *P, int n_sectors);
+
+/*
+ * lks_design_cyclic_expand -- gamma[m] = gamma_sector[sector index of m's orbit].
+ *   gamma_sector [lks_cyclic_sector_points] T (read only)
+ *   gamma        [ND] T, out; must not overlap gamma_sector
+ * Enqueued on `stream`. Errors: LKS_EINVAL, LKS_EHIP.
+ */
+int lks_design_cyclic_expand(const lks_problem_t *P, int n_sectors, const void *gamma_sector, void *gamma,
+                             void *stream);
+
+/*
+ * lks_design_cyclic_collect -- transpose of the expansion (FP64): every sector point
+ * receives the sum of the sensitivities over its orbit (group order R^0, R^1, ...).
+ *   grad        [ND] double (read only), e.g. the grad of lks_adjoint
+ *   grad_sector [lks_cyclic_sector_points] double, out; must not overlap grad
+ * Enqueued on `stream`. Errors: LKS_EINVAL, LKS_EHIP.
+ */
+int lks_design_cyclic_collect(const lks_problem_t *P, int n_sectors, const double *grad, double *grad_sector,
                               void *stream);
 
 /* Message of the last error on this thread ("" if none). */

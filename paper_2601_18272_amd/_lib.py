@@ -22,7 +22,8 @@ OK, EINVAL, ENOSPACE, EUNSTABLE, EDIVERGED, EHIP = 0, -1, -2, -3, -4, -5
 EXPORTS = ("lks_state_elems", "lks_checkpoint_bytes", "lks_workspace_bytes", "lks_forward",
            "lks_adjoint", "map_design", "body_step", "lks_last_error", "lks_profile_read",
            "lks_profile_reset", "lks_design_filter", "lks_design_filter_adjoint",
-           "lks_filter_workspace_bytes")
+           "lks_filter_workspace_bytes", "lks_cyclic_sector_points", "lks_design_cyclic_expand",
+           "lks_design_cyclic_collect")
 
 
 class LksProblem(C.Structure):
@@ -81,7 +82,7 @@ def load():
     L.lks_workspace_bytes.restype = C.c_size_t
     L.lks_forward.argtypes = [pp, vp, vp, dp, vp, C.c_size_t, vp, C.c_size_t, dp, vp]
     L.lks_forward.restype = C.c_int
-    L.lks_adjoint.argtypes = [pp, vp, vp, C.c_size_t, vp, C.c_size_t, C.c_double, dp, vp, dp, vp]
+    L.lks_adjoint.argtypes = [pp, vp, vp, C.c_size_t, vp, C.c_size_t, C.c_double, vp, dp, dp, vp, dp, vp]
     L.lks_adjoint.restype = C.c_int
     L.map_design.argtypes = [pp, vp, dp, vp, vp, vp]
     L.map_design.restype = C.c_int
@@ -94,6 +95,12 @@ def load():
     L.lks_design_filter_adjoint.restype = C.c_int
     L.lks_filter_workspace_bytes.argtypes = [pp]
     L.lks_filter_workspace_bytes.restype = C.c_size_t
+    L.lks_cyclic_sector_points.argtypes = [pp, C.c_int]
+    L.lks_cyclic_sector_points.restype = C.c_size_t
+    L.lks_design_cyclic_expand.argtypes = [pp, C.c_int, vp, vp, vp]
+    L.lks_design_cyclic_expand.restype = C.c_int
+    L.lks_design_cyclic_collect.argtypes = [pp, C.c_int, dp, dp, vp]
+    L.lks_design_cyclic_collect.restype = C.c_int
     L.lks_last_error.argtypes = []
     L.lks_last_error.restype = C.c_char_p
     L.lks_profile_read.argtypes = [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]

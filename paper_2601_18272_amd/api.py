@@ -108,19 +108,26 @@ def forward(pb, gamma, state0, body0, precision="fp32", buffers: Buffers | None 
 
 
 def adjoint(pb, gamma, buffers: Buffers, seed: float = 1.0, precision="fp32",
-            want_initial: bool = False, flags: int = 0):
-    """Reverse sweep after forward(..., store_ckpt=True). Returns grad (float64) and,
-    with want_initial, the cotangents of the initial state and body."""
+            want_initial: bool = False, flags: int = 0, dstate_T=None, dbody_T=None):
+    """Reverse sweep after forward(..., store_ckpt=True) of seed * J plus, optionally,
+    <dstate_T, final state> + <dbody_T, final body> (terminal adjoint values). Returns
+    grad (float64) and, with want_initial, the cotangents of the initial state and body."""
     L = _lib.load()
     dt = DTYPES[precision]
     s = problem_struct(pb, precision, flags)
     g = _dev(gamma, dt) if gamma is not None else None
+    sT = _dev(dstate_T, dt) if dstate_T is not None else None
+    bT = _dev(dbody_T, torch.float64) if dbody_T is not None else None
+    if sT is not None and sT.numel() != state_elems(pb):
+        raise ValueError("dstate_T must have the size of a state")
+    if bT is not None and bT.numel() < 8:
+        raise ValueError("dbody_T needs at least 8 entries")
     grad = torch.empty(max(int(pb.nd[0] * pb.nd[1] * pb.nd[2]), 1), dtype=torch.float64, device="cuda")
     ds = torch.empty(state_elems(pb), dtype=dt, device="cuda") if want_initial else None
     db = torch.empty(12, dtype=torch.float64, device="cuda") if want_initial else None
     _lib.check(L.lks_adjoint(C.byref(s), _p(g), _p(buffers.ckpt), buffers.ckpt.numel(),
-                             _p(buffers.work), buffers.work.numel(), float(seed), _p(grad), _p(ds),
-                             _p(db), _stream()))
+                             _p(buffers.work), buffers.work.numel(), float(seed), _p(sT), _p(bT), _p(grad),
+                             _p(ds), _p(db), _stream()))
     return (grad, ds, db) if want_initial else grad
 
 
@@ -191,6 +198,34 @@ def design_filter_adjoint(pb, gamma_tilde, dJ_dgamma_hat, radius, beta, eta=0.5,
     _lib.check(L.lks_design_filter_adjoint(C.byref(s), C.byref(f), _p(gt), _p(gbh), _p(work), work.numel(),
                                            _p(gb), _stream()))
     return gb
+
+
+def cyclic_sector_points(pb, n_sectors: int) -> int:
+    return int(_lib.load().lks_cyclic_sector_points(C.byref(problem_struct(pb)), int(n_sectors)))
+
+
+def design_cyclic_expand(pb, n_sectors: int, gamma_sector, precision="fp32"):
+    """Sector design -> design grid (cyclic periodic design)."""
+    L = _lib.load()
+    dt = DTYPES[precision]
+    s = problem_struct(pb, precision)
+    gs = _dev(gamma_sector, dt).reshape(-1)
+    g = torch.empty(int(pb.nd[0] * pb.nd[1] * pb.nd[2]), dtype=dt, device="cuda")
+    _lib.check(L.lks_design_cyclic_expand(C.byref(s), int(n_sectors), _p(gs), _p(g), _stream()))
+    return g
+
+
+def design_cyclic_collect(pb, n_sectors: int, grad):
+    """Design-grid sensitivities (FP64) -> sector (transpose of the expansion)."""
+    L = _lib.load()
+    s = problem_struct(pb)
+    gr = _dev(grad, torch.float64).reshape(-1)
+    n = int(L.lks_cyclic_sector_points(C.byref(s), int(n_sectors)))
+    if n == 0:
+        raise LksError(_lib.EINVAL, L.lks_last_error().decode())
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    _lib.check(L.lks_design_cyclic_collect(C.byref(s), int(n_sectors), _p(gr), _p(out), _stream()))
+    return out
 
 
 class LKSFunction(torch.autograd.Function):

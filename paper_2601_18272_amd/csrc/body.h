@@ -799,10 +799,13 @@ __global__ void k_objective(const double *__restrict__ B0, const double *__restr
 enum { AR_BBAR = 0, AR_ACC = 12, AR_FTB = 24, AR_SIZE = 32 };
 
 template <int DIM>
-__global__ void k_adj_init(BodyParams bp, int obj, double seed, double *__restrict__ rec) {
+__global__ void k_adj_init(BodyParams bp, int obj, double seed, const double *__restrict__ dbody_T,
+                           double *__restrict__ rec) {
     if (threadIdx.x != 0) return;
     for (int j = 0; j < AR_SIZE; j++) rec[j] = 0.0;
-    rec[AR_BBAR + (obj == 3 ? B_TH : obj)] = seed;
+    if (dbody_T)
+        for (int j = 0; j < 8; j++) rec[AR_BBAR + j] = dbody_T[j];
+    rec[AR_BBAR + (obj == 3 ? B_TH : obj)] += seed;
     body_update_rev<DIM>(bp, rec + AR_BBAR, rec + AR_FTB, rec + AR_ACC);
 }
 

@@ -23,6 +23,7 @@
 
 #include "../../include/lks.h"
 #include "body.h"
+#include "cyclic.h"
 #include "filter.h"
 
 using namespace lks;
@@ -693,7 +694,7 @@ int forward_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, T *state
 
 template <typename T>
 int adjoint_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, const void *ckpt, void *work, double seed,
-                 double *grad, T *dstate0, double *dbody0, hipStream_t st) {
+                 const T *dstate_T, const double *dbody_T, double *grad, T *dstate0, double *dbody0, hipStream_t st) {
     Ctx c = c0;
     CkptHeader h{};
     HIP_TRY(hipMemcpyAsync(&h, ckpt, sizeof h, hipMemcpyDeviceToHost, st));
@@ -753,11 +754,14 @@ int adjoint_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, const vo
     HIP_TRY(hipMemsetAsync(flag, 0, 16, st));
     R.kappa_ref(gamma, krT, krD);
     if (c.has_body) HIP_TRY(hipMemsetAsync(krb, 0, (size_t)c.D.ND * 8, st));
-    HIP_TRY(hipMemsetAsync(ab, 0, S * sizeof(T), st));
+    // terminal adjoint values: the given cotangent of the final state (else zero), the
+    // seed on the objective's coordinate plus the given cotangent of the final body
+    if (dstate_T) HIP_TRY(hipMemcpyAsync(ab, dstate_T, S * sizeof(T), hipMemcpyDeviceToDevice, st));
+    else HIP_TRY(hipMemsetAsync(ab, 0, S * sizeof(T), st));
     if (c.dim == 2)
-        hipLaunchKernelGGL(k_adj_init<2>, dim3(1), dim3(64), 0, st, c.bp, P->objective, seed, rec);
+        hipLaunchKernelGGL(k_adj_init<2>, dim3(1), dim3(64), 0, st, c.bp, P->objective, seed, dbody_T, rec);
     else
-        hipLaunchKernelGGL(k_adj_init<3>, dim3(1), dim3(64), 0, st, c.bp, P->objective, seed, rec);
+        hipLaunchKernelGGL(k_adj_init<3>, dim3(1), dim3(64), 0, st, c.bp, P->objective, seed, dbody_T, rec);
     HIP_TRY(hipEventRecord(evEntry, st));
     HIP_TRY(hipStreamWaitEvent(side.s, evEntry, 0));
     T *ab_cur = ab, *ab_nxt = ab + S;
@@ -935,6 +939,26 @@ int filter_adj(const Ctx &c, const FltArgs &a, bool prof, hipStream_t st, const 
 
 }  // namespace
 
+// =================================================================== cyclic design
+namespace {
+
+int cyc_ctx(const lks_problem_t *P, int n_sec, Ctx &c, CycArgs &a) {
+    int rc = make_ctx(P, c);
+    if (rc) return rc;
+    if (!c.has_body) return fail(LKS_EINVAL, "the cyclic design needs a design grid");
+    for (int k = 0; k < 3; k++) a.nd[k] = c.D.nd[k];
+    a.pi = c.D.pi;
+    a.pj = c.D.pj;
+    a.ax = c.D.axis;
+    a.n_sec = n_sec;
+    a.sector_plane = cyc_sector_plane(a.nd[a.pi], a.nd[a.pj], n_sec);
+    if (a.sector_plane < 0)
+        return fail(LKS_EINVAL, "%d sectors: supported are 1, 2 and (square rotation plane) 4", n_sec);
+    return LKS_OK;
+}
+
+}  // namespace
+
 // =================================================================== C ABI
 extern "C" {
 
@@ -999,7 +1023,8 @@ int lks_forward(const lks_problem_t *P, const void *gamma, void *state, double *
 }
 
 int lks_adjoint(const lks_problem_t *P, const void *gamma, const void *ckpt, size_t ckpt_bytes_, void *work,
-                size_t work_bytes, double seed, double *grad, void *dstate0, double *dbody0, void *stream) {
+                size_t work_bytes, double seed, const void *dstate_T, const double *dbody_T, double *grad,
+                void *dstate0, double *dbody0, void *stream) {
     g_err.clear();
     Ctx c;
     int rc = make_ctx(P, c);
@@ -1009,10 +1034,14 @@ int lks_adjoint(const lks_problem_t *P, const void *gamma, const void *ckpt, siz
     if (ckpt_bytes_ < ckpt_bytes(c)) return fail(LKS_ENOSPACE, "checkpoint buffer too small");
     if (work_bytes < layout(c, true).total) return fail(LKS_ENOSPACE, "work buffer too small");
     if (!std::isfinite(seed)) return fail(LKS_EINVAL, "seed not finite");
+    if (dstate_T && overlap(dstate_T, (size_t)c.S * c.elt, work, work_bytes))
+        return fail(LKS_EINVAL, "dstate_T must not overlap work");
     hipStream_t st = (hipStream_t)stream;
     if (c.prec == LKS_FP32)
-        return adjoint_impl<float>(c, P, (const float *)gamma, ckpt, work, seed, grad, (float *)dstate0, dbody0, st);
-    return adjoint_impl<double>(c, P, (const double *)gamma, ckpt, work, seed, grad, (double *)dstate0, dbody0, st);
+        return adjoint_impl<float>(c, P, (const float *)gamma, ckpt, work, seed, (const float *)dstate_T, dbody_T,
+                                   grad, (float *)dstate0, dbody0, st);
+    return adjoint_impl<double>(c, P, (const double *)gamma, ckpt, work, seed, (const double *)dstate_T, dbody_T,
+                                grad, (double *)dstate0, dbody0, st);
 }
 
 int map_design(const lks_problem_t *P, const void *kappa_ref, const double *body, void *kappa, void *uS,
@@ -1109,6 +1138,53 @@ int lks_design_filter_adjoint(const lks_problem_t *P, const lks_filter_t *F, con
     if (c.prec == LKS_FP32)
         return filter_adj<3>(c, a, prof, st, (const float *)gamma_tilde, dJ_dgamma_hat, t, dJ_dgamma);
     return filter_adj<3>(c, a, prof, st, (const double *)gamma_tilde, dJ_dgamma_hat, t, dJ_dgamma);
+}
+
+size_t lks_cyclic_sector_points(const lks_problem_t *P, int n_sectors) {
+    Ctx c;
+    CycArgs a;
+    if (cyc_ctx(P, n_sectors, c, a) != LKS_OK) return 0;
+    return (size_t)(a.sector_plane * a.nd[a.ax]);
+}
+
+int lks_design_cyclic_expand(const lks_problem_t *P, int n_sectors, const void *gamma_sector, void *gamma,
+                             void *stream) {
+    g_err.clear();
+    Ctx c;
+    CycArgs a;
+    int rc = cyc_ctx(P, n_sectors, c, a);
+    if (rc) return rc;
+    if (!gamma_sector || !gamma) return fail(LKS_EINVAL, "null pointer argument");
+    const size_t ns = (size_t)(a.sector_plane * a.nd[a.ax]);
+    if (overlap(gamma_sector, ns * c.elt, gamma, (size_t)c.D.ND * c.elt))
+        return fail(LKS_EINVAL, "gamma_sector and gamma must not overlap");
+    hipStream_t st = (hipStream_t)stream;
+    const dim3 grid(blocks(c.D.ND, 256));
+    if (c.prec == LKS_FP32)
+        hipLaunchKernelGGL(k_cyc_expand<float>, grid, dim3(256), 0, st, a, (const float *)gamma_sector,
+                           (float *)gamma);
+    else
+        hipLaunchKernelGGL(k_cyc_expand<double>, grid, dim3(256), 0, st, a, (const double *)gamma_sector,
+                           (double *)gamma);
+    HIP_TRY(hipGetLastError());
+    return LKS_OK;
+}
+
+int lks_design_cyclic_collect(const lks_problem_t *P, int n_sectors, const double *grad, double *grad_sector,
+                              void *stream) {
+    g_err.clear();
+    Ctx c;
+    CycArgs a;
+    int rc = cyc_ctx(P, n_sectors, c, a);
+    if (rc) return rc;
+    if (!grad || !grad_sector) return fail(LKS_EINVAL, "null pointer argument");
+    const long long ns = a.sector_plane * a.nd[a.ax];
+    if (overlap(grad, (size_t)c.D.ND * 8, grad_sector, (size_t)ns * 8))
+        return fail(LKS_EINVAL, "grad and grad_sector must not overlap");
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_cyc_collect, dim3(blocks(ns, 256)), dim3(256), 0, st, a, grad, grad_sector);
+    HIP_TRY(hipGetLastError());
+    return LKS_OK;
 }
 
 }  // extern "C"

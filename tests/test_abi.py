@@ -97,13 +97,16 @@ def test_validation_errors_without_gpu(lib):
     assert L.lks_forward(C.byref(s), None, dummy, dummy, None, 0, dummy, 1 << 30, dummy, None) == lib.EINVAL
     assert L.lks_forward(C.byref(s), dummy, dummy, dummy, None, 0, dummy, 16, dummy, None) == lib.ENOSPACE
     s.ckpt_every = 0
-    assert L.lks_adjoint(C.byref(s), dummy, dummy, 1 << 30, dummy, 1 << 30, 1.0, dummy, None, None,
-                         None) == lib.EINVAL
+    assert L.lks_adjoint(C.byref(s), dummy, dummy, 1 << 30, dummy, 1 << 30, 1.0, None, None, dummy, None,
+                         None, None) == lib.EINVAL
     s.ckpt_every = 4
-    assert L.lks_adjoint(C.byref(s), dummy, dummy, 8, dummy, 1 << 30, 1.0, dummy, None, None,
+    assert L.lks_adjoint(C.byref(s), dummy, dummy, 8, dummy, 1 << 30, 1.0, None, None, dummy, None, None,
                          None) == lib.ENOSPACE
-    assert L.lks_adjoint(C.byref(s), dummy, dummy, 1 << 30, dummy, 1 << 30, float("nan"), dummy,
+    assert L.lks_adjoint(C.byref(s), dummy, dummy, 1 << 30, dummy, 1 << 30, float("nan"), None, None, dummy,
                          None, None, None) == lib.EINVAL
+    # terminal adjoint values inside the workspace
+    assert L.lks_adjoint(C.byref(s), dummy, dummy, 1 << 30, C.c_void_p(1 << 20), 1 << 30, 1.0,
+                         C.c_void_p((1 << 20) + 64), None, dummy, None, None, None) == lib.EINVAL
     assert L.body_step(C.byref(s), dummy, dummy, dummy, None) == lib.EINVAL  # aliasing
 
 
@@ -160,3 +163,28 @@ def test_filter_validation_errors_without_gpu(lib):
     assert L.lks_design_filter_adjoint(C.byref(s), C.byref(good), a, b, d, 1 << 20, inside, None) == lib.EINVAL
     assert L.lks_design_filter_adjoint(C.byref(s), C.byref(good), inside, b, d, 1 << 20, a, None) == lib.EINVAL
     assert L.lks_design_filter_adjoint(C.byref(s), C.byref(good), a, c, inside, 1 << 20, d, None) == lib.EINVAL
+
+
+def test_cyclic_validation_errors_without_gpu(lib):
+    """Unsupported sector counts, non-square planes for quarter turns, null and
+    overlapping arrays are rejected before any HIP call."""
+    from paper_2601_18272_amd import api
+
+    L = lib.load()
+    pb = W.small2d()  # design 10 x 8: half turns only
+    s = api.problem_struct(pb)
+    a, b = C.c_void_p(1 << 20), C.c_void_p(2 << 20)
+    assert L.lks_cyclic_sector_points(C.byref(s), 2) == 40
+    assert L.lks_cyclic_sector_points(C.byref(s), 1) == 80
+    for n in (0, 3, 4, 6, -2):
+        assert L.lks_cyclic_sector_points(C.byref(s), n) == 0
+        assert L.lks_design_cyclic_expand(C.byref(s), n, a, b, None) == lib.EINVAL
+        assert L.lks_design_cyclic_collect(C.byref(s), n, a, b, None) == lib.EINVAL
+    assert L.lks_design_cyclic_expand(C.byref(s), 2, None, b, None) == lib.EINVAL
+    assert L.lks_design_cyclic_collect(C.byref(s), 2, a, None, None) == lib.EINVAL
+    assert L.lks_design_cyclic_expand(C.byref(s), 2, a, C.c_void_p((1 << 20) + 8), None) == lib.EINVAL
+    assert L.lks_design_cyclic_collect(C.byref(s), 2, a, C.c_void_p((1 << 20) + 8), None) == lib.EINVAL
+    s3 = api.problem_struct(W.small3d())  # design 6 x 5 x 5, axis 0: plane 5 x 5
+    assert L.lks_cyclic_sector_points(C.byref(s3), 4) == 7 * 6
+    nob = api.problem_struct(pb.replace(nd=(0, 0, 0)))
+    assert L.lks_cyclic_sector_points(C.byref(nob), 1) == 0

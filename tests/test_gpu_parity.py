@@ -230,3 +230,55 @@ def test_divergence_is_reported(L):
     with pytest.raises(L.LksError) as e:
         L.forward(pb, g, s0, b0, precision="fp64", store_ckpt=False)
     assert e.value.code == -4
+
+
+# ------------------------------------------ terminal adjoint values (Sec. 3.4, warm start)
+
+TERMINAL = ["small2d", "small2d-walls", "small3d"]
+
+
+@pytest.mark.parametrize("case", TERMINAL)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_adjoint_with_terminal_values(L, orc, case, prec):
+    """lks_adjoint started from given cotangents of the final state and body matches the
+    oracle's sweep of seed J + <dstate_T, state> + <dbody_T, body> (gradient and initial
+    cotangents)."""
+    pb = BODY[case]()
+    g, s0, b0 = W.design(pb), W.initial_state(pb), W.initial_body(pb)
+    rng = np.random.default_rng(91)
+    sT = rng.standard_normal(s0.size) * 0.05
+    bT = np.zeros(12)
+    bT[:8] = rng.standard_normal(8)
+    seed = 0.8
+    if prec == "fp32":
+        sT = sT.astype(np.float32).astype(np.float64)
+    J, gref, dsref, dbref = orc.gradient(pb, g, s0, b0, seed=seed, with_initial=True, dstate_T=sT, dbody_T=bT)
+    _, _, Jg, B = L.forward(pb, g, s0, b0, precision=prec)
+    gg, ds, db = L.adjoint(pb, g, B, seed=seed, precision=prec, want_initial=True, dstate_T=sT, dbody_T=bT)
+    tol = 1e-8 if prec == "fp64" else 1e-3
+    assert rel(gg.cpu().numpy(), gref) < tol
+    assert rel(ds.cpu().numpy(), dsref) < tol
+    assert np.abs(db.cpu().numpy()[:8] - dbref[:8]).max() <= tol * np.abs(dbref[:8]).max()
+
+
+@pytest.mark.parametrize("case", ["small2d-rot", "small3d"])
+def test_gradient_chains_over_split_runs(L, case):
+    """Two lks_forward calls (the second from the first's final state and body) and two
+    lks_adjoint calls (the first run's sweep starting from the second's initial
+    cotangents) give the gradient of one run over all steps."""
+    pb = BODY[case]().replace(n_steps=11, ckpt_every=3)
+    n1 = 5
+    g, s0, b0 = W.design(pb), W.initial_state(pb), W.initial_body(pb)
+    _, _, J, B = L.forward(pb, g, s0, b0, precision="fp64")
+    grad, ds, db = L.adjoint(pb, g, B, seed=1.1, precision="fp64", want_initial=True)
+    p1, p2 = pb.replace(n_steps=n1), pb.replace(n_steps=pb.n_steps - n1)
+    s1, b1, J1, B1 = L.forward(p1, g, s0, b0, precision="fp64")
+    _, _, J2, B2 = L.forward(p2, g, s1, b1, precision="fp64")
+    g2, ds1, db1 = L.adjoint(p2, g, B2, seed=1.1, precision="fp64", want_initial=True)
+    g1, ds0, db0 = L.adjoint(p1, g, B1, seed=1.1, precision="fp64", want_initial=True, dstate_T=ds1, dbody_T=db1)
+    assert J1.item() + J2.item() == pytest.approx(J.item(), rel=1e-11, abs=1e-15)
+    gr = grad.cpu().numpy()
+    assert np.abs((g1 + g2).cpu().numpy() - gr).max() <= 1e-10 * np.abs(gr).max()
+    assert np.abs(ds0.cpu().numpy() - ds.cpu().numpy()).max() <= 1e-10 * np.abs(ds.cpu().numpy()).max()
+    dbr = db.cpu().numpy()[:8]
+    assert np.abs(db0.cpu().numpy()[:8] - dbr).max() <= 1e-10 * np.abs(dbr).max()
