@@ -236,6 +236,40 @@ def filter_measure(pb, reps=20):
     }
 
 
+def cyclic_measure(pb, reps=20):
+    """Cyclic periodic design on the workload's design grid (quarter turns when the
+    rotation plane is square, else half turns): expansion (FP32) and collection (FP64),
+    live kernel durations from HIP events (LKS_FLAG_PROFILE)."""
+    import torch
+
+    import paper_2601_18272_amd as lks
+    import workloads as W
+    from paper_2601_18272_amd import _lib
+
+    a = pb.axis if pb.dim == 3 else 2
+    n = 4 if pb.nd[(a + 1) % 3] == pb.nd[(a + 2) % 3] else 2
+    ns = lks.cyclic_sector_points(pb, n)
+    ND = int(np.prod(pb.nd))
+    gs = torch.rand(ns, dtype=torch.float32, device="cuda")
+    grad = torch.tensor(W.cotangent(ND, pb.seed + 2), dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        lks.design_cyclic_expand(pb, n, gs, "fp32")
+        lks.design_cyclic_collect(pb, n, grad)
+    torch.cuda.synchronize()
+    _lib.profile_reset()
+    for _ in range(reps):
+        lks.design_cyclic_expand(pb, n, gs, "fp32", flags=_lib.FLAG_PROFILE)
+        lks.design_cyclic_collect(pb, n, grad, flags=_lib.FLAG_PROFILE)
+    p = _lib.profile_read()
+    _lib.profile_reset()
+    out = {"sectors": n, "sector_points": ns, "design_points": ND}
+    for name, key, by in (("expand", "cyc_expand", 4 * (ns + ND)), ("collect", "cyc_collect", 8 * (ND + ns))):
+        us = p[key][0] / p[key][1] * 1e3
+        out[name] = {"avg_launch_us": round(us, 3), "samples": p[key][1], "bound": "hbm", "bytes": by,
+                     "GBs": round(by / us / 1e3, 1), "frac": round(by / us / 1e3 / HBM_PEAK_GBS, 4)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -375,7 +409,8 @@ def main():
     extra["forward_only"] = {"ms": round(tf * 1e3, 2), "MLUPS": round(pb.N * pb.n_steps / tf / 1e6, 2)}
     extra["copy_GBs_elementwise_1GiB"] = round(copy_bandwidth(), 1)
     extra["design_filter"] = filter_measure(pb)
-    print("# design filter done", file=sys.stderr, flush=True)
+    extra["cyclic_design"] = cyclic_measure(pb)
+    print("# design filter and cyclic design done", file=sys.stderr, flush=True)
 
     if not args.no_fp64:
         bufs64 = lks.Buffers(pb, "fp64", adjoint=True)

@@ -219,7 +219,8 @@ size_t lks_cyclic_sector_points(const lks_problem_t *P, int n_sectors);
  * lks_design_cyclic_expand -- gamma[m] = gamma_sector[sector index of m's orbit].
  *   gamma_sector [lks_cyclic_sector_points] T (read only)
  *   gamma        [ND] T, out; must not overlap gamma_sector
- * Enqueued on `stream`. Errors: LKS_EINVAL, LKS_EHIP.
+ * Enqueued on `stream` (LKS_FLAG_PROFILE: synchronises it and records LKS_K_CYC_EXPAND).
+ * Errors: LKS_EINVAL, LKS_EHIP.
  */
 int lks_design_cyclic_expand(const lks_problem_t *P, int n_sectors, const void *gamma_sector, void *gamma,
                              void *stream);
@@ -229,7 +230,8 @@ int lks_design_cyclic_expand(const lks_problem_t *P, int n_sectors, const void *
  * receives the sum of the sensitivities over its orbit (group order R^0, R^1, ...).
  *   grad        [ND] double (read only), e.g. the grad of lks_adjoint
  *   grad_sector [lks_cyclic_sector_points] double, out; must not overlap grad
- * Enqueued on `stream`. Errors: LKS_EINVAL, LKS_EHIP.
+ * Enqueued on `stream` (LKS_FLAG_PROFILE: synchronises it and records LKS_K_CYC_COLLECT).
+ * Errors: LKS_EINVAL, LKS_EHIP.
  */
 int lks_design_cyclic_collect(const lks_problem_t *P, int n_sectors, const double *grad, double *grad_sector,
                               void *stream);
@@ -268,7 +270,9 @@ enum {
     LKS_K_ADJ_GATHER_SPAN = 12, /* LKS_K_ADJ_GATHER, the kernel's own span */
     LKS_K_FILTER = 13,          /* lks_design_filter */
     LKS_K_FILTER_ADJ = 14,      /* lks_design_filter_adjoint (its two launches) */
-    LKS_K_COUNT = 15
+    LKS_K_CYC_EXPAND = 15,      /* lks_design_cyclic_expand */
+    LKS_K_CYC_COLLECT = 16,     /* lks_design_cyclic_collect */
+    LKS_K_COUNT = 17
 };
 int lks_profile_read(int kernel, double *total_ms, long long *samples);
 void lks_profile_reset(void);

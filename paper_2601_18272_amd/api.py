@@ -204,21 +204,21 @@ def cyclic_sector_points(pb, n_sectors: int) -> int:
     return int(_lib.load().lks_cyclic_sector_points(C.byref(problem_struct(pb)), int(n_sectors)))
 
 
-def design_cyclic_expand(pb, n_sectors: int, gamma_sector, precision="fp32"):
+def design_cyclic_expand(pb, n_sectors: int, gamma_sector, precision="fp32", flags: int = 0):
     """Sector design -> design grid (cyclic periodic design)."""
     L = _lib.load()
     dt = DTYPES[precision]
-    s = problem_struct(pb, precision)
+    s = problem_struct(pb, precision, flags)
     gs = _dev(gamma_sector, dt).reshape(-1)
     g = torch.empty(int(pb.nd[0] * pb.nd[1] * pb.nd[2]), dtype=dt, device="cuda")
     _lib.check(L.lks_design_cyclic_expand(C.byref(s), int(n_sectors), _p(gs), _p(g), _stream()))
     return g
 
 
-def design_cyclic_collect(pb, n_sectors: int, grad):
+def design_cyclic_collect(pb, n_sectors: int, grad, flags: int = 0):
     """Design-grid sensitivities (FP64) -> sector (transpose of the expansion)."""
     L = _lib.load()
-    s = problem_struct(pb)
+    s = problem_struct(pb, "fp32", flags)
     gr = _dev(grad, torch.float64).reshape(-1)
     n = int(L.lks_cyclic_sector_points(C.byref(s), int(n_sectors)))
     if n == 0:

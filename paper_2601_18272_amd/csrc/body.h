@@ -434,6 +434,118 @@ __device__ __forceinline__ void interp_finish(const Design &D, const BodyParams 
 
 // flag bits: 1 non-finite body state, 2 drift beyond the footprint margin. With
 // last = 0 the kernel only writes its partials (k_interp_finish follows).
+// ------------------------------------------------------------------ 3D design tiles
+// In 3D (FP32) the interpolation reverse (R1), which reads the 64 taps of a point twice,
+// runs one 512-thread block per 8x8x8 tile of design points and stages in LDS the
+// analysis-grid patch the tile's stencils touch, so the taps are read from LDS instead
+// of L2. pose_point rounds
+// monotonically in each design index (see k_iter2d), so the stencil floors of a tile are
+// extreme at its eight corners and the patch floor(X) - 1 .. floor(X) + 2 over the corners
+// holds every tap of nonzero weight; it spans at most 12 nodes along the rotation axis
+// (corners 7 apart) and 14 across it (7 sqrt 2 + 4).
+struct Tile3 {
+    static constexpr int E = 8, SA = 12, SP = 14, PN = SA * SP * SP, NT = 512;
+    static constexpr int CH = (PN + NT - 1) / NT;  // patch nodes per thread
+    long long m;  // this thread's design point
+    bool own;     // the point exists (ragged tiles)
+    int lo[3], s[3];  // patch origin (grid coordinates) and extent
+};
+
+// Tile of this block, the thread's point and the patch; false if the patch exceeds its
+// bound (excluded above; the extents are then clamped so every access stays in range).
+// Every thread of the block must call it (it has a barrier).
+__device__ __forceinline__ bool tile3_setup(const Grid &g, const Design &D, const double *B, Tile3 &t) {
+    constexpr int E = Tile3::E;
+    const int ntx = (D.nd[0] + E - 1) / E, nty = (D.nd[1] + E - 1) / E;
+    const int b = (int)blockIdx.x;
+    const int tx = b % ntx, ty = (b / ntx) % nty, tz = b / (ntx * nty);
+    const int tid = (int)threadIdx.x;
+    const int i = tx * E + tid % E, j = ty * E + (tid / E) % E, kz = tz * E + tid / (E * E);
+    t.own = i < D.nd[0] && j < D.nd[1] && kz < D.nd[2];
+    t.m = t.own ? i + (long long)D.nd[0] * (j + (long long)D.nd[1] * kz) : 0;
+    // the eight corner poses, one per thread, shared through LDS
+    __shared__ int cfl[8][3];
+    if (tid < 8) {
+        const int cc = tid;
+        const int ci = tx * E + ((cc & 1) ? min(E, D.nd[0] - tx * E) - 1 : 0);
+        const int cj = ty * E + ((cc & 2) ? min(E, D.nd[1] - ty * E) - 1 : 0);
+        const int ck = tz * E + ((cc & 4) ? min(E, D.nd[2] - tz * E) - 1 : 0);
+        double xi[3];
+        design_xi<3>(D, ci + (long long)D.nd[0] * (cj + (long long)D.nd[1] * ck), xi);
+        Pose P;
+        pose_point(D, B, xi, P);
+#pragma unroll
+        for (int a = 0; a < 3; a++) cfl[cc][a] = (int)fmax(fmin(floor(P.X[a]), 1.0e9), -1.0e9);
+    }
+    __syncthreads();
+    int lo[3], hi[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        lo[a] = cfl[0][a];
+        hi[a] = cfl[0][a];
+#pragma unroll
+        for (int cc = 1; cc < 8; cc++) {
+            lo[a] = min(lo[a], cfl[cc][a]);
+            hi[a] = max(hi[a], cfl[cc][a]);
+        }
+        lo[a] -= 1;
+        hi[a] += 2;
+    }
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        lo[a] = min(max(lo[a], 0), g.n[a] - 1);
+        hi[a] = min(max(hi[a], 0), g.n[a] - 1);
+        const int cap = a == D.axis ? Tile3::SA : Tile3::SP;
+        t.lo[a] = lo[a];
+        t.s[a] = hi[a] - lo[a] + 1;
+        if (t.s[a] > cap) {
+            ok = false;
+            t.s[a] = cap;
+        }
+    }
+    return ok;
+}
+
+// Stage NC components of a field on the patch: get(x, v) fills v at grid node x. All of
+// a thread's loads are issued before its LDS stores. Ends with a barrier.
+template <int NC, typename T, typename Get>
+__device__ __forceinline__ void tile3_stage(const Tile3 &t, T (*pt)[Tile3::PN], Get &&get) {
+    const int n = t.s[0] * t.s[1] * t.s[2];
+    T v[Tile3::CH][NC];
+#pragma unroll
+    for (int r = 0; r < Tile3::CH; r++) {
+        const int l = (int)threadIdx.x + r * Tile3::NT;
+#pragma unroll
+        for (int c = 0; c < NC; c++) v[r][c] = T(0);
+        if (l < n) {
+            const int x[3] = {t.lo[0] + l % t.s[0], t.lo[1] + (l / t.s[0]) % t.s[1], t.lo[2] + l / (t.s[0] * t.s[1])};
+            get(x, v[r]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < Tile3::CH; r++) {
+        const int l = (int)threadIdx.x + r * Tile3::NT;
+        if (l < n)
+#pragma unroll
+            for (int c = 0; c < NC; c++) pt[c][l] = v[r][c];
+    }
+    __syncthreads();
+}
+
+// Patch offsets of a point's taps (clamped: taps outside the patch have weight zero).
+template <typename T> struct TapIdx3 {
+    int x[4], y[4], z[4];
+    __device__ __forceinline__ TapIdx3(const Tile3 &t, const Taps<3, T> &tp) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            x[q] = min(max(tp.c[0][q] - t.lo[0], 0), t.s[0] - 1);
+            y[q] = t.s[0] * min(max(tp.c[1][q] - t.lo[1], 0), t.s[1] - 1);
+            z[q] = t.s[0] * t.s[1] * min(max(tp.c[2][q] - t.lo[2], 0), t.s[2] - 1);
+        }
+    }
+};
+
 template <int DIM, typename T>
 __global__ __launch_bounds__(Dblk<DIM>::v) void k_interp_force(Grid g, Design D, BodyParams bp,
                                                        const T *__restrict__ u, const double *__restrict__ krD,
@@ -861,39 +973,78 @@ __device__ __forceinline__ void pose_rev(const Design &D, const double *B, const
 }
 
 // R1: reverse of the force/torque and of the interpolation at iteration k.
-template <int DIM, typename T>
+template <int DIM, typename T, bool TL = false>
 __global__ __launch_bounds__(Dblk<DIM>::v) void k_adj_r1(Grid g, Design D, const double *__restrict__ Bk, int k,
                                                  const T *__restrict__ uk, const double *__restrict__ krD,
                                                  const double *__restrict__ rec, T *__restrict__ URb,
                                                  double *__restrict__ krb, double *__restrict__ part) {
-    const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long bN = D.boxN;
     const double *B = Bk + k * B_REC;
     const T *u = uk + (long long)k * DIM * bN;
     double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (m < D.ND) {
-        int o[3];
-        box_origin<DIM>(D, Bk, o);
+    int o[3];
+    box_origin<DIM>(D, Bk, o);
+    __shared__ T pt[TL ? 3 : 1][TL ? Tile3::PN : 1];
+    Tile3 t;
+    long long m;
+    bool own;
+    if constexpr (TL) {
+        tile3_setup(g, D, B, t);
+        tile3_stage<3>(t, pt, [&](const int x[3], T *vv) {
+            const int bx = x[0] - o[0], by = x[1] - o[1], bz = x[2] - o[2];
+            if (bx >= 0 && bx < D.L[0] && by >= 0 && by < D.L[1] && bz >= 0 && bz < D.L[2]) {
+                const long long bi = bx + (long long)D.L[0] * (by + (long long)D.L[1] * bz);
+#pragma unroll
+                for (int e = 0; e < 3; e++) vv[e] = u[e * bN + bi];
+            }
+        });
+        m = t.m;
+        own = t.own;
+    } else {
+        m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+        own = m < D.ND;
+    }
+    if (own) {
         double xi[3];
         design_xi<DIM>(D, m, xi);
         Pose P;
         pose_point(D, B, xi, P);
         Taps<DIM, T> tp;
-        tp.init(g, P.X, true, o, D.L);
+        if (TL) tp.init(g, P.X, true);
+        else tp.init(g, P.X, true, o, D.L);
         constexpr int TZ = DIM == 3 ? 4 : 1;
         T ur[3] = {0, 0, 0};
+        // offsets of the taps: in the staged patch (TL) or in the box arrays
+        int ox[4], oy[4], oz[4];
+        const T *src[3];
+        if constexpr (TL) {
+            const TapIdx3<T> ti(t, tp);
+#pragma unroll
+            for (int q = 0; q < 4; q++) ox[q] = ti.x[q], oy[q] = ti.y[q], oz[q] = ti.z[q];
+#pragma unroll
+            for (int e = 0; e < 3; e++) src[e] = pt[e];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                ox[q] = tp.c[0][q];
+                oy[q] = D.L[0] * tp.c[1][q];
+                oz[q] = D.L[0] * D.L[1] * tp.c[2][q];
+            }
+#pragma unroll
+            for (int e = 0; e < 3; e++) src[e] = u + (e < DIM ? e : 0) * bN;
+        }
 #pragma unroll 1
         for (int c = 0; c < TZ; c++) {
             const T wz = sel4(tp.w[2], c);
-            const int cz = sel4(tp.c[2], c);
+            const int cz = sel4(oz, c);
 #pragma unroll
             for (int b = 0; b < 4; b++) {
-                const long long row = (long long)D.L[0] * (tp.c[1][b] + (long long)D.L[1] * cz);
 #pragma unroll
                 for (int a = 0; a < 4; a++) {
                     const T W = tp.w[0][a] * tp.w[1][b] * wz;
+                    const int l = ox[a] + oy[b] + cz;
 #pragma unroll
-                    for (int e = 0; e < DIM; e++) ur[e] += W * u[e * bN + row + tp.c[0][a]];
+                    for (int e = 0; e < DIM; e++) ur[e] += W * src[e][l];
                 }
             }
         }
@@ -926,15 +1077,15 @@ __global__ __launch_bounds__(Dblk<DIM>::v) void k_adj_r1(Grid g, Design D, const
 #pragma unroll 1
         for (int c = 0; c < TZ; c++) {
             const T wz = sel4(tp.w[2], c), dwz = sel4(tp.dw[2], c);
-            const int cz = sel4(tp.c[2], c);
+            const int cz = sel4(oz, c);
 #pragma unroll
             for (int b = 0; b < 4; b++) {
-                const long long row = (long long)D.L[0] * (tp.c[1][b] + (long long)D.L[1] * cz);
 #pragma unroll
                 for (int a = 0; a < 4; a++) {
                     T dot = 0;
+                    const int l = ox[a] + oy[b] + cz;
 #pragma unroll
-                    for (int e = 0; e < DIM; e++) dot += db[e] * u[e * bN + row + tp.c[0][a]];
+                    for (int e = 0; e < DIM; e++) dot += db[e] * src[e][l];
                     xb[0] -= tp.dw[0][a] * tp.w[1][b] * wz * dot;
                     xb[1] -= tp.w[0][a] * tp.dw[1][b] * wz * dot;
                     if (DIM == 3) xb[2] -= tp.w[0][a] * tp.w[1][b] * dwz * dot;

@@ -170,6 +170,7 @@ struct Ctx {
     int dblk = 128;      // threads per block of the design-point kernels
     int tt2 = 0;         // 2D fused iteration: design tile edge (0: separate kernels)
     unsigned ntile = 0;  // its number of tiles
+    bool tile3 = false;  // 3D R1 over 8^3 design tiles (nblk = tiles)
 };
 
 constexpr int MARGIN = 2;
@@ -287,8 +288,14 @@ int make_ctx(const lks_problem_t *P, Ctx &c) {
     c.Kc = P->ckpt_every;
     if (P->objective < 0 || P->objective > 3) return fail(LKS_EINVAL, "bad objective");
     if (P->objective < 3 && P->objective >= c.dim) return fail(LKS_EINVAL, "objective axis >= dim");
+    if (c.has_body && D.boxN > 0x7fffffffLL) return fail(LKS_EINVAL, "design footprint box too large");
     c.dblk = c.dim == 3 ? Dblk<3>::v : Dblk<2>::v;
     c.nblk = c.has_body ? blocks(D.ND, c.dblk) : 1;
+    // 3D FP32: the interpolation reverse (R1) runs over 8^3 design tiles with the stencil
+    // patch staged in LDS; the other design-point kernels keep the linear point order on
+    // as many blocks (nblk * 512 >= ND), so that R1's and R3's partials pair up
+    c.tile3 = c.has_body && c.dim == 3 && c.prec == LKS_FP32;
+    if (c.tile3) c.nblk = blocks(D.nd[0], Tile3::E) * blocks(D.nd[1], Tile3::E) * blocks(D.nd[2], Tile3::E);
     // fused 2D iterations while every block can afford to read all partials (<= 256)
     if (c.has_body && c.dim == 2) {
         for (int tt : {8, 16}) {
@@ -545,6 +552,15 @@ template <typename T> struct Run {
             });
             for (int k = c.K - 1; k >= 0; k--) {
                 pf->run(LKS_K_ADJ_R1, [&](hipEvent_t e0, hipEvent_t e1) {
+                    bool done = false;
+                    if constexpr (DIM == 3 && std::is_same<T, float>::value) {
+                        if (c.tile3) {
+                        hipExtLaunchKernelGGL((k_adj_r1<DIM, T, true>), dim3(c.nblk), dim3(c.dblk), 0, st, e0, e1, 0, c.g,
+                                              c.D, Bk, k, uk, krD, rec, URb, krb, p1);
+                            done = true;
+                        }
+                    }
+                    if (!done)
                     hipExtLaunchKernelGGL((k_adj_r1<DIM, T>), dim3(c.nblk), dim3(c.dblk), 0, st, e0, e1, 0, c.g, c.D, Bk, k, uk, krD,
                                        rec, URb, krb, p1);
                 });
@@ -1160,14 +1176,14 @@ int lks_design_cyclic_expand(const lks_problem_t *P, int n_sectors, const void *
         return fail(LKS_EINVAL, "gamma_sector and gamma must not overlap");
     hipStream_t st = (hipStream_t)stream;
     const dim3 grid(blocks(c.D.ND, 256));
-    if (c.prec == LKS_FP32)
-        hipLaunchKernelGGL(k_cyc_expand<float>, grid, dim3(256), 0, st, a, (const float *)gamma_sector,
-                           (float *)gamma);
-    else
-        hipLaunchKernelGGL(k_cyc_expand<double>, grid, dim3(256), 0, st, a, (const double *)gamma_sector,
-                           (double *)gamma);
-    HIP_TRY(hipGetLastError());
-    return LKS_OK;
+    return filter_timed((P->flags & LKS_FLAG_PROFILE) != 0, LKS_K_CYC_EXPAND, st, [&](hipEvent_t e0, hipEvent_t e1) {
+        if (c.prec == LKS_FP32)
+            hipExtLaunchKernelGGL(k_cyc_expand<float>, grid, dim3(256), 0, st, e0, e1, 0, a,
+                                  (const float *)gamma_sector, (float *)gamma);
+        else
+            hipExtLaunchKernelGGL(k_cyc_expand<double>, grid, dim3(256), 0, st, e0, e1, 0, a,
+                                  (const double *)gamma_sector, (double *)gamma);
+    });
 }
 
 int lks_design_cyclic_collect(const lks_problem_t *P, int n_sectors, const double *grad, double *grad_sector,
@@ -1182,9 +1198,9 @@ int lks_design_cyclic_collect(const lks_problem_t *P, int n_sectors, const doubl
     if (overlap(grad, (size_t)c.D.ND * 8, grad_sector, (size_t)ns * 8))
         return fail(LKS_EINVAL, "grad and grad_sector must not overlap");
     hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_cyc_collect, dim3(blocks(ns, 256)), dim3(256), 0, st, a, grad, grad_sector);
-    HIP_TRY(hipGetLastError());
-    return LKS_OK;
+    return filter_timed((P->flags & LKS_FLAG_PROFILE) != 0, LKS_K_CYC_COLLECT, st, [&](hipEvent_t e0, hipEvent_t e1) {
+        hipExtLaunchKernelGGL(k_cyc_collect, dim3(blocks(ns, 256)), dim3(256), 0, st, e0, e1, 0, a, grad, grad_sector);
+    });
 }
 
 }  // extern "C"
