@@ -249,13 +249,143 @@ __device__ __forceinline__ void spread_node(const Design &D, const double *B, co
     spread_node_kr<DIM, T, ROT, LPN>(D, B, [&](long long m, const int *) { return krT[m]; }, x, q, kap, us);
 }
 
+// ------------------------------------------------------------------ 3D axial sums
+// In 3D the body rotates about a fixed axis, so the position of design point m along the
+// axis is x^G_a + xi_a(m) and the mapping weight of node x and point m factors into an
+// axial weight and a weight in the rotation plane. The axial offset of node x from point
+// m is (x_a - ia) + frac part shared by every node: with c = half_a - x^G_a, the axial base
+// index of node x is ib = x_a + floor(c) and its four axial weights w(t - 1 - frac(c)),
+// t = 0..3, are the same for all nodes. Sums over the design points therefore take the
+// axial sum first, once per pose, on an array the size of the design grid:
+//   A[ib][p] = sum_t w(t - 1 - frac(c)) F[ib + t - 1][p]   (ib = -2 .. nd_a + 1),
+// and a node then visits only the candidates in the plane (one value each).
+struct Axial {
+    int fl;     // ib = x_a + fl
+    double fr;  // frac(half_a - x^G_a)
+};
+
+__device__ __forceinline__ Axial axial_of(const Design &D, const double *B) {
+    const double c = D.half[D.axis] - B[B_XG + D.axis];
+    const double fl = floor(c);
+    return {(int)fmax(fmin(fl, 1.0e9), -1.0e9), c - fl};
+}
+
+// The sum of the valid axial weights of base ib.
+template <typename T> __device__ __forceinline__ T axial_sum(const Design &D, const Axial &ax, int ib) {
+    T s = 0;
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+        const int ia = ib + t - 1;
+        if (ia >= 0 && ia < D.nd[D.axis]) s += wk(T(t - 1) - T(ax.fr));
+    }
+    return s;
+}
+
+// Axial sums of NC design fields (stride sstride) at the poses B^(k0 + blockIdx.y):
+// dst[(y * NC + c) * NA * NP + (ib + 2) + NA * p], NA = nd_a + 4, p = ii + nd_pi * jj.
+template <int NC, typename T>
+__global__ __launch_bounds__(256) void k_axial(Design D, const double *__restrict__ Bk, int k0,
+                                               const T *__restrict__ src, long long sstride, T *__restrict__ dst) {
+    const int na = D.nd[D.axis], NA = na + 4;
+    const long long NP = (long long)D.nd[D.pi] * D.nd[D.pj];
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= NA * NP) return;
+    const Axial ax = axial_of(D, Bk + (k0 + blockIdx.y) * B_REC);
+    const int ib = (int)(t % NA) - 2;
+    const long long p = t / NA;
+    int idx[3];
+    idx[D.pi] = (int)(p % D.nd[D.pi]);
+    idx[D.pj] = (int)(p / D.nd[D.pi]);
+    T acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; c++) acc[c] = T(0);
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const int ia = ib + q - 1;
+        if (ia < 0 || ia >= na) continue;
+        idx[D.axis] = ia;
+        const long long m = idx[0] + (long long)D.nd[0] * (idx[1] + (long long)D.nd[1] * idx[2]);
+        const T w = wk(T(q - 1) - T(ax.fr));
+#pragma unroll
+        for (int c = 0; c < NC; c++) acc[c] += w * src[c * sstride + m];
+    }
+#pragma unroll
+    for (int c = 0; c < NC; c++) dst[((long long)blockIdx.y * NC + c) * NA * NP + t] = acc[c];
+}
+
+// Plane candidates of node x (3D, gather form, LPN lanes): f(W, plane index p, r_pi, r_pj)
+// for every design column (ii, jj) whose plane weight is nonzero. Returns the node's axial
+// base ib and fills d = x - x^G.
+template <typename T, bool ROT, int LPN, typename F>
+__device__ __forceinline__ int gather_plane(const Design &D, const double *B, const Axial &ax, const int x[3],
+                                            double d[3], int q, F &&f) {
+    const double c = B[B_COS], s = B[B_SIN];
+#pragma unroll
+    for (int a = 0; a < 3; a++) d[a] = (double)x[a] - B[B_XG + a];
+    const double xp = c * pick3(d, D.pi) + s * pick3(d, D.pj);
+    const double xq = -s * pick3(d, D.pi) + c * pick3(d, D.pj);
+    const double i0 = xp + D.half[D.pi], j0 = xq + D.half[D.pj];
+    const double fi = floor(i0), fj = floor(j0);
+    const int bi = (int)fmax(fmin(fi, 1.0e9), -1.0e9), bj = (int)fmax(fmin(fj, 1.0e9), -1.0e9);
+    const T fri = T(i0 - fi), frj = T(j0 - fj);
+    const int ib = x[D.axis] + ax.fl;
+    if (ib < -2 || ib > D.nd[D.axis] + 1) return ib;  // no design point along the axis
+    const T cc = T(c), ss = T(s);
+    constexpr int PW = ROT ? 6 : 4, P0 = ROT ? -2 : -1;
+    const int ni = D.nd[D.pi], nj = D.nd[D.pj];
+    for (int cidx = q; cidx < PW * PW; cidx += LPN) {
+        const int u = cidx / PW, v = cidx - u * PW;
+        const int ii = bi + P0 + u, jj = bj + P0 + v;
+        if (ii < 0 || ii >= ni || jj < 0 || jj >= nj) continue;
+        const T ei = T(P0 + u) - fri, ej = T(P0 + v) - frj;
+        const T rp = -(cc * ei - ss * ej), rq = -(ss * ei + cc * ej);
+        if (!(fabs(rp) < T(2) && fabs(rq) < T(2))) continue;
+        f(wk(rp) * wk(rq), ii + (long long)ni * jj, rp, rq);
+    }
+    return ib;
+}
+
+// kappa, u^S at node x (3D) from the axial sums K1 of kappa_ref at pose B (see k_axial).
+template <typename T, bool ROT, int LPN>
+__device__ __forceinline__ void spread_node_ax(const Design &D, const double *B, const Axial &ax,
+                                               const T *__restrict__ K1, const int x[3], int q, T &kap, T us[3]) {
+    const int NA = D.nd[D.axis] + 4;
+    double d[3];
+    T k = 0, phi = 0, wp = 0, wq = 0;
+    const int ib = x[D.axis] + ax.fl;
+    gather_plane<T, ROT, LPN>(D, B, ax, x, d, q, [&](T W, long long p, T rp, T rq) {
+        k += W * K1[(ib + 2) + NA * p];
+        phi += W;
+        wp += W * rp;
+        wq += W * rq;
+    });
+    k = lane_sum<LPN>(k);
+    phi = lane_sum<LPN>(phi);
+    wp = lane_sum<LPN>(wp);
+    wq = lane_sum<LPN>(wq);
+    const T sa = axial_sum<T>(D, ax, ib);
+    phi *= sa;
+    wp *= sa;
+    wq *= sa;
+    // u^S(x) = sum_m W (u^G + omega a x (x^ref_m - x^G)) = u^G phi + omega a x (phi d - sum W r)
+    const double armp = (double)phi * pick3(d, D.pi) - (double)wp;
+    const double armq = (double)phi * pick3(d, D.pj) - (double)wq;
+    const double om = B[B_OM];
+    kap = k;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const double axa = a == D.axis ? 0.0 : (a == D.pi ? -armq : armp);
+        us[a] = T(B[B_UG + a] * (double)phi + om * axa);
+    }
+}
+
 // ------------------------------------------------------------------ forward spread
 // Iteration k of a step: footprint nodes get kappa, u^S at pose B^(k) and the Brinkman
 // correction of u* (read from the state at k = 0 and kept in ustar; from ustar after).
 template <int DIM, typename T, bool ROT, int LPN>
 __global__ __launch_bounds__(256) void k_spread_fwd(Grid g, Design D, const double *__restrict__ Bk, int k,
-                                                    const T *__restrict__ krT, T *__restrict__ u,
-                                                    T *__restrict__ ustar) {
+                                                    const T *__restrict__ krT, const T *__restrict__ K1,
+                                                    T *__restrict__ u, T *__restrict__ ustar) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long l = t / LPN;
     const int q = (int)(t % LPN);
@@ -264,7 +394,10 @@ __global__ __launch_bounds__(256) void k_spread_fwd(Grid g, Design D, const doub
     box_origin<DIM>(D, Bk, o);
     if (!box_node<DIM>(g, D, o, l, x)) return;
     T kap, us[3];
-    spread_node<DIM, T, ROT, LPN>(D, Bk + k * B_REC, krT, x, q, kap, us);
+    if constexpr (DIM == 3)  // axial sums of kappa_ref at B^(k) in K1 (k_axial)
+        spread_node_ax<T, ROT, LPN>(D, Bk + k * B_REC, axial_of(D, Bk + k * B_REC), K1, x, q, kap, us);
+    else
+        spread_node<DIM, T, ROT, LPN>(D, Bk + k * B_REC, krT, x, q, kap, us);
     if (q != 0) return;
     const long long N = g.N;
     const long long id = node_id(g, x[0], x[1], x[2]);
@@ -926,9 +1059,10 @@ __global__ void k_adj_init(BodyParams bp, int obj, double seed, const double *__
 // the cotangent of u* on the box.
 template <int DIM, typename T, bool ROT, int LPN>
 __global__ __launch_bounds__(256) void k_adj_recompute(Grid g, Design D, const double *__restrict__ Bk,
-                                                       const T *__restrict__ krT, const T *__restrict__ ustar,
-                                                       T *__restrict__ kapk, T *__restrict__ usk,
-                                                       T *__restrict__ uk, T *__restrict__ ustb) {
+                                                       const T *__restrict__ krT, const T *__restrict__ K1,
+                                                       const T *__restrict__ ustar, T *__restrict__ kapk,
+                                                       T *__restrict__ usk, T *__restrict__ uk,
+                                                       T *__restrict__ ustb) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long l = t / LPN;
     const int q = (int)(t % LPN);
@@ -942,7 +1076,14 @@ __global__ __launch_bounds__(256) void k_adj_recompute(Grid g, Design D, const d
     box_origin<DIM>(D, Bk, o);
     T kap = 0, us[3] = {0, 0, 0};
     const bool ok = box_node<DIM>(g, D, o, l, x);
-    if (ok) spread_node<DIM, T, ROT, LPN>(D, Bk + k * B_REC, krT, x, q, kap, us);
+    if (ok) {
+        if constexpr (DIM == 3)  // axial sums of kappa_ref at B^(k) in K1 + k NA NP (k_axial)
+            spread_node_ax<T, ROT, LPN>(D, Bk + k * B_REC, axial_of(D, Bk + k * B_REC),
+                                        K1 + (long long)k * (D.nd[D.axis] + 4) * D.nd[D.pi] * D.nd[D.pj], x, q,
+                                        kap, us);
+        else
+            spread_node<DIM, T, ROT, LPN>(D, Bk + k * B_REC, krT, x, q, kap, us);
+    }
     if (q != 0) return;
     kapk[k * bN + l] = kap;
     const T inv = T(1) / (T(1) + kap);
@@ -1105,9 +1246,9 @@ __global__ __launch_bounds__(Dblk<DIM>::v) void k_adj_r1(Grid g, Design D, const
 template <int DIM, typename T, bool ROT, int LPN>
 __global__ __launch_bounds__(256) void k_adj_r2(Grid g, Bc bc, Design D, const double *__restrict__ Bk, int k,
                                                 int K, const T *__restrict__ ab, const T *__restrict__ URb,
-                                                const T *__restrict__ kapk, const T *__restrict__ usk,
-                                                const T *__restrict__ uk, T *__restrict__ ustb,
-                                                T *__restrict__ kb, T *__restrict__ usb) {
+                                                const T *__restrict__ AU, const T *__restrict__ kapk,
+                                                const T *__restrict__ usk, const T *__restrict__ uk,
+                                                T *__restrict__ ustb, T *__restrict__ kb, T *__restrict__ usb) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long l = t / LPN;
     const int q = (int)(t % LPN);
@@ -1124,10 +1265,22 @@ __global__ __launch_bounds__(256) void k_adj_r2(Grid g, Bc bc, Design D, const d
     }
     T ub[3] = {0, 0, 0};
     double d[3];
-    gather_design<DIM, T, ROT, LPN>(D, Bk + k * B_REC, x, d, q, [&](long long m, T W, const T *, const int *) {
+    if constexpr (DIM == 3) {  // axial sums of URb at B^(k) in AU (k_axial, 3 components)
+        const Axial ax = axial_of(D, Bk + k * B_REC);
+        const int NA = D.nd[D.axis] + 4;
+        const long long NANP = (long long)NA * D.nd[D.pi] * D.nd[D.pj];
+        const int ib = x[D.axis] + ax.fl;
+        gather_plane<T, ROT, LPN>(D, Bk + k * B_REC, ax, x, d, q, [&](T W, long long p, T, T) {
+            const long long i = (ib + 2) + NA * p;
 #pragma unroll
-        for (int a = 0; a < DIM; a++) ub[a] += W * URb[a * D.ND + m];
-    });
+            for (int a = 0; a < 3; a++) ub[a] += W * AU[a * NANP + i];
+        });
+    } else {
+        gather_design<DIM, T, ROT, LPN>(D, Bk + k * B_REC, x, d, q, [&](long long m, T W, const T *, const int *) {
+#pragma unroll
+            for (int a = 0; a < DIM; a++) ub[a] += W * URb[a * D.ND + m];
+        });
+    }
 #pragma unroll
     for (int a = 0; a < DIM; a++) ub[a] = lane_sum<LPN>(ub[a]);
     if (q != 0) return;

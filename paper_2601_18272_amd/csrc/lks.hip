@@ -317,8 +317,16 @@ struct Layout {
     // of the other), each of seg_n / ustar_seg_n / Bseg_n bytes
     size_t seg, ustar_seg, Bseg, seg_n, ustar_seg_n, Bseg_n;
     size_t ab, kapk, usk, uk, ustb, kb, usb, URb, krb, part1, part3, rec, counter2;
+    size_t K1f, K1r;  // 3D axial sums of kappa_ref: forward (one pose), reverse (n_itr poses)
+    size_t AU;        // 3D axial sums of the u^ref cotangents (one pose, 3 components)
     size_t total;
 };
+
+// Elements of one pose's axial sums (3D bodies; see k_axial).
+size_t axial_elems(const Ctx &c) {
+    if (!c.has_body || c.dim != 3) return 1;
+    return (size_t)(c.D.nd[c.D.axis] + 4) * c.D.nd[c.D.pi] * c.D.nd[c.D.pj];
+}
 
 Layout layout(const Ctx &c, bool adjoint) {
     Layout L{};
@@ -343,7 +351,11 @@ Layout layout(const Ctx &c, bool adjoint) {
     L.counter = take(16);
     L.flag = take(16);
     L.span = take(2 * NSPAN * sizeof(unsigned long long));
+    const size_t axN = axial_elems(c);
+    L.K1f = take(axN * e);
     if (adjoint) {
+        L.K1r = take(K * axN * e);
+        L.AU = take(3 * axN * e);
         const size_t Kc = (size_t)(c.Kc > 0 ? c.Kc : 1);
         L.seg_n = up((Kc + 1) * stateB);
         L.ustar_seg_n = up(Kc * d * bN * e);
@@ -422,6 +434,7 @@ template <typename T> struct Run {
     const Ctx &c;
     hipStream_t st;
     Prof *pf;
+    T *ax = nullptr;  // 3D: axial sums of kappa_ref (k_axial), one pose per iteration run
 
     // The cross-block finish of the design-point reductions runs in the last block to
     // arrive while the grid is small; beyond that the arrival counter serialises the
@@ -489,8 +502,14 @@ template <typename T> struct Run {
             constexpr bool ROT = decltype(rt)::value;
             for (int k = 0; k < c.K; k++) {
                 pf->run(LKS_K_SPREAD, [&](hipEvent_t e0, hipEvent_t e1) {
+                    hipEvent_t es = e0;
+                    if (DIM == 3) {  // axial sums of kappa_ref at B^(k)
+                        hipExtLaunchKernelGGL((k_axial<1, T>), dim3(blocks((long long)axial_elems(c), 256), 1), dim3(256),
+                                              0, st, e0, nullptr, 0, c.D, Bk, k, krT, (long long)c.D.ND, ax);
+                        es = nullptr;
+                    }
                     hipExtLaunchKernelGGL((k_spread_fwd<DIM, T, ROT, lpn<DIM>()>), dim3(blocks(c.D.boxN * lpn<DIM>(), 256)),
-                                       dim3(256), 0, st, e0, e1, 0, c.g, c.D, Bk, k, krT, u, ustar);
+                                          dim3(256), 0, st, es, e1, 0, c.g, c.D, Bk, k, krT, (const T *)ax, u, ustar);
                 });
                 pf->run(LKS_K_INTERP, [&](hipEvent_t e0, hipEvent_t e1) {
                     hipExtLaunchKernelGGL((k_interp_force<DIM, T>), dim3(c.nblk), dim3(c.dblk), 0, st, e0,
@@ -541,14 +560,21 @@ template <typename T> struct Run {
         T *ustb = at<T>(w, L.ustb), *kb = at<T>(w, L.kb), *usb = at<T>(w, L.usb), *URb = at<T>(w, L.URb);
         double *krb = at<double>(w, L.krb), *p1 = at<double>(w, L.part1), *p3 = at<double>(w, L.part3);
         double *rec = at<double>(w, L.rec);
+        T *AU = at<T>(w, L.AU);
         unsigned *counter = at<unsigned>(w, L.counter2);
         const dim3 gb(blocks(c.D.boxN * (c.dim == 2 ? 4 : 1), 256), c.K);
         dispatch(c, [&](auto dm, auto rt) {
             constexpr int DIM = decltype(dm)::value;
             constexpr bool ROT = decltype(rt)::value;
             pf->run(LKS_K_ADJ_RECOMPUTE, [&](hipEvent_t e0, hipEvent_t e1) {
-                hipExtLaunchKernelGGL((k_adj_recompute<DIM, T, ROT, lpn<DIM>()>), gb, dim3(256), 0, st, e0, e1, 0, c.g, c.D, Bk,
-                                   krT, ustar, kapk, usk, uk, ustb);
+                hipEvent_t es = e0;
+                if (DIM == 3) {  // axial sums of kappa_ref at B^(0) .. B^(K-1)
+                    hipExtLaunchKernelGGL((k_axial<1, T>), dim3(blocks((long long)axial_elems(c), 256), c.K), dim3(256), 0,
+                                          st, e0, nullptr, 0, c.D, Bk, 0, krT, (long long)c.D.ND, ax);
+                    es = nullptr;
+                }
+                hipExtLaunchKernelGGL((k_adj_recompute<DIM, T, ROT, lpn<DIM>()>), gb, dim3(256), 0, st, es, e1, 0, c.g,
+                                      c.D, Bk, krT, (const T *)ax, ustar, kapk, usk, uk, ustb);
             });
             for (int k = c.K - 1; k >= 0; k--) {
                 pf->run(LKS_K_ADJ_R1, [&](hipEvent_t e0, hipEvent_t e1) {
@@ -565,9 +591,15 @@ template <typename T> struct Run {
                                        rec, URb, krb, p1);
                 });
                 pf->run(LKS_K_ADJ_R2, [&](hipEvent_t e0, hipEvent_t e1) {
+                    hipEvent_t es = e0;
+                    if (DIM == 3) {  // axial sums of URb at B^(k)
+                        hipExtLaunchKernelGGL((k_axial<3, T>), dim3(blocks((long long)axial_elems(c), 256), 1), dim3(256),
+                                              0, st, e0, nullptr, 0, c.D, Bk, k, (const T *)URb, (long long)c.D.ND, AU);
+                        es = nullptr;
+                    }
                     hipExtLaunchKernelGGL((k_adj_r2<DIM, T, ROT, lpn<DIM>()>), dim3(blocks(c.D.boxN * lpn<DIM>(), 256)),
-                                       dim3(256), 0, st, e0, e1, 0, c.g, c.bc, c.D, Bk, k, c.K, ab, URb, kapk, usk, uk, ustb, kb,
-                                       usb);
+                                          dim3(256), 0, st, es, e1, 0, c.g, c.bc, c.D, Bk, k, c.K, ab, URb, (const T *)AU,
+                                          kapk, usk, uk, ustb, kb, usb);
                 });
                 pf->run(LKS_K_ADJ_R3, [&](hipEvent_t e0, hipEvent_t e1) {
                     hipExtLaunchKernelGGL((k_adj_r3<DIM, T>), dim3(c.nblk), dim3(c.dblk), 0, st, e0,
@@ -640,6 +672,7 @@ int forward_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, T *state
     pf.arm(at<unsigned long long>(work, L.span), NSPAN, st);
     const int every = c.NT > 32 ? (c.NT + 31) / 32 : 1;
     Run<T> R{c, st, &pf};
+    R.ax = at<T>(work, L.K1f);
     T *krT = at<T>(work, L.krT);
     double *krD = at<double>(work, L.krD);
     T *st1 = at<T>(work, L.st1), *ustar = at<T>(work, L.ustar);
@@ -751,6 +784,8 @@ int adjoint_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, const vo
     hipEvent_t evEntry = side.ev[0], *evFwd = side.ev + 1, *evRev = side.ev + 3;
     Run<T> R{c, st, &pf};
     Run<T> F{c, side.s, &pf};
+    F.ax = at<T>(work, L.K1f);
+    R.ax = at<T>(work, L.K1r);
     T *krT = at<T>(work, L.krT);
     double *krD = at<double>(work, L.krD);
     double *part = at<double>(work, L.part);
