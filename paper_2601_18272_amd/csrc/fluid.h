@@ -618,13 +618,111 @@ __global__ __launch_bounds__(512) void k_adjgather2d(Grid g, Bc bc, T A, const T
 }
 
 // ===================================================================== adjoint, 3D
+// The cotangent g of the post-streaming moments (p*bar / 3, u*bar) that the 3D kernel
+// reads is prepared in place in `ab` by two small launches over the walls and the body
+// box, so the bulk kernel reads plain arrays:
+//   k_adj_fold3d: each interior node one layer in from a non-periodic wall adds the
+//     entries of the wall nodes that copy it (fold_bc; the wall nodes are only read);
+//   k_adj_clear3d: the wall nodes are zeroed (the moments see no cotangent there), and
+//     u*bar of the interior nodes of the body box is replaced by ustb.
+// The sums are those of star_bar, in the same order.
+
+// Node t of the layers `lay` and n_a - 1 - lay of the non-periodic axes a = 0, 1, 2 in
+// turn: t = (a, side, i, j) with side 0 for layer lay, and i, j over the other two axes
+// (the lower one fastest). Returns the axis, or -1 past the end.
+__device__ __forceinline__ int layer_node(const Grid &g, long long t, int lay, int x[3]) {
+    for (int a = 0; a < 3; a++) {
+        const int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
+        const long long face = (long long)g.n[b] * g.n[c];
+        if (g.per[a]) continue;
+        if (t >= 2 * face) {
+            t -= 2 * face;
+            continue;
+        }
+        const int side = (int)(t / face);
+        const long long r = t - side * face;
+        x[a] = side ? g.n[a] - 1 - lay : lay;
+        x[b] = (int)(r % g.n[b]);
+        x[c] = (int)(r / g.n[b]);
+        return a;
+    }
+    return -1;
+}
+
+// Interior nodes one layer in from a non-periodic wall, each once: a node that also lies
+// on such a layer of an earlier axis belongs to that axis.
+__device__ __forceinline__ bool shell_node(const Grid &g, long long t, int x[3]) {
+    const int a = layer_node(g, t, 1, x);
+    if (a < 0 || !is_interior<3>(g, x)) return false;
+    for (int e = 0; e < a; e++)
+        if (!g.per[e] && (x[e] == 1 || x[e] == g.n[e] - 2)) return false;
+    return true;
+}
+
+// Nodes of one layer pair per non-periodic axis (the launch size of layer_node).
+__host__ __device__ inline long long layer_count(const int n[3], const int per[3]) {
+    long long m = 0;
+    for (int a = 0; a < 3; a++)
+        if (!per[a]) m += 2LL * n[a == 0 ? 1 : 0] * n[a == 2 ? 1 : 2];
+    return m;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_fold3d(Grid g, Bc bc, T *__restrict__ ab, long long m) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    int x[3];
+    if (t >= m || !shell_node(g, t, x)) return;
+    const long long id = node_id(g, x[0], x[1], x[2]);
+    T pb, ub[3];
+    fold_bc<3, T>(g, bc, ab, x, id, pb, ub, true);
+    ab[id] = pb;
+#pragma unroll
+    for (int a = 0; a < 3; a++) ab[(1 + a) * g.N + id] = ub[a];
+}
+
+// Threads [0, m) zero the wall nodes (the faces of the non-periodic axes, in the same
+// enumeration with layers 0 and n_a - 1; nodes on several faces are written more than
+// once, with the same zeros), threads [m, m + boxN) set u*bar of the box nodes.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_clear3d(Grid g, T *__restrict__ ab, long long m, Design D,
+                                                     const double *__restrict__ Bprev, const T *__restrict__ ustb,
+                                                     int has_box) {
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long N = g.N;
+    int x[3];
+    if (t < m) {
+        if (layer_node(g, t, 0, x) < 0) return;
+        const long long id = node_id(g, x[0], x[1], x[2]);
+#pragma unroll
+        for (int k = 0; k < 4; k++) ab[k * N + id] = T(0);
+        return;
+    }
+    t -= m;
+    if (!has_box || t >= D.boxN) return;
+    // box node t: x = o + (t in the box's x-fastest order), on the grid and interior
+    int o[3];
+    box_origin<3>(D, Bprev, o);
+    long long r = t;
+    for (int a = 0; a < 3; a++) {
+        x[a] = o[a] + (int)(r % D.L[a]);
+        r /= D.L[a];
+        if (x[a] < 0 || x[a] >= g.n[a]) return;
+    }
+    if (!is_interior<3>(g, x)) return;
+    const long long id = node_id(g, x[0], x[1], x[2]);
+#pragma unroll
+    for (int a = 0; a < 3; a++) ab[(1 + a) * N + id] = ustb[a * D.boxN + t];
+}
+
 // 2.5D blocking like the forward kernel. A block of TX x TY threads is the tile of
 // columns whose moments pi, ups, sig it evaluates (one column per thread); it writes the
 // inner (TX-2) x (TY-2) columns. Per plane s: g of plane s+1 (own column and a one-node
 // ring) goes into a three-plane LDS ring, the moments of plane s are formed from the
 // ring, the in-plane transposed-difference terms need sig of the x and y neighbours
 // (LDS), the z term the own column's sig history (registers), so a column's output is
-// complete two planes later.
+// complete two planes later. The global loads run one plane ahead in registers (g of
+// plane s+2, the previous state of plane s+1), so their latency overlaps the work and
+// the barriers of plane s.
 //
 // The second-order one-sided difference on a wall node reaches two nodes inward, so the
 // transpose at the node two away from a wall needs sig on the wall node. Tile origins
@@ -638,11 +736,11 @@ template <typename T> struct A3 {
     static constexpr int RING = 2 * WX + 2 * TY;
 };
 
+// ab as prepared by k_adj_fold3d and k_adj_clear3d.
 template <typename T, bool SP>
 __global__ __launch_bounds__(A3<T>::NT, sizeof(T) == 4 ? 4 : 2) void k_adjgather3d(
-    Grid g, Bc bc, T A, int ZC, int offx, int offy, const T *__restrict__ ab, const T *__restrict__ ustb,
-    const double *__restrict__ Bprev, Design D, int has_box, const T *__restrict__ sprev, T *__restrict__ out,
-    unsigned long long *ts) {
+    Grid g, T A, int ZC, int offx, int offy, const T *__restrict__ ab, const T *__restrict__ sprev,
+    T *__restrict__ out, unsigned long long *ts) {
     using G = A3<T>;
     constexpr int TX = G::TX, TY = G::TY, WX = G::WX, WY = G::WY;
     __shared__ T gr[3][4][WY][WX];  // g = (p*bar / 3, u*bar) of planes s-1, s, s+1
@@ -654,13 +752,6 @@ __global__ __launch_bounds__(A3<T>::NT, sizeof(T) == 4 ? 4 : 2) void k_adjgather
     const int x0 = (int)tb.x * G::OX - offx, y0 = (int)tb.y * G::OY - offy;
     const int z0 = tb.z * ZC, z1 = min(z0 + ZC, nz);
     const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TX * ty;
-    Box bx;
-    if (has_box) {
-        box_origin<3>(D, Bprev, bx.o);
-        bx.L[0] = D.L[0];
-        bx.L[1] = D.L[1];
-        bx.L[2] = D.L[2];
-    }
     // own column (x, y as the output node when inside the output tile)
     const int ox = x0 - 1 + tx, oy = y0 - 1 + ty;
     int cx = ox, cy = oy;
@@ -677,40 +768,42 @@ __global__ __launch_bounds__(A3<T>::NT, sizeof(T) == 4 ? 4 : 2) void k_adjgather
     }
     int gx = x0 - 2 + rx, gy = y0 - 2 + ry;
     const bool ringok = tid < G::RING && wrap_coord(gx, nx, g.per[0]) && wrap_coord(gy, ny, g.per[1]);
+    const long long cid = (long long)cx + (long long)nx * cy, rid = (long long)gx + (long long)nx * gy;
+    const long long plane = (long long)nx * ny;
 
-    // g at (x, y, plane zp): zero off the interior
-    auto g_at = [&](bool ok, int x, int y, int zp, T v[4]) {
+    // g at plane zp of the own column and the ring node (zero off the grid)
+    T gc[4], gq[4];
+    auto load = [&](int zp) {
         int zw = zp;
-        v[0] = v[1] = v[2] = v[3] = T(0);
-        int xx[3] = {x, y, zw};
-        if (ok && wrap_coord(zw, nz, g.per[2])) {
-            xx[2] = zw;
-            if (is_interior<3>(g, xx)) {
-                const long long id = node_id(g, x, y, zw);
-                T pb, ub[3];
-                star_bar<3, T>(g, bc, ab, ustb, bx, has_box, D.boxN, xx, id, pb, ub);
-                v[0] = pb * T(1.0 / 3.0);
-                v[1] = ub[0];
-                v[2] = ub[1];
-                v[3] = ub[2];
-            }
-        }
+        const bool zok = wrap_coord(zw, nz, g.per[2]);
+        const long long zo = (long long)zw * plane;
+#pragma unroll
+        for (int c = 0; c < 4; c++) gc[c] = (zok && colok) ? ab[c * N + zo + cid] : T(0);
+#pragma unroll
+        for (int c = 0; c < 4; c++) gq[c] = (zok && ringok) ? ab[c * N + zo + rid] : T(0);
     };
-    auto put = [&](int zp) {
+    auto store = [&](int zp) {
         const int sl = ((zp % 3) + 3) % 3;
-        T v[4];
-        g_at(colok, cx, cy, zp, v);
+        gr[sl][0][ty + 1][tx + 1] = gc[0] * T(1.0 / 3.0);
 #pragma unroll
-        for (int c = 0; c < 4; c++) gr[sl][c][ty + 1][tx + 1] = v[c];
+        for (int c = 1; c < 4; c++) gr[sl][c][ty + 1][tx + 1] = gc[c];
         if (tid < G::RING) {
-            g_at(ringok, gx, gy, zp, v);
+            gr[sl][0][ry][rx] = gq[0] * T(1.0 / 3.0);
 #pragma unroll
-            for (int c = 0; c < 4; c++) gr[sl][c][ry][rx] = v[c];
+            for (int c = 1; c < 4; c++) gr[sl][c][ry][rx] = gq[c];
         }
     };
 
     const bool outcol = tx >= 1 && tx <= G::OX && ty >= 1 && ty <= G::OY && ox >= 0 && ox < nx && oy >= 0 &&
                         oy < ny;
+    const long long oid = (long long)ox + (long long)nx * oy;
+    // previous state u at the output column of plane s (loaded a plane ahead)
+    T uc[3] = {0, 0, 0};
+    auto load_u = [&](int zp) {
+        const bool ok = outcol && zp >= z0 && zp < z1;
+#pragma unroll
+        for (int a = 0; a < 3; a++) uc[a] = ok ? sprev[(1 + a) * N + (long long)zp * plane + oid] : T(0);
+    };
     T part[3][4];  // local + in-plane terms of planes s-2, s-1, s
     T hz[5][3];    // sig_xz, sig_yz, sig_zz of planes s-4 .. s
 #pragma unroll
@@ -722,10 +815,17 @@ __global__ __launch_bounds__(A3<T>::NT, sizeof(T) == 4 ? 4 : 2) void k_adjgather
     const T A2 = T(2) * A;
     constexpr T w0 = T(2.0 / 9.0), w1 = T(1.0 / 9.0), w2 = T(1.0 / 72.0);
 
-    put(z0 - 3);
-    put(z0 - 2);
+    load(z0 - 3);
+    store(z0 - 3);
+    load(z0 - 2);
+    store(z0 - 2);
+    load(z0 - 1);
+    load_u(z0 - 2);
     for (int s = z0 - 2; s <= z1 + 1; s++) {
-        put(s + 1);
+        store(s + 1);
+        const T u0 = uc[0], u1 = uc[1], u2 = uc[2];
+        if (s + 2 <= z1 + 2) load(s + 2);
+        load_u(s + 1);
         __syncthreads();
         // moments of plane s at the own node: g_i taken at the node + c_i
         const int sm = ((s - 1) % 3 + 3) % 3, s0 = ((s % 3) + 3) % 3, sp = ((s + 1) % 3 + 3) % 3;
@@ -798,8 +898,6 @@ __global__ __launch_bounds__(A3<T>::NT, sizeof(T) == 4 ? 4 : 2) void k_adjgather
         part[2][0] = part[2][1] = part[2][2] = part[2][3] = 0;
         __syncthreads();
         if (outcol && s >= z0 && s < z1) {
-            const long long id = (long long)ox + (long long)nx * ((long long)oy + (long long)ny * s);
-            const T u0 = sprev[N + id], u1 = sprev[2 * N + id], u2 = sprev[3 * N + id];
             T o0 = T(3) * up[0] + T(9) * (sxx * u0 + sxy * u1 + sxz * u2) - T(3) * pi * u0;
             T o1 = T(3) * up[1] + T(9) * (sxy * u0 + syy * u1 + syz * u2) - T(3) * pi * u1;
             T o2 = T(3) * up[2] + T(9) * (sxz * u0 + syz * u1 + szz * u2) - T(3) * pi * u2;
@@ -833,7 +931,7 @@ __global__ __launch_bounds__(A3<T>::NT, sizeof(T) == 4 ? 4 : 2) void k_adjgather
                 v[1] = hz[d + 2][1];
                 v[2] = hz[d + 2][2];
             }, o);
-            const long long id = (long long)ox + (long long)nx * ((long long)oy + (long long)ny * zo);
+            const long long id = oid + (long long)zo * plane;
             out[id] = part[0][0];
             out[N + id] = o[0];
             out[2 * N + id] = o[1];

@@ -611,7 +611,8 @@ template <typename T> struct Run {
             }
         });
     }
-    void adj_gather(const T *ab, const T *ustb, const double *Bprev, const T *sprev, T *out) const {
+    // In 3D the cotangent ab is consumed: k_adj_fold3d and k_adj_clear3d prepare it in place.
+    void adj_gather(T *ab, const T *ustb, const double *Bprev, const T *sprev, T *out) const {
         const int hb = c.has_body ? 1 : 0;
         pf->run_span(LKS_K_ADJ_GATHER, c.dim == 2 ? LKS_K_ADJ_GATHER_SPAN : -1,
                      [&](hipEvent_t e0, hipEvent_t e1, unsigned long long *ts) {
@@ -632,8 +633,21 @@ template <typename T> struct Run {
                 const int zc = zchunk(A3<T>::OX, A3<T>::OY, res);
                 const dim3 grid(blocks(c.g.n[0] + offx, A3<T>::OX), blocks(c.g.n[1] + offy, A3<T>::OY),
                                 blocks(c.g.n[2], zc));
-                hipExtLaunchKernelGGL((k_adjgather3d<T, false>), grid, dim3(A3<T>::TX, A3<T>::TY), 0, st, e0, e1, 0,
-                                      c.g, c.bc, T(c.A), zc, offx, offy, ab, ustb, Bprev, c.D, hb, sprev, out, ts);
+                const long long m = layer_count(c.g.n, c.g.per);
+                const long long nclr = m + (c.has_body ? c.D.boxN : 0);
+                hipEvent_t es = e0;
+                if (m > 0) {
+                    hipExtLaunchKernelGGL((k_adj_fold3d<T>), dim3(blocks(m, 256)), dim3(256), 0, st, es, nullptr, 0,
+                                          c.g, c.bc, ab, m);
+                    es = nullptr;
+                }
+                if (nclr > 0) {
+                    hipExtLaunchKernelGGL((k_adj_clear3d<T>), dim3(blocks(nclr, 256)), dim3(256), 0, st, es, nullptr,
+                                          0, c.g, ab, m, c.D, Bprev, ustb, hb);
+                    es = nullptr;
+                }
+                hipExtLaunchKernelGGL((k_adjgather3d<T, false>), grid, dim3(A3<T>::TX, A3<T>::TY), 0, st, es, e1, 0,
+                                      c.g, T(c.A), zc, offx, offy, (const T *)ab, sprev, out, ts);
             }
         });
     }
