@@ -1113,12 +1113,34 @@ __device__ __forceinline__ void pose_rev(const Design &D, const double *B, const
     v[7] += ui * (-rj) + uj * ri;
 }
 
-// R1: reverse of the force/torque and of the interpolation at iteration k.
+template <int DIM, int NTHR>
+__device__ __forceinline__ void rec_finish(const BodyParams &bp, int k, const double *part1, const double *part3,
+                                           unsigned nb, const double *rin, double *rs);
+
+// R1: reverse of the force/torque and of the interpolation at iteration k. The
+// force/torque cotangent comes from the record rin, or, with pnb > 0, every block first
+// finishes the previous iteration kfin from its pnb R1 and R3 partials (pp1, pp3; the
+// same fixed-order sum and record step in every block, so the same bits) and block 0
+// stores the stepped record in rout (rin and rout are distinct, since other blocks may
+// still read rin).
 template <int DIM, typename T, bool TL = false>
-__global__ __launch_bounds__(Dblk<DIM>::v) void k_adj_r1(Grid g, Design D, const double *__restrict__ Bk, int k,
+__global__ __launch_bounds__(Dblk<DIM>::v) void k_adj_r1(Grid g, Design D, BodyParams bp, const double *__restrict__ Bk,
+                                                 int k,
                                                  const T *__restrict__ uk, const double *__restrict__ krD,
-                                                 const double *__restrict__ rec, T *__restrict__ URb,
+                                                 const double *__restrict__ rin, double *__restrict__ rout,
+                                                 const double *__restrict__ pp1, const double *__restrict__ pp3,
+                                                 unsigned pnb, int kfin, T *__restrict__ URb,
                                                  double *__restrict__ krb, double *__restrict__ part) {
+    __shared__ double rs[AR_SIZE];
+    // The record step runs first in 3D (keeps the registers of the long tap loops
+    // free) and after the interpolation in 2D (overlaps its loads).
+    constexpr bool EARLY = DIM == 3;
+    const double *FTb = rin + AR_FTB;
+    if (EARLY && pnb > 0) {
+        rec_finish<DIM, Dblk<DIM>::v>(bp, kfin, pp1, pp3, pnb, rin, rs);
+        FTb = rs + AR_FTB;
+        if (blockIdx.x == 0 && threadIdx.x < AR_SIZE) rout[threadIdx.x] = rs[threadIdx.x];
+    }
     const long long bN = D.boxN;
     const double *B = Bk + k * B_REC;
     const T *u = uk + (long long)k * DIM * bN;
@@ -1145,19 +1167,22 @@ __global__ __launch_bounds__(Dblk<DIM>::v) void k_adj_r1(Grid g, Design D, const
         m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
         own = m < D.ND;
     }
+    // interpolation of u^(k) at the point (independent of the record)
+    Pose P;
+    Taps<DIM, T> tp;
+    constexpr int TZ = DIM == 3 ? 4 : 1;
+    T ur[3] = {0, 0, 0};
+    // offsets of the taps: in the staged patch (TL) or in the box arrays
+    int ox[4], oy[4], oz[4];
+    const T *src[3];
+    double kr = 0.0;
     if (own) {
+        kr = krD[m];
         double xi[3];
         design_xi<DIM>(D, m, xi);
-        Pose P;
         pose_point(D, B, xi, P);
-        Taps<DIM, T> tp;
         if (TL) tp.init(g, P.X, true);
         else tp.init(g, P.X, true, o, D.L);
-        constexpr int TZ = DIM == 3 ? 4 : 1;
-        T ur[3] = {0, 0, 0};
-        // offsets of the taps: in the staged patch (TL) or in the box arrays
-        int ox[4], oy[4], oz[4];
-        const T *src[3];
         if constexpr (TL) {
             const TapIdx3<T> ti(t, tp);
 #pragma unroll
@@ -1189,8 +1214,13 @@ __global__ __launch_bounds__(Dblk<DIM>::v) void k_adj_r1(Grid g, Design D, const
                 }
             }
         }
-        const double kr = krD[m];
-        const double *FTb = rec + AR_FTB;
+    }
+    if (!EARLY && pnb > 0) {
+        rec_finish<DIM, Dblk<DIM>::v>(bp, kfin, pp1, pp3, pnb, rin, rs);
+        FTb = rs + AR_FTB;
+        if (blockIdx.x == 0 && threadIdx.x < AR_SIZE) rout[threadIdx.x] = rs[threadIdx.x];
+    }
+    if (own) {
         double Dv[3] = {0, 0, 0}, Db[3] = {0, 0, 0};
 #pragma unroll
         for (int e = 0; e < DIM; e++) Dv[e] = (double)ur[e] - P.US[e];
@@ -1308,14 +1338,13 @@ __device__ __forceinline__ void r3_finish(const BodyParams &bp, int k, const dou
                                           unsigned nb, double *rec);
 
 // R3: transpose of the spread at iteration k (design-point parallel), the pose
-// reversed; the last block (or k_r3_finish when last = 0) forms the body cotangent
-// B^(k)bar and steps the record.
+// reversed; its partials and R1's form the body cotangent B^(k)bar (rec_finish, in the
+// next R1 or in k_r3_finish).
 template <int DIM, typename T>
-__global__ __launch_bounds__(Dblk<DIM>::v) void k_adj_r3(Grid g, Design D, BodyParams bp, const double *__restrict__ Bk,
-                                                 int k, const T *__restrict__ kb, const T *__restrict__ usb,
+__global__ __launch_bounds__(Dblk<DIM>::v) void k_adj_r3(Grid g, Design D, const double *__restrict__ Bk, int k,
+                                                 const T *__restrict__ kb, const T *__restrict__ usb,
                                                  const double *__restrict__ krD, double *__restrict__ krb,
-                                                 const double *__restrict__ part1, double *__restrict__ part3,
-                                                 unsigned *__restrict__ counter, double *__restrict__ rec, int last) {
+                                                 double *__restrict__ part3) {
     const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long bN = D.boxN;
     const double *B = Bk + k * B_REC;
@@ -1369,42 +1398,44 @@ __global__ __launch_bounds__(Dblk<DIM>::v) void k_adj_r3(Grid g, Design D, BodyP
         pose_rev(D, B, P, Xb, USb, rb, v);
     }
     block_reduce_store<8, Dblk<DIM>::v>(v, part3);
-    if (!last) return;
-    if (!last_block(counter)) return;
-    r3_finish<DIM, Dblk<DIM>::v>(bp, k, part1, part3, gridDim.x, rec);
-    if (threadIdx.x == 0) *counter = 0u;
 }
 
-// Body cotangent B^(k)bar from the R1 and R3 partials (fixed order), then the record
-// step: the force/torque cotangent of iteration k-1, or at k = 0 the cotangent of
-// B(t-1) and the force/torque cotangent of the previous step's last iteration.
+// Body cotangent B^(k)bar from the R1 and R3 partials of iteration k (fixed order), then
+// the record step on a copy of rin in rs (shared or global memory; rs may be rin): the
+// force/torque cotangent of iteration k-1, or at k = 0 the cotangent of B(t-1) and the
+// force/torque cotangent of the previous step's last iteration. Every thread of the
+// block calls it; rs is complete on return.
 template <int DIM, int NTHR>
-__device__ __forceinline__ void r3_finish(const BodyParams &bp, int k, const double *part1, const double *part3,
-                                          unsigned nb, double *rec) {
+__device__ __forceinline__ void rec_finish(const BodyParams &bp, int k, const double *part1, const double *part3,
+                                           unsigned nb, const double *rin, double *rs) {
     __shared__ double Bkb[8];
+    if (rs != rin && threadIdx.x < AR_SIZE) rs[threadIdx.x] = rin[threadIdx.x];  // published by the barriers below
     reduce_partials<8, NTHR>(part1, part3, nb, Bkb);
     if (threadIdx.x == 0) {
         double bb[B_REC];
         for (int j = 0; j < B_REC; j++) bb[j] = j < 8 ? Bkb[j] : 0.0;
         if (k > 0) {
-            body_update_rev<DIM>(bp, bb, rec + AR_FTB, rec + AR_ACC);
+            body_update_rev<DIM>(bp, bb, rs + AR_FTB, rs + AR_ACC);
         } else {
-            double *acc = rec + AR_ACC;
+            double *acc = rs + AR_ACC;
             for (int j = 0; j < 8; j++) acc[j] += bb[j];
             for (int j = 0; j < B_REC; j++) {
-                rec[AR_BBAR + j] = acc[j];
+                rs[AR_BBAR + j] = acc[j];
                 acc[j] = 0.0;
             }
-            body_update_rev<DIM>(bp, rec + AR_BBAR, rec + AR_FTB, acc);
+            body_update_rev<DIM>(bp, rs + AR_BBAR, rs + AR_FTB, acc);
         }
     }
+    __syncthreads();
 }
 
+// One block: the record step of iteration k in place (rec_finish), for grids whose R1
+// would read too many partials per block, and after the last iteration.
 template <int DIM>
 __global__ __launch_bounds__(1024) void k_r3_finish(BodyParams bp, int k, const double *__restrict__ part1,
                                                    const double *__restrict__ part3, unsigned nb,
                                                    double *__restrict__ rec) {
-    r3_finish<DIM, 1024>(bp, k, part1, part3, nb, rec);
+    rec_finish<DIM, 1024>(bp, k, part1, part3, nb, rec, rec);
 }
 
 // grad = krb * d kappa_ref / d gamma; optional body cotangent of t = 0.

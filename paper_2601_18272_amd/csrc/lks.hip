@@ -316,7 +316,7 @@ struct Layout {
     // adjoint: two segment buffers (recompute of one segment overlaps the reverse sweep
     // of the other), each of seg_n / ustar_seg_n / Bseg_n bytes
     size_t seg, ustar_seg, Bseg, seg_n, ustar_seg_n, Bseg_n;
-    size_t ab, kapk, usk, uk, ustb, kb, usb, URb, krb, part1, part3, rec, counter2;
+    size_t ab, kapk, usk, uk, ustb, kb, usb, URb, krb, part1, part3, rec;
     size_t K1f, K1r;  // 3D axial sums of kappa_ref: forward (one pose), reverse (n_itr poses)
     size_t AU;        // 3D axial sums of the u^ref cotangents (one pose, 3 components)
     size_t total;
@@ -372,10 +372,9 @@ Layout layout(const Ctx &c, bool adjoint) {
         L.usb = take(d * bN * e);
         L.URb = take(d * ND * e);
         L.krb = take(ND * 8);
-        L.part1 = take((size_t)c.nblk * 8 * 8);
+        L.part1 = take(2 * (size_t)c.nblk * 8 * 8);  // two buffers (see Run::body_rev)
         L.part3 = take((size_t)c.nblk * 8 * 8);
-        L.rec = take(AR_SIZE * 8);
-        L.counter2 = take(16);
+        L.rec = take(2 * AR_SIZE * 8);
     }
     L.total = o;
     return L;
@@ -435,6 +434,15 @@ template <typename T> struct Run {
     hipStream_t st;
     Prof *pf;
     T *ax = nullptr;  // 3D: axial sums of kappa_ref (k_axial), one pose per iteration run
+
+    // Adjoint record (body_rev): two copies, since an R1 that steps the record reads one
+    // and writes the other (rcur: the current one); R1 partial buffers alternate (p1cur:
+    // the one the next R1 writes); pend: the iteration whose partials still wait for
+    // their record step, or -1.
+    mutable int rcur = 0, p1cur = 0, pend = -1;
+    // The next R1 steps the record itself (every block reads all partials) on small
+    // grids; larger ones use k_r3_finish after each R3.
+    bool defer_finish() const { return c.nblk <= 256; }
 
     // The cross-block finish of the design-point reductions runs in the last block to
     // arrive while the grid is small; beyond that the arrival counter serialises the
@@ -558,10 +566,10 @@ template <typename T> struct Run {
                   void *w) const {
         T *kapk = at<T>(w, L.kapk), *usk = at<T>(w, L.usk), *uk = at<T>(w, L.uk);
         T *ustb = at<T>(w, L.ustb), *kb = at<T>(w, L.kb), *usb = at<T>(w, L.usb), *URb = at<T>(w, L.URb);
-        double *krb = at<double>(w, L.krb), *p1 = at<double>(w, L.part1), *p3 = at<double>(w, L.part3);
-        double *rec = at<double>(w, L.rec);
+        double *krb = at<double>(w, L.krb), *p3 = at<double>(w, L.part3);
+        auto p1b = [&](int b) { return at<double>(w, L.part1) + (size_t)b * c.nblk * 8; };
+        auto recb = [&](int b) { return at<double>(w, L.rec) + (size_t)b * AR_SIZE; };
         T *AU = at<T>(w, L.AU);
-        unsigned *counter = at<unsigned>(w, L.counter2);
         const dim3 gb(blocks(c.D.boxN * (c.dim == 2 ? 4 : 1), 256), c.K);
         dispatch(c, [&](auto dm, auto rt) {
             constexpr int DIM = decltype(dm)::value;
@@ -577,19 +585,34 @@ template <typename T> struct Run {
                                       c.D, Bk, krT, (const T *)ax, ustar, kapk, usk, uk, ustb);
             });
             for (int k = c.K - 1; k >= 0; k--) {
+                // record step of the pending iteration inside this R1 (reads recb(rcur) and
+                // the other partial buffer, writes recb(1 - rcur))
+                const bool fin = pend >= 0;
+                const double *rin = recb(rcur);
+                double *rout = recb(1 - rcur);
+                const double *pp1 = p1b(1 - p1cur);
+                const unsigned pnb = fin ? (unsigned)c.nblk : 0u;
+                const int kfin = pend;
+                double *p1 = p1b(p1cur);
                 pf->run(LKS_K_ADJ_R1, [&](hipEvent_t e0, hipEvent_t e1) {
                     bool done = false;
                     if constexpr (DIM == 3 && std::is_same<T, float>::value) {
                         if (c.tile3) {
-                        hipExtLaunchKernelGGL((k_adj_r1<DIM, T, true>), dim3(c.nblk), dim3(c.dblk), 0, st, e0, e1, 0, c.g,
-                                              c.D, Bk, k, uk, krD, rec, URb, krb, p1);
+                            hipExtLaunchKernelGGL((k_adj_r1<DIM, T, true>), dim3(c.nblk), dim3(c.dblk), 0, st, e0, e1, 0,
+                                                  c.g, c.D, c.bp, Bk, k, uk, krD, rin, rout, pp1, (const double *)p3,
+                                                  pnb, kfin, URb, krb, p1);
                             done = true;
                         }
                     }
                     if (!done)
-                    hipExtLaunchKernelGGL((k_adj_r1<DIM, T>), dim3(c.nblk), dim3(c.dblk), 0, st, e0, e1, 0, c.g, c.D, Bk, k, uk, krD,
-                                       rec, URb, krb, p1);
+                        hipExtLaunchKernelGGL((k_adj_r1<DIM, T>), dim3(c.nblk), dim3(c.dblk), 0, st, e0, e1, 0, c.g,
+                                              c.D, c.bp, Bk, k, uk, krD, rin, rout, pp1, (const double *)p3, pnb, kfin,
+                                              URb, krb, p1);
                 });
+                if (fin) {
+                    rcur = 1 - rcur;
+                    pend = -1;
+                }
                 pf->run(LKS_K_ADJ_R2, [&](hipEvent_t e0, hipEvent_t e1) {
                     hipEvent_t es = e0;
                     if (DIM == 3) {  // axial sums of URb at B^(k)
@@ -602,14 +625,31 @@ template <typename T> struct Run {
                                           kapk, usk, uk, ustb, kb, usb);
                 });
                 pf->run(LKS_K_ADJ_R3, [&](hipEvent_t e0, hipEvent_t e1) {
-                    hipExtLaunchKernelGGL((k_adj_r3<DIM, T>), dim3(c.nblk), dim3(c.dblk), 0, st, e0,
-                                          last_block_ok() ? e1 : nullptr, 0, c.g, c.D, c.bp, Bk, k,
-                                       kb, usb, krD, krb, p1, p3, counter, rec, last_block_ok() ? 1 : 0);
-                    if (!last_block_ok())
-                        hipExtLaunchKernelGGL((k_r3_finish<DIM>), dim3(1), dim3(1024), 0, st, nullptr, e1, 0, c.bp, k, p1, p3, c.nblk, rec);
+                    const bool d = defer_finish();
+                    hipExtLaunchKernelGGL((k_adj_r3<DIM, T>), dim3(c.nblk), dim3(c.dblk), 0, st, e0, d ? e1 : nullptr, 0,
+                                          c.g, c.D, Bk, k, kb, usb, krD, krb, p3);
+                    if (!d)
+                        hipExtLaunchKernelGGL((k_r3_finish<DIM>), dim3(1), dim3(1024), 0, st, nullptr, e1, 0, c.bp, k,
+                                              (const double *)p1, (const double *)p3, (unsigned)c.nblk, recb(rcur));
                 });
+                if (defer_finish()) pend = k;
+                p1cur = 1 - p1cur;
             }
         });
+    }
+    // Record step of a pending iteration (after the last R3); returns the current record.
+    double *rev_flush(const Layout &L, void *w) const {
+        double *rec = at<double>(w, L.rec) + (size_t)rcur * AR_SIZE;
+        if (pend >= 0) {
+            const double *pp1 = at<double>(w, L.part1) + (size_t)(1 - p1cur) * c.nblk * 8;
+            const double *p3 = at<double>(w, L.part3);
+            if (c.dim == 2)
+                hipLaunchKernelGGL(k_r3_finish<2>, dim3(1), dim3(1024), 0, st, c.bp, pend, pp1, p3, (unsigned)c.nblk, rec);
+            else
+                hipLaunchKernelGGL(k_r3_finish<3>, dim3(1), dim3(1024), 0, st, c.bp, pend, pp1, p3, (unsigned)c.nblk, rec);
+            pend = -1;
+        }
+        return rec;
     }
     // In 3D the cotangent ab is consumed: k_adj_fold3d and k_adj_clear3d prepare it in place.
     void adj_gather(T *ab, const T *ustb, const double *Bprev, const T *sprev, T *out) const {
@@ -803,7 +843,7 @@ int adjoint_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, const vo
     T *krT = at<T>(work, L.krT);
     double *krD = at<double>(work, L.krD);
     double *part = at<double>(work, L.part);
-    unsigned *counter = at<unsigned>(work, L.counter), *counter2 = at<unsigned>(work, L.counter2);
+    unsigned *counter = at<unsigned>(work, L.counter);
     int *flag = at<int>(work, L.flag);
     T *ab = at<T>(work, L.ab);
     double *rec = at<double>(work, L.rec), *krb = at<double>(work, L.krb);
@@ -815,7 +855,6 @@ int adjoint_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, const vo
     const size_t S = (size_t)c.S;
     const size_t fp = (size_t)c.dim * (size_t)c.D.boxN;
     HIP_TRY(hipMemsetAsync(counter, 0, 16, st));
-    HIP_TRY(hipMemsetAsync(counter2, 0, 16, st));
     HIP_TRY(hipMemsetAsync(flag, 0, 16, st));
     R.kappa_ref(gamma, krT, krD);
     if (c.has_body) HIP_TRY(hipMemsetAsync(krb, 0, (size_t)c.D.ND * 8, st));
@@ -882,9 +921,11 @@ int adjoint_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, const vo
         HIP_TRY(hipEventRecord(evRev[b], st));
         HIP_TRY(hipGetLastError());
     }
-    if (c.has_body)
+    if (c.has_body) {
+        rec = R.rev_flush(L, work);
         hipLaunchKernelGGL(k_grad_final<T>, dim3(blocks(c.D.ND, 256)), dim3(256), 0, st, c.D.ND, c.bp.kmax, c.bp.q,
                            gamma, krb, grad, rec, P->objective, seed, dbody0);
+    }
     else if (dbody0)
         HIP_TRY(hipMemsetAsync(dbody0, 0, 12 * sizeof(double), st));
     if (dstate0) HIP_TRY(hipMemcpyAsync(dstate0, ab_cur, S * sizeof(T), hipMemcpyDeviceToDevice, st));
