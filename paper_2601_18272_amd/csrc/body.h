@@ -1175,9 +1175,10 @@ __global__ __launch_bounds__(Dblk<DIM>::v) void k_adj_r1(Grid g, Design D, BodyP
     // offsets of the taps: in the staged patch (TL) or in the box arrays
     int ox[4], oy[4], oz[4];
     const T *src[3];
-    double kr = 0.0;
+    double kr = 0.0, kb0 = 0.0;  // kappa_ref and its running cotangent, requested early
     if (own) {
         kr = krD[m];
+        kb0 = krb[m];
         double xi[3];
         design_xi<DIM>(D, m, xi);
         pose_point(D, B, xi, P);
@@ -1232,7 +1233,7 @@ __global__ __launch_bounds__(Dblk<DIM>::v) void k_adj_r1(Grid g, Design D, BodyP
         }
         const double dp = pick3(Dv, D.pi), dq = pick3(Dv, D.pj);
         gsum += FTb[3] * (pick3(P.r, D.pi) * dq - pick3(P.r, D.pj) * dp);
-        krb[m] += gsum;
+        krb[m] = kb0 + gsum;
         double rb[3], USb[3] = {0, 0, 0}, Xb[3] = {0, 0, 0};
 #pragma unroll
         for (int e = 0; e < 3; e++)
@@ -1293,6 +1294,16 @@ __global__ __launch_bounds__(256) void k_adj_r2(Grid g, Bc bc, Design D, const d
         for (int a = 0; a < DIM; a++) usb[a * bN + l] = T(0);
         return;
     }
+    // the node's own fields, requested before the gather
+    T kap = 0, ust[3] = {0, 0, 0}, dus[3] = {0, 0, 0};
+    if (q == 0) {
+        kap = kapk[k * bN + l];
+#pragma unroll
+        for (int a = 0; a < DIM; a++) {
+            ust[a] = ustb[a * bN + l];
+            dus[a] = usk[(k * DIM + a) * bN + l] - uk[(k * DIM + a) * bN + l];
+        }
+    }
     T ub[3] = {0, 0, 0};
     double d[3];
     if constexpr (DIM == 3) {  // axial sums of URb at B^(k) in AU (k_axial, 3 components)
@@ -1321,13 +1332,12 @@ __global__ __launch_bounds__(256) void k_adj_r2(Grid g, Bc bc, Design D, const d
 #pragma unroll
         for (int a = 0; a < DIM; a++) ub[a] += uf[a];
     }
-    const T kap = kapk[k * bN + l];
     const T inv = T(1) / (T(1) + kap);
     T kbar = 0;
 #pragma unroll
     for (int a = 0; a < DIM; a++) {
-        ustb[a * bN + l] += ub[a] * inv;
-        kbar += ub[a] * (usk[(k * DIM + a) * bN + l] - uk[(k * DIM + a) * bN + l]) * inv;
+        ustb[a * bN + l] = ust[a] + ub[a] * inv;
+        kbar += ub[a] * dus[a] * inv;
         usb[a * bN + l] = ub[a] * kap * inv;
     }
     kb[l] = kbar;
