@@ -847,30 +847,33 @@ __global__ __launch_bounds__(It2<TT>::NT) void k_iter2d(Grid g, Design D, BodyPa
                 if (!(fabs(Bs[B_XG + a] - B0[B_XG + a]) <= (double)D.margin)) atomicOr(flag, 2);
         }
     }
-    // this thread's design point and its interpolation stencil
     // Patch: the nodes of the tile points' stencils, floor(X) - 1 .. floor(X) + 2 per
     // axis (clamped to the grid like the taps). pose_point rounds c xi_p, s xi_q, their
     // difference and the sum with x^G, each monotone in its operands, so the computed X
     // is monotone in each design index and its floors are extreme at the tile's corners
-    // (exactly, not only up to rounding); every thread forms the four corners.
-    int lo[2] = {0x7fffffff, 0x7fffffff}, hi[2] = {-0x7fffffff, -0x7fffffff};
-    {
+    // (exactly, not only up to rounding); threads 0..3 form one corner each.
+    __shared__ int cfl[4][2];
+    if (tid < 4) {
         const int i0 = ti * TT, i1 = min(i0 + TT, D.nd[0]) - 1;
         const int j0 = tj * TT, j1 = min(j0 + TT, D.nd[1]) - 1;
+        const long long mc = ((tid & 1) ? i1 : i0) + (long long)D.nd[0] * ((tid & 2) ? j1 : j0);
+        double xi[3];
+        design_xi<2>(D, mc, xi);
+        Pose Pc;
+        pose_point(D, Bs, xi, Pc);
 #pragma unroll
-        for (int cc = 0; cc < 4; cc++) {
-            const long long mc = ((cc & 1) ? i1 : i0) + (long long)D.nd[0] * ((cc & 2) ? j1 : j0);
-            double xi[3];
-            design_xi<2>(D, mc, xi);
-            Pose Pc;
-            pose_point(D, Bs, xi, Pc);
+        for (int a = 0; a < 2; a++) cfl[tid][a] = (int)fmax(fmin(floor(Pc.X[a]), 1.0e9), -1.0e9);
+    }
+    __syncthreads();
+    int lo[2] = {0x7fffffff, 0x7fffffff}, hi[2] = {-0x7fffffff, -0x7fffffff};
+    {
+#pragma unroll
+        for (int cc = 0; cc < 4; cc++)
 #pragma unroll
             for (int a = 0; a < 2; a++) {
-                const int f = (int)fmax(fmin(floor(Pc.X[a]), 1.0e9), -1.0e9);
-                lo[a] = min(lo[a], f - 1);
-                hi[a] = max(hi[a], f + 2);
+                lo[a] = min(lo[a], cfl[cc][a] - 1);
+                hi[a] = max(hi[a], cfl[cc][a] + 2);
             }
-        }
 #pragma unroll
         for (int a = 0; a < 2; a++) {
             lo[a] = min(max(lo[a], 0), g.n[a] - 1);
@@ -882,21 +885,16 @@ __global__ __launch_bounds__(It2<TT>::NT) void k_iter2d(Grid g, Design D, BodyPa
         if (tid == 0) atomicOr(flag, 4);
         return;
     }
-    // own point's pose and stencil (used after the patch)
-    Pose P;
-    Taps<2, T> tp;
-    if (own) {
-        double xi[3];
-        design_xi<2>(D, m, xi);
-        pose_point(D, Bs, xi, P);
-        tp.init(g, P.X, false);
-    }
-    // patch: kappa, u^S at pose B^(k), Brinkman correction of u* (LPN lanes per node)
+    // patch: kappa, u^S at pose B^(k), Brinkman correction of u* (LPN lanes per node).
+    // The tasks start at the waves after those holding design points, so that these
+    // waves get the fewest tasks (none for TT = 8) and form their points' pose and
+    // stencil meanwhile.
     int bo[3];
     box_origin<2>(D, B0s, bo);
     const long long N = g.N;
     constexpr int LPN = 4;
-    for (int task = tid; task < PE * PE * LPN; task += NT) {
+    const int pt = (tid + NT - NW * 64) % NT;
+    for (int task = pt; task < PE * PE * LPN; task += NT) {
         const int node = task / LPN, q = task % LPN;
         const int px = node % PE, py = node / PE;
         const int x[3] = {ox + px, oy + py, 0};
@@ -927,6 +925,15 @@ __global__ __launch_bounds__(It2<TT>::NT) void k_iter2d(Grid g, Design D, BodyPa
             up[0][py][px] = v0;
             up[1][py][px] = v1;
         }
+    }
+    // own point's pose and stencil
+    Pose P;
+    Taps<2, T> tp;
+    if (own) {
+        double xi[3];
+        design_xi<2>(D, m, xi);
+        pose_point(D, Bs, xi, P);
+        tp.init(g, P.X, false);
     }
     __syncthreads();
     // interpolation at the tile's points, force and torque terms
