@@ -483,8 +483,9 @@ template <typename V> __device__ __forceinline__ V sel4(const V v[4], int i) {
 }
 
 // ------------------------------------------------------------------ block reduction
+// Thread j < NV stores the block's sum of v[j] (plus its `add`, when given).
 template <int NV, int NTHR>
-__device__ __forceinline__ void block_reduce_store(double v[NV], double *__restrict__ out) {
+__device__ __forceinline__ void block_reduce_store(double v[NV], double *__restrict__ out, const double *add = nullptr) {
     __shared__ double red[NV][NTHR / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -497,7 +498,7 @@ __device__ __forceinline__ void block_reduce_store(double v[NV], double *__restr
         double s = 0.0;
 #pragma unroll
         for (int w = 0; w < NTHR / 64; w++) s += red[threadIdx.x][w];
-        out[(long long)blockIdx.x * NV + threadIdx.x] = s;
+        out[(long long)blockIdx.x * NV + threadIdx.x] = add ? *add + s : s;
     }
 }
 
@@ -1121,22 +1122,67 @@ __device__ __forceinline__ void pose_rev(const Design &D, const double *B, const
 }
 
 template <int DIM, int NTHR>
-__device__ __forceinline__ void rec_finish(const BodyParams &bp, int k, const double *part1, const double *part3,
-                                           unsigned nb, const double *rin, double *rs);
+__device__ __forceinline__ void rec_finish(const BodyParams &bp, int k, const double *parts, unsigned nb,
+                                           const double *rin, double *rs);
+
+// Record step of iteration k by one wave: the same as rec_finish, with the partials summed
+// by the wave alone (lane l adds the blocks l, l + 64, ... compensated, four blocks' loads
+// in flight, then a fixed xor tree), so the other waves of the block need not wait. rs
+// complete after a barrier.
+template <int DIM>
+__device__ __forceinline__ void wave_rec_finish(const BodyParams &bp, int k, const double *parts, unsigned nb,
+                                                const double *rin, double *rs) {
+    const unsigned lane = threadIdx.x & 63;
+    Kahan s[8];
+    for (unsigned b0 = lane; b0 < nb; b0 += 256) {
+        double v[4][8];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const unsigned b = b0 + u * 64;
+#pragma unroll
+            for (int j = 0; j < 8; j++) v[u][j] = b < nb ? parts[(size_t)b * 8 + j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+#pragma unroll
+            for (int j = 0; j < 8; j++) s[j].add(v[u][j]);
+    }
+    double bb[B_REC];
+#pragma unroll
+    for (int j = 0; j < B_REC; j++) bb[j] = j < 8 ? wave_sum(s[j].value()) : 0.0;
+    if (lane == 0) {
+        for (int j = 0; j < AR_SIZE; j++) rs[j] = rin[j];
+        if (k > 0) {
+            body_update_rev<DIM>(bp, bb, rs + AR_FTB, rs + AR_ACC);
+        } else {
+            double *acc = rs + AR_ACC;
+            for (int j = 0; j < 8; j++) acc[j] += bb[j];
+            for (int j = 0; j < B_REC; j++) {
+                rs[AR_BBAR + j] = acc[j];
+                acc[j] = 0.0;
+            }
+            body_update_rev<DIM>(bp, rs + AR_BBAR, rs + AR_FTB, acc);
+        }
+    }
+}
+
+// Threads of an R1 block: one per design point, plus in 2D a wave that steps the record.
+template <int DIM> struct R1blk {
+    static constexpr int pts = Dblk<DIM>::v, v = pts + (DIM == 2 ? 64 : 0);
+};
 
 // R1: reverse of the force/torque and of the interpolation at iteration k. The
 // force/torque cotangent comes from the record rin, or, with pnb > 0, every block first
-// finishes the previous iteration kfin from its pnb R1 and R3 partials (pp1, pp3; the
-// same fixed-order sum and record step in every block, so the same bits) and block 0
+// finishes the previous iteration kfin from its pnb partials pp (R1's and R3's summed by
+// R3; the same fixed-order sum and record step in every block, so the same bits) and block 0
 // stores the stepped record in rout (rin and rout are distinct, since other blocks may
-// still read rin).
+// still read rin). In 2D the block's extra wave does that while the others interpolate.
 template <int DIM, typename T, bool TL = false>
-__global__ __launch_bounds__(Dblk<DIM>::v) void k_adj_r1(Grid g, Design D, BodyParams bp, const double *__restrict__ Bk,
+__global__ __launch_bounds__(R1blk<DIM>::v) void k_adj_r1(Grid g, Design D, BodyParams bp, const double *__restrict__ Bk,
                                                  int k,
                                                  const T *__restrict__ uk, const double *__restrict__ krD,
                                                  const double *__restrict__ rin, double *__restrict__ rout,
-                                                 const double *__restrict__ pp1, const double *__restrict__ pp3,
-                                                 unsigned pnb, int kfin, T *__restrict__ URb,
+                                                 const double *__restrict__ pp, unsigned pnb, int kfin, T *__restrict__ URb,
                                                  double *__restrict__ krb, double *__restrict__ part) {
     __shared__ double rs[AR_SIZE];
     // The record step runs first in 3D (keeps the registers of the long tap loops
@@ -1144,7 +1190,7 @@ __global__ __launch_bounds__(Dblk<DIM>::v) void k_adj_r1(Grid g, Design D, BodyP
     constexpr bool EARLY = DIM == 3;
     const double *FTb = rin + AR_FTB;
     if (EARLY && pnb > 0) {
-        rec_finish<DIM, Dblk<DIM>::v>(bp, kfin, pp1, pp3, pnb, rin, rs);
+        rec_finish<DIM, Dblk<DIM>::v>(bp, kfin, pp, pnb, rin, rs);
         FTb = rs + AR_FTB;
         if (blockIdx.x == 0 && threadIdx.x < AR_SIZE) rout[threadIdx.x] = rs[threadIdx.x];
     }
@@ -1171,8 +1217,8 @@ __global__ __launch_bounds__(Dblk<DIM>::v) void k_adj_r1(Grid g, Design D, BodyP
         m = t.m;
         own = t.own;
     } else {
-        m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-        own = m < D.ND;
+        m = (long long)blockIdx.x * R1blk<DIM>::pts + threadIdx.x;
+        own = threadIdx.x < R1blk<DIM>::pts && m < D.ND;
     }
     // interpolation of u^(k) at the point (independent of the record)
     Pose P;
@@ -1224,7 +1270,8 @@ __global__ __launch_bounds__(Dblk<DIM>::v) void k_adj_r1(Grid g, Design D, BodyP
         }
     }
     if (!EARLY && pnb > 0) {
-        rec_finish<DIM, Dblk<DIM>::v>(bp, kfin, pp1, pp3, pnb, rin, rs);
+        if (threadIdx.x >= R1blk<DIM>::pts) wave_rec_finish<DIM>(bp, kfin, pp, pnb, rin, rs);
+        __syncthreads();
         FTb = rs + AR_FTB;
         if (blockIdx.x == 0 && threadIdx.x < AR_SIZE) rout[threadIdx.x] = rs[threadIdx.x];
     }
@@ -1275,7 +1322,7 @@ __global__ __launch_bounds__(Dblk<DIM>::v) void k_adj_r1(Grid g, Design D, BodyP
         for (int e = 0; e < DIM; e++) Xb[e] = (double)xb[e];
         pose_rev(D, B, P, Xb, USb, rb, v);
     }
-    block_reduce_store<8, Dblk<DIM>::v>(v, part);
+    block_reduce_store<8, R1blk<DIM>::v>(v, part);
 }
 
 // R2: box nodes. u^(k) cotangent = (k = last: the step's velocity cotangent, with the
@@ -1350,19 +1397,20 @@ __global__ __launch_bounds__(256) void k_adj_r2(Grid g, Bc bc, Design D, const d
     kb[l] = kbar;
 }
 
-template <int DIM, int NTHR>
-__device__ __forceinline__ void r3_finish(const BodyParams &bp, int k, const double *part1, const double *part3,
-                                          unsigned nb, double *rec);
-
 // R3: transpose of the spread at iteration k (design-point parallel), the pose
-// reversed; its partials and R1's form the body cotangent B^(k)bar (rec_finish, in the
-// next R1 or in k_r3_finish).
+// reversed. Block b stores its partial plus R1's partial b (part1) in part3: their sum
+// over the blocks is the body cotangent B^(k)bar (rec_finish, in the next R1 or in
+// k_r3_finish).
 template <int DIM, typename T>
 __global__ __launch_bounds__(Dblk<DIM>::v) void k_adj_r3(Grid g, Design D, const double *__restrict__ Bk, int k,
                                                  const T *__restrict__ kb, const T *__restrict__ usb,
                                                  const double *__restrict__ krD, double *__restrict__ krb,
-                                                 double *__restrict__ part3) {
+                                                 const double *__restrict__ part1, double *__restrict__ part3) {
     const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    // R1's partial of this block, added to this block's at the end: requested first in 2D;
+    // in 3D, held across the tap loop, the early load slowed the kernel
+    const bool p1t = threadIdx.x < 8;
+    double p1v = (DIM == 2 && p1t) ? part1[(long long)blockIdx.x * 8 + threadIdx.x] : 0.0;
     const long long bN = D.boxN;
     const double *B = Bk + k * B_REC;
     double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -1414,20 +1462,21 @@ __global__ __launch_bounds__(Dblk<DIM>::v) void k_adj_r3(Grid g, Design D, const
         }
         pose_rev(D, B, P, Xb, USb, rb, v);
     }
-    block_reduce_store<8, Dblk<DIM>::v>(v, part3);
+    if (DIM == 3 && p1t) p1v = part1[(long long)blockIdx.x * 8 + threadIdx.x];
+    block_reduce_store<8, Dblk<DIM>::v>(v, part3, &p1v);
 }
 
-// Body cotangent B^(k)bar from the R1 and R3 partials of iteration k (fixed order), then
+// Body cotangent B^(k)bar from the partials of iteration k (fixed order), then
 // the record step on a copy of rin in rs (shared or global memory; rs may be rin): the
 // force/torque cotangent of iteration k-1, or at k = 0 the cotangent of B(t-1) and the
 // force/torque cotangent of the previous step's last iteration. Every thread of the
 // block calls it; rs is complete on return.
 template <int DIM, int NTHR>
-__device__ __forceinline__ void rec_finish(const BodyParams &bp, int k, const double *part1, const double *part3,
-                                           unsigned nb, const double *rin, double *rs) {
+__device__ __forceinline__ void rec_finish(const BodyParams &bp, int k, const double *parts, unsigned nb,
+                                           const double *rin, double *rs) {
     __shared__ double Bkb[8];
     if (rs != rin && threadIdx.x < AR_SIZE) rs[threadIdx.x] = rin[threadIdx.x];  // published by the barriers below
-    reduce_partials<8, NTHR>(part1, part3, nb, Bkb);
+    reduce_partials<8, NTHR>(parts, nullptr, nb, Bkb);
     if (threadIdx.x == 0) {
         double bb[B_REC];
         for (int j = 0; j < B_REC; j++) bb[j] = j < 8 ? Bkb[j] : 0.0;
@@ -1449,10 +1498,9 @@ __device__ __forceinline__ void rec_finish(const BodyParams &bp, int k, const do
 // One block: the record step of iteration k in place (rec_finish), for grids whose R1
 // would read too many partials per block, and after the last iteration.
 template <int DIM>
-__global__ __launch_bounds__(1024) void k_r3_finish(BodyParams bp, int k, const double *__restrict__ part1,
-                                                   const double *__restrict__ part3, unsigned nb,
-                                                   double *__restrict__ rec) {
-    rec_finish<DIM, 1024>(bp, k, part1, part3, nb, rec, rec);
+__global__ __launch_bounds__(1024) void k_r3_finish(BodyParams bp, int k, const double *__restrict__ parts,
+                                                   unsigned nb, double *__restrict__ rec) {
+    rec_finish<DIM, 1024>(bp, k, parts, nb, rec, rec);
 }
 
 // grad = krb * d kappa_ref / d gamma; optional body cotangent of t = 0.

@@ -372,7 +372,7 @@ Layout layout(const Ctx &c, bool adjoint) {
         L.usb = take(d * bN * e);
         L.URb = take(d * ND * e);
         L.krb = take(ND * 8);
-        L.part1 = take(2 * (size_t)c.nblk * 8 * 8);  // two buffers (see Run::body_rev)
+        L.part1 = take((size_t)c.nblk * 8 * 8);
         L.part3 = take((size_t)c.nblk * 8 * 8);
         L.rec = take(2 * AR_SIZE * 8);
     }
@@ -436,13 +436,13 @@ template <typename T> struct Run {
     T *ax = nullptr;  // 3D: axial sums of kappa_ref (k_axial), one pose per iteration run
 
     // Adjoint record (body_rev): two copies, since an R1 that steps the record reads one
-    // and writes the other (rcur: the current one); R1 partial buffers alternate (p1cur:
-    // the one the next R1 writes); pend: the iteration whose partials still wait for
-    // their record step, or -1.
-    mutable int rcur = 0, p1cur = 0, pend = -1;
+    // and writes the other (rcur: the current one); pend: the iteration whose partials
+    // (part3) still wait for their record step, or -1.
+    mutable int rcur = 0, pend = -1;
     // The next R1 steps the record itself (every block reads all partials) on small
-    // grids; larger ones use k_r3_finish after each R3.
-    bool defer_finish() const { return c.nblk <= 256; }
+    // grids (in 2D a dedicated wave per block, overlapped with the interpolation);
+    // larger ones use k_r3_finish after each R3.
+    bool defer_finish() const { return c.nblk <= (c.dim == 2 ? 1024 : 256); }
 
     // The cross-block finish of the design-point reductions runs in the last block to
     // arrive while the grid is small; beyond that the arrival counter serialises the
@@ -566,8 +566,7 @@ template <typename T> struct Run {
                   void *w) const {
         T *kapk = at<T>(w, L.kapk), *usk = at<T>(w, L.usk), *uk = at<T>(w, L.uk);
         T *ustb = at<T>(w, L.ustb), *kb = at<T>(w, L.kb), *usb = at<T>(w, L.usb), *URb = at<T>(w, L.URb);
-        double *krb = at<double>(w, L.krb), *p3 = at<double>(w, L.part3);
-        auto p1b = [&](int b) { return at<double>(w, L.part1) + (size_t)b * c.nblk * 8; };
+        double *krb = at<double>(w, L.krb), *p1 = at<double>(w, L.part1), *p3 = at<double>(w, L.part3);
         auto recb = [&](int b) { return at<double>(w, L.rec) + (size_t)b * AR_SIZE; };
         T *AU = at<T>(w, L.AU);
         const dim3 gb(blocks(c.D.boxN * (c.dim == 2 ? 4 : 1), 256), c.K);
@@ -586,27 +585,25 @@ template <typename T> struct Run {
             });
             for (int k = c.K - 1; k >= 0; k--) {
                 // record step of the pending iteration inside this R1 (reads recb(rcur) and
-                // the other partial buffer, writes recb(1 - rcur))
+                // the partials in p3, writes recb(1 - rcur))
                 const bool fin = pend >= 0;
                 const double *rin = recb(rcur);
                 double *rout = recb(1 - rcur);
-                const double *pp1 = p1b(1 - p1cur);
                 const unsigned pnb = fin ? (unsigned)c.nblk : 0u;
                 const int kfin = pend;
-                double *p1 = p1b(p1cur);
                 pf->run(LKS_K_ADJ_R1, [&](hipEvent_t e0, hipEvent_t e1) {
                     bool done = false;
                     if constexpr (DIM == 3 && std::is_same<T, float>::value) {
                         if (c.tile3) {
                             hipExtLaunchKernelGGL((k_adj_r1<DIM, T, true>), dim3(c.nblk), dim3(c.dblk), 0, st, e0, e1, 0,
-                                                  c.g, c.D, c.bp, Bk, k, uk, krD, rin, rout, pp1, (const double *)p3,
+                                                  c.g, c.D, c.bp, Bk, k, uk, krD, rin, rout, (const double *)p3,
                                                   pnb, kfin, URb, krb, p1);
                             done = true;
                         }
                     }
                     if (!done)
-                        hipExtLaunchKernelGGL((k_adj_r1<DIM, T>), dim3(c.nblk), dim3(c.dblk), 0, st, e0, e1, 0, c.g,
-                                              c.D, c.bp, Bk, k, uk, krD, rin, rout, pp1, (const double *)p3, pnb, kfin,
+                        hipExtLaunchKernelGGL((k_adj_r1<DIM, T>), dim3(c.nblk), dim3(R1blk<DIM>::v), 0, st, e0, e1, 0, c.g,
+                                              c.D, c.bp, Bk, k, uk, krD, rin, rout, (const double *)p3, pnb, kfin,
                                               URb, krb, p1);
                 });
                 if (fin) {
@@ -627,13 +624,12 @@ template <typename T> struct Run {
                 pf->run(LKS_K_ADJ_R3, [&](hipEvent_t e0, hipEvent_t e1) {
                     const bool d = defer_finish();
                     hipExtLaunchKernelGGL((k_adj_r3<DIM, T>), dim3(c.nblk), dim3(c.dblk), 0, st, e0, d ? e1 : nullptr, 0,
-                                          c.g, c.D, Bk, k, kb, usb, krD, krb, p3);
+                                          c.g, c.D, Bk, k, kb, usb, krD, krb, (const double *)p1, p3);
                     if (!d)
                         hipExtLaunchKernelGGL((k_r3_finish<DIM>), dim3(1), dim3(1024), 0, st, nullptr, e1, 0, c.bp, k,
-                                              (const double *)p1, (const double *)p3, (unsigned)c.nblk, recb(rcur));
+                                              (const double *)p3, (unsigned)c.nblk, recb(rcur));
                 });
                 if (defer_finish()) pend = k;
-                p1cur = 1 - p1cur;
             }
         });
     }
@@ -641,12 +637,11 @@ template <typename T> struct Run {
     double *rev_flush(const Layout &L, void *w) const {
         double *rec = at<double>(w, L.rec) + (size_t)rcur * AR_SIZE;
         if (pend >= 0) {
-            const double *pp1 = at<double>(w, L.part1) + (size_t)(1 - p1cur) * c.nblk * 8;
             const double *p3 = at<double>(w, L.part3);
             if (c.dim == 2)
-                hipLaunchKernelGGL(k_r3_finish<2>, dim3(1), dim3(1024), 0, st, c.bp, pend, pp1, p3, (unsigned)c.nblk, rec);
+                hipLaunchKernelGGL(k_r3_finish<2>, dim3(1), dim3(1024), 0, st, c.bp, pend, p3, (unsigned)c.nblk, rec);
             else
-                hipLaunchKernelGGL(k_r3_finish<3>, dim3(1), dim3(1024), 0, st, c.bp, pend, pp1, p3, (unsigned)c.nblk, rec);
+                hipLaunchKernelGGL(k_r3_finish<3>, dim3(1), dim3(1024), 0, st, c.bp, pend, p3, (unsigned)c.nblk, rec);
             pend = -1;
         }
         return rec;
