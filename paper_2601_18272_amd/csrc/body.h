@@ -185,6 +185,44 @@ __device__ __forceinline__ void gather_design(const Design &D, const double *B, 
     }
 }
 
+// 2D form of gather_design (rotation about z: plane axes 0, 1) for sums over design
+// arrays: the NC candidates of lane q are listed first (index m and weight w; w = 0 and
+// m = 0 for the candidates gather_design skips), so that the caller can issue all their
+// loads at once. Summed in list order, zero terms included, the result equals
+// gather_design's.
+template <typename T, bool ROT, int LPN> struct Cand2 {
+    static constexpr int PW = ROT ? 6 : 4, P0 = ROT ? -2 : -1, NC = (PW * PW + LPN - 1) / LPN;
+    long long m[NC];
+    T w[NC];
+    __device__ __forceinline__ void init(const Design &D, const double *B, const int x[3], int q) {
+        const double c = B[B_COS], s = B[B_SIN];
+        const double d0 = (double)x[0] - B[B_XG + 0], d1 = (double)x[1] - B[B_XG + 1];
+        const double xi0[2] = {c * d0 + s * d1, -s * d0 + c * d1};
+        int ib[2];
+        T fr[2];
+#pragma unroll
+        for (int a = 0; a < 2; a++) {
+            const double i0 = xi0[a] + D.half[a];
+            const double fl = floor(i0);
+            ib[a] = (int)fmax(fmin(fl, 1.0e9), -1.0e9);
+            fr[a] = T(i0 - fl);
+        }
+        const T cc = T(c), ss = T(s);
+#pragma unroll
+        for (int it = 0; it < NC; it++) {
+            const int cidx = q + it * LPN;
+            const int u = cidx / PW, v = cidx - u * PW;
+            const int ii = ib[0] + P0 + u, jj = ib[1] + P0 + v;
+            const T ei = T(P0 + u) - fr[0], ej = T(P0 + v) - fr[1];
+            const T ri = -(cc * ei - ss * ej), rj = -(ss * ei + cc * ej);
+            const bool ok = cidx < PW * PW && ii >= 0 && ii < D.nd[0] && jj >= 0 && jj < D.nd[1] &&
+                            fabs(ri) < T(2) && fabs(rj) < T(2);
+            w[it] = ok ? wk(ri) * wk(rj) : T(0);
+            m[it] = ok ? ii + (long long)D.nd[0] * jj : 0;
+        }
+    }
+};
+
 // Sum over the LPN lanes of a group (xor tree, identical result in every lane).
 template <int LPN, typename V> __device__ __forceinline__ V lane_sum(V v) {
     if (LPN >= 2) v += __shfl_xor(v, 1, 64);
@@ -1371,10 +1409,19 @@ __global__ __launch_bounds__(256) void k_adj_r2(Grid g, Bc bc, Design D, const d
             for (int a = 0; a < 3; a++) ub[a] += W * AU[a * NANP + i];
         });
     } else {
-        gather_design<DIM, T, ROT, LPN>(D, Bk + k * B_REC, x, d, q, [&](long long m, T W, const T *, const int *) {
+        // candidates listed first, then all their loads in flight together
+        Cand2<T, ROT, LPN> cd;
+        cd.init(D, Bk + k * B_REC, x, q);
+        T v[2][Cand2<T, ROT, LPN>::NC];
 #pragma unroll
-            for (int a = 0; a < DIM; a++) ub[a] += W * URb[a * D.ND + m];
-        });
+        for (int it = 0; it < Cand2<T, ROT, LPN>::NC; it++)
+#pragma unroll
+            for (int a = 0; a < 2; a++) v[a][it] = URb[a * D.ND + cd.m[it]];
+#pragma unroll
+        for (int it = 0; it < Cand2<T, ROT, LPN>::NC; it++)
+#pragma unroll
+            for (int a = 0; a < 2; a++) ub[a] += cd.w[it] * v[a][it];
+        (void)d;
     }
 #pragma unroll
     for (int a = 0; a < DIM; a++) ub[a] = lane_sum<LPN>(ub[a]);
