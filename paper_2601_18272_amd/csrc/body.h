@@ -369,16 +369,34 @@ __device__ __forceinline__ int gather_plane(const Design &D, const double *B, co
     const int ib = x[D.axis] + ax.fl;
     if (ib < -2 || ib > D.nd[D.axis] + 1) return ib;  // no design point along the axis
     const T cc = T(c), ss = T(s);
-    constexpr int PW = ROT ? 6 : 4, P0 = ROT ? -2 : -1;
+    constexpr int PW = ROT ? 6 : 4, P0 = ROT ? -2 : -1, NC = (PW * PW + LPN - 1) / LPN;
     const int ni = D.nd[D.pi], nj = D.nd[D.pj];
-    for (int cidx = q; cidx < PW * PW; cidx += LPN) {
-        const int u = cidx / PW, v = cidx - u * PW;
-        const int ii = bi + P0 + u, jj = bj + P0 + v;
-        if (ii < 0 || ii >= ni || jj < 0 || jj >= nj) continue;
-        const T ei = T(P0 + u) - fri, ej = T(P0 + v) - frj;
-        const T rp = -(cc * ei - ss * ej), rq = -(ss * ei + cc * ej);
-        if (!(fabs(rp) < T(2) && fabs(rq) < T(2))) continue;
-        f(wk(rp) * wk(rq), ii + (long long)ni * jj, rp, rq);
+    if constexpr (ROT) {
+        // rotated window: about half of the 36 candidates lie outside the support
+        for (int cidx = q; cidx < PW * PW; cidx += LPN) {
+            const int u = cidx / PW, v = cidx - u * PW;
+            const int ii = bi + P0 + u, jj = bj + P0 + v;
+            if (ii < 0 || ii >= ni || jj < 0 || jj >= nj) continue;
+            const T ei = T(P0 + u) - fri, ej = T(P0 + v) - frj;
+            const T rp = -(cc * ei - ss * ej), rq = -(ss * ei + cc * ej);
+            if (!(fabs(rp) < T(2) && fabs(rq) < T(2))) continue;
+            f(wk(rp) * wk(rq), ii + (long long)ni * jj, rp, rq);
+        }
+    } else {
+        // axis-aligned window: without branches, unrolled by rows; a skipped candidate is
+        // visited with W = 0 at p = 0, so that the callers' loads of a row are in flight
+        // together (the sums are unchanged)
+#pragma unroll PW
+        for (int it = 0; it < NC; it++) {
+            const int cidx = q + it * LPN;
+            const int u = cidx / PW, v = cidx - u * PW;
+            const int ii = bi + P0 + u, jj = bj + P0 + v;
+            const T ei = T(P0 + u) - fri, ej = T(P0 + v) - frj;
+            const T rp = -(cc * ei - ss * ej), rq = -(ss * ei + cc * ej);
+            const bool ok = cidx < PW * PW && ii >= 0 && ii < ni && jj >= 0 && jj < nj && fabs(rp) < T(2) &&
+                            fabs(rq) < T(2);
+            f(ok ? wk(rp) * wk(rq) : T(0), ok ? ii + (long long)ni * jj : 0LL, rp, rq);
+        }
     }
     return ib;
 }
