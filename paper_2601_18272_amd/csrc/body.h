@@ -352,9 +352,12 @@ __global__ __launch_bounds__(256) void k_axial(Design D, const double *__restric
 }
 
 // Plane candidates of node x (3D, gather form, LPN lanes): f(W, plane index p, r_pi, r_pj)
-// for every design column (ii, jj) whose plane weight is nonzero. Returns the node's axial
-// base ib and fills d = x - x^G.
-template <typename T, bool ROT, int LPN, typename F>
+// for every design column (ii, jj) whose plane weight is nonzero, and for others with
+// W = 0 at p = 0 (their terms vanish). Returns the node's axial base ib and fills
+// d = x - x^G. Plane indices and axial-sum offsets fit in int (checked on the host).
+// BATCH (rotated window, one lane per node): rows without branches, for callers whose
+// loads per candidate dominate.
+template <typename T, bool ROT, int LPN, bool BATCH = false, typename F>
 __device__ __forceinline__ int gather_plane(const Design &D, const double *B, const Axial &ax, const int x[3],
                                             double d[3], int q, F &&f) {
     const double c = B[B_COS], s = B[B_SIN];
@@ -371,7 +374,35 @@ __device__ __forceinline__ int gather_plane(const Design &D, const double *B, co
     const T cc = T(c), ss = T(s);
     constexpr int PW = ROT ? 6 : 4, P0 = ROT ? -2 : -1, NC = (PW * PW + LPN - 1) / LPN;
     const int ni = D.nd[D.pi], nj = D.nd[D.pj];
-    if constexpr (ROT) {
+    if constexpr (ROT && LPN == 1 && BATCH) {
+        // rotated window, row by row: the column terms are formed once per node and a
+        // row's six candidates run without branches (a skipped one with W = 0 at p = 0),
+        // so that the row's loads are in flight together
+        T sej[PW], cej[PW];
+        int jjv[PW];
+        bool okv[PW];
+#pragma unroll
+        for (int v = 0; v < PW; v++) {
+            const T ej = T(P0 + v) - frj;
+            sej[v] = ss * ej;
+            cej[v] = cc * ej;
+            jjv[v] = bj + P0 + v;
+            okv[v] = jjv[v] >= 0 && jjv[v] < nj;
+        }
+#pragma unroll 1
+        for (int u = 0; u < PW; u++) {
+            const int ii = bi + P0 + u;
+            const bool oku = ii >= 0 && ii < ni;
+            const T ei = T(P0 + u) - fri;
+            const T cei = cc * ei, sei = ss * ei;
+#pragma unroll
+            for (int v = 0; v < PW; v++) {
+                const T rp = -(cei - sej[v]), rq = -(sei + cej[v]);
+                const bool ok = oku && okv[v] && fabs(rp) < T(2) && fabs(rq) < T(2);
+                f(ok ? wk(rp) * wk(rq) : T(0), ok ? ii + ni * jjv[v] : 0, rp, rq);
+            }
+        }
+    } else if constexpr (ROT) {
         // rotated window: about half of the 36 candidates lie outside the support
         for (int cidx = q; cidx < PW * PW; cidx += LPN) {
             const int u = cidx / PW, v = cidx - u * PW;
@@ -380,7 +411,7 @@ __device__ __forceinline__ int gather_plane(const Design &D, const double *B, co
             const T ei = T(P0 + u) - fri, ej = T(P0 + v) - frj;
             const T rp = -(cc * ei - ss * ej), rq = -(ss * ei + cc * ej);
             if (!(fabs(rp) < T(2) && fabs(rq) < T(2))) continue;
-            f(wk(rp) * wk(rq), ii + (long long)ni * jj, rp, rq);
+            f(wk(rp) * wk(rq), ii + ni * jj, rp, rq);
         }
     } else {
         // axis-aligned window: without branches, unrolled by rows; a skipped candidate is
@@ -395,7 +426,7 @@ __device__ __forceinline__ int gather_plane(const Design &D, const double *B, co
             const T rp = -(cc * ei - ss * ej), rq = -(ss * ei + cc * ej);
             const bool ok = cidx < PW * PW && ii >= 0 && ii < ni && jj >= 0 && jj < nj && fabs(rp) < T(2) &&
                             fabs(rq) < T(2);
-            f(ok ? wk(rp) * wk(rq) : T(0), ok ? ii + (long long)ni * jj : 0LL, rp, rq);
+            f(ok ? wk(rp) * wk(rq) : T(0), ok ? ii + ni * jj : 0, rp, rq);
         }
     }
     return ib;
@@ -409,7 +440,7 @@ __device__ __forceinline__ void spread_node_ax(const Design &D, const double *B,
     double d[3];
     T k = 0, phi = 0, wp = 0, wq = 0;
     const int ib = x[D.axis] + ax.fl;
-    gather_plane<T, ROT, LPN>(D, B, ax, x, d, q, [&](T W, long long p, T rp, T rq) {
+    gather_plane<T, ROT, LPN>(D, B, ax, x, d, q, [&](T W, int p, T rp, T rq) {
         k += W * K1[(ib + 2) + NA * p];
         phi += W;
         wp += W * rp;
@@ -1421,8 +1452,8 @@ __global__ __launch_bounds__(256) void k_adj_r2(Grid g, Bc bc, Design D, const d
         const int NA = D.nd[D.axis] + 4;
         const long long NANP = (long long)NA * D.nd[D.pi] * D.nd[D.pj];
         const int ib = x[D.axis] + ax.fl;
-        gather_plane<T, ROT, LPN>(D, Bk + k * B_REC, ax, x, d, q, [&](T W, long long p, T, T) {
-            const long long i = (ib + 2) + NA * p;
+        gather_plane<T, ROT, LPN, true>(D, Bk + k * B_REC, ax, x, d, q, [&](T W, int p, T, T) {
+            const int i = (ib + 2) + NA * p;
 #pragma unroll
             for (int a = 0; a < 3; a++) ub[a] += W * AU[a * NANP + i];
         });
