@@ -234,12 +234,13 @@ template <int LPN, typename V> __device__ __forceinline__ V lane_sum(V v) {
 template <int DIM>
 __device__ __forceinline__ bool box_node(const Grid &g, const Design &D, const int o[3], long long l,
                                          int x[3]) {
-    long long r = l;
+    unsigned r = (unsigned)l;  // boxN < 2^31 (checked on the host): 32-bit division
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         if (a < DIM) {
-            x[a] = o[a] + (int)(r % D.L[a]);
-            r /= D.L[a];
+            const unsigned L = (unsigned)D.L[a], q = r / L;
+            x[a] = o[a] + (int)(r - q * L);
+            r = q;
         } else {
             x[a] = 0;
         }
@@ -329,11 +330,13 @@ __global__ __launch_bounds__(256) void k_axial(Design D, const double *__restric
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= NA * NP) return;
     const Axial ax = axial_of(D, Bk + (k0 + blockIdx.y) * B_REC);
-    const int ib = (int)(t % NA) - 2;
-    const long long p = t / NA;
+    // NA * NP < 2^31 (checked on the host): 32-bit division
+    const unsigned tu = (unsigned)t, pu = tu / (unsigned)NA, ni = (unsigned)D.nd[D.pi];
+    const int ib = (int)(tu - pu * (unsigned)NA) - 2;
+    const long long p = pu;
     int idx[3];
-    idx[D.pi] = (int)(p % D.nd[D.pi]);
-    idx[D.pj] = (int)(p / D.nd[D.pi]);
+    idx[D.pi] = (int)(pu % ni);
+    idx[D.pj] = (int)(pu / ni);
     T acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; c++) acc[c] = T(0);

@@ -629,21 +629,23 @@ __global__ __launch_bounds__(512) void k_adjgather2d(Grid g, Bc bc, T A, const T
 
 // Node t of the layers `lay` and n_a - 1 - lay of the non-periodic axes a = 0, 1, 2 in
 // turn: t = (a, side, i, j) with side 0 for layer lay, and i, j over the other two axes
-// (the lower one fastest). Returns the axis, or -1 past the end.
-__device__ __forceinline__ int layer_node(const Grid &g, long long t, int lay, int x[3]) {
+// (the lower one fastest). Returns the axis, or -1 past the end. layer_count < 2^31
+// (checked on the host): 32-bit arithmetic.
+__device__ __forceinline__ int layer_node(const Grid &g, long long t64, int lay, int x[3]) {
+    unsigned t = (unsigned)t64;
     for (int a = 0; a < 3; a++) {
         const int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
-        const long long face = (long long)g.n[b] * g.n[c];
+        const unsigned nb = (unsigned)g.n[b], face = nb * (unsigned)g.n[c];
         if (g.per[a]) continue;
         if (t >= 2 * face) {
             t -= 2 * face;
             continue;
         }
-        const int side = (int)(t / face);
-        const long long r = t - side * face;
+        const unsigned side = t >= face ? 1u : 0u;
+        const unsigned r = t - side * face, q = r / nb;
         x[a] = side ? g.n[a] - 1 - lay : lay;
-        x[b] = (int)(r % g.n[b]);
-        x[c] = (int)(r / g.n[b]);
+        x[b] = (int)(r - q * nb);
+        x[c] = (int)q;
         return a;
     }
     return -1;
@@ -700,12 +702,14 @@ __global__ __launch_bounds__(256) void k_adj_clear3d(Grid g, T *__restrict__ ab,
     t -= m;
     if (!has_box || t >= D.boxN) return;
     // box node t: x = o + (t in the box's x-fastest order), on the grid and interior
+    // (boxN < 2^31: 32-bit division)
     int o[3];
     box_origin<3>(D, Bprev, o);
-    long long r = t;
+    unsigned r = (unsigned)t;
     for (int a = 0; a < 3; a++) {
-        x[a] = o[a] + (int)(r % D.L[a]);
-        r /= D.L[a];
+        const unsigned L = (unsigned)D.L[a], q = r / L;
+        x[a] = o[a] + (int)(r - q * L);
+        r = q;
         if (x[a] < 0 || x[a] >= g.n[a]) return;
     }
     if (!is_interior<3>(g, x)) return;

@@ -289,6 +289,8 @@ int make_ctx(const lks_problem_t *P, Ctx &c) {
     if (P->objective < 0 || P->objective > 3) return fail(LKS_EINVAL, "bad objective");
     if (P->objective < 3 && P->objective >= c.dim) return fail(LKS_EINVAL, "objective axis >= dim");
     if (c.has_body && D.boxN > 0x7fffffffLL) return fail(LKS_EINVAL, "design footprint box too large");
+    if (c.has_body && D.ND > 0x7fffffffLL) return fail(LKS_EINVAL, "design grid too large");
+    if (c.dim == 3 && layer_count(c.g.n, c.g.per) > 0x7fffffffLL) return fail(LKS_EINVAL, "grid faces too large");
     if (c.has_body && c.dim == 3 && (long long)(D.nd[D.axis] + 4) * D.nd[D.pi] * D.nd[D.pj] > 0x7fffffffLL)
         return fail(LKS_EINVAL, "design grid too large");
     c.dblk = c.dim == 3 ? Dblk<3>::v : Dblk<2>::v;

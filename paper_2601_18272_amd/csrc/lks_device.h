@@ -192,9 +192,10 @@ struct Pose {
 
 template <int DIM>
 __device__ __forceinline__ void design_xi(const Design &D, long long m, double xi[3]) {
-    const long long i = m % D.nd[0];
-    const long long j = (m / D.nd[0]) % D.nd[1];
-    const long long k = m / ((long long)D.nd[0] * D.nd[1]);
+    // ND < 2^31 (checked on the host): 32-bit division
+    const unsigned mu = (unsigned)m, n0 = (unsigned)D.nd[0], n1 = (unsigned)D.nd[1];
+    const unsigned r = mu / n0;
+    const unsigned i = mu - r * n0, j = r % n1, k = r / n1;
     xi[0] = (double)i - D.half[0];
     xi[1] = (double)j - D.half[1];
     xi[2] = DIM == 3 ? (double)k - D.half[2] : 0.0;
