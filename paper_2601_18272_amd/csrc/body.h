@@ -190,13 +190,18 @@ __device__ __forceinline__ void gather_design(const Design &D, const double *B, 
 // m = 0 for the candidates gather_design skips), so that the caller can issue all their
 // loads at once. Summed in list order, zero terms included, the result equals
 // gather_design's.
-template <typename T, bool ROT, int LPN> struct Cand2 {
+// With WR the offsets r (lab frame, as gather_design passes them) and d = x - x^G are kept.
+template <typename T, bool ROT, int LPN, bool WR = false> struct Cand2 {
     static constexpr int PW = ROT ? 6 : 4, P0 = ROT ? -2 : -1, NC = (PW * PW + LPN - 1) / LPN;
     long long m[NC];
     T w[NC];
+    T r0[WR ? NC : 1], r1[WR ? NC : 1];
+    double d[2];
     __device__ __forceinline__ void init(const Design &D, const double *B, const int x[3], int q) {
         const double c = B[B_COS], s = B[B_SIN];
         const double d0 = (double)x[0] - B[B_XG + 0], d1 = (double)x[1] - B[B_XG + 1];
+        d[0] = d0;
+        d[1] = d1;
         const double xi0[2] = {c * d0 + s * d1, -s * d0 + c * d1};
         int ib[2];
         T fr[2];
@@ -219,6 +224,10 @@ template <typename T, bool ROT, int LPN> struct Cand2 {
                             fabs(ri) < T(2) && fabs(rj) < T(2);
             w[it] = ok ? wk(ri) * wk(rj) : T(0);
             m[it] = ok ? ii + (long long)D.nd[0] * jj : 0;
+            if constexpr (WR) {
+                r0[it] = ri;
+                r1[it] = rj;
+            }
         }
     }
 };
@@ -285,7 +294,37 @@ __device__ __forceinline__ void spread_node_kr(const Design &D, const double *B,
 template <int DIM, typename T, bool ROT, int LPN = 1>
 __device__ __forceinline__ void spread_node(const Design &D, const double *B, const T *__restrict__ krT,
                                             const int x[3], int q, T &kap, T us[3]) {
-    spread_node_kr<DIM, T, ROT, LPN>(D, B, [&](long long m, const int *) { return krT[m]; }, x, q, kap, us);
+    if constexpr (DIM == 2) {
+        // candidates listed first (Cand2), then all their kappa_ref loads at once; the
+        // sums, zero terms included, equal spread_node_kr's
+        using C2 = Cand2<T, ROT, LPN, true>;
+        C2 cd;
+        cd.init(D, B, x, q);
+        T kv[C2::NC];
+#pragma unroll
+        for (int it = 0; it < C2::NC; it++) kv[it] = krT[cd.m[it]];
+        T k = 0, phi = 0, wr[2] = {0, 0};
+#pragma unroll
+        for (int it = 0; it < C2::NC; it++) {
+            const T W = cd.w[it];
+            k += W * kv[it];
+            phi += W;
+            wr[0] += W * cd.r0[it];
+            wr[1] += W * cd.r1[it];
+        }
+        k = lane_sum<LPN>(k);
+        phi = lane_sum<LPN>(phi);
+        wr[0] = lane_sum<LPN>(wr[0]);
+        wr[1] = lane_sum<LPN>(wr[1]);
+        const double armp = (double)phi * cd.d[0] - (double)wr[0], armq = (double)phi * cd.d[1] - (double)wr[1];
+        const double om = B[B_OM];
+        kap = k;
+        us[0] = T(B[B_UG + 0] * (double)phi + om * (-armq));
+        us[1] = T(B[B_UG + 1] * (double)phi + om * armp);
+        us[2] = T(0);
+    } else {
+        spread_node_kr<DIM, T, ROT, LPN>(D, B, [&](long long m, const int *) { return krT[m]; }, x, q, kap, us);
+    }
 }
 
 // ------------------------------------------------------------------ 3D axial sums
