@@ -190,12 +190,14 @@ __device__ __forceinline__ void gather_design(const Design &D, const double *B, 
 // m = 0 for the candidates gather_design skips), so that the caller can issue all their
 // loads at once. Summed in list order, zero terms included, the result equals
 // gather_design's.
-// With WR the offsets r (lab frame, as gather_design passes them) and d = x - x^G are kept.
+// With WR the offsets r (lab frame, as gather_design passes them), the design indices
+// (ci, cj) and d = x - x^G are kept.
 template <typename T, bool ROT, int LPN, bool WR = false> struct Cand2 {
     static constexpr int PW = ROT ? 6 : 4, P0 = ROT ? -2 : -1, NC = (PW * PW + LPN - 1) / LPN;
     long long m[NC];
     T w[NC];
     T r0[WR ? NC : 1], r1[WR ? NC : 1];
+    int ci[WR ? NC : 1], cj[WR ? NC : 1];
     double d[2];
     __device__ __forceinline__ void init(const Design &D, const double *B, const int x[3], int q) {
         const double c = B[B_COS], s = B[B_SIN];
@@ -227,6 +229,8 @@ template <typename T, bool ROT, int LPN, bool WR = false> struct Cand2 {
             if constexpr (WR) {
                 r0[it] = ri;
                 r1[it] = rj;
+                ci[it] = ii;
+                cj[it] = jj;
             }
         }
     }
@@ -291,40 +295,47 @@ __device__ __forceinline__ void spread_node_kr(const Design &D, const double *B,
     for (int a = 0; a < 3; a++) us[a] = a < DIM ? T(B[B_UG + a] * (double)phi + om * axa[a]) : T(0);
 }
 
+// 2D spread_node_kr with the candidates listed first (Cand2) and all their kappa_ref
+// values requested at once; kr(m, ii, jj) returns kappa_ref of design point m = (ii, jj)
+// (called for skipped candidates too, with weight 0). The sums, zero terms included,
+// equal spread_node_kr's.
+template <typename T, bool ROT, int LPN, typename KR>
+__device__ __forceinline__ void spread_node2(const Design &D, const double *B, KR &&kr, const int x[3], int q,
+                                             T &kap, T us[3]) {
+    using C2 = Cand2<T, ROT, LPN, true>;
+    C2 cd;
+    cd.init(D, B, x, q);
+    T kv[C2::NC];
+#pragma unroll
+    for (int it = 0; it < C2::NC; it++) kv[it] = kr(cd.m[it], cd.ci[it], cd.cj[it]);
+    T k = 0, phi = 0, wr[2] = {0, 0};
+#pragma unroll
+    for (int it = 0; it < C2::NC; it++) {
+        const T W = cd.w[it];
+        k += W * kv[it];
+        phi += W;
+        wr[0] += W * cd.r0[it];
+        wr[1] += W * cd.r1[it];
+    }
+    k = lane_sum<LPN>(k);
+    phi = lane_sum<LPN>(phi);
+    wr[0] = lane_sum<LPN>(wr[0]);
+    wr[1] = lane_sum<LPN>(wr[1]);
+    const double armp = (double)phi * cd.d[0] - (double)wr[0], armq = (double)phi * cd.d[1] - (double)wr[1];
+    const double om = B[B_OM];
+    kap = k;
+    us[0] = T(B[B_UG + 0] * (double)phi + om * (-armq));
+    us[1] = T(B[B_UG + 1] * (double)phi + om * armp);
+    us[2] = T(0);
+}
+
 template <int DIM, typename T, bool ROT, int LPN = 1>
 __device__ __forceinline__ void spread_node(const Design &D, const double *B, const T *__restrict__ krT,
                                             const int x[3], int q, T &kap, T us[3]) {
-    if constexpr (DIM == 2) {
-        // candidates listed first (Cand2), then all their kappa_ref loads at once; the
-        // sums, zero terms included, equal spread_node_kr's
-        using C2 = Cand2<T, ROT, LPN, true>;
-        C2 cd;
-        cd.init(D, B, x, q);
-        T kv[C2::NC];
-#pragma unroll
-        for (int it = 0; it < C2::NC; it++) kv[it] = krT[cd.m[it]];
-        T k = 0, phi = 0, wr[2] = {0, 0};
-#pragma unroll
-        for (int it = 0; it < C2::NC; it++) {
-            const T W = cd.w[it];
-            k += W * kv[it];
-            phi += W;
-            wr[0] += W * cd.r0[it];
-            wr[1] += W * cd.r1[it];
-        }
-        k = lane_sum<LPN>(k);
-        phi = lane_sum<LPN>(phi);
-        wr[0] = lane_sum<LPN>(wr[0]);
-        wr[1] = lane_sum<LPN>(wr[1]);
-        const double armp = (double)phi * cd.d[0] - (double)wr[0], armq = (double)phi * cd.d[1] - (double)wr[1];
-        const double om = B[B_OM];
-        kap = k;
-        us[0] = T(B[B_UG + 0] * (double)phi + om * (-armq));
-        us[1] = T(B[B_UG + 1] * (double)phi + om * armp);
-        us[2] = T(0);
-    } else {
+    if constexpr (DIM == 2)
+        spread_node2<T, ROT, LPN>(D, B, [&](long long m, int, int) { return krT[m]; }, x, q, kap, us);
+    else
         spread_node_kr<DIM, T, ROT, LPN>(D, B, [&](long long m, const int *) { return krT[m]; }, x, q, kap, us);
-    }
 }
 
 // ------------------------------------------------------------------ 3D axial sums
@@ -1038,11 +1049,11 @@ __global__ __launch_bounds__(It2<TT>::NT) void k_iter2d(Grid g, Design D, BodyPa
             const int lx = x[0] - bo[0], ly = x[1] - bo[1];
             if (lx >= 0 && lx < D.L[0] && ly >= 0 && ly < D.L[1]) {
                 T kap, us[3];
-                spread_node_kr<2, T, ROT, LPN>(
+                spread_node2<T, ROT, LPN>(
                     D, Bs,
-                    [&](long long, const int *idx) {
+                    [&](long long, int ii, int jj) {
                         // always inside the halo (see kh); the clamp only keeps the read in range
-                        const int li = min(max(idx[0] - hi0, 0), HE - 1), lj = min(max(idx[1] - hj0, 0), HE - 1);
+                        const int li = min(max(ii - hi0, 0), HE - 1), lj = min(max(jj - hj0, 0), HE - 1);
                         return kh[lj * HE + li];
                     },
                     x, q, kap, us);
