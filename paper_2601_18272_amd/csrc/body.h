@@ -946,34 +946,64 @@ __global__ __launch_bounds__(It2<TT>::NT) void k_iter2d(Grid g, Design D, BodyPa
     __shared__ T up[2][PE][PE];
     __shared__ T kh[HE * HE];
     const int tid = threadIdx.x;
-    // everything that does not depend on B^(k) is requested first: B(t-1), the point's
-    // kappa^ref, the kappa^ref halo; then the partials
-    if (tid < B_REC) B0s[tid] = Bk[tid];
+    // Every load is requested first, into registers: the previous iteration's partials
+    // (wave 0; nb <= 256), B(t-1), the point's kappa^ref, the kappa^ref halo. Stores into
+    // LDS come after, so that no load waits behind another's store.
+    double pv[4][4];
+    if (k > 0 && tid < 64) {
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const unsigned b = tid + 64u * u;
+#pragma unroll
+            for (int j = 0; j < 4; j++) pv[u][j] = b < nb ? part_in[(size_t)b * 4 + j] : 0.0;
+        }
+    }
+    const double b0v = tid < B_REC ? Bk[tid] : 0.0;
     const int tilesX = (D.nd[0] + TT - 1) / TT;
     const int ti = (int)blockIdx.x % tilesX, tj = (int)blockIdx.x / tilesX;
     const int mi = ti * TT + tid % TT, mj = tj * TT + tid / TT;
     const bool own = tid < TT * TT && mi < D.nd[0] && mj < D.nd[1];
     const long long m = own ? mi + (long long)D.nd[0] * mj : 0;
     const double kr = own ? krD[m] : 0.0;
-    // kappa^ref of the tile and a six-point halo, loaded while the partials are summed.
-    // A patch node x lies within 2 grid spacings (per axis) of a tile point p, so its
-    // body-frame position is within 2 sqrt 2 of xi_p, its window base within 3 of xi_p
-    // and its gather-form candidates (base - 2 .. base + 3) within 5 of xi_p.
+    // kappa^ref of the tile and a six-point halo. A patch node x lies within 2 grid
+    // spacings (per axis) of a tile point p, so its body-frame position is within 2 sqrt 2
+    // of xi_p, its window base within 3 of xi_p and its gather-form candidates (base - 2 ..
+    // base + 3) within 5 of xi_p.
     const int hi0 = ti * TT - 6, hj0 = tj * TT - 6;
-    for (int l = tid; l < HE * HE; l += NT) {
+    constexpr int KHT = (HE * HE + NT - 1) / NT;
+    T khv[KHT];
+#pragma unroll
+    for (int r = 0; r < KHT; r++) {
+        const int l = tid + r * NT;
         const int i = hi0 + l % HE, j = hj0 + l / HE;
-        kh[l] = (i >= 0 && i < D.nd[0] && j >= 0 && j < D.nd[1]) ? krT[i + (long long)D.nd[0] * j] : T(0);
+        khv[r] = (l < HE * HE && i >= 0 && i < D.nd[0] && j >= 0 && j < D.nd[1]) ? krT[i + (long long)D.nd[0] * j]
+                                                                               : T(0);
     }
-    // B^(k) in every thread's registers: B(t-1) at k = 0, else the Euler update with the
-    // fixed-order sum of iteration k-1's partials (reduce_partials ends with a barrier,
-    // which also publishes B0s)
+#pragma unroll
+    for (int r = 0; r < KHT; r++)
+        if (tid + r * NT < HE * HE) kh[tid + r * NT] = khv[r];
+    if (tid < B_REC) B0s[tid] = b0v;
+    // the fixed-order sum of iteration k-1's partials by wave 0 (lane l adds the vectors
+    // l, l + 64, l + 128, l + 192 compensated, then a fixed xor tree)
+    if (k > 0 && tid < 64) {
+        Kahan sk[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) sk[j].add(pv[u][j]);
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const double f = wave_sum(sk[j].value());
+            if (tid == 0) FT[j] = f;
+        }
+    }
+    __syncthreads();
+    // B^(k) in every thread's registers: B(t-1) at k = 0, else the Euler update
     double Bs[B_REC];
     if (k == 0) {
-        __syncthreads();
 #pragma unroll
         for (int j = 0; j < B_REC; j++) Bs[j] = B0s[j];
     } else {
-        reduce_partials<4, NT>(part_in, nullptr, nb, FT);
         const double ft[4] = {FT[0], FT[1], FT[2], FT[3]};
         double B0[B_REC];
 #pragma unroll
