@@ -84,6 +84,9 @@ def test_validation_errors_without_gpu(lib):
         pb.replace(nd=(10, 0, 1)),
         pb.replace(n=(2, 26, 1), bc=(W.VELOCITY, W.PRESSURE, 0, 0, 0, 0)),
         pb.replace(objective=2),
+        pb.replace(nd=(50000, 50000, 1)),  # footprint box and design grid beyond 32-bit indexing
+        W.small3d().replace(nd=(1400, 1400, 1400)),
+        W.small3d().replace(n=(65536, 65536, 8)),
     ]
     dummy = C.c_void_p(16)
     for b in bad:
