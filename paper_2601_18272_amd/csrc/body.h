@@ -924,15 +924,6 @@ template <int TT> struct It2 {
     static constexpr int NW = (TT * TT + 63) / 64;  // waves holding design points
 };
 
-// B^(k) (k >= 1) into shared memory from B(t-1) and the partials of iteration k-1.
-template <int DIM, int NTHR>
-__device__ __forceinline__ void body_from_partials(const BodyParams &bp, const double *B0, const double *part,
-                                                   unsigned nb, double *Bs, double *FT) {
-    reduce_partials<4, NTHR>(part, nullptr, nb, FT);
-    if (threadIdx.x == 0) body_update<DIM>(bp, B0, FT, Bs);
-    __syncthreads();
-}
-
 template <typename T, bool ROT, int TT>
 __global__ __launch_bounds__(It2<TT>::NT) void k_iter2d(Grid g, Design D, BodyParams bp, double *__restrict__ Bk,
                                                          int k, const T *__restrict__ krT,
@@ -1146,21 +1137,39 @@ __global__ __launch_bounds__(It2<TT>::NT) void k_iter2d(Grid g, Design D, BodyPa
     }
 }
 
-// Last step of the 2D loop: block 0 forms B^(K) from the partials of iteration K-1
-// (record, next step's first record, finiteness flag); all blocks spread at pose
-// B^(K-1) over the footprint box and write u <- (u* + kappa u^S) / (1 + kappa) into
-// the state, keeping u* in ustar.
+// Last step of the 2D loop: the last block (one beyond the box's) forms B^(K) from the
+// partials of iteration K-1 (record, next step's first record, finiteness flag), in
+// parallel with the others, which spread at pose B^(K-1) over the footprint box and write
+// u <- (u* + kappa u^S) / (1 + kappa) into the state, keeping u* in ustar.
 template <typename T, bool ROT, int LPN>
 __global__ __launch_bounds__(256) void k_iter_final2d(Grid g, Design D, BodyParams bp, double *__restrict__ Bk,
                                                       int K, const T *__restrict__ krT, T *__restrict__ u,
                                                       T *__restrict__ ustar, const double *__restrict__ part_in,
                                                       unsigned nb, double *__restrict__ Bnext0,
                                                       int *__restrict__ flag) {
-    if (blockIdx.x == 0) {
-        __shared__ double Bs[B_REC];
-        __shared__ double FT[4];
-        body_from_partials<2, 256>(bp, Bk, part_in, nb, Bs, FT);
+    if (blockIdx.x == gridDim.x - 1) {
+        // wave 0: the fixed-order sum of the nb <= 256 partials (lane l adds l, l + 64,
+        // l + 128, l + 192 compensated, then a fixed xor tree), all loads requested first
+        if (threadIdx.x >= 64) return;
+        double pv[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const unsigned b = threadIdx.x + 64u * u;
+#pragma unroll
+            for (int j = 0; j < 4; j++) pv[u][j] = b < nb ? part_in[(size_t)b * 4 + j] : 0.0;
+        }
+        Kahan sk[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) sk[j].add(pv[u][j]);
+        double ft[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) ft[j] = wave_sum(sk[j].value());
         if (threadIdx.x == 0) {
+            double B0[B_REC], Bs[B_REC];
+            for (int j = 0; j < B_REC; j++) B0[j] = Bk[j];
+            body_update<2>(bp, B0, ft, Bs);
             bool bad = false;
             for (int j = 0; j < B_REC; j++) Bk[K * B_REC + j] = Bs[j];
             for (int j = 0; j < 8; j++) bad = bad || !isfinite(Bs[j]);
@@ -1168,6 +1177,7 @@ __global__ __launch_bounds__(256) void k_iter_final2d(Grid g, Design D, BodyPara
             if (Bnext0)
                 for (int j = 0; j < B_REC; j++) Bnext0[j] = Bs[j];
         }
+        return;
     }
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long l = t / LPN;

@@ -551,7 +551,7 @@ template <typename T> struct Run {
             }
             const double *plast = part + (size_t)((c.K - 1) & 1) * half;
             pf->run(LKS_K_ITER_FINAL, [&](hipEvent_t e0, hipEvent_t e1) {
-                hipExtLaunchKernelGGL((k_iter_final2d<T, ROT, 4>), dim3(blocks(c.D.boxN * 4, 256)), dim3(256), 0, st,
+                hipExtLaunchKernelGGL((k_iter_final2d<T, ROT, 4>), dim3(blocks(c.D.boxN * 4, 256) + 1), dim3(256), 0, st,
                                       e0, e1, 0, c.g, c.D, c.bp, Bk, c.K, krT, u, ustar, plast, c.ntile, Bnext0,
                                       flag);
             });
