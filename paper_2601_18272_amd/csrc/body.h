@@ -519,6 +519,174 @@ __device__ __forceinline__ void spread_node_ax(const Design &D, const double *B,
     }
 }
 
+// ------------------------------------------------------------------ 3D box rows
+// The footprint-box nodes along the rotation axis (a box row) share their plane
+// coordinates, hence their plane candidates and weights (only the axial base ib
+// differs). The 3D node-side mapping kernels therefore give each box row to one wave:
+// the wave forms the row's candidates once, one per lane, into its slot of LDS, and its
+// lanes then sweep the row's nodes, reading each candidate (weight, plane index, offsets)
+// from LDS at a wave-uniform index, in gather_plane's order, so the sums are the same.
+// (LDS, not cross-lane reads of registers: the compiler may recompute a register value
+// inside the sweep, where some lanes are inactive.)
+template <typename T> struct RowSlot {
+    T w[36], rp[36], rq[36];
+    int p[36];
+};
+
+template <typename T, bool ROT> struct PlaneRow {
+    RowSlot<T> *sl;             // this wave's slot
+    unsigned long long valid;   // candidates in the support (wave-uniform)
+    double dp, dq;              // x - x^G along the plane axes
+    // every lane of the wave calls it (the whole wave, no lane inactive)
+    __device__ __forceinline__ void init(const Design &D, const double *B, int xi, int xj, RowSlot<T> *slot) {
+        sl = slot;
+        const double c = B[B_COS], s = B[B_SIN];
+        dp = (double)xi - B[B_XG + D.pi];
+        dq = (double)xj - B[B_XG + D.pj];
+        const double xp = c * dp + s * dq, xq = -s * dp + c * dq;
+        const double i0 = xp + D.half[D.pi], j0 = xq + D.half[D.pj];
+        const double fi = floor(i0), fj = floor(j0);
+        const int bi = (int)fmax(fmin(fi, 1.0e9), -1.0e9), bj = (int)fmax(fmin(fj, 1.0e9), -1.0e9);
+        const T fri = T(i0 - fi), frj = T(j0 - fj);
+        const T cc = T(c), ss = T(s);
+        constexpr int PW = ROT ? 6 : 4, P0 = ROT ? -2 : -1;
+        const int lane = threadIdx.x & 63;
+        const int u = lane / PW, v = lane - u * PW;
+        const int ii = bi + P0 + u, jj = bj + P0 + v;
+        const T ei = T(P0 + u) - fri, ej = T(P0 + v) - frj;
+        const T rp = -(cc * ei - ss * ej);
+        const T rq = -(ss * ei + cc * ej);
+        const bool ok = lane < PW * PW && ii >= 0 && ii < D.nd[D.pi] && jj >= 0 && jj < D.nd[D.pj] &&
+                        fabs(rp) < T(2) && fabs(rq) < T(2);
+        if (lane < PW * PW) {
+            sl->w[lane] = ok ? wk(rp) * wk(rq) : T(0);
+            sl->rp[lane] = rp;
+            sl->rq[lane] = rq;
+            sl->p[lane] = ok ? ii + D.nd[D.pi] * jj : 0;
+        }
+        valid = __ballot(ok);
+        // the slot is this wave's alone: order its stores before the sweep's loads
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // f(W, p, r_pi, r_pj) for the row's candidates in order (wave-uniform loop), NB at a
+    // time without branches between them, so that their loads are in flight together (a
+    // batch's missing tail is visited with W = 0 at p = 0: its terms vanish)
+    template <int NB, typename F> __device__ __forceinline__ void visit(F &&f) const {
+        unsigned long long m = valid;
+        while (m) {
+            int jb[NB];
+            bool on[NB];
+#pragma unroll
+            for (int b = 0; b < NB; b++) {
+                on[b] = m != 0;
+                jb[b] = on[b] ? __builtin_amdgcn_readfirstlane(__ffsll((long long)m) - 1) : 0;
+                m &= m - 1;
+            }
+#pragma unroll
+            for (int b = 0; b < NB; b++)
+                f(on[b] ? sl->w[jb[b]] : T(0), on[b] ? sl->p[jb[b]] : 0, sl->rp[jb[b]], sl->rq[jb[b]]);
+        }
+    }
+};
+
+// The box row of wave `row`: plane box coordinates and, per node, the grid node.
+struct BoxRow {
+    int row, bp, bq;  // row index; its box coordinates along the plane axes
+    __device__ __forceinline__ static int count(const Design &D) { return D.L[D.pi] * D.L[D.pj]; }
+    __device__ __forceinline__ void init(const Design &D, int r) {
+        row = r;
+        bq = r / D.L[D.pi];
+        bp = r - bq * D.L[D.pi];
+    }
+    // box index l and grid node x of the row's node at axial box coordinate ba; returns
+    // whether x is a box node (on the grid and interior), as box_node
+    __device__ __forceinline__ bool node(const Grid &g, const Design &D, const int o[3], int ba, long long &l,
+                                         int x[3]) const {
+        int b[3];
+        b[D.axis] = ba;
+        b[D.pi] = bp;
+        b[D.pj] = bq;
+        l = b[0] + (long long)D.L[0] * (b[1] + (long long)D.L[1] * b[2]);
+#pragma unroll
+        for (int a = 0; a < 3; a++) x[a] = o[a] + b[a];
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+            if (x[a] < 0 || x[a] >= g.n[a]) return false;
+        return is_interior<3>(g, x);
+    }
+};
+
+// spread_node_ax for a node of a box row (candidates from the row's PlaneRow).
+template <typename T, bool ROT>
+__device__ __forceinline__ void spread_node_row(const Design &D, const double *B, const Axial &ax,
+                                                const T *__restrict__ K1, int xa, const PlaneRow<T, ROT> &pr,
+                                                T &kap, T us[3]) {
+    const int NA = D.nd[D.axis] + 4;
+    T k = 0, phi = 0, wp = 0, wq = 0;
+    const int ib = xa + ax.fl;
+    if (ib >= -2 && ib <= D.nd[D.axis] + 1)
+        pr.template visit<4>([&](T W, int p, T rp, T rq) {
+            k += W * K1[(ib + 2) + NA * p];
+            phi += W;
+            wp += W * rp;
+            wq += W * rq;
+        });
+    const T sa = axial_sum<T>(D, ax, ib);
+    phi *= sa;
+    wp *= sa;
+    wq *= sa;
+    const double armp = (double)phi * pr.dp - (double)wp;
+    const double armq = (double)phi * pr.dq - (double)wq;
+    const double om = B[B_OM];
+    kap = k;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const double axa = a == D.axis ? 0.0 : (a == D.pi ? -armq : armp);
+        us[a] = T(B[B_UG + a] * (double)phi + om * axa);
+    }
+}
+
+// Forward spread (k_spread_fwd) in 3D over box rows: 4 waves per block, one row each.
+template <typename T, bool ROT>
+__global__ __launch_bounds__(256) void k_spread_fwd_rows(Grid g, Design D, const double *__restrict__ Bk, int k,
+                                                         const T *__restrict__ K1, T *__restrict__ u,
+                                                         T *__restrict__ ustar) {
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (r >= BoxRow::count(D)) return;  // whole waves
+    BoxRow br;
+    br.init(D, r);
+    int o[3];
+    box_origin<3>(D, Bk, o);
+    const double *B = Bk + k * B_REC;
+    __shared__ RowSlot<T> slots[4];
+    PlaneRow<T, ROT> pr;
+    pr.init(D, B, o[D.pi] + br.bp, o[D.pj] + br.bq, &slots[threadIdx.x >> 6]);
+    const Axial ax = axial_of(D, B);
+    const long long N = g.N, bN = D.boxN;
+    for (int ba = lane; ba < D.L[D.axis]; ba += 64) {
+        long long l;
+        int x[3];
+        if (!br.node(g, D, o, ba, l, x)) continue;
+        T kap, us[3];
+        spread_node_row<T, ROT>(D, B, ax, K1, x[D.axis], pr, kap, us);
+        const long long id = node_id(g, x[0], x[1], x[2]);
+        const T inv = T(1) / (T(1) + kap);
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            T s;
+            if (k == 0) {
+                s = u[a * N + id];
+                ustar[a * bN + l] = s;
+            } else {
+                s = ustar[a * bN + l];
+            }
+            u[a * N + id] = (s + kap * us[a]) * inv;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ forward spread
 // Iteration k of a step: footprint nodes get kappa, u^S at pose B^(k) and the Brinkman
 // correction of u* (read from the state at k = 0 and kept in ustar; from ustar after).
@@ -1282,6 +1450,45 @@ __global__ __launch_bounds__(256) void k_adj_recompute(Grid g, Design D, const d
     }
 }
 
+// k_adj_recompute in 3D over box rows (4 waves per block, one row each; blockIdx.y = k).
+template <typename T, bool ROT>
+__global__ __launch_bounds__(256) void k_adj_recompute_rows(Grid g, Design D, const double *__restrict__ Bk,
+                                                            const T *__restrict__ K1, const T *__restrict__ ustar,
+                                                            T *__restrict__ kapk, T *__restrict__ usk,
+                                                            T *__restrict__ uk, T *__restrict__ ustb) {
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int k = blockIdx.y;
+    if (r >= BoxRow::count(D)) return;  // whole waves
+    BoxRow br;
+    br.init(D, r);
+    int o[3];
+    box_origin<3>(D, Bk, o);
+    const double *B = Bk + k * B_REC;
+    __shared__ RowSlot<T> slots[4];
+    PlaneRow<T, ROT> pr;
+    pr.init(D, B, o[D.pi] + br.bp, o[D.pj] + br.bq, &slots[threadIdx.x >> 6]);
+    const Axial ax = axial_of(D, B);
+    const T *K1k = K1 + (long long)k * (D.nd[D.axis] + 4) * D.nd[D.pi] * D.nd[D.pj];
+    const long long bN = D.boxN;
+    for (int ba = lane; ba < D.L[D.axis]; ba += 64) {
+        long long l;
+        int x[3];
+        const bool ok = br.node(g, D, o, ba, l, x);
+        if (k == 0)
+#pragma unroll
+            for (int a = 0; a < 3; a++) ustb[a * bN + l] = T(0);
+        T kap = 0, us[3] = {0, 0, 0};
+        if (ok) spread_node_row<T, ROT>(D, B, ax, K1k, x[D.axis], pr, kap, us);
+        kapk[k * bN + l] = kap;
+        const T inv = T(1) / (T(1) + kap);
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            usk[(k * 3 + a) * bN + l] = us[a];
+            uk[(k * 3 + a) * bN + l] = ok ? (ustar[a * bN + l] + kap * us[a]) * inv : T(0);
+        }
+    }
+}
+
 // Per-point pose cotangents -> (x^G, u^G, theta, omega) contributions.
 // Xb: cotangent of x^ref, USb: of u^S,ref, rb: of r = R xi used by the torque.
 __device__ __forceinline__ void pose_rev(const Design &D, const double *B, const Pose &P, const double Xb[3],
@@ -1653,6 +1860,71 @@ __global__ __launch_bounds__(Dblk<DIM>::v) void k_adj_r3(Grid g, Design D, const
     }
     if (DIM == 3 && p1t) p1v = part1[(long long)blockIdx.x * 8 + threadIdx.x];
     block_reduce_store<8, Dblk<DIM>::v>(v, part3, &p1v);
+}
+
+// k_adj_r2 in 3D over box rows (4 waves per block, one row each).
+template <typename T, bool ROT>
+__global__ __launch_bounds__(256) void k_adj_r2_rows(Grid g, Bc bc, Design D, const double *__restrict__ Bk, int k,
+                                                     int K, const T *__restrict__ ab, const T *__restrict__ AU,
+                                                     const T *__restrict__ kapk, const T *__restrict__ usk,
+                                                     const T *__restrict__ uk, T *__restrict__ ustb,
+                                                     T *__restrict__ kb, T *__restrict__ usb) {
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (r >= BoxRow::count(D)) return;  // whole waves
+    BoxRow br;
+    br.init(D, r);
+    int o[3];
+    box_origin<3>(D, Bk, o);
+    const double *B = Bk + k * B_REC;
+    __shared__ RowSlot<T> slots[4];
+    PlaneRow<T, ROT> pr;
+    pr.init(D, B, o[D.pi] + br.bp, o[D.pj] + br.bq, &slots[threadIdx.x >> 6]);
+    const Axial ax = axial_of(D, B);
+    const int NA = D.nd[D.axis] + 4;
+    const long long NANP = (long long)NA * D.nd[D.pi] * D.nd[D.pj];
+    const long long bN = D.boxN;
+    for (int ba = lane; ba < D.L[D.axis]; ba += 64) {
+        long long l;
+        int x[3];
+        if (!br.node(g, D, o, ba, l, x)) {
+            kb[l] = T(0);
+#pragma unroll
+            for (int a = 0; a < 3; a++) usb[a * bN + l] = T(0);
+            continue;
+        }
+        // the node's own fields, requested before the gather
+        const T kap = kapk[k * bN + l];
+        T ust[3], dus[3];
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            ust[a] = ustb[a * bN + l];
+            dus[a] = usk[(k * 3 + a) * bN + l] - uk[(k * 3 + a) * bN + l];
+        }
+        T ub[3] = {0, 0, 0};
+        const int ib = x[D.axis] + ax.fl;
+        if (ib >= -2 && ib <= D.nd[D.axis] + 1)
+            pr.template visit<4>([&](T W, int p, T, T) {
+                const int i = (ib + 2) + NA * p;
+#pragma unroll
+                for (int a = 0; a < 3; a++) ub[a] += W * AU[a * NANP + i];
+            });
+        if (k == K - 1) {
+            const long long id = node_id(g, x[0], x[1], x[2]);
+            T pdummy, uf[3];
+            fold_bc<3, T>(g, bc, ab, x, id, pdummy, uf, true);
+#pragma unroll
+            for (int a = 0; a < 3; a++) ub[a] += uf[a];
+        }
+        const T inv = T(1) / (T(1) + kap);
+        T kbar = 0;
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            ustb[a * bN + l] = ust[a] + ub[a] * inv;
+            kbar += ub[a] * dus[a] * inv;
+            usb[a * bN + l] = ub[a] * kap * inv;
+        }
+        kb[l] = kbar;
+    }
 }
 
 // Body cotangent B^(k)bar from the partials of iteration k (fixed order), then

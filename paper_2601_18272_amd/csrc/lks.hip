@@ -326,6 +326,9 @@ struct Layout {
     size_t total;
 };
 
+// Rows of the footprint box along the rotation axis (3D row kernels: one wave each).
+long long box_rows(const Ctx &c) { return (long long)c.D.L[c.D.pi] * c.D.L[c.D.pj]; }
+
 // Elements of one pose's axial sums (3D bodies; see k_axial).
 size_t axial_elems(const Ctx &c) {
     if (!c.has_body || c.dim != 3) return 1;
@@ -520,8 +523,13 @@ template <typename T> struct Run {
                                               0, st, e0, nullptr, 0, c.D, Bk, k, krT, (long long)c.D.ND, ax);
                         es = nullptr;
                     }
-                    hipExtLaunchKernelGGL((k_spread_fwd<DIM, T, ROT, lpn<DIM>()>), dim3(blocks(c.D.boxN * lpn<DIM>(), 256)),
-                                          dim3(256), 0, st, es, e1, 0, c.g, c.D, Bk, k, krT, (const T *)ax, u, ustar);
+                    if constexpr (DIM == 3 && ROT)  // one wave per box row (k_spread_fwd_rows)
+                        hipExtLaunchKernelGGL((k_spread_fwd_rows<T, ROT>), dim3(blocks(box_rows(c), 4)), dim3(256), 0, st,
+                                              es, e1, 0, c.g, c.D, Bk, k, (const T *)ax, u, ustar);
+                    else
+                        hipExtLaunchKernelGGL((k_spread_fwd<DIM, T, ROT, lpn<DIM>()>),
+                                              dim3(blocks(c.D.boxN * lpn<DIM>(), 256)), dim3(256), 0, st, es, e1, 0,
+                                              c.g, c.D, Bk, k, krT, (const T *)ax, u, ustar);
                 });
                 pf->run(LKS_K_INTERP, [&](hipEvent_t e0, hipEvent_t e1) {
                     hipExtLaunchKernelGGL((k_interp_force<DIM, T>), dim3(c.nblk), dim3(c.dblk), 0, st, e0,
@@ -584,8 +592,12 @@ template <typename T> struct Run {
                                           st, e0, nullptr, 0, c.D, Bk, 0, krT, (long long)c.D.ND, ax);
                     es = nullptr;
                 }
-                hipExtLaunchKernelGGL((k_adj_recompute<DIM, T, ROT, lpn<DIM>()>), gb, dim3(256), 0, st, es, e1, 0, c.g,
-                                      c.D, Bk, krT, (const T *)ax, ustar, kapk, usk, uk, ustb);
+                if constexpr (DIM == 3 && ROT)  // one wave per box row and pose (k_adj_recompute_rows)
+                    hipExtLaunchKernelGGL((k_adj_recompute_rows<T, ROT>), dim3(blocks(box_rows(c), 4), c.K), dim3(256), 0,
+                                          st, es, e1, 0, c.g, c.D, Bk, (const T *)ax, ustar, kapk, usk, uk, ustb);
+                else
+                    hipExtLaunchKernelGGL((k_adj_recompute<DIM, T, ROT, lpn<DIM>()>), gb, dim3(256), 0, st, es, e1, 0,
+                                          c.g, c.D, Bk, krT, (const T *)ax, ustar, kapk, usk, uk, ustb);
             });
             for (int k = c.K - 1; k >= 0; k--) {
                 // record step of the pending iteration inside this R1 (reads recb(rcur) and
@@ -621,9 +633,14 @@ template <typename T> struct Run {
                                               0, st, e0, nullptr, 0, c.D, Bk, k, (const T *)URb, (long long)c.D.ND, AU);
                         es = nullptr;
                     }
-                    hipExtLaunchKernelGGL((k_adj_r2<DIM, T, ROT, lpn<DIM>()>), dim3(blocks(c.D.boxN * lpn<DIM>(), 256)),
-                                          dim3(256), 0, st, es, e1, 0, c.g, c.bc, c.D, Bk, k, c.K, ab, URb, (const T *)AU,
-                                          kapk, usk, uk, ustb, kb, usb);
+                    if constexpr (DIM == 3 && ROT)  // one wave per box row (k_adj_r2_rows)
+                        hipExtLaunchKernelGGL((k_adj_r2_rows<T, ROT>), dim3(blocks(box_rows(c), 4)), dim3(256), 0, st, es,
+                                              e1, 0, c.g, c.bc, c.D, Bk, k, c.K, ab, (const T *)AU, kapk, usk, uk, ustb,
+                                              kb, usb);
+                    else
+                        hipExtLaunchKernelGGL((k_adj_r2<DIM, T, ROT, lpn<DIM>()>),
+                                              dim3(blocks(c.D.boxN * lpn<DIM>(), 256)), dim3(256), 0, st, es, e1, 0, c.g,
+                                              c.bc, c.D, Bk, k, c.K, ab, URb, (const T *)AU, kapk, usk, uk, ustb, kb, usb);
                 });
                 pf->run(LKS_K_ADJ_R3, [&](hipEvent_t e0, hipEvent_t e1) {
                     const bool d = defer_finish();
