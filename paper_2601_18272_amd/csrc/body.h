@@ -404,13 +404,12 @@ __global__ __launch_bounds__(256) void k_axial(Design D, const double *__restric
     for (int c = 0; c < NC; c++) dst[((long long)blockIdx.y * NC + c) * NA * NP + t] = acc[c];
 }
 
-// Plane candidates of node x (3D, gather form, LPN lanes): f(W, plane index p, r_pi, r_pj)
-// for every design column (ii, jj) whose plane weight is nonzero, and for others with
-// W = 0 at p = 0 (their terms vanish). Returns the node's axial base ib and fills
-// d = x - x^G. Plane indices and axial-sum offsets fit in int (checked on the host).
-// BATCH (rotated window, one lane per node): rows without branches, for callers whose
-// loads per candidate dominate.
-template <typename T, bool ROT, int LPN, bool BATCH = false, typename F>
+// Plane candidates of node x (3D, gather form, LPN lanes; axis-aligned window: rotated
+// windows go through box rows, PlaneRow): f(W, plane index p, r_pi, r_pj) for every design
+// column (ii, jj) of the window, with W = 0 at p = 0 for those outside the support (their
+// terms vanish). Returns the node's axial base ib and fills d = x - x^G. Plane indices and
+// axial-sum offsets fit in int (checked on the host).
+template <typename T, bool ROT, int LPN, typename F>
 __device__ __forceinline__ int gather_plane(const Design &D, const double *B, const Axial &ax, const int x[3],
                                             double d[3], int q, F &&f) {
     const double c = B[B_COS], s = B[B_SIN];
@@ -427,60 +426,19 @@ __device__ __forceinline__ int gather_plane(const Design &D, const double *B, co
     const T cc = T(c), ss = T(s);
     constexpr int PW = ROT ? 6 : 4, P0 = ROT ? -2 : -1, NC = (PW * PW + LPN - 1) / LPN;
     const int ni = D.nd[D.pi], nj = D.nd[D.pj];
-    if constexpr (ROT && LPN == 1 && BATCH) {
-        // rotated window, row by row: the column terms are formed once per node and a
-        // row's six candidates run without branches (a skipped one with W = 0 at p = 0),
-        // so that the row's loads are in flight together
-        T sej[PW], cej[PW];
-        int jjv[PW];
-        bool okv[PW];
-#pragma unroll
-        for (int v = 0; v < PW; v++) {
-            const T ej = T(P0 + v) - frj;
-            sej[v] = ss * ej;
-            cej[v] = cc * ej;
-            jjv[v] = bj + P0 + v;
-            okv[v] = jjv[v] >= 0 && jjv[v] < nj;
-        }
-#pragma unroll 1
-        for (int u = 0; u < PW; u++) {
-            const int ii = bi + P0 + u;
-            const bool oku = ii >= 0 && ii < ni;
-            const T ei = T(P0 + u) - fri;
-            const T cei = cc * ei, sei = ss * ei;
-#pragma unroll
-            for (int v = 0; v < PW; v++) {
-                const T rp = -(cei - sej[v]), rq = -(sei + cej[v]);
-                const bool ok = oku && okv[v] && fabs(rp) < T(2) && fabs(rq) < T(2);
-                f(ok ? wk(rp) * wk(rq) : T(0), ok ? ii + ni * jjv[v] : 0, rp, rq);
-            }
-        }
-    } else if constexpr (ROT) {
-        // rotated window: about half of the 36 candidates lie outside the support
-        for (int cidx = q; cidx < PW * PW; cidx += LPN) {
-            const int u = cidx / PW, v = cidx - u * PW;
-            const int ii = bi + P0 + u, jj = bj + P0 + v;
-            if (ii < 0 || ii >= ni || jj < 0 || jj >= nj) continue;
-            const T ei = T(P0 + u) - fri, ej = T(P0 + v) - frj;
-            const T rp = -(cc * ei - ss * ej), rq = -(ss * ei + cc * ej);
-            if (!(fabs(rp) < T(2) && fabs(rq) < T(2))) continue;
-            f(wk(rp) * wk(rq), ii + ni * jj, rp, rq);
-        }
-    } else {
-        // axis-aligned window: without branches, unrolled by rows; a skipped candidate is
-        // visited with W = 0 at p = 0, so that the callers' loads of a row are in flight
-        // together (the sums are unchanged)
+    static_assert(!ROT, "rotated windows: box rows (PlaneRow)");
+    // without branches, unrolled by rows, so that the callers' loads of a row are in
+    // flight together (the sums are unchanged by the zero terms)
 #pragma unroll PW
-        for (int it = 0; it < NC; it++) {
-            const int cidx = q + it * LPN;
-            const int u = cidx / PW, v = cidx - u * PW;
-            const int ii = bi + P0 + u, jj = bj + P0 + v;
-            const T ei = T(P0 + u) - fri, ej = T(P0 + v) - frj;
-            const T rp = -(cc * ei - ss * ej), rq = -(ss * ei + cc * ej);
-            const bool ok = cidx < PW * PW && ii >= 0 && ii < ni && jj >= 0 && jj < nj && fabs(rp) < T(2) &&
-                            fabs(rq) < T(2);
-            f(ok ? wk(rp) * wk(rq) : T(0), ok ? ii + ni * jj : 0, rp, rq);
-        }
+    for (int it = 0; it < NC; it++) {
+        const int cidx = q + it * LPN;
+        const int u = cidx / PW, v = cidx - u * PW;
+        const int ii = bi + P0 + u, jj = bj + P0 + v;
+        const T ei = T(P0 + u) - fri, ej = T(P0 + v) - frj;
+        const T rp = -(cc * ei - ss * ej), rq = -(ss * ei + cc * ej);
+        const bool ok = cidx < PW * PW && ii >= 0 && ii < ni && jj >= 0 && jj < nj && fabs(rp) < T(2) &&
+                        fabs(rq) < T(2);
+        f(ok ? wk(rp) * wk(rq) : T(0), ok ? ii + ni * jj : 0, rp, rq);
     }
     return ib;
 }
@@ -627,7 +585,7 @@ __device__ __forceinline__ void spread_node_row(const Design &D, const double *B
     T k = 0, phi = 0, wp = 0, wq = 0;
     const int ib = xa + ax.fl;
     if (ib >= -2 && ib <= D.nd[D.axis] + 1)
-        pr.template visit<4>([&](T W, int p, T rp, T rq) {
+        pr.template visit<8>([&](T W, int p, T rp, T rq) {
             k += W * K1[(ib + 2) + NA * p];
             phi += W;
             wp += W * rp;
@@ -1752,7 +1710,7 @@ __global__ __launch_bounds__(256) void k_adj_r2(Grid g, Bc bc, Design D, const d
         const int NA = D.nd[D.axis] + 4;
         const long long NANP = (long long)NA * D.nd[D.pi] * D.nd[D.pj];
         const int ib = x[D.axis] + ax.fl;
-        gather_plane<T, ROT, LPN, true>(D, Bk + k * B_REC, ax, x, d, q, [&](T W, int p, T, T) {
+        gather_plane<T, ROT, LPN>(D, Bk + k * B_REC, ax, x, d, q, [&](T W, int p, T, T) {
             const int i = (ib + 2) + NA * p;
 #pragma unroll
             for (int a = 0; a < 3; a++) ub[a] += W * AU[a * NANP + i];
@@ -1903,7 +1861,7 @@ __global__ __launch_bounds__(256) void k_adj_r2_rows(Grid g, Bc bc, Design D, co
         T ub[3] = {0, 0, 0};
         const int ib = x[D.axis] + ax.fl;
         if (ib >= -2 && ib <= D.nd[D.axis] + 1)
-            pr.template visit<4>([&](T W, int p, T, T) {
+            pr.template visit<8>([&](T W, int p, T, T) {
                 const int i = (ib + 2) + NA * p;
 #pragma unroll
                 for (int a = 0; a < 3; a++) ub[a] += W * AU[a * NANP + i];
