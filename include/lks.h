@@ -236,6 +236,42 @@ int lks_design_cyclic_expand(const lks_problem_t *P, int n_sectors, const void *
 int lks_design_cyclic_collect(const lks_problem_t *P, int n_sectors, const double *grad, double *grad_sector,
                               void *stream);
 
+/* ---------------------------------------------------------------- design update (MMA)
+ * One step of the method of moving asymptotes for one inequality constraint, the
+ * update of Sec. 3.5 / Algorithm 1 (gamma^k, dJ/dgamma, G, dG/dgamma -> gamma^(k+1);
+ * the paper cites Svanberg 1987). Minimisation form: pass df0 = -dJ/dgamma to maximise J.
+ * All arrays are device FP64 of n entries; the caller keeps the history:
+ *   x     [n] in: x^k, out: x^(k+1)
+ *   xold1, xold2 [n] x^(k-1), x^(k-2) (read when iter > 2; may be NULL otherwise)
+ *   low, upp [n] in: the previous asymptotes (read when iter > 2), out: this step's
+ *   df0, dg1 [n] gradients of the objective and of the constraint at x^k
+ *   g1    [1] device: the constraint value at x^k (feasible when <= 0)
+ *   lambda [1] device, may be NULL: the multiplier of the constraint
+ * iter counts from 1. Asymptotes start at x -+ 0.5 (xmax - xmin), then widen by 1.2 /
+ * narrow by 0.7 where the iterates move monotonically / oscillate, within 0.01 .. 10 box
+ * widths; move limits are opt->move box widths and 10 % of the way to the asymptotes. The
+ * dual is solved by multi-section to double precision; if no multiplier up to 1e20 makes
+ * the approximated constraint hold, the step uses 1e20. Deterministic (fixed-order sums).
+ * Errors: LKS_EINVAL for n < 1, iter < 1, xmin >= xmax, move <= 0, null or aliased arrays,
+ * a workspace smaller than lks_mma_workspace_bytes(n). Asynchronous on `stream`. */
+typedef struct {
+    double xmin, xmax; /* box of the design variables (0, 1 for gamma) */
+    double move;       /* move limit, fraction of xmax - xmin */
+} lks_mma_t;
+
+size_t lks_mma_workspace_bytes(long long n);
+int lks_mma_update(const lks_mma_t *opt, long long n, int iter, double *x, const double *xold1,
+                   const double *xold2, double *low, double *upp, const double *df0, const double *g1,
+                   const double *dg1, double *lambda, void *work, size_t work_bytes, void *stream);
+
+/* Volume constraint of Eq. constraint, read as a lower bound on the solid volume (the
+ * paper's text; the printed inequality has the opposite sense):
+ * G = 1 - sum(gh) / (vmin n) <= 0 and dG/dgh_j = -1 / (vmin n), from the projected design gh
+ * [n] (device FP64). G [1] and dG [n] (may be NULL) are device outputs. work: at least
+ * lks_mma_workspace_bytes(n) bytes. */
+int lks_volume_constraint(long long n, const double *gh, double vmin, double *G, double *dG, void *work,
+                          size_t work_bytes, void *stream);
+
 /* Message of the last error on this thread ("" if none). */
 const char *lks_last_error(void);
 

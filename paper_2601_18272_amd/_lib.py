@@ -24,7 +24,7 @@ EXPORTS = ("lks_state_elems", "lks_checkpoint_bytes", "lks_workspace_bytes", "lk
            "lks_adjoint", "map_design", "body_step", "lks_last_error", "lks_profile_read",
            "lks_profile_reset", "lks_design_filter", "lks_design_filter_adjoint",
            "lks_filter_workspace_bytes", "lks_cyclic_sector_points", "lks_design_cyclic_expand",
-           "lks_design_cyclic_collect")
+           "lks_design_cyclic_collect", "lks_mma_workspace_bytes", "lks_mma_update", "lks_volume_constraint")
 
 
 class LksProblem(C.Structure):
@@ -53,6 +53,10 @@ class LksProblem(C.Structure):
 
 class LksFilter(C.Structure):
     _fields_ = [("radius", C.c_double), ("beta", C.c_double), ("eta", C.c_double)]
+
+
+class LksMma(C.Structure):
+    _fields_ = [("xmin", C.c_double), ("xmax", C.c_double), ("move", C.c_double)]
 
 
 class LksError(RuntimeError):
@@ -102,6 +106,13 @@ def load():
     L.lks_design_cyclic_expand.restype = C.c_int
     L.lks_design_cyclic_collect.argtypes = [pp, C.c_int, dp, dp, vp]
     L.lks_design_cyclic_collect.restype = C.c_int
+    L.lks_mma_workspace_bytes.argtypes = [C.c_longlong]
+    L.lks_mma_workspace_bytes.restype = C.c_size_t
+    L.lks_mma_update.argtypes = [C.POINTER(LksMma), C.c_longlong, C.c_int, dp, dp, dp, dp, dp, dp, dp, dp, dp,
+                                 vp, C.c_size_t, vp]
+    L.lks_mma_update.restype = C.c_int
+    L.lks_volume_constraint.argtypes = [C.c_longlong, dp, C.c_double, dp, dp, vp, C.c_size_t, vp]
+    L.lks_volume_constraint.restype = C.c_int
     L.lks_last_error.argtypes = []
     L.lks_last_error.restype = C.c_char_p
     L.lks_profile_read.argtypes = [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]

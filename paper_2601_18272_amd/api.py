@@ -228,6 +228,52 @@ def design_cyclic_collect(pb, n_sectors: int, grad, flags: int = 0):
     return out
 
 
+def mma_workspace_bytes(n: int) -> int:
+    return int(_lib.load().lks_mma_workspace_bytes(int(n)))
+
+
+def mma_update(x, df0, g1, dg1, it: int, xold1=None, xold2=None, low=None, upp=None, xmin: float = 0.0,
+               xmax: float = 1.0, move: float = 0.2, work=None):
+    """One MMA step (FP64, on the device): returns (x_new, low, upp, lambda). x, df0, dg1 are
+    design arrays, g1 the constraint value (a 1-element device tensor or a float); pass the
+    previous asymptotes low, upp and x^(k-1), x^(k-2) from iteration 3 on."""
+    L = _lib.load()
+    xd = _dev(x, torch.float64).reshape(-1).clone()
+    n = xd.numel()
+    f0 = _dev(df0, torch.float64).reshape(-1)
+    f1 = _dev(dg1, torch.float64).reshape(-1)
+    if not torch.is_tensor(g1):
+        g1 = torch.tensor([float(g1)], dtype=torch.float64)
+    g = _dev(g1, torch.float64).reshape(-1)
+    lo = _dev(low, torch.float64).reshape(-1).clone() if low is not None else torch.zeros(n, dtype=torch.float64,
+                                                                                           device="cuda")
+    up = _dev(upp, torch.float64).reshape(-1).clone() if upp is not None else torch.zeros(n, dtype=torch.float64,
+                                                                                           device="cuda")
+    x1 = _dev(xold1, torch.float64).reshape(-1) if xold1 is not None else None
+    x2 = _dev(xold2, torch.float64).reshape(-1) if xold2 is not None else None
+    lam = torch.zeros(1, dtype=torch.float64, device="cuda")
+    nbytes = mma_workspace_bytes(n)
+    if work is None:
+        work = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    opt = _lib.LksMma(float(xmin), float(xmax), float(move))
+    _lib.check(L.lks_mma_update(C.byref(opt), n, int(it), _p(xd), _p(x1), _p(x2), _p(lo), _p(up), _p(f0), _p(g),
+                                _p(f1), _p(lam), _p(work), work.numel(), _stream()))
+    return xd, lo, up, lam
+
+
+def volume_constraint(gh, vmin: float, work=None):
+    """G = 1 - sum(gh) / (vmin n) and dG/dgh on the device (FP64)."""
+    L = _lib.load()
+    g = _dev(gh, torch.float64).reshape(-1)
+    n = g.numel()
+    G = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dG = torch.empty(n, dtype=torch.float64, device="cuda")
+    if work is None:
+        work = torch.empty(mma_workspace_bytes(n), dtype=torch.uint8, device="cuda")
+    _lib.check(L.lks_volume_constraint(n, _p(g), float(vmin), _p(G), _p(dG), _p(work), work.numel(), _stream()))
+    return G, dG
+
+
 class LKSFunction(torch.autograd.Function):
     """J = LKSFunction.apply(gamma, problem, precision, state0, body0).
 

@@ -25,6 +25,7 @@
 #include "body.h"
 #include "cyclic.h"
 #include "filter.h"
+#include "mma.h"
 
 using namespace lks;
 
@@ -1082,6 +1083,17 @@ int cyc_ctx(const lks_problem_t *P, int n_sec, Ctx &c, CycArgs &a) {
 }  // namespace
 
 // =================================================================== C ABI
+namespace {
+
+// MMA workspace: coefficients (MC_COUNT n doubles), block partials, the state.
+unsigned mma_blocks(long long n) { return std::min(blocks(n, MMA_NT), 1024u); }
+size_t mma_work_bytes(long long n) {
+    const size_t nb = mma_blocks(n);
+    return (size_t)MC_COUNT * (size_t)n * 8 + nb * MMA_M * 8 + 256;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *lks_last_error(void) { return g_err.c_str(); }
@@ -1307,6 +1319,84 @@ int lks_design_cyclic_collect(const lks_problem_t *P, int n_sectors, const doubl
     return filter_timed((P->flags & LKS_FLAG_PROFILE) != 0, LKS_K_CYC_COLLECT, st, [&](hipEvent_t e0, hipEvent_t e1) {
         hipExtLaunchKernelGGL(k_cyc_collect, dim3(blocks(ns, 256)), dim3(256), 0, st, e0, e1, 0, a, grad, grad_sector);
     });
+}
+
+size_t lks_mma_workspace_bytes(long long n) {
+    if (n < 1) {
+        fail(LKS_EINVAL, "n < 1");
+        return 0;
+    }
+    return mma_work_bytes(n);
+}
+
+int lks_mma_update(const lks_mma_t *opt, long long n, int iter, double *x, const double *xold1, const double *xold2,
+                   double *low, double *upp, const double *df0, const double *g1, const double *dg1, double *lambda,
+                   void *work, size_t work_bytes, void *stream) {
+    if (!opt) return fail(LKS_EINVAL, "null MMA parameters");
+    if (n < 1) return fail(LKS_EINVAL, "n < 1");
+    if (iter < 1) return fail(LKS_EINVAL, "iter < 1");
+    if (!(opt->xmin < opt->xmax) || !std::isfinite(opt->xmin) || !std::isfinite(opt->xmax))
+        return fail(LKS_EINVAL, "need xmin < xmax");
+    if (!(opt->move > 0.0)) return fail(LKS_EINVAL, "move limit must be > 0");
+    if (!x || !low || !upp || !df0 || !g1 || !dg1 || !work) return fail(LKS_EINVAL, "null pointer");
+    if (iter > 2 && (!xold1 || !xold2)) return fail(LKS_EINVAL, "iter > 2 needs x^(k-1) and x^(k-2)");
+    if (work_bytes < mma_work_bytes(n)) return fail(LKS_EINVAL, "workspace too small");
+    const size_t nb8 = (size_t)n * 8;
+    const void *ins[] = {xold1, xold2, df0, dg1, g1, lambda};
+    const size_t insz[] = {nb8, nb8, nb8, nb8, 8, 8};
+    void *outs[] = {x, low, upp};
+    for (void *o : outs) {
+        for (int i = 0; i < 6; i++)
+            if (ins[i] && overlap(o, nb8, ins[i], insz[i])) return fail(LKS_EINVAL, "an output overlaps an input");
+        if (overlap(o, nb8, work, work_bytes)) return fail(LKS_EINVAL, "an output overlaps the workspace");
+    }
+    for (int i = 0; i < 6; i++)
+        if (ins[i] && overlap(work, work_bytes, ins[i], insz[i])) return fail(LKS_EINVAL, "an input overlaps the workspace");
+    if (overlap(x, nb8, low, nb8) || overlap(x, nb8, upp, nb8) || overlap(low, nb8, upp, nb8))
+        return fail(LKS_EINVAL, "x, low and upp overlap");
+    hipStream_t st = (hipStream_t)stream;
+    MmaArgs a;
+    a.xmin = opt->xmin;
+    a.xmax = opt->xmax;
+    a.move = opt->move;
+    a.iter = iter;
+    const unsigned nb = mma_blocks(n);
+    double *coef = (double *)work;
+    double *part = coef + (size_t)MC_COUNT * n;
+    MmaState *ms = (MmaState *)(part + (size_t)nb * MMA_M);
+    hipLaunchKernelGGL(k_mma_prep, dim3(nb), dim3(MMA_NT), 0, st, a, n, (const double *)x, xold1, xold2, low, upp,
+                       df0, dg1, coef, part);
+    hipLaunchKernelGGL(k_mma_r1, dim3(1), dim3(MMA_NT), 0, st, (const double *)part, (int)nb, g1, ms);
+    for (int pass = 0; pass < MMA_PASSES; pass++) {
+        hipLaunchKernelGGL(k_mma_dual, dim3(nb), dim3(MMA_NT), 0, st, n, pass, (const double *)coef,
+                           (const MmaState *)ms, part);
+        hipLaunchKernelGGL(k_mma_pick, dim3(1), dim3(MMA_NT), 0, st, pass, (const double *)part, (int)nb, ms);
+    }
+    hipLaunchKernelGGL(k_mma_x, dim3(nb), dim3(MMA_NT), 0, st, n, (const double *)coef, (const MmaState *)ms, x,
+                       lambda);
+    HIP_TRY(hipGetLastError());
+    return LKS_OK;
+}
+
+int lks_volume_constraint(long long n, const double *gh, double vmin, double *G, double *dG, void *work,
+                          size_t work_bytes, void *stream) {
+    if (n < 1) return fail(LKS_EINVAL, "n < 1");
+    if (!(vmin > 0.0) || !std::isfinite(vmin)) return fail(LKS_EINVAL, "vmin must be > 0");
+    if (!gh || !G || !work) return fail(LKS_EINVAL, "null pointer");
+    if (work_bytes < mma_work_bytes(n)) return fail(LKS_EINVAL, "workspace too small");
+    const size_t nb8 = (size_t)n * 8;
+    if (overlap(G, 8, gh, nb8) || (dG && (overlap(dG, nb8, gh, nb8) || overlap(dG, nb8, G, 8))))
+        return fail(LKS_EINVAL, "outputs overlap the input");
+    if (overlap(work, work_bytes, gh, nb8) || overlap(work, work_bytes, G, 8) ||
+        (dG && overlap(work, work_bytes, dG, nb8)))
+        return fail(LKS_EINVAL, "the workspace overlaps an argument");
+    hipStream_t st = (hipStream_t)stream;
+    const unsigned nb = mma_blocks(n);
+    double *part = (double *)work;
+    hipLaunchKernelGGL(k_vol_part, dim3(nb), dim3(MMA_NT), 0, st, n, gh, part);
+    hipLaunchKernelGGL(k_vol_finish, dim3(nb), dim3(MMA_NT), 0, st, n, vmin, (const double *)part, (int)nb, G, dG);
+    HIP_TRY(hipGetLastError());
+    return LKS_OK;
 }
 
 }  // extern "C"

@@ -191,3 +191,44 @@ def test_cyclic_validation_errors_without_gpu(lib):
     assert L.lks_cyclic_sector_points(C.byref(s3), 4) == 7 * 6
     nob = api.problem_struct(pb.replace(nd=(0, 0, 0)))
     assert L.lks_cyclic_sector_points(C.byref(nob), 1) == 0
+
+
+def test_mma_validation_errors_without_gpu(lib):
+    """Bad sizes, bounds, missing history, short or overlapping workspaces are rejected
+    before any HIP call."""
+    L = lib.load()
+    n = 1000
+    wb = L.lks_mma_workspace_bytes(n)
+    assert wb >= 8 * 8 * n
+    assert L.lks_mma_workspace_bytes(0) == 0
+    good = lib.LksMma(0.0, 1.0, 0.2)
+    base = 1 << 30
+    x, lo, up, d0, d1, x1, x2 = (C.c_void_p(base + k * (1 << 24)) for k in range(7))
+    g1, lam = C.c_void_p(base + 7 * (1 << 24)), C.c_void_p(base + 7 * (1 << 24) + 64)
+    work = C.c_void_p(base + 8 * (1 << 24))
+
+    def call(opt=good, n=n, it=3, **kw):
+        a = dict(x=x, x1=x1, x2=x2, lo=lo, up=up, d0=d0, g1=g1, d1=d1, lam=lam, work=work, wb=wb)
+        a.update(kw)
+        return L.lks_mma_update(C.byref(opt) if opt is not None else None, n, it, a["x"], a["x1"], a["x2"], a["lo"],
+                                a["up"], a["d0"], a["g1"], a["d1"], a["lam"], a["work"], a["wb"], None)
+
+    assert call(opt=None) == lib.EINVAL
+    assert call(n=0) == lib.EINVAL
+    assert call(it=0) == lib.EINVAL
+    assert call(opt=lib.LksMma(1.0, 1.0, 0.2)) == lib.EINVAL
+    assert call(opt=lib.LksMma(0.0, float("inf"), 0.2)) == lib.EINVAL
+    assert call(opt=lib.LksMma(0.0, 1.0, 0.0)) == lib.EINVAL
+    assert call(x=None) == lib.EINVAL
+    assert call(x1=None) == lib.EINVAL          # iteration 3 needs the history
+    assert call(wb=wb - 8) == lib.EINVAL
+    assert call(lo=C.c_void_p(x.value + 8)) == lib.EINVAL           # x and low overlap
+    assert call(d0=C.c_void_p(up.value + 8 * (n - 1))) == lib.EINVAL  # an input inside an output
+    assert call(work=C.c_void_p(d1.value + 8)) == lib.EINVAL        # workspace over an input
+    assert "overlaps" in L.lks_last_error().decode()
+    G, dG = C.c_void_p(base + 9 * (1 << 24)), C.c_void_p(base + 10 * (1 << 24))
+    assert L.lks_volume_constraint(0, x, 0.3, G, dG, work, wb, None) == lib.EINVAL
+    assert L.lks_volume_constraint(n, x, 0.0, G, dG, work, wb, None) == lib.EINVAL
+    assert L.lks_volume_constraint(n, x, float("nan"), G, dG, work, wb, None) == lib.EINVAL
+    assert L.lks_volume_constraint(n, x, 0.3, G, C.c_void_p(x.value + 8), work, wb, None) == lib.EINVAL
+    assert L.lks_volume_constraint(n, x, 0.3, G, dG, work, 8, None) == lib.EINVAL

@@ -1,0 +1,101 @@
+"""MMA design update on the GPU against the oracle (oracle/mma.py), FP64."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mma as omma
+
+pytestmark = pytest.mark.gpu
+
+
+def run_both(n, seed, it, g1, move=0.2, hist=True):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0.05, 0.95, n)
+    xo1 = np.clip(x + rng.normal(0, 0.05, n), 0, 1) if hist else None
+    xo2 = np.clip(x + rng.normal(0, 0.05, n), 0, 1) if hist else None
+    low = x - rng.uniform(0.1, 0.6, n)
+    upp = x + rng.uniform(0.1, 0.6, n)
+    df0 = rng.normal(size=n) * 1e-3
+    dg1 = -np.full(n, 1.0 / (0.3 * n))  # the volume constraint's gradient
+    xr, lor, upr, lamr = omma.mma_step(x, xo1 if hist else x, xo2 if hist else x, low, upp, df0, g1, dg1, it, 0.0,
+                                       1.0, move)
+    from paper_2601_18272_amd import api
+    xg, log_, upg, lamg = api.mma_update(torch.tensor(x), torch.tensor(df0), g1, torch.tensor(dg1), it,
+                                         torch.tensor(xo1) if hist else None, torch.tensor(xo2) if hist else None,
+                                         torch.tensor(low), torch.tensor(upp), 0.0, 1.0, move)
+    return (xr, lor, upr, lamr), (xg.cpu().numpy(), log_.cpu().numpy(), upg.cpu().numpy(), lamg.item())
+
+
+@pytest.mark.parametrize("n,it,g1", [(1000, 1, 0.02), (1000, 3, 0.02), (1000, 5, -0.3), (4099, 4, 0.05),
+                                     (100003, 3, 0.01), (1, 1, 0.0), (257, 2, 1e-6)])
+def test_mma_matches_oracle(n, it, g1):
+    """Asymptotes to rounding; the update is the subproblem's minimiser at the GPU's
+    multiplier, that multiplier meets the dual condition h(lam) = 0 to the rounding of the
+    sum, and it agrees with the oracle's bisection to 1e-9 relative (the multi-section
+    leaves a bracket of a few ulps; the sums are taken in different orders)."""
+    (xr, lor, upr, lamr), (xg, log_, upg, lamg) = run_both(n, 11 + n + it, it, g1)
+    assert np.abs(log_ - lor).max() <= 1e-14 and np.abs(upg - upr).max() <= 1e-14
+    # the inputs as run_both drew them
+    rng = np.random.default_rng(11 + n + it)
+    x = rng.uniform(0.05, 0.95, n)
+    rng.normal(0, 0.05, n), rng.normal(0, 0.05, n), rng.uniform(0.1, 0.6, n), rng.uniform(0.1, 0.6, n)
+    df0 = rng.normal(size=n) * 1e-3
+    dg1 = -np.full(n, 1.0 / (0.3 * n))
+    alpha, beta = omma.move_limits(x, lor, upr, 0.0, 1.0, 0.2)
+    p0, q0 = omma.approximation(x, lor, upr, df0, 0.0, 1.0)
+    p1, q1 = omma.approximation(x, lor, upr, dg1, 0.0, 1.0)
+    x_at = omma.x_of_lambda(lamg, p0, q0, p1, q1, lor, upr, alpha, beta)
+    assert np.abs(xg - x_at).max() <= 1e-12
+    r1 = g1 - np.sum(p1 / (upr - x) + q1 / (x - lor))
+    terms = p1 / (upr - xg) + q1 / (xg - lor)
+    h = r1 + terms.sum()
+    scale = np.abs(terms).sum() + abs(r1)
+    if lamg == 0.0:
+        assert lamr == 0.0 and h <= 1e-13 * scale
+    else:
+        assert abs(h) <= 1e-13 * scale
+        assert abs(lamg - lamr) <= 1e-9 * abs(lamr)
+    assert np.abs(xg - xr).max() <= 1e-10
+
+
+def test_mma_infeasible_step_uses_the_largest_multiplier():
+    """A constraint the move limit cannot meet: the step goes as far as the limits allow."""
+    (xr, _, _, lamr), (xg, _, _, lamg) = run_both(500, 3, 3, 5.0)
+    assert lamg >= 1e19 and lamr >= 1e19
+    assert np.abs(xg - xr).max() <= 1e-12
+
+
+def test_mma_is_deterministic():
+    a = run_both(50000, 7, 4, 0.03)[1]
+    b = run_both(50000, 7, 4, 0.03)[1]
+    assert all(np.array_equal(u, v) for u, v in zip(a[:3], b[:3])) and a[3] == b[3]
+
+
+def test_mma_converges_like_the_oracle():
+    """The closed-form problem of the oracle pins, iterated on the GPU."""
+    from paper_2601_18272_amd import api
+    rng = np.random.default_rng(3)
+    n = 40
+    c = rng.uniform(0.5, 2.0, n)
+    V = 0.3 * n
+    xs = V * np.sqrt(c) / np.sqrt(c).sum()
+    x = torch.full((n,), 0.25, dtype=torch.float64, device="cuda")
+    xo1 = xo2 = x.clone()
+    lo = up = None
+    for it in range(1, 120):
+        xc = x.cpu().numpy()
+        xn, lo, up, lam = api.mma_update(x, torch.tensor(-c / xc ** 2), float(xc.sum() - V), torch.ones(n), it,
+                                         xo1, xo2, lo, up, 1e-3, 1.0, 0.2)
+        xo2, xo1, x = xo1, x, xn
+    assert np.abs(x.cpu().numpy() - xs).max() < 1e-6
+
+
+@pytest.mark.parametrize("n", [1, 1000, 884736])
+def test_volume_constraint(n):
+    from paper_2601_18272_amd import api
+    rng = np.random.default_rng(n)
+    gh = rng.uniform(0, 1, n)
+    G, dG = api.volume_constraint(torch.tensor(gh), 0.3)
+    Gr, dGr = omma.volume_constraint(gh, 0.3)
+    assert abs(G.item() - Gr) <= 1e-13 * max(1.0, abs(Gr))
+    assert np.abs(dG.cpu().numpy() - dGr).max() == 0.0
