@@ -95,10 +95,10 @@ def mma_step(x, xold1, xold2, low, upp, df0, g1, dg1, it, xmin=0.0, xmax=1.0, mo
     else:
         hi = 1.0
         while h(hi) > 0.0 and hi < LAM_MAX:
-            hi *= 2.0
+            hi = min(2.0 * hi, LAM_MAX)
         lo_l = 0.0
         if h(hi) > 0.0:
-            lam = hi
+            lam = hi  # LAM_MAX: the approximated constraint cannot be met
         else:
             for _ in range(iters):
                 mid = 0.5 * (lo_l + hi)
