@@ -239,7 +239,9 @@ int lks_design_cyclic_collect(const lks_problem_t *P, int n_sectors, const doubl
 /* ---------------------------------------------------------------- design update (MMA)
  * One step of the method of moving asymptotes for one inequality constraint, the
  * update of Sec. 3.5 / Algorithm 1 (gamma^k, dJ/dgamma, G, dG/dgamma -> gamma^(k+1);
- * the paper cites Svanberg 1987). Minimisation form: pass df0 = -dJ/dgamma to maximise J.
+ * the paper cites Svanberg 1987). Minimisation form: the objective's gradient is
+ * opt->f0_scale * df0, so df0 = dJ/dgamma with f0_scale = -1 / |J_ref| maximises J scaled
+ * to order one.
  * All arrays are device FP64 of n entries; the caller keeps the history:
  *   x     [n] in: x^k, out: x^(k+1)
  *   xold1, xold2 [n] x^(k-1), x^(k-2) (read when iter > 2; may be NULL otherwise)
@@ -257,6 +259,7 @@ int lks_design_cyclic_collect(const lks_problem_t *P, int n_sectors, const doubl
 typedef struct {
     double xmin, xmax; /* box of the design variables (0, 1 for gamma) */
     double move;       /* move limit, fraction of xmax - xmin */
+    double f0_scale;   /* factor on df0 (1 to minimise the given function) */
 } lks_mma_t;
 
 size_t lks_mma_workspace_bytes(long long n);

@@ -56,7 +56,7 @@ class LksFilter(C.Structure):
 
 
 class LksMma(C.Structure):
-    _fields_ = [("xmin", C.c_double), ("xmax", C.c_double), ("move", C.c_double)]
+    _fields_ = [("xmin", C.c_double), ("xmax", C.c_double), ("move", C.c_double), ("f0_scale", C.c_double)]
 
 
 class LksError(RuntimeError):

@@ -233,10 +233,11 @@ def mma_workspace_bytes(n: int) -> int:
 
 
 def mma_update(x, df0, g1, dg1, it: int, xold1=None, xold2=None, low=None, upp=None, xmin: float = 0.0,
-               xmax: float = 1.0, move: float = 0.2, work=None):
-    """One MMA step (FP64, on the device): returns (x_new, low, upp, lambda). x, df0, dg1 are
-    design arrays, g1 the constraint value (a 1-element device tensor or a float); pass the
-    previous asymptotes low, upp and x^(k-1), x^(k-2) from iteration 3 on."""
+               xmax: float = 1.0, move: float = 0.2, work=None, f0_scale: float = 1.0):
+    """One MMA step (FP64, on the device) minimising the function whose gradient is
+    f0_scale * df0: returns (x_new, low, upp, lambda). x, df0, dg1 are design arrays, g1 the
+    constraint value (a 1-element device tensor or a float); pass the previous asymptotes
+    low, upp and x^(k-1), x^(k-2) from iteration 3 on."""
     L = _lib.load()
     xd = _dev(x, torch.float64).reshape(-1).clone()
     n = xd.numel()
@@ -255,7 +256,7 @@ def mma_update(x, df0, g1, dg1, it: int, xold1=None, xold2=None, low=None, upp=N
     nbytes = mma_workspace_bytes(n)
     if work is None:
         work = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-    opt = _lib.LksMma(float(xmin), float(xmax), float(move))
+    opt = _lib.LksMma(float(xmin), float(xmax), float(move), float(f0_scale))
     _lib.check(L.lks_mma_update(C.byref(opt), n, int(it), _p(xd), _p(x1), _p(x2), _p(lo), _p(up), _p(f0), _p(g),
                                 _p(f1), _p(lam), _p(work), work.numel(), _stream()))
     return xd, lo, up, lam
@@ -272,6 +273,67 @@ def volume_constraint(gh, vmin: float, work=None):
         work = torch.empty(mma_workspace_bytes(n), dtype=torch.uint8, device="cuda")
     _lib.check(L.lks_volume_constraint(n, _p(g), float(vmin), _p(G), _p(dG), _p(work), work.numel(), _stream()))
     return G, dG
+
+
+def optimize(pb, gamma0, state0, body0, vmin: float, radius: float, betas, qs=None, n_opt: int = 40,
+             eta: float = 0.5, move: float = 0.2, precision: str = "fp32", periodic: bool = False,
+             tol: float = 1e-6, callback=None):
+    """The optimisation procedure of Sec. 3.5 / Algorithm 1 with the continuation scheme of
+    Sec. 3.3: for each continuation step l (beta = betas[l], q = qs[l]) up to n_opt design
+    iterations of filter + projection -> forward -> J, G -> adjoint -> reverse of the filter
+    -> MMA update, ending a step early when |J^k - J^(k-1)| <= tol |J^(k-1)| with G <= 0
+    (Eq. stopping_criterion). J is maximised subject to the minimum-volume constraint
+    G = 1 - sum(gamma_hat) / (vmin n) <= 0. With periodic=True the terminal state and body
+    start the next iteration and the initial adjoint values end its reverse sweep (Sec. 3.4).
+
+    The host only sequences the library's calls; every array stays on the device. The
+    objective is scaled by 1 / |J| of the first iteration; the asymptote history restarts
+    with each continuation step (the subproblem changes with beta and q). pb.ckpt_every
+    sets the checkpoint interval of the reverse sweeps. Returns (gamma, history), history
+    a list of dicts with l, k, J, G, lambda."""
+    dt = DTYPES[precision]
+    qs = list(qs) if qs is not None else [pb.q] * len(betas)
+    if len(qs) != len(betas):
+        raise ValueError("qs and betas need the same length")
+    g = _dev(gamma0, torch.float64).reshape(-1).clone()
+    n = g.numel()
+    s0 = _dev(state0, dt).clone()
+    b0 = _dev(body0, torch.float64).clone()
+    mwork = torch.empty(mma_workspace_bytes(n), dtype=torch.uint8, device="cuda")
+    fwork = torch.empty(filter_workspace_bytes(pb), dtype=torch.uint8, device="cuda")
+    scale, hist = None, []
+    adj_s = adj_b = None
+    for l, (beta, q) in enumerate(zip(betas, qs)):
+        pbl = pb.replace(q=float(q))
+        B = Buffers(pbl, precision, adjoint=True)
+        lo = up = x1 = x2 = None
+        J_prev = None
+        for k in range(1, n_opt + 1):
+            gt, gh = design_filter(pbl, g, radius, beta, eta, precision)
+            st, bd, J, _ = forward(pbl, gh, s0, b0, precision, buffers=B, store_ckpt=True)
+            G, dGh = volume_constraint(gh, vmin, work=mwork)
+            Jv, Gv = float(J.item()), float(G.item())
+            if J_prev is not None and Gv <= 0.0 and abs(Jv - J_prev) <= tol * abs(J_prev):
+                hist.append(dict(l=l, k=k, J=Jv, G=Gv, lam=None))
+                break
+            if periodic:
+                grad_h, ds, db = adjoint(pbl, gh, B, 1.0, precision, want_initial=True, dstate_T=adj_s, dbody_T=adj_b)
+                adj_s, adj_b = ds, db
+                s0, b0 = st, bd
+            else:
+                grad_h = adjoint(pbl, gh, B, 1.0, precision)
+            dJ = design_filter_adjoint(pbl, gt, grad_h, radius, beta, eta, precision, work=fwork)
+            dG = design_filter_adjoint(pbl, gt, dGh, radius, beta, eta, precision, work=fwork)
+            if scale is None:
+                scale = -1.0 / abs(Jv) if Jv != 0.0 else -1.0
+            g_old = g.clone()
+            g, lo, up, lam = mma_update(g, dJ, G, dG, k, x1, x2, lo, up, 0.0, 1.0, move, mwork, scale)
+            x2, x1 = x1, g_old
+            hist.append(dict(l=l, k=k, J=Jv, G=Gv, lam=float(lam.item())))
+            if callback is not None:
+                callback(hist[-1], g)
+            J_prev = Jv
+    return g, hist
 
 
 class LKSFunction(torch.autograd.Function):

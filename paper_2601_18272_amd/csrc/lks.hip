@@ -1338,6 +1338,7 @@ int lks_mma_update(const lks_mma_t *opt, long long n, int iter, double *x, const
     if (!(opt->xmin < opt->xmax) || !std::isfinite(opt->xmin) || !std::isfinite(opt->xmax))
         return fail(LKS_EINVAL, "need xmin < xmax");
     if (!(opt->move > 0.0)) return fail(LKS_EINVAL, "move limit must be > 0");
+    if (!std::isfinite(opt->f0_scale)) return fail(LKS_EINVAL, "f0_scale must be finite");
     if (!x || !low || !upp || !df0 || !g1 || !dg1 || !work) return fail(LKS_EINVAL, "null pointer");
     if (iter > 2 && (!xold1 || !xold2)) return fail(LKS_EINVAL, "iter > 2 needs x^(k-1) and x^(k-2)");
     if (work_bytes < mma_work_bytes(n)) return fail(LKS_EINVAL, "workspace too small");
@@ -1359,6 +1360,7 @@ int lks_mma_update(const lks_mma_t *opt, long long n, int iter, double *x, const
     a.xmin = opt->xmin;
     a.xmax = opt->xmax;
     a.move = opt->move;
+    a.f0_scale = opt->f0_scale;
     a.iter = iter;
     const unsigned nb = mma_blocks(n);
     double *coef = (double *)work;

@@ -24,7 +24,7 @@ constexpr double MMA_ASYINIT = 0.5, MMA_ASYDECR = 0.7, MMA_ASYINCR = 1.2, MMA_AL
 constexpr double MMA_LOG_LO = -16.0, MMA_LOG_HI = 20.0;  // ladder of the first pass: 0, 10^LO .. 10^HI
 
 struct MmaArgs {
-    double xmin, xmax, move;
+    double xmin, xmax, move, f0_scale;
     int iter;  // 1, 2, ...
 };
 
@@ -102,7 +102,7 @@ __global__ __launch_bounds__(MMA_NT) void k_mma_prep(MmaArgs a, long long n, con
         double pq[4];
 #pragma unroll
         for (int i = 0; i < 2; i++) {
-            const double d = i == 0 ? df0[j] : dg1[j];
+            const double d = i == 0 ? a.f0_scale * df0[j] : dg1[j];
             const double dp = fmax(d, 0.0), dm = fmax(-d, 0.0);
             pq[2 * i] = ux2 * (1.001 * dp + 0.001 * dm + MMA_RAA0 / w);
             pq[2 * i + 1] = xl2 * (0.001 * dp + 1.001 * dm + MMA_RAA0 / w);

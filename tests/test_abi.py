@@ -113,20 +113,22 @@ def test_validation_errors_without_gpu(lib):
     assert L.body_step(C.byref(s), dummy, dummy, dummy, None) == lib.EINVAL  # aliasing
 
 
-def test_filter_struct_layout_matches_header(lib, tmp_path):
-    fields = [f[0] for f in lib.LksFilter._fields_]
+@pytest.mark.parametrize("cname,pyname", [("lks_filter_t", "LksFilter"), ("lks_mma_t", "LksMma")])
+def test_small_struct_layout_matches_header(lib, tmp_path, cname, pyname):
+    S = getattr(lib, pyname)
+    fields = [f[0] for f in S._fields_]
     src = ['#include <stdio.h>', '#include <stddef.h>', '#include "lks.h"', "int main(void){",
-           'printf("%zu\\n", sizeof(lks_filter_t));']
-    src += [f'printf("%zu\\n", offsetof(lks_filter_t, {f}));' for f in fields]
+           f'printf("%zu\\n", sizeof({cname}));']
+    src += [f'printf("%zu\\n", offsetof({cname}, {f}));' for f in fields]
     src.append("return 0;}")
     c = tmp_path / "probe.c"
     c.write_text("\n".join(src))
     exe = tmp_path / "probe"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(c)])
     out = [int(v) for v in subprocess.check_output([str(exe)]).split()]
-    assert out[0] == C.sizeof(lib.LksFilter)
+    assert out[0] == C.sizeof(S)
     for f, off in zip(fields, out[1:]):
-        assert getattr(lib.LksFilter, f).offset == off, f
+        assert getattr(S, f).offset == off, f
 
 
 def test_filter_validation_errors_without_gpu(lib):
@@ -201,7 +203,7 @@ def test_mma_validation_errors_without_gpu(lib):
     wb = L.lks_mma_workspace_bytes(n)
     assert wb >= 8 * 8 * n
     assert L.lks_mma_workspace_bytes(0) == 0
-    good = lib.LksMma(0.0, 1.0, 0.2)
+    good = lib.LksMma(0.0, 1.0, 0.2, 1.0)
     base = 1 << 30
     x, lo, up, d0, d1, x1, x2 = (C.c_void_p(base + k * (1 << 24)) for k in range(7))
     g1, lam = C.c_void_p(base + 7 * (1 << 24)), C.c_void_p(base + 7 * (1 << 24) + 64)
@@ -216,9 +218,10 @@ def test_mma_validation_errors_without_gpu(lib):
     assert call(opt=None) == lib.EINVAL
     assert call(n=0) == lib.EINVAL
     assert call(it=0) == lib.EINVAL
-    assert call(opt=lib.LksMma(1.0, 1.0, 0.2)) == lib.EINVAL
-    assert call(opt=lib.LksMma(0.0, float("inf"), 0.2)) == lib.EINVAL
-    assert call(opt=lib.LksMma(0.0, 1.0, 0.0)) == lib.EINVAL
+    assert call(opt=lib.LksMma(1.0, 1.0, 0.2, 1.0)) == lib.EINVAL
+    assert call(opt=lib.LksMma(0.0, float("inf"), 0.2, 1.0)) == lib.EINVAL
+    assert call(opt=lib.LksMma(0.0, 1.0, 0.0, 1.0)) == lib.EINVAL
+    assert call(opt=lib.LksMma(0.0, 1.0, 0.2, float("nan"))) == lib.EINVAL
     assert call(x=None) == lib.EINVAL
     assert call(x1=None) == lib.EINVAL          # iteration 3 needs the history
     assert call(wb=wb - 8) == lib.EINVAL
