@@ -236,6 +236,49 @@ def filter_measure(pb, reps=20):
     }
 
 
+def mma_measure(pb, reps=20):
+    """One MMA design update (FP64, iteration 3: asymptote history read) and the volume
+    constraint on the workload's design grid, timed with HIP events on the stream the
+    library's kernels run on (torch's current stream). Algorithmic bytes of the update per
+    design variable: the prep pass reads x, x^(k-1), x^(k-2), L, U, df0, dg1 and writes L,
+    U and 8 coefficients (17 x 8 B); each of the MMA_PASSES = 16 dual passes reads the 8
+    coefficients (128 x 8 B); the final pass reads them and writes x (9 x 8 B)."""
+    import torch
+
+    import paper_2601_18272_amd as lks
+
+    n = int(np.prod(pb.nd))
+    rng = np.random.default_rng(pb.seed + 5)
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")  # noqa: E731
+    x = rng.uniform(0.05, 0.95, n)
+    x1, x2 = np.clip(x + rng.normal(0, 0.05, n), 0, 1), np.clip(x + rng.normal(0, 0.05, n), 0, 1)
+    args = dict(xold1=t(x1), xold2=t(x2), low=t(x - rng.uniform(0.1, 0.6, n)), upp=t(x + rng.uniform(0.1, 0.6, n)))
+    xd, df0, dg1 = t(x), t(rng.normal(size=n) * 1e-3), t(np.full(n, -1.0 / (0.3 * n)))
+    work = torch.empty(lks.mma_workspace_bytes(n), dtype=torch.uint8, device="cuda")
+    G, _ = lks.volume_constraint(xd, 0.3, work=work)
+    for _ in range(3):
+        lks.mma_update(xd, df0, G, dg1, 3, work=work, **args)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    for _ in range(reps):
+        lks.mma_update(xd, df0, G, dg1, 3, work=work, **args)
+    ev[1].record()
+    for _ in range(reps):
+        lks.volume_constraint(xd, 0.3, work=work)
+    ev[2].record()
+    torch.cuda.synchronize()
+    upd_us = ev[0].elapsed_time(ev[1]) / reps * 1e3
+    vol_us = ev[1].elapsed_time(ev[2]) / reps * 1e3
+    by = (17 + 16 * 8 + 9) * 8 * n
+    vby = 2 * 8 * n
+    return {"design_points": n,
+            "update": {"kernels": "k_mma_prep, k_mma_r1, 16 x (k_mma_dual, k_mma_pick), k_mma_x",
+                       "avg_us": round(upd_us, 2), "bytes": by, "GBs": round(by / upd_us / 1e3, 1),
+                       "frac_hbm": round(by / upd_us / 1e3 / HBM_PEAK_GBS, 4)},
+            "volume_constraint": {"avg_us": round(vol_us, 2), "bytes": vby, "GBs": round(vby / vol_us / 1e3, 1)}}
+
+
 def cyclic_measure(pb, reps=20):
     """Cyclic periodic design on the workload's design grid (quarter turns when the
     rotation plane is square, else half turns): expansion (FP32) and collection (FP64),
@@ -410,7 +453,8 @@ def main():
     extra["copy_GBs_elementwise_1GiB"] = round(copy_bandwidth(), 1)
     extra["design_filter"] = filter_measure(pb)
     extra["cyclic_design"] = cyclic_measure(pb)
-    print("# design filter and cyclic design done", file=sys.stderr, flush=True)
+    extra["mma_update"] = mma_measure(pb)
+    print("# design filter, cyclic design and MMA update done", file=sys.stderr, flush=True)
 
     if not args.no_fp64:
         bufs64 = lks.Buffers(pb, "fp64", adjoint=True)
