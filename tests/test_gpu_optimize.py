@@ -52,16 +52,16 @@ def oracle_optimize(pb, gamma0, state0, body0, vmin, R, betas, qs, n_opt, eta, m
     return g, hist, iterates
 
 
-def run_both(pb, vmin, R, betas, qs, n_opt, periodic, eta=0.5, move=0.1):
+def run_both(pb, vmin, R, betas, qs, n_opt, periodic, eta=0.5, move=0.1, tol=1e-6):
     from paper_2601_18272_amd import api
     g0 = W.design(pb).astype(np.float64).reshape(-1)
     s0 = W.initial_state(pb).astype(np.float64)
     b0 = W.initial_body(pb).astype(np.float64)
     print(f"optimize {pb.name} betas={betas} qs={qs} n_opt={n_opt} periodic={periodic}", flush=True)
-    ref = oracle_optimize(pb, g0, s0, b0, vmin, R, betas, qs, n_opt, eta, move, periodic)
+    ref = oracle_optimize(pb, g0, s0, b0, vmin, R, betas, qs, n_opt, eta, move, periodic, tol)
     its = []
     g, hist = api.optimize(pb, torch.tensor(g0), torch.tensor(s0), torch.tensor(b0), vmin, R, betas, qs, n_opt,
-                           eta, move, "fp64", periodic, callback=lambda h, x: its.append(x.cpu().numpy()))
+                           eta, move, "fp64", periodic, tol, callback=lambda h, x: its.append(x.cpu().numpy()))
     return ref, (g.cpu().numpy(), hist, its)
 
 
@@ -101,3 +101,13 @@ def test_optimize_3d_periodic_matches_oracle():
     ref, gpu = run_both(pb, 0.53, 1.2, [2.0], [0.1], 3, True)
     compare(ref, gpu)
     assert any(h["lam"] is not None and 0.0 < h["lam"] < 1e20 for h in gpu[1])
+
+
+def test_optimize_stopping_criterion_ends_a_continuation_step():
+    """With a loose tolerance the second continuation step ends when J changes by less than
+    5 % with the constraint met; the next step starts from that design."""
+    pb = W.small2d(ckpt_every=5)
+    ref, gpu = run_both(pb, 0.55, 1.5, [1.0, 4.0, 8.0], [0.1, 1.0, 1.0], 4, False, tol=0.05)
+    compare(ref, gpu)
+    stops = [(h["l"], h["k"]) for h in gpu[1] if h["lam"] is None]
+    assert stops and stops[0][0] == 1 and stops[0][1] < 4
