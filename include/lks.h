@@ -254,14 +254,19 @@ int lks_design_cyclic_collect(const lks_problem_t *P, int n_sectors, const doubl
  * widths; move limits are opt->move box widths and 10 % of the way to the asymptotes. The
  * dual is solved by multi-section to double precision; if no multiplier up to 1e20 makes
  * the approximated constraint hold, the step uses 1e20. Deterministic (fixed-order sums).
- * Errors: LKS_EINVAL for n < 1, iter < 1, xmin >= xmax, move <= 0, null or aliased arrays,
- * a workspace smaller than lks_mma_workspace_bytes(n). Asynchronous on `stream`. */
+ * work: at least lks_mma_workspace_bytes(n) bytes of device scratch, caller-owned.
+ * Errors: LKS_EINVAL for n < 1, iter < 1, xmin >= xmax, move <= 0, a non-finite f0_scale,
+ * null arrays, outputs that overlap inputs, each other or the workspace, a workspace
+ * smaller than lks_mma_workspace_bytes(n); LKS_EHIP for a failed launch. Asynchronous on
+ * `stream` (no synchronisation). */
 typedef struct {
     double xmin, xmax; /* box of the design variables (0, 1 for gamma) */
     double move;       /* move limit, fraction of xmax - xmin */
     double f0_scale;   /* factor on df0 (1 to minimise the given function) */
 } lks_mma_t;
 
+/* Device scratch bytes for lks_mma_update / lks_volume_constraint on n variables (0 and
+ * LKS_EINVAL for n < 1). */
 size_t lks_mma_workspace_bytes(long long n);
 int lks_mma_update(const lks_mma_t *opt, long long n, int iter, double *x, const double *xold1,
                    const double *xold2, double *low, double *upp, const double *df0, const double *g1,
@@ -271,7 +276,9 @@ int lks_mma_update(const lks_mma_t *opt, long long n, int iter, double *x, const
  * paper's text; the printed inequality has the opposite sense):
  * G = 1 - sum(gh) / (vmin n) <= 0 and dG/dgh_j = -1 / (vmin n), from the projected design gh
  * [n] (device FP64). G [1] and dG [n] (may be NULL) are device outputs. work: at least
- * lks_mma_workspace_bytes(n) bytes. */
+ * lks_mma_workspace_bytes(n) bytes. Errors: LKS_EINVAL for n < 1, vmin not positive and
+ * finite, null arrays, overlaps among the arguments and the workspace, a short workspace;
+ * LKS_EHIP for a failed launch. Asynchronous on `stream`. */
 int lks_volume_constraint(long long n, const double *gh, double vmin, double *G, double *dG, void *work,
                           size_t work_bytes, void *stream);
 
