@@ -330,8 +330,9 @@ def main():
                     help="also run a 256 MiB device copy (reference for HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the grid would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (the grid would be "
+              "cut into x-slabs, one per GPU, with a two-layer halo exchange per step and a "
+              "force/torque allreduce per fluid-body iteration)", file=sys.stderr)
         sys.exit(2)
 
     import torch
