@@ -383,7 +383,6 @@ __global__ __launch_bounds__(256) void k_axial(Design D, const double *__restric
     // NA * NP < 2^31 (checked on the host): 32-bit division
     const unsigned tu = (unsigned)t, pu = tu / (unsigned)NA, ni = (unsigned)D.nd[D.pi];
     const int ib = (int)(tu - pu * (unsigned)NA) - 2;
-    const long long p = pu;
     int idx[3];
     idx[D.pi] = (int)(pu % ni);
     idx[D.pj] = (int)(pu / ni);
@@ -1370,7 +1369,9 @@ __global__ void k_adj_init(BodyParams bp, int obj, double seed, const double *__
 
 // Recompute, for all iterations of a step at once (blockIdx.y = k), the footprint
 // fields kappa^(k), u^S^(k), u^(k) from u* and the stored iterates B^(k). Also clears
-// the cotangent of u* on the box.
+// the cotangent of u* on the box when ustb is given (3D; in 2D the fields of a whole
+// checkpoint segment are formed beside its forward recompute, and k_adj_r2 starts the
+// cotangent at the first reverse iteration instead).
 template <int DIM, typename T, bool ROT, int LPN>
 __global__ __launch_bounds__(256) void k_adj_recompute(Grid g, Design D, const double *__restrict__ Bk,
                                                        const T *__restrict__ krT, const T *__restrict__ K1,
@@ -1383,7 +1384,7 @@ __global__ __launch_bounds__(256) void k_adj_recompute(Grid g, Design D, const d
     const int k = blockIdx.y;
     if (l >= D.boxN) return;
     const long long bN = D.boxN;
-    if (k == 0 && q == 0)
+    if (ustb && k == 0 && q == 0)
 #pragma unroll
         for (int a = 0; a < DIM; a++) ustb[a * bN + l] = T(0);
     int o[3], x[3];
@@ -1693,13 +1694,14 @@ __global__ __launch_bounds__(256) void k_adj_r2(Grid g, Bc bc, Design D, const d
         for (int a = 0; a < DIM; a++) usb[a * bN + l] = T(0);
         return;
     }
-    // the node's own fields, requested before the gather
+    // the node's own fields, requested before the gather; the cotangent of u* starts
+    // at the first reverse iteration (k = K - 1), which writes every node of the grid
     T kap = 0, ust[3] = {0, 0, 0}, dus[3] = {0, 0, 0};
     if (q == 0) {
         kap = kapk[k * bN + l];
 #pragma unroll
         for (int a = 0; a < DIM; a++) {
-            ust[a] = ustb[a * bN + l];
+            ust[a] = k == K - 1 ? T(0) : ustb[a * bN + l];
             dus[a] = usk[(k * DIM + a) * bN + l] - uk[(k * DIM + a) * bN + l];
         }
     }

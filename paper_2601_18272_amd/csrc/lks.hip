@@ -324,6 +324,9 @@ struct Layout {
     size_t ab, kapk, usk, uk, ustb, kb, usb, URb, krb, part1, part3, rec;
     size_t K1f, K1r;  // 3D axial sums of kappa_ref: forward (one pose), reverse (n_itr poses)
     size_t AU;        // 3D axial sums of the u^ref cotangents (one pose, 3 components)
+    // 2D adjoint: kappa^(k), u^S^(k), u^(k) on the box for every step of a segment (two
+    // buffers like the segments), pre_n bytes each; 0 in 3D
+    size_t pre, pre_n;
     size_t total;
 };
 
@@ -335,6 +338,10 @@ size_t axial_elems(const Ctx &c) {
     if (!c.has_body || c.dim != 3) return 1;
     return (size_t)(c.D.nd[c.D.axis] + 4) * c.D.nd[c.D.pi] * c.D.nd[c.D.pj];
 }
+
+// Elements of one step's footprint fields for the reverse sweep: kappa^(k), u^S^(k),
+// u^(k) for the n_itr iterations, in that order.
+size_t pre_elems(const Ctx &c) { return (size_t)c.K * (size_t)(1 + 2 * c.dim) * (size_t)c.D.boxN; }
 
 Layout layout(const Ctx &c, bool adjoint) {
     Layout L{};
@@ -371,6 +378,8 @@ Layout layout(const Ctx &c, bool adjoint) {
         L.seg = take(2 * L.seg_n);
         L.ustar_seg = take(2 * L.ustar_seg_n);
         L.Bseg = take(2 * L.Bseg_n);
+        L.pre_n = (c.dim == 2 && c.has_body) ? up(Kc * pre_elems(c) * e) : 0;
+        L.pre = take(2 * L.pre_n);
         L.ab = take(2 * stateB);
         L.kapk = take(K * bN * e);
         L.usk = take(K * d * bN * e);
@@ -575,13 +584,9 @@ template <typename T> struct Run {
         }
     }
     // reverse of the body loop of one step (records Bk, footprint u* of the step)
-    void body_rev(const double *Bk, const T *ustar, const T *ab, const T *krT, const double *krD, const Layout &L,
-                  void *w) const {
-        T *kapk = at<T>(w, L.kapk), *usk = at<T>(w, L.usk), *uk = at<T>(w, L.uk);
-        T *ustb = at<T>(w, L.ustb), *kb = at<T>(w, L.kb), *usb = at<T>(w, L.usb), *URb = at<T>(w, L.URb);
-        double *krb = at<double>(w, L.krb), *p1 = at<double>(w, L.part1), *p3 = at<double>(w, L.part3);
-        auto recb = [&](int b) { return at<double>(w, L.rec) + (size_t)b * AR_SIZE; };
-        T *AU = at<T>(w, L.AU);
+    // footprint fields of every iteration of one step (kappa^(k), u^S^(k), u^(k)) from the
+    // stored iterates and u*, for the reverse sweep; ustb (may be null) is cleared
+    void adj_fields(const double *Bk, const T *ustar, const T *krT, T *kapk, T *usk, T *uk, T *ustb) const {
         const dim3 gb(blocks(c.D.boxN * (c.dim == 2 ? 4 : 1), 256), c.K);
         dispatch(c, [&](auto dm, auto rt) {
             constexpr int DIM = decltype(dm)::value;
@@ -600,6 +605,28 @@ template <typename T> struct Run {
                     hipExtLaunchKernelGGL((k_adj_recompute<DIM, T, ROT, lpn<DIM>()>), gb, dim3(256), 0, st, es, e1, 0,
                                           c.g, c.D, Bk, krT, (const T *)ax, ustar, kapk, usk, uk, ustb);
             });
+        });
+    }
+    // reverse of the body loop of one step (records Bk, footprint u* of the step); pre
+    // (2D): the step's footprint fields, formed beside the segment's forward recompute
+    void body_rev(const double *Bk, const T *ustar, const T *ab, const T *krT, const double *krD, const Layout &L,
+                  void *w, const T *pre) const {
+        T *kapk = at<T>(w, L.kapk), *usk = at<T>(w, L.usk), *uk = at<T>(w, L.uk);
+        T *ustb = at<T>(w, L.ustb), *kb = at<T>(w, L.kb), *usb = at<T>(w, L.usb), *URb = at<T>(w, L.URb);
+        double *krb = at<double>(w, L.krb), *p1 = at<double>(w, L.part1), *p3 = at<double>(w, L.part3);
+        auto recb = [&](int b) { return at<double>(w, L.rec) + (size_t)b * AR_SIZE; };
+        T *AU = at<T>(w, L.AU);
+        const size_t bN = (size_t)c.D.boxN;
+        if (pre) {
+            kapk = const_cast<T *>(pre);
+            usk = kapk + (size_t)c.K * bN;
+            uk = usk + (size_t)c.K * c.dim * bN;
+        } else {
+            adj_fields(Bk, ustar, krT, kapk, usk, uk, ustb);
+        }
+        dispatch(c, [&](auto dm, auto rt) {
+            constexpr int DIM = decltype(dm)::value;
+            constexpr bool ROT = decltype(rt)::value;
             for (int k = c.K - 1; k >= 0; k--) {
                 // record step of the pending iteration inside this R1 (reads recb(rcur) and
                 // the partials in p3, writes recb(1 - rcur))
@@ -822,6 +849,8 @@ int adjoint_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, const vo
     if (memcmp(h.magic, "LKSCKPT", 8) != 0 || h.dim != c.dim || h.prec != c.prec || h.K != c.K || h.Kc != c.Kc ||
         h.NT != c.NT || h.N != c.g.N || h.ND != (c.has_body ? c.D.ND : 0))
         return fail(LKS_EINVAL, "checkpoint store does not match the problem (run lks_forward with it first)");
+    if (c.has_body && (h.boxN < 1 || h.boxN > c0.D.boxN))  // the workspace holds boxes of c0.D.boxN nodes
+        return fail(LKS_EINVAL, "checkpoint store: footprint box larger than the problem's");
     for (int a = 0; a < 3; a++) {
         c.D.H[a] = h.H[a];
         c.D.L[a] = h.L[a];
@@ -868,6 +897,7 @@ int adjoint_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, const vo
     auto segb = [&](int b) { return at<T>(work, L.seg + (size_t)b * L.seg_n); };
     auto ustar_segb = [&](int b) { return at<T>(work, L.ustar_seg + (size_t)b * L.ustar_seg_n); };
     auto Bsegb = [&](int b) { return at<double>(work, L.Bseg + (size_t)b * L.Bseg_n); };
+    auto preb = [&](int b) { return at<T>(work, L.pre + (size_t)b * L.pre_n); };
     const size_t recN = (size_t)(c.K + 1) * B_REC;
     const size_t S = (size_t)c.S;
     const size_t fp = (size_t)c.dim * (size_t)c.D.boxN;
@@ -907,6 +937,12 @@ int adjoint_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, const vo
                 F.body_loop(cur, Bk, Bseg + (size_t)(j + 1) * recN, krT, krD, ustar_seg + (size_t)(j - 1) * fp, part,
                             counter, flag);
             F.bcs(cur);
+            if (L.pre_n) {  // 2D: the step's footprint fields for the reverse sweep
+                T *pk = preb(b) + (size_t)(j - 1) * pre_elems(c);
+                T *pu = pk + (size_t)c.K * c.D.boxN;
+                F.adj_fields(Bk, ustar_seg + (size_t)(j - 1) * fp, krT, pk, pu, pu + (size_t)c.K * c.dim * c.D.boxN,
+                             nullptr);
+            }
         }
         HIP_TRY(hipEventRecord(evFwd[b], side.s));
         return LKS_OK;
@@ -929,7 +965,9 @@ int adjoint_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, const vo
         for (int j = len; j >= 1; j--) {
             pf.sample = (t0 + j - 1) % every == 0;
             const double *Bk = Bseg + (size_t)j * recN;
-            if (c.has_body) R.body_rev(Bk, ustar_seg + (size_t)(j - 1) * fp, ab_cur, krT, krD, L, work);
+            if (c.has_body)
+                R.body_rev(Bk, ustar_seg + (size_t)(j - 1) * fp, ab_cur, krT, krD, L, work,
+                           L.pre_n ? preb(b) + (size_t)(j - 1) * pre_elems(c) : nullptr);
             R.adj_gather(ab_cur, ustb, Bk, seg + (size_t)(j - 1) * S, ab_nxt);
             T *tmp = ab_cur;
             ab_cur = ab_nxt;
