@@ -1410,7 +1410,7 @@ int lks_mma_update(const lks_mma_t *opt, long long n, int iter, double *x, const
     for (int pass = 0; pass < MMA_PASSES; pass++) {
         hipLaunchKernelGGL(k_mma_dual, dim3(nb), dim3(MMA_NT), 0, st, n, pass, (const double *)coef,
                            (const MmaState *)ms, part);
-        hipLaunchKernelGGL(k_mma_pick, dim3(1), dim3(MMA_NT), 0, st, pass, (const double *)part, (int)nb, ms);
+        hipLaunchKernelGGL(k_mma_pick, dim3(1), dim3(MMA_PICK_NT), 0, st, pass, (const double *)part, (int)nb, ms);
     }
     hipLaunchKernelGGL(k_mma_x, dim3(nb), dim3(MMA_NT), 0, st, n, (const double *)coef, (const MmaState *)ms, x,
                        lambda);

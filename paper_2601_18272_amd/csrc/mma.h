@@ -9,8 +9,9 @@
 // multiplier lam >= 0 the minimiser x_j(lam) is in closed form, and the dual derivative
 // h(lam) = f~_1(x(lam)) is non-increasing. lam is found by multi-section: each pass
 // evaluates h at MMA_M multipliers at once (every thread adds its variables' terms for
-// all of them, fixed-order block sums, then one block sums the partials in block order
-// and keeps the bracket [lo, hi] with h(lo) > 0 >= h(hi)); the first pass uses a
+// all of them, fixed-order block sums stored multiplier-major, then one block with a
+// wave per multiplier sums them in a fixed order and keeps the bracket [lo, hi] with
+// h(lo) > 0 >= h(hi)); the first pass uses a
 // geometric ladder from 0 to 10^(MMA_LOG_HI), the next ones split the bracket evenly.
 // The update is x_j(hi) (k_mma_x). No atomics; two runs give the same bits.
 #pragma once
@@ -43,13 +44,15 @@ __device__ __forceinline__ double mma_x_of(double lam, const double c[MC_COUNT])
     return fmin(fmax(xs, c[MC_A]), c[MC_B]);
 }
 
+// p_1 / (U - x) + q_1 / (x - L) over one division (x lies strictly inside (L, U)).
 __device__ __forceinline__ double mma_h_term(double lam, const double c[MC_COUNT]) {
     const double x = mma_x_of(lam, c);
-    return c[MC_P1] / (c[MC_U] - x) + c[MC_Q1] / (x - c[MC_L]);
+    const double a = c[MC_U] - x, b = x - c[MC_L];
+    return (c[MC_P1] * b + c[MC_Q1] * a) / (a * b);
 }
 
 // Block sum of NV values per thread (fixed order: per wave an xor tree, then the
-// waves in order); thread j < NV stores sum j into out[blockIdx.x * NV + j].
+// waves in order); thread j < NV stores sum j into out[j * gridDim.x + blockIdx.x].
 template <int NV>
 __device__ __forceinline__ void mma_block_store(double v[NV], double *__restrict__ out) {
     __shared__ double red[NV][MMA_NT / 64];
@@ -66,7 +69,7 @@ __device__ __forceinline__ void mma_block_store(double v[NV], double *__restrict
         double s = 0.0;
 #pragma unroll
         for (int w = 0; w < MMA_NT / 64; w++) s += red[threadIdx.x][w];
-        out[(size_t)blockIdx.x * NV + threadIdx.x] = s;
+        out[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
     }
 }
 
@@ -171,27 +174,24 @@ __global__ __launch_bounds__(MMA_NT) void k_mma_dual(long long n, int pass, cons
     mma_block_store<MMA_M>(acc, part);
 }
 
-// One block: h at the pass's multipliers from the partials (block order), then the new
-// bracket: the first multiplier with h <= 0 closes it; at the ladder's 0 the update is
-// lam = 0; if none, lam is the last multiplier (the approximated constraint cannot be
-// met within the move limits).
-__global__ __launch_bounds__(MMA_NT) void k_mma_pick(int pass, const double *__restrict__ part, int nb,
-                                                     MmaState *__restrict__ st) {
+// One block, a wave per multiplier: h at the pass's multipliers from the partials (lane l
+// adds blocks l, l + 64, ..., then a fixed xor tree), then the new bracket: the first
+// multiplier with h <= 0 closes it; at the ladder's 0 the update is lam = 0; if none, lam
+// is the last multiplier (the approximated constraint cannot be met within the move
+// limits).
+constexpr int MMA_PICK_NT = MMA_M * 64;
+__global__ __launch_bounds__(MMA_PICK_NT) void k_mma_pick(int pass, const double *__restrict__ part, int nb,
+                                                          MmaState *__restrict__ st) {
     __shared__ double h[MMA_M];
-    __shared__ double red[MMA_M][MMA_NT / MMA_M];
     const MmaState s = *st;
     if (s.done) return;
-    constexpr int G = MMA_NT / MMA_M;  // threads per multiplier
-    const int i = threadIdx.x % MMA_M, g = threadIdx.x / MMA_M;
+    const int i = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const double *pi = part + (size_t)i * nb;
     double a = 0.0;
-    for (int b = g; b < nb; b += G) a += part[(size_t)b * MMA_M + i];
-    red[i][g] = a;
-    __syncthreads();
-    if (threadIdx.x < MMA_M) {
-        double t = s.r1;
-        for (int k = 0; k < G; k++) t += red[threadIdx.x][k];
-        h[threadIdx.x] = t;
-    }
+    for (int b = lane; b < nb; b += 64) a += pi[b];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+    if (lane == 0) h[i] = s.r1 + a;
     __syncthreads();
     if (threadIdx.x != 0) return;
     int first = -1;
