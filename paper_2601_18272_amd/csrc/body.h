@@ -1368,25 +1368,20 @@ __global__ void k_adj_init(BodyParams bp, int obj, double seed, const double *__
 }
 
 // Recompute, for all iterations of a step at once (blockIdx.y = k), the footprint
-// fields kappa^(k), u^S^(k), u^(k) from u* and the stored iterates B^(k). Also clears
-// the cotangent of u* on the box when ustb is given (3D; in 2D the fields of a whole
-// checkpoint segment are formed beside its forward recompute, and k_adj_r2 starts the
-// cotangent at the first reverse iteration instead).
+// fields kappa^(k), u^S^(k), u^(k) from u* and the stored iterates B^(k). These depend
+// on forward data only (the cotangent of u* on the box needs no clearing: k_adj_r2
+// starts it at the first reverse iteration).
 template <int DIM, typename T, bool ROT, int LPN>
 __global__ __launch_bounds__(256) void k_adj_recompute(Grid g, Design D, const double *__restrict__ Bk,
                                                        const T *__restrict__ krT, const T *__restrict__ K1,
                                                        const T *__restrict__ ustar, T *__restrict__ kapk,
-                                                       T *__restrict__ usk, T *__restrict__ uk,
-                                                       T *__restrict__ ustb) {
+                                                       T *__restrict__ usk, T *__restrict__ uk) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long l = t / LPN;
     const int q = (int)(t % LPN);
     const int k = blockIdx.y;
     if (l >= D.boxN) return;
     const long long bN = D.boxN;
-    if (ustb && k == 0 && q == 0)
-#pragma unroll
-        for (int a = 0; a < DIM; a++) ustb[a * bN + l] = T(0);
     int o[3], x[3];
     box_origin<DIM>(D, Bk, o);
     T kap = 0, us[3] = {0, 0, 0};
@@ -1414,7 +1409,7 @@ template <typename T, bool ROT>
 __global__ __launch_bounds__(256) void k_adj_recompute_rows(Grid g, Design D, const double *__restrict__ Bk,
                                                             const T *__restrict__ K1, const T *__restrict__ ustar,
                                                             T *__restrict__ kapk, T *__restrict__ usk,
-                                                            T *__restrict__ uk, T *__restrict__ ustb) {
+                                                            T *__restrict__ uk) {
     const int r = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int k = blockIdx.y;
     if (r >= BoxRow::count(D)) return;  // whole waves
@@ -1433,9 +1428,6 @@ __global__ __launch_bounds__(256) void k_adj_recompute_rows(Grid g, Design D, co
         long long l;
         int x[3];
         const bool ok = br.node(g, D, o, ba, l, x);
-        if (k == 0)
-#pragma unroll
-            for (int a = 0; a < 3; a++) ustb[a * bN + l] = T(0);
         T kap = 0, us[3] = {0, 0, 0};
         if (ok) spread_node_row<T, ROT>(D, B, ax, K1k, x[D.axis], pr, kap, us);
         kapk[k * bN + l] = kap;
@@ -1852,12 +1844,13 @@ __global__ __launch_bounds__(256) void k_adj_r2_rows(Grid g, Bc bc, Design D, co
             for (int a = 0; a < 3; a++) usb[a * bN + l] = T(0);
             continue;
         }
-        // the node's own fields, requested before the gather
+        // the node's own fields, requested before the gather; the cotangent of u* starts
+        // at the first reverse iteration (k = K - 1)
         const T kap = kapk[k * bN + l];
         T ust[3], dus[3];
 #pragma unroll
         for (int a = 0; a < 3; a++) {
-            ust[a] = ustb[a * bN + l];
+            ust[a] = k == K - 1 ? T(0) : ustb[a * bN + l];
             dus[a] = usk[(k * 3 + a) * bN + l] - uk[(k * 3 + a) * bN + l];
         }
         T ub[3] = {0, 0, 0};

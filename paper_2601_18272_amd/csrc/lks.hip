@@ -585,8 +585,8 @@ template <typename T> struct Run {
     }
     // reverse of the body loop of one step (records Bk, footprint u* of the step)
     // footprint fields of every iteration of one step (kappa^(k), u^S^(k), u^(k)) from the
-    // stored iterates and u*, for the reverse sweep; ustb (may be null) is cleared
-    void adj_fields(const double *Bk, const T *ustar, const T *krT, T *kapk, T *usk, T *uk, T *ustb) const {
+    // stored iterates and u*, for the reverse sweep
+    void adj_fields(const double *Bk, const T *ustar, const T *krT, T *kapk, T *usk, T *uk) const {
         const dim3 gb(blocks(c.D.boxN * (c.dim == 2 ? 4 : 1), 256), c.K);
         dispatch(c, [&](auto dm, auto rt) {
             constexpr int DIM = decltype(dm)::value;
@@ -600,10 +600,10 @@ template <typename T> struct Run {
                 }
                 if constexpr (DIM == 3 && ROT)  // one wave per box row and pose (k_adj_recompute_rows)
                     hipExtLaunchKernelGGL((k_adj_recompute_rows<T, ROT>), dim3(blocks(box_rows(c), 4), c.K), dim3(256), 0,
-                                          st, es, e1, 0, c.g, c.D, Bk, (const T *)ax, ustar, kapk, usk, uk, ustb);
+                                          st, es, e1, 0, c.g, c.D, Bk, (const T *)ax, ustar, kapk, usk, uk);
                 else
                     hipExtLaunchKernelGGL((k_adj_recompute<DIM, T, ROT, lpn<DIM>()>), gb, dim3(256), 0, st, es, e1, 0,
-                                          c.g, c.D, Bk, krT, (const T *)ax, ustar, kapk, usk, uk, ustb);
+                                          c.g, c.D, Bk, krT, (const T *)ax, ustar, kapk, usk, uk);
             });
         });
     }
@@ -622,7 +622,7 @@ template <typename T> struct Run {
             usk = kapk + (size_t)c.K * bN;
             uk = usk + (size_t)c.K * c.dim * bN;
         } else {
-            adj_fields(Bk, ustar, krT, kapk, usk, uk, ustb);
+            adj_fields(Bk, ustar, krT, kapk, usk, uk);
         }
         dispatch(c, [&](auto dm, auto rt) {
             constexpr int DIM = decltype(dm)::value;
@@ -940,8 +940,7 @@ int adjoint_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, const vo
             if (L.pre_n) {  // 2D: the step's footprint fields for the reverse sweep
                 T *pk = preb(b) + (size_t)(j - 1) * pre_elems(c);
                 T *pu = pk + (size_t)c.K * c.D.boxN;
-                F.adj_fields(Bk, ustar_seg + (size_t)(j - 1) * fp, krT, pk, pu, pu + (size_t)c.K * c.dim * c.D.boxN,
-                             nullptr);
+                F.adj_fields(Bk, ustar_seg + (size_t)(j - 1) * fp, krT, pk, pu, pu + (size_t)c.K * c.dim * c.D.boxN);
             }
         }
         HIP_TRY(hipEventRecord(evFwd[b], side.s));
