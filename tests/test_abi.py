@@ -235,3 +235,12 @@ def test_mma_validation_errors_without_gpu(lib):
     assert L.lks_volume_constraint(n, x, float("nan"), G, dG, work, wb, None) == lib.EINVAL
     assert L.lks_volume_constraint(n, x, 0.3, G, C.c_void_p(x.value + 8), work, wb, None) == lib.EINVAL
     assert L.lks_volume_constraint(n, x, 0.3, G, dG, work, 8, None) == lib.EINVAL
+
+
+def test_optimize_rejects_mismatched_continuation_lists():
+    """The continuation lists are checked on the host before any device work."""
+    from paper_2601_18272_amd import api
+
+    pb = W.small2d(ckpt_every=5)
+    with pytest.raises(ValueError):
+        api.optimize(pb, None, None, None, 0.5, 1.5, betas=[1.0, 2.0], qs=[0.1])
