@@ -88,16 +88,35 @@ __global__ __launch_bounds__(512) void k_gather2d(Grid g, T A, const T *__restri
                 dyuy = T(0.5) * (T(3) * suy[ly][lx] - T(4) * suy[ly - 1][lx] + suy[ly - 2][lx]);
             }
             const T p = sp[ly][lx], ux = sux[ly][lx], uy = suy[ly][lx];
-            // f_i = w_i (3p - 3/2 u.u + 3 c.u + 9/2 (c.u)^2 + A c.(S + S^T).c)
+            // f_i = w_i (3p - 3/2 u.u + 3 c.u + 9/2 (c.u)^2 + A c.(S + S^T).c), formed for the
+            // pairs +-c at once: the even part w (base + 9/2 (c.u)^2 + A c.(S + S^T).c) is
+            // shared, the odd part 3 w c.u changes sign; no term with a zero component of c
             const T base = T(3) * p - T(1.5) * (ux * ux + uy * uy);
-            const T axx = T(2) * A * dxux, ayy = T(2) * A * dyuy, axy = T(2) * A * (dxuy + dyux);
+            const T A2 = T(2) * A;
+            const T axx = A2 * dxux, ayy = A2 * dyuy, axy = A2 * (dxuy + dyux);
             f[0] = w0 * base;
-#pragma unroll
-            for (int i = 1; i < 9; i++) {
-                const int cx = Lat<2>::c(i, 0), cy = Lat<2>::c(i, 1);
-                const T cu = T(cx) * ux + T(cy) * uy;
-                const T an = T(cx * cx) * axx + T(cy * cy) * ayy + T(cx * cy) * axy;
-                f[i] = (i < 5 ? w1 : w2) * (base + T(3) * cu + T(4.5) * cu * cu + an);
+            {
+                const T ev = w1 * (base + T(4.5) * ux * ux + axx), od = T(3) * w1 * ux;
+                f[1] = ev + od;
+                f[2] = ev - od;
+            }
+            {
+                const T ev = w1 * (base + T(4.5) * uy * uy + ayy), od = T(3) * w1 * uy;
+                f[3] = ev + od;
+                f[4] = ev - od;
+            }
+            const T bd = base + axx + ayy;
+            {
+                const T cu = ux + uy;
+                const T ev = w2 * (bd + T(4.5) * cu * cu + axy), od = T(3) * w2 * cu;
+                f[5] = ev + od;
+                f[6] = ev - od;
+            }
+            {
+                const T cu = ux - uy;
+                const T ev = w2 * (bd + T(4.5) * cu * cu - axy), od = T(3) * w2 * cu;
+                f[7] = ev + od;
+                f[8] = ev - od;
             }
         } else {
 #pragma unroll
@@ -112,15 +131,15 @@ __global__ __launch_bounds__(512) void k_gather2d(Grid g, T A, const T *__restri
     const bool act = x < nx && y < ny && !((!g.per[0] && (x == 0 || x == nx - 1)) ||
                                            (!g.per[1] && (y == 0 || y == ny - 1)));
     if (act) {
-        T ps = 0, usx = 0, usy = 0;
+        // the f_i streaming into the node, then the moments with the signs of c written out
+        T fi[9];
 #pragma unroll
-        for (int i = 0; i < 9; i++) {
-            const int cx = Lat<2>::c(i, 0), cy = Lat<2>::c(i, 1);
-            const T f = sf[i][threadIdx.y + 1 - cy][threadIdx.x + 1 - cx];
-            ps += f;
-            usx += T(cx) * f;
-            usy += T(cy) * f;
-        }
+        for (int i = 0; i < 9; i++)
+            fi[i] = sf[i][threadIdx.y + 1 - Lat<2>::c(i, 1)][threadIdx.x + 1 - Lat<2>::c(i, 0)];
+        const T d56 = fi[5] - fi[6], d78 = fi[7] - fi[8];
+        const T ps = fi[0] + (fi[1] + fi[2]) + (fi[3] + fi[4]) + (fi[5] + fi[6]) + (fi[7] + fi[8]);
+        const T usx = (fi[1] - fi[2]) + d56 + d78;
+        const T usy = (fi[3] - fi[4]) + d56 - d78;
         const long long id = (long long)x + (long long)nx * y;
         sout[id] = ps * T(1.0 / 3.0);
         sout[N + id] = usx;
