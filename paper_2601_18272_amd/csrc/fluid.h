@@ -587,19 +587,22 @@ __global__ __launch_bounds__(512) void k_adjgather2d(Grid g, Bc bc, T A, const T
     for (int l = tid; l < MX * MY; l += 512) {
         const int mx = l % MX, my = l / MX;
         const int lx = mx + 1, ly = my + 1;  // in the 3-ring arrays
-        T pi = 0, ux = 0, uy = 0, sxx = 0, syy = 0, sxy = 0;
-#pragma unroll
-        for (int i = 0; i < 9; i++) {
-            const int cx = Lat<2>::c(i, 0), cy = Lat<2>::c(i, 1);
-            const T gi = sP[ly + cy][lx + cx] + T(cx) * sU[ly + cy][lx + cx] + T(cy) * sV[ly + cy][lx + cx];
-            const T wg = T(Lat<2>::w(i)) * gi;
-            pi += wg;
-            ux += T(cx) * wg;
-            uy += T(cy) * wg;
-            sxx += T(cx * cx) * wg;
-            syy += T(cy * cy) * wg;
-            sxy += T(cx * cy) * wg;
-        }
+        // g_i = (p*bar/3 + c_i.u*bar)(x + c_i) and the moments sum_i w_i g_i (1, c_i, c_i c_i),
+        // with the signs of c written out (no term with a zero component of c)
+        const T g0 = sP[ly][lx];
+        const T g1 = sP[ly][lx + 1] + sU[ly][lx + 1], g2 = sP[ly][lx - 1] - sU[ly][lx - 1];
+        const T g3 = sP[ly + 1][lx] + sV[ly + 1][lx], g4 = sP[ly - 1][lx] - sV[ly - 1][lx];
+        const T g5 = sP[ly + 1][lx + 1] + sU[ly + 1][lx + 1] + sV[ly + 1][lx + 1];
+        const T g6 = sP[ly - 1][lx - 1] - sU[ly - 1][lx - 1] - sV[ly - 1][lx - 1];
+        const T g7 = sP[ly - 1][lx + 1] + sU[ly - 1][lx + 1] - sV[ly - 1][lx + 1];
+        const T g8 = sP[ly + 1][lx - 1] - sU[ly + 1][lx - 1] + sV[ly + 1][lx - 1];
+        const T w0 = T(4.0 / 9.0), w1 = T(1.0 / 9.0), w2 = T(1.0 / 36.0);
+        const T e1 = g1 + g2, e2 = g3 + g4, s56 = g5 + g6, s78 = g7 + g8, d56 = g5 - g6, d78 = g7 - g8;
+        const T dd = w2 * (s56 + s78);
+        const T pi = w0 * g0 + w1 * (e1 + e2) + dd;
+        const T ux = w1 * (g1 - g2) + w2 * (d56 + d78);
+        const T uy = w1 * (g3 - g4) + w2 * (d56 - d78);
+        const T sxx = w1 * e1 + dd, syy = w1 * e2 + dd, sxy = w2 * (s56 - s78);
         mpi[my][mx] = pi;
         mux[my][mx] = ux;
         muy[my][mx] = uy;
