@@ -81,3 +81,16 @@ def test_volume_constraint_reading():
     G, dG = mma.volume_constraint(gh, 0.3)
     assert abs(G) < 1e-15 and np.allclose(dG, -1.0 / (0.3 * 64))
     assert mma.volume_constraint(np.full(64, 0.2), 0.3)[0] > 0  # too little solid: violated
+
+
+def test_infeasible_step_takes_the_multiplier_cap():
+    """No artificial variables: when no multiplier meets the approximated constraint within
+    the move limits, the step uses lambda = LAM_MAX itself, and x(LAM_MAX) is the
+    constraint's own minimiser on [alpha, beta]; here every variable moves to its upper
+    move limit x + 0.2 (the constraint falls as x grows, dg1 = -1)."""
+    n = 30
+    x = np.full(n, 0.3)
+    df0 = np.linspace(-1e-3, 1e-3, n)
+    xn, lo, up, lam = mma.mma_step(x, x, x, np.zeros(n), np.zeros(n), df0, float(n), -np.ones(n), 1, 0.0, 1.0, 0.2)
+    assert lam == mma.LAM_MAX == 1e20
+    assert np.abs(xn - 0.5).max() <= 1e-12
