@@ -669,3 +669,211 @@ def test_cyclic_expansion_small_tables(orc):
     assert np.array_equal(orc.cyclic_expand(pb, 2, [a, b, c]), [a, b, c, c, b, a])
     assert orc.cyclic_sector_points(pb, 4) == -1  # quarter turns need a square plane
     assert orc.cyclic_sector_points(pb, 3) == -1
+
+
+# ----------------------------- coupling constant of the fluid <-> body iteration (Sec. 3.1)
+
+def _covering3d(kmax=0.4, gam=0.5):
+    """Periodic 6x5x4 grid covered by a node-aligned 12x11x10 design (design points on
+    nodes, >= 2 beyond every face): kappa(x) = kappa_ref and sum_m W r_m = x - x^G."""
+    pb = periodic(3, (6, 5, 4), nu=0.1, nd=(12, 11, 10), kappa_max=kmax, q=0.1, mass=60.0,
+                  inertia=1e3, axis=0, dof_mask=W.DOF_TX, n_itr=1, n_steps=1,
+                  x_g0=(2.5, 2.0, 1.5), u0=(0.04, 0.01, -0.02))
+    kr = kmax * 0.1 * gam / (1 - gam + 0.1)
+    return pb, np.full(pb.ND, gam), kr
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_coupling_constant_closed_form(orc, dim):
+    """The coupling constants K = -dF/du^G and K_theta = -dT/domega at a frozen pose and
+    u* (Sec. 3.1's iteration contracts when K/M < 1). With a node-aligned design covering
+    the grid, kappa = kappa_ref, sum_m W = 1 at every node and sum_m W r_m = x - x^G
+    (the three node weights 1/4, 1/2, 1/4 are symmetric), so
+    K = kappa_ref (N_D - N kappa_ref/(1 + kappa_ref)) and
+    K_theta = kappa_ref (sum_m |r_m,perp|^2 - kappa_ref/(1 + kappa_ref) sum_x |(x - x^G)_perp|^2),
+    perp = the part across the rotation axis. Sums over coordinates only; no weights."""
+    if dim == 2:
+        pb, g, kr = covering(1, W.DOF_TX)
+        plane = (0, 1)
+    else:
+        pb, g, kr = _covering3d()
+        plane = (1, 2)
+    N, ND = pb.N, pb.ND
+    K = orc.coupling(pb, g, W.initial_state(pb), W.initial_body(pb))
+    f = kr / (1 + kr)
+    Kt = kr * (ND - N * f)
+    # lever arms: design offsets xi_m (theta = 0) and node offsets from x^G
+    xi = [np.arange(pb.nd[a]) - 0.5 * (pb.nd[a] - 1) for a in range(3)]
+    XI = np.meshgrid(*xi, indexing="ij")
+    xs = [np.arange(pb.n[a]) - pb.x_g0[a] for a in range(3)]
+    XS = np.meshgrid(*xs, indexing="ij")
+    r2 = sum((XI[a] ** 2).sum() for a in plane)
+    x2 = sum((XS[a] ** 2).sum() for a in plane)
+    Kr = kr * (r2 - f * x2)
+    for a in range(dim):
+        assert K[a] == pytest.approx(Kt, rel=1e-12)
+    for a in range(dim, 3):
+        assert K[a] == 0.0
+    assert K[3] == pytest.approx(Kr, rel=1e-12)
+    assert Kt > 0 and Kr > 0
+
+
+@pytest.mark.parametrize("mass", [400.0, 60.0, 25.0])
+def test_iteration_contracts_at_ratio_K_over_M(orc, mass):
+    """Within one step the iterates of Sec. 3.1 satisfy u^G,(k+1) = u^G(t-1) + F(u^G,(k))/M,
+    and F is affine in the body velocity with slope -K at a frozen pose: successive
+    differences of the iterates shrink by the factor -K/M (the pose moves only by the
+    tiny u^G itself). Ties the forward loop to the coupling constant on a generic body
+    in a channel, with K/M from 0.007 to 0.11."""
+    pb = W.small2d(dof_mask=W.DOF_TX, n_steps=1, mass=mass, theta0=0.0)
+    g, s0, b0 = W.design(pb), W.initial_state(pb), W.initial_body(pb)
+    K = orc.coupling(pb, g, s0, b0)
+    it = [orc.forward(pb.replace(n_itr=n), g, s0, b0)[1][3] for n in range(1, 6)]
+    d = np.diff(it)
+    for r in d[1:] / d[:-1]:
+        assert r == pytest.approx(-K[0] / mass, rel=1e-4)
+
+
+def test_rotation_iteration_contracts_at_ratio_K_over_I(orc):
+    """The same for a body rotating about a fixed pivot: the angular velocity iterates
+    shrink by -K_theta/I (the pose turns with the iterate, so only to 0.5 %)."""
+    pb = W.small2d(dof_mask=W.DOF_ROT, n_steps=1, inertia=300.0, theta0=0.0)
+    g, s0, b0 = W.design(pb), W.initial_state(pb), W.initial_body(pb)
+    K = orc.coupling(pb, g, s0, b0)
+    it = [orc.forward(pb.replace(n_itr=n), g, s0, b0)[1][7] for n in range(1, 6)]
+    d = np.diff(it)
+    for r in d[1:] / d[:-1]:
+        assert r == pytest.approx(-K[3] / pb.inertia, rel=5e-3)
+
+
+# ------------------------------------------- steady channel: flux and Poiseuille law (Sec. 2.2)
+
+def test_steady_channel_flux_and_poiseuille_law(orc):
+    """A body-free channel with a VELOCITY inlet, a PRESSURE outlet and WALLs reaches a
+    steady state whose developed part is the plane Poiseuille flow of the scheme's
+    viscosity: the flux sum_y u_x is the same in every developed cross-section, the
+    pressure is uniform across it, and u_x = (G / 2 nu) y (H - y) with G the measured
+    pressure slope (the discrete profile is an exact fixed point, so this holds to
+    convergence). Pins the three boundary kinds together with nu = 1/6 - 2A/9."""
+    U, nu = 0.05, 0.2
+    pb = W.Problem(dim=2, n=(60, 12, 1), bc=(W.VELOCITY, W.PRESSURE, W.WALL, W.WALL, 0, 0),
+                   bc_u=((U, 0, 0),) + ((0, 0, 0),) * 5, nu=nu, u0=(U, 0, 0), n_steps=6000)
+    s, _, _ = orc.forward(pb, None, W.initial_state(pb), np.zeros(12))
+    N, nx, ny = pb.N, pb.n[0], pb.n[1]
+    s2, _, _ = orc.forward(pb.replace(n_steps=50), None, s, np.zeros(12))
+    assert np.abs(s2 - s).max() < 1e-14  # steady
+    p = s[:N].reshape(ny, nx)
+    ux = s[N:2 * N].reshape(ny, nx)
+    uy = s[2 * N:].reshape(ny, nx)
+    Q = ux.sum(axis=0)
+    dev = slice(40, nx - 2)
+    assert np.abs(Q[dev] - Q[dev].mean()).max() <= 1e-8 * Q[dev].mean()
+    H = ny - 1
+    y = np.arange(ny)
+    for x in range(45, nx - 2):
+        G = -(p[1:-1, x + 1] - p[1:-1, x - 1]).mean() / 2
+        assert np.abs(p[:, x] - p[:, x].mean()).max() <= 1e-9 * G
+        assert np.abs(ux[:, x] - G / (2 * nu) * y * (H - y)).max() <= 1e-7 * ux[:, x].max()
+        assert np.abs(uy[:, x]).max() <= 1e-9 * ux[:, x].max()
+    # the inlet's flux sum_y u_x = (ny - 2) U is not the scheme's conserved flux (the
+    # macroscopic u differs from the mass flux by the viscous term near the inlet)
+    assert Q[0] == pytest.approx((ny - 2) * U, rel=1e-15)
+
+
+# --------------------------------------- dot-product tests of the reverse sweep (adjointness)
+
+def _rand_state(pb, seed, amp=0.01):
+    rng = np.random.default_rng(seed)
+    return W.initial_state(pb) + amp * rng.standard_normal(pb.N * (pb.dim + 1))
+
+
+DOT_CASES = {
+    "2d-vel-pres-walls": lambda: W.Problem(dim=2, n=(13, 9, 1),
+                                           bc=(W.VELOCITY, W.PRESSURE, W.WALL, W.WALL, 0, 0),
+                                           bc_u=((0.05, 0.01, 0),) + ((0, 0, 0),) * 5,
+                                           bc_p=(0, 0.002, 0, 0, 0, 0), nu=0.12, u0=(0.05, 0, 0)),
+    "2d-pres-pres-periodic": lambda: W.Problem(dim=2, n=(11, 8, 1),
+                                               bc=(W.PRESSURE, W.PRESSURE, 0, 0, 0, 0),
+                                               bc_p=(0.01, 0.0, 0, 0, 0, 0), nu=0.15),
+    "3d-duct": lambda: W.duct3d(9, 7, 6, 0.04, 0.05),
+    "3d-mixed": lambda: W.Problem(dim=3, n=(8, 7, 6),
+                                  bc=(W.WALL, W.VELOCITY, W.PRESSURE, W.WALL, 0, 0),
+                                  bc_u=((0, 0, 0), (0.02, -0.03, 0.01)) + ((0, 0, 0),) * 4,
+                                  bc_p=(0, 0, 0.003, 0, 0, 0), nu=0.07),
+}
+
+
+@pytest.mark.parametrize("case", sorted(DOT_CASES))
+def test_one_step_adjoint_dot_product_body_free(orc, case):
+    """One LKS step with its boundary values is a quadratic polynomial in the state
+    (the equilibrium of Sec. 2.2 is quadratic in u, the gradients linear), so its central
+    difference is exact up to rounding: <w, (F(s + h v) - F(s - h v)) / 2h> must equal
+    <F'(s)^T w, v>, the reverse sweep's initial-state cotangent for the terminal
+    cotangent w, to 1e-11. A transposed stencil, boundary copy or one-sided gradient
+    fails it."""
+    pb = DOT_CASES[case]().replace(n_steps=1, nd=(0, 0, 0))
+    s0 = _rand_state(pb, 5)
+    rng = np.random.default_rng(6)
+    v = rng.standard_normal(s0.size)
+    w = rng.standard_normal(s0.size)
+    h = 1e-3
+    fp = orc.forward(pb, None, s0 + h * v, np.zeros(12))[0]
+    fm = orc.forward(pb, None, s0 - h * v, np.zeros(12))[0]
+    lhs = w @ ((fp - fm) / (2 * h))
+    _, _, ds, _ = orc.gradient(pb, np.zeros(1), s0, np.zeros(12), seed=0.0, with_initial=True,
+                               dstate_T=w)
+    rhs = ds @ v
+    assert lhs == pytest.approx(rhs, rel=1e-11, abs=1e-13 * np.abs(ds).sum())
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_one_step_adjoint_dot_product_held_body(orc, dim):
+    """With every degree of freedom held, the pose is fixed and a step (LKS, then the
+    Brinkman correction with the mapped kappa, u^S of Eqs. kappa_mapping, us_mapping, u)
+    stays quadratic in the state: the same exact dot-product test covers the Brinkman
+    transpose and the spread over the body's footprint, with a body moving at a given
+    velocity (u^S != 0)."""
+    pb = (W.small2d() if dim == 2 else W.small3d()).replace(n_steps=1, dof_mask=0, n_itr=2)
+    g = W.design(pb)
+    s0 = _rand_state(pb, 7)
+    b0 = W.initial_body(pb)
+    b0[3:6] = (0.01, -0.02, 0.015)[:3]
+    b0[7] = 0.003
+    rng = np.random.default_rng(8)
+    v = rng.standard_normal(s0.size)
+    w = rng.standard_normal(s0.size)
+    h = 1e-3
+    fp = orc.forward(pb, g, s0 + h * v, b0)[0]
+    fm = orc.forward(pb, g, s0 - h * v, b0)[0]
+    lhs = w @ ((fp - fm) / (2 * h))
+    _, _, ds, _ = orc.gradient(pb, g, s0, b0, seed=0.0, with_initial=True, dstate_T=w)
+    assert lhs == pytest.approx(ds @ v, rel=1e-11, abs=1e-13 * np.abs(ds).sum())
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_one_step_adjoint_dot_product_free_body(orc, dim):
+    """A free body makes the step nonlinear in the state and the body (the pose enters the
+    cosine weights): the reverse sweep's cotangents of the initial state and body, for
+    random terminal cotangents of both, match a joint central difference (h = 1e-6) along
+    random directions, to the truncation error."""
+    pb = (W.small2d() if dim == 2 else W.small3d()).replace(n_steps=1, inertia=200.0)
+    g = W.design(pb)
+    s0 = _rand_state(pb, 9)
+    b0 = W.initial_body(pb)
+    rng = np.random.default_rng(10)
+    v, w = rng.standard_normal(s0.size), rng.standard_normal(s0.size)
+    vb, wb = np.zeros(12), np.zeros(12)
+    vb[:8] = rng.standard_normal(8)
+    wb[:8] = rng.standard_normal(8)
+    if dim == 2:  # z components do not exist in 2D
+        vb[[2, 5]] = 0.0
+        wb[[2, 5]] = 0.0
+    h = 1e-6
+
+    def L(s, b):
+        st, bd, _ = orc.forward(pb, g, s, b)
+        return w @ st + wb[:8] @ bd[:8]
+
+    fd = (L(s0 + h * v, b0 + h * vb) - L(s0 - h * v, b0 - h * vb)) / (2 * h)
+    _, _, ds, db = orc.gradient(pb, g, s0, b0, seed=0.0, with_initial=True, dstate_T=w, dbody_T=wb)
+    assert ds @ v + db[:8] @ vb[:8] == pytest.approx(fd, rel=1e-7)
