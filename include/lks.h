@@ -41,15 +41,25 @@ enum { LKS_FP32 = 0, LKS_FP64 = 1 };
 enum { LKS_OBJ_DISP_X = 0, LKS_OBJ_DISP_Y = 1, LKS_OBJ_DISP_Z = 2, LKS_OBJ_ANGLE = 3 };
 /* free degrees of freedom of the body (Eqs. equation_of_motion_*) */
 enum { LKS_DOF_TX = 1, LKS_DOF_TY = 2, LKS_DOF_TZ = 4, LKS_DOF_ROT = 8 };
-enum { LKS_FLAG_ASYNC = 1, LKS_FLAG_PROFILE = 2 };
+/* LKS_FLAG_ASYNC: lks_forward / lks_adjoint return without synchronising the stream (the
+ *   device error flag is then not read). LKS_FLAG_PROFILE: live kernel timing (below).
+ * LKS_FLAG_STABILITY: lks_forward first computes the coupling constants of the fluid <->
+ *   body iteration at t = 0 (lks_coupling) and returns LKS_EUNSTABLE, before any time
+ *   step, when an active degree of freedom has K/M >= 1 or K_theta/I >= 1 (the
+ *   iteration of Sec. 3.1 then does not contract). */
+enum { LKS_FLAG_ASYNC = 1, LKS_FLAG_PROFILE = 2, LKS_FLAG_STABILITY = 4 };
 
 enum {
     LKS_OK = 0,
     LKS_EINVAL = -1,    /* bad argument: dims, null pointer, n_itr < 1, ... */
     LKS_ENOSPACE = -2,  /* `work` or `ckpt` smaller than the size query returned */
-    LKS_EUNSTABLE = -3, /* reserved */
-    LKS_EDIVERGED = -4, /* non-finite body state, or the body moved more than the
-                           footprint margin (2 nodes) within one step */
+    LKS_EUNSTABLE = -3, /* LKS_FLAG_STABILITY pre-check: the fluid <-> body iteration
+                           does not contract (K/M >= 1 or K_theta/I >= 1) */
+    LKS_EDIVERGED = -4, /* non-finite body state; a fluid state with a non-finite value
+                           or a speed beyond the lattice sound speed 1/sqrt(3) (checked
+                           at every checkpoint, every 256 steps without checkpoints, and
+                           at the end); or the body moved more than the footprint margin
+                           (2 nodes) within one step */
     LKS_EHIP = -5       /* HIP runtime error (text in lks_last_error) */
 };
 
@@ -98,7 +108,12 @@ size_t lks_workspace_bytes(const lks_problem_t *P, int adjoint);
  *   work    scratch of lks_workspace_bytes(P, 0) bytes
  *   J       [1] double, out: objective (x^G component or theta at n_steps minus its
  *           initial value)
- * Errors: LKS_EINVAL, LKS_ENOSPACE, LKS_EDIVERGED, LKS_EHIP.
+ * The state arrays passed in and out hold u itself; during the run (and in the
+ * checkpoints) the velocity is held as its deviation from the velocity prescribed on
+ * the first VELOCITY face (none: no shift), which keeps FP32 fields precise on the small
+ * deviations that drive the body.
+ * Errors: LKS_EINVAL, LKS_ENOSPACE, LKS_EUNSTABLE (with LKS_FLAG_STABILITY), LKS_EDIVERGED,
+ * LKS_EHIP.
  */
 int lks_forward(const lks_problem_t *P, const void *gamma, void *state, double *body,
                 void *ckpt, size_t ckpt_bytes, void *work, size_t work_bytes, double *J,
@@ -154,6 +169,27 @@ int map_design(const lks_problem_t *P, const void *kappa_ref, const double *body
  */
 int body_step(const lks_problem_t *P, const double *ft, const double *body_prev, double *body,
               void *stream);
+
+/*
+ * lks_coupling -- coupling constants of the fluid <-> body iteration of Sec. 3.1 at the
+ * pose `body`: within a time step the iterates satisfy u^G,(k+1) = u^G(t-1) +
+ * F(u^G,(k))/M with F affine in the body velocity at a frozen pose and u*, so the
+ * iteration contracts when K/M < 1 (and K_theta/I < 1), where
+ *   K[a] = -dF_a/du^G_a = sum_m kappa_ref_m - sum_x kappa^2 phi / (1 + kappa)   (a < dim)
+ *   K[3] = -dT/domega   = sum_m kappa_ref_m |a x r_m|^2 - sum_x kappa/(1 + kappa) S . S_k
+ * with the mapped kappa (Eq. kappa_mapping), phi = sum_m W, S = sum_m W (a x r_m),
+ * S_k = sum_m W kappa_ref_m (a x r_m), r_m = x^ref_m - x^G (Eq. rigid_body_position),
+ * sums over interior nodes and design points, FP64. Independent of the fluid state.
+ *   gamma  [ND] T (read only)
+ *   body   [12] double (read only): the pose (x^G, theta)
+ *   K      [4] double, out (device); K[a] = 0 for a >= dim
+ *   work   scratch of lks_workspace_bytes(P, 0) bytes
+ * Synchronises the stream once at the start (to size the footprint box from theta), then
+ * enqueues its kernels without synchronising.
+ * Errors: LKS_EINVAL (no design grid, null pointer, non-finite body), LKS_ENOSPACE, LKS_EHIP.
+ */
+int lks_coupling(const lks_problem_t *P, const void *gamma, const double *body, double *K, void *work,
+                 size_t work_bytes, void *stream);
 
 /* Density filter and Heaviside projection of the design field (Sec. 3.2). */
 typedef struct lks_filter {

@@ -14,6 +14,7 @@ PERIODIC, VELOCITY, PRESSURE, WALL = 0, 1, 2, 3
 FP32, FP64 = 0, 1
 FLAG_ASYNC = 1
 FLAG_PROFILE = 2
+FLAG_STABILITY = 4
 KERNELS = ("gather", "bc", "spread", "interp", "adj_gather", "adj_recompute", "adj_r1", "adj_r2",
            "adj_r3", "iter", "iter_final", "gather_span", "adj_gather_span", "filter", "filter_adj",
            "cyc_expand", "cyc_collect")
@@ -24,7 +25,8 @@ EXPORTS = ("lks_state_elems", "lks_checkpoint_bytes", "lks_workspace_bytes", "lk
            "lks_adjoint", "map_design", "body_step", "lks_last_error", "lks_profile_read",
            "lks_profile_reset", "lks_design_filter", "lks_design_filter_adjoint",
            "lks_filter_workspace_bytes", "lks_cyclic_sector_points", "lks_design_cyclic_expand",
-           "lks_design_cyclic_collect", "lks_mma_workspace_bytes", "lks_mma_update", "lks_volume_constraint")
+           "lks_design_cyclic_collect", "lks_mma_workspace_bytes", "lks_mma_update", "lks_volume_constraint",
+           "lks_coupling")
 
 
 class LksProblem(C.Structure):
@@ -92,6 +94,8 @@ def load():
     L.map_design.argtypes = [pp, vp, dp, vp, vp, vp]
     L.map_design.restype = C.c_int
     L.body_step.argtypes = [pp, dp, dp, dp, vp]
+    L.lks_coupling.argtypes = [pp, vp, dp, dp, vp, C.c_size_t, vp]
+    L.lks_coupling.restype = C.c_int
     L.body_step.restype = C.c_int
     fp = C.POINTER(LksFilter)
     L.lks_design_filter.argtypes = [pp, fp, vp, vp, vp, vp]

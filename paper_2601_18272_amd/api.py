@@ -131,6 +131,23 @@ def adjoint(pb, gamma, buffers: Buffers, seed: float = 1.0, precision="fp32",
     return (grad, ds, db) if want_initial else grad
 
 
+def coupling(pb, gamma, body, precision="fp32"):
+    """Coupling constants K[0..2] = -dF/du^G and K[3] = -dT/domega of the fluid <-> body
+    iteration at the pose `body` (float64 tensor of 4)."""
+    L = _lib.load()
+    dt = DTYPES[precision]
+    s = problem_struct(pb, precision)
+    nbytes = int(L.lks_workspace_bytes(C.byref(s), 0))
+    if nbytes == 0:
+        raise LksError(_lib.EINVAL, L.lks_last_error().decode())
+    work = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    g = _dev(gamma, dt)
+    bd = _dev(body, torch.float64)
+    K = torch.empty(4, dtype=torch.float64, device="cuda")
+    _lib.check(L.lks_coupling(C.byref(s), _p(g), _p(bd), _p(K), _p(work), work.numel(), _stream()))
+    return K
+
+
 def map_design(pb, kappa_ref, body, precision="fp32"):
     """Mapped Brinkman coefficient and body velocity on the analysis grid."""
     L = _lib.load()

@@ -639,7 +639,7 @@ __global__ __launch_bounds__(256) void k_spread_fwd_rows(Grid g, Design D, const
             } else {
                 s = ustar[a * bN + l];
             }
-            u[a * N + id] = (s + kap * us[a]) * inv;
+            u[a * N + id] = (s + kap * (us[a] - gU<T>(g, a))) * inv;
         }
     }
 }
@@ -676,7 +676,7 @@ __global__ __launch_bounds__(256) void k_spread_fwd(Grid g, Design D, const doub
         } else {
             s = ustar[a * D.boxN + l];
         }
-        u[a * N + id] = (s + kap * us[a]) * inv;
+        u[a * N + id] = (s + kap * (us[a] - gU<T>(g, a))) * inv;
     }
 }
 
@@ -963,7 +963,7 @@ __global__ __launch_bounds__(Dblk<DIM>::v) void k_interp_force(Grid g, Design D,
         pose_point(D, B, xi, P);
         Taps<DIM, T> tp;
         tp.init(g, P.X, false);
-        T ur[3] = {0, 0, 0};
+        T ur[3] = {0, 0, 0}, sw = 0;
         constexpr int TZ = DIM == 3 ? 4 : 1;
 #pragma unroll 1
         for (int c = 0; c < TZ; c++) {
@@ -977,6 +977,7 @@ __global__ __launch_bounds__(Dblk<DIM>::v) void k_interp_force(Grid g, Design D,
                 for (int a = 0; a < 4; a++) {
                     const T W = tp.w[0][a] * wyz;
                     const long long id = row + tp.c[0][a];
+                    sw += W;
 #pragma unroll
                     for (int e = 0; e < DIM; e++) ur[e] += W * u[e * N + id];
                 }
@@ -984,9 +985,10 @@ __global__ __launch_bounds__(Dblk<DIM>::v) void k_interp_force(Grid g, Design D,
         }
         const double kr = krD[m];
         double Dv[3] = {0.0, 0.0, 0.0};
+        // u^ref = sum W v + U sum W (the state holds v = u - U)
 #pragma unroll
         for (int e = 0; e < DIM; e++) {
-            Dv[e] = (double)ur[e] - P.US[e];
+            Dv[e] = ((double)ur[e] + g.U[e] * (double)sw) - P.US[e];
             v[e] = kr * Dv[e];
         }
         v[3] = kr * (pick3(P.r, D.pi) * pick3(Dv, D.pj) - pick3(P.r, D.pj) * pick3(Dv, D.pi));
@@ -1204,8 +1206,8 @@ __global__ __launch_bounds__(It2<TT>::NT) void k_iter2d(Grid g, Design D, BodyPa
                     },
                     x, q, kap, us);
                 const T inv = T(1) / (T(1) + kap);
-                v0 = (v0 + kap * us[0]) * inv;
-                v1 = (v1 + kap * us[1]) * inv;
+                v0 = (v0 + kap * (us[0] - gU<T>(g, 0))) * inv;
+                v1 = (v1 + kap * (us[1] - gU<T>(g, 1))) * inv;
             }
         }
         if (q == 0 && px < sx && py < sy) {
@@ -1226,7 +1228,7 @@ __global__ __launch_bounds__(It2<TT>::NT) void k_iter2d(Grid g, Design D, BodyPa
     // interpolation at the tile's points, force and torque terms
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     if (own) {
-        T ur[2] = {0, 0};
+        T ur[2] = {0, 0}, sw = 0;
 #pragma unroll
         for (int b = 0; b < 4; b++) {
             const T wyz = tp.w[1][b] * tp.w[2][0];
@@ -1235,11 +1237,14 @@ __global__ __launch_bounds__(It2<TT>::NT) void k_iter2d(Grid g, Design D, BodyPa
             for (int a = 0; a < 4; a++) {
                 const T W = tp.w[0][a] * wyz;
                 const int xx = min(max(tp.c[0][a] - ox, 0), PE - 1);
+                sw += W;
                 ur[0] += W * up[0][yy][xx];
                 ur[1] += W * up[1][yy][xx];
             }
         }
-        double Dv[3] = {(double)ur[0] - P.US[0], (double)ur[1] - P.US[1], 0.0};
+        // u^ref = sum W v + U sum W (the patch holds v = u - U)
+        double Dv[3] = {((double)ur[0] + g.U[0] * (double)sw) - P.US[0],
+                        ((double)ur[1] + g.U[1] * (double)sw) - P.US[1], 0.0};
         v[0] = kr * Dv[0];
         v[1] = kr * Dv[1];
         v[3] = kr * (pick3(P.r, D.pi) * pick3(Dv, D.pj) - pick3(P.r, D.pj) * pick3(Dv, D.pi));
@@ -1321,7 +1326,7 @@ __global__ __launch_bounds__(256) void k_iter_final2d(Grid g, Design D, BodyPara
     for (int a = 0; a < 2; a++) {
         const T s = u[a * N + id];
         ustar[a * D.boxN + l] = s;
-        u[a * N + id] = (s + kap * us[a]) * inv;
+        u[a * N + id] = (s + kap * (us[a] - gU<T>(g, a))) * inv;
     }
 }
 
@@ -1400,7 +1405,7 @@ __global__ __launch_bounds__(256) void k_adj_recompute(Grid g, Design D, const d
 #pragma unroll
     for (int a = 0; a < DIM; a++) {
         usk[(k * DIM + a) * bN + l] = us[a];
-        uk[(k * DIM + a) * bN + l] = ok ? (ustar[a * bN + l] + kap * us[a]) * inv : T(0);
+        uk[(k * DIM + a) * bN + l] = ok ? (ustar[a * bN + l] + kap * (us[a] - gU<T>(g, a))) * inv : T(0);
     }
 }
 
@@ -1435,7 +1440,7 @@ __global__ __launch_bounds__(256) void k_adj_recompute_rows(Grid g, Design D, co
 #pragma unroll
         for (int a = 0; a < 3; a++) {
             usk[(k * 3 + a) * bN + l] = us[a];
-            uk[(k * 3 + a) * bN + l] = ok ? (ustar[a * bN + l] + kap * us[a]) * inv : T(0);
+            uk[(k * 3 + a) * bN + l] = ok ? (ustar[a * bN + l] + kap * (us[a] - gU<T>(g, a))) * inv : T(0);
         }
     }
 }
@@ -1521,7 +1526,8 @@ __global__ __launch_bounds__(R1blk<DIM>::v) void k_adj_r1(Grid g, Design D, Body
                                                  const T *__restrict__ uk, const double *__restrict__ krD,
                                                  const double *__restrict__ rin, double *__restrict__ rout,
                                                  const double *__restrict__ pp, unsigned pnb, int kfin, T *__restrict__ URb,
-                                                 double *__restrict__ krb, double *__restrict__ part) {
+                                                 double *__restrict__ krb, double *__restrict__ part,
+                                                 int *__restrict__ flag) {
     __shared__ double rs[AR_SIZE];
     // The record step runs first in 3D (keeps the registers of the long tap loops
     // free) and after the interpolation in 2D (overlaps its loads).
@@ -1543,7 +1549,8 @@ __global__ __launch_bounds__(R1blk<DIM>::v) void k_adj_r1(Grid g, Design D, Body
     long long m;
     bool own;
     if constexpr (TL) {
-        tile3_setup(g, D, B, t);
+        // a patch beyond its bound would clamp taps onto its edge: report it (flag 4)
+        if (!tile3_setup(g, D, B, t) && threadIdx.x == 0) atomicOr(flag, 4);
         tile3_stage<3>(t, pt, [&](const int x[3], T *vv) {
             const int bx = x[0] - o[0], by = x[1] - o[1], bz = x[2] - o[2];
             if (bx >= 0 && bx < D.L[0] && by >= 0 && by < D.L[1] && bz >= 0 && bz < D.L[2]) {
@@ -1562,7 +1569,7 @@ __global__ __launch_bounds__(R1blk<DIM>::v) void k_adj_r1(Grid g, Design D, Body
     Pose P;
     Taps<DIM, T> tp;
     constexpr int TZ = DIM == 3 ? 4 : 1;
-    T ur[3] = {0, 0, 0};
+    T ur[3] = {0, 0, 0}, sw = 0;
     // offsets of the taps: in the staged patch (TL) or in the box arrays
     int ox[4], oy[4], oz[4];
     const T *src[3];
@@ -1601,6 +1608,7 @@ __global__ __launch_bounds__(R1blk<DIM>::v) void k_adj_r1(Grid g, Design D, Body
                 for (int a = 0; a < 4; a++) {
                     const T W = tp.w[0][a] * tp.w[1][b] * wz;
                     const int l = ox[a] + oy[b] + cz;
+                    sw += W;
 #pragma unroll
                     for (int e = 0; e < DIM; e++) ur[e] += W * src[e][l];
                 }
@@ -1616,7 +1624,7 @@ __global__ __launch_bounds__(R1blk<DIM>::v) void k_adj_r1(Grid g, Design D, Body
     if (own) {
         double Dv[3] = {0, 0, 0}, Db[3] = {0, 0, 0};
 #pragma unroll
-        for (int e = 0; e < DIM; e++) Dv[e] = (double)ur[e] - P.US[e];
+        for (int e = 0; e < DIM; e++) Dv[e] = ((double)ur[e] + g.U[e] * (double)sw) - P.US[e];
         double gsum = 0.0;
 #pragma unroll
         for (int e = 0; e < DIM; e++) {
@@ -1635,9 +1643,12 @@ __global__ __launch_bounds__(R1blk<DIM>::v) void k_adj_r1(Grid g, Design D, Body
             USb[e] = -Db[e];
             URb[e * D.ND + m] = T(Db[e]);
         }
-        // x^ref cotangent from the interpolation: sum_x dW/dX (Db . u(x))
+        // x^ref cotangent from the interpolation: sum_x dW/dX (Db . u(x)), u = U + v
         T xb[3] = {0, 0, 0};
         const T db[3] = {T(Db[0]), T(Db[1]), T(Db[2])};
+        T dbU = 0;
+#pragma unroll
+        for (int e = 0; e < DIM; e++) dbU += db[e] * gU<T>(g, e);
 #pragma unroll 1
         for (int c = 0; c < TZ; c++) {
             const T wz = sel4(tp.w[2], c), dwz = sel4(tp.dw[2], c);
@@ -1646,7 +1657,7 @@ __global__ __launch_bounds__(R1blk<DIM>::v) void k_adj_r1(Grid g, Design D, Body
             for (int b = 0; b < 4; b++) {
 #pragma unroll
                 for (int a = 0; a < 4; a++) {
-                    T dot = 0;
+                    T dot = dbU;
                     const int l = ox[a] + oy[b] + cz;
 #pragma unroll
                     for (int e = 0; e < DIM; e++) dot += db[e] * src[e][l];
@@ -1694,7 +1705,7 @@ __global__ __launch_bounds__(256) void k_adj_r2(Grid g, Bc bc, Design D, const d
 #pragma unroll
         for (int a = 0; a < DIM; a++) {
             ust[a] = k == K - 1 ? T(0) : ustb[a * bN + l];
-            dus[a] = usk[(k * DIM + a) * bN + l] - uk[(k * DIM + a) * bN + l];
+            dus[a] = (usk[(k * DIM + a) * bN + l] - gU<T>(g, a)) - uk[(k * DIM + a) * bN + l];
         }
     }
     T ub[3] = {0, 0, 0};
@@ -1851,7 +1862,7 @@ __global__ __launch_bounds__(256) void k_adj_r2_rows(Grid g, Bc bc, Design D, co
 #pragma unroll
         for (int a = 0; a < 3; a++) {
             ust[a] = k == K - 1 ? T(0) : ustb[a * bN + l];
-            dus[a] = usk[(k * 3 + a) * bN + l] - uk[(k * 3 + a) * bN + l];
+            dus[a] = (usk[(k * 3 + a) * bN + l] - gU<T>(g, a)) - uk[(k * 3 + a) * bN + l];
         }
         T ub[3] = {0, 0, 0};
         const int ib = x[D.axis] + ax.fl;
@@ -1928,6 +1939,71 @@ __global__ __launch_bounds__(256) void k_grad_final(long long ND, double kmax, d
     if (m == 0 && dbody0) {
         for (int j = 0; j < 12; j++) dbody0[j] = j < 8 ? rec[AR_BBAR + j] : 0.0;
         dbody0[obj == 3 ? B_TH : obj] -= seed;
+    }
+}
+
+// ------------------------------------------------------------------ coupling constants
+// The fluid <-> body iteration of Sec. 3.1 (u^G,(k+1) = u^G(t-1) + F(u^G,(k))/M at a
+// frozen pose and u*) contracts when K/M < 1, K = -dF/du^G (and K_theta/I < 1,
+// K_theta = -dT/domega). F and T are affine in u^G and omega, and the spread, the
+// Brinkman factor and the interpolation give, with phi = sum_m W, kappa = sum_m W kappa_m,
+// s_m = a x (x^ref_m - x^G), S = sum_m W s_m, S_k = sum_m W kappa_m s_m over interior nodes:
+//   K       = sum_m kappa_m - sum_x kappa^2 phi / (1 + kappa)           (every axis)
+//   K_theta = sum_m kappa_m |s_m|^2 - sum_x kappa / (1 + kappa) S . S_k
+// Threads [0, boxN) take the footprint box nodes (gather form, FP64), threads [boxN,
+// boxN + ND) the design points; grid-stride, fixed order, one partial per block.
+template <int DIM, bool ROT>
+__global__ __launch_bounds__(256) void k_coupling(Grid g, Design D, const double *__restrict__ B,
+                                                  const double *__restrict__ krD, double *__restrict__ part) {
+    double v[4] = {0.0, 0.0, 0.0, 0.0};  // node sums (K, K_theta), design sums (K, K_theta)
+    int o[3];
+    box_origin<DIM>(D, B, o);
+    const long long total = D.boxN + D.ND;
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (long long)gridDim.x * blockDim.x) {
+        if (t < D.boxN) {
+            int x[3];
+            if (!box_node<DIM>(g, D, o, t, x)) continue;
+            double d[3];
+            double kap = 0.0, phi = 0.0, S[3] = {0, 0, 0}, Sk[3] = {0, 0, 0};
+            gather_design<DIM, double, ROT, 1>(D, B, x, d, 0, [&](long long m, double W, const double r[3], const int *) {
+                const double km = krD[m];
+                // s_m = a x (x^ref - x^G), x^ref - x^G = d - r (r = x - x^ref)
+                const double rp = pick3(d, D.pi) - r[D.pi], rq = pick3(d, D.pj) - r[D.pj];
+                kap += W * km;
+                phi += W;
+                S[D.pi] += W * -rq;
+                S[D.pj] += W * rp;
+                Sk[D.pi] += W * km * -rq;
+                Sk[D.pj] += W * km * rp;
+            });
+            const double f = kap / (1.0 + kap);
+            v[0] += f * kap * phi;
+            v[1] += f * (S[0] * Sk[0] + S[1] * Sk[1] + S[2] * Sk[2]);
+        } else {
+            const long long m = t - D.boxN;
+            double xi[3];
+            design_xi<DIM>(D, m, xi);
+            Pose P;
+            pose_point(D, B, xi, P);
+            const double km = krD[m], rp = pick3(P.r, D.pi), rq = pick3(P.r, D.pj);
+            v[2] += km;
+            v[3] += km * (rp * rp + rq * rq);
+        }
+    }
+    block_reduce_store<4, 256>(v, part);
+}
+
+// One block: K[0..2] (zero beyond dim), K[3] from the nb partials (fixed order).
+template <int DIM>
+__global__ __launch_bounds__(1024) void k_coupling_finish(const double *__restrict__ part, unsigned nb,
+                                                          double *__restrict__ K) {
+    __shared__ double s[4];
+    reduce_partials<4, 1024>(part, nullptr, nb, s);
+    if (threadIdx.x == 0) {
+        const double kt = s[2] - s[0];
+        for (int a = 0; a < 3; a++) K[a] = a < DIM ? kt : 0.0;
+        K[3] = s[3] - s[1];
     }
 }
 

@@ -7,12 +7,20 @@
 // printed +3/2). Gradients: central differences, second-order one-sided along the
 // normal on boundary nodes of non-periodic faces.
 //
+// The state holds v = u - U (Grid::U). The equilibrium of the uniform flow,
+// f_i^U = w_i (3 c.U + 9/2 (c.U)^2 - 3/2 U.U), satisfies sum_i f_i^U = 0 and
+// sum_i c_i f_i^U = U, so with df_i = f_i - f_i^U,
+//   df_i = w_i (3p + 3 c.v + 9 (c.U)(c.v) + 9/2 (c.v)^2 - 3 U.v - 3/2 v.v) + w_i A (...),
+//   p* = 1/3 sum_i df_i(x - c_i),   v* = sum_i c_i df_i(x - c_i),
+// the same update with every term small (the gradients of u and v are equal).
+//
 // Adjoint: the exact transpose. With g_i(x) = p*bar(x)/3 + c_i . u*bar(x) on interior
 // nodes, the moments pi = sum_i w_i g_i(y + c_i), ups_a = sum_i w_i c_ia g_i(y + c_i),
 // sig_ab = sum_i w_i c_ia c_ib g_i(y + c_i) (the ALKS moments p~, u~, s~ of Eqs.
 // ap_tmp..as_tmp) give
 //   pbar(y) = 3 pi,  ubar_b(y) = 3 ups_b + 9 sig_ba u_a - 3 pi u_b + 2A sum_a D_a^T sig_ab,
-// with D_a^T the transpose of the boundary-aware difference operator.
+// with D_a^T the transpose of the boundary-aware difference operator and u = U + v the
+// forward velocity. The cotangents of u and of v = u - U are the same.
 #pragma once
 #include <type_traits>
 
@@ -88,33 +96,35 @@ __global__ __launch_bounds__(512) void k_gather2d(Grid g, T A, const T *__restri
                 dyuy = T(0.5) * (T(3) * suy[ly][lx] - T(4) * suy[ly - 1][lx] + suy[ly - 2][lx]);
             }
             const T p = sp[ly][lx], ux = sux[ly][lx], uy = suy[ly][lx];
-            // f_i = w_i (3p - 3/2 u.u + 3 c.u + 9/2 (c.u)^2 + A c.(S + S^T).c), formed for the
-            // pairs +-c at once: the even part w (base + 9/2 (c.u)^2 + A c.(S + S^T).c) is
-            // shared, the odd part 3 w c.u changes sign; no term with a zero component of c
-            const T base = T(3) * p - T(1.5) * (ux * ux + uy * uy);
+            // df_i = w_i (3p - 3 U.v - 3/2 v.v + 3 c.v + 9 (c.U)(c.v) + 9/2 (c.v)^2
+            // + A c.(S + S^T).c) (ux, uy hold v), formed for the pairs +-c at once: the even
+            // part w (base + (9 c.U + 9/2 c.v)(c.v) + A c.(S + S^T).c) is shared, the odd
+            // part 3 w c.v changes sign; no term with a zero component of c
+            const T Ux = gU<T>(g, 0), Uy = gU<T>(g, 1);
+            const T base = T(3) * p - T(1.5) * (ux * ux + uy * uy) - T(3) * (Ux * ux + Uy * uy);
             const T A2 = T(2) * A;
             const T axx = A2 * dxux, ayy = A2 * dyuy, axy = A2 * (dxuy + dyux);
             f[0] = w0 * base;
             {
-                const T ev = w1 * (base + T(4.5) * ux * ux + axx), od = T(3) * w1 * ux;
+                const T ev = w1 * (base + (T(9) * Ux + T(4.5) * ux) * ux + axx), od = T(3) * w1 * ux;
                 f[1] = ev + od;
                 f[2] = ev - od;
             }
             {
-                const T ev = w1 * (base + T(4.5) * uy * uy + ayy), od = T(3) * w1 * uy;
+                const T ev = w1 * (base + (T(9) * Uy + T(4.5) * uy) * uy + ayy), od = T(3) * w1 * uy;
                 f[3] = ev + od;
                 f[4] = ev - od;
             }
             const T bd = base + axx + ayy;
             {
-                const T cu = ux + uy;
-                const T ev = w2 * (bd + T(4.5) * cu * cu + axy), od = T(3) * w2 * cu;
+                const T cu = ux + uy, cU = Ux + Uy;
+                const T ev = w2 * (bd + (T(9) * cU + T(4.5) * cu) * cu + axy), od = T(3) * w2 * cu;
                 f[5] = ev + od;
                 f[6] = ev - od;
             }
             {
-                const T cu = ux - uy;
-                const T ev = w2 * (bd + T(4.5) * cu * cu - axy), od = T(3) * w2 * cu;
+                const T cu = ux - uy, cU = Ux - Uy;
+                const T ev = w2 * (bd + (T(9) * cU + T(4.5) * cu) * cu - axy), od = T(3) * w2 * cu;
                 f[7] = ev + od;
                 f[8] = ev - od;
             }
@@ -178,15 +188,36 @@ __device__ __forceinline__ T d2(T m2, T m1, T c, T p1, T p2, int v, int n, int p
 // D[a][b] = 2 d_a u_b. Opposite directions share the quadratic part and differ in the
 // sign of 3 c.u, so each +-c pair costs one evaluation; the weights are folded into
 // the per-class constants.
+// With the deviation form (u holds v, U the reference velocity) the base gains -3 U.v
+// and the quadratic part of pair c gains 9 (c.U)(c.v). Those coefficients are uniform
+// over the grid: formed once on the host (FeqU) and passed as a kernel argument, so
+// they stay in scalar registers.
+template <typename T> struct FeqU {
+    T m3U[3];  // -3 U_a
+    T k1[3];   // 9 w1 U_a          (axis pairs)
+    T k2[4];   // 9 w2 (c_k . U)    (corner pairs, c_k = (1, +-1, +-1))
+    static FeqU make(const double U[3]) {
+        FeqU f;
+        for (int a = 0; a < 3; a++) {
+            f.m3U[a] = T(-3.0 * U[a]);
+            f.k1[a] = T(U[a]);  // 9 w1 = 1
+        }
+        const double cU[4] = {U[0] + U[1] + U[2], U[0] + U[1] - U[2], U[0] - U[1] + U[2], U[0] - U[1] - U[2]};
+        for (int k = 0; k < 4; k++) f.k2[k] = T(9.0 / 72.0 * cU[k]);
+        return f;
+    }
+};
+
 template <typename T>
-__device__ __forceinline__ void feq3(T p, const T u[3], const T D[3][3], T A, T F[15]) {
+__device__ __forceinline__ void feq3(T p, const T u[3], const FeqU<T> &fu, const T D[3][3], T A, T F[15]) {
     constexpr T w0 = T(2.0 / 9.0), w1 = T(1.0 / 9.0), w2 = T(1.0 / 72.0);
-    const T B = T(3) * p - T(1.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    const T B = T(3) * p - T(1.5) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) +
+                (fu.m3U[0] * u[0] + fu.m3U[1] * u[1] + fu.m3U[2] * u[2]);
     F[0] = w0 * B;
     const T B1 = w1 * B, a1 = w1 * A;
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        const T sq = B1 + a1 * D[a][a] + (T(4.5) * w1 * u[a]) * u[a];
+        const T sq = B1 + a1 * D[a][a] + (T(4.5) * w1 * u[a] + fu.k1[a]) * u[a];
         const T li = (T(3) * w1) * u[a];
         F[1 + 2 * a] = sq + li;
         F[2 + 2 * a] = sq - li;
@@ -200,7 +231,7 @@ __device__ __forceinline__ void feq3(T p, const T u[3], const T D[3][3], T A, T 
     constexpr int ip[4] = {7, 8, 9, 10}, im[4] = {14, 13, 12, 11};
 #pragma unroll
     for (int k = 0; k < 4; k++) {
-        const T sq = C + q[k] + (T(4.5) * w2 * cu[k]) * cu[k];
+        const T sq = C + q[k] + (T(4.5) * w2 * cu[k] + fu.k2[k]) * cu[k];
         const T li = (T(3) * w2) * cu[k];
         F[ip[k]] = sq + li;
         F[im[k]] = sq - li;
@@ -208,8 +239,9 @@ __device__ __forceinline__ void feq3(T p, const T u[3], const T D[3][3], T A, T 
 }
 
 template <typename T, bool SP>
-__global__ __launch_bounds__(G3<T>::NT, sizeof(T) == 4 ? 6 : 2) void k_gather3d(Grid g, T A, int ZC, const T *__restrict__ sin_,
-                                                        T *__restrict__ sout, unsigned long long *ts) {
+__global__ __launch_bounds__(G3<T>::NT, sizeof(T) == 4 ? 6 : 2) void k_gather3d(Grid g, T A, FeqU<T> fu, int ZC,
+                                                        const T *__restrict__ sin_, T *__restrict__ sout,
+                                                        unsigned long long *ts) {
     using G = G3<T>;
     constexpr int TX = G::TX, TY = G::TY, WX = G::WX, WY = G::WY;
     __shared__ T wu[2][3][WY][WX];
@@ -297,7 +329,7 @@ __global__ __launch_bounds__(G3<T>::NT, sizeof(T) == 4 ? 6 : 2) void k_gather3d(
                 D[2][c] = d2(q[0][1 + c], q[1][1 + c], q[2][1 + c], q[3][1 + c], q[4][1 + c], zs, nz, g.per[2]);
             }
             const T u[3] = {q[2][1], q[2][2], q[2][3]};
-            feq3(q[2][0], u, D, A, f);
+            feq3(q[2][0], u, fu, D, A, f);
         }
 #pragma unroll
         for (int i = 0; i < 15; i++) fb[i][ty][tx] = f[i];
@@ -388,8 +420,9 @@ __global__ __launch_bounds__(256) void k_bc(Grid g, Bc bc, T *__restrict__ s, in
     const long long id = node_id(g, x[0], x[1], x[2]);
     const long long in = node_id(g, r.in[0], r.in[1], r.in[2]);
     s[id] = r.p_fixed ? T(r.p) : s[in];
+    // a prescribed velocity is stored as its deviation from U
 #pragma unroll
-    for (int a = 0; a < DIM; a++) s[(1 + a) * N + id] = r.u_fixed ? T(r.u[a]) : s[(1 + a) * N + in];
+    for (int a = 0; a < DIM; a++) s[(1 + a) * N + id] = r.u_fixed ? T(r.u[a] - g.U[a]) : s[(1 + a) * N + in];
 }
 
 // ===================================================================== adjoint helpers
@@ -615,7 +648,7 @@ __global__ __launch_bounds__(512) void k_adjgather2d(Grid g, Bc bc, T A, const T
     if (x < nx && y < ny) {
         const int mx = threadIdx.x + 2, my = threadIdx.y + 2;
         const long long id = (long long)x + (long long)nx * y;
-        const T u0 = sprev[N + id], u1 = sprev[2 * N + id];
+        const T u0 = gU<T>(g, 0) + sprev[N + id], u1 = gU<T>(g, 1) + sprev[2 * N + id];
         const T pi = mpi[my][mx];
         T ox = T(3) * mux[my][mx] + T(9) * (mxx[my][mx] * u0 + mxy[my][mx] * u1) - T(3) * pi * u0;
         T oy = T(3) * muy[my][mx] + T(9) * (mxy[my][mx] * u0 + myy[my][mx] * u1) - T(3) * pi * u1;
@@ -828,7 +861,7 @@ __global__ __launch_bounds__(A3<T>::NT, sizeof(T) == 4 ? 4 : 2) void k_adjgather
     auto load_u = [&](int zp) {
         const bool ok = outcol && zp >= z0 && zp < z1;
 #pragma unroll
-        for (int a = 0; a < 3; a++) uc[a] = ok ? sprev[(1 + a) * N + (long long)zp * plane + oid] : T(0);
+        for (int a = 0; a < 3; a++) uc[a] = ok ? gU<T>(g, a) + sprev[(1 + a) * N + (long long)zp * plane + oid] : T(0);
     };
     T part[3][4];  // local + in-plane terms of planes s-2, s-1, s
     T hz[5][3];    // sig_xz, sig_yz, sig_zz of planes s-4 .. s
@@ -965,6 +998,29 @@ __global__ __launch_bounds__(A3<T>::NT, sizeof(T) == 4 ? 4 : 2) void k_adjgather
         }
     }
     if (SP) span_end(ts);
+}
+
+// ===================================================================== divergence check
+// Flag bit 8 when some node of the state holds a non-finite pressure or velocity, or a
+// speed |u| = |U + v| beyond the lattice sound speed 1/sqrt(3), where the scheme no
+// longer represents a flow. Grid-stride; an atomic only from a wave that found one.
+template <typename T>
+__global__ __launch_bounds__(256) void k_check_state(Grid g, int dim, const T *__restrict__ s,
+                                                     int *__restrict__ flag) {
+    const long long N = g.N;
+    bool bad = false;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
+        const T p = s[i];
+        double uu = 0.0;
+        bool fin = isfinite((double)p);
+        for (int a = 0; a < dim; a++) {
+            const double u = g.U[a] + (double)s[(1 + a) * N + i];
+            fin = fin && isfinite(u);
+            uu += u * u;
+        }
+        bad = bad || !fin || !(uu <= 1.0 / 3.0);
+    }
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 8);
 }
 
 }  // namespace lks

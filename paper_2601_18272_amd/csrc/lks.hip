@@ -70,6 +70,18 @@ __global__ void k_span_init(unsigned long long *s, int n) {
     }
 }
 
+// v = u - U on entry (sign -1) and u = v + U on exit (sign +1), velocity components of
+// a state in place.
+template <typename T>
+__global__ __launch_bounds__(256) void k_shift(T *__restrict__ s, long long N, int dim, double U0, double U1,
+                                               double U2, double sign) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double U[3] = {U0, U1, U2};
+    for (int a = 0; a < dim; a++)
+        if (U[a] != 0.0) s[(1 + a) * N + i] = T((double)s[(1 + a) * N + i] + sign * U[a]);
+}
+
 struct Prof {
     bool on = false;
     bool sample = false;
@@ -175,6 +187,7 @@ struct Ctx {
 };
 
 constexpr int MARGIN = 2;
+constexpr unsigned CPL_BLOCKS = 1024;  // blocks of the coupling-constant kernel (at most)
 
 // Footprint box: half-extents H from the largest distance of a design point from the
 // rotation centre (any angle if `rot_any`, else at angle theta0), plus the mapping
@@ -248,6 +261,17 @@ int make_ctx(const lks_problem_t *P, Ctx &c) {
         c.bc.p[f] = P->bc_p[f];
         for (int a = 0; a < 3; a++) c.bc.u[f][a] = P->bc_u[f][a];
     }
+    // reference velocity of the stored deviation v = u - U: the first VELOCITY face's
+    for (int a = 0; a < 3; a++) c.g.U[a] = 0.0;
+    for (int f = 0; f < 2 * c.dim; f++)
+        if (c.bc.kind[f] == LKS_VELOCITY) {
+            for (int a = 0; a < c.dim; a++) {
+                if (!std::isfinite(c.bc.u[f][a])) return fail(LKS_EINVAL, "bc_u not finite");
+                c.g.U[a] = c.bc.u[f][a];
+            }
+            break;
+        }
+    for (int a = 0; a < 3; a++) c.g.Uf[a] = (float)c.g.U[a];
     if (!std::isfinite(P->nu)) return fail(LKS_EINVAL, "nu not finite");
     c.A = 4.5 * (1.0 / 6.0 - P->nu);
     c.S = (long long)(c.dim + 1) * c.g.N;
@@ -317,7 +341,7 @@ int make_ctx(const lks_problem_t *P, Ctx &c) {
 
 // ------------------------------------------------------------------ layout
 struct Layout {
-    size_t krT, krD, st1, ustar, Bf, Binit, part, counter, flag, span;
+    size_t krT, krD, st1, ustar, Bf, Binit, part, counter, flag, span, cpl;
     // adjoint: two segment buffers (recompute of one segment overlaps the reverse sweep
     // of the other), each of seg_n / ustar_seg_n / Bseg_n bytes
     size_t seg, ustar_seg, Bseg, seg_n, ustar_seg_n, Bseg_n;
@@ -366,6 +390,7 @@ Layout layout(const Ctx &c, bool adjoint) {
     L.counter = take(16);
     L.flag = take(16);
     L.span = take(2 * NSPAN * sizeof(unsigned long long));
+    L.cpl = take((CPL_BLOCKS * 4 + 4) * sizeof(double));
     const size_t axN = axial_elems(c);
     L.K1f = take(axN * e);
     if (adjoint) {
@@ -405,6 +430,7 @@ struct CkptHeader {
     int H[3], L[3];
     long long boxN;
     int rot;
+    double U[3];  // reference velocity of the stored states (v = u - U)
 };
 
 size_t ckpt_count(const Ctx &c) { return c.Kc > 0 ? (size_t)((c.NT + c.Kc - 1) / c.Kc) : 0; }
@@ -499,7 +525,7 @@ template <typename T> struct Run {
             // 3D: launch events only (long launches; the stamping variant would spill)
             pf->run_span(LKS_K_GATHER, -1, [&](hipEvent_t e0, hipEvent_t e1, unsigned long long *) {
                 hipExtLaunchKernelGGL((k_gather3d<T, false>), grid, dim3(G3<T>::TX, G3<T>::TY), 0, st, e0, e1, 0,
-                                      c.g, T(c.A), zc, in, out, nullptr);
+                                      c.g, T(c.A), FeqU<T>::make(c.g.U), zc, in, out, nullptr);
             });
         }
     }
@@ -614,6 +640,7 @@ template <typename T> struct Run {
         T *kapk = at<T>(w, L.kapk), *usk = at<T>(w, L.usk), *uk = at<T>(w, L.uk);
         T *ustb = at<T>(w, L.ustb), *kb = at<T>(w, L.kb), *usb = at<T>(w, L.usb), *URb = at<T>(w, L.URb);
         double *krb = at<double>(w, L.krb), *p1 = at<double>(w, L.part1), *p3 = at<double>(w, L.part3);
+        int *flag = at<int>(w, L.flag);
         auto recb = [&](int b) { return at<double>(w, L.rec) + (size_t)b * AR_SIZE; };
         T *AU = at<T>(w, L.AU);
         const size_t bN = (size_t)c.D.boxN;
@@ -641,14 +668,14 @@ template <typename T> struct Run {
                         if (c.tile3) {
                             hipExtLaunchKernelGGL((k_adj_r1<DIM, T, true>), dim3(c.nblk), dim3(c.dblk), 0, st, e0, e1, 0,
                                                   c.g, c.D, c.bp, Bk, k, uk, krD, rin, rout, (const double *)p3,
-                                                  pnb, kfin, URb, krb, p1);
+                                                  pnb, kfin, URb, krb, p1, flag);
                             done = true;
                         }
                     }
                     if (!done)
                         hipExtLaunchKernelGGL((k_adj_r1<DIM, T>), dim3(c.nblk), dim3(R1blk<DIM>::v), 0, st, e0, e1, 0, c.g,
                                               c.D, c.bp, Bk, k, uk, krD, rin, rout, (const double *)p3, pnb, kfin,
-                                              URb, krb, p1);
+                                              URb, krb, p1, flag);
                 });
                 if (fin) {
                     rcur = 1 - rcur;
@@ -742,12 +769,51 @@ template <typename T> struct Run {
     }
 };
 
+// Coupling constants K[4] (device) at pose B (a record with cos/sin) from kappa_ref in
+// FP64; part holds CPL_BLOCKS * 4 doubles.
+void coupling_launch(const Ctx &c, hipStream_t st, const double *B, const double *krD, double *part, double *K) {
+    const unsigned nb = std::min(blocks(c.D.boxN + c.D.ND, 256), CPL_BLOCKS);
+    dispatch(c, [&](auto dm, auto rt) {
+        constexpr int DIM = decltype(dm)::value;
+        constexpr bool ROT = decltype(rt)::value;
+        hipLaunchKernelGGL((k_coupling<DIM, ROT>), dim3(nb), dim3(256), 0, st, c.g, c.D, B, krD, part);
+        hipLaunchKernelGGL((k_coupling_finish<DIM>), dim3(1), dim3(1024), 0, st, (const double *)part, nb, K);
+    });
+}
+
+// Stability pre-check of the fluid <-> body iteration (Sec. 3.1): LKS_EUNSTABLE when an
+// active degree of freedom has K/M >= 1 (translation) or K_theta/I >= 1 (rotation).
+int check_coupling(const Ctx &c, const double *K_d, hipStream_t st) {
+    double K[4];
+    HIP_TRY(hipMemcpyAsync(K, K_d, sizeof K, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const char *ax = "xyz";
+    for (int a = 0; a < c.dim; a++)
+        if ((c.bp.dof & (1 << a)) && !(K[a] / c.bp.mass < 1.0))
+            return fail(LKS_EUNSTABLE,
+                        "fluid <-> body iteration does not contract: K/M = %.4g along %c (K = %.6g, M = %.6g)",
+                        K[a] / c.bp.mass, ax[a], K[a], c.bp.mass);
+    if ((c.bp.dof & LKS_DOF_ROT) && !(K[3] / c.bp.inertia < 1.0))
+        return fail(LKS_EUNSTABLE,
+                    "fluid <-> body iteration does not contract: K_theta/I = %.4g (K_theta = %.6g, I = %.6g)",
+                    K[3] / c.bp.inertia, K[3], c.bp.inertia);
+    return LKS_OK;
+}
+
+// Divergence check of a fluid state (flag bit 8).
+template <typename T> void check_state(const Ctx &c, hipStream_t st, const T *s, int *flag) {
+    const unsigned nb = std::min(blocks(c.g.N, 256), 2048u);
+    hipLaunchKernelGGL(k_check_state<T>, dim3(nb), dim3(256), 0, st, c.g, c.dim, s, flag);
+}
+
 int check_flag(const Ctx &, const int *flag_d, hipStream_t st) {
     int flag = 0;
     HIP_TRY(hipMemcpyAsync(&flag, flag_d, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (flag & 1) return fail(LKS_EDIVERGED, "non-finite body state");
     if (flag & 2) return fail(LKS_EDIVERGED, "body moved more than %d nodes within one step", MARGIN);
+    if (flag & 8)
+        return fail(LKS_EDIVERGED, "fluid state not finite, or faster than the lattice sound speed 1/sqrt(3)");
     if (flag & 4) return fail(LKS_EHIP, "internal: design tile patch exceeds its bound");
     return LKS_OK;
 }
@@ -784,6 +850,13 @@ int forward_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, T *state
     R.kappa_ref(gamma, krT, krD);
     hipLaunchKernelGGL(k_body_init<2>, dim3(1), dim3(64), 0, st, body, Bf);
     HIP_TRY(hipMemcpyAsync(Binit, Bf, B_REC * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if ((P->flags & LKS_FLAG_STABILITY) && c.has_body) {
+        double *cp = at<double>(work, L.cpl);
+        coupling_launch(c, st, Bf, krD, cp, cp + 4 * CPL_BLOCKS);
+        HIP_TRY(hipGetLastError());
+        const int rc = check_coupling(c, cp + 4 * CPL_BLOCKS, st);
+        if (rc != LKS_OK) return rc;
+    }
     if (ckpt) {
         CkptHeader h{};
         memcpy(h.magic, "LKSCKPT", 8);
@@ -801,13 +874,22 @@ int forward_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, T *state
         }
         h.boxN = c.D.boxN;
         h.rot = c.rot ? 1 : 0;
+        for (int a = 0; a < 3; a++) h.U[a] = c.g.U[a];
         HIP_TRY(hipMemcpyAsync(ckpt, &h, sizeof h, hipMemcpyHostToDevice, st));
         HIP_TRY(hipStreamSynchronize(st));
     }
+    const bool shift = c.g.U[0] != 0.0 || c.g.U[1] != 0.0 || c.g.U[2] != 0.0;
+    if (shift)
+        hipLaunchKernelGGL(k_shift<T>, dim3(blocks(c.g.N, 256)), dim3(256), 0, st, state, c.g.N, c.dim, c.g.U[0],
+                           c.g.U[1], c.g.U[2], -1.0);
     T *cur = state, *nxt = st1;
+    // the fluid state is checked for divergence at every checkpoint (every 256 steps
+    // without checkpoints) and at the end; the flag is read once, after the run
+    const int chk = ckpt ? c.Kc : 256;
     for (int t = 1; t <= c.NT; t++) {
         double *Bc = Bf + (size_t)((t - 1) & 1) * rec;
         double *Bn = Bf + (size_t)(t & 1) * rec;
+        if (t > 1 && (t - 1) % chk == 0) check_state(c, st, cur, flag);
         if (ckpt && (t - 1) % c.Kc == 0) {
             const size_t ci = (size_t)((t - 1) / c.Kc);
             HIP_TRY(hipMemcpyAsync(at<char>(ckpt, ckpt_state_off(c, ci)), cur, stateB, hipMemcpyDeviceToDevice, st));
@@ -827,7 +909,11 @@ int forward_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, T *state
         if ((t & 255) == 0) HIP_TRY(hipGetLastError());
     }
     HIP_TRY(hipGetLastError());
+    check_state(c, st, cur, flag);
     if (cur != state) HIP_TRY(hipMemcpyAsync(state, cur, stateB, hipMemcpyDeviceToDevice, st));
+    if (shift)
+        hipLaunchKernelGGL(k_shift<T>, dim3(blocks(c.g.N, 256)), dim3(256), 0, st, state, c.g.N, c.dim, c.g.U[0],
+                           c.g.U[1], c.g.U[2], 1.0);
     const double *Bfinal = Bf + (size_t)(c.NT & 1) * rec;
     hipLaunchKernelGGL(k_objective, dim3(1), dim3(64), 0, st, Binit, Bfinal, P->objective, J, body);
     HIP_TRY(hipGetLastError());
@@ -847,7 +933,8 @@ int adjoint_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, const vo
     HIP_TRY(hipMemcpyAsync(&h, ckpt, sizeof h, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (memcmp(h.magic, "LKSCKPT", 8) != 0 || h.dim != c.dim || h.prec != c.prec || h.K != c.K || h.Kc != c.Kc ||
-        h.NT != c.NT || h.N != c.g.N || h.ND != (c.has_body ? c.D.ND : 0))
+        h.NT != c.NT || h.N != c.g.N || h.ND != (c.has_body ? c.D.ND : 0) || h.U[0] != c.g.U[0] ||
+        h.U[1] != c.g.U[1] || h.U[2] != c.g.U[2])
         return fail(LKS_EINVAL, "checkpoint store does not match the problem (run lks_forward with it first)");
     if (c.has_body && (h.boxN < 1 || h.boxN > c0.D.boxN))  // the workspace holds boxes of c0.D.boxN nodes
         return fail(LKS_EINVAL, "checkpoint store: footprint box larger than the problem's");
@@ -1249,6 +1336,38 @@ int body_step(const lks_problem_t *P, const double *ft, const double *body_prev,
         hipLaunchKernelGGL(k_body_step<2>, dim3(1), dim3(64), 0, st, c.bp, ft, body_prev, body);
     else
         hipLaunchKernelGGL(k_body_step<3>, dim3(1), dim3(64), 0, st, c.bp, ft, body_prev, body);
+    HIP_TRY(hipGetLastError());
+    return LKS_OK;
+}
+
+int lks_coupling(const lks_problem_t *P, const void *gamma, const double *body, double *K, void *work,
+                 size_t work_bytes, void *stream) {
+    g_err.clear();
+    Ctx c;
+    int rc = make_ctx(P, c);
+    if (rc) return rc;
+    if (!c.has_body) return fail(LKS_EINVAL, "the problem has no design grid");
+    if (!gamma || !body || !K || !work) return fail(LKS_EINVAL, "null pointer argument");
+    const Layout L = layout(c, false);
+    if (work_bytes < L.total) return fail(LKS_ENOSPACE, "work buffer too small");
+    hipStream_t st = (hipStream_t)stream;
+    double b0[12];
+    HIP_TRY(hipMemcpyAsync(b0, body, sizeof b0, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int j = 0; j < 8; j++)
+        if (!std::isfinite(b0[j])) return fail(LKS_EINVAL, "body state not finite");
+    box_params(c, P, (c.bp.dof & LKS_DOF_ROT) != 0, b0[6]);
+    double *krD = at<double>(work, L.krD), *Bf = at<double>(work, L.Bf), *cp = at<double>(work, L.cpl);
+    Prof pf;
+    if (c.prec == LKS_FP32) {
+        Run<float> R{c, st, &pf};
+        R.kappa_ref((const float *)gamma, at<float>(work, L.krT), krD);
+    } else {
+        Run<double> R{c, st, &pf};
+        R.kappa_ref((const double *)gamma, at<double>(work, L.krT), krD);
+    }
+    hipLaunchKernelGGL(k_body_init<2>, dim3(1), dim3(64), 0, st, body, Bf);
+    coupling_launch(c, st, Bf, krD, cp, K);
     HIP_TRY(hipGetLastError());
     return LKS_OK;
 }

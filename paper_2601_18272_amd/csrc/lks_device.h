@@ -42,11 +42,25 @@ template <> struct Lat<3> {
 };
 
 // ------------------------------------------------------------ geometry
+// The velocity field is held as its deviation v = u - U from a constant reference
+// velocity U (the velocity prescribed on the first VELOCITY face, else zero): every
+// kernel that needs the velocity itself adds U back. The equilibrium of a uniform flow
+// U streams into itself (p* = 0, u* = U), so the LKS update of v involves only small
+// quantities; in FP32 the fields then keep their relative precision on the small
+// transverse velocities and pressure that drive the body, instead of rounding them
+// against |U|.
 struct Grid {
     int n[3];
     int per[3];      // axis is periodic (2D: z counts as periodic)
     long long N;
+    double U[3];     // reference velocity of the stored deviation
+    float Uf[3];     // the same rounded to float (kernel arguments, no conversion on the device)
 };
+
+// U_a in the arithmetic type of a kernel.
+template <typename T> __device__ __forceinline__ T gU(const Grid &g, int a);
+template <> __device__ __forceinline__ float gU<float>(const Grid &g, int a) { return g.Uf[a]; }
+template <> __device__ __forceinline__ double gU<double>(const Grid &g, int a) { return g.U[a]; }
 
 struct Bc {
     int kind[6];

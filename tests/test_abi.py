@@ -244,3 +244,21 @@ def test_optimize_rejects_mismatched_continuation_lists():
     pb = W.small2d(ckpt_every=5)
     with pytest.raises(ValueError):
         api.optimize(pb, None, None, None, 0.5, 1.5, betas=[1.0, 2.0], qs=[0.1])
+
+
+def test_coupling_validation_without_gpu(lib):
+    """lks_coupling rejects a problem without a design grid, null pointers and a short
+    workspace before any HIP call."""
+    from paper_2601_18272_amd import api
+
+    L = lib.load()
+    dummy = C.c_void_p(16)
+    pb = W.small2d()
+    s = api.problem_struct(pb)
+    nob = api.problem_struct(pb.replace(nd=(0, 0, 0)))
+    assert L.lks_coupling(C.byref(nob), dummy, dummy, dummy, dummy, 1 << 30, None) == lib.EINVAL
+    assert L.lks_coupling(C.byref(s), None, dummy, dummy, dummy, 1 << 30, None) == lib.EINVAL
+    assert L.lks_coupling(C.byref(s), dummy, None, dummy, dummy, 1 << 30, None) == lib.EINVAL
+    assert L.lks_coupling(C.byref(s), dummy, dummy, None, dummy, 1 << 30, None) == lib.EINVAL
+    assert L.lks_coupling(C.byref(s), dummy, dummy, dummy, dummy, 16, None) == lib.ENOSPACE
+    assert lib.FLAG_STABILITY == 4

@@ -4,10 +4,16 @@ configuration the benchmark times (same kernels, same grids).
 - The oracle computes truncated runs of every configuration element by element
   (config 1 in full), compared with the GPU FP64 path (tight) and the FP32 path (the
   accuracy targets: 1e-4 relative on J, 1e-3 relative L2 on the gradient).
-- Config 5 is too large for the oracle beyond a step, so at its full size the FP64 GPU
-  gradient is checked against central finite differences of the FP64 GPU forward (a
-  property of the exact discrete adjoint at any size), and FP32 against FP64.
+- Config 5 at its full size: the FP64 GPU gradient against central finite differences
+  of the FP64 GPU forward (a property of the exact discrete adjoint at any size), FP32
+  against FP64, and a 3-step run against the oracle's stored values (the oracle needs
+  minutes for it: tests/golden/make_config5_oracle.py writes them).
+- A 3D design of 343 tiles runs config 5's reverse path (tiled R1, separate finish
+  kernels) against the oracle itself.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -33,6 +39,13 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+def elem(a, b):
+    """Largest entry-wise difference relative to the largest reference entry."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
 def test_config1_full_forward(L, orc):
     """Config 1 in full: 1000 steps of the 128x64 channel with the free 32x32 body."""
     pb = W.config("config1")
@@ -46,11 +59,12 @@ def test_config1_full_forward(L, orc):
     assert abs(J32.item() - Jref) <= 1e-4 * abs(Jref)
 
 
-# FP32 objective tolerance. The 3D rotation angle (configs 5, 5d) is driven by a torque
-# that is a small difference of large per-point terms (a nearly symmetric random body in
-# a nearly uniform flow), which amplifies FP32 field rounding: measured 3.0e-4 (5d, 8
-# steps) and 4.5e-4 (config 5, 100 steps); held to 5e-3. All others: the 1e-4 target.
-TOL_J32 = {"config5d": 5e-3, "config5": 5e-3}
+# FP32 objective tolerance: the 1e-4 target everywhere. The 3D rotation angle (configs
+# 5, 5d) is driven by a torque that is a small difference of large per-point terms (a
+# nearly symmetric random body in a nearly uniform flow); the velocity is held as its
+# deviation from the inflow so that FP32 rounding does not swamp the small transverse
+# flow that produces it.
+TOL_J32 = {}
 
 TRUNC = {
     "config1": (200, 64),
@@ -71,10 +85,12 @@ def test_truncated_gradient_vs_oracle(L, orc, name):
     g64 = L.adjoint(pb, g, B, precision="fp64").cpu().numpy()
     assert abs(J.item() - Jref) <= 1e-9 * abs(Jref) + 1e-18
     assert rel(g64, gref) < 1e-8
+    assert elem(g64, gref) < 1e-8
     _, _, J32, B32 = L.forward(pb, g, s0, b0, precision="fp32")
     g32 = L.adjoint(pb, g, B32, precision="fp32").cpu().numpy()
     assert abs(J32.item() - Jref) <= TOL_J32.get(name, 1e-4) * abs(Jref)
     assert rel(g32, gref) < 1e-3
+    assert elem(g32, gref) < 1e-3
 
 
 @pytest.mark.parametrize("name,nt,K", [("config5", 6, 4), ("config3", 40, 16)])
@@ -108,3 +124,62 @@ def test_fullsize_gradient_vs_finite_differences(L, name, nt, K):
     g32 = L.adjoint(pb, g, B32, precision="fp32").cpu().numpy()
     assert abs(J32.item() - J.item()) <= TOL_J32.get(name, 1e-4) * abs(J.item())
     assert rel(g32, grad) < 1e-3
+    assert elem(g32, grad) < 1e-3
+
+
+def _tiles343(n_steps=3, K=2):
+    """A 3D duct whose 56^3 design has 7^3 = 343 8^3 tiles: more than 256 blocks, so the
+    FP32 reverse takes the tiled interpolation reverse (R1 over 8^3 design tiles) with
+    the separate one-block finish kernels (k_interp_finish, k_r3_finish after every
+    R3), the path config 5 (1728 tiles) runs. Rotation about x plus axial translation,
+    objective the axial displacement (well conditioned from the first step)."""
+    pb = W.duct3d(112, 80, 80, 0.04, 0.02, nd=(56, 56, 56), kappa_max=0.01, q=0.1, mass=2000.0,
+                  inertia=1e6, axis=0, dof_mask=W.DOF_TX | W.DOF_ROT, n_itr=3, n_steps=n_steps,
+                  objective=W.OBJ_DISP_X, ckpt_every=K, x_g0=(40.0, 40.0, 40.0), theta0=0.2, seed=7)
+    return pb
+
+
+def test_many_tile_3d_gradient_vs_oracle(L, orc):
+    pb = _tiles343()
+    g, s0, b0 = W.design(pb), W.initial_state(pb), W.initial_body(pb)
+    print(f"tiles343: oracle gradient ({pb.n}, nd {pb.nd}, {pb.n_steps} steps)", flush=True)
+    Jref, gref = orc.gradient(pb, g, s0, b0)
+    for prec, tj, tg in (("fp64", 1e-9, 1e-8), ("fp32", 1e-4, 1e-3)):
+        _, _, J, B = L.forward(pb, g, s0, b0, precision=prec)
+        gg = L.adjoint(pb, g, B, precision=prec).cpu().numpy()
+        del B
+        print(f"tiles343 {prec}: J {J.item():.9e} oracle {Jref:.9e}, grad rel {rel(gg, gref):.2e}, "
+              f"elem {elem(gg, gref):.2e}", flush=True)
+        assert abs(J.item() - Jref) <= tj * abs(Jref)
+        assert rel(gg, gref) < tg
+        assert elem(gg, gref) < tg
+
+
+GOLDEN5 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "config5_oracle_3steps.json")
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN5), reason="stored oracle values not generated")
+def test_config5_fullsize_vs_stored_oracle(L):
+    """Config 5 at its full size (4.2M nodes, 96^3 design, 1728 design tiles), 3 steps
+    with checkpoints every 2, in the benchmark's launch configuration, against the FP64
+    oracle's values stored by tests/golden/make_config5_oracle.py: FP64 objective and
+    body to 1e-9, the gradient's norm and 64 sampled entries to 1e-8 of its largest;
+    FP32 gradient entries to 1e-3 of the largest."""
+    ref = json.load(open(GOLDEN5))
+    pb = W.config("config5").replace(n_steps=ref["n_steps"], ckpt_every=ref["ckpt_every"])
+    g, s0, b0 = W.design(pb), W.initial_state(pb), W.initial_body(pb)
+    idx = np.array(ref["idx"])
+    gr = np.array(ref["grad"])
+    gmax = ref["grad_max"]
+    for prec, tb, tg in (("fp64", 1e-9, 1e-8), ("fp32", None, 1e-3)):
+        _, bd, J, B = L.forward(pb, g, s0, b0, precision=prec)
+        gg = L.adjoint(pb, g, B, precision=prec).cpu().numpy()
+        del B
+        print(f"config5 {prec}: J {J.item():.9e} oracle {ref['J']:.9e}, sampled grad "
+              f"{np.abs(gg[idx] - gr).max() / gmax:.2e}", flush=True)
+        if tb is not None:
+            assert abs(J.item() - ref["J"]) <= tb * abs(ref["J"]) + 1e-20
+            bodyr = np.array(ref["body"])
+            assert np.abs(bd.cpu().numpy()[:8] - bodyr).max() <= tb * np.abs(bodyr).max()
+            assert abs(np.linalg.norm(gg) - ref["grad_l2"]) <= tg * ref["grad_l2"]
+        assert np.abs(gg[idx] - gr).max() <= tg * gmax

@@ -33,6 +33,14 @@ def rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
+def elem(a, b):
+    """Largest entry-wise difference relative to the largest reference entry: a wrong
+    small entry (for example on the body's rim) cannot hide under the L2 norm."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
 def smooth_state(pb, seed, amp=1e-2):
     """Random smooth perturbation of the initial state (boundary values untouched
     matter not: the first step re-imposes them)."""
@@ -102,7 +110,9 @@ def test_bodyfree_adjoint_initial_state(L, orc, case):
     gg, dsg, dbg = L.adjoint(pb, g, B, precision="fp64", want_initial=True)
     assert abs(Jg.item() - J) <= 1e-9 * abs(J) + 1e-15
     assert rel(gg.cpu().numpy(), grad) < 1e-8
+    assert elem(gg.cpu().numpy(), grad) < 1e-8
     assert rel(dsg.cpu().numpy(), ds) < 1e-8
+    assert elem(dsg.cpu().numpy(), ds) < 1e-8
     assert np.abs(dbg.cpu().numpy()[:8] - db[:8]).max() <= 1e-8 * np.abs(db[:8]).max()
 
 
@@ -139,6 +149,7 @@ def test_coupled_gradient_fp64(L, orc, case):
     gg = L.adjoint(pb, g, B, seed=1.7, precision="fp64").cpu().numpy()
     assert abs(J.item() - Jref) <= 1e-9 * abs(Jref) + 1e-16
     assert rel(gg, gref) < 1e-8
+    assert elem(gg, gref) < 1e-8
 
 
 @pytest.mark.parametrize("case", sorted(BODY))
@@ -152,6 +163,7 @@ def test_coupled_fp32_targets(L, orc, case):
     gg = L.adjoint(pb, g, B, precision="fp32").cpu().numpy()
     assert abs(J.item() - Jref) <= 1e-4 * abs(Jref)
     assert rel(gg, gref) < 1e-3
+    assert elem(gg, gref) < 1e-3
 
 
 def test_map_design_matches_oracle(L, orc):
@@ -210,6 +222,7 @@ def test_autograd_function(L, orc):
     Jref, gref = orc.gradient(pb, W.design(pb), W.initial_state(pb), W.initial_body(pb), seed=2.5)
     assert abs(J.item() - Jref) <= 1e-9 * abs(Jref)
     assert rel(g.grad.cpu().numpy(), gref) < 1e-8
+    assert elem(g.grad.cpu().numpy(), gref) < 1e-8
 
 
 def test_empty_run_and_no_body(L, orc):
@@ -257,7 +270,9 @@ def test_adjoint_with_terminal_values(L, orc, case, prec):
     gg, ds, db = L.adjoint(pb, g, B, seed=seed, precision=prec, want_initial=True, dstate_T=sT, dbody_T=bT)
     tol = 1e-8 if prec == "fp64" else 1e-3
     assert rel(gg.cpu().numpy(), gref) < tol
+    assert elem(gg.cpu().numpy(), gref) < tol
     assert rel(ds.cpu().numpy(), dsref) < tol
+    assert elem(ds.cpu().numpy(), dsref) < tol
     assert np.abs(db.cpu().numpy()[:8] - dbref[:8]).max() <= tol * np.abs(dbref[:8]).max()
 
 

@@ -877,3 +877,21 @@ def test_one_step_adjoint_dot_product_free_body(orc, dim):
     fd = (L(s0 + h * v, b0 + h * vb) - L(s0 - h * v, b0 - h * vb)) / (2 * h)
     _, _, ds, db = orc.gradient(pb, g, s0, b0, seed=0.0, with_initial=True, dstate_T=w, dbody_T=wb)
     assert ds @ v + db[:8] @ vb[:8] == pytest.approx(fd, rel=1e-7)
+
+
+def test_unstable_coupling_diverges(orc):
+    """The stability reading of Sec. 3.1's iteration: with K/M above one the iterates of
+    every step overshoot and the body velocity grows without bound within a few dozen
+    steps; at K/M = 0.5 (how the configurations are set) it stays of the order of the
+    flow's drag. This is what the library's LKS_FLAG_STABILITY pre-check rejects."""
+    base = W.small2d(dof_mask=W.DOF_TX, theta0=0.0, n_steps=1)
+    g, s0, b0 = W.design(base), W.initial_state(base), W.initial_body(base)
+    K = orc.coupling(base, g, s0, b0)[0]
+    speeds = {}
+    for ratio in (0.5, 1.6):
+        pb = base.replace(mass=K / ratio, n_steps=40)
+        _, b, _, tr = orc.forward(pb, g, s0, b0, traj=True)
+        speeds[ratio] = np.abs(tr[:, 3])
+    assert np.all(np.isfinite(speeds[0.5])) and speeds[0.5].max() < 0.1
+    grown = speeds[1.6]
+    assert not np.all(np.isfinite(grown)) or grown[-1] > 1e3 * speeds[0.5].max()
