@@ -120,6 +120,25 @@ int lks_forward(const lks_problem_t *P, const void *gamma, void *state, double *
                 void *stream);
 
 /*
+ * lks_forward_noalloc -- lks_forward without checkpoints, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the scratch space lks_forward takes through `work` comes from
+ * a static device array of LKS_NOALLOC_SCRATCH_BYTES that the library holds on every GPU
+ * it runs on (until the process ends). The call allocates nothing: no hipMalloc, hipFree
+ * or allocating library routine. The caller still passes the inputs and outputs, with
+ * the meaning of lks_forward's (state in/out, body in/out, J out).
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU (several
+ * streams or host threads) race and must be serialised by the caller. Each call starts
+ * from cleared counters and flags; nothing is carried between calls.
+ * Errors: as lks_forward, plus LKS_ENOSPACE when the problem needs more than
+ * LKS_NOALLOC_SCRATCH_BYTES of scratch (lks_workspace_bytes(P, 0)), and LKS_EINVAL with
+ * LKS_FLAG_PROFILE (profiling creates events).
+ */
+#define LKS_NOALLOC_SCRATCH_BYTES (32u << 20)
+int lks_forward_noalloc(const lks_problem_t *P, const void *gamma, void *state, double *body, double *J,
+                        void *stream);
+
+/*
  * lks_adjoint -- reverse-time sweep (Sec. 2.5, Algorithm 1, adjoint loop) giving the
  * design sensitivity (Eq. design_sensitivity) as the exact derivative of the discrete
  * map that lks_forward computes: segments of ckpt_every steps are recomputed from the

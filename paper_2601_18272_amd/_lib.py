@@ -26,7 +26,8 @@ EXPORTS = ("lks_state_elems", "lks_checkpoint_bytes", "lks_workspace_bytes", "lk
            "lks_profile_reset", "lks_design_filter", "lks_design_filter_adjoint",
            "lks_filter_workspace_bytes", "lks_cyclic_sector_points", "lks_design_cyclic_expand",
            "lks_design_cyclic_collect", "lks_mma_workspace_bytes", "lks_mma_update", "lks_volume_constraint",
-           "lks_coupling")
+           "lks_coupling", "lks_forward_noalloc")
+NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
 class LksProblem(C.Structure):
@@ -96,6 +97,8 @@ def load():
     L.body_step.argtypes = [pp, dp, dp, dp, vp]
     L.lks_coupling.argtypes = [pp, vp, dp, dp, vp, C.c_size_t, vp]
     L.lks_coupling.restype = C.c_int
+    L.lks_forward_noalloc.argtypes = [pp, vp, vp, dp, dp, vp]
+    L.lks_forward_noalloc.restype = C.c_int
     L.body_step.restype = C.c_int
     fp = C.POINTER(LksFilter)
     L.lks_design_filter.argtypes = [pp, fp, vp, vp, vp, vp]

@@ -19,6 +19,7 @@
 #include <cstring>
 #include <string>
 #include <type_traits>
+#include <mutex>
 #include <vector>
 
 #include "../../include/lks.h"
@@ -80,6 +81,12 @@ __global__ __launch_bounds__(256) void k_shift(T *__restrict__ s, long long N, i
     const double U[3] = {U0, U1, U2};
     for (int a = 0; a < dim; a++)
         if (U[a] != 0.0) s[(1 + a) * N + i] = T((double)s[(1 + a) * N + i] + sign * U[a]);
+}
+
+// Clears n 32-bit words (a fill kernel rather than hipMemsetAsync, so that a caller
+// may capture the enqueued work in a graph).
+__global__ void k_zero32(unsigned *p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
 }
 
 struct Prof {
@@ -845,8 +852,8 @@ int forward_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, T *state
     int *flag = at<int>(work, L.flag);
     const size_t rec = (size_t)(c.K + 1) * B_REC;
     const size_t stateB = (size_t)c.S * sizeof(T);
-    HIP_TRY(hipMemsetAsync(counter, 0, 16, st));
-    HIP_TRY(hipMemsetAsync(flag, 0, 16, st));
+    hipLaunchKernelGGL(k_zero32, dim3(1), dim3(64), 0, st, counter, 4);
+    hipLaunchKernelGGL(k_zero32, dim3(1), dim3(64), 0, st, (unsigned *)flag, 4);
     R.kappa_ref(gamma, krT, krD);
     hipLaunchKernelGGL(k_body_init<2>, dim3(1), dim3(64), 0, st, body, Bf);
     HIP_TRY(hipMemcpyAsync(Binit, Bf, B_REC * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -1210,6 +1217,31 @@ int cyc_ctx(const lks_problem_t *P, int n_sec, Ctx &c, CycArgs &a) {
 namespace {
 
 // MMA workspace: coefficients (MC_COUNT n doubles), block partials, the state.
+// ------------------------------------------------------------------ no-allocation scratch
+// Workspace of lks_forward_noalloc: a file-scope device array that every GPU the library
+// runs on holds until the process ends. Host code never passes its name to a kernel (in
+// host code the name is a host-side stand-in): the address is taken once per device,
+// with that device current, and kept.
+static __device__ __align__(256) unsigned char scratch[LKS_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch_ptr;  // per device id, null until taken
+
+int noalloc_scratch(void **ptr) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(LKS_EHIP, "hipGetSymbolAddress returned a null address for the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return LKS_OK;
+}
+
 unsigned mma_blocks(long long n) { return std::min(blocks(n, MMA_NT), 1024u); }
 size_t mma_work_bytes(long long n) {
     const size_t nb = mma_blocks(n);
@@ -1278,6 +1310,28 @@ int lks_forward(const lks_problem_t *P, const void *gamma, void *state, double *
     if (c.prec == LKS_FP32)
         return forward_impl<float>(c, P, (const float *)gamma, (float *)state, body, ckpt, work, J, st);
     return forward_impl<double>(c, P, (const double *)gamma, (double *)state, body, ckpt, work, J, st);
+}
+
+int lks_forward_noalloc(const lks_problem_t *P, const void *gamma, void *state, double *body, double *J,
+                        void *stream) {
+    g_err.clear();
+    Ctx c;
+    int rc = make_ctx(P, c);
+    if (rc) return rc;
+    if (!state || !body || !J || (c.has_body && !gamma)) return fail(LKS_EINVAL, "null pointer argument");
+    if (P->flags & LKS_FLAG_PROFILE)
+        return fail(LKS_EINVAL, "lks_forward_noalloc: LKS_FLAG_PROFILE is not available (it creates events)");
+    const size_t need = layout(c, false).total;
+    if (need > LKS_NOALLOC_SCRATCH_BYTES)
+        return fail(LKS_ENOSPACE, "lks_forward_noalloc: the problem needs %zu bytes of scratch, the static array holds %zu",
+                    need, (size_t)LKS_NOALLOC_SCRATCH_BYTES);
+    void *work = nullptr;
+    rc = noalloc_scratch(&work);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (c.prec == LKS_FP32)
+        return forward_impl<float>(c, P, (const float *)gamma, (float *)state, body, nullptr, work, J, st);
+    return forward_impl<double>(c, P, (const double *)gamma, (double *)state, body, nullptr, work, J, st);
 }
 
 int lks_adjoint(const lks_problem_t *P, const void *gamma, const void *ckpt, size_t ckpt_bytes_, void *work,
