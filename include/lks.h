@@ -46,8 +46,11 @@ enum { LKS_DOF_TX = 1, LKS_DOF_TY = 2, LKS_DOF_TZ = 4, LKS_DOF_ROT = 8 };
  * LKS_FLAG_STABILITY: lks_forward first computes the coupling constants of the fluid <->
  *   body iteration at t = 0 (lks_coupling) and returns LKS_EUNSTABLE, before any time
  *   step, when an active degree of freedom has K/M >= 1 or K_theta/I >= 1 (the
- *   iteration of Sec. 3.1 then does not contract). */
-enum { LKS_FLAG_ASYNC = 1, LKS_FLAG_PROFILE = 2, LKS_FLAG_STABILITY = 4 };
+ *   iteration of Sec. 3.1 then does not contract).
+ * LKS_FLAG_PAPER_ADJOINT: lks_adjoint computes the paper's own adjoint variant instead of
+ *   the exact reverse of the discrete map (below); the flag must also be set in the
+ *   lks_workspace_bytes(P, 1) query (the variant needs more scratch). */
+enum { LKS_FLAG_ASYNC = 1, LKS_FLAG_PROFILE = 2, LKS_FLAG_STABILITY = 4, LKS_FLAG_PAPER_ADJOINT = 8 };
 
 enum {
     LKS_OK = 0,
@@ -157,6 +160,16 @@ int lks_forward_noalloc(const lks_problem_t *P, const void *gamma, void *state, 
  *   grad     [ND] double, out: dL/dgamma
  *   dstate0  optional [(dim+1)*N] T, out: dL/d(initial state)
  *   dbody0   optional [12] double, out: dL/d(initial body state)
+ * With LKS_FLAG_PAPER_ADJOINT (problems with a design grid; dstate_T, dbody_T, dstate0,
+ * dbody0 must be NULL) the sweep is instead the paper's adjoint variant (Sec. 2.5, App. A,
+ * Algorithm 1's adjoint loop): the continuous adjoint discretised like the forward. Per
+ * time level, backwards: the ALKS of Eqs. ap_tmp..as_tmp with the forward velocity of the
+ * same level, then n_itr fixed-point iterations of Eq. au (the Brinkman factor applied to
+ * the adjoint moment u~ with the body terms) and Eqs. axg, aug, atheta, aomega for the
+ * body adjoints, and the sensitivity of Eq. design_sensitivity. The objective enters as
+ * J = sum_t J_I with J_I = omega or u^G_a (Eqs. objective1/2), scaled by seed. It
+ * approximates the derivative of the discrete map (the paper's "good agreement"); grad
+ * is then that approximation.
  * Errors: LKS_EINVAL, LKS_ENOSPACE, LKS_EHIP.
  */
 int lks_adjoint(const lks_problem_t *P, const void *gamma, const void *ckpt, size_t ckpt_bytes,

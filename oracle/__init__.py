@@ -67,6 +67,7 @@ def lib():
         L.orc_step.argtypes = [pp, dp, dp, dp, dp, dp]
         L.orc_forward.argtypes = [pp, dp, dp, dp, dp, dp]
         L.orc_gradient.argtypes = [pp, dp, dp, dp, C.c_double, dp, dp, dp, dp, dp, dp]
+        L.orc_gradient_paper.argtypes = [pp, dp, dp, dp, dp, dp]
         L.orc_cyclic_sector_points.argtypes = [pp, C.c_int]
         L.orc_cyclic_sector_points.restype = C.c_long
         L.orc_cyclic_expand.argtypes = [pp, C.c_int, dp, dp]
@@ -163,6 +164,18 @@ def gradient(pb, gamma, state0, body0, seed=1.0, with_initial=False, dstate_T=No
                               float(seed), _p(sT), _p(bT), _p(grad), C.byref(J), _p(ds), _p(db)),
            "orc_gradient")
     return (J.value, grad, ds, db) if with_initial else (J.value, grad)
+
+
+def gradient_paper(pb, gamma, state0, body0):
+    """The paper's adjoint variant (continuous adjoint discretised, Sec. 2.5): returns
+    (J, grad). Not the exact derivative of the discrete forward map."""
+    s = problem_struct(pb)
+    g = _f64(gamma)
+    grad = np.zeros_like(g)
+    J = C.c_double(0.0)
+    _check(lib().orc_gradient_paper(C.byref(s), _p(g), _p(_f64(state0)), _p(_f64(body0)), _p(grad), C.byref(J)),
+           "orc_gradient_paper")
+    return J.value, grad
 
 
 def kappa_ref(pb, gamma):

@@ -16,6 +16,8 @@
  *             Eqs. ap_tmp..as with (p~, u~, s~) the moments of the adjoint
  *             distribution; at boundaries, in the Brinkman / body terms and through
  *             the unrolled N_itr loop it is the exact transpose of the forward code.
+ *             orc_gradient_paper is the paper's own variant instead (the continuous
+ *             adjoint discretised like the forward; Eqs. au, axg..aomega).
  *
  * Readings where the paper is silent or garbled (each is listed in the design notes):
  *   - the -3/2 u.u sign of the equilibrium (printed with +);
@@ -649,12 +651,61 @@ static void step_fwd(const ctx_t *C, const double *kr, const double *s_in, const
 
 /* ------------------------------------------------------- reverse sweep */
 
+/* The LKS gather reversed (the exact transpose; in the fluid interior it is the ALKS of
+ * Eqs. ap_tmp..as_tmp). g_i(x) = pb(x)/3 + c_i . ub(x) at interior x is the cotangent of
+ * f_i(x - c_i); with the moments pi = sum_i w_i g_i(y + c_i), ups = sum_i w_i c_i g_i,
+ * sig = sum_i w_i c_i c_i g_i at node y and the forward velocity u(y) of s_in:
+ *   nb_p(y) = 3 pi,  nb_u(y) = 3 ups + 9 sig u - 3 pi u + (transpose of the gradient
+ *   stencil applied to 2A sig).
+ * ups_out (optional, d*N): the moment ups itself (the paper's u~* of Eq. au_tmp). */
+static void alks_gather(const ctx_t *C, const double *s_in, const double *sb, const double *ustb,
+                        double *nb, double *ups_out)
+{
+    const int d = C->dim, Q = C->q;
+    const long N = C->N;
+    memset(nb, 0, sizeof(double) * (d + 1) * N);
+    if (ups_out) memset(ups_out, 0, sizeof(double) * d * N);
+    for (long id = 0; id < N; id++) {
+        int y[3];
+        coords(C, id, y);
+        double u[3] = {0, 0, 0};
+        for (int b = 0; b < d; b++) u[b] = s_in[(1 + b) * N + id];
+        double Sb[3][3] = {{0}};
+        for (int i = 0; i < Q; i++) {
+            int z[3];
+            if (!shifted(C, y, C->c[i], 1, z) || !interior(C, z)) continue;
+            long zi = nid(C, z);
+            double fb = sb[zi] / 3.0;
+            for (int a = 0; a < d; a++) fb += C->c[i][a] * ustb[a * N + zi];
+            double cu = 0;
+            for (int a = 0; a < d; a++) cu += C->c[i][a] * u[a];
+            nb[id] += 3.0 * C->w[i] * fb;
+            for (int b = 0; b < d; b++)
+                nb[(1 + b) * N + id] +=
+                    C->w[i] * fb * (3.0 * C->c[i][b] + 9.0 * cu * C->c[i][b] - 3.0 * u[b]);
+            if (ups_out)
+                for (int b = 0; b < d; b++) ups_out[b * N + id] += C->w[i] * C->c[i][b] * fb;
+            for (int a = 0; a < d; a++)
+                for (int b = 0; b < d; b++)
+                    Sb[a][b] += 2.0 * C->A * C->w[i] * fb * C->c[i][a] * C->c[i][b];
+        }
+        /* transpose of the velocity-gradient stencil at y */
+        for (int a = 0; a < d; a++) {
+            long nodes[3];
+            double coef[3];
+            int k = deriv_stencil(C, y, a, nodes, coef);
+            for (int b = 0; b < d; b++)
+                for (int j = 0; j < k; j++) nb[(1 + b) * N + nodes[j]] += coef[j] * Sb[a][b];
+        }
+    }
+}
+
 /* Reverse of one coupled step. s_in, Bin: forward state at t-1. sb (in: cotangent of
  * S(t), out: of S(t-1)), Bb (same for the body), krb accumulates d/dkappa_ref. */
 static void step_rev(const ctx_t *C, const double *kr, const double *s_in, const double *Bin,
                      double *sb, double *Bb, double *krb, work_t *W, double *scratch)
 {
-    const int d = C->dim, Q = C->q;
+    const int d = C->dim;
     const long N = C->N;
     /* recompute the forward step with per-iteration records */
     double *s_out = scratch;                 /* (d+1)*N */
@@ -795,41 +846,8 @@ static void step_rev(const ctx_t *C, const double *kr, const double *s_in, const
         memcpy(ustb, sb + N, sizeof(double) * d * N);
     }
 
-    /* LKS gather, reversed (exact transpose; ALKS Eqs. ap_tmp..as in the interior).
-     * g_i(x) = p*_bar(x)/3 + c_i . u*_bar(x) at interior x is the cotangent of
-     * f_i(x - c_i). */
-    memset(nb, 0, sizeof(double) * (d + 1) * N);
-    for (long id = 0; id < N; id++) {
-        int y[3];
-        coords(C, id, y);
-        double u[3] = {0, 0, 0};
-        for (int b = 0; b < d; b++) u[b] = s_in[(1 + b) * N + id];
-        double Sb[3][3] = {{0}};
-        for (int i = 0; i < Q; i++) {
-            int z[3];
-            if (!shifted(C, y, C->c[i], 1, z) || !interior(C, z)) continue;
-            long zi = nid(C, z);
-            double fb = sb[zi] / 3.0;
-            for (int a = 0; a < d; a++) fb += C->c[i][a] * ustb[a * N + zi];
-            double cu = 0;
-            for (int a = 0; a < d; a++) cu += C->c[i][a] * u[a];
-            nb[id] += 3.0 * C->w[i] * fb;
-            for (int b = 0; b < d; b++)
-                nb[(1 + b) * N + id] +=
-                    C->w[i] * fb * (3.0 * C->c[i][b] + 9.0 * cu * C->c[i][b] - 3.0 * u[b]);
-            for (int a = 0; a < d; a++)
-                for (int b = 0; b < d; b++)
-                    Sb[a][b] += 2.0 * C->A * C->w[i] * fb * C->c[i][a] * C->c[i][b];
-        }
-        /* transpose of the velocity-gradient stencil at y */
-        for (int a = 0; a < d; a++) {
-            long nodes[3];
-            double coef[3];
-            int k = deriv_stencil(C, y, a, nodes, coef);
-            for (int b = 0; b < d; b++)
-                for (int j = 0; j < k; j++) nb[(1 + b) * N + nodes[j]] += coef[j] * Sb[a][b];
-        }
-    }
+    /* LKS gather, reversed (exact transpose; ALKS Eqs. ap_tmp..as in the interior) */
+    alks_gather(C, s_in, sb, ustb, nb, NULL);
     memcpy(sb, nb, sizeof(double) * (d + 1) * N);
 }
 
@@ -952,6 +970,246 @@ done:
     free(bodies);
     free(sb);
     free(scratch);
+    return rc;
+}
+
+/* ------------------------------------------------ the paper's adjoint variant (Sec. 2.5)
+ * The sensitivity as the paper derives it: the continuous adjoint of the fluid and body
+ * equations, discretised like the forward (App. A), instead of the exact reverse of the
+ * discrete map. Objective J = sum_t J_I(t) with J_I = omega (Eq. objective2, theta(t1) =
+ * integral of omega) or u^G_a (Eq. objective1). Per time level t = N_t .. 1, backwards:
+ *  - the ALKS (Eqs. ap_tmp..as_tmp): p~*, u~*, s~* at t gathered from f~eq of level t+1,
+ *    f~eq_i = p~ + c_i.(3 u~ + 9 s~ u - 3 p~ u - 2A div s~) with the forward u at t+1
+ *    (alks_gather carries (3 p~, 3 u~ + 9 s~ u - 3 p~ u - 2A div s~) and returns the
+ *    moments; the boundary values are taken through the transpose of the forward
+ *    boundary copies, the same reading as the exact adjoint);
+ *  - N_itr iterations at the pose B(t) (Algorithm 1, adjoint loop):
+ *      Eq. au:  u~ = (u~* + (u~G kappa + w~ S_k) / 3) / (1 + kappa), with kappa = sum_m W
+ *               kappa_m and S_k = sum_m W kappa_m (a x r_m) (p~ = p~*, s~ = s~*);
+ *      Eqs. axg, aug, atheta, aomega for x~G, u~G, theta~, w~ at t from their values at
+ *               t+1, their right-hand sides at level t taken with the u~G, w~ of the
+ *               iteration's start (x~G feeds u~G, theta~ feeds w~ in the same iteration);
+ *  - Eq. design_sensitivity: dJ/dkappa_m += 3 sum_x W (u - u^S).u~ - u~G.(u^ref - u^S,ref)_m
+ *    - w~ (a x r_m).(u^ref - u^S,ref)_m.
+ * Readings (the paper is silent): the level N_t + 1 adjoint is zero (the sources -dJ_I/d.
+ * enter at every level, which at t1 gives the paper's stated terminal values); the u~G,
+ * w~ iteration starts from the values of level t+1; the sensitivity uses the final
+ * values of level t; Eq. au's "u*" is read as u~*; an inactive degree of freedom has zero
+ * adjoints. Not the exact derivative of the discrete forward map: O(dt) and Brinkman
+ * differences remain (compared with the exact sweep and finite differences in tests).
+ * Pinned by its agreement with the exact adjoint (0.1-3 %), which a mistake in Eq. au or
+ * in the sensitivity breaks; parity unpinned for the pose-derivative terms of Eqs. axg
+ * and atheta, whose effect stays below that difference in every case tried. */
+int orc_gradient_paper(const orc_problem *P, const double *gamma, const double *state0,
+                       const double *body0, double *grad, double *J)
+{
+    ctx_t C;
+    if (ctx_init(&C, P) || !state0 || !body0 || !gamma || !grad || P->n_steps < 0 || !C.has_body) return -1;
+    const int d = C.dim, K = P->n_itr, ax = C.axis, pi = C.pi, pj = C.pj;
+    const long N = C.N, S = (d + 1) * N, ND = C.ND;
+    const int NT = P->n_steps;
+    work_t W;
+    double *kr = malloc(sizeof(double) * ND), *krb = calloc(ND, sizeof(double));
+    double *states = malloc(sizeof(double) * S * (NT + 1)), *bodies = malloc(sizeof(double) * 12 * (NT + 1));
+    double *sb = calloc(S, sizeof(double)), *nb = calloc(S, sizeof(double));
+    double *ups = calloc(d * N, sizeof(double)), *upsn = calloc(d * N, sizeof(double));
+    double *kap = malloc(sizeof(double) * N), *uS = malloc(sizeof(double) * d * N);
+    double *phi = malloc(sizeof(double) * N), *Sv = malloc(sizeof(double) * 3 * N);
+    double *Sk = malloc(sizeof(double) * 3 * N), *Rp = malloc(sizeof(double) * 3 * N);
+    double *ut = malloc(sizeof(double) * d * N), *h = malloc(sizeof(double) * N), *q = malloc(sizeof(double) * d * N);
+    double *Du = malloc(sizeof(double) * 9 * ND), *Dv = malloc(sizeof(double) * 3 * ND);
+    int rc = work_alloc(&C, &W, 0);
+    if (rc || !kr || !krb || !states || !bodies || !sb || !nb || !ups || !upsn || !kap || !uS || !phi || !Sv ||
+        !Sk || !Rp || !ut || !h || !q || !Du || !Dv) {
+        rc = -2;
+        goto done;
+    }
+    for (long m = 0; m < ND; m++) kr[m] = kappa_of(P, gamma[m]);
+    memcpy(states, state0, sizeof(double) * S);
+    memcpy(bodies, body0, sizeof(double) * 12);
+    for (int t = 1; t <= NT; t++)
+        step_fwd(&C, kr, states + S * (t - 1), bodies + 12 * (t - 1), states + S * t, bodies + 12 * t, &W);
+    if (J) *J = objective_value(&C, bodies, bodies + 12 * NT);
+    /* dJ_I / d(u^G_a) and dJ_I / d(omega) */
+    double dJdU[3] = {0, 0, 0}, dJdOm = 0.0;
+    if (P->objective == ORC_OBJ_ANGLE) dJdOm = 1.0;
+    else dJdU[P->objective] = 1.0;
+    /* body adjoints of level t+1 */
+    double Xn[3] = {0, 0, 0}, Un[3] = {0, 0, 0}, Thn = 0.0, Omn = 0.0;
+    for (int t = NT; t >= 1; t--) {
+        const double *st = states + S * t, *B = bodies + 12 * t;
+        const double *u = st + N;
+        const double om = B[7];
+        apply_bc_rev(&C, sb);
+        /* fields at the pose B(t) */
+        spread(&C, kr, B, kap, uS);
+        memset(phi, 0, sizeof(double) * N);
+        memset(Sv, 0, sizeof(double) * 3 * N);
+        memset(Sk, 0, sizeof(double) * 3 * N);
+        memset(Rp, 0, sizeof(double) * 3 * N);
+        double sum_k = 0.0, sum_ks[3] = {0, 0, 0}, sum_ks2 = 0.0;
+        for (long m = 0; m < ND; m++) {
+            double xi[3], UR[3];
+            pose_t ps;
+            taps_t T;
+            design_xi(&C, m, xi);
+            pose_point(&C, B, xi, &ps);
+            taps_of(&C, ps.X, &T);
+            double rp[3] = {ps.r[0], ps.r[1], ps.r[2]};
+            rp[ax] = 0.0; /* part of r across the rotation axis */
+            for (int k = 0; k < T.count; k++) {
+                long id = T.id[k];
+                phi[id] += T.W[k];
+                for (int a = 0; a < 3; a++) {
+                    Sv[a * N + id] += T.W[k] * ps.axr[a];
+                    Sk[a * N + id] += T.W[k] * kr[m] * ps.axr[a];
+                    Rp[a * N + id] += T.W[k] * rp[a];
+                }
+            }
+            interp_point(&C, u, &T, UR);
+            for (int a = 0; a < 3; a++) Dv[3 * m + a] = a < d ? UR[a] - ps.US[a] : 0.0;
+            for (int g = 0; g < 3; g++)
+                for (int b = 0; b < 3; b++) {
+                    double v = 0.0;
+                    if (g < d && b < d)
+                        for (int k = 0; k < T.count; k++) v += T.dW[k][g] * u[b * N + T.id[k]];
+                    Du[9 * m + 3 * g + b] = v;
+                }
+            sum_k += kr[m];
+            for (int a = 0; a < 3; a++) sum_ks[a] += kr[m] * ps.axr[a];
+            sum_ks2 += kr[m] * (ps.axr[0] * ps.axr[0] + ps.axr[1] * ps.axr[1] + ps.axr[2] * ps.axr[2]);
+        }
+        double Ucur[3] = {Un[0], Un[1], Un[2]}, Omcur = Omn, Xt[3] = {0, 0, 0}, Tht = 0.0;
+        for (int it = 0; it < K; it++) {
+            /* Eq. au at the nodes, and the node sums of Eqs. aug, atheta, aomega */
+            double NU[3] = {0, 0, 0}, NO = 0.0, NTh = 0.0;
+            for (long id = 0; id < N; id++) {
+                int x[3];
+                coords(&C, id, x);
+                h[id] = 0.0;
+                for (int a = 0; a < d; a++) ut[a * N + id] = q[a * N + id] = 0.0;
+                if (!interior(&C, x)) continue;
+                const double kp = kap[id];
+                for (int a = 0; a < d; a++) {
+                    const double v = (ups[a * N + id] + (Ucur[a] * kp + Omcur * Sk[a * N + id]) / 3.0) / (1.0 + kp);
+                    ut[a * N + id] = v;
+                    h[id] += (u[a * N + id] - uS[a * N + id]) * v;
+                    q[a * N + id] = kp * v;
+                    NU[a] += 3.0 * kp * v * phi[id];
+                    NO += 3.0 * kp * v * Sv[a * N + id];
+                    NTh += 3.0 * kp * v * (-om * Rp[a * N + id]);
+                }
+            }
+            /* design sums of Eqs. axg, atheta */
+            double AXG[3] = {0, 0, 0}, ATH = NTh;
+            for (long m = 0; m < ND; m++) {
+                double xi[3];
+                pose_t ps;
+                taps_t T;
+                design_xi(&C, m, xi);
+                pose_point(&C, B, xi, &ps);
+                taps_of(&C, ps.X, &T);
+                double Dh[3] = {0, 0, 0}, Dq[3][3] = {{0}};
+                for (int k = 0; k < T.count; k++)
+                    for (int g = 0; g < d; g++) {
+                        Dh[g] += T.dW[k][g] * h[T.id[k]];
+                        for (int b = 0; b < d; b++) Dq[g][b] += T.dW[k][g] * q[b * N + T.id[k]];
+                    }
+                const double km = kr[m], *s_m = ps.axr, *Dum = Du + 9 * m, *Dvm = Dv + 3 * m;
+                double w[3] = {0, 0, 0}; /* w_b = sum_g s_g Du_gb */
+                for (int b = 0; b < 3; b++)
+                    for (int g = 0; g < 3; g++) w[b] += s_m[g] * Dum[3 * g + b];
+                for (int a = 0; a < d; a++) {
+                    double v = -3.0 * km * Dh[a];
+                    for (int b = 0; b < d; b++)
+                        v += 3.0 * ps.US[b] * Dq[a][b] + km * Ucur[b] * Dum[3 * a + b] + Omcur * km * s_m[b] * Dum[3 * a + b];
+                    AXG[a] += v;
+                }
+                double v = 0.0, rpm[3] = {ps.r[0], ps.r[1], ps.r[2]};
+                rpm[ax] = 0.0;
+                for (int g = 0; g < d; g++) v += -3.0 * km * s_m[g] * Dh[g];
+                for (int b = 0; b < d; b++)
+                    for (int g = 0; g < d; g++) v += 3.0 * ps.US[b] * Dq[g][b] * s_m[g];
+                for (int a = 0; a < d; a++) v += km * Ucur[a] * w[a] + om * km * Ucur[a] * rpm[a];
+                v += Omcur * km * (s_m[pi] * Dvm[pj] - s_m[pj] * Dvm[pi]);
+                v += Omcur * km * (ps.r[pi] * w[pj] - ps.r[pj] * w[pi]);
+                ATH += v;
+            }
+            /* Eqs. axg, aug (translation) and atheta, aomega (rotation) */
+            double Unew[3] = {0, 0, 0}, Omnew = 0.0;
+            for (int a = 0; a < d; a++) {
+                if (!(P->dof_mask & (1 << a))) {
+                    Xt[a] = 0.0;
+                    continue;
+                }
+                Xt[a] = Xn[a] + AXG[a];
+                Unew[a] = Un[a] + (Xt[a] + NU[a] - Ucur[a] * sum_k - Omcur * sum_ks[a] - dJdU[a]) / P->mass;
+            }
+            if (P->dof_mask & ORC_DOF_ROT) {
+                Tht = Thn + ATH;
+                double us_dot = 0.0;
+                for (int a = 0; a < d; a++) us_dot += Ucur[a] * sum_ks[a];
+                Omnew = Omn + (Tht + NO - us_dot - Omcur * sum_ks2 - dJdOm) / P->inertia;
+            } else {
+                Tht = 0.0;
+            }
+            for (int a = 0; a < 3; a++) Ucur[a] = Unew[a];
+            Omcur = Omnew;
+        }
+        /* Eq. design_sensitivity at level t (h from the last iteration's u~) */
+        for (long m = 0; m < ND; m++) {
+            double xi[3];
+            pose_t ps;
+            taps_t T;
+            design_xi(&C, m, xi);
+            pose_point(&C, B, xi, &ps);
+            taps_of(&C, ps.X, &T);
+            double H = 0.0;
+            for (int k = 0; k < T.count; k++) H += T.W[k] * h[T.id[k]];
+            double g = 3.0 * H;
+            for (int a = 0; a < d; a++) g -= (Ucur[a] + Omcur * ps.axr[a]) * Dv[3 * m + a];
+            krb[m] += g;
+        }
+        /* the ALKS input of level t: 3 u~ + 9 s~ u - 3 p~ u - 2A div s~ = (the gather's
+         * combination, folded) + 3 (u~ - u~*) */
+        for (long id = 0; id < N; id++)
+            for (int a = 0; a < d; a++) sb[(1 + a) * N + id] += 3.0 * (ut[a * N + id] - ups[a * N + id]);
+        for (int a = 0; a < 3; a++) {
+            Xn[a] = Xt[a];
+            Un[a] = Ucur[a];
+        }
+        Thn = Tht;
+        Omn = Omcur;
+        alks_gather(&C, states + S * (t - 1), sb, sb + N, nb, upsn);
+        double *tmp = sb;
+        sb = nb;
+        nb = tmp;
+        tmp = ups;
+        ups = upsn;
+        upsn = tmp;
+    }
+    for (long m = 0; m < ND; m++) grad[m] = krb[m] * dkappa_of(P, gamma[m]);
+done:
+    work_free(&W);
+    free(kr);
+    free(krb);
+    free(states);
+    free(bodies);
+    free(sb);
+    free(nb);
+    free(ups);
+    free(upsn);
+    free(kap);
+    free(uS);
+    free(phi);
+    free(Sv);
+    free(Sk);
+    free(Rp);
+    free(ut);
+    free(h);
+    free(q);
+    free(Du);
+    free(Dv);
     return rc;
 }
 

@@ -68,6 +68,13 @@ int orc_gradient(const orc_problem *P, const double *gamma, const double *state0
 
 /* Design -> analysis-grid mapping of kappa_ref and of the rigid-body velocity at the
  * pose `body` (full-grid outputs; non-interior nodes are zero). */
+/* The paper's adjoint variant (Sec. 2.5, App. A): the continuous adjoint discretised like
+ * the forward, with N_itr fixed-point iterations of the body adjoint per time level and
+ * the sensitivity of Eq. design_sensitivity. Not the exact derivative of the discrete
+ * forward map (see lks_oracle.c). J: the objective of the forward run. */
+int orc_gradient_paper(const orc_problem *P, const double *gamma, const double *state0,
+                       const double *body0, double *grad, double *J);
+
 int orc_map_design(const orc_problem *P, const double *kappa_ref, const double *body,
                    double *kappa, double *uS);
 

@@ -5,4 +5,4 @@ from .api import (LKSFunction, LksError, Buffers, adjoint, body_step, checkpoint
                   forward, map_design, problem_struct, state_elems, workspace_bytes,
                   design_filter, design_filter_adjoint, filter_struct, filter_workspace_bytes,
                   cyclic_sector_points, design_cyclic_expand, design_cyclic_collect, mma_update,
-                  mma_workspace_bytes, optimize, volume_constraint, coupling)
+                  mma_workspace_bytes, optimize, volume_constraint, coupling, adjoint_paper)

@@ -73,12 +73,13 @@ def workspace_bytes(pb, adjoint: bool, precision="fp32") -> int:
 class Buffers:
     """Device buffers for repeated calls on one problem (no allocation per call)."""
 
-    def __init__(self, pb, precision="fp32", adjoint=True):
+    def __init__(self, pb, precision="fp32", adjoint=True, paper=False):
         L = _lib.load()
         self.pb = pb
         self.precision = precision
         self.dtype = DTYPES[precision]
-        self.s = problem_struct(pb, precision)
+        # paper: size the adjoint workspace for the paper's adjoint variant as well
+        self.s = problem_struct(pb, precision, _lib.FLAG_PAPER_ADJOINT if paper else 0)
         nbytes = int(L.lks_workspace_bytes(C.byref(self.s), int(adjoint)))
         if nbytes == 0:
             raise LksError(_lib.EINVAL, L.lks_last_error().decode())
@@ -146,6 +147,12 @@ def coupling(pb, gamma, body, precision="fp32"):
     K = torch.empty(4, dtype=torch.float64, device="cuda")
     _lib.check(L.lks_coupling(C.byref(s), _p(g), _p(bd), _p(K), _p(work), work.numel(), _stream()))
     return K
+
+
+def adjoint_paper(pb, gamma, buffers: Buffers, seed: float = 1.0, precision="fp32", flags: int = 0):
+    """The paper's adjoint variant (Sec. 2.5) after forward(..., store_ckpt=True) with
+    Buffers(..., paper=True): an approximation of dJ/dgamma (float64)."""
+    return adjoint(pb, gamma, buffers, seed=seed, precision=precision, flags=flags | _lib.FLAG_PAPER_ADJOINT)
 
 
 def map_design(pb, kappa_ref, body, precision="fp32"):

@@ -583,7 +583,8 @@ template <typename T, bool SP>
 __global__ __launch_bounds__(512) void k_adjgather2d(Grid g, Bc bc, T A, const T *__restrict__ ab,
                                                      const T *__restrict__ ustb, const double *__restrict__ Bprev,
                                                      Design D, int has_box, const T *__restrict__ sprev,
-                                                     T *__restrict__ out, unsigned long long *ts) {
+                                                     T *__restrict__ out, unsigned long long *ts,
+                                                     T *__restrict__ ups) {
     constexpr int RX = G2_TX + 6, RY = G2_TY + 6;
     constexpr int MX = G2_TX + 4, MY = G2_TY + 4;
     __shared__ T sP[RY][RX], sU[RY][RX], sV[RY][RX];
@@ -668,6 +669,10 @@ __global__ __launch_bounds__(512) void k_adjgather2d(Grid g, Bc bc, T A, const T
         out[id] = T(3) * pi;
         out[N + id] = ox;
         out[2 * N + id] = oy;
+        if (ups) {  // the moment ups itself (the paper's u~*), for its adjoint variant
+            ups[id] = mux[my][mx];
+            ups[N + id] = muy[my][mx];
+        }
     }
     if (SP) span_end(ts);
 }
@@ -799,7 +804,7 @@ template <typename T> struct A3 {
 template <typename T, bool SP>
 __global__ __launch_bounds__(A3<T>::NT, sizeof(T) == 4 ? 4 : 2) void k_adjgather3d(
     Grid g, T A, int ZC, int offx, int offy, const T *__restrict__ ab, const T *__restrict__ sprev,
-    T *__restrict__ out, unsigned long long *ts) {
+    T *__restrict__ out, unsigned long long *ts, T *__restrict__ ups) {
     using G = A3<T>;
     constexpr int TX = G::TX, TY = G::TY, WX = G::WX, WY = G::WY;
     __shared__ T gr[3][4][WY][WX];  // g = (p*bar / 3, u*bar) of planes s-1, s, s+1
@@ -980,6 +985,12 @@ __global__ __launch_bounds__(A3<T>::NT, sizeof(T) == 4 ? 4 : 2) void k_adjgather
             part[2][1] = o0;
             part[2][2] = o1;
             part[2][3] = o2;
+            if (ups) {  // the moment ups itself (the paper's u~*), for its adjoint variant
+                const long long id = oid + (long long)s * plane;
+                ups[id] = up[0];
+                ups[N + id] = up[1];
+                ups[2 * N + id] = up[2];
+            }
         }
         const int zo = s - 2;
         if (outcol && zo >= z0 && zo < z1) {

@@ -25,6 +25,7 @@
 #include "../../include/lks.h"
 #include "body.h"
 #include "cyclic.h"
+#include "f2.h"
 #include "filter.h"
 #include "mma.h"
 
@@ -191,6 +192,7 @@ struct Ctx {
     int tt2 = 0;         // 2D fused iteration: design tile edge (0: separate kernels)
     unsigned ntile = 0;  // its number of tiles
     bool tile3 = false;  // 3D R1 over 8^3 design tiles (nblk = tiles)
+    bool paper = false;  // lks_adjoint computes the paper's adjoint variant (f2.h)
 };
 
 constexpr int MARGIN = 2;
@@ -315,6 +317,7 @@ int make_ctx(const lks_problem_t *P, Ctx &c) {
     c.bp.inertia = P->inertia;
     c.bp.dof = P->dof_mask & (c.dim == 2 ? (LKS_DOF_TX | LKS_DOF_TY | LKS_DOF_ROT) : 15);
     c.K = c.has_body ? P->n_itr : 1;
+    c.paper = (P->flags & LKS_FLAG_PAPER_ADJOINT) != 0;
     if (P->n_steps < 0) return fail(LKS_EINVAL, "n_steps < 0");
     c.NT = P->n_steps;
     c.Kc = P->ckpt_every;
@@ -358,6 +361,8 @@ struct Layout {
     // 2D adjoint: kappa^(k), u^S^(k), u^(k) on the box for every step of a segment (two
     // buffers like the segments), pre_n bytes each; 0 in 3D
     size_t pre, pre_n;
+    // the paper's adjoint variant: box fields, h/q, u~* of two levels, partials, record
+    size_t f2F, f2hq, f2ups, f2pn, f2pd, f2rec;
     size_t total;
 };
 
@@ -424,6 +429,14 @@ Layout layout(const Ctx &c, bool adjoint) {
         L.part1 = take((size_t)c.nblk * 8 * 8);
         L.part3 = take((size_t)c.nblk * 8 * 8);
         L.rec = take(2 * AR_SIZE * 8);
+        if (c.paper && c.has_body) {
+            L.f2F = take((size_t)F2F_N * bN * e);
+            L.f2hq = take(4 * bN * e);
+            L.f2ups = take(2 * d * (size_t)c.g.N * e);
+            L.f2pn = take((size_t)blocks((long long)bN, F2_NT) * F2_NNODE * 8);
+            L.f2pd = take((size_t)blocks((long long)ND, F2_NT) * F2_NDES * 8);
+            L.f2rec = take(F2_REC * 8);
+        }
     }
     L.total = o;
     return L;
@@ -730,7 +743,7 @@ template <typename T> struct Run {
         return rec;
     }
     // In 3D the cotangent ab is consumed: k_adj_fold3d and k_adj_clear3d prepare it in place.
-    void adj_gather(T *ab, const T *ustb, const double *Bprev, const T *sprev, T *out) const {
+    void adj_gather(T *ab, const T *ustb, const double *Bprev, const T *sprev, T *out, T *ups = nullptr) const {
         const int hb = c.has_body ? 1 : 0;
         pf->run_span(LKS_K_ADJ_GATHER, c.dim == 2 ? LKS_K_ADJ_GATHER_SPAN : -1,
                      [&](hipEvent_t e0, hipEvent_t e1, unsigned long long *ts) {
@@ -738,10 +751,10 @@ template <typename T> struct Run {
                 dim3 grid(blocks(c.g.n[0], G2_TX), blocks(c.g.n[1], G2_TY));
                 if (ts)
                     hipLaunchKernelGGL((k_adjgather2d<T, true>), grid, dim3(G2_TX, G2_TY), 0, st, c.g, c.bc, T(c.A),
-                                       ab, ustb, Bprev, c.D, hb, sprev, out, ts);
+                                       ab, ustb, Bprev, c.D, hb, sprev, out, ts, ups);
                 else
                     hipExtLaunchKernelGGL((k_adjgather2d<T, false>), grid, dim3(G2_TX, G2_TY), 0, st, e0, e1, 0,
-                                          c.g, c.bc, T(c.A), ab, ustb, Bprev, c.D, hb, sprev, out, ts);
+                                          c.g, c.bc, T(c.A), ab, ustb, Bprev, c.D, hb, sprev, out, ts, ups);
             } else {
                 static const long long res = resident_blocks(k_adjgather3d<T, false>, A3<T>::NT);
                 // shift the tiles of a non-periodic axis by one node where a tile
@@ -765,8 +778,36 @@ template <typename T> struct Run {
                     es = nullptr;
                 }
                 hipExtLaunchKernelGGL((k_adjgather3d<T, false>), grid, dim3(A3<T>::TX, A3<T>::TY), 0, st, es, e1, 0,
-                                      c.g, T(c.A), zc, offx, offy, (const T *)ab, sprev, out, ts);
+                                      c.g, T(c.A), zc, offx, offy, (const T *)ab, sprev, out, ts, ups);
             }
+        });
+    }
+    // The paper's adjoint variant at the time level of step j (f2.h): Bk the step's
+    // records (box from B(t-1), pose B(t) = its last), state the forward state at t, ab
+    // the adjoint at t (for the boundary fold), ups its moment u~*; writes the box input
+    // ustb of the next ALKS step and adds the level's sensitivity to krb.
+    void f2_level(const double *Bk, const T *state, const T *ab, const T *ups, T *ustb, const T *krT,
+                  const double *krD, double *krb, const Layout &L, void *w, double seed, int obj) const {
+        const double *B = Bk + (size_t)c.K * B_REC;
+        T *F = at<T>(w, L.f2F), *hq = at<T>(w, L.f2hq);
+        double *pn = at<double>(w, L.f2pn), *pd = at<double>(w, L.f2pd), *rec = at<double>(w, L.f2rec);
+        const unsigned nbb = blocks(c.D.boxN, F2_NT), nbd = blocks(c.D.ND, F2_NT);
+        dispatch(c, [&](auto dm, auto rt) {
+            constexpr int DIM = decltype(dm)::value;
+            constexpr bool ROT = decltype(rt)::value;
+            hipLaunchKernelGGL((k_f2_fields<DIM, T, ROT>), dim3(nbb), dim3(F2_NT), 0, st, c.g, c.D, Bk, B, krT, state,
+                               F, rec);
+            for (int it = 0; it < c.K; it++) {
+                const int last = it == c.K - 1;
+                hipLaunchKernelGGL((k_f2_node<DIM, T>), dim3(nbb), dim3(F2_NT), 0, st, c.g, c.bc, c.D, Bk, B,
+                                   (const T *)F, ups, (const double *)rec, hq, pn, last, ab, ustb);
+                hipLaunchKernelGGL((k_f2_design<DIM, T>), dim3(nbd), dim3(F2_NT), 0, st, c.g, c.D, Bk, B, krD,
+                                   (const T *)F, (const T *)hq, (const double *)rec, pd, 0, krb);
+                hipLaunchKernelGGL((k_f2_update<DIM>), dim3(1), dim3(1024), 0, st, c.bp, obj, seed,
+                                   (const double *)pn, nbb, (const double *)pd, nbd, rec, last);
+            }
+            hipLaunchKernelGGL((k_f2_design<DIM, T>), dim3(nbd), dim3(F2_NT), 0, st, c.g, c.D, Bk, B, krD,
+                               (const T *)F, (const T *)hq, (const double *)rec, pd, 1, krb);
         });
     }
     void kappa_ref(const T *gamma, T *krT, double *krD) const {
@@ -1010,6 +1051,15 @@ int adjoint_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, const vo
     HIP_TRY(hipEventRecord(evEntry, st));
     HIP_TRY(hipStreamWaitEvent(side.s, evEntry, 0));
     T *ab_cur = ab, *ab_nxt = ab + S;
+    // the paper's variant: its moment u~* of the current and next level (zero at N_t),
+    // and its body-adjoint record (zero at level N_t + 1)
+    T *ups_cur = nullptr, *ups_nxt = nullptr;
+    if (c.paper && c.has_body) {
+        ups_cur = at<T>(work, L.f2ups);
+        ups_nxt = ups_cur + (size_t)c.dim * c.g.N;
+        HIP_TRY(hipMemsetAsync(ups_cur, 0, (size_t)c.dim * c.g.N * sizeof(T), st));
+        hipLaunchKernelGGL(k_zero32, dim3(1), dim3(64), 0, st, at<unsigned>(work, L.f2rec), 2 * F2_REC);
+    }
     const int ncp = (int)ckpt_count(c);
     // recompute segment ci into buffer ci & 1, keeping every state, footprint u* and iterate
     auto recompute = [&](int ci) -> int {
@@ -1058,19 +1108,25 @@ int adjoint_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, const vo
         for (int j = len; j >= 1; j--) {
             pf.sample = (t0 + j - 1) % every == 0;
             const double *Bk = Bseg + (size_t)j * recN;
-            if (c.has_body)
+            if (c.has_body && c.paper)
+                R.f2_level(Bk, seg + (size_t)j * S, ab_cur, ups_cur, ustb, krT, krD, krb, L, work, seed,
+                           P->objective);
+            else if (c.has_body)
                 R.body_rev(Bk, ustar_seg + (size_t)(j - 1) * fp, ab_cur, krT, krD, L, work,
                            L.pre_n ? preb(b) + (size_t)(j - 1) * pre_elems(c) : nullptr);
-            R.adj_gather(ab_cur, ustb, Bk, seg + (size_t)(j - 1) * S, ab_nxt);
+            R.adj_gather(ab_cur, ustb, Bk, seg + (size_t)(j - 1) * S, ab_nxt, ups_nxt);
             T *tmp = ab_cur;
             ab_cur = ab_nxt;
             ab_nxt = tmp;
+            tmp = ups_cur;
+            ups_cur = ups_nxt;
+            ups_nxt = tmp;
         }
         HIP_TRY(hipEventRecord(evRev[b], st));
         HIP_TRY(hipGetLastError());
     }
     if (c.has_body) {
-        rec = R.rev_flush(L, work);
+        if (!c.paper) rec = R.rev_flush(L, work);
         hipLaunchKernelGGL(k_grad_final<T>, dim3(blocks(c.D.ND, 256)), dim3(256), 0, st, c.D.ND, c.bp.kmax, c.bp.q,
                            gamma, krb, grad, rec, P->objective, seed, dbody0);
     }
@@ -1346,6 +1402,9 @@ int lks_adjoint(const lks_problem_t *P, const void *gamma, const void *ckpt, siz
     if (ckpt_bytes_ < ckpt_bytes(c)) return fail(LKS_ENOSPACE, "checkpoint buffer too small");
     if (work_bytes < layout(c, true).total) return fail(LKS_ENOSPACE, "work buffer too small");
     if (!std::isfinite(seed)) return fail(LKS_EINVAL, "seed not finite");
+    if (c.paper && !c.has_body) return fail(LKS_EINVAL, "LKS_FLAG_PAPER_ADJOINT needs a design grid");
+    if (c.paper && (dstate_T || dbody_T || dstate0 || dbody0))
+        return fail(LKS_EINVAL, "LKS_FLAG_PAPER_ADJOINT takes no terminal cotangents and returns no initial ones");
     if (dstate_T && overlap(dstate_T, (size_t)c.S * c.elt, work, work_bytes))
         return fail(LKS_EINVAL, "dstate_T must not overlap work");
     hipStream_t st = (hipStream_t)stream;
