@@ -43,6 +43,11 @@ DESCRIPTIONS = {
 }
 
 
+# Kernels of the fluid <-> body iterations: per launch the method must read kappa_ref once
+# per design point (4 B); the footprint fields they build and read stay in LDS / L2.
+BODY_KERNELS = ("iter", "iter_final", "spread", "interp", "adj_recompute", "adj_r1", "adj_r2", "adj_r3")
+
+
 def alg_bytes_per_launch(kernel, pb, elt):
     """Bytes the method must move per launch (each field read and written once)."""
     d, N = pb.dim, pb.N
@@ -50,7 +55,31 @@ def alg_bytes_per_launch(kernel, pb, elt):
         return 2 * (d + 1) * N * elt
     if kernel == "adj_gather":    # read pbar, ubar and forward u(t-1); write pbar, ubar
         return (3 * d + 2) * N * elt
+    if kernel in BODY_KERNELS:    # kappa_ref, one read per design point
+        return 4 * pb.ND
     return None
+
+
+def gradient_bytes_per_node_step(dim, elt=4):
+    """Algorithmic bytes of one gradient per node and time step: forward (read and write
+    p, u), checkpoint recompute (the forward plus storing the state), adjoint (read pbar,
+    ubar and forward u; write pbar, ubar): 92 B in 2D, 124 B in 3D (FP32)."""
+    fwd = 2 * (dim + 1) * elt
+    rec = fwd + (dim + 1) * elt
+    adj = (3 * dim + 2) * elt
+    return fwd + rec + adj
+
+
+def cpu_info():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count()
 
 
 def kernel_source_hash():
@@ -84,7 +113,10 @@ def measured_traffic(workload, kernel):
 
 def launches_per_gradient(pb):
     NT, K = pb.n_steps, pb.n_itr
-    return {"gather": 2 * NT, "bc": 2 * NT, "spread": 2 * K * NT, "interp": 2 * K * NT,
+    # 2D: the forward pass forms the boundary values inside its LKS kernel and runs the
+    # boundary launch only at checkpoints and at the end; the recompute after every step
+    nbc = NT + NT // max(pb.ckpt_every, 1) + 1 if pb.dim == 2 else 2 * NT
+    return {"gather": 2 * NT, "bc": nbc, "spread": 2 * K * NT, "interp": 2 * K * NT,
             "adj_gather": NT, "adj_recompute": NT, "adj_r1": K * NT, "adj_r2": K * NT,
             "adj_r3": K * NT, "iter": 2 * K * NT, "iter_final": 2 * NT}
 
@@ -139,46 +171,158 @@ def roofline_sweep(args):
 
     for dim in (2, 3):
         for n in SWEEP[dim]:
-            # one checkpoint segment: the adjoint's recompute then runs alone, not beside
-            # the reverse sweep, so every sampled kernel has the GPU to itself
-            if dim == 2:
-                pb = W.channel2d(n[0], n[1], 0.05, 0.128, n_steps=16, ckpt_every=16, name=f"channel {n[0]}x{n[1]}")
-            else:
-                pb = W.duct3d(*n, 0.04, 0.01707, n_steps=8, ckpt_every=8, name="duct " + "x".join(map(str, n)))
-            s0 = torch.tensor(W.initial_state(pb), dtype=torch.float32, device="cuda")
-            b0 = torch.zeros(12, dtype=torch.float64, device="cuda")
-            bufs = lks.Buffers(pb, "fp32", adjoint=True)
-
-            def grad_step():
-                _, _, _, B = lks.forward(pb, None, s0, b0, "fp32", buffers=bufs, flags=_lib.FLAG_PROFILE)
-                lks.adjoint(pb, None, B, precision="fp32", flags=_lib.FLAG_PROFILE)
-
-            grad_step()
-            torch.cuda.synchronize()
-            _lib.profile_reset()
-            t0 = time.perf_counter()
-            for _ in range(max(args.steps, 1)):
-                grad_step()
-            torch.cuda.synchronize()
-            wall = (time.perf_counter() - t0) / max(args.steps, 1)
-            prof = _lib.profile_read()
-            line = {"sweep": "body-free roofline", "workload": pb.name, "dim": dim, "nodes": pb.N,
-                    "dtype": "f32", "gradient_MLUPS": round(pb.N * pb.n_steps / wall / 1e6, 1)}
-            for k in ("gather", "adj_gather"):
-                ms, cnt = prof[k]
-                us = ms / cnt * 1e3
-                by = alg_bytes_per_launch(k, pb, 4)
-                line[k] = {"avg_launch_us": round(us, 2), "bytes_per_launch": by,
-                           "achieved_GBs": round(by / us / 1e3, 1), "frac": round(by / us / 1e3 / HBM_PEAK_GBS, 4),
-                           "samples": cnt}
-                sms, scnt = prof.get(k + "_span", (0.0, 0))
-                if scnt:
-                    sus = sms / scnt * 1e3
-                    line[k].update({"kernel_span_us": round(sus, 2), "achieved_GBs_span": round(by / sus / 1e3, 1)})
-            print(json.dumps(line), flush=True)
-            del bufs, s0
-            torch.cuda.empty_cache()
+            print(json.dumps(sweep_point(dim, n, args.steps)), flush=True)
     print(json.dumps({"sweep": "copy", "elementwise_copy_1GiB_GBs": round(copy_bandwidth(), 1)}), flush=True)
+
+
+def sweep_point(dim, n, steps):
+    """One body-free gradient size of the roofline sweep: the LKS and adjoint LKS kernels'
+    live launch durations against their algorithmic bytes."""
+    import torch
+
+    import paper_2601_18272_amd as lks
+    import workloads as W
+    from paper_2601_18272_amd import _lib
+
+    # one checkpoint segment: the adjoint's recompute then runs alone, not beside the
+    # reverse sweep, so every sampled kernel has the GPU to itself
+    if dim == 2:
+        pb = W.channel2d(n[0], n[1], 0.05, 0.128, n_steps=16, ckpt_every=16, name=f"channel {n[0]}x{n[1]}")
+    else:
+        pb = W.duct3d(*n, 0.04, 0.01707, n_steps=8, ckpt_every=8, name="duct " + "x".join(map(str, n)))
+    s0 = torch.tensor(W.initial_state(pb), dtype=torch.float32, device="cuda")
+    b0 = torch.zeros(12, dtype=torch.float64, device="cuda")
+    bufs = lks.Buffers(pb, "fp32", adjoint=True)
+
+    def grad_step():
+        _, _, _, B = lks.forward(pb, None, s0, b0, "fp32", buffers=bufs, flags=_lib.FLAG_PROFILE)
+        lks.adjoint(pb, None, B, precision="fp32", flags=_lib.FLAG_PROFILE)
+
+    grad_step()
+    torch.cuda.synchronize()
+    _lib.profile_reset()
+    t0 = time.perf_counter()
+    for _ in range(max(steps, 1)):
+        grad_step()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / max(steps, 1)
+    prof = _lib.profile_read()
+    _lib.profile_reset()
+    line = {"sweep": "body-free roofline", "workload": pb.name, "dim": dim, "nodes": pb.N,
+            "dtype": "f32", "gradient_MLUPS": round(pb.N * pb.n_steps / wall / 1e6, 1)}
+    for k in ("gather", "adj_gather"):
+        ms, cnt = prof[k]
+        us = ms / cnt * 1e3
+        by = alg_bytes_per_launch(k, pb, 4)
+        line[k] = {"avg_launch_us": round(us, 2), "bytes_per_launch": by,
+                   "achieved_GBs": round(by / us / 1e3, 1), "frac": round(by / us / 1e3 / HBM_PEAK_GBS, 4),
+                   "samples": cnt}
+        sms, scnt = prof.get(k + "_span", (0.0, 0))
+        if scnt:
+            sus = sms / scnt * 1e3
+            line[k].update({"kernel_span_us": round(sus, 2), "achieved_GBs_span": round(by / sus / 1e3, 1)})
+    del bufs, s0
+    torch.cuda.empty_cache()
+    return line
+
+
+def config5_measure():
+    """Config 5 in full: one 10000-step FP32 gradient (forward with checkpoints every 500 +
+    adjoint), timed, with live kernel durations on sampled steps; then the FP64 gradient of
+    the same workload (checkpoints every 250, untimed) for the FP32 errors per result."""
+    import torch
+
+    import paper_2601_18272_amd as lks
+    import workloads as W
+    from paper_2601_18272_amd import _lib
+
+    pb = W.config("config5")
+    g = torch.tensor(W.design(pb), dtype=torch.float32, device="cuda")
+    s0 = torch.tensor(W.initial_state(pb), dtype=torch.float32, device="cuda")
+    b0 = torch.tensor(W.initial_body(pb), dtype=torch.float64, device="cuda")
+    bufs = lks.Buffers(pb, "fp32", adjoint=True)
+    _lib.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st32, bd32, J32, B = lks.forward(pb, g, s0, b0, "fp32", buffers=bufs, flags=_lib.FLAG_PROFILE)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t0
+    prof_f = _lib.profile_read()
+    _lib.profile_reset()
+    grad32 = lks.adjoint(pb, g, B, precision="fp32", flags=_lib.FLAG_PROFILE)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof_a = _lib.profile_read()
+    _lib.profile_reset()
+    g32, bd32 = grad32.cpu().numpy(), bd32.cpu().numpy()
+    del bufs, B, st32, grad32
+    torch.cuda.empty_cache()
+    print("# config5 fp32 gradient done", file=sys.stderr, flush=True)
+    out = {"workload": "config5: " + DESCRIPTIONS["config5"], "nodes": pb.N, "n_steps": pb.n_steps,
+           "gradient_s": round(wall, 3), "gradient_MLUPS": round(pb.N * pb.n_steps / wall / 1e6, 1),
+           "forward_s": round(tf, 3), "forward_MLUPS": round(pb.N * pb.n_steps / tf / 1e6, 1)}
+    avg = {}
+    for src in (prof_a, prof_f):  # forward kernels at their forward-pass durations
+        for k, (ms, n) in src.items():
+            if n > 0:
+                avg[k] = (ms, n)
+    lp = launches_per_gradient(pb)
+    est = {k: ms / n * lp[k] for k, (ms, n) in avg.items() if k in lp}
+    dom = max(est, key=est.get)
+    out["kernel_avg_us"] = {k: round(ms / n * 1e3, 3) for k, (ms, n) in avg.items()}
+    out["share_of_gradient_est"] = {k: round(v / sum(est.values()), 3) for k, v in est.items()}
+    for name in dict.fromkeys([dom, "gather", "adj_gather"]):
+        by = alg_bytes_per_launch(name, pb, 4)
+        ms, n = avg[name]
+        us = ms / n * 1e3
+        out[f"roofline_{name}"] = {"bound": "hbm", "bytes_per_launch": by, "avg_launch_us": round(us, 2),
+                                   "achieved": round(by / us / 1e3, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                   "frac": round(by / us / 1e3 / HBM_PEAK_GBS, 4),
+                                   "traffic": measured_traffic("config5", name), "samples": n}
+    out["dominant_kernel"] = dom
+    gb = gradient_bytes_per_node_step(3) * pb.N * pb.n_steps
+    out["gradient_pass"] = {"algorithmic_bytes": gb, "GBs": round(gb / wall / 1e9, 1),
+                            "frac": round(gb / wall / 1e9 / HBM_PEAK_GBS, 4)}
+    pb64 = pb.replace(ckpt_every=250)
+    bufs64 = lks.Buffers(pb64, "fp64", adjoint=True)
+    _, bd64, J64, B64 = lks.forward(pb64, g.double(), s0.double(), b0, "fp64", buffers=bufs64)
+    g64 = lks.adjoint(pb64, g.double(), B64, precision="fp64").cpu().numpy()
+    bd64 = bd64.cpu().numpy()
+    del bufs64, B64
+    torch.cuda.empty_cache()
+    print("# config5 fp64 reference done", file=sys.stderr, flush=True)
+    j32, j64 = J32.item(), J64.item()
+    x0 = float(W.initial_body(pb)[0])
+    out["fp32_vs_fp64"] = {
+        "theta_J_fp32": j32, "theta_J_fp64": j64, "J_rel_err": abs(j32 - j64) / max(abs(j64), 1e-300),
+        "x_displacement_fp32": float(bd32[0] - x0), "x_displacement_fp64": float(bd64[0] - x0),
+        "x_displacement_rel_err": abs(bd32[0] - bd64[0]) / max(abs(bd64[0] - x0), 1e-300),
+        "grad_rel_l2": float(np.linalg.norm(g32 - g64) / max(np.linalg.norm(g64), 1e-300)),
+        "grad_max_rel": float(np.abs(g32 - g64).max() / max(np.abs(g64).max(), 1e-300))}
+    return out
+
+
+def paper_adjoint_measure(pb, g, s0, b0, grad_exact):
+    """The paper's adjoint variant (LKS_FLAG_PAPER_ADJOINT) on the workload: one FP32
+    gradient (forward with checkpoints + the variant's sweep), timed, and its relative L2
+    difference from the exact adjoint's gradient of the timed run."""
+    import torch
+
+    import paper_2601_18272_amd as lks
+
+    bufs = lks.Buffers(pb, "fp32", adjoint=True, paper=True)
+    lks.forward(pb, g, s0, b0, "fp32", buffers=bufs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, _, B = lks.forward(pb, g, s0, b0, "fp32", buffers=bufs)
+    gp = lks.adjoint_paper(pb, g, B, precision="fp32")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gp = gp.cpu().numpy()
+    del bufs
+    torch.cuda.empty_cache()
+    return {"gradient_s": round(wall, 3), "gradient_MLUPS": round(pb.N * pb.n_steps / wall / 1e6, 1),
+            "rel_l2_vs_exact_adjoint": float(np.linalg.norm(gp - grad_exact) / np.linalg.norm(grad_exact))}
 
 
 def ball_taps(dim, R):
@@ -326,9 +470,16 @@ def main():
     ap.add_argument("--sweep", action="store_true",
                     help="body-free roofline sweep of the LKS and adjoint LKS kernels over grid sizes "
                          "up to > 1 GB per step (one JSON line per size instead of the headline)")
+    ap.add_argument("--only-gradient", action="store_true",
+                    help="time the gradient steps only (no extra measurements, no FP64 or CPU runs): "
+                         "for profiler runs")
+    ap.add_argument("--no-config5", action="store_true", help="skip the full config 5 gradient in extra")
+    ap.add_argument("--no-sweep-points", action="store_true", help="skip the largest sweep points in extra")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB device copy (reference for HBM traffic counters)")
     args = ap.parse_args()
+    if args.only_gradient:
+        args.no_cpu = args.no_fp64 = args.no_config5 = args.no_sweep_points = True
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (the grid would be "
               "cut into x-slabs, one per GPU, with a two-layer halo exchange per step and a "
@@ -408,27 +559,33 @@ def main():
     lp = launches_per_gradient(pb)
     est = {k: (ms / n) * lp[k] for k, (ms, n) in prof.items() if n > 0 and k in lp}
     dom = max(est, key=est.get)
-    roof = None
-    hbm_kernels = {k: v for k, v in est.items() if alg_bytes_per_launch(k, pb, elt)}
-    for name in [dom] + sorted(hbm_kernels, key=hbm_kernels.get, reverse=True):
+
+    def roofline_of(name):
         by = alg_bytes_per_launch(name, pb, elt)
-        if by is None:
-            continue
         ms, n = prof[name]
         avg_s = ms / n / 1e3
         ach = by / avg_s / 1e9
-        roof = {"bound": "hbm", "kernel": name, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(pb.name, name),
-                "bytes_per_launch": by, "avg_launch_us": round(avg_s * 1e6, 3),
-                "samples": n, "dominant_kernel": dom,
-                "share_of_gradient_est": {k: round(v / sum(est.values()), 3) for k, v in est.items()}}
+        r = {"bound": "hbm", "kernel": name, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+             "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 6),
+             "traffic": measured_traffic(pb.name, name),
+             "bytes_per_launch": by, "avg_launch_us": round(avg_s * 1e6, 3), "samples": n}
         span = prof.get(name + "_span")
         if span and span[1] > 0:
             span_s = span[0] / span[1] / 1e3
-            roof["kernel_span_us"] = round(span_s * 1e6, 3)
-            roof["achieved_kernel_span"] = round(by / span_s / 1e9, 1)
-        break
+            r["kernel_span_us"] = round(span_s * 1e6, 3)
+            r["achieved_kernel_span"] = round(by / span_s / 1e9, 1)
+        return r
+
+    # the dominant kernel (largest estimated share of the gradient) against the HBM
+    # roofline with its algorithmic bytes; the LKS kernel beside it
+    roof = roofline_of(dom)
+    roof["dominant_kernel"] = dom
+    roof["share_of_gradient_est"] = {k: round(v / sum(est.values()), 3) for k, v in est.items()}
+    gb = gradient_bytes_per_node_step(pb.dim) * pb.N * pb.n_steps
+    roof["gradient_pass"] = {"algorithmic_bytes_per_node_step": gradient_bytes_per_node_step(pb.dim),
+                             "GBs": round(gb / (wall / args.steps) / 1e9, 1),
+                             "frac": round(gb / (wall / args.steps) / 1e9 / HBM_PEAK_GBS, 4)}
+    roof_lks = roofline_of("gather") if "gather" in prof else None
 
     if args.calibrate_copy:
         n = 64 * 1024 * 1024
@@ -440,9 +597,15 @@ def main():
         del src, dst
         print("# calibration copy done (2 x 256 MiB)", file=sys.stderr, flush=True)
 
-    extra = {"ms_per_step_gpu_events": round(gpu_ms / args.steps, 3),
+    extra = {"ms_per_step_gpu_events": round(gpu_ms / args.steps, 3), "roofline_lks_kernel": roof_lks,
              "kernel_avg_us": {"forward_pass": {k: round(v * 1e3, 3) for k, v in avg_f.items()},
                                "adjoint_pass": {k: round(v * 1e3, 3) for k, v in avg_a.items()}}}
+
+    if args.only_gradient:
+        print(json.dumps({"metric": METRIC, "value": round(value, 2), "unit": "MLUPS", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 2),
+                          "workload": pb.name, "roofline": roof, "extra": extra}), flush=True)
+        return
 
     # forward pass alone (with its checkpoints), outside the timed region
     torch.cuda.synchronize()
@@ -456,6 +619,8 @@ def main():
     extra["cyclic_design"] = cyclic_measure(pb)
     extra["mma_update"] = mma_measure(pb)
     print("# design filter, cyclic design and MMA update done", file=sys.stderr, flush=True)
+    extra["paper_adjoint"] = paper_adjoint_measure(pb, g, s0, b0, grad32.cpu().numpy())
+    print("# paper's adjoint variant done", file=sys.stderr, flush=True)
 
     if not args.no_fp64:
         bufs64 = lks.Buffers(pb, "fp64", adjoint=True)
@@ -475,13 +640,23 @@ def main():
         del bufs64
         print("# fp64 reference done", file=sys.stderr, flush=True)
 
+    del bufs
+    torch.cuda.empty_cache()
+    if not args.no_config5:
+        extra["config5"] = config5_measure()
+    if not args.no_sweep_points:
+        extra["sweep_largest"] = [sweep_point(2, SWEEP[2][-1], 2), sweep_point(3, SWEEP[3][-1], 2)]
+        print("# largest sweep points done", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu:
         spb, Jo, go, dt = run_cpu_baseline(pb, args.cpu_steps)
+        model, ncpu = cpu_info()
         cpu = {"value": round(spb.N * spb.n_steps / dt / 1e6, 4), "unit": "MLUPS", "cores": 1,
                "kind": "oracle",
                "sample": f"{pb.name} truncated to its first {spb.n_steps} time steps "
-                         f"(forward + exact adjoint, serial FP64, {dt:.1f} s)"}
+                         f"(forward + exact adjoint, serial FP64, {dt:.1f} s, one core of {ncpu} x {model})",
+               "cpu_model": model, "nproc": ncpu}
         # parity of the GPU FP32 path on the same full-grid sample
         sb = lks.Buffers(spb, "fp32", adjoint=True)
         _, _, Js, Bs = lks.forward(spb, g, s0, b0, "fp32", buffers=sb)

@@ -610,7 +610,7 @@ template <typename T, bool ROT>
 __global__ __launch_bounds__(256) void k_spread_fwd_rows(Grid g, Design D, const double *__restrict__ Bk, int k,
                                                          const T *__restrict__ K1, T *__restrict__ u,
                                                          T *__restrict__ ustar) {
-    const int r = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int r = (int)xcd_block() * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (r >= BoxRow::count(D)) return;  // whole waves
     BoxRow br;
     br.init(D, r);
@@ -651,7 +651,7 @@ template <int DIM, typename T, bool ROT, int LPN>
 __global__ __launch_bounds__(256) void k_spread_fwd(Grid g, Design D, const double *__restrict__ Bk, int k,
                                                     const T *__restrict__ krT, const T *__restrict__ K1,
                                                     T *__restrict__ u, T *__restrict__ ustar) {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long t = (long long)xcd_block() * blockDim.x + threadIdx.x;
     const long long l = t / LPN;
     const int q = (int)(t % LPN);
     if (l >= D.boxN) return;
@@ -750,7 +750,8 @@ template <typename V> __device__ __forceinline__ V sel4(const V v[4], int i) {
 // ------------------------------------------------------------------ block reduction
 // Thread j < NV stores the block's sum of v[j] (plus its `add`, when given).
 template <int NV, int NTHR>
-__device__ __forceinline__ void block_reduce_store(double v[NV], double *__restrict__ out, const double *add = nullptr) {
+__device__ __forceinline__ void block_reduce_store(double v[NV], double *__restrict__ out, const double *add = nullptr,
+                                                   long long slot = -1) {
     __shared__ double red[NV][NTHR / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -763,7 +764,7 @@ __device__ __forceinline__ void block_reduce_store(double v[NV], double *__restr
         double s = 0.0;
 #pragma unroll
         for (int w = 0; w < NTHR / 64; w++) s += red[threadIdx.x][w];
-        out[(long long)blockIdx.x * NV + threadIdx.x] = add ? *add + s : s;
+        out[(slot < 0 ? (long long)blockIdx.x : slot) * NV + threadIdx.x] = add ? *add + s : s;
     }
 }
 
@@ -856,7 +857,7 @@ struct Tile3 {
 __device__ __forceinline__ bool tile3_setup(const Grid &g, const Design &D, const double *B, Tile3 &t) {
     constexpr int E = Tile3::E;
     const int ntx = (D.nd[0] + E - 1) / E, nty = (D.nd[1] + E - 1) / E;
-    const int b = (int)blockIdx.x;
+    const int b = (int)xcd_block();
     const int tx = b % ntx, ty = (b / ntx) % nty, tz = b / (ntx * nty);
     const int tid = (int)threadIdx.x;
     const int i = tx * E + tid % E, j = ty * E + (tid / E) % E, kz = tz * E + tid / (E * E);
@@ -953,7 +954,8 @@ __global__ __launch_bounds__(Dblk<DIM>::v) void k_interp_force(Grid g, Design D,
                                                        unsigned *__restrict__ counter, int *__restrict__ flag,
                                                        int last) {
     const long long N = g.N;
-    const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned lb = xcd_block();
+    const long long m = (long long)lb * blockDim.x + threadIdx.x;
     const double *B = Bk + k * B_REC;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     if (m < D.ND) {
@@ -993,7 +995,7 @@ __global__ __launch_bounds__(Dblk<DIM>::v) void k_interp_force(Grid g, Design D,
         }
         v[3] = kr * (pick3(P.r, D.pi) * pick3(Dv, D.pj) - pick3(P.r, D.pj) * pick3(Dv, D.pi));
     }
-    block_reduce_store<4, Dblk<DIM>::v>(v, part);
+    block_reduce_store<4, Dblk<DIM>::v>(v, part, nullptr, lb);
     if (!last) return;
     if (!last_block(counter)) return;
     interp_finish<DIM, Dblk<DIM>::v>(D, bp, Bk, k, K, Bnext0, part, gridDim.x, flag);
@@ -1381,10 +1383,11 @@ __global__ __launch_bounds__(256) void k_adj_recompute(Grid g, Design D, const d
                                                        const T *__restrict__ krT, const T *__restrict__ K1,
                                                        const T *__restrict__ ustar, T *__restrict__ kapk,
                                                        T *__restrict__ usk, T *__restrict__ uk) {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned lb = xcd_block();
+    const long long t = (long long)(lb % gridDim.x) * blockDim.x + threadIdx.x;
     const long long l = t / LPN;
     const int q = (int)(t % LPN);
-    const int k = blockIdx.y;
+    const int k = (int)(lb / gridDim.x);
     if (l >= D.boxN) return;
     const long long bN = D.boxN;
     int o[3], x[3];
@@ -1415,8 +1418,9 @@ __global__ __launch_bounds__(256) void k_adj_recompute_rows(Grid g, Design D, co
                                                             const T *__restrict__ K1, const T *__restrict__ ustar,
                                                             T *__restrict__ kapk, T *__restrict__ usk,
                                                             T *__restrict__ uk) {
-    const int r = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int k = blockIdx.y;
+    const unsigned lb = xcd_block();
+    const int r = (int)(lb % gridDim.x) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int k = (int)(lb / gridDim.x);
     if (r >= BoxRow::count(D)) return;  // whole waves
     BoxRow br;
     br.init(D, r);
@@ -1562,7 +1566,7 @@ __global__ __launch_bounds__(R1blk<DIM>::v) void k_adj_r1(Grid g, Design D, Body
         m = t.m;
         own = t.own;
     } else {
-        m = (long long)blockIdx.x * R1blk<DIM>::pts + threadIdx.x;
+        m = (long long)xcd_block() * R1blk<DIM>::pts + threadIdx.x;
         own = threadIdx.x < R1blk<DIM>::pts && m < D.ND;
     }
     // interpolation of u^(k) at the point (independent of the record)
@@ -1671,7 +1675,7 @@ __global__ __launch_bounds__(R1blk<DIM>::v) void k_adj_r1(Grid g, Design D, Body
         for (int e = 0; e < DIM; e++) Xb[e] = (double)xb[e];
         pose_rev(D, B, P, Xb, USb, rb, v);
     }
-    block_reduce_store<8, R1blk<DIM>::v>(v, part);
+    block_reduce_store<8, R1blk<DIM>::v>(v, part, nullptr, xcd_block());
 }
 
 // R2: box nodes. u^(k) cotangent = (k = last: the step's velocity cotangent, with the
@@ -1683,7 +1687,7 @@ __global__ __launch_bounds__(256) void k_adj_r2(Grid g, Bc bc, Design D, const d
                                                 const T *__restrict__ AU, const T *__restrict__ kapk,
                                                 const T *__restrict__ usk, const T *__restrict__ uk,
                                                 T *__restrict__ ustb, T *__restrict__ kb, T *__restrict__ usb) {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long t = (long long)xcd_block() * blockDim.x + threadIdx.x;
     const long long l = t / LPN;
     const int q = (int)(t % LPN);
     if (l >= D.boxN) return;
@@ -1765,11 +1769,12 @@ __global__ __launch_bounds__(Dblk<DIM>::v) void k_adj_r3(Grid g, Design D, const
                                                  const T *__restrict__ kb, const T *__restrict__ usb,
                                                  const double *__restrict__ krD, double *__restrict__ krb,
                                                  const double *__restrict__ part1, double *__restrict__ part3) {
-    const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    // R1's partial of this block, added to this block's at the end: requested first in 2D;
-    // in 3D, held across the tap loop, the early load slowed the kernel
+    const unsigned lb = xcd_block();
+    const long long m = (long long)lb * blockDim.x + threadIdx.x;
+    // R1's partial of this (logical) block, added to this block's at the end: requested
+    // first in 2D; in 3D, held across the tap loop, the early load slowed the kernel
     const bool p1t = threadIdx.x < 8;
-    double p1v = (DIM == 2 && p1t) ? part1[(long long)blockIdx.x * 8 + threadIdx.x] : 0.0;
+    double p1v = (DIM == 2 && p1t) ? part1[(long long)lb * 8 + threadIdx.x] : 0.0;
     const long long bN = D.boxN;
     const double *B = Bk + k * B_REC;
     double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -1821,8 +1826,8 @@ __global__ __launch_bounds__(Dblk<DIM>::v) void k_adj_r3(Grid g, Design D, const
         }
         pose_rev(D, B, P, Xb, USb, rb, v);
     }
-    if (DIM == 3 && p1t) p1v = part1[(long long)blockIdx.x * 8 + threadIdx.x];
-    block_reduce_store<8, Dblk<DIM>::v>(v, part3, &p1v);
+    if (DIM == 3 && p1t) p1v = part1[(long long)lb * 8 + threadIdx.x];
+    block_reduce_store<8, Dblk<DIM>::v>(v, part3, &p1v, lb);
 }
 
 // k_adj_r2 in 3D over box rows (4 waves per block, one row each).
@@ -1832,7 +1837,7 @@ __global__ __launch_bounds__(256) void k_adj_r2_rows(Grid g, Bc bc, Design D, co
                                                      const T *__restrict__ kapk, const T *__restrict__ usk,
                                                      const T *__restrict__ uk, T *__restrict__ ustb,
                                                      T *__restrict__ kb, T *__restrict__ usb) {
-    const int r = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int r = (int)xcd_block() * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (r >= BoxRow::count(D)) return;  // whole waves
     BoxRow br;
     br.init(D, r);

@@ -35,8 +35,11 @@ namespace lks {
 // ring nodes).
 constexpr int G2_TX = 64, G2_TY = 8;
 
+// With fold, the boundary nodes of sin_ are not read: their values are formed on load
+// from the interior node they copy (bc_resolve), as k_bc would have stored them, so the
+// forward step needs no separate boundary launch.
 template <typename T, bool SP>
-__global__ __launch_bounds__(512) void k_gather2d(Grid g, T A, const T *__restrict__ sin_,
+__global__ __launch_bounds__(512) void k_gather2d(Grid g, T A, Bc bc, int fold, const T *__restrict__ sin_,
                                                   T *__restrict__ sout, unsigned long long *ts) {
     constexpr int RX = G2_TX + 4, RY = G2_TY + 4;  // p, u with a 2-ring
     constexpr int FX = G2_TX + 2, FY = G2_TY + 2;  // f with a 1-ring
@@ -54,10 +57,33 @@ __global__ __launch_bounds__(512) void k_gather2d(Grid g, T A, const T *__restri
         int x = x0 + lx - 2, y = y0 + ly - 2;
         T vp = 0, vx = 0, vy = 0;
         if (wrap_coord(x, nx, g.per[0]) && wrap_coord(y, ny, g.per[1])) {
-            const long long id = (long long)x + (long long)nx * y;
+            // the node itself, or with fold for a boundary node the interior node it
+            // copies; the three loads are issued the same way for every node, the
+            // prescribed values replace them afterwards
+            int sx = x, sy = y;
+            bool pfix = false, ufix = false;
+            T pv = 0, uxv = 0, uyv = 0;
+            if (fold && ((!g.per[0] && (x == 0 || x == nx - 1)) || (!g.per[1] && (y == 0 || y == ny - 1)))) {
+                const int xx[3] = {x, y, 0};
+                BcNode r;
+                bc_resolve<2>(g, bc, xx, r);
+                sx = r.in[0];
+                sy = r.in[1];
+                pfix = r.p_fixed;
+                ufix = r.u_fixed;
+                pv = T(r.p);
+                uxv = T(r.u[0] - g.U[0]);
+                uyv = T(r.u[1] - g.U[1]);
+            }
+            const long long id = (long long)sx + (long long)nx * sy;
             vp = sin_[id];
             vx = sin_[N + id];
             vy = sin_[2 * N + id];
+            if (pfix) vp = pv;
+            if (ufix) {
+                vx = uxv;
+                vy = uyv;
+            }
         }
         sp[ly][lx] = vp;
         sux[ly][lx] = vx;

@@ -527,16 +527,18 @@ template <typename T> struct Run {
         return best;
     }
 
-    void gather(const T *in, T *out) const {
+    // fold (2D): the boundary values of `in` are formed on load (see k_gather2d)
+    void gather(const T *in, T *out, bool fold = false) const {
         if (c.dim == 2) {
             dim3 grid(blocks(c.g.n[0], G2_TX), blocks(c.g.n[1], G2_TY));
+            const int fd = fold ? 1 : 0;
             pf->run_span(LKS_K_GATHER, LKS_K_GATHER_SPAN, [&](hipEvent_t e0, hipEvent_t e1, unsigned long long *ts) {
                 if (ts)
-                    hipLaunchKernelGGL((k_gather2d<T, true>), grid, dim3(G2_TX, G2_TY), 0, st, c.g, T(c.A), in, out,
-                                       ts);
+                    hipLaunchKernelGGL((k_gather2d<T, true>), grid, dim3(G2_TX, G2_TY), 0, st, c.g, T(c.A), c.bc, fd,
+                                       in, out, ts);
                 else
                     hipExtLaunchKernelGGL((k_gather2d<T, false>), grid, dim3(G2_TX, G2_TY), 0, st, e0, e1, 0, c.g,
-                                          T(c.A), in, out, ts);
+                                          T(c.A), c.bc, fd, in, out, ts);
             });
         } else {
             static const long long res = resident_blocks(k_gather3d<T, false>, G3<T>::NT);
@@ -934,9 +936,16 @@ int forward_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, T *state
     // the fluid state is checked for divergence at every checkpoint (every 256 steps
     // without checkpoints) and at the end; the flag is read once, after the run
     const int chk = ckpt ? c.Kc : 256;
+    // 2D: the boundary values of a step are formed by the next step's LKS kernel as it
+    // loads them (k_gather2d with fold), so the state's boundary nodes are brought up to
+    // date (k_bc) only where the state is read as a whole: checkpoints, divergence
+    // checks and the end. 3D keeps the boundary launch after every step.
+    const bool fold = c.dim == 2 && c.face_total > 0;
     for (int t = 1; t <= c.NT; t++) {
         double *Bc = Bf + (size_t)((t - 1) & 1) * rec;
         double *Bn = Bf + (size_t)(t & 1) * rec;
+        const bool whole = (t > 1 && (t - 1) % chk == 0) || (ckpt && (t - 1) % c.Kc == 0);
+        if (fold && whole && t > 1) R.bcs(cur);
         if (t > 1 && (t - 1) % chk == 0) check_state(c, st, cur, flag);
         if (ckpt && (t - 1) % c.Kc == 0) {
             const size_t ci = (size_t)((t - 1) / c.Kc);
@@ -945,18 +954,19 @@ int forward_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, T *state
                                    hipMemcpyDeviceToDevice, st));
         }
         pf.sample = (t - 1) % every == 0;
-        R.gather(cur, nxt);
+        R.gather(cur, nxt, fold && t > 1);
         if (c.has_body)
             R.body_loop(nxt, Bc, Bn, krT, krD, ustar, part, counter, flag);
         else
             HIP_TRY(hipMemcpyAsync(Bn, Bc, B_REC * sizeof(double), hipMemcpyDeviceToDevice, st));
-        R.bcs(nxt);
+        if (!fold) R.bcs(nxt);
         T *tmp = cur;
         cur = nxt;
         nxt = tmp;
         if ((t & 255) == 0) HIP_TRY(hipGetLastError());
     }
     HIP_TRY(hipGetLastError());
+    if (fold && c.NT > 0) R.bcs(cur);
     check_state(c, st, cur, flag);
     if (cur != state) HIP_TRY(hipMemcpyAsync(state, cur, stateB, hipMemcpyDeviceToDevice, st));
     if (shift)
@@ -971,6 +981,30 @@ int forward_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, T *state
     }
     if (P->flags & LKS_FLAG_ASYNC) return LKS_OK;
     return check_flag(c, flag, st);
+}
+
+// Second stream of lks_adjoint (segment recompute beside the reverse sweep) and its
+// events, created on first use by each host thread on each device and kept for the
+// thread's lifetime: calls from one thread are serial, so they can share them, and calls
+// from other threads get their own. Default stream priority.
+struct SideRes {
+    hipStream_t s = nullptr;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // entry, fwd[2], rev[2]
+};
+thread_local std::vector<SideRes *> t_side;
+
+int side_resources(SideRes **out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if ((int)t_side.size() <= dev) t_side.resize(dev + 1, nullptr);
+    if (!t_side[dev]) {
+        SideRes r;
+        HIP_TRY(hipStreamCreateWithFlags(&r.s, hipStreamNonBlocking));
+        for (hipEvent_t &e : r.ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        t_side[dev] = new SideRes(r);
+    }
+    *out = t_side[dev];
+    return LKS_OK;
 }
 
 template <typename T>
@@ -1002,23 +1036,21 @@ int adjoint_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, const vo
     // sweep of the following segment runs on `st`; two segment buffers alternate, and
     // events order each recompute after the sweep that last used its buffer and each
     // sweep after its recompute.
-    struct Side {
-        hipStream_t s = nullptr;
-        hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // entry, fwd[2], rev[2]
-        ~Side() {
-            if (s) {
-                (void)hipStreamSynchronize(s);
-                (void)hipStreamDestroy(s);
-            }
-            for (hipEvent_t e : ev)
-                if (e) (void)hipEventDestroy(e);
-        }
-    } side;
-    HIP_TRY(hipStreamCreateWithFlags(&side.s, hipStreamNonBlocking));
-    for (hipEvent_t &e : side.ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    hipEvent_t evEntry = side.ev[0], *evFwd = side.ev + 1, *evRev = side.ev + 3;
+    // The stream and events are created once per host thread and device and kept (see
+    // side_resources); at exit the call waits for the second stream's work, as its own
+    // buffers are no longer needed then.
+    SideRes *sr = nullptr;
+    {
+        const int rc = side_resources(&sr);
+        if (rc != LKS_OK) return rc;
+    }
+    struct SideWait {
+        hipStream_t s;
+        ~SideWait() { (void)hipStreamSynchronize(s); }
+    } side{sr->s};
+    hipEvent_t evEntry = sr->ev[0], *evFwd = sr->ev + 1, *evRev = sr->ev + 3;
     Run<T> R{c, st, &pf};
-    Run<T> F{c, side.s, &pf};
+    Run<T> F{c, sr->s, &pf};
     F.ax = at<T>(work, L.K1f);
     R.ax = at<T>(work, L.K1r);
     T *krT = at<T>(work, L.krT);
@@ -1049,7 +1081,7 @@ int adjoint_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, const vo
     else
         hipLaunchKernelGGL(k_adj_init<3>, dim3(1), dim3(64), 0, st, c.bp, P->objective, seed, dbody_T, rec);
     HIP_TRY(hipEventRecord(evEntry, st));
-    HIP_TRY(hipStreamWaitEvent(side.s, evEntry, 0));
+    HIP_TRY(hipStreamWaitEvent(sr->s, evEntry, 0));
     T *ab_cur = ab, *ab_nxt = ab + S;
     // the paper's variant: its moment u~* of the current and next level (zero at N_t),
     // and its body-adjoint record (zero at level N_t + 1)
@@ -1067,7 +1099,7 @@ int adjoint_impl(const Ctx &c0, const lks_problem_t *P, const T *gamma, const vo
         const int t0 = ci * c.Kc, t1 = std::min(t0 + c.Kc, c.NT), len = t1 - t0;
         T *seg = segb(b), *ustar_seg = ustar_segb(b);
         double *Bseg = Bsegb(b);
-        if (ci + 2 < ncp) HIP_TRY(hipStreamWaitEvent(side.s, evRev[b], 0));
+        if (ci + 2 < ncp) HIP_TRY(hipStreamWaitEvent(sr->s, evRev[b], 0));
         HIP_TRY(hipMemcpyAsync(seg, at<const char>(const_cast<void *>(ckpt), ckpt_state_off(c, ci)), S * sizeof(T),
                                hipMemcpyDeviceToDevice, side.s));
         HIP_TRY(hipMemcpyAsync(Bseg + recN, at<const char>(const_cast<void *>(ckpt), ckpt_body_off(c, ci)),

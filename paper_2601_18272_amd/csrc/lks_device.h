@@ -116,6 +116,16 @@ __device__ __forceinline__ uint3 xcd_tile() {
     return make_uint3(t % gx, (t / gx) % gy, t / (gx * gy));
 }
 
+// The same renumbering for grids of independent work items (design points, box rows):
+// the logical block of this workgroup, so that XCD j runs the j-th contiguous run of
+// logical blocks and the footprint fields a run touches stay in one L2. Over a 2D grid
+// (blockIdx.y a second index) the linear order x fastest is renumbered and split again.
+__device__ __forceinline__ unsigned xcd_block() {
+    const unsigned nb = gridDim.x * gridDim.y, b = blockIdx.x + gridDim.x * blockIdx.y;
+    const unsigned per = nb >> 3, rem = nb & 7, x = b & 7;
+    return x * per + min(x, rem) + (b >> 3);
+}
+
 template <int DIM>
 __device__ __forceinline__ bool is_interior(const Grid &g, const int x[3]) {
 #pragma unroll
