@@ -49,8 +49,19 @@ enum { LKS_DOF_TX = 1, LKS_DOF_TY = 2, LKS_DOF_TZ = 4, LKS_DOF_ROT = 8 };
  *   iteration of Sec. 3.1 then does not contract).
  * LKS_FLAG_PAPER_ADJOINT: lks_adjoint computes the paper's own adjoint variant instead of
  *   the exact reverse of the discrete map (below); the flag must also be set in the
- *   lks_workspace_bytes(P, 1) query (the variant needs more scratch). */
-enum { LKS_FLAG_ASYNC = 1, LKS_FLAG_PROFILE = 2, LKS_FLAG_STABILITY = 4, LKS_FLAG_PAPER_ADJOINT = 8 };
+ *   lks_workspace_bytes(P, 1) query (the variant needs more scratch).
+ * LKS_FLAG_MARCH2D: 2D problems use the column-march LKS and adjoint LKS kernels whatever
+ *   the grid size (by default grids of at least 4M nodes march in the forward, of at least
+ *   1M nodes in the adjoint, smaller ones use the tile kernels). The results agree to
+ *   rounding; a forward and the adjoint that recomputes it should be given the same flag
+ *   for the recompute to reproduce the forward bit for bit. */
+enum {
+    LKS_FLAG_ASYNC = 1,
+    LKS_FLAG_PROFILE = 2,
+    LKS_FLAG_STABILITY = 4,
+    LKS_FLAG_PAPER_ADJOINT = 8,
+    LKS_FLAG_MARCH2D = 16
+};
 
 enum {
     LKS_OK = 0,

@@ -708,14 +708,25 @@ __global__ __launch_bounds__(256) void k_spread_map(Grid g, Design D, const doub
 // interior nodes) and the coordinates are clamped, so the tap loops have no branches.
 // Box-relative variant: coordinates relative to the footprint box, zero weight outside.
 template <int DIM, typename T>
+//
+// S[a] = sum_t w[a][t] and dS[a] = sum_t dw[a][t] are the per-axis weight sums in FP64:
+// the sum of W over the taps is S[0] S[1] S[2]. The cosine kernel is a partition of
+// unity, so where all four taps of an axis lie on the interior grid S = 1 and dS = 0
+// exactly; only an axis with a masked tap (next to a wall) sums its weights, in FP64.
+// The interpolation of u = U + v uses them for its U part, U S[0] S[1] S[2], which in
+// the weights' own precision would add their rounding times |U| to every force term.
 struct Taps {
     int c[3][4];
     T w[3][4], dw[3][4];
+    double S[3], dS[3];
     __device__ __forceinline__ void init(const Grid &g, const double X[3], bool want_dw, const int *bo = nullptr,
                                          const int *bl = nullptr) {
 #pragma unroll
         for (int a = 0; a < 3; a++) {
             const int base = a < DIM ? (int)fmax(fmin(floor(X[a]), 1.0e9), -1.0e9) - 1 : 0;
+            S[a] = 1.0;
+            dS[a] = 0.0;
+            int okm = 0;
 #pragma unroll
             for (int t = 0; t < 4; t++) {
                 if (a >= DIM) {
@@ -738,9 +749,24 @@ struct Taps {
                 const T r = T((double)v - X[a]);
                 w[a][t] = ok ? wk(r) : T(0);
                 dw[a][t] = (ok && want_dw) ? dwk(r) : T(0);
+                okm |= ok ? 1 << t : 0;
+            }
+            if (a < DIM && okm != 15) {
+                double s = 0.0, ds = 0.0;
+#pragma unroll
+                for (int t = 0; t < 4; t++)
+                    if (okm & (1 << t)) {
+                        const double r = (double)(base + t) - X[a];
+                        s += wk(r);
+                        ds += dwk(r);
+                    }
+                S[a] = s;
+                dS[a] = want_dw ? ds : 0.0;
             }
         }
     }
+    // sum of W over the taps
+    __device__ __forceinline__ double wsum() const { return S[0] * S[1] * S[2]; }
 };
 
 template <typename V> __device__ __forceinline__ V sel4(const V v[4], int i) {
@@ -965,7 +991,7 @@ __global__ __launch_bounds__(Dblk<DIM>::v) void k_interp_force(Grid g, Design D,
         pose_point(D, B, xi, P);
         Taps<DIM, T> tp;
         tp.init(g, P.X, false);
-        T ur[3] = {0, 0, 0}, sw = 0;
+        T ur[3] = {0, 0, 0};
         constexpr int TZ = DIM == 3 ? 4 : 1;
 #pragma unroll 1
         for (int c = 0; c < TZ; c++) {
@@ -979,7 +1005,6 @@ __global__ __launch_bounds__(Dblk<DIM>::v) void k_interp_force(Grid g, Design D,
                 for (int a = 0; a < 4; a++) {
                     const T W = tp.w[0][a] * wyz;
                     const long long id = row + tp.c[0][a];
-                    sw += W;
 #pragma unroll
                     for (int e = 0; e < DIM; e++) ur[e] += W * u[e * N + id];
                 }
@@ -988,9 +1013,10 @@ __global__ __launch_bounds__(Dblk<DIM>::v) void k_interp_force(Grid g, Design D,
         const double kr = krD[m];
         double Dv[3] = {0.0, 0.0, 0.0};
         // u^ref = sum W v + U sum W (the state holds v = u - U)
+        const double sw = tp.wsum();
 #pragma unroll
         for (int e = 0; e < DIM; e++) {
-            Dv[e] = ((double)ur[e] + g.U[e] * (double)sw) - P.US[e];
+            Dv[e] = ((double)ur[e] + g.U[e] * sw) - P.US[e];
             v[e] = kr * Dv[e];
         }
         v[3] = kr * (pick3(P.r, D.pi) * pick3(Dv, D.pj) - pick3(P.r, D.pj) * pick3(Dv, D.pi));
@@ -1230,7 +1256,7 @@ __global__ __launch_bounds__(It2<TT>::NT) void k_iter2d(Grid g, Design D, BodyPa
     // interpolation at the tile's points, force and torque terms
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     if (own) {
-        T ur[2] = {0, 0}, sw = 0;
+        T ur[2] = {0, 0};
 #pragma unroll
         for (int b = 0; b < 4; b++) {
             const T wyz = tp.w[1][b] * tp.w[2][0];
@@ -1239,14 +1265,13 @@ __global__ __launch_bounds__(It2<TT>::NT) void k_iter2d(Grid g, Design D, BodyPa
             for (int a = 0; a < 4; a++) {
                 const T W = tp.w[0][a] * wyz;
                 const int xx = min(max(tp.c[0][a] - ox, 0), PE - 1);
-                sw += W;
                 ur[0] += W * up[0][yy][xx];
                 ur[1] += W * up[1][yy][xx];
             }
         }
         // u^ref = sum W v + U sum W (the patch holds v = u - U)
-        double Dv[3] = {((double)ur[0] + g.U[0] * (double)sw) - P.US[0],
-                        ((double)ur[1] + g.U[1] * (double)sw) - P.US[1], 0.0};
+        const double sw = tp.wsum();
+        double Dv[3] = {((double)ur[0] + g.U[0] * sw) - P.US[0], ((double)ur[1] + g.U[1] * sw) - P.US[1], 0.0};
         v[0] = kr * Dv[0];
         v[1] = kr * Dv[1];
         v[3] = kr * (pick3(P.r, D.pi) * pick3(Dv, D.pj) - pick3(P.r, D.pj) * pick3(Dv, D.pi));
@@ -1573,7 +1598,7 @@ __global__ __launch_bounds__(R1blk<DIM>::v) void k_adj_r1(Grid g, Design D, Body
     Pose P;
     Taps<DIM, T> tp;
     constexpr int TZ = DIM == 3 ? 4 : 1;
-    T ur[3] = {0, 0, 0}, sw = 0;
+    T ur[3] = {0, 0, 0};
     // offsets of the taps: in the staged patch (TL) or in the box arrays
     int ox[4], oy[4], oz[4];
     const T *src[3];
@@ -1612,7 +1637,6 @@ __global__ __launch_bounds__(R1blk<DIM>::v) void k_adj_r1(Grid g, Design D, Body
                 for (int a = 0; a < 4; a++) {
                     const T W = tp.w[0][a] * tp.w[1][b] * wz;
                     const int l = ox[a] + oy[b] + cz;
-                    sw += W;
 #pragma unroll
                     for (int e = 0; e < DIM; e++) ur[e] += W * src[e][l];
                 }
@@ -1628,7 +1652,7 @@ __global__ __launch_bounds__(R1blk<DIM>::v) void k_adj_r1(Grid g, Design D, Body
     if (own) {
         double Dv[3] = {0, 0, 0}, Db[3] = {0, 0, 0};
 #pragma unroll
-        for (int e = 0; e < DIM; e++) Dv[e] = ((double)ur[e] + g.U[e] * (double)sw) - P.US[e];
+        for (int e = 0; e < DIM; e++) Dv[e] = ((double)ur[e] + g.U[e] * tp.wsum()) - P.US[e];
         double gsum = 0.0;
 #pragma unroll
         for (int e = 0; e < DIM; e++) {
@@ -1647,12 +1671,13 @@ __global__ __launch_bounds__(R1blk<DIM>::v) void k_adj_r1(Grid g, Design D, Body
             USb[e] = -Db[e];
             URb[e * D.ND + m] = T(Db[e]);
         }
-        // x^ref cotangent from the interpolation: sum_x dW/dX (Db . u(x)), u = U + v
+        // x^ref cotangent from the interpolation: sum_x dW/dX (Db . u(x)), u = U + v; the
+        // U part, (Db . U) d(S0 S1 S2)/dX, from the FP64 weight sums (zero away from walls)
         T xb[3] = {0, 0, 0};
         const T db[3] = {T(Db[0]), T(Db[1]), T(Db[2])};
-        T dbU = 0;
+        double dbU = 0.0;
 #pragma unroll
-        for (int e = 0; e < DIM; e++) dbU += db[e] * gU<T>(g, e);
+        for (int e = 0; e < DIM; e++) dbU += Db[e] * g.U[e];
 #pragma unroll 1
         for (int c = 0; c < TZ; c++) {
             const T wz = sel4(tp.w[2], c), dwz = sel4(tp.dw[2], c);
@@ -1661,7 +1686,7 @@ __global__ __launch_bounds__(R1blk<DIM>::v) void k_adj_r1(Grid g, Design D, Body
             for (int b = 0; b < 4; b++) {
 #pragma unroll
                 for (int a = 0; a < 4; a++) {
-                    T dot = dbU;
+                    T dot = 0;
                     const int l = ox[a] + oy[b] + cz;
 #pragma unroll
                     for (int e = 0; e < DIM; e++) dot += db[e] * src[e][l];
@@ -1671,8 +1696,9 @@ __global__ __launch_bounds__(R1blk<DIM>::v) void k_adj_r1(Grid g, Design D, Body
                 }
             }
         }
-#pragma unroll
-        for (int e = 0; e < DIM; e++) Xb[e] = (double)xb[e];
+        Xb[0] = (double)xb[0] - dbU * (tp.dS[0] * tp.S[1] * tp.S[2]);
+        Xb[1] = (double)xb[1] - dbU * (tp.S[0] * tp.dS[1] * tp.S[2]);
+        if (DIM == 3) Xb[2] = (double)xb[2] - dbU * (tp.S[0] * tp.S[1] * tp.dS[2]);
         pose_rev(D, B, P, Xb, USb, rb, v);
     }
     block_reduce_store<8, R1blk<DIM>::v>(v, part, nullptr, xcd_block());

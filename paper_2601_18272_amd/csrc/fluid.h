@@ -28,7 +28,283 @@
 
 namespace lks {
 
-// ===================================================================== forward, 2D
+// ===================================================================== lane shifts
+// A register's value in lane l - 1 (from_left) or l + 1 (from_right) of the wave,
+// through the DPP whole-wave shifts (wave_shr:1, wave_shl:1); lanes past either end of
+// the wave read zero. FP64 values move as two 32-bit halves.
+__device__ __forceinline__ float from_left(float v) {
+    return __builtin_bit_cast(float,
+                              __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float from_right(float v) {
+    return __builtin_bit_cast(float,
+                              __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
+}
+__device__ __forceinline__ double dpp64(double v, int ctrl_left) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    int lo, hi;
+    if (ctrl_left) {
+        lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0x138, 0xf, 0xf, true);
+        hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0x138, 0xf, 0xf, true);
+    } else {
+        lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0x130, 0xf, 0xf, true);
+        hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0x130, 0xf, 0xf, true);
+    }
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double from_left(double v) { return dpp64(v, 1); }
+__device__ __forceinline__ double from_right(double v) { return dpp64(v, 0); }
+
+// ===================================================================== forward, 2D: column march
+// The kernel of large grids (k_gather2d below serves those whose tiles fill the device
+// only a few times over, where the march's serial rows cost more than they save).
+// Column march. Each wave works alone: its lane l holds column x0 - 2 + l, and it
+// writes the C2_W = 60 columns x0 .. x0+59 of a run of `rows` rows, marching along y.
+// Neighbours along x are the wave's other lanes (DPP shifts), neighbours along y are rows
+// the lane keeps in registers, so the kernel uses no LDS and no barriers. At iteration r
+// the lane holds p, u of rows r-2 .. r+2 (a one-sided y derivative at a non-periodic end
+// reaches two rows) and has rows r+3 .. r+5 in flight; it evaluates the f_i of row r,
+// pushes them into the moments of rows r-1, r, r+1 and stores row r-1, now complete.
+// Rows live in a ring of 8 register slots (row q in slot (q - Ya + 3) mod 8); the loop
+// is unrolled by 8 so that every slot index is a compile-time constant.
+//
+// With fold, boundary nodes are read from the interior node they copy and their
+// prescribed values replace what the face fixes (bc_resolve), as k_bc would have stored
+// them; the replacement is applied when the row is first needed (as row r+2), long
+// after its loads were issued.
+constexpr int C2_W = 60, C2_NT = 256;
+
+// Prescribed values of 2D node (x, y) as a fold applies them: mask (bit 0 p, bit 1 u)
+// and the values (u as its deviation from U).
+template <typename T>
+__device__ __forceinline__ void fold_values2(const Grid &g, const Bc &bc, int x, int y, int &m, T &vp, T &vu,
+                                             T &vv) {
+    const int xx[3] = {x, y, 0};
+    BcNode b;
+    bc_resolve<2>(g, bc, xx, b);
+    m = (b.p_fixed ? 1 : 0) | (b.u_fixed ? 2 : 0);
+    vp = T(b.p);
+    vu = T(b.u[0] - g.U[0]);
+    vv = T(b.u[1] - g.U[1]);
+}
+
+template <typename T, bool SP>
+__global__ __launch_bounds__(C2_NT) void k_gather2d_march(Grid g, T A, Bc bc, int fold, int rows, int nstrip, int nwave,
+                                                    const T *__restrict__ sin_, T *__restrict__ sout,
+                                                    unsigned long long *ts) {
+    if (SP) span_begin(ts);
+    // the grid as plain scalars: the march below is written without closures or
+    // references, so that every per-lane value stays in a register
+    const int nx = g.n[0], ny = g.n[1], perx = g.per[0], pery = g.per[1];
+    const long long N = g.N;
+    const T Ux = gU<T>(g, 0), Uy = gU<T>(g, 1);
+    const int lane = threadIdx.x & 63;
+    // the wave's index, in a scalar register (uniform over the wave)
+    const int wv = (int)xcd_block() * (C2_NT / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (wv < nwave) {
+        // uniform over the wave: kept in scalar registers (readfirstlane), so that the row
+        // logic below is scalar code and its branches are scalar branches
+        const int strip = __builtin_amdgcn_readfirstlane(wv % nstrip);
+        const int run = __builtin_amdgcn_readfirstlane(wv / nstrip);
+        const int x0 = strip * C2_W, Ya = run * rows, Yb = min(Ya + rows, ny);
+        // this lane's column; lanes off the grid (a non-periodic x axis) read a column on
+        // the grid instead: their f_i reach only boundary nodes, which are not written
+        const int x = x0 - 2 + lane;
+        int xw = x;
+        const bool colok = wrap_coord(xw, nx, perx);
+        if (!colok) xw = x < 0 ? 0 : nx - 1;
+        const int xcls = (!perx && colok) ? (xw == 0 ? 1 : (xw == nx - 1 ? 2 : 0)) : 0;
+        const unsigned xl = (unsigned)((fold && xcls) ? (xcls == 1 ? 1 : nx - 2) : xw);
+        const bool wave_xb = !perx && (x0 - 2 <= 0 || x0 + 61 >= nx - 1);
+        const bool outc = lane >= 2 && lane < 2 + C2_W && x < nx && xcls == 0;
+        // prescribed values of this lane's node (fold): on rows off the y faces (0, x faces
+        // only), on the low and on the high y face (1, 2); resolved once here
+        int fx0 = 0, fx1 = 0, fx2 = 0;
+        T fp0 = 0, fp1 = 0, fp2 = 0, fu0 = 0, fu1 = 0, fu2 = 0, fv0 = 0, fv1 = 0, fv2 = 0;
+        if (fold) {
+            fold_values2<T>(g, bc, xw, pery ? 0 : 1, fx0, fp0, fu0, fv0);
+            if (!pery) {
+                fold_values2<T>(g, bc, xw, 0, fx1, fp1, fu1, fv1);
+                fold_values2<T>(g, bc, xw, ny - 1, fx2, fp2, fu2, fv2);
+            }
+        }
+        const T w0 = T(4.0 / 9.0), w1 = T(1.0 / 9.0), w2 = T(1.0 / 36.0);
+        const T A2 = T(2) * A;
+        const int nit = Yb - Ya + 2;  // iterations r = Ya-1 .. Yb
+
+// face class of a wrapped row (0 interior, 1 low face, 2 high face of a non-periodic y)
+#define C2_YCLS(yw) (pery ? 0 : ((yw) == 0 ? 1 : ((yw) == ny - 1 ? 2 : 0)))
+// p, u of row r into (p, u, v): rows Ya-2 .. Yb+1 are read (the f_i of rows Ya-1 .. Yb);
+// a row off the grid reads a row on it, for the same reason as the columns; with fold a
+// face row reads the interior row it copies
+#define C2_LOAD(r, p, u, v)                                                          \
+    do {                                                                             \
+        const int r_ = (r);                                                          \
+        if (r_ >= Ya - 2 && r_ <= Yb + 1) {                                          \
+            int yw_ = r_;                                                            \
+            if (!wrap_coord(yw_, ny, pery)) yw_ = r_ < 0 ? 0 : ny - 1;               \
+            const int yc_ = C2_YCLS(yw_);                                            \
+            const int yl_ = (fold && yc_) ? (yc_ == 1 ? 1 : ny - 2) : yw_;           \
+            const T *rp_ = sin_ + (size_t)yl_ * (size_t)nx;                          \
+            (p) = rp_[xl];                                                           \
+            (u) = rp_[N + xl];                                                       \
+            (v) = rp_[2 * N + xl];                                                   \
+        }                                                                            \
+    } while (0)
+// the prescribed values of row r replace what its nodes' faces fix (fold)
+#define C2_FIX(r, p, u, v)                                                           \
+    do {                                                                             \
+        int yw_ = (r);                                                               \
+        if (fold && wrap_coord(yw_, ny, pery)) {                                     \
+            const int yc_ = C2_YCLS(yw_);                                            \
+            if (yc_ != 0 || wave_xb) {                                               \
+                const bool s1_ = yc_ == 1, s2_ = yc_ == 2;                           \
+                const int m_ = s1_ ? fx1 : (s2_ ? fx2 : fx0);                        \
+                (p) = (m_ & 1) ? (s1_ ? fp1 : (s2_ ? fp2 : fp0)) : (p);              \
+                (u) = (m_ & 2) ? (s1_ ? fu1 : (s2_ ? fu2 : fu0)) : (u);              \
+                (v) = (m_ & 2) ? (s1_ ? fv1 : (s2_ ? fv2 : fv0)) : (v);              \
+            }                                                                        \
+        }                                                                            \
+    } while (0)
+
+        T P[8], U[8], V[8];     // rows, slot (q - Ya + 3) & 7
+        T AP[8], AX[8], AY[8];  // moments being gathered, same slots
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            AP[k] = AX[k] = AY[k] = T(0);
+            P[k] = U[k] = V[k] = T(0);
+            C2_LOAD(Ya - 3 + k, P[k], U[k], V[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; k++) C2_FIX(Ya - 3 + k, P[k], U[k], V[k]);
+
+// Iteration r = Ya - 1 + i0 + J. BULK: every row it touches (r-1 .. r+6) lies inside the
+// run, off the y faces and the periodic seam: no row checks, only the x-face values.
+#define C2_STEP(J, BULK)                                                                            \
+    {                                                                                               \
+        constexpr int m2 = (J) & 7, m1 = ((J) + 1) & 7, c0 = ((J) + 2) & 7, p1 = ((J) + 3) & 7,      \
+                      p2 = ((J) + 4) & 7;                                                           \
+        const int r = Ya - 1 + i0 + (J);                                                            \
+        int yc = 0;                                                                                 \
+        if (BULK) {                                                                                 \
+            if (fold && wave_xb) {                                                                  \
+                P[p2] = (fx0 & 1) ? fp0 : P[p2];                                                    \
+                U[p2] = (fx0 & 2) ? fu0 : U[p2];                                                    \
+                V[p2] = (fx0 & 2) ? fv0 : V[p2];                                                    \
+            }                                                                                       \
+        } else {                                                                                    \
+            C2_FIX(r + 2, P[p2], U[p2], V[p2]);                                                     \
+            int yw = r;                                                                             \
+            yc = wrap_coord(yw, ny, pery) ? C2_YCLS(yw) : 0;                                        \
+        }                                                                                           \
+        /* S_ab = d_a u_b: along x from the neighbouring lanes, along y from the rows */           \
+        const T u = U[c0], v = V[c0];                                                               \
+        const T uL = from_left(u), uR = from_right(u), vL = from_left(v), vR = from_right(v);       \
+        T dxu = T(0.5) * (uR - uL), dxv = T(0.5) * (vR - vL);                                       \
+        if (wave_xb) {                                                                              \
+            /* one-sided on the end columns of a non-periodic x axis; the lanes two away are       \
+               read with every lane active (DPP reads zero from inactive lanes) */                  \
+            const T uRR = from_right(uR), vRR = from_right(vR), uLL = from_left(uL),                \
+                    vLL = from_left(vL);                                                            \
+            if (xcls == 1) {                                                                        \
+                dxu = T(0.5) * (T(-3) * u + T(4) * uR - uRR);                                       \
+                dxv = T(0.5) * (T(-3) * v + T(4) * vR - vRR);                                       \
+            } else if (xcls == 2) {                                                                 \
+                dxu = T(0.5) * (T(3) * u - T(4) * uL + uLL);                                        \
+                dxv = T(0.5) * (T(3) * v - T(4) * vL + vLL);                                        \
+            }                                                                                       \
+        }                                                                                           \
+        T dyu, dyv;                                                                                 \
+        if (yc == 0) {                                                                              \
+            dyu = T(0.5) * (U[p1] - U[m1]);                                                         \
+            dyv = T(0.5) * (V[p1] - V[m1]);                                                         \
+        } else if (yc == 1) {                                                                       \
+            dyu = T(0.5) * (T(-3) * u + T(4) * U[p1] - U[p2]);                                      \
+            dyv = T(0.5) * (T(-3) * v + T(4) * V[p1] - V[p2]);                                      \
+        } else {                                                                                    \
+            dyu = T(0.5) * (T(3) * u - T(4) * U[m1] + U[m2]);                                       \
+            dyv = T(0.5) * (T(3) * v - T(4) * V[m1] + V[m2]);                                       \
+        }                                                                                           \
+        /* df_i = w_i (3p - 3 U.v - 3/2 v.v + 3 c.v + 9 (c.U)(c.v) + 9/2 (c.v)^2                    \
+           + A c.(S + S^T).c) (u, v hold the deviation), formed for the pairs +-c at once: the      \
+           even part is shared, the odd part 3 w c.v changes sign; evaluated on every lane (off     \
+           the grid the values reach no written node) */                                            \
+        const T base = T(3) * P[c0] - T(1.5) * (u * u + v * v) - T(3) * (Ux * u + Uy * v);          \
+        const T axx = A2 * dxu, ayy = A2 * dyv, axy = A2 * (dxv + dyu);                             \
+        const T f0 = w0 * base;                                                                     \
+        const T e12 = w1 * (base + (T(9) * Ux + T(4.5) * u) * u + axx), o12 = T(3) * w1 * u;        \
+        const T e34 = w1 * (base + (T(9) * Uy + T(4.5) * v) * v + ayy), o34 = T(3) * w1 * v;        \
+        const T bd = base + axx + ayy;                                                              \
+        const T cu56 = u + v, cu78 = u - v;                                                         \
+        const T e56 = w2 * (bd + (T(9) * (Ux + Uy) + T(4.5) * cu56) * cu56 + axy),                  \
+                o56 = T(3) * w2 * cu56;                                                             \
+        const T e78 = w2 * (bd + (T(9) * (Ux - Uy) + T(4.5) * cu78) * cu78 - axy),                  \
+                o78 = T(3) * w2 * cu78;                                                             \
+        /* push: f_i of this node reaches node (x + c_ix, r + c_iy) */                              \
+        const T a1 = from_left(e12 + o12), a2 = from_right(e12 - o12); /* row r */                 \
+        const T a5 = from_left(e56 + o56), a8 = from_right(e78 - o78); /* row r+1 */               \
+        const T a7 = from_left(e78 + o78), a6 = from_right(e56 - o56); /* row r-1 */               \
+        const T s0 = f0 + (a1 + a2), sp = (e34 + o34) + (a5 + a8), sm = (e34 - o34) + (a6 + a7);    \
+        AP[p1] = sp;                                                                                \
+        AX[p1] = a5 - a8;                                                                           \
+        AY[p1] = sp;                                                                                \
+        AP[c0] += s0;                                                                               \
+        AX[c0] += a1 - a2;                                                                          \
+        AP[m1] += sm;                                                                               \
+        AX[m1] += a7 - a6;                                                                          \
+        AY[m1] -= sm;                                                                               \
+        /* row r-1 is complete */                                                                   \
+        const int yo = r - 1;                                                                       \
+        if (((BULK) || (yo >= Ya && yo < Yb && C2_YCLS(yo) == 0)) && outc) {                         \
+            T *op = sout + (size_t)yo * (size_t)nx + (unsigned)x;                                   \
+            op[0] = AP[m1] * T(1.0 / 3.0);                                                          \
+            op[N] = AX[m1];                                                                         \
+            op[2 * N] = AY[m1];                                                                     \
+        }                                                                                           \
+        /* row r-2 is no longer needed: its slot takes row r+6 */                                   \
+        if (BULK) {                                                                                 \
+            const T *rp = sin_ + (size_t)(r + 6) * (size_t)nx;                                      \
+            P[m2] = rp[xl];                                                                         \
+            U[m2] = rp[N + xl];                                                                     \
+            V[m2] = rp[2 * N + xl];                                                                 \
+        } else {                                                                                    \
+            C2_LOAD(r + 6, P[m2], U[m2], V[m2]);                                                    \
+        }                                                                                           \
+    }
+
+        // Groups of 8 iterations (the slots follow the iteration index mod 8) whose rows
+        // r-1 .. r+6 all lie in [lo, hi] run in bulk.
+        const int lo = max(Ya, 1), hi = min(Yb + 1, ny - 2);
+        for (int i0 = 0; i0 < nit; i0 += 8) {
+            const int rf = Ya - 1 + i0;
+            if (i0 + 8 <= nit && rf - 1 >= lo && rf + 13 <= hi) {
+                C2_STEP(0, true) C2_STEP(1, true) C2_STEP(2, true) C2_STEP(3, true)
+                C2_STEP(4, true) C2_STEP(5, true) C2_STEP(6, true) C2_STEP(7, true)
+            } else {
+                C2_STEP(0, false) if (i0 + 1 < nit) {
+                    C2_STEP(1, false) if (i0 + 2 < nit) {
+                        C2_STEP(2, false) if (i0 + 3 < nit) {
+                            C2_STEP(3, false) if (i0 + 4 < nit) {
+                                C2_STEP(4, false) if (i0 + 5 < nit) {
+                                    C2_STEP(5, false) if (i0 + 6 < nit) {
+                                        C2_STEP(6, false) if (i0 + 7 < nit) { C2_STEP(7, false) }
+                                    }
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+#undef C2_STEP
+#undef C2_FIX
+#undef C2_LOAD
+#undef C2_YCLS
+    }
+    if (SP) span_end(ts);
+}
+
+// ===================================================================== forward, 2D: tiles
 // 64 x 8 tile, one node per thread. Push form: every source node of the tile plus a
 // one-node ring evaluates its nine f_i once into LDS; each node then gathers the nine
 // values that stream into it. p, u are staged with a two-node ring (gradients of the
@@ -602,7 +878,308 @@ __device__ __forceinline__ void star_bar(const Grid &g, const Bc &bc, const T *_
         for (int a = 0; a < DIM; a++) ub[a] = ustb[a * boxN + bi];
 }
 
-// ===================================================================== adjoint, 2D
+// ===================================================================== adjoint, 2D: column march
+// Column march like the forward (large grids; k_adjgather2d below serves the others): lane l of a wave holds column x0 - 2 + l (x0 = 60 s -
+// off), the wave writes columns x0 .. x0+59 of a run of `rows` rows and marches along y
+// with no LDS and no barriers. Per row r the lane forms the cotangent g of the
+// post-streaming moments (p*bar / 3, u*bar; zero off the interior) from the raw adjoint
+// state (the fold of the boundary copies by DPP shifts and the neighbouring rows, u*bar
+// from ustb inside the body box), the moments (pi, ups, sig) of row r from g rows r-1 ..
+// r+1, the part of the outputs of row r that needs only row r (with the x transpose of
+// the gradient through the neighbouring lanes), and completes row r-2 with the y
+// transpose from sig rows r-4 .. r. Rows live in rings of 8 register slots (row q in
+// slot (q - Ya + 4) mod 8), the loop unrolled by 8 so the slots are compile-time
+// constants; the raw rows are loaded 4 iterations ahead. off = 1 where a strip edge
+// would cut the two-lane reach of the one-sided transpose next to a non-periodic x face.
+constexpr int A2_W = 60, A2_NT = 256;
+
+// Coefficients with which sig at offsets -2 .. 2 along an axis enters D^T sig at
+// coordinate z (the transpose of the boundary-aware difference; dT_stencil's values).
+template <typename T>
+__device__ __forceinline__ void dT_coef(int z, int n, int per, T &cm2, T &cm1, T &c0, T &cp1, T &cp2) {
+    if (per) {
+        cm2 = c0 = cp2 = T(0);
+        cm1 = T(0.5);
+        cp1 = T(-0.5);
+        return;
+    }
+    cm1 = z - 1 >= 0 ? (z - 1 == 0 ? T(2) : T(0.5)) : T(0);
+    cp1 = z + 1 <= n - 1 ? (z + 1 == n - 1 ? T(-2) : T(-0.5)) : T(0);
+    c0 = (z == 0 ? T(-1.5) : T(0)) + (z == n - 1 ? T(1.5) : T(0));
+    cm2 = z - 2 == 0 ? T(-0.5) : T(0);
+    cp2 = z + 2 == n - 1 ? T(0.5) : T(0);
+}
+
+// p fixed (bit 0) / u fixed (bit 1) at boundary node (x, y)
+__device__ __forceinline__ int fix_mask2(const Grid &g, const Bc &bc, int x, int y) {
+    const int xx[3] = {x, y, 0};
+    BcNode b;
+    bc_resolve<2>(g, bc, xx, b);
+    return (b.p_fixed ? 1 : 0) | (b.u_fixed ? 2 : 0);
+}
+
+template <typename T, bool SP>
+__global__ __launch_bounds__(A2_NT) void k_adjgather2d_march(Grid g, Bc bc, T A, int rows, int nstrip, int nwave, int off,
+                                                       const T *__restrict__ ab, const T *__restrict__ ustb,
+                                                       const double *__restrict__ Bprev, Design D, int has_box,
+                                                       const T *__restrict__ sprev, T *__restrict__ out,
+                                                       unsigned long long *ts, T *__restrict__ ups) {
+    if (SP) span_begin(ts);
+    const int nx = g.n[0], ny = g.n[1], perx = g.per[0], pery = g.per[1];
+    const long long N = g.N;
+    const T Ux = gU<T>(g, 0), Uy = gU<T>(g, 1);
+    const int lane = threadIdx.x & 63;
+    const int wv = (int)xcd_block() * (A2_NT / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (wv < nwave) {
+        const int strip = __builtin_amdgcn_readfirstlane(wv % nstrip);
+        const int run = __builtin_amdgcn_readfirstlane(wv / nstrip);
+        const int x0 = strip * A2_W - off, Ya = run * rows, Yb = min(Ya + rows, ny);
+        // the body box (rows and columns of the box nodes, from the pose at t-1)
+        int bo0 = 0, bo1 = 0, bl0 = 0, bl1 = 0;
+        if (has_box) {
+            int o[3];
+            box_origin<2>(D, Bprev, o);
+            bo0 = __builtin_amdgcn_readfirstlane(o[0]);
+            bo1 = __builtin_amdgcn_readfirstlane(o[1]);
+            bl0 = D.L[0];
+            bl1 = D.L[1];
+        }
+        const long long bN = D.boxN;
+        // this lane's column (lanes off the grid read column 0 or nx-1; g is zero there)
+        const int x = x0 - 2 + lane;
+        int xw = x;
+        const bool colok = wrap_coord(xw, nx, perx);
+        if (!colok) xw = x < 0 ? 0 : nx - 1;
+        const bool xint = colok && (perx || (xw >= 1 && xw <= nx - 2));
+        const unsigned xo = (unsigned)xw;
+        const bool wave_xb = !perx && (x0 - 2 <= 1 || x0 + 61 >= nx - 2);
+        const bool outc = lane >= 2 && lane < 2 + A2_W && x >= 0 && x < nx;
+        const bool xbox = has_box && xint && xw - bo0 >= 0 && xw - bo0 < bl0;  // interior box column
+        // fold of the boundary copies (transpose of the boundary treatment): which of the
+        // neighbouring boundary nodes copy this node, and whether their p / u are free
+        const bool isx1 = !perx && xw == 1, isxn = !perx && xw == nx - 2;
+        const int mxl = perx ? 3 : fix_mask2(g, bc, 0, pery ? 0 : 1);
+        const int mxh = perx ? 3 : fix_mask2(g, bc, nx - 1, pery ? 0 : 1);
+        const int myl = pery ? 3 : fix_mask2(g, bc, perx ? 0 : 1, 0);
+        const int myh = pery ? 3 : fix_mask2(g, bc, perx ? 0 : 1, ny - 1);
+        const int mll = (perx || pery) ? 3 : fix_mask2(g, bc, 0, 0);
+        const int mhl = (perx || pery) ? 3 : fix_mask2(g, bc, nx - 1, 0);
+        const int mlh = (perx || pery) ? 3 : fix_mask2(g, bc, 0, ny - 1);
+        const int mhh = (perx || pery) ? 3 : fix_mask2(g, bc, nx - 1, ny - 1);
+        // per-lane weights of the x fold: the left / right neighbour is a boundary node
+        // copying this one on rows off the y faces, and its p / u are free there
+        const T fLp = (isx1 && !(mxl & 1)) ? T(1) : T(0), fLu = (isx1 && !(mxl & 2)) ? T(1) : T(0);
+        const T fRp = (isxn && !(mxh & 1)) ? T(1) : T(0), fRu = (isxn && !(mxh & 2)) ? T(1) : T(0);
+        // x transpose of the gradient at this column
+        T xm2, xm1, x00, xp1, xp2;
+        dT_coef<T>(xw, nx, perx, xm2, xm1, x00, xp1, xp2);
+        const T w0 = T(4.0 / 9.0), w1 = T(1.0 / 9.0), w2 = T(1.0 / 36.0);
+        const T A2 = T(2) * A;
+        const int nit = Yb - Ya + 4;  // iterations r = Ya-2 .. Yb+1
+
+#define A2_INT(yw) (pery || ((yw) >= 1 && (yw) <= ny - 2))
+// raw adjoint state of row r: rows Ya-4 .. Yb+3 are read, a row off the grid reads a
+// row on it (its g is zero); inside the body box u*bar comes from ustb
+#define A2_LOAD(r, p, u, v)                                                          \
+    do {                                                                             \
+        const int r_ = (r);                                                          \
+        if (r_ >= Ya - 4 && r_ <= Yb + 3) {                                          \
+            int yw_ = r_;                                                            \
+            if (!wrap_coord(yw_, ny, pery)) yw_ = r_ < 0 ? 0 : ny - 1;               \
+            const T *rp_ = ab + (size_t)yw_ * (size_t)nx;                            \
+            (p) = rp_[xo];                                                           \
+            const int by_ = yw_ - bo1;                                               \
+            if (has_box && by_ >= 0 && by_ < bl1 && A2_INT(yw_)) {                   \
+                if (xbox) {                                                          \
+                    const T *bp_ = ustb + (size_t)by_ * (size_t)bl0 + (xw - bo0);    \
+                    (u) = bp_[0];                                                    \
+                    (v) = bp_[bN];                                                   \
+                } else {                                                             \
+                    (u) = rp_[N + xo];                                               \
+                    (v) = rp_[2 * N + xo];                                           \
+                }                                                                    \
+            } else {                                                                 \
+                (u) = rp_[N + xo];                                                   \
+                (v) = rp_[2 * N + xo];                                               \
+            }                                                                        \
+        }                                                                            \
+    } while (0)
+#define A2_SPREV(r, a, b)                                                            \
+    do {                                                                             \
+        const int r_ = (r);                                                          \
+        if (r_ >= Ya && r_ < Yb) {                                                   \
+            const T *rp_ = sprev + (size_t)r_ * (size_t)nx;                          \
+            (a) = rp_[N + xo];                                                       \
+            (b) = rp_[2 * N + xo];                                                   \
+        }                                                                            \
+    } while (0)
+
+        T RP[8], RU[8], RV[8];     // raw rows, slot (q - Ya + 4) & 7
+        T GP[8], GU[8], GV[8];     // g rows
+        T S0[8], S1[8];            // forward velocity at t-1 (deviation)
+        T MXY[8], MYY[8];          // sig_xy, sig_yy rows
+        T OP[8], OX[8], OY[8];     // outputs being completed
+        T QX[8], QY[8];            // the moment ups (for the paper's variant)
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            RP[k] = RU[k] = RV[k] = GP[k] = GU[k] = GV[k] = T(0);
+            S0[k] = S1[k] = MXY[k] = MYY[k] = OP[k] = OX[k] = OY[k] = QX[k] = QY[k] = T(0);
+            A2_LOAD(Ya - 4 + k, RP[k], RU[k], RV[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < 3; k++) A2_SPREV(Ya - 2 + k, S0[k + 2], S1[k + 2]);
+
+// fold of a y-face row (raw values bp, bu, bv) into the row it copies: the node below /
+// above, and the corner nodes beside it (masks my: face, ml / mh: the low / high x corner)
+#define A2_YFOLD(bp, bu, bv, my, ml, mh)                                                            \
+    {                                                                                               \
+        const T bp_ = (bp), bu_ = (bu), bv_ = (bv);                                                 \
+        const T yp_ = ((my) & 1) ? T(0) : T(1), yu_ = ((my) & 2) ? T(0) : T(1);                     \
+        gp_ += yp_ * bp_;                                                                           \
+        gu_ += yu_ * bu_;                                                                           \
+        gv_ += yu_ * bv_;                                                                           \
+        if (wave_xb) {                                                                              \
+            const T lp_ = from_left(bp_), rq_ = from_right(bp_);                                    \
+            const T lu_ = from_left(bu_), ru_ = from_right(bu_);                                    \
+            const T lv_ = from_left(bv_), rv_ = from_right(bv_);                                    \
+            const T cLp_ = (isx1 && !((ml) & 1)) ? T(1) : T(0), cLu_ = (isx1 && !((ml) & 2)) ? T(1) : T(0); \
+            const T cRp_ = (isxn && !((mh) & 1)) ? T(1) : T(0), cRu_ = (isxn && !((mh) & 2)) ? T(1) : T(0); \
+            gp_ += cLp_ * lp_ + cRp_ * rq_;                                                         \
+            gu_ += cLu_ * lu_ + cRu_ * ru_;                                                         \
+            gv_ += cLu_ * lv_ + cRu_ * rv_;                                                         \
+        }                                                                                           \
+    }
+// g of row q (slot c) from the raw rows q-1 (slot m), q, q+1 (slot p): the raw values of
+// an interior node plus, next to a non-periodic face, those of the boundary nodes that
+// copy it (where they are not prescribed); zero off the interior
+#define A2_G(q, m, c, p)                                                                            \
+    {                                                                                               \
+        int yw_ = (q);                                                                              \
+        const bool rowok_ = wrap_coord(yw_, ny, pery);                                              \
+        const bool yint_ = rowok_ && A2_INT(yw_);                                                   \
+        T gp_ = RP[c], gu_ = RU[c], gv_ = RV[c];                                                    \
+        if (wave_xb) {                                                                              \
+            const T lp_ = from_left(RP[c]), rp_ = from_right(RP[c]);                                \
+            const T lu_ = from_left(RU[c]), ru_ = from_right(RU[c]);                                \
+            const T lv_ = from_left(RV[c]), rv_ = from_right(RV[c]);                                \
+            gp_ += fLp * lp_ + fRp * rp_;                                                           \
+            gu_ += fLu * lu_ + fRu * ru_;                                                           \
+            gv_ += fLu * lv_ + fRu * rv_;                                                           \
+        }                                                                                           \
+        /* the rows on the y faces that copy this one, and their corners */                         \
+        if (!pery && yw_ == 1) A2_YFOLD(RP[m], RU[m], RV[m], myl, mll, mhl)                         \
+        if (!pery && yw_ == ny - 2) A2_YFOLD(RP[p], RU[p], RV[p], myh, mlh, mhh)                    \
+        /* inside the body box u*bar is ustb itself (no fold) */                                    \
+        const int by_ = yw_ - bo1;                                                                  \
+        if (has_box && by_ >= 0 && by_ < bl1 && yint_ && xbox) {                                    \
+            gu_ = RU[c];                                                                            \
+            gv_ = RV[c];                                                                            \
+        }                                                                                           \
+        const bool in_ = yint_ && xint;                                                             \
+        GP[c] = in_ ? gp_ * T(1.0 / 3.0) : T(0);                                                    \
+        GU[c] = in_ ? gu_ : T(0);                                                                   \
+        GV[c] = in_ ? gv_ : T(0);                                                                   \
+    }
+
+        // g rows Ya-3, Ya-2 (the first iteration forms row Ya-1)
+        A2_G(Ya - 3, 0, 1, 2)
+        A2_G(Ya - 2, 1, 2, 3)
+
+// Iteration r = Ya - 2 + i0 + J (slot of row r + k: (J + 2 + k) & 7).
+#define A2_STEP(J)                                                                                  \
+    {                                                                                               \
+        constexpr int sm4 = ((J) + 6) & 7, sm2 = (J) & 7, sm1 = ((J) + 1) & 7, s0 = ((J) + 2) & 7,   \
+                      sp1 = ((J) + 3) & 7, sp2 = ((J) + 4) & 7, sp3 = ((J) + 5) & 7;                \
+        constexpr int sm3 = ((J) + 7) & 7;                                                          \
+        const int r = Ya - 2 + i0 + (J);                                                            \
+        A2_G(r + 1, s0, sp1, sp2)                                                                   \
+        /* moments of row r: g_i = (p*bar/3 + c_i.u*bar)(x + c_i), sum_i w_i g_i (1, c, cc) */      \
+        const T g0 = GP[s0];                                                                        \
+        const T g1 = from_right(GP[s0] + GU[s0]), g2 = from_left(GP[s0] - GU[s0]);                  \
+        const T g3 = GP[sp1] + GV[sp1], g4 = GP[sm1] - GV[sm1];                                     \
+        const T g5 = from_right(GP[sp1] + GU[sp1] + GV[sp1]);                                       \
+        const T g8 = from_left(GP[sp1] - GU[sp1] + GV[sp1]);                                        \
+        const T g6 = from_left(GP[sm1] - GU[sm1] - GV[sm1]);                                        \
+        const T g7 = from_right(GP[sm1] + GU[sm1] - GV[sm1]);                                       \
+        const T e1 = g1 + g2, e2 = g3 + g4, s56 = g5 + g6, s78 = g7 + g8, d56 = g5 - g6,            \
+                d78 = g7 - g8;                                                                      \
+        const T dd = w2 * (s56 + s78);                                                              \
+        const T pi = w0 * g0 + w1 * (e1 + e2) + dd;                                                 \
+        const T mux = w1 * (g1 - g2) + w2 * (d56 + d78);                                            \
+        const T muy = w1 * (g3 - g4) + w2 * (d56 - d78);                                            \
+        const T sxx = w1 * e1 + dd, syy = w1 * e2 + dd, sxy = w2 * (s56 - s78);                     \
+        MXY[s0] = sxy;                                                                              \
+        MYY[s0] = syy;                                                                              \
+        /* outputs of row r except the y transpose: pbar = 3 pi, ubar = 3 ups + 9 sig u -          \
+           3 pi u + 2A (D_x^T sig_x.) */                                                            \
+        {                                                                                           \
+            const T u0 = Ux + S0[s0], u1 = Uy + S1[s0];                                             \
+            const T lxx = from_left(sxx), rxx = from_right(sxx), lxy = from_left(sxy),              \
+                    rxy = from_right(sxy);                                                          \
+            T tx = T(0.5) * (lxx - rxx), ty = T(0.5) * (lxy - rxy);                                 \
+            if (wave_xb) {                                                                          \
+                tx = xm2 * from_left(lxx) + xm1 * lxx + x00 * sxx + xp1 * rxx + xp2 * from_right(rxx); \
+                ty = xm2 * from_left(lxy) + xm1 * lxy + x00 * sxy + xp1 * rxy + xp2 * from_right(rxy); \
+            }                                                                                       \
+            OP[s0] = T(3) * pi;                                                                     \
+            OX[s0] = T(3) * mux + T(9) * (sxx * u0 + sxy * u1) - T(3) * pi * u0 + A2 * tx;          \
+            OY[s0] = T(3) * muy + T(9) * (sxy * u0 + syy * u1) - T(3) * pi * u1 + A2 * ty;          \
+            QX[s0] = mux;                                                                           \
+            QY[s0] = muy;                                                                           \
+        }                                                                                           \
+        /* row r-2 is complete with the y transpose of sig rows r-4 .. r */                         \
+        const int yo = r - 2;                                                                       \
+        if (yo >= Ya && yo < Yb) {                                                                  \
+            T cm2, cm1, c00, cp1, cp2;                                                              \
+            dT_coef<T>(yo, ny, pery, cm2, cm1, c00, cp1, cp2);                                      \
+            const T ox = OX[sm2] + A2 * (cm2 * MXY[sm4] + cm1 * MXY[sm3] + c00 * MXY[sm2] +          \
+                                         cp1 * MXY[sm1] + cp2 * MXY[s0]);                           \
+            const T oy = OY[sm2] + A2 * (cm2 * MYY[sm4] + cm1 * MYY[sm3] + c00 * MYY[sm2] +          \
+                                         cp1 * MYY[sm1] + cp2 * MYY[s0]);                           \
+            if (outc) {                                                                             \
+                T *op = out + (size_t)yo * (size_t)nx + (unsigned)x;                                \
+                op[0] = OP[sm2];                                                                    \
+                op[N] = ox;                                                                         \
+                op[2 * N] = oy;                                                                     \
+                if (ups) {                                                                          \
+                    T *uq = ups + (size_t)yo * (size_t)nx + (unsigned)x;                            \
+                    uq[0] = QX[sm2];                                                                \
+                    uq[N] = QY[sm2];                                                                \
+                }                                                                                   \
+            }                                                                                       \
+        }                                                                                           \
+        /* raw row r-2 is no longer needed (g rows up to r+1 are formed): its slot takes row       \
+           r+6; the forward velocity of row r+3 */                                                  \
+        A2_LOAD(r + 6, RP[sm2], RU[sm2], RV[sm2]);                                                  \
+        A2_SPREV(r + 3, S0[sp3], S1[sp3]);                                                          \
+    }
+
+        for (int i0 = 0; i0 < nit; i0 += 8) {
+            A2_STEP(0) if (i0 + 1 < nit) {
+                A2_STEP(1) if (i0 + 2 < nit) {
+                    A2_STEP(2) if (i0 + 3 < nit) {
+                        A2_STEP(3) if (i0 + 4 < nit) {
+                            A2_STEP(4) if (i0 + 5 < nit) {
+                                A2_STEP(5) if (i0 + 6 < nit) {
+                                    A2_STEP(6) if (i0 + 7 < nit) { A2_STEP(7) }
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+#undef A2_STEP
+#undef A2_G
+#undef A2_YFOLD
+#undef A2_SPREV
+#undef A2_LOAD
+#undef A2_INT
+    }
+    if (SP) span_end(ts);
+}
+
+// ===================================================================== adjoint, 2D: tiles
 // 64 x 8 tile. Stage p*bar, u*bar with a 3-node ring (zero off the interior), form
 // the moments (pi, ups, sig) on the tile plus a 2-ring, then the outputs.
 template <typename T, bool SP>

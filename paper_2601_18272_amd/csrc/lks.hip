@@ -193,7 +193,14 @@ struct Ctx {
     unsigned ntile = 0;  // its number of tiles
     bool tile3 = false;  // 3D R1 over 8^3 design tiles (nblk = tiles)
     bool paper = false;  // lks_adjoint computes the paper's adjoint variant (f2.h)
+    // 2D LKS / adjoint LKS kernels: the column march (large grids) or the tiles
+    bool march_fwd = false, march_adj = false;
 };
+
+// Grids from which the 2D column-march kernels are faster than the tile kernels
+// (measured: the tile forward is faster up to 2M nodes, the march from 8M; the march
+// adjoint from 2M, the tile adjoint up to 0.5M).
+constexpr long long MARCH_FWD_NODES = 1LL << 22, MARCH_ADJ_NODES = 1LL << 20;
 
 constexpr int MARGIN = 2;
 constexpr unsigned CPL_BLOCKS = 1024;  // blocks of the coupling-constant kernel (at most)
@@ -318,6 +325,11 @@ int make_ctx(const lks_problem_t *P, Ctx &c) {
     c.bp.dof = P->dof_mask & (c.dim == 2 ? (LKS_DOF_TX | LKS_DOF_TY | LKS_DOF_ROT) : 15);
     c.K = c.has_body ? P->n_itr : 1;
     c.paper = (P->flags & LKS_FLAG_PAPER_ADJOINT) != 0;
+    {
+        const bool force = (P->flags & LKS_FLAG_MARCH2D) != 0;
+        c.march_fwd = c.dim == 2 && (force || c.g.N >= MARCH_FWD_NODES);
+        c.march_adj = c.dim == 2 && (force || c.g.N >= MARCH_ADJ_NODES);
+    }
     if (P->n_steps < 0) return fail(LKS_EINVAL, "n_steps < 0");
     c.NT = P->n_steps;
     c.Kc = P->ckpt_every;
@@ -527,9 +539,33 @@ template <typename T> struct Run {
         return best;
     }
 
+    // Launch shape of the 2D column-march kernels: strips of `width` columns (the first
+    // shifted left by `off`), each cut into runs of `rows` rows, one wave per run. The
+    // runs are as long as possible while every wave of the grid is resident at once
+    // (`resident` waves), and at least 2 rows long.
+    void col_march(int width, int off, long long resident, int &rows, int &nstrip, int &nwave) const {
+        nstrip = (int)blocks(c.g.n[0] + off, width);
+        const long long runs = std::max(1LL, resident / nstrip);
+        rows = (int)std::max(2LL, (c.g.n[1] + runs - 1) / runs);
+        nwave = nstrip * (int)blocks(c.g.n[1], rows);
+    }
     // fold (2D): the boundary values of `in` are formed on load (see k_gather2d)
     void gather(const T *in, T *out, bool fold = false) const {
-        if (c.dim == 2) {
+        if (c.dim == 2 && c.march_fwd) {
+            static const long long res = resident_blocks(k_gather2d_march<T, false>, C2_NT);
+            int rows, nstrip, nwave;
+            col_march(C2_W, 0, res * (C2_NT / 64), rows, nstrip, nwave);
+            const dim3 grid(blocks(nwave, C2_NT / 64));
+            const int fd = fold ? 1 : 0;
+            pf->run_span(LKS_K_GATHER, LKS_K_GATHER_SPAN, [&](hipEvent_t e0, hipEvent_t e1, unsigned long long *ts) {
+                if (ts)
+                    hipLaunchKernelGGL((k_gather2d_march<T, true>), grid, dim3(C2_NT), 0, st, c.g, T(c.A), c.bc, fd,
+                                       rows, nstrip, nwave, in, out, ts);
+                else
+                    hipExtLaunchKernelGGL((k_gather2d_march<T, false>), grid, dim3(C2_NT), 0, st, e0, e1, 0, c.g,
+                                          T(c.A), c.bc, fd, rows, nstrip, nwave, in, out, ts);
+            });
+        } else if (c.dim == 2) {
             dim3 grid(blocks(c.g.n[0], G2_TX), blocks(c.g.n[1], G2_TY));
             const int fd = fold ? 1 : 0;
             pf->run_span(LKS_K_GATHER, LKS_K_GATHER_SPAN, [&](hipEvent_t e0, hipEvent_t e1, unsigned long long *ts) {
@@ -749,7 +785,22 @@ template <typename T> struct Run {
         const int hb = c.has_body ? 1 : 0;
         pf->run_span(LKS_K_ADJ_GATHER, c.dim == 2 ? LKS_K_ADJ_GATHER_SPAN : -1,
                      [&](hipEvent_t e0, hipEvent_t e1, unsigned long long *ts) {
-            if (c.dim == 2) {
+            if (c.dim == 2 && c.march_adj) {
+                static const long long res = resident_blocks(k_adjgather2d_march<T, false>, A2_NT);
+                // shift the strips by one column where a strip edge would cut the two-lane
+                // reach of the one-sided transpose next to the high x face
+                const int off = !c.g.per[0] && (c.g.n[0] - 62) % A2_W == 0 ? 1 : 0;
+                int rows, nstrip, nwave;
+                col_march(A2_W, off, res * (A2_NT / 64), rows, nstrip, nwave);
+                const dim3 grid(blocks(nwave, A2_NT / 64));
+                if (ts)
+                    hipLaunchKernelGGL((k_adjgather2d_march<T, true>), grid, dim3(A2_NT), 0, st, c.g, c.bc, T(c.A),
+                                       rows, nstrip, nwave, off, ab, ustb, Bprev, c.D, hb, sprev, out, ts, ups);
+                else
+                    hipExtLaunchKernelGGL((k_adjgather2d_march<T, false>), grid, dim3(A2_NT), 0, st, e0, e1, 0, c.g,
+                                          c.bc, T(c.A), rows, nstrip, nwave, off, ab, ustb, Bprev, c.D, hb, sprev,
+                                          out, ts, ups);
+            } else if (c.dim == 2) {
                 dim3 grid(blocks(c.g.n[0], G2_TX), blocks(c.g.n[1], G2_TY));
                 if (ts)
                     hipLaunchKernelGGL((k_adjgather2d<T, true>), grid, dim3(G2_TX, G2_TY), 0, st, c.g, c.bc, T(c.A),

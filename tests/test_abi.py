@@ -262,3 +262,4 @@ def test_coupling_validation_without_gpu(lib):
     assert L.lks_coupling(C.byref(s), dummy, dummy, None, dummy, 1 << 30, None) == lib.EINVAL
     assert L.lks_coupling(C.byref(s), dummy, dummy, dummy, dummy, 16, None) == lib.ENOSPACE
     assert lib.FLAG_STABILITY == 4
+    assert lib.FLAG_MARCH2D == 16

@@ -41,6 +41,14 @@ def elem(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
+def kernel_flags(L, pb, march):
+    """Flags selecting the 2D LKS kernels: the column march (march=True, forced) or the
+    size default (the tile kernels at these sizes). 3D problems have one kernel each."""
+    if march and pb.dim != 2:
+        pytest.skip("the column-march kernels are 2D")
+    return L._lib.FLAG_MARCH2D if march else 0
+
+
 def smooth_state(pb, seed, amp=1e-2):
     """Random smooth perturbation of the initial state (boundary values untouched
     matter not: the first step re-imposes them)."""
@@ -75,25 +83,29 @@ BODYFREE = {
 }
 
 
+@pytest.mark.parametrize("march", [False, True], ids=["tiles", "march"])
 @pytest.mark.parametrize("case", sorted(BODYFREE))
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_bodyfree_forward(L, orc, case, prec):
+def test_bodyfree_forward(L, orc, case, prec, march):
     pb = BODYFREE[case]()
+    fl = kernel_flags(L, pb, march)
     s0 = smooth_state(pb, 3)
     b0 = np.zeros(12)
     ref, _, _ = orc.forward(pb, None, s0, b0)
-    st, _, _, _ = L.forward(pb, None, s0, b0, precision=prec, store_ckpt=False)
+    st, _, _, _ = L.forward(pb, None, s0, b0, precision=prec, store_ckpt=False, flags=fl)
     got = st.cpu().numpy()
     scale = np.abs(ref).max()
     tol = 1e-12 if prec == "fp64" else 2e-6
     assert np.abs(got - ref).max() <= tol * scale, np.abs(got - ref).max() / scale
 
 
+@pytest.mark.parametrize("march", [False, True], ids=["tiles", "march"])
 @pytest.mark.parametrize("case", sorted(BODYFREE))
-def test_bodyfree_adjoint_initial_state(L, orc, case):
-    """dJ/d(initial state) is zero without a body; use a body of zero kappa far from
-    anything? No: check the fluid adjoint through a tiny porous body instead."""
+def test_bodyfree_adjoint_initial_state(L, orc, case, march):
+    """The fluid adjoint of the body-free channels, observed through a tiny porous body:
+    the gradient and the cotangents of the initial state and body."""
     pb = BODYFREE[case]()
+    fl = kernel_flags(L, pb, march)
     pb = pb.replace(ckpt_every=3)
     # attach a small porous body so that the objective depends on the fluid
     d = pb.dim
@@ -106,8 +118,8 @@ def test_bodyfree_adjoint_initial_state(L, orc, case):
     g = W.design(pb)
     b0 = W.initial_body(pb)
     J, grad, ds, db = orc.gradient(pb, g, s0, b0, with_initial=True)
-    _, _, Jg, B = L.forward(pb, g, s0, b0, precision="fp64")
-    gg, dsg, dbg = L.adjoint(pb, g, B, precision="fp64", want_initial=True)
+    _, _, Jg, B = L.forward(pb, g, s0, b0, precision="fp64", flags=fl)
+    gg, dsg, dbg = L.adjoint(pb, g, B, precision="fp64", want_initial=True, flags=fl)
     assert abs(Jg.item() - J) <= 1e-9 * abs(J) + 1e-15
     assert rel(gg.cpu().numpy(), grad) < 1e-8
     assert elem(gg.cpu().numpy(), grad) < 1e-8
@@ -140,27 +152,31 @@ def test_coupled_forward_fp64(L, orc, case):
     assert abs(J.item() - Jref) <= 1e-9 * abs(Jref) + 1e-16
 
 
+@pytest.mark.parametrize("march", [False, True], ids=["tiles", "march"])
 @pytest.mark.parametrize("case", sorted(BODY))
-def test_coupled_gradient_fp64(L, orc, case):
+def test_coupled_gradient_fp64(L, orc, case, march):
     pb = BODY[case]()
+    fl = kernel_flags(L, pb, march)
     g, s0, b0 = W.design(pb), W.initial_state(pb), W.initial_body(pb)
     Jref, gref = orc.gradient(pb, g, s0, b0, seed=1.7)
-    _, _, J, B = L.forward(pb, g, s0, b0, precision="fp64")
-    gg = L.adjoint(pb, g, B, seed=1.7, precision="fp64").cpu().numpy()
+    _, _, J, B = L.forward(pb, g, s0, b0, precision="fp64", flags=fl)
+    gg = L.adjoint(pb, g, B, seed=1.7, precision="fp64", flags=fl).cpu().numpy()
     assert abs(J.item() - Jref) <= 1e-9 * abs(Jref) + 1e-16
     assert rel(gg, gref) < 1e-8
     assert elem(gg, gref) < 1e-8
 
 
+@pytest.mark.parametrize("march", [False, True], ids=["tiles", "march"])
 @pytest.mark.parametrize("case", sorted(BODY))
-def test_coupled_fp32_targets(L, orc, case):
+def test_coupled_fp32_targets(L, orc, case, march):
     """FP32 fields with FP64 body state and reductions: objective within 1e-4 relative,
     gradient within 1e-3 relative L2 of the FP64 oracle."""
     pb = BODY[case]()
+    fl = kernel_flags(L, pb, march)
     g, s0, b0 = W.design(pb), W.initial_state(pb), W.initial_body(pb)
     Jref, gref = orc.gradient(pb, g, s0, b0)
-    _, _, J, B = L.forward(pb, g, s0, b0, precision="fp32")
-    gg = L.adjoint(pb, g, B, precision="fp32").cpu().numpy()
+    _, _, J, B = L.forward(pb, g, s0, b0, precision="fp32", flags=fl)
+    gg = L.adjoint(pb, g, B, precision="fp32", flags=fl).cpu().numpy()
     assert abs(J.item() - Jref) <= 1e-4 * abs(Jref)
     assert rel(gg, gref) < 1e-3
     assert elem(gg, gref) < 1e-3
@@ -192,22 +208,24 @@ def test_body_step_matches_oracle(L, orc):
         assert np.array_equal(got[8:], b[8:])
 
 
-def test_deterministic_and_checkpoint_consistent(L):
+@pytest.mark.parametrize("march", [False, True], ids=["tiles", "march"])
+def test_deterministic_and_checkpoint_consistent(L, march):
     """Two runs are bitwise identical (gather-form mapping, fixed-order reductions),
     and the gradient does not depend on the checkpoint interval beyond rounding."""
     pb = W.small2d(ckpt_every=5)
+    fl = kernel_flags(L, pb, march)
     g, s0, b0 = W.design(pb), W.initial_state(pb), W.initial_body(pb)
     outs = []
     for _ in range(2):
-        st, bd, J, B = L.forward(pb, g, s0, b0, precision="fp32")
-        gr = L.adjoint(pb, g, B, precision="fp32")
+        st, bd, J, B = L.forward(pb, g, s0, b0, precision="fp32", flags=fl)
+        gr = L.adjoint(pb, g, B, precision="fp32", flags=fl)
         outs.append((st.cpu().numpy(), bd.cpu().numpy(), J.item(), gr.cpu().numpy()))
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
     assert outs[0][2] == outs[1][2] and np.array_equal(outs[0][3], outs[1][3])
     # the recomputed segment reproduces the forward bit for bit: any K gives the same
     pb2 = pb.replace(ckpt_every=3)
-    _, _, J2, B2 = L.forward(pb2, g, s0, b0, precision="fp32")
-    gr2 = L.adjoint(pb2, g, B2, precision="fp32").cpu().numpy()
+    _, _, J2, B2 = L.forward(pb2, g, s0, b0, precision="fp32", flags=fl)
+    gr2 = L.adjoint(pb2, g, B2, precision="fp32", flags=fl).cpu().numpy()
     assert J2.item() == outs[0][2]
     assert np.array_equal(gr2, outs[0][3])
 
@@ -250,13 +268,15 @@ def test_divergence_is_reported(L):
 TERMINAL = ["small2d", "small2d-walls", "small3d"]
 
 
+@pytest.mark.parametrize("march", [False, True], ids=["tiles", "march"])
 @pytest.mark.parametrize("case", TERMINAL)
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_adjoint_with_terminal_values(L, orc, case, prec):
+def test_adjoint_with_terminal_values(L, orc, case, prec, march):
     """lks_adjoint started from given cotangents of the final state and body matches the
     oracle's sweep of seed J + <dstate_T, state> + <dbody_T, body> (gradient and initial
     cotangents)."""
     pb = BODY[case]()
+    fl = kernel_flags(L, pb, march)
     g, s0, b0 = W.design(pb), W.initial_state(pb), W.initial_body(pb)
     rng = np.random.default_rng(91)
     sT = rng.standard_normal(s0.size) * 0.05
@@ -266,8 +286,9 @@ def test_adjoint_with_terminal_values(L, orc, case, prec):
     if prec == "fp32":
         sT = sT.astype(np.float32).astype(np.float64)
     J, gref, dsref, dbref = orc.gradient(pb, g, s0, b0, seed=seed, with_initial=True, dstate_T=sT, dbody_T=bT)
-    _, _, Jg, B = L.forward(pb, g, s0, b0, precision=prec)
-    gg, ds, db = L.adjoint(pb, g, B, seed=seed, precision=prec, want_initial=True, dstate_T=sT, dbody_T=bT)
+    _, _, Jg, B = L.forward(pb, g, s0, b0, precision=prec, flags=fl)
+    gg, ds, db = L.adjoint(pb, g, B, seed=seed, precision=prec, want_initial=True, dstate_T=sT, dbody_T=bT,
+                           flags=fl)
     tol = 1e-8 if prec == "fp64" else 1e-3
     assert rel(gg.cpu().numpy(), gref) < tol
     assert elem(gg.cpu().numpy(), gref) < tol
