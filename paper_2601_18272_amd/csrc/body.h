@@ -265,11 +265,14 @@ __device__ __forceinline__ bool box_node(const Grid &g, const Design &D, const i
 }
 
 // kappa(x) and u^S(x) at node x: sum W kappa_ref, and u^G phi + omega a x (sum W (x^ref - x^G))
-// with phi = sum W and sum W (x^ref - x^G) = phi d - sum W r formed in FP64.
+// with phi = sum W and sum W (x^ref - x^G) = phi d - sum W r formed in FP64. us returns
+// u^S(x) - Uref (the fields' reference velocity; Uref null: u^S itself), subtracted in
+// FP64 before the rounding to T: a body moving with the flow has u^S close to U, whose
+// difference in T would lose the digits that drive the Brinkman term.
 // kr(m, idx) returns kappa^ref of design point m (design index idx).
 template <int DIM, typename T, bool ROT, int LPN = 1, typename KR>
 __device__ __forceinline__ void spread_node_kr(const Design &D, const double *B, KR &&kr, const int x[3], int q,
-                                               T &kap, T us[3]) {
+                                               T &kap, T us[3], const double *Uref) {
     double d[3];
     T k = 0, phi = 0, wr[3] = {0, 0, 0};
     gather_design<DIM, T, ROT, LPN>(D, B, x, d, q, [&](long long m, T W, const T r[3], const int *idx) {
@@ -292,7 +295,8 @@ __device__ __forceinline__ void spread_node_kr(const Design &D, const double *B,
     const double om = B[B_OM];
     kap = k;
 #pragma unroll
-    for (int a = 0; a < 3; a++) us[a] = a < DIM ? T(B[B_UG + a] * (double)phi + om * axa[a]) : T(0);
+    for (int a = 0; a < 3; a++)
+        us[a] = a < DIM ? T((B[B_UG + a] * (double)phi - (Uref ? Uref[a] : 0.0)) + om * axa[a]) : T(0);
 }
 
 // 2D spread_node_kr with the candidates listed first (Cand2) and all their kappa_ref
@@ -301,7 +305,7 @@ __device__ __forceinline__ void spread_node_kr(const Design &D, const double *B,
 // equal spread_node_kr's.
 template <typename T, bool ROT, int LPN, typename KR>
 __device__ __forceinline__ void spread_node2(const Design &D, const double *B, KR &&kr, const int x[3], int q,
-                                             T &kap, T us[3]) {
+                                             T &kap, T us[3], const double *Uref) {
     using C2 = Cand2<T, ROT, LPN, true>;
     C2 cd;
     cd.init(D, B, x, q);
@@ -324,18 +328,19 @@ __device__ __forceinline__ void spread_node2(const Design &D, const double *B, K
     const double armp = (double)phi * cd.d[0] - (double)wr[0], armq = (double)phi * cd.d[1] - (double)wr[1];
     const double om = B[B_OM];
     kap = k;
-    us[0] = T(B[B_UG + 0] * (double)phi + om * (-armq));
-    us[1] = T(B[B_UG + 1] * (double)phi + om * armp);
+    us[0] = T((B[B_UG + 0] * (double)phi - (Uref ? Uref[0] : 0.0)) + om * (-armq));
+    us[1] = T((B[B_UG + 1] * (double)phi - (Uref ? Uref[1] : 0.0)) + om * armp);
     us[2] = T(0);
 }
 
 template <int DIM, typename T, bool ROT, int LPN = 1>
 __device__ __forceinline__ void spread_node(const Design &D, const double *B, const T *__restrict__ krT,
-                                            const int x[3], int q, T &kap, T us[3]) {
+                                            const int x[3], int q, T &kap, T us[3], const double *Uref) {
     if constexpr (DIM == 2)
-        spread_node2<T, ROT, LPN>(D, B, [&](long long m, int, int) { return krT[m]; }, x, q, kap, us);
+        spread_node2<T, ROT, LPN>(D, B, [&](long long m, int, int) { return krT[m]; }, x, q, kap, us, Uref);
     else
-        spread_node_kr<DIM, T, ROT, LPN>(D, B, [&](long long m, const int *) { return krT[m]; }, x, q, kap, us);
+        spread_node_kr<DIM, T, ROT, LPN>(D, B, [&](long long m, const int *) { return krT[m]; }, x, q, kap, us,
+                                         Uref);
 }
 
 // ------------------------------------------------------------------ 3D axial sums
@@ -445,7 +450,8 @@ __device__ __forceinline__ int gather_plane(const Design &D, const double *B, co
 // kappa, u^S at node x (3D) from the axial sums K1 of kappa_ref at pose B (see k_axial).
 template <typename T, bool ROT, int LPN>
 __device__ __forceinline__ void spread_node_ax(const Design &D, const double *B, const Axial &ax,
-                                               const T *__restrict__ K1, const int x[3], int q, T &kap, T us[3]) {
+                                               const T *__restrict__ K1, const int x[3], int q, T &kap, T us[3],
+                                               const double *Uref) {
     const int NA = D.nd[D.axis] + 4;
     double d[3];
     T k = 0, phi = 0, wp = 0, wq = 0;
@@ -472,7 +478,7 @@ __device__ __forceinline__ void spread_node_ax(const Design &D, const double *B,
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         const double axa = a == D.axis ? 0.0 : (a == D.pi ? -armq : armp);
-        us[a] = T(B[B_UG + a] * (double)phi + om * axa);
+        us[a] = T((B[B_UG + a] * (double)phi - (Uref ? Uref[a] : 0.0)) + om * axa);
     }
 }
 
@@ -579,7 +585,7 @@ struct BoxRow {
 template <typename T, bool ROT>
 __device__ __forceinline__ void spread_node_row(const Design &D, const double *B, const Axial &ax,
                                                 const T *__restrict__ K1, int xa, const PlaneRow<T, ROT> &pr,
-                                                T &kap, T us[3]) {
+                                                T &kap, T us[3], const double *Uref) {
     const int NA = D.nd[D.axis] + 4;
     T k = 0, phi = 0, wp = 0, wq = 0;
     const int ib = xa + ax.fl;
@@ -601,7 +607,7 @@ __device__ __forceinline__ void spread_node_row(const Design &D, const double *B
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         const double axa = a == D.axis ? 0.0 : (a == D.pi ? -armq : armp);
-        us[a] = T(B[B_UG + a] * (double)phi + om * axa);
+        us[a] = T((B[B_UG + a] * (double)phi - (Uref ? Uref[a] : 0.0)) + om * axa);
     }
 }
 
@@ -627,7 +633,7 @@ __global__ __launch_bounds__(256) void k_spread_fwd_rows(Grid g, Design D, const
         int x[3];
         if (!br.node(g, D, o, ba, l, x)) continue;
         T kap, us[3];
-        spread_node_row<T, ROT>(D, B, ax, K1, x[D.axis], pr, kap, us);
+        spread_node_row<T, ROT>(D, B, ax, K1, x[D.axis], pr, kap, us, g.U);
         const long long id = node_id(g, x[0], x[1], x[2]);
         const T inv = T(1) / (T(1) + kap);
 #pragma unroll
@@ -639,7 +645,7 @@ __global__ __launch_bounds__(256) void k_spread_fwd_rows(Grid g, Design D, const
             } else {
                 s = ustar[a * bN + l];
             }
-            u[a * N + id] = (s + kap * (us[a] - gU<T>(g, a))) * inv;
+            u[a * N + id] = (s + kap * us[a]) * inv;
         }
     }
 }
@@ -660,9 +666,9 @@ __global__ __launch_bounds__(256) void k_spread_fwd(Grid g, Design D, const doub
     if (!box_node<DIM>(g, D, o, l, x)) return;
     T kap, us[3];
     if constexpr (DIM == 3)  // axial sums of kappa_ref at B^(k) in K1 (k_axial)
-        spread_node_ax<T, ROT, LPN>(D, Bk + k * B_REC, axial_of(D, Bk + k * B_REC), K1, x, q, kap, us);
+        spread_node_ax<T, ROT, LPN>(D, Bk + k * B_REC, axial_of(D, Bk + k * B_REC), K1, x, q, kap, us, g.U);
     else
-        spread_node<DIM, T, ROT, LPN>(D, Bk + k * B_REC, krT, x, q, kap, us);
+        spread_node<DIM, T, ROT, LPN>(D, Bk + k * B_REC, krT, x, q, kap, us, g.U);
     if (q != 0) return;
     const long long N = g.N;
     const long long id = node_id(g, x[0], x[1], x[2]);
@@ -676,7 +682,7 @@ __global__ __launch_bounds__(256) void k_spread_fwd(Grid g, Design D, const doub
         } else {
             s = ustar[a * D.boxN + l];
         }
-        u[a * N + id] = (s + kap * (us[a] - gU<T>(g, a))) * inv;
+        u[a * N + id] = (s + kap * us[a]) * inv;
     }
 }
 
@@ -696,7 +702,7 @@ __global__ __launch_bounds__(256) void k_spread_map(Grid g, Design D, const doub
     x[1] = (int)((id / g.n[0]) % g.n[1]);
     x[2] = (int)(id / ((long long)g.n[0] * g.n[1]));
     T kap = 0, us[3] = {0, 0, 0};
-    if (is_interior<DIM>(g, x)) spread_node<DIM, T, true>(D, B, krT, x, 0, kap, us);
+    if (is_interior<DIM>(g, x)) spread_node<DIM, T, true>(D, B, krT, x, 0, kap, us, nullptr);
     kap_out[id] = kap;
 #pragma unroll
     for (int a = 0; a < DIM; a++) us_out[a * g.N + id] = us[a];
@@ -1232,10 +1238,10 @@ __global__ __launch_bounds__(It2<TT>::NT) void k_iter2d(Grid g, Design D, BodyPa
                         const int li = min(max(ii - hi0, 0), HE - 1), lj = min(max(jj - hj0, 0), HE - 1);
                         return kh[lj * HE + li];
                     },
-                    x, q, kap, us);
+                    x, q, kap, us, g.U);
                 const T inv = T(1) / (T(1) + kap);
-                v0 = (v0 + kap * (us[0] - gU<T>(g, 0))) * inv;
-                v1 = (v1 + kap * (us[1] - gU<T>(g, 1))) * inv;
+                v0 = (v0 + kap * us[0]) * inv;
+                v1 = (v1 + kap * us[1]) * inv;
             }
         }
         if (q == 0 && px < sx && py < sy) {
@@ -1344,7 +1350,7 @@ __global__ __launch_bounds__(256) void k_iter_final2d(Grid g, Design D, BodyPara
     box_origin<2>(D, Bk, o);
     if (!box_node<2>(g, D, o, l, x)) return;
     T kap, us[3];
-    spread_node<2, T, ROT, LPN>(D, Bk + (K - 1) * B_REC, krT, x, q, kap, us);
+    spread_node<2, T, ROT, LPN>(D, Bk + (K - 1) * B_REC, krT, x, q, kap, us, g.U);
     if (q != 0) return;
     const long long N = g.N;
     const long long id = node_id(g, x[0], x[1], x[2]);
@@ -1353,7 +1359,7 @@ __global__ __launch_bounds__(256) void k_iter_final2d(Grid g, Design D, BodyPara
     for (int a = 0; a < 2; a++) {
         const T s = u[a * N + id];
         ustar[a * D.boxN + l] = s;
-        u[a * N + id] = (s + kap * (us[a] - gU<T>(g, a))) * inv;
+        u[a * N + id] = (s + kap * us[a]) * inv;
     }
 }
 
@@ -1423,9 +1429,9 @@ __global__ __launch_bounds__(256) void k_adj_recompute(Grid g, Design D, const d
         if constexpr (DIM == 3)  // axial sums of kappa_ref at B^(k) in K1 + k NA NP (k_axial)
             spread_node_ax<T, ROT, LPN>(D, Bk + k * B_REC, axial_of(D, Bk + k * B_REC),
                                         K1 + (long long)k * (D.nd[D.axis] + 4) * D.nd[D.pi] * D.nd[D.pj], x, q,
-                                        kap, us);
+                                        kap, us, g.U);
         else
-            spread_node<DIM, T, ROT, LPN>(D, Bk + k * B_REC, krT, x, q, kap, us);
+            spread_node<DIM, T, ROT, LPN>(D, Bk + k * B_REC, krT, x, q, kap, us, g.U);
     }
     if (q != 0) return;
     kapk[k * bN + l] = kap;
@@ -1433,7 +1439,7 @@ __global__ __launch_bounds__(256) void k_adj_recompute(Grid g, Design D, const d
 #pragma unroll
     for (int a = 0; a < DIM; a++) {
         usk[(k * DIM + a) * bN + l] = us[a];
-        uk[(k * DIM + a) * bN + l] = ok ? (ustar[a * bN + l] + kap * (us[a] - gU<T>(g, a))) * inv : T(0);
+        uk[(k * DIM + a) * bN + l] = ok ? (ustar[a * bN + l] + kap * us[a]) * inv : T(0);
     }
 }
 
@@ -1463,13 +1469,13 @@ __global__ __launch_bounds__(256) void k_adj_recompute_rows(Grid g, Design D, co
         int x[3];
         const bool ok = br.node(g, D, o, ba, l, x);
         T kap = 0, us[3] = {0, 0, 0};
-        if (ok) spread_node_row<T, ROT>(D, B, ax, K1k, x[D.axis], pr, kap, us);
+        if (ok) spread_node_row<T, ROT>(D, B, ax, K1k, x[D.axis], pr, kap, us, g.U);
         kapk[k * bN + l] = kap;
         const T inv = T(1) / (T(1) + kap);
 #pragma unroll
         for (int a = 0; a < 3; a++) {
             usk[(k * 3 + a) * bN + l] = us[a];
-            uk[(k * 3 + a) * bN + l] = ok ? (ustar[a * bN + l] + kap * (us[a] - gU<T>(g, a))) * inv : T(0);
+            uk[(k * 3 + a) * bN + l] = ok ? (ustar[a * bN + l] + kap * us[a]) * inv : T(0);
         }
     }
 }
@@ -1735,7 +1741,7 @@ __global__ __launch_bounds__(256) void k_adj_r2(Grid g, Bc bc, Design D, const d
 #pragma unroll
         for (int a = 0; a < DIM; a++) {
             ust[a] = k == K - 1 ? T(0) : ustb[a * bN + l];
-            dus[a] = (usk[(k * DIM + a) * bN + l] - gU<T>(g, a)) - uk[(k * DIM + a) * bN + l];
+            dus[a] = usk[(k * DIM + a) * bN + l] - uk[(k * DIM + a) * bN + l];
         }
     }
     T ub[3] = {0, 0, 0};
@@ -1893,7 +1899,7 @@ __global__ __launch_bounds__(256) void k_adj_r2_rows(Grid g, Bc bc, Design D, co
 #pragma unroll
         for (int a = 0; a < 3; a++) {
             ust[a] = k == K - 1 ? T(0) : ustb[a * bN + l];
-            dus[a] = (usk[(k * 3 + a) * bN + l] - gU<T>(g, a)) - uk[(k * 3 + a) * bN + l];
+            dus[a] = usk[(k * 3 + a) * bN + l] - uk[(k * 3 + a) * bN + l];
         }
         T ub[3] = {0, 0, 0};
         const int ib = x[D.axis] + ax.fl;

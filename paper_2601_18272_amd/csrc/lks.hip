@@ -277,13 +277,16 @@ int make_ctx(const lks_problem_t *P, Ctx &c) {
         c.bc.p[f] = P->bc_p[f];
         for (int a = 0; a < 3; a++) c.bc.u[f][a] = P->bc_u[f][a];
     }
-    // reference velocity of the stored deviation v = u - U: the first VELOCITY face's
+    // reference velocity of the stored deviation v = u - U: the first VELOCITY face's,
+    // rounded to FP32, so that U and -U (the deviation of a wall or of a fluid at rest)
+    // are exact in FP32 fields; the inflow's own deviation is then a tiny number that
+    // FP32 holds to its full relative precision
     for (int a = 0; a < 3; a++) c.g.U[a] = 0.0;
     for (int f = 0; f < 2 * c.dim; f++)
         if (c.bc.kind[f] == LKS_VELOCITY) {
             for (int a = 0; a < c.dim; a++) {
                 if (!std::isfinite(c.bc.u[f][a])) return fail(LKS_EINVAL, "bc_u not finite");
-                c.g.U[a] = c.bc.u[f][a];
+                c.g.U[a] = (double)(float)c.bc.u[f][a];
             }
             break;
         }
