@@ -461,14 +461,20 @@ __global__ __launch_bounds__(512) void k_gather2d(Grid g, T A, Bc bc, int fold, 
 }
 
 // ===================================================================== forward, 3D
-// 2.5D blocking. A block of TX x TY threads is the tile of source columns (x, y) whose
-// f_i it evaluates, one column per thread; it writes the inner (TX-2) x (TY-2) columns
-// and marches along z over ZC output planes. Per source plane s each thread evaluates
-// the 15 f_i of its node into LDS and pushes them (by the gather of its output column)
-// to the destination planes s-1, s, s+1, whose moments it keeps in registers. The
-// thread's own column of p, u for planes s-2..s+2 (the z-derivative, one-sided at a
-// wall, reaches two planes) lives in registers, filled one plane ahead; only u of
-// plane s with a one-node ring is staged in LDS for the x and y derivatives.
+// 2.5D blocking. A block of TX x TY threads (one wave per row of 64 columns) is the tile
+// of source columns (x, y) whose f_i it evaluates, one column per thread; it writes the
+// inner (TX-2) x (TY-2) columns and marches along z over ZC output planes. Per source
+// plane s each thread evaluates the 15 f_i of its node into LDS and pushes them (by the
+// gather of its output column) to the destination planes s-1, s, s+1, whose moments it
+// keeps in registers. The thread's own column of p, u for planes s-2..s+2 lives in
+// registers, loaded three planes ahead; u of plane s with a one-node ring is staged in
+// LDS for the x and y derivatives. The march is unrolled six planes deep, so the plane
+// ring (six slots), the destination ring (three) and the ring-node buffer (two) are
+// addressed by constants. Derivatives are central; the second-order one-sided forms at
+// the nodes of a non-periodic wall are applied in branches that are uniform over a wave
+// (a y-wall row, a tile holding an x-wall column) or over the block (a z-wall plane).
+// Loads and stores go through buffer resources: a lane off the grid reads zeros and
+// writes nothing.
 template <typename T> struct G3 {
     static constexpr int TX = 64, TY = 8, NT = TX * TY;
     static constexpr int OX = TX - 2, OY = TY - 2;  // output tile
@@ -476,15 +482,21 @@ template <typename T> struct G3 {
     static constexpr int RING = 2 * WX + 2 * TY;    // staged nodes outside the tile
 };
 
-// Twice the derivative along one axis from the values at offsets -2..2: central in the
-// interior and on periodic axes, second-order one-sided on the end nodes of a
-// non-periodic axis.
+// Resource over component c of plane p of a field of N-node components (zero size when
+// p is off the grid, so that every load returns 0). The plane's bytes stay below
+// BOFF_NONE (checked on the host).
 template <typename T>
-__device__ __forceinline__ T d2(T m2, T m1, T c, T p1, T p2, int v, int n, int per) {
-    T d = p1 - m1;
-    if (!per && (v == 0 || v == n - 1)) d = v == 0 ? T(-3) * c + T(4) * p1 - p2 : T(3) * c - T(4) * m1 + m2;
-    return d;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const T *base, long long N, int c, int p, int nz,
+                                                              int pz, unsigned plane) {
+    int zw = p;
+    const bool ok = wrap_coord(zw, nz, pz);
+    return brsrc(base + (long long)c * N + (long long)(ok ? zw : 0) * plane, ok ? plane * (unsigned)sizeof(T) : 0u);
 }
+
+// Second-order one-sided doubled derivatives at the first (lo) and last (hi) node of a
+// non-periodic axis: c the node, p1, p2 (m1, m2) the next (previous) nodes along the axis.
+template <typename T> __device__ __forceinline__ T d2_lo(T c, T p1, T p2) { return T(-3) * c + T(4) * p1 - p2; }
+template <typename T> __device__ __forceinline__ T d2_hi(T c, T m1, T m2) { return T(3) * c - T(4) * m1 + m2; }
 
 // Weighted equilibria F_i = w_i f_i of one D3Q15 node (Lat<3> order), from p, u and
 // D[a][b] = 2 d_a u_b. Opposite directions share the quadratic part and differ in the
@@ -546,20 +558,25 @@ __global__ __launch_bounds__(G3<T>::NT, sizeof(T) == 4 ? 6 : 2) void k_gather3d(
                                                         unsigned long long *ts) {
     using G = G3<T>;
     constexpr int TX = G::TX, TY = G::TY, WX = G::WX, WY = G::WY;
-    __shared__ T wu[2][3][WY][WX];
+    // u of plane s (one buffer: its readers pass the second barrier of a plane before
+    // anyone stages the next one)
+    __shared__ T wu[3][WY][WX];
     __shared__ T fb[15][TY][TX];
     if (SP) span_begin(ts);
     const long long N = g.N;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const int px = g.per[0], py = g.per[1], pz = g.per[2];
     const uint3 tb = xcd_tile();
     const int x0 = tb.x * G::OX, y0 = tb.y * G::OY;
     const int z0 = tb.z * ZC, z1 = min(z0 + ZC, nz);
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TX * ty;
+    // a wave is one row of the tile: ty is uniform over it
+    const int tx = threadIdx.x, ty = __builtin_amdgcn_readfirstlane(threadIdx.y), tid = tx + TX * ty;
+    const unsigned plane = (unsigned)nx * (unsigned)ny, pbytes = plane * (unsigned)sizeof(T);
 
     // this thread's source column
     int cx = x0 - 1 + tx, cy = y0 - 1 + ty;
-    const bool colok = wrap_coord(cx, nx, g.per[0]) && wrap_coord(cy, ny, g.per[1]);
-    const long long col = colok ? (long long)cx + (long long)nx * cy : 0;
+    const bool colok = wrap_coord(cx, nx, px) && wrap_coord(cy, ny, py);
+    const unsigned coff = colok ? ((unsigned)cx + (unsigned)nx * (unsigned)cy) * (unsigned)sizeof(T) : BOFF_NONE;
     // ring node of the staged plane handled by this thread (tid < RING)
     int rx = 0, ry = 0;
     if (tid < 2 * WX) {
@@ -571,116 +588,131 @@ __global__ __launch_bounds__(G3<T>::NT, sizeof(T) == 4 ? 6 : 2) void k_gather3d(
         rx = (k & 1) ? WX - 1 : 0;
     }
     int gx = x0 - 2 + rx, gy = y0 - 2 + ry;
-    const bool ringok = tid < G::RING && wrap_coord(gx, nx, g.per[0]) && wrap_coord(gy, ny, g.per[1]);
-    const long long rcol = ringok ? (long long)gx + (long long)nx * gy : 0;
+    const bool ringok = tid < G::RING && wrap_coord(gx, nx, px) && wrap_coord(gy, ny, py);
+    const unsigned roff = ringok ? ((unsigned)gx + (unsigned)nx * (unsigned)gy) * (unsigned)sizeof(T) : BOFF_NONE;
+    // output node (x0 + tx, y0 + ty), written when it is an interior node of the x-y plane
+    const int ox = x0 + tx, oy = y0 + ty;
+    const bool outrow = ty < G::OY;
+    const bool outok = tx < G::OX && outrow && ox < nx && oy < ny && !(!px && (ox == 0 || ox == nx - 1)) &&
+                       !(!py && (oy == 0 || oy == ny - 1));
+    const unsigned ooff = outok ? ((unsigned)ox + (unsigned)nx * (unsigned)oy) * (unsigned)sizeof(T) : BOFF_NONE;
+    // one-sided derivatives: the tile holds an x-wall column (block-uniform), the lane's
+    // column is one (1 first, 2 last), the wave's row is a y-wall row (wave-uniform)
+    const bool xw = !px && (x0 - 1 <= 0 || x0 + TX - 2 >= nx - 1);
+    const T xlo = (!px && colok && cx == 0) ? T(1) : T(0), xhi = (!px && colok && cx == nx - 1) ? T(1) : T(0);
+    const int ys = (!py && cy >= 0 && cy < ny) ? (cy == 0 ? 1 : (cy == ny - 1 ? 2 : 0)) : 0;
 
-    const long long plane = (long long)nx * ny;
-    auto load_col = [&](int zp, T v[4]) {
-        int zw = zp;
-        const bool ok = colok && wrap_coord(zw, nz, g.per[2]);
-        const long long id = col + plane * zw;
+    T q[6][4];  // own column: plane s + k in slot (J + k + 2) mod 6 at unrolled step J
 #pragma unroll
-        for (int c = 0; c < 4; c++) v[c] = ok ? sin_[c * N + id] : T(0);
-    };
-    auto load_ring = [&](int zp, T v[3]) {
-        int zw = zp;
-        const bool ok = ringok && wrap_coord(zw, nz, g.per[2]);
-        const long long id = rcol + plane * zw;
+    for (int j = 0; j < 5; j++)
 #pragma unroll
-        for (int c = 0; c < 3; c++) v[c] = ok ? sin_[(c + 1) * N + id] : T(0);
-    };
+        for (int c = 0; c < 4; c++) q[j][c] = bload<T>(plane_rsrc(sin_, N, c, z0 - 3 + j, nz, pz, plane), coff);
+    T rv[3];  // ring node of plane s (reloaded with plane s + 1 once staged)
+    if (tid < G::RING) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) rv[c] = bload<T>(plane_rsrc(sin_, N, 1 + c, z0 - 1, nz, pz, plane), roff);
+    }
+    T acc[3][4];  // destination plane s + k in slot (J + k + 1) mod 3
+#pragma unroll
+    for (int k = 0; k < 3; k++) acc[k][0] = acc[k][1] = acc[k][2] = acc[k][3] = T(0);
 
-    T q[5][4];  // own column, planes s-2 .. s+2
+    const int nsteps = z1 - z0 + 2;  // source planes z0 - 1 .. z1
+    for (int jb = 0; jb < nsteps; jb += 6) {
 #pragma unroll
-    for (int j = 0; j < 5; j++) load_col(z0 - 3 + j, q[j]);
-    T rv[3];
-    load_ring(z0 - 1, rv);
-
-    T accP[3] = {0, 0, 0}, accU[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    for (int s = z0 - 1; s <= z1; s++) {
-        const int b = s & 1;
-        // stage u of plane s: own node and ring node
+        for (int J = 0; J < 6; J++) {
+            if (jb + J < nsteps) {
+            const int s = z0 - 1 + jb + J;
+            const int qm2 = J % 6, qm1 = (J + 1) % 6, qc = (J + 2) % 6, qp1 = (J + 3) % 6, qp2 = (J + 4) % 6,
+                      qp3 = (J + 5) % 6;
+            // stage u of plane s: own node and ring node
 #pragma unroll
-        for (int c = 0; c < 3; c++) wu[b][c][ty + 1][tx + 1] = q[2][1 + c];
-        if (tid < G::RING) {
+            for (int c = 0; c < 3; c++) wu[c][ty + 1][tx + 1] = q[qc][1 + c];
+            if (tid < G::RING) {
 #pragma unroll
-            for (int c = 0; c < 3; c++) wu[b][c][ry][rx] = rv[c];
-        }
-        // next planes in flight while this one is evaluated
-        const bool more = s + 3 <= z1 + 2;
-        T nq[4], nr[3];
-        if (more) load_col(s + 3, nq);
-        if (s + 1 <= z1) load_ring(s + 1, nr);
-        __syncthreads();
-
-        // Sources off the grid (non-periodic axes) only feed boundary nodes, which this
-        // kernel does not write; their f_i are evaluated from zeros and never used.
-        int zs = s;
-        (void)wrap_coord(zs, nz, g.per[2]);
-        T f[15];
-        {
-            const int lx = tx + 1, ly = ty + 1;
-            T D[3][3];  // D[a][b] = 2 d_a u_b
-#pragma unroll
-            for (int c = 0; c < 3; c++) {
-                const T(*U)[WX] = wu[b][c];
-                D[0][c] = d2(U[ly][lx - 2 < 0 ? 0 : lx - 2], U[ly][lx - 1], U[ly][lx], U[ly][lx + 1],
-                             U[ly][lx + 2 >= WX ? WX - 1 : lx + 2], cx, nx, g.per[0]);
-                D[1][c] = d2(U[ly - 2 < 0 ? 0 : ly - 2][lx], U[ly - 1][lx], U[ly][lx], U[ly + 1][lx],
-                             U[ly + 2 >= WY ? WY - 1 : ly + 2][lx], cy, ny, g.per[1]);
-                D[2][c] = d2(q[0][1 + c], q[1][1 + c], q[2][1 + c], q[3][1 + c], q[4][1 + c], zs, nz, g.per[2]);
+                for (int c = 0; c < 3; c++) wu[c][ry][rx] = rv[c];
             }
-            const T u[3] = {q[2][1], q[2][2], q[2][3]};
-            feq3(q[2][0], u, fu, D, A, f);
-        }
+            // next planes in flight while this one is evaluated: the ring node first (it is
+            // staged at the next plane, and the wait for it must not drain the own column's
+            // loads, which run three planes ahead)
+            if (s + 1 <= z1 && tid < G::RING) {
 #pragma unroll
-        for (int i = 0; i < 15; i++) fb[i][ty][tx] = f[i];
-        __syncthreads();
-
-        const bool out = tx < G::OX && ty < G::OY;
-        if (out) {
-#pragma unroll
-            for (int i = 0; i < 15; i++) {
-                const int ex = Lat<3>::c(i, 0), ey = Lat<3>::c(i, 1), ez = Lat<3>::c(i, 2);
-                const T v = fb[i][ty + 1 - ey][tx + 1 - ex];
-                accP[ez + 1] += v;
-                accU[ez + 1][0] += T(ex) * v;
-                accU[ez + 1][1] += T(ey) * v;
-                accU[ez + 1][2] += T(ez) * v;
+                for (int c = 0; c < 3; c++)
+                    rv[c] = bload<T>(plane_rsrc(sin_, N, 1 + c, s + 1, nz, pz, plane), roff);
             }
-            // destination plane s - 1 has received all its sources
-            const int zd = s - 1, x = x0 + tx, y = y0 + ty;
-            if (zd >= z0 && zd < z1 && x < nx && y < ny) {
-                const int xx[3] = {x, y, zd};
-                if (is_interior<3>(g, xx)) {
-                    const long long id = (long long)x + (long long)nx * ((long long)y + (long long)ny * zd);
-                    sout[id] = accP[0] * T(1.0 / 3.0);
+            if (s + 3 <= z1 + 2) {
 #pragma unroll
-                    for (int a = 0; a < 3; a++) sout[(1 + a) * N + id] = accU[0][a];
+                for (int c = 0; c < 4; c++) q[qp3][c] = bload<T>(plane_rsrc(sin_, N, c, s + 3, nz, pz, plane), coff);
+            }
+            __syncthreads();
+
+            // Sources off the grid (non-periodic axes) only feed boundary nodes, which this
+            // kernel does not write; their f_i are evaluated from zeros and never used.
+            int zs = s;
+            (void)wrap_coord(zs, nz, pz);
+            T f[15];
+            {
+                const int lx = tx + 1, ly = ty + 1;
+                T D[3][3];  // D[a][b] = 2 d_a u_b
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    D[0][c] = wu[c][ly][lx + 1] - wu[c][ly][lx - 1];
+                    D[1][c] = wu[c][ly + 1][lx] - wu[c][ly - 1][lx];
+                    D[2][c] = q[qp1][1 + c] - q[qm1][1 + c];
+                }
+                if (xw) {  // blend in the one-sided form on the wall lane (weights 0 or 1)
+#pragma unroll
+                    for (int c = 0; c < 3; c++) {
+                        const T(*U)[WX] = wu[c];
+                        const T m2 = U[ly][lx - 2 < 0 ? 0 : lx - 2], p2 = U[ly][lx + 2 >= WX ? WX - 1 : lx + 2];
+                        const T lo = d2_lo(U[ly][lx], U[ly][lx + 1], p2), hi = d2_hi(U[ly][lx], U[ly][lx - 1], m2);
+                        D[0][c] = D[0][c] + xlo * (lo - D[0][c]) + xhi * (hi - D[0][c]);
+                    }
+                }
+                if (ys) {
+#pragma unroll
+                    for (int c = 0; c < 3; c++) {
+                        const T(*U)[WX] = wu[c];
+                        D[1][c] = ys == 1 ? d2_lo(U[ly][lx], U[ly + 1][lx], U[ly + 2 >= WY ? WY - 1 : ly + 2][lx])
+                                          : d2_hi(U[ly][lx], U[ly - 1][lx], U[ly - 2 < 0 ? 0 : ly - 2][lx]);
+                    }
+                }
+                if (!pz && (zs == 0 || zs == nz - 1)) {
+#pragma unroll
+                    for (int c = 0; c < 3; c++)
+                        D[2][c] = zs == 0 ? d2_lo(q[qc][1 + c], q[qp1][1 + c], q[qp2][1 + c])
+                                          : d2_hi(q[qc][1 + c], q[qm1][1 + c], q[qm2][1 + c]);
+                }
+                const T u[3] = {q[qc][1], q[qc][2], q[qc][3]};
+                feq3(q[qc][0], u, fu, D, A, f);
+            }
+#pragma unroll
+            for (int i = 0; i < 15; i++) fb[i][ty][tx] = f[i];
+            __syncthreads();
+
+            if (outrow && tx < G::OX) {
+                const int km = J % 3, k0 = (J + 1) % 3, kp = (J + 2) % 3;
+#pragma unroll
+                for (int c = 0; c < 4; c++) acc[kp][c] = T(0);
+#pragma unroll
+                for (int i = 0; i < 15; i++) {
+                    const int ex = Lat<3>::c(i, 0), ey = Lat<3>::c(i, 1), ez = Lat<3>::c(i, 2);
+                    const int k = ez < 0 ? km : (ez == 0 ? k0 : kp);
+                    const T v = fb[i][ty + 1 - ey][tx + 1 - ex];
+                    acc[k][0] += v;
+                    if (ex) acc[k][1] += T(ex) * v;
+                    if (ey) acc[k][2] += T(ey) * v;
+                    if (ez) acc[k][3] += T(ez) * v;
+                }
+                // destination plane s - 1 has received all its sources
+                const int zd = s - 1;
+                if (zd >= z0 && zd < z1 && !(!pz && (zd == 0 || zd == nz - 1))) {
+                    const long long zo = (long long)zd * plane;
+                    bstore(acc[km][0] * T(1.0 / 3.0), brsrc(sout + zo, pbytes), ooff);
+#pragma unroll
+                    for (int a = 0; a < 3; a++) bstore(acc[km][1 + a], brsrc(sout + (1 + a) * N + zo, pbytes), ooff);
                 }
             }
-        }
-        accP[0] = accP[1];
-        accP[1] = accP[2];
-        accP[2] = 0;
-#pragma unroll
-        for (int a = 0; a < 3; a++) {
-            accU[0][a] = accU[1][a];
-            accU[1][a] = accU[2][a];
-            accU[2][a] = 0;
-        }
-#pragma unroll
-        for (int j = 0; j < 4; j++) {
-#pragma unroll
-            for (int c = 0; c < 4; c++) q[j][c] = q[j + 1][c];
-        }
-        if (more) {
-#pragma unroll
-            for (int c = 0; c < 4; c++) q[4][c] = nq[c];
-        }
-        if (s + 1 <= z1) {
-#pragma unroll
-            for (int c = 0; c < 3; c++) rv[c] = nr[c];
+            }
         }
     }
     if (SP) span_end(ts);
@@ -1403,8 +1435,28 @@ template <typename T> struct A3 {
     static constexpr int RING = 2 * WX + 2 * TY;
 };
 
-// ab as prepared by k_adj_fold3d and k_adj_clear3d.
-template <typename T, bool SP>
+// g = (p*bar, u*bar) of plane p at the own column (v[0..3]) and, for ring threads, at the
+// ring node (v[4..7]); zeros off the grid.
+template <typename T>
+__device__ __forceinline__ void a3_load(const T *ab, long long N, int p, int nz, int pz, unsigned plane,
+                                        unsigned coff, unsigned roff, bool ring, T v[8]) {
+#pragma unroll
+    for (int c = 0; c < 4; c++) v[c] = bload<T>(plane_rsrc(ab, N, c, p, nz, pz, plane), coff);
+    if (ring) {
+#pragma unroll
+        for (int c = 0; c < 4; c++) v[4 + c] = bload<T>(plane_rsrc(ab, N, c, p, nz, pz, plane), roff);
+    }
+}
+
+// ab as prepared by k_adj_fold3d and k_adj_clear3d. The march is unrolled six planes
+// deep: the sig history ring (six slots), the partial-output ring and the LDS plane ring
+// (three) and the g registers (two) are addressed by constants. g is loaded two planes
+// ahead, the previous state one plane ahead and first, so that waiting for it does not
+// drain the g loads. Loads and stores go through buffer resources (a lane off the grid
+// reads zeros and writes nothing). The transposes are central; the one-sided forms near
+// a non-periodic wall are taken in branches uniform over the block (x), the wave (y) or
+// the plane (z). UPS: also store the moment ups itself (the paper's u~*).
+template <typename T, bool SP, bool UPS>
 __global__ __launch_bounds__(A3<T>::NT, sizeof(T) == 4 ? 4 : 2) void k_adjgather3d(
     Grid g, T A, int ZC, int offx, int offy, const T *__restrict__ ab, const T *__restrict__ sprev,
     T *__restrict__ out, unsigned long long *ts, T *__restrict__ ups) {
@@ -1415,14 +1467,19 @@ __global__ __launch_bounds__(A3<T>::NT, sizeof(T) == 4 ? 4 : 2) void k_adjgather
     if (SP) span_begin(ts);
     const long long N = g.N;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const int px = g.per[0], py = g.per[1], pz = g.per[2];
+    const T U0 = gU<T>(g, 0), U1 = gU<T>(g, 1), U2 = gU<T>(g, 2);
     const uint3 tb = xcd_tile();
     const int x0 = (int)tb.x * G::OX - offx, y0 = (int)tb.y * G::OY - offy;
     const int z0 = tb.z * ZC, z1 = min(z0 + ZC, nz);
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TX * ty;
+    // a wave is one row of the tile: ty is uniform over it
+    const int tx = threadIdx.x, ty = __builtin_amdgcn_readfirstlane(threadIdx.y), tid = tx + TX * ty;
+    const unsigned plane = (unsigned)nx * (unsigned)ny, pbytes = plane * (unsigned)sizeof(T);
     // own column (x, y as the output node when inside the output tile)
     const int ox = x0 - 1 + tx, oy = y0 - 1 + ty;
     int cx = ox, cy = oy;
-    const bool colok = wrap_coord(cx, nx, g.per[0]) && wrap_coord(cy, ny, g.per[1]);
+    const bool colok = wrap_coord(cx, nx, px) && wrap_coord(cy, ny, py);
+    const unsigned coff = colok ? ((unsigned)cx + (unsigned)nx * (unsigned)cy) * (unsigned)sizeof(T) : BOFF_NONE;
     // ring node of the g planes handled by this thread (tid < RING)
     int rx = 0, ry = 0;
     if (tid < 2 * WX) {
@@ -1434,181 +1491,197 @@ __global__ __launch_bounds__(A3<T>::NT, sizeof(T) == 4 ? 4 : 2) void k_adjgather
         rx = (k & 1) ? WX - 1 : 0;
     }
     int gx = x0 - 2 + rx, gy = y0 - 2 + ry;
-    const bool ringok = tid < G::RING && wrap_coord(gx, nx, g.per[0]) && wrap_coord(gy, ny, g.per[1]);
-    const long long cid = (long long)cx + (long long)nx * cy, rid = (long long)gx + (long long)nx * gy;
-    const long long plane = (long long)nx * ny;
-
-    // g at plane zp of the own column and the ring node (zero off the grid)
-    T gc[4], gq[4];
-    auto load = [&](int zp) {
-        int zw = zp;
-        const bool zok = wrap_coord(zw, nz, g.per[2]);
-        const long long zo = (long long)zw * plane;
-#pragma unroll
-        for (int c = 0; c < 4; c++) gc[c] = (zok && colok) ? ab[c * N + zo + cid] : T(0);
-#pragma unroll
-        for (int c = 0; c < 4; c++) gq[c] = (zok && ringok) ? ab[c * N + zo + rid] : T(0);
-    };
-    auto store = [&](int zp) {
-        const int sl = ((zp % 3) + 3) % 3;
-        gr[sl][0][ty + 1][tx + 1] = gc[0] * T(1.0 / 3.0);
-#pragma unroll
-        for (int c = 1; c < 4; c++) gr[sl][c][ty + 1][tx + 1] = gc[c];
-        if (tid < G::RING) {
-            gr[sl][0][ry][rx] = gq[0] * T(1.0 / 3.0);
-#pragma unroll
-            for (int c = 1; c < 4; c++) gr[sl][c][ry][rx] = gq[c];
-        }
-    };
-
+    const bool ring = tid < G::RING;
+    const bool ringok = ring && wrap_coord(gx, nx, px) && wrap_coord(gy, ny, py);
+    const unsigned roff = ringok ? ((unsigned)gx + (unsigned)nx * (unsigned)gy) * (unsigned)sizeof(T) : BOFF_NONE;
     const bool outcol = tx >= 1 && tx <= G::OX && ty >= 1 && ty <= G::OY && ox >= 0 && ox < nx && oy >= 0 &&
                         oy < ny;
-    const long long oid = (long long)ox + (long long)nx * oy;
-    // previous state u at the output column of plane s (loaded a plane ahead)
-    T uc[3] = {0, 0, 0};
-    auto load_u = [&](int zp) {
-        const bool ok = outcol && zp >= z0 && zp < z1;
-#pragma unroll
-        for (int a = 0; a < 3; a++) uc[a] = ok ? gU<T>(g, a) + sprev[(1 + a) * N + (long long)zp * plane + oid] : T(0);
-    };
-    T part[3][4];  // local + in-plane terms of planes s-2, s-1, s
-    T hz[5][3];    // sig_xz, sig_yz, sig_zz of planes s-4 .. s
-#pragma unroll
-    for (int j = 0; j < 3; j++)
-#pragma unroll
-        for (int c = 0; c < 4; c++) part[j][c] = 0;
-#pragma unroll
-    for (int j = 0; j < 5; j++) hz[j][0] = hz[j][1] = hz[j][2] = 0;
+    const unsigned ooff = outcol ? ((unsigned)ox + (unsigned)nx * (unsigned)oy) * (unsigned)sizeof(T) : BOFF_NONE;
+    // some output column of the tile (x) / the wave's output row (y) lies within two
+    // nodes of a non-periodic wall, where the transposes are one-sided
+    const bool xnear = !px && (x0 <= 2 || x0 + G::OX - 1 >= nx - 3);
+    const bool ynear = !py && (oy <= 2 || oy >= ny - 3);
     const T A2 = T(2) * A;
     constexpr T w0 = T(2.0 / 9.0), w1 = T(1.0 / 9.0), w2 = T(1.0 / 72.0);
 
-    load(z0 - 3);
-    store(z0 - 3);
-    load(z0 - 2);
-    store(z0 - 2);
-    load(z0 - 1);
-    load_u(z0 - 2);
-    for (int s = z0 - 2; s <= z1 + 1; s++) {
-        store(s + 1);
-        const T u0 = uc[0], u1 = uc[1], u2 = uc[2];
-        if (s + 2 <= z1 + 2) load(s + 2);
-        load_u(s + 1);
-        __syncthreads();
-        // moments of plane s at the own node: g_i taken at the node + c_i
-        const int sm = ((s - 1) % 3 + 3) % 3, s0 = ((s % 3) + 3) % 3, sp = ((s + 1) % 3 + 3) % 3;
-        const int lx = tx + 1, ly = ty + 1;
-        T pi, up[3], sxx, syy, szz, sxy, sxz, syz;
-        {
-            // rest and axis pairs: s = g(+e) + g(-e), d = g(+e) - g(-e)
-            const T g0 = gr[s0][0][ly][lx];
-            T sa[3], da[3];
-            {
-                const T gp = gr[s0][0][ly][lx + 1] + gr[s0][1][ly][lx + 1];
-                const T gm = gr[s0][0][ly][lx - 1] - gr[s0][1][ly][lx - 1];
-                sa[0] = gp + gm;
-                da[0] = gp - gm;
-            }
-            {
-                const T gp = gr[s0][0][ly + 1][lx] + gr[s0][2][ly + 1][lx];
-                const T gm = gr[s0][0][ly - 1][lx] - gr[s0][2][ly - 1][lx];
-                sa[1] = gp + gm;
-                da[1] = gp - gm;
-            }
-            {
-                const T gp = gr[sp][0][ly][lx] + gr[sp][3][ly][lx];
-                const T gm = gr[sm][0][ly][lx] - gr[sm][3][ly][lx];
-                sa[2] = gp + gm;
-                da[2] = gp - gm;
-            }
-            // corner pairs (+,+,+), (+,+,-), (+,-,+), (+,-,-) and their opposites
-            T sc[4], dc[4];
-            constexpr int cyk[4] = {1, 1, -1, -1}, czk[4] = {1, -1, 1, -1};
+    auto stage = [&](int sl, const T v[8]) {
+        gr[sl][0][ty + 1][tx + 1] = v[0] * T(1.0 / 3.0);
 #pragma unroll
-            for (int k = 0; k < 4; k++) {
-                const int ey = cyk[k], ez = czk[k];
-                const int zl = ez > 0 ? sp : sm, zo = ez > 0 ? sm : sp;
-                const T gp = gr[zl][0][ly + ey][lx + 1] + gr[zl][1][ly + ey][lx + 1] +
-                             T(ey) * gr[zl][2][ly + ey][lx + 1] + T(ez) * gr[zl][3][ly + ey][lx + 1];
-                const T gm = gr[zo][0][ly - ey][lx - 1] - gr[zo][1][ly - ey][lx - 1] -
-                             T(ey) * gr[zo][2][ly - ey][lx - 1] - T(ez) * gr[zo][3][ly - ey][lx - 1];
-                sc[k] = gp + gm;
-                dc[k] = gp - gm;
-            }
-            const T scs = (sc[0] + sc[1]) + (sc[2] + sc[3]);
-            pi = w0 * g0 + w1 * (sa[0] + sa[1] + sa[2]) + w2 * scs;
-            up[0] = w1 * da[0] + w2 * ((dc[0] + dc[1]) + (dc[2] + dc[3]));
-            up[1] = w1 * da[1] + w2 * ((dc[0] + dc[1]) - (dc[2] + dc[3]));
-            up[2] = w1 * da[2] + w2 * ((dc[0] - dc[1]) + (dc[2] - dc[3]));
-            sxx = w1 * sa[0] + w2 * scs;
-            syy = w1 * sa[1] + w2 * scs;
-            szz = w1 * sa[2] + w2 * scs;
-            sxy = w2 * ((sc[0] + sc[1]) - (sc[2] + sc[3]));
-            sxz = w2 * ((sc[0] - sc[1]) + (sc[2] - sc[3]));
-            syz = w2 * ((sc[0] - sc[1]) - (sc[2] - sc[3]));
+        for (int c = 1; c < 4; c++) gr[sl][c][ty + 1][tx + 1] = v[c];
+        if (ring) {
+            gr[sl][0][ry][rx] = v[4] * T(1.0 / 3.0);
+#pragma unroll
+            for (int c = 1; c < 4; c++) gr[sl][c][ry][rx] = v[4 + c];
         }
-        sg[0][ty][tx] = sxx;
-        sg[1][ty][tx] = sxy;
-        sg[2][ty][tx] = sxz;
-        sg[3][ty][tx] = syy;
-        sg[4][ty][tx] = syz;
+    };
+
+    // planes z0-3, z0-2 staged (LDS slots 0, 1); z0-1, z0 in registers (slots 0, 1)
+    T gv[2][8];
+    a3_load(ab, N, z0 - 3, nz, pz, plane, coff, roff, ring, gv[0]);
+    stage(0, gv[0]);
+    a3_load(ab, N, z0 - 2, nz, pz, plane, coff, roff, ring, gv[1]);
+    stage(1, gv[1]);
+    a3_load(ab, N, z0 - 1, nz, pz, plane, coff, roff, ring, gv[0]);
+    a3_load(ab, N, z0, nz, pz, plane, coff, roff, ring, gv[1]);
+    T uc[3] = {0, 0, 0};  // U + v of the previous state at the output node of plane s
+    T hz[6][3];           // sig_xz, sig_yz, sig_zz of plane s + k in slot (J + k + 6) mod 6
+    T part[3][4];         // local + in-plane terms of plane s + k in slot (J + k + 3) mod 3
 #pragma unroll
-        for (int j = 0; j < 4; j++)
+    for (int j = 0; j < 6; j++) hz[j][0] = hz[j][1] = hz[j][2] = T(0);
 #pragma unroll
-            for (int c = 0; c < 3; c++) hz[j][c] = hz[j + 1][c];
-        hz[4][0] = sxz;
-        hz[4][1] = syz;
-        hz[4][2] = szz;
+    for (int j = 0; j < 3; j++) part[j][0] = part[j][1] = part[j][2] = part[j][3] = T(0);
+
+    const int nsteps = z1 - z0 + 4;  // planes s = z0 - 2 .. z1 + 1
+    for (int jb = 0; jb < nsteps; jb += 6) {
 #pragma unroll
-        for (int j = 0; j < 2; j++)
-#pragma unroll
-            for (int c = 0; c < 4; c++) part[j][c] = part[j + 1][c];
-        part[2][0] = part[2][1] = part[2][2] = part[2][3] = 0;
-        __syncthreads();
-        if (outcol && s >= z0 && s < z1) {
-            T o0 = T(3) * up[0] + T(9) * (sxx * u0 + sxy * u1 + sxz * u2) - T(3) * pi * u0;
-            T o1 = T(3) * up[1] + T(9) * (sxy * u0 + syy * u1 + syz * u2) - T(3) * pi * u1;
-            T o2 = T(3) * up[2] + T(9) * (sxz * u0 + syz * u1 + szz * u2) - T(3) * pi * u2;
-            T o[3] = {o0, o1, o2};
-            dT_apply3<T>(ox, nx, g.per[0], A2, [&](int d, T v[3]) {  // a = x: sig_xb -> u_b
-                const int xi = min(max(tx + d, 0), TX - 1);
-                v[0] = sg[0][ty][xi];
-                v[1] = sg[1][ty][xi];
-                v[2] = sg[2][ty][xi];
-            }, o);
-            dT_apply3<T>(oy, ny, g.per[1], A2, [&](int d, T v[3]) {  // a = y: sig_yb -> u_b
-                const int yi = min(max(ty + d, 0), TY - 1);
-                v[0] = sg[1][yi][tx];
-                v[1] = sg[3][yi][tx];
-                v[2] = sg[4][yi][tx];
-            }, o);
-            o0 = o[0];
-            o1 = o[1];
-            o2 = o[2];
-            part[2][0] = T(3) * pi;
-            part[2][1] = o0;
-            part[2][2] = o1;
-            part[2][3] = o2;
-            if (ups) {  // the moment ups itself (the paper's u~*), for its adjoint variant
-                const long long id = oid + (long long)s * plane;
-                ups[id] = up[0];
-                ups[N + id] = up[1];
-                ups[2 * N + id] = up[2];
+        for (int J = 0; J < 6; J++) {
+            if (jb + J < nsteps) {
+            const int s = z0 - 2 + jb + J;
+            const int sm = J % 3, s0 = (J + 1) % 3, sp = (J + 2) % 3;  // LDS slots of planes s-1, s, s+1
+            stage(sp, gv[J & 1]);
+            const T u0 = uc[0], u1 = uc[1], u2 = uc[2];
+            {
+                const int pu = s + 1;
+                const bool ok = pu >= z0 && pu < z1;
+                const long long zo = ok ? (long long)pu * plane : 0;
+                uc[0] = U0 + bload<T>(brsrc(sprev + N + zo, ok ? pbytes : 0u), ooff);
+                uc[1] = U1 + bload<T>(brsrc(sprev + 2 * N + zo, ok ? pbytes : 0u), ooff);
+                uc[2] = U2 + bload<T>(brsrc(sprev + 3 * N + zo, ok ? pbytes : 0u), ooff);
             }
-        }
-        const int zo = s - 2;
-        if (outcol && zo >= z0 && zo < z1) {
-            T o[3] = {part[0][1], part[0][2], part[0][3]};
-            // a = z: sig_zb -> u_b from the history (plane zo + d is entry d + 2)
-            dT_apply3<T>(zo, nz, g.per[2], A2, [&](int d, T v[3]) {
-                v[0] = hz[d + 2][0];
-                v[1] = hz[d + 2][1];
-                v[2] = hz[d + 2][2];
-            }, o);
-            const long long id = oid + (long long)zo * plane;
-            out[id] = part[0][0];
-            out[N + id] = o[0];
-            out[2 * N + id] = o[1];
-            out[3 * N + id] = o[2];
+            if (s + 3 <= z1 + 2) a3_load(ab, N, s + 3, nz, pz, plane, coff, roff, ring, gv[J & 1]);
+            __syncthreads();
+            // moments of plane s at the own node: g_i taken at the node + c_i
+            const int lx = tx + 1, ly = ty + 1;
+            T pi, up[3], sxx, syy, szz, sxy, sxz, syz;
+            {
+                // rest and axis pairs: s = g(+e) + g(-e), d = g(+e) - g(-e)
+                const T g0 = gr[s0][0][ly][lx];
+                T sa[3], da[3];
+                {
+                    const T gp = gr[s0][0][ly][lx + 1] + gr[s0][1][ly][lx + 1];
+                    const T gm = gr[s0][0][ly][lx - 1] - gr[s0][1][ly][lx - 1];
+                    sa[0] = gp + gm;
+                    da[0] = gp - gm;
+                }
+                {
+                    const T gp = gr[s0][0][ly + 1][lx] + gr[s0][2][ly + 1][lx];
+                    const T gm = gr[s0][0][ly - 1][lx] - gr[s0][2][ly - 1][lx];
+                    sa[1] = gp + gm;
+                    da[1] = gp - gm;
+                }
+                {
+                    const T gp = gr[sp][0][ly][lx] + gr[sp][3][ly][lx];
+                    const T gm = gr[sm][0][ly][lx] - gr[sm][3][ly][lx];
+                    sa[2] = gp + gm;
+                    da[2] = gp - gm;
+                }
+                // corner pairs (+,+,+), (+,+,-), (+,-,+), (+,-,-) and their opposites
+                T sc[4], dc[4];
+                constexpr int cyk[4] = {1, 1, -1, -1}, czk[4] = {1, -1, 1, -1};
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    const int ey = cyk[k], ez = czk[k];
+                    const int zl = ez > 0 ? sp : sm, zf = ez > 0 ? sm : sp;
+                    const T gp = gr[zl][0][ly + ey][lx + 1] + gr[zl][1][ly + ey][lx + 1] +
+                                 T(ey) * gr[zl][2][ly + ey][lx + 1] + T(ez) * gr[zl][3][ly + ey][lx + 1];
+                    const T gm = gr[zf][0][ly - ey][lx - 1] - gr[zf][1][ly - ey][lx - 1] -
+                                 T(ey) * gr[zf][2][ly - ey][lx - 1] - T(ez) * gr[zf][3][ly - ey][lx - 1];
+                    sc[k] = gp + gm;
+                    dc[k] = gp - gm;
+                }
+                const T scs = (sc[0] + sc[1]) + (sc[2] + sc[3]);
+                pi = w0 * g0 + w1 * (sa[0] + sa[1] + sa[2]) + w2 * scs;
+                up[0] = w1 * da[0] + w2 * ((dc[0] + dc[1]) + (dc[2] + dc[3]));
+                up[1] = w1 * da[1] + w2 * ((dc[0] + dc[1]) - (dc[2] + dc[3]));
+                up[2] = w1 * da[2] + w2 * ((dc[0] - dc[1]) + (dc[2] - dc[3]));
+                sxx = w1 * sa[0] + w2 * scs;
+                syy = w1 * sa[1] + w2 * scs;
+                szz = w1 * sa[2] + w2 * scs;
+                sxy = w2 * ((sc[0] + sc[1]) - (sc[2] + sc[3]));
+                sxz = w2 * ((sc[0] - sc[1]) + (sc[2] - sc[3]));
+                syz = w2 * ((sc[0] - sc[1]) - (sc[2] - sc[3]));
+            }
+            sg[0][ty][tx] = sxx;
+            sg[1][ty][tx] = sxy;
+            sg[2][ty][tx] = sxz;
+            sg[3][ty][tx] = syy;
+            sg[4][ty][tx] = syz;
+            hz[J][0] = sxz;
+            hz[J][1] = syz;
+            hz[J][2] = szz;
+            __syncthreads();
+            if (outcol && s >= z0 && s < z1) {
+                T o[3];
+                o[0] = T(3) * up[0] + T(9) * (sxx * u0 + sxy * u1 + sxz * u2) - T(3) * pi * u0;
+                o[1] = T(3) * up[1] + T(9) * (sxy * u0 + syy * u1 + syz * u2) - T(3) * pi * u1;
+                o[2] = T(3) * up[2] + T(9) * (sxz * u0 + syz * u1 + szz * u2) - T(3) * pi * u2;
+                if (xnear) {
+                    dT_apply3<T>(ox, nx, px, A2, [&](int d, T v[3]) {  // a = x: sig_xb -> u_b
+                        const int xi = min(max(tx + d, 0), TX - 1);
+                        v[0] = sg[0][ty][xi];
+                        v[1] = sg[1][ty][xi];
+                        v[2] = sg[2][ty][xi];
+                    }, o);
+                } else {
+                    const T km = A2 * T(0.5), kp = A2 * T(-0.5);
+#pragma unroll
+                    for (int c = 0; c < 3; c++) o[c] += km * sg[c][ty][tx - 1];
+#pragma unroll
+                    for (int c = 0; c < 3; c++) o[c] += kp * sg[c][ty][tx + 1];
+                }
+                if (ynear) {
+                    dT_apply3<T>(oy, ny, py, A2, [&](int d, T v[3]) {  // a = y: sig_yb -> u_b
+                        const int yi = min(max(ty + d, 0), TY - 1);
+                        v[0] = sg[1][yi][tx];
+                        v[1] = sg[3][yi][tx];
+                        v[2] = sg[4][yi][tx];
+                    }, o);
+                } else {
+                    const T km = A2 * T(0.5), kp = A2 * T(-0.5);
+                    o[0] += km * sg[1][ty - 1][tx];
+                    o[1] += km * sg[3][ty - 1][tx];
+                    o[2] += km * sg[4][ty - 1][tx];
+                    o[0] += kp * sg[1][ty + 1][tx];
+                    o[1] += kp * sg[3][ty + 1][tx];
+                    o[2] += kp * sg[4][ty + 1][tx];
+                }
+                const int ps = J % 3;
+                part[ps][0] = T(3) * pi;
+                part[ps][1] = o[0];
+                part[ps][2] = o[1];
+                part[ps][3] = o[2];
+                if (UPS) {  // the moment ups itself (the paper's u~*), for its adjoint variant
+                    const long long zo = (long long)s * plane;
+#pragma unroll
+                    for (int c = 0; c < 3; c++) bstore(up[c], brsrc(ups + c * N + zo, pbytes), ooff);
+                }
+            }
+            const int zo = s - 2;
+            if (outcol && zo >= z0 && zo < z1) {
+                const int ps = (J + 1) % 3;
+                T o[3] = {part[ps][1], part[ps][2], part[ps][3]};
+                // a = z: sig_zb -> u_b from the history (plane zo + d in slot (J + d + 4) mod 6)
+                if (!pz && (zo <= 2 || zo >= nz - 3)) {
+                    dT_apply3<T>(zo, nz, pz, A2, [&](int d, T v[3]) {
+                        const int h = (J + d + 4) % 6;
+                        v[0] = hz[h][0];
+                        v[1] = hz[h][1];
+                        v[2] = hz[h][2];
+                    }, o);
+                } else {
+                    const T km = A2 * T(0.5), kp = A2 * T(-0.5);
+                    const int hm = (J + 3) % 6, hp = (J + 5) % 6;
+#pragma unroll
+                    for (int c = 0; c < 3; c++) o[c] += km * hz[hm][c];
+#pragma unroll
+                    for (int c = 0; c < 3; c++) o[c] += kp * hz[hp][c];
+                }
+                const long long zoff = (long long)zo * plane;
+                bstore(part[ps][0], brsrc(out + zoff, pbytes), ooff);
+#pragma unroll
+                for (int c = 0; c < 3; c++) bstore(o[c], brsrc(out + (1 + c) * N + zoff, pbytes), ooff);
+            }
+            }
         }
     }
     if (SP) span_end(ts);

@@ -341,6 +341,8 @@ int make_ctx(const lks_problem_t *P, Ctx &c) {
     if (c.has_body && D.boxN > 0x7fffffffLL) return fail(LKS_EINVAL, "design footprint box too large");
     if (c.has_body && D.ND > 0x7fffffffLL) return fail(LKS_EINVAL, "design grid too large");
     if (c.dim == 3 && layer_count(c.g.n, c.g.per) > 0x7fffffffLL) return fail(LKS_EINVAL, "grid faces too large");
+    // the 3D LKS kernels address one plane of a field with 32-bit byte offsets
+    if (c.dim == 3 && (long long)c.g.n[0] * c.g.n[1] * 8 >= (1LL << 31)) return fail(LKS_EINVAL, "grid plane too large");
     if (c.has_body && c.dim == 3 && (long long)(D.nd[D.axis] + 4) * D.nd[D.pi] * D.nd[D.pj] > 0x7fffffffLL)
         return fail(LKS_EINVAL, "design grid too large");
     c.dblk = c.dim == 3 ? Dblk<3>::v : Dblk<2>::v;
@@ -812,7 +814,7 @@ template <typename T> struct Run {
                     hipExtLaunchKernelGGL((k_adjgather2d<T, false>), grid, dim3(G2_TX, G2_TY), 0, st, e0, e1, 0,
                                           c.g, c.bc, T(c.A), ab, ustb, Bprev, c.D, hb, sprev, out, ts, ups);
             } else {
-                static const long long res = resident_blocks(k_adjgather3d<T, false>, A3<T>::NT);
+                static const long long res = resident_blocks(k_adjgather3d<T, false, false>, A3<T>::NT);
                 // shift the tiles of a non-periodic axis by one node where a tile
                 // boundary would fall on node n-2 (see k_adjgather3d)
                 const int offx = !c.g.per[0] && (c.g.n[0] - 2) % A3<T>::OX == 0 ? 1 : 0;
@@ -833,8 +835,12 @@ template <typename T> struct Run {
                                           0, c.g, ab, m, c.D, Bprev, ustb, hb);
                     es = nullptr;
                 }
-                hipExtLaunchKernelGGL((k_adjgather3d<T, false>), grid, dim3(A3<T>::TX, A3<T>::TY), 0, st, es, e1, 0,
-                                      c.g, T(c.A), zc, offx, offy, (const T *)ab, sprev, out, ts, ups);
+                if (ups)
+                    hipExtLaunchKernelGGL((k_adjgather3d<T, false, true>), grid, dim3(A3<T>::TX, A3<T>::TY), 0, st, es,
+                                          e1, 0, c.g, T(c.A), zc, offx, offy, (const T *)ab, sprev, out, ts, ups);
+                else
+                    hipExtLaunchKernelGGL((k_adjgather3d<T, false, false>), grid, dim3(A3<T>::TX, A3<T>::TY), 0, st,
+                                          es, e1, 0, c.g, T(c.A), zc, offx, offy, (const T *)ab, sprev, out, ts, ups);
             }
         });
     }

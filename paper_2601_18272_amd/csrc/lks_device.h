@@ -82,6 +82,30 @@ __device__ __forceinline__ bool wrap_coord(int &v, int n, int per) {
     return v >= 0 && v < n;
 }
 
+// Raw buffer access (gfx9 buffer resource, untyped dword access): a load at a byte
+// offset at or past the resource's size returns 0 and such a store is dropped, so a lane
+// is switched off by giving it the offset BOFF_NONE (the resource sizes used stay below
+// it). Offsets are 32-bit and the base is wave-uniform, so the per-lane address needs
+// no 64-bit arithmetic.
+constexpr unsigned BOFF_NONE = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t brsrc(const void *p, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T> __device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, unsigned off);
+template <> __device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+template <> __device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off, 0, 0);
+}
+
 // Span of a sampled launch on the constant-rate wall clock: ts[0] keeps the earliest
 // block start, ts[1] the latest block end (preset to all-ones and zero on the host
 // side). Blocks are dispatched in index order and do equal work here, so the first 64
