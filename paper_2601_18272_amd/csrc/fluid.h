@@ -482,15 +482,37 @@ template <typename T> struct G3 {
     static constexpr int RING = 2 * WX + 2 * TY;    // staged nodes outside the tile
 };
 
-// Resource over component c of plane p of a field of N-node components (zero size when
-// p is off the grid, so that every load returns 0). The plane's bytes stay below
-// BOFF_NONE (checked on the host).
-template <typename T>
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const T *base, long long N, int c, int p, int nz,
-                                                              int pz, unsigned plane) {
+// Component c of plane p of a field of N-node components, read at the byte offset `off`
+// within the plane (zeros when p is off the grid). WHOLE (the field's bytes stay below
+// BOFF_NONE, checked on the host): `rw` is one resource over the whole field, set up
+// once per kernel, and the component and plane are chosen by the scalar offset; a plane
+// off the grid switches every lane off through its vector offset. Otherwise a resource
+// per plane of `base` (a plane's bytes stay below BOFF_NONE, checked on the host).
+template <typename T, bool WHOLE>
+__device__ __forceinline__ T pload(const T *base, __amdgpu_buffer_rsrc_t rw, long long N, int c, int p, int nz,
+                                   int pz, unsigned plane, unsigned off) {
     int zw = p;
     const bool ok = wrap_coord(zw, nz, pz);
-    return brsrc(base + (long long)c * N + (long long)(ok ? zw : 0) * plane, ok ? plane * (unsigned)sizeof(T) : 0u);
+    if (WHOLE)
+        return bload<T>(rw, ok ? off : BOFF_NONE,
+                        ((unsigned)c * (unsigned)N + (unsigned)(ok ? zw : 0) * plane) * (unsigned)sizeof(T));
+    return bload<T>(brsrc(base + (long long)c * N + (long long)(ok ? zw : 0) * plane,
+                          ok ? plane * (unsigned)sizeof(T) : 0u),
+                    off);
+}
+// Store to component c of plane p (on the grid) at the byte offset `off` within it.
+template <typename T, bool WHOLE>
+__device__ __forceinline__ void pstore(T v, T *base, __amdgpu_buffer_rsrc_t rw, long long N, int c, int p,
+                                       unsigned plane, unsigned off) {
+    if (WHOLE)
+        bstore(v, rw, off, ((unsigned)c * (unsigned)N + (unsigned)p * plane) * (unsigned)sizeof(T));
+    else
+        bstore(v, brsrc(base + (long long)c * N + (long long)p * plane, plane * (unsigned)sizeof(T)), off);
+}
+// The whole-field resource of a field of nc components (WHOLE only).
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t field_rsrc(const T *base, long long N, int nc) {
+    return brsrc(base, (unsigned)nc * (unsigned)N * (unsigned)sizeof(T));
 }
 
 // Second-order one-sided doubled derivatives at the first (lo) and last (hi) node of a
@@ -552,7 +574,7 @@ __device__ __forceinline__ void feq3(T p, const T u[3], const FeqU<T> &fu, const
     }
 }
 
-template <typename T, bool SP>
+template <typename T, bool SP, bool WHOLE>
 __global__ __launch_bounds__(G3<T>::NT, sizeof(T) == 4 ? 6 : 2) void k_gather3d(Grid g, T A, FeqU<T> fu, int ZC,
                                                         const T *__restrict__ sin_, T *__restrict__ sout,
                                                         unsigned long long *ts) {
@@ -571,7 +593,8 @@ __global__ __launch_bounds__(G3<T>::NT, sizeof(T) == 4 ? 6 : 2) void k_gather3d(
     const int z0 = tb.z * ZC, z1 = min(z0 + ZC, nz);
     // a wave is one row of the tile: ty is uniform over it
     const int tx = threadIdx.x, ty = __builtin_amdgcn_readfirstlane(threadIdx.y), tid = tx + TX * ty;
-    const unsigned plane = (unsigned)nx * (unsigned)ny, pbytes = plane * (unsigned)sizeof(T);
+    const unsigned plane = (unsigned)nx * (unsigned)ny;
+    const __amdgpu_buffer_rsrc_t rin = field_rsrc(sin_, N, 4), rout = field_rsrc(sout, N, 4);
 
     // this thread's source column
     int cx = x0 - 1 + tx, cy = y0 - 1 + ty;
@@ -606,11 +629,11 @@ __global__ __launch_bounds__(G3<T>::NT, sizeof(T) == 4 ? 6 : 2) void k_gather3d(
 #pragma unroll
     for (int j = 0; j < 5; j++)
 #pragma unroll
-        for (int c = 0; c < 4; c++) q[j][c] = bload<T>(plane_rsrc(sin_, N, c, z0 - 3 + j, nz, pz, plane), coff);
+        for (int c = 0; c < 4; c++) q[j][c] = pload<T, WHOLE>(sin_, rin, N, c, z0 - 3 + j, nz, pz, plane, coff);
     T rv[3];  // ring node of plane s (reloaded with plane s + 1 once staged)
     if (tid < G::RING) {
 #pragma unroll
-        for (int c = 0; c < 3; c++) rv[c] = bload<T>(plane_rsrc(sin_, N, 1 + c, z0 - 1, nz, pz, plane), roff);
+        for (int c = 0; c < 3; c++) rv[c] = pload<T, WHOLE>(sin_, rin, N, 1 + c, z0 - 1, nz, pz, plane, roff);
     }
     T acc[3][4];  // destination plane s + k in slot (J + k + 1) mod 3
 #pragma unroll
@@ -637,11 +660,11 @@ __global__ __launch_bounds__(G3<T>::NT, sizeof(T) == 4 ? 6 : 2) void k_gather3d(
             if (s + 1 <= z1 && tid < G::RING) {
 #pragma unroll
                 for (int c = 0; c < 3; c++)
-                    rv[c] = bload<T>(plane_rsrc(sin_, N, 1 + c, s + 1, nz, pz, plane), roff);
+                    rv[c] = pload<T, WHOLE>(sin_, rin, N, 1 + c, s + 1, nz, pz, plane, roff);
             }
             if (s + 3 <= z1 + 2) {
 #pragma unroll
-                for (int c = 0; c < 4; c++) q[qp3][c] = bload<T>(plane_rsrc(sin_, N, c, s + 3, nz, pz, plane), coff);
+                for (int c = 0; c < 4; c++) q[qp3][c] = pload<T, WHOLE>(sin_, rin, N, c, s + 3, nz, pz, plane, coff);
             }
             __syncthreads();
 
@@ -706,10 +729,9 @@ __global__ __launch_bounds__(G3<T>::NT, sizeof(T) == 4 ? 6 : 2) void k_gather3d(
                 // destination plane s - 1 has received all its sources
                 const int zd = s - 1;
                 if (zd >= z0 && zd < z1 && !(!pz && (zd == 0 || zd == nz - 1))) {
-                    const long long zo = (long long)zd * plane;
-                    bstore(acc[km][0] * T(1.0 / 3.0), brsrc(sout + zo, pbytes), ooff);
+                    pstore<T, WHOLE>(acc[km][0] * T(1.0 / 3.0), sout, rout, N, 0, zd, plane, ooff);
 #pragma unroll
-                    for (int a = 0; a < 3; a++) bstore(acc[km][1 + a], brsrc(sout + (1 + a) * N + zo, pbytes), ooff);
+                    for (int a = 0; a < 3; a++) pstore<T, WHOLE>(acc[km][1 + a], sout, rout, N, 1 + a, zd, plane, ooff);
                 }
             }
             }
@@ -1437,14 +1459,14 @@ template <typename T> struct A3 {
 
 // g = (p*bar, u*bar) of plane p at the own column (v[0..3]) and, for ring threads, at the
 // ring node (v[4..7]); zeros off the grid.
-template <typename T>
-__device__ __forceinline__ void a3_load(const T *ab, long long N, int p, int nz, int pz, unsigned plane,
-                                        unsigned coff, unsigned roff, bool ring, T v[8]) {
+template <typename T, bool WHOLE>
+__device__ __forceinline__ void a3_load(const T *ab, __amdgpu_buffer_rsrc_t rw, long long N, int p, int nz, int pz,
+                                        unsigned plane, unsigned coff, unsigned roff, bool ring, T v[8]) {
 #pragma unroll
-    for (int c = 0; c < 4; c++) v[c] = bload<T>(plane_rsrc(ab, N, c, p, nz, pz, plane), coff);
+    for (int c = 0; c < 4; c++) v[c] = pload<T, WHOLE>(ab, rw, N, c, p, nz, pz, plane, coff);
     if (ring) {
 #pragma unroll
-        for (int c = 0; c < 4; c++) v[4 + c] = bload<T>(plane_rsrc(ab, N, c, p, nz, pz, plane), roff);
+        for (int c = 0; c < 4; c++) v[4 + c] = pload<T, WHOLE>(ab, rw, N, c, p, nz, pz, plane, roff);
     }
 }
 
@@ -1456,7 +1478,7 @@ __device__ __forceinline__ void a3_load(const T *ab, long long N, int p, int nz,
 // reads zeros and writes nothing). The transposes are central; the one-sided forms near
 // a non-periodic wall are taken in branches uniform over the block (x), the wave (y) or
 // the plane (z). UPS: also store the moment ups itself (the paper's u~*).
-template <typename T, bool SP, bool UPS>
+template <typename T, bool SP, bool UPS, bool WHOLE>
 __global__ __launch_bounds__(A3<T>::NT, sizeof(T) == 4 ? 4 : 2) void k_adjgather3d(
     Grid g, T A, int ZC, int offx, int offy, const T *__restrict__ ab, const T *__restrict__ sprev,
     T *__restrict__ out, unsigned long long *ts, T *__restrict__ ups) {
@@ -1474,7 +1496,9 @@ __global__ __launch_bounds__(A3<T>::NT, sizeof(T) == 4 ? 4 : 2) void k_adjgather
     const int z0 = tb.z * ZC, z1 = min(z0 + ZC, nz);
     // a wave is one row of the tile: ty is uniform over it
     const int tx = threadIdx.x, ty = __builtin_amdgcn_readfirstlane(threadIdx.y), tid = tx + TX * ty;
-    const unsigned plane = (unsigned)nx * (unsigned)ny, pbytes = plane * (unsigned)sizeof(T);
+    const unsigned plane = (unsigned)nx * (unsigned)ny;
+    const __amdgpu_buffer_rsrc_t rab = field_rsrc(ab, N, 4), rsp = field_rsrc(sprev, N, 4),
+                                 rout = field_rsrc(out, N, 4), rups = field_rsrc(ups, N, UPS ? 3 : 0);
     // own column (x, y as the output node when inside the output tile)
     const int ox = x0 - 1 + tx, oy = y0 - 1 + ty;
     int cx = ox, cy = oy;
@@ -1517,12 +1541,12 @@ __global__ __launch_bounds__(A3<T>::NT, sizeof(T) == 4 ? 4 : 2) void k_adjgather
 
     // planes z0-3, z0-2 staged (LDS slots 0, 1); z0-1, z0 in registers (slots 0, 1)
     T gv[2][8];
-    a3_load(ab, N, z0 - 3, nz, pz, plane, coff, roff, ring, gv[0]);
+    a3_load<T, WHOLE>(ab, rab, N, z0 - 3, nz, pz, plane, coff, roff, ring, gv[0]);
     stage(0, gv[0]);
-    a3_load(ab, N, z0 - 2, nz, pz, plane, coff, roff, ring, gv[1]);
+    a3_load<T, WHOLE>(ab, rab, N, z0 - 2, nz, pz, plane, coff, roff, ring, gv[1]);
     stage(1, gv[1]);
-    a3_load(ab, N, z0 - 1, nz, pz, plane, coff, roff, ring, gv[0]);
-    a3_load(ab, N, z0, nz, pz, plane, coff, roff, ring, gv[1]);
+    a3_load<T, WHOLE>(ab, rab, N, z0 - 1, nz, pz, plane, coff, roff, ring, gv[0]);
+    a3_load<T, WHOLE>(ab, rab, N, z0, nz, pz, plane, coff, roff, ring, gv[1]);
     T uc[3] = {0, 0, 0};  // U + v of the previous state at the output node of plane s
     T hz[6][3];           // sig_xz, sig_yz, sig_zz of plane s + k in slot (J + k + 6) mod 6
     T part[3][4];         // local + in-plane terms of plane s + k in slot (J + k + 3) mod 3
@@ -1541,14 +1565,13 @@ __global__ __launch_bounds__(A3<T>::NT, sizeof(T) == 4 ? 4 : 2) void k_adjgather
             stage(sp, gv[J & 1]);
             const T u0 = uc[0], u1 = uc[1], u2 = uc[2];
             {
-                const int pu = s + 1;
-                const bool ok = pu >= z0 && pu < z1;
-                const long long zo = ok ? (long long)pu * plane : 0;
-                uc[0] = U0 + bload<T>(brsrc(sprev + N + zo, ok ? pbytes : 0u), ooff);
-                uc[1] = U1 + bload<T>(brsrc(sprev + 2 * N + zo, ok ? pbytes : 0u), ooff);
-                uc[2] = U2 + bload<T>(brsrc(sprev + 3 * N + zo, ok ? pbytes : 0u), ooff);
+                // (planes outside [z0, z1) are never output planes: read as off the grid)
+                const int pu = s + 1 >= z0 && s + 1 < z1 ? s + 1 : -1;
+                uc[0] = U0 + pload<T, WHOLE>(sprev, rsp, N, 1, pu, nz, 0, plane, ooff);
+                uc[1] = U1 + pload<T, WHOLE>(sprev, rsp, N, 2, pu, nz, 0, plane, ooff);
+                uc[2] = U2 + pload<T, WHOLE>(sprev, rsp, N, 3, pu, nz, 0, plane, ooff);
             }
-            if (s + 3 <= z1 + 2) a3_load(ab, N, s + 3, nz, pz, plane, coff, roff, ring, gv[J & 1]);
+            if (s + 3 <= z1 + 2) a3_load<T, WHOLE>(ab, rab, N, s + 3, nz, pz, plane, coff, roff, ring, gv[J & 1]);
             __syncthreads();
             // moments of plane s at the own node: g_i taken at the node + c_i
             const int lx = tx + 1, ly = ty + 1;
@@ -1651,9 +1674,8 @@ __global__ __launch_bounds__(A3<T>::NT, sizeof(T) == 4 ? 4 : 2) void k_adjgather
                 part[ps][2] = o[1];
                 part[ps][3] = o[2];
                 if (UPS) {  // the moment ups itself (the paper's u~*), for its adjoint variant
-                    const long long zo = (long long)s * plane;
 #pragma unroll
-                    for (int c = 0; c < 3; c++) bstore(up[c], brsrc(ups + c * N + zo, pbytes), ooff);
+                    for (int c = 0; c < 3; c++) pstore<T, WHOLE>(up[c], ups, rups, N, c, s, plane, ooff);
                 }
             }
             const int zo = s - 2;
@@ -1676,10 +1698,9 @@ __global__ __launch_bounds__(A3<T>::NT, sizeof(T) == 4 ? 4 : 2) void k_adjgather
 #pragma unroll
                     for (int c = 0; c < 3; c++) o[c] += kp * hz[hp][c];
                 }
-                const long long zoff = (long long)zo * plane;
-                bstore(part[ps][0], brsrc(out + zoff, pbytes), ooff);
+                pstore<T, WHOLE>(part[ps][0], out, rout, N, 0, zo, plane, ooff);
 #pragma unroll
-                for (int c = 0; c < 3; c++) bstore(o[c], brsrc(out + (1 + c) * N + zoff, pbytes), ooff);
+                for (int c = 0; c < 3; c++) pstore<T, WHOLE>(o[c], out, rout, N, 1 + c, zo, plane, ooff);
             }
             }
         }

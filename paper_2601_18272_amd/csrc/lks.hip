@@ -532,6 +532,9 @@ template <typename T> struct Run {
     // z planes per block of the 2.5D 3D kernels. A block costs about (planes + 2) plane
     // steps (two planes of lead-in), and `resident` blocks run at once (occupancy x
     // CUs); pick the chunk (4..32 planes) that minimises rounds x (planes + 2).
+    // the 3D LKS kernels address a whole field (4 components) with 32-bit byte offsets
+    // below BOFF_NONE (else one plane at a time)
+    bool whole_fields() const { return 4ULL * (unsigned long long)c.g.N * sizeof(T) < (unsigned long long)BOFF_NONE; }
     int zchunk(int ox, int oy, long long resident) const {
         const long long bxy = (long long)blocks(c.g.n[0], ox) * blocks(c.g.n[1], oy);
         int best = 32;
@@ -582,13 +585,17 @@ template <typename T> struct Run {
                                           T(c.A), c.bc, fd, in, out, ts);
             });
         } else {
-            static const long long res = resident_blocks(k_gather3d<T, false>, G3<T>::NT);
+            static const long long res = resident_blocks(k_gather3d<T, false, true>, G3<T>::NT);
             const int zc = zchunk(G3<T>::OX, G3<T>::OY, res);
             const dim3 grid(blocks(c.g.n[0], G3<T>::OX), blocks(c.g.n[1], G3<T>::OY), blocks(c.g.n[2], zc));
-            // 3D: launch events only (long launches; the stamping variant would spill)
+            // 3D: launch events only (long launches)
             pf->run_span(LKS_K_GATHER, -1, [&](hipEvent_t e0, hipEvent_t e1, unsigned long long *) {
-                hipExtLaunchKernelGGL((k_gather3d<T, false>), grid, dim3(G3<T>::TX, G3<T>::TY), 0, st, e0, e1, 0,
-                                      c.g, T(c.A), FeqU<T>::make(c.g.U), zc, in, out, nullptr);
+                if (whole_fields())
+                    hipExtLaunchKernelGGL((k_gather3d<T, false, true>), grid, dim3(G3<T>::TX, G3<T>::TY), 0, st, e0,
+                                          e1, 0, c.g, T(c.A), FeqU<T>::make(c.g.U), zc, in, out, nullptr);
+                else
+                    hipExtLaunchKernelGGL((k_gather3d<T, false, false>), grid, dim3(G3<T>::TX, G3<T>::TY), 0, st, e0,
+                                          e1, 0, c.g, T(c.A), FeqU<T>::make(c.g.U), zc, in, out, nullptr);
             });
         }
     }
@@ -814,7 +821,7 @@ template <typename T> struct Run {
                     hipExtLaunchKernelGGL((k_adjgather2d<T, false>), grid, dim3(G2_TX, G2_TY), 0, st, e0, e1, 0,
                                           c.g, c.bc, T(c.A), ab, ustb, Bprev, c.D, hb, sprev, out, ts, ups);
             } else {
-                static const long long res = resident_blocks(k_adjgather3d<T, false, false>, A3<T>::NT);
+                static const long long res = resident_blocks(k_adjgather3d<T, false, false, true>, A3<T>::NT);
                 // shift the tiles of a non-periodic axis by one node where a tile
                 // boundary would fall on node n-2 (see k_adjgather3d)
                 const int offx = !c.g.per[0] && (c.g.n[0] - 2) % A3<T>::OX == 0 ? 1 : 0;
@@ -835,12 +842,24 @@ template <typename T> struct Run {
                                           0, c.g, ab, m, c.D, Bprev, ustb, hb);
                     es = nullptr;
                 }
-                if (ups)
-                    hipExtLaunchKernelGGL((k_adjgather3d<T, false, true>), grid, dim3(A3<T>::TX, A3<T>::TY), 0, st, es,
-                                          e1, 0, c.g, T(c.A), zc, offx, offy, (const T *)ab, sprev, out, ts, ups);
-                else
-                    hipExtLaunchKernelGGL((k_adjgather3d<T, false, false>), grid, dim3(A3<T>::TX, A3<T>::TY), 0, st,
-                                          es, e1, 0, c.g, T(c.A), zc, offx, offy, (const T *)ab, sprev, out, ts, ups);
+                const dim3 blk(A3<T>::TX, A3<T>::TY);
+                const T A = T(c.A);
+                const T *abc = ab;
+                if (whole_fields()) {
+                    if (ups)
+                        hipExtLaunchKernelGGL((k_adjgather3d<T, false, true, true>), grid, blk, 0, st, es, e1, 0, c.g,
+                                              A, zc, offx, offy, abc, sprev, out, ts, ups);
+                    else
+                        hipExtLaunchKernelGGL((k_adjgather3d<T, false, false, true>), grid, blk, 0, st, es, e1, 0, c.g,
+                                              A, zc, offx, offy, abc, sprev, out, ts, ups);
+                } else {
+                    if (ups)
+                        hipExtLaunchKernelGGL((k_adjgather3d<T, false, true, false>), grid, blk, 0, st, es, e1, 0, c.g,
+                                              A, zc, offx, offy, abc, sprev, out, ts, ups);
+                    else
+                        hipExtLaunchKernelGGL((k_adjgather3d<T, false, false, false>), grid, blk, 0, st, es, e1, 0,
+                                              c.g, A, zc, offx, offy, abc, sprev, out, ts, ups);
+                }
             }
         });
     }
