@@ -54,13 +54,18 @@ enum { LKS_DOF_TX = 1, LKS_DOF_TY = 2, LKS_DOF_TZ = 4, LKS_DOF_ROT = 8 };
  *   the grid size (by default grids of at least 4M nodes march in the forward, of at least
  *   1M nodes in the adjoint, smaller ones use the tile kernels). The results agree to
  *   rounding; a forward and the adjoint that recomputes it should be given the same flag
- *   for the recompute to reproduce the forward bit for bit. */
+ *   for the recompute to reproduce the forward bit for bit.
+ * LKS_FLAG_PLANE3D: the 3D LKS and adjoint LKS kernels address the fields one plane at a
+ *   time, the form they take by themselves for fields of 2^31 bytes and more (smaller
+ *   fields are addressed whole). The arithmetic is the same, so are the results; the flag
+ *   exists so that the large-field form can be tested on small grids. */
 enum {
     LKS_FLAG_ASYNC = 1,
     LKS_FLAG_PROFILE = 2,
     LKS_FLAG_STABILITY = 4,
     LKS_FLAG_PAPER_ADJOINT = 8,
-    LKS_FLAG_MARCH2D = 16
+    LKS_FLAG_MARCH2D = 16,
+    LKS_FLAG_PLANE3D = 32
 };
 
 enum {

@@ -17,6 +17,7 @@ FLAG_PROFILE = 2
 FLAG_STABILITY = 4
 FLAG_PAPER_ADJOINT = 8
 FLAG_MARCH2D = 16
+FLAG_PLANE3D = 32
 KERNELS = ("gather", "bc", "spread", "interp", "adj_gather", "adj_recompute", "adj_r1", "adj_r2",
            "adj_r3", "iter", "iter_final", "gather_span", "adj_gather_span", "filter", "filter_adj",
            "cyc_expand", "cyc_collect")

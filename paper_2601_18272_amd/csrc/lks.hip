@@ -195,6 +195,7 @@ struct Ctx {
     bool paper = false;  // lks_adjoint computes the paper's adjoint variant (f2.h)
     // 2D LKS / adjoint LKS kernels: the column march (large grids) or the tiles
     bool march_fwd = false, march_adj = false;
+    bool plane3d = false;  // 3D: LKS kernels address the fields one plane at a time
 };
 
 // Grids from which the 2D column-march kernels are faster than the tile kernels
@@ -332,6 +333,9 @@ int make_ctx(const lks_problem_t *P, Ctx &c) {
         const bool force = (P->flags & LKS_FLAG_MARCH2D) != 0;
         c.march_fwd = c.dim == 2 && (force || c.g.N >= MARCH_FWD_NODES);
         c.march_adj = c.dim == 2 && (force || c.g.N >= MARCH_ADJ_NODES);
+        c.plane3d = c.dim == 3 && ((P->flags & LKS_FLAG_PLANE3D) != 0 ||
+                                   4ULL * (unsigned long long)c.g.N * (P->precision == LKS_FP64 ? 8 : 4) >=
+                                       (unsigned long long)BOFF_NONE);
     }
     if (P->n_steps < 0) return fail(LKS_EINVAL, "n_steps < 0");
     c.NT = P->n_steps;
@@ -533,8 +537,8 @@ template <typename T> struct Run {
     // steps (two planes of lead-in), and `resident` blocks run at once (occupancy x
     // CUs); pick the chunk (4..32 planes) that minimises rounds x (planes + 2).
     // the 3D LKS kernels address a whole field (4 components) with 32-bit byte offsets
-    // below BOFF_NONE (else one plane at a time)
-    bool whole_fields() const { return 4ULL * (unsigned long long)c.g.N * sizeof(T) < (unsigned long long)BOFF_NONE; }
+    // below BOFF_NONE, else one plane at a time
+    bool whole_fields() const { return !c.plane3d; }
     int zchunk(int ox, int oy, long long resident) const {
         const long long bxy = (long long)blocks(c.g.n[0], ox) * blocks(c.g.n[1], oy);
         int best = 32;

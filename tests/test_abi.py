@@ -263,3 +263,4 @@ def test_coupling_validation_without_gpu(lib):
     assert L.lks_coupling(C.byref(s), dummy, dummy, dummy, dummy, 16, None) == lib.ENOSPACE
     assert lib.FLAG_STABILITY == 4
     assert lib.FLAG_MARCH2D == 16
+    assert lib.FLAG_PLANE3D == 32

@@ -42,11 +42,13 @@ def elem(a, b):
 
 
 def kernel_flags(L, pb, march):
-    """Flags selecting the 2D LKS kernels: the column march (march=True, forced) or the
-    size default (the tile kernels at these sizes). 3D problems have one kernel each."""
-    if march and pb.dim != 2:
-        pytest.skip("the column-march kernels are 2D")
-    return L._lib.FLAG_MARCH2D if march else 0
+    """Flags selecting the form of the LKS kernels. 2D: the column march (march=True,
+    forced) or the size default (the tile kernels at these sizes). 3D: with march=True the
+    fields are addressed one plane at a time (the form of fields of 2^31 bytes and more),
+    else whole (the form at these sizes)."""
+    if march:
+        return L._lib.FLAG_MARCH2D if pb.dim == 2 else L._lib.FLAG_PLANE3D
+    return 0
 
 
 def smooth_state(pb, seed, amp=1e-2):
@@ -83,7 +85,7 @@ BODYFREE = {
 }
 
 
-@pytest.mark.parametrize("march", [False, True], ids=["tiles", "march"])
+@pytest.mark.parametrize("march", [False, True], ids=["default", "alt"])
 @pytest.mark.parametrize("case", sorted(BODYFREE))
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_bodyfree_forward(L, orc, case, prec, march):
@@ -99,7 +101,7 @@ def test_bodyfree_forward(L, orc, case, prec, march):
     assert np.abs(got - ref).max() <= tol * scale, np.abs(got - ref).max() / scale
 
 
-@pytest.mark.parametrize("march", [False, True], ids=["tiles", "march"])
+@pytest.mark.parametrize("march", [False, True], ids=["default", "alt"])
 @pytest.mark.parametrize("case", sorted(BODYFREE))
 def test_bodyfree_adjoint_initial_state(L, orc, case, march):
     """The fluid adjoint of the body-free channels, observed through a tiny porous body:
@@ -152,7 +154,7 @@ def test_coupled_forward_fp64(L, orc, case):
     assert abs(J.item() - Jref) <= 1e-9 * abs(Jref) + 1e-16
 
 
-@pytest.mark.parametrize("march", [False, True], ids=["tiles", "march"])
+@pytest.mark.parametrize("march", [False, True], ids=["default", "alt"])
 @pytest.mark.parametrize("case", sorted(BODY))
 def test_coupled_gradient_fp64(L, orc, case, march):
     pb = BODY[case]()
@@ -166,7 +168,7 @@ def test_coupled_gradient_fp64(L, orc, case, march):
     assert elem(gg, gref) < 1e-8
 
 
-@pytest.mark.parametrize("march", [False, True], ids=["tiles", "march"])
+@pytest.mark.parametrize("march", [False, True], ids=["default", "alt"])
 @pytest.mark.parametrize("case", sorted(BODY))
 def test_coupled_fp32_targets(L, orc, case, march):
     """FP32 fields with FP64 body state and reductions: objective within 1e-4 relative,
@@ -208,7 +210,7 @@ def test_body_step_matches_oracle(L, orc):
         assert np.array_equal(got[8:], b[8:])
 
 
-@pytest.mark.parametrize("march", [False, True], ids=["tiles", "march"])
+@pytest.mark.parametrize("march", [False, True], ids=["default", "alt"])
 def test_deterministic_and_checkpoint_consistent(L, march):
     """Two runs are bitwise identical (gather-form mapping, fixed-order reductions),
     and the gradient does not depend on the checkpoint interval beyond rounding."""
@@ -268,7 +270,7 @@ def test_divergence_is_reported(L):
 TERMINAL = ["small2d", "small2d-walls", "small3d"]
 
 
-@pytest.mark.parametrize("march", [False, True], ids=["tiles", "march"])
+@pytest.mark.parametrize("march", [False, True], ids=["default", "alt"])
 @pytest.mark.parametrize("case", TERMINAL)
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_adjoint_with_terminal_values(L, orc, case, prec, march):
