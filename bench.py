@@ -125,7 +125,9 @@ def run_cpu_baseline(pb, sample_steps):
     import oracle
     import workloads as W
 
-    spb = pb.replace(n_steps=sample_steps)
+    # checkpoint interval no longer than the sample (the oracle stores every state; the
+    # GPU's segment buffers are then sized for the sample, not for the full workload)
+    spb = pb.replace(n_steps=sample_steps, ckpt_every=max(1, min(pb.ckpt_every, sample_steps)))
     g, s0, b0 = W.design(spb), W.initial_state(spb), W.initial_body(spb)
     t0 = time.perf_counter()
     J, grad = oracle.gradient(spb, g, s0, b0)
@@ -169,9 +171,11 @@ def roofline_sweep(args):
     import workloads as W
     from paper_2601_18272_amd import _lib
 
+    only = [tuple(int(v) for v in g.split("x")) for g in args.grids.split(",")] if args.grids else None
     for dim in (2, 3):
         for n in SWEEP[dim]:
-            print(json.dumps(sweep_point(dim, n, args.steps)), flush=True)
+            if only is None or tuple(n) in only:
+                print(json.dumps(sweep_point(dim, n, args.steps)), flush=True)
     print(json.dumps({"sweep": "copy", "elementwise_copy_1GiB_GBs": round(copy_bandwidth(), 1)}), flush=True)
 
 
@@ -470,6 +474,8 @@ def main():
     ap.add_argument("--sweep", action="store_true",
                     help="body-free roofline sweep of the LKS and adjoint LKS kernels over grid sizes "
                          "up to > 1 GB per step (one JSON line per size instead of the headline)")
+    ap.add_argument("--grids", default=None,
+                    help="with --sweep: only these grids of the sweep, comma-separated (e.g. 8192x8192,512x256x256)")
     ap.add_argument("--only-gradient", action="store_true",
                     help="time the gradient steps only (no extra measurements, no FP64 or CPU runs): "
                          "for profiler runs")
