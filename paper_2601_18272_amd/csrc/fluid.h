@@ -477,9 +477,9 @@ __global__ __launch_bounds__(512) void k_gather2d(Grid g, T A, Bc bc, int fold, 
 // writes nothing.
 template <typename T> struct G3 {
     static constexpr int TX = 64, TY = 8, NT = TX * TY;
-    static constexpr int OX = TX - 2, OY = TY - 2;  // output tile
-    static constexpr int WX = TX + 2, WY = TY + 2;  // staged u plane
-    static constexpr int RING = 2 * WX + 2 * TY;    // staged nodes outside the tile
+    static constexpr int OX = TX - 4, OY = TY - 2;  // output tile: lanes 2 .. 61, rows 1 .. TY-2
+    static constexpr int WY = TY + 2;               // staged u plane: the tile's rows and one more each side
+    static constexpr int RING = 2 * TX;             // staged nodes outside the tile (two rows)
 };
 
 // Component c of plane p of a field of N-node components, read at the byte offset `off`
@@ -579,10 +579,10 @@ __global__ __launch_bounds__(G3<T>::NT, sizeof(T) == 4 ? 6 : 2) void k_gather3d(
                                                         const T *__restrict__ sin_, T *__restrict__ sout,
                                                         unsigned long long *ts) {
     using G = G3<T>;
-    constexpr int TX = G::TX, TY = G::TY, WX = G::WX, WY = G::WY;
-    // u of plane s (one buffer: its readers pass the second barrier of a plane before
-    // anyone stages the next one)
-    __shared__ T wu[3][WY][WX];
+    constexpr int TX = G::TX, TY = G::TY, WY = G::WY;
+    // u of plane s for the y derivatives (one buffer: its readers pass the second barrier
+    // of a plane before anyone stages the next one)
+    __shared__ T wu[3][WY][TX];
     __shared__ T fb[15][TY][TX];
     if (SP) span_begin(ts);
     const long long N = g.N;
@@ -596,32 +596,30 @@ __global__ __launch_bounds__(G3<T>::NT, sizeof(T) == 4 ? 6 : 2) void k_gather3d(
     const unsigned plane = (unsigned)nx * (unsigned)ny;
     const __amdgpu_buffer_rsrc_t rin = field_rsrc(sin_, N, 4), rout = field_rsrc(sout, N, 4);
 
-    // this thread's source column
-    int cx = x0 - 1 + tx, cy = y0 - 1 + ty;
+    // this thread's source column (x0 - 2 + tx, y0 - 1 + ty); the x neighbours of a node
+    // are the neighbouring lanes of its wave, so the tile needs no ring columns
+    int cx = x0 - 2 + tx, cy = y0 - 1 + ty;
     const bool colok = wrap_coord(cx, nx, px) && wrap_coord(cy, ny, py);
     const unsigned coff = colok ? ((unsigned)cx + (unsigned)nx * (unsigned)cy) * (unsigned)sizeof(T) : BOFF_NONE;
-    // ring node of the staged plane handled by this thread (tid < RING)
-    int rx = 0, ry = 0;
-    if (tid < 2 * WX) {
-        rx = tid % WX;
-        ry = tid < WX ? 0 : WY - 1;
-    } else if (tid < G::RING) {
-        const int k = tid - 2 * WX;
-        ry = 1 + (k >> 1);
-        rx = (k & 1) ? WX - 1 : 0;
-    }
-    int gx = x0 - 2 + rx, gy = y0 - 2 + ry;
-    const bool ringok = tid < G::RING && wrap_coord(gx, nx, px) && wrap_coord(gy, ny, py);
+    // ring node of the staged plane handled by this thread (waves 0 and 1: the rows
+    // y0 - 2 and y0 + TY - 1 of the tile's columns)
+    const bool ring = tid < G::RING;
+    const int ry = tid < TX ? 0 : WY - 1;
+    int gx = x0 - 2 + tx, gy = ry == 0 ? y0 - 2 : y0 + TY - 1;
+    const bool ringok = ring && wrap_coord(gx, nx, px) && wrap_coord(gy, ny, py);
     const unsigned roff = ringok ? ((unsigned)gx + (unsigned)nx * (unsigned)gy) * (unsigned)sizeof(T) : BOFF_NONE;
-    // output node (x0 + tx, y0 + ty), written when it is an interior node of the x-y plane
-    const int ox = x0 + tx, oy = y0 + ty;
-    const bool outrow = ty < G::OY;
-    const bool outok = tx < G::OX && outrow && ox < nx && oy < ny && !(!px && (ox == 0 || ox == nx - 1)) &&
+    // output node: the thread's own node for lanes 2 .. 61 and rows 1 .. TY-2, written
+    // when it is an interior node of the x-y plane
+    // (unwrapped: on a periodic axis a node past the end belongs to the first tile)
+    const int ox = x0 - 2 + tx, oy = y0 - 1 + ty;
+    const bool outrow = ty >= 1 && ty <= G::OY;
+    const bool outlane = tx >= 2 && tx < 2 + G::OX;
+    const bool outok = outlane && outrow && ox < nx && oy < ny && !(!px && (ox == 0 || ox == nx - 1)) &&
                        !(!py && (oy == 0 || oy == ny - 1));
     const unsigned ooff = outok ? ((unsigned)ox + (unsigned)nx * (unsigned)oy) * (unsigned)sizeof(T) : BOFF_NONE;
     // one-sided derivatives: the tile holds an x-wall column (block-uniform), the lane's
     // column is one (1 first, 2 last), the wave's row is a y-wall row (wave-uniform)
-    const bool xw = !px && (x0 - 1 <= 0 || x0 + TX - 2 >= nx - 1);
+    const bool xw = !px && (x0 - 2 <= 0 || x0 + TX - 3 >= nx - 1);
     const T xlo = (!px && colok && cx == 0) ? T(1) : T(0), xhi = (!px && colok && cx == nx - 1) ? T(1) : T(0);
     const int ys = (!py && cy >= 0 && cy < ny) ? (cy == 0 ? 1 : (cy == ny - 1 ? 2 : 0)) : 0;
 
@@ -631,7 +629,7 @@ __global__ __launch_bounds__(G3<T>::NT, sizeof(T) == 4 ? 6 : 2) void k_gather3d(
 #pragma unroll
         for (int c = 0; c < 4; c++) q[j][c] = pload<T, WHOLE>(sin_, rin, N, c, z0 - 3 + j, nz, pz, plane, coff);
     T rv[3];  // ring node of plane s (reloaded with plane s + 1 once staged)
-    if (tid < G::RING) {
+    if (ring) {
 #pragma unroll
         for (int c = 0; c < 3; c++) rv[c] = pload<T, WHOLE>(sin_, rin, N, 1 + c, z0 - 1, nz, pz, plane, roff);
     }
@@ -649,15 +647,15 @@ __global__ __launch_bounds__(G3<T>::NT, sizeof(T) == 4 ? 6 : 2) void k_gather3d(
                       qp3 = (J + 5) % 6;
             // stage u of plane s: own node and ring node
 #pragma unroll
-            for (int c = 0; c < 3; c++) wu[c][ty + 1][tx + 1] = q[qc][1 + c];
-            if (tid < G::RING) {
+            for (int c = 0; c < 3; c++) wu[c][ty + 1][tx] = q[qc][1 + c];
+            if (ring) {
 #pragma unroll
-                for (int c = 0; c < 3; c++) wu[c][ry][rx] = rv[c];
+                for (int c = 0; c < 3; c++) wu[c][ry][tx] = rv[c];
             }
             // next planes in flight while this one is evaluated: the ring node first (it is
             // staged at the next plane, and the wait for it must not drain the own column's
             // loads, which run three planes ahead)
-            if (s + 1 <= z1 && tid < G::RING) {
+            if (s + 1 <= z1 && ring) {
 #pragma unroll
                 for (int c = 0; c < 3; c++)
                     rv[c] = pload<T, WHOLE>(sin_, rin, N, 1 + c, s + 1, nz, pz, plane, roff);
@@ -674,29 +672,34 @@ __global__ __launch_bounds__(G3<T>::NT, sizeof(T) == 4 ? 6 : 2) void k_gather3d(
             (void)wrap_coord(zs, nz, pz);
             T f[15];
             {
-                const int lx = tx + 1, ly = ty + 1;
+                const int ly = ty + 1;
                 T D[3][3];  // D[a][b] = 2 d_a u_b
+                T um[3], up[3];  // u at the lanes on either side (every lane active here)
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
-                    D[0][c] = wu[c][ly][lx + 1] - wu[c][ly][lx - 1];
-                    D[1][c] = wu[c][ly + 1][lx] - wu[c][ly - 1][lx];
+                    um[c] = from_left(q[qc][1 + c]);
+                    up[c] = from_right(q[qc][1 + c]);
+                }
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    D[0][c] = up[c] - um[c];
+                    D[1][c] = wu[c][ly + 1][tx] - wu[c][ly - 1][tx];
                     D[2][c] = q[qp1][1 + c] - q[qm1][1 + c];
                 }
                 if (xw) {  // blend in the one-sided form on the wall lane (weights 0 or 1)
 #pragma unroll
                     for (int c = 0; c < 3; c++) {
-                        const T(*U)[WX] = wu[c];
-                        const T m2 = U[ly][lx - 2 < 0 ? 0 : lx - 2], p2 = U[ly][lx + 2 >= WX ? WX - 1 : lx + 2];
-                        const T lo = d2_lo(U[ly][lx], U[ly][lx + 1], p2), hi = d2_hi(U[ly][lx], U[ly][lx - 1], m2);
+                        const T m2 = from_left(um[c]), p2 = from_right(up[c]);
+                        const T lo = d2_lo(q[qc][1 + c], up[c], p2), hi = d2_hi(q[qc][1 + c], um[c], m2);
                         D[0][c] = D[0][c] + xlo * (lo - D[0][c]) + xhi * (hi - D[0][c]);
                     }
                 }
                 if (ys) {
 #pragma unroll
                     for (int c = 0; c < 3; c++) {
-                        const T(*U)[WX] = wu[c];
-                        D[1][c] = ys == 1 ? d2_lo(U[ly][lx], U[ly + 1][lx], U[ly + 2 >= WY ? WY - 1 : ly + 2][lx])
-                                          : d2_hi(U[ly][lx], U[ly - 1][lx], U[ly - 2 < 0 ? 0 : ly - 2][lx]);
+                        const T(*U)[TX] = wu[c];
+                        D[1][c] = ys == 1 ? d2_lo(U[ly][tx], U[ly + 1][tx], U[ly + 2 >= WY ? WY - 1 : ly + 2][tx])
+                                          : d2_hi(U[ly][tx], U[ly - 1][tx], U[ly - 2 < 0 ? 0 : ly - 2][tx]);
                     }
                 }
                 if (!pz && (zs == 0 || zs == nz - 1)) {
@@ -712,7 +715,7 @@ __global__ __launch_bounds__(G3<T>::NT, sizeof(T) == 4 ? 6 : 2) void k_gather3d(
             for (int i = 0; i < 15; i++) fb[i][ty][tx] = f[i];
             __syncthreads();
 
-            if (outrow && tx < G::OX) {
+            if (outrow && outlane) {
                 const int km = J % 3, k0 = (J + 1) % 3, kp = (J + 2) % 3;
 #pragma unroll
                 for (int c = 0; c < 4; c++) acc[kp][c] = T(0);
@@ -720,7 +723,7 @@ __global__ __launch_bounds__(G3<T>::NT, sizeof(T) == 4 ? 6 : 2) void k_gather3d(
                 for (int i = 0; i < 15; i++) {
                     const int ex = Lat<3>::c(i, 0), ey = Lat<3>::c(i, 1), ez = Lat<3>::c(i, 2);
                     const int k = ez < 0 ? km : (ez == 0 ? k0 : kp);
-                    const T v = fb[i][ty + 1 - ey][tx + 1 - ex];
+                    const T v = fb[i][ty - ey][tx - ex];
                     acc[k][0] += v;
                     if (ex) acc[k][1] += T(ex) * v;
                     if (ey) acc[k][2] += T(ey) * v;
