@@ -1448,16 +1448,19 @@ __global__ __launch_bounds__(256) void k_adj_clear3d(Grid g, T *__restrict__ ab,
 // plane s+2, the previous state of plane s+1), so their latency overlaps the work and
 // the barriers of plane s.
 //
-// The second-order one-sided difference on a wall node reaches two nodes inward, so the
-// transpose at the node two away from a wall needs sig on the wall node. Tile origins
-// are shifted by `off` (0 or 1 per axis, chosen on the host) so that no tile boundary
-// falls on node 2 or node n-2 of a non-periodic axis; the one-node moment ring then
-// always contains the wall node where it is needed.
+// Along x a wave's 64 lanes are the columns x0 - 2 .. x0 + 61: the g planes are staged
+// for those columns only (plus a ring of two rows), so the moments are complete at lanes
+// 1 .. 62 and the outputs at lanes 2 .. 61. The second-order one-sided difference on a
+// wall node reaches two nodes inward, so the transpose at the node two away from a wall
+// needs sig on the wall node. Tile origins are shifted by `off` (0 or 1 per axis, chosen
+// on the host) so that no tile boundary falls where that reach would leave the tile's
+// complete moments (node n-3 on a tile's last output column along x, nodes 2 and n-3 on
+// a tile's first and last output row along y).
 template <typename T> struct A3 {
     static constexpr int TX = 64, TY = 8, NT = TX * TY;
-    static constexpr int OX = TX - 2, OY = TY - 2;
-    static constexpr int WX = TX + 2, WY = TY + 2;
-    static constexpr int RING = 2 * WX + 2 * TY;
+    static constexpr int OX = TX - 4, OY = TY - 2;
+    static constexpr int WX = TX + 2, WY = TY + 2;  // LDS rows padded by a zero column each side
+    static constexpr int RING = 2 * TX;             // the two ring rows
 };
 
 // g = (p*bar, u*bar) of plane p at the own column (v[0..3]) and, for ring threads, at the
@@ -1503,25 +1506,18 @@ __global__ __launch_bounds__(A3<T>::NT, sizeof(T) == 4 ? 4 : 2) void k_adjgather
     const __amdgpu_buffer_rsrc_t rab = field_rsrc(ab, N, 4), rsp = field_rsrc(sprev, N, 4),
                                  rout = field_rsrc(out, N, 4), rups = field_rsrc(ups, N, UPS ? 3 : 0);
     // own column (x, y as the output node when inside the output tile)
-    const int ox = x0 - 1 + tx, oy = y0 - 1 + ty;
+    const int ox = x0 - 2 + tx, oy = y0 - 1 + ty;
     int cx = ox, cy = oy;
     const bool colok = wrap_coord(cx, nx, px) && wrap_coord(cy, ny, py);
     const unsigned coff = colok ? ((unsigned)cx + (unsigned)nx * (unsigned)cy) * (unsigned)sizeof(T) : BOFF_NONE;
-    // ring node of the g planes handled by this thread (tid < RING)
-    int rx = 0, ry = 0;
-    if (tid < 2 * WX) {
-        rx = tid % WX;
-        ry = tid < WX ? 0 : WY - 1;
-    } else if (tid < G::RING) {
-        const int k = tid - 2 * WX;
-        ry = 1 + (k >> 1);
-        rx = (k & 1) ? WX - 1 : 0;
-    }
-    int gx = x0 - 2 + rx, gy = y0 - 2 + ry;
+    // ring node of the g planes handled by this thread (waves 0 and 1: the rows y0 - 2
+    // and y0 + TY - 1 of the tile's columns)
     const bool ring = tid < G::RING;
+    const int ry = tid < TX ? 0 : WY - 1;
+    int gx = ox, gy = ry == 0 ? y0 - 2 : y0 + TY - 1;
     const bool ringok = ring && wrap_coord(gx, nx, px) && wrap_coord(gy, ny, py);
     const unsigned roff = ringok ? ((unsigned)gx + (unsigned)nx * (unsigned)gy) * (unsigned)sizeof(T) : BOFF_NONE;
-    const bool outcol = tx >= 1 && tx <= G::OX && ty >= 1 && ty <= G::OY && ox >= 0 && ox < nx && oy >= 0 &&
+    const bool outcol = tx >= 2 && tx < 2 + G::OX && ty >= 1 && ty <= G::OY && ox >= 0 && ox < nx && oy >= 0 &&
                         oy < ny;
     const unsigned ooff = outcol ? ((unsigned)ox + (unsigned)nx * (unsigned)oy) * (unsigned)sizeof(T) : BOFF_NONE;
     // some output column of the tile (x) / the wave's output row (y) lies within two
@@ -1536,11 +1532,16 @@ __global__ __launch_bounds__(A3<T>::NT, sizeof(T) == 4 ? 4 : 2) void k_adjgather
 #pragma unroll
         for (int c = 1; c < 4; c++) gr[sl][c][ty + 1][tx + 1] = v[c];
         if (ring) {
-            gr[sl][0][ry][rx] = v[4] * T(1.0 / 3.0);
+            gr[sl][0][ry][tx + 1] = v[4] * T(1.0 / 3.0);
 #pragma unroll
-            for (int c = 1; c < 4; c++) gr[sl][c][ry][rx] = v[4 + c];
+            for (int c = 1; c < 4; c++) gr[sl][c][ry][tx + 1] = v[4 + c];
         }
     };
+    // the pad columns stay zero (read only by lanes 0 and 63, whose moments no output uses)
+    if (tid < 3 * 4 * WY * 2) {
+        const int k = tid >> 1, side = tid & 1;
+        gr[k / (4 * WY)][(k / WY) % 4][k % WY][side ? WX - 1 : 0] = T(0);
+    }
 
     // planes z0-3, z0-2 staged (LDS slots 0, 1); z0-1, z0 in registers (slots 0, 1)
     T gv[2][8];
