@@ -463,20 +463,21 @@ __global__ __launch_bounds__(512) void k_gather2d(Grid g, T A, Bc bc, int fold, 
 // ===================================================================== forward, 3D
 // 2.5D blocking. A block of TX x TY threads (one wave per row of 64 columns) is the tile
 // of source columns (x, y) whose f_i it evaluates, one column per thread; it writes the
-// inner (TX-2) x (TY-2) columns and marches along z over ZC output planes. Per source
-// plane s each thread evaluates the 15 f_i of its node into LDS and pushes them (by the
-// gather of its output column) to the destination planes s-1, s, s+1, whose moments it
-// keeps in registers. The thread's own column of p, u for planes s-2..s+2 lives in
-// registers, loaded three planes ahead; u of plane s with a one-node ring is staged in
-// LDS for the x and y derivatives. The march is unrolled six planes deep, so the plane
-// ring (six slots), the destination ring (three) and the ring-node buffer (two) are
-// addressed by constants. Derivatives are central; the second-order one-sided forms at
-// the nodes of a non-periodic wall are applied in branches that are uniform over a wave
-// (a y-wall row, a tile holding an x-wall column) or over the block (a z-wall plane).
-// Loads and stores go through buffer resources: a lane off the grid reads zeros and
-// writes nothing.
+// columns of lanes 2 .. 61 of rows 1 .. TY-2 and marches along z over ZC output planes.
+// Per source plane s each thread evaluates the 15 f_i of its node into LDS and pushes
+// them (by the gather of its output column) to the destination planes s-1, s, s+1, whose
+// moments it keeps in registers. The thread's own column of p, u for planes s-2..s+2
+// lives in registers, loaded three planes ahead. The x derivatives take u from the
+// neighbouring lanes (DPP shifts: the tile needs no ring columns, whose loads would each
+// fetch a cache line for one value); u of plane s with a ring of two rows is staged in
+// LDS for the y derivatives. The march is unrolled six planes deep, so the plane ring
+// (six slots) and the destination ring (three) are addressed by constants. Derivatives
+// are central; the second-order one-sided forms at the nodes of a non-periodic wall are
+// applied in branches that are uniform over a wave (a y-wall row, a tile holding an
+// x-wall column) or over the block (a z-wall plane). Loads and stores go through buffer
+// resources: a lane off the grid reads zeros and writes nothing.
 template <typename T> struct G3 {
-    static constexpr int TX = 64, TY = 8, NT = TX * TY;
+    static constexpr int TX = 64, TY = 12, NT = TX * TY;
     static constexpr int OX = TX - 4, OY = TY - 2;  // output tile: lanes 2 .. 61, rows 1 .. TY-2
     static constexpr int WY = TY + 2;               // staged u plane: the tile's rows and one more each side
     static constexpr int RING = 2 * TX;             // staged nodes outside the tile (two rows)
