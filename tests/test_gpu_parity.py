@@ -76,9 +76,12 @@ BODYFREE = {
                                      bc_u=((0, 0, 0),) * 3 + ((0.02, 0, 0),) + ((0, 0, 0),) * 2,
                                      bc_p=(1e-3, -1e-3, 0, 0, 0, 0), nu=0.05, n_steps=9),
     "3d-periodic": lambda: W.Problem(dim=3, n=(13, 11, 9), bc=(0,) * 6, nu=0.07, n_steps=5),
+    # two tiles along x (60 columns each) that wrap across the periodic seam
+    "3d-periodic-wide": lambda: W.Problem(dim=3, n=(67, 8, 6), bc=(0,) * 6, nu=0.07, n_steps=4),
     "3d-duct": lambda: W.duct3d(19, 10, 9, 0.04, 0.03, n_steps=6),
-    # n - 2 a multiple of the 3D adjoint tile (62 x 6): its tiles shift by one node
-    "3d-duct-shifted-tiles": lambda: W.duct3d(64, 14, 7, 0.04, 0.03, n_steps=4),
+    # n - 2 a multiple of the 3D adjoint's output tile (60 x 6): its tiles shift by one
+    # node along x and along y
+    "3d-duct-shifted-tiles": lambda: W.duct3d(62, 14, 7, 0.04, 0.03, n_steps=4),
     "3d-mixed": lambda: W.Problem(dim=3, n=(12, 9, 10), bc=(W.PRESSURE, W.PRESSURE, 0, 0, W.WALL, W.VELOCITY),
                                   bc_u=((0, 0, 0),) * 5 + ((0.03, -0.01, 0),), bc_p=(2e-3, 0, 0, 0, 0, 0),
                                   nu=0.1, n_steps=5),
